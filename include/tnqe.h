@@ -1,0 +1,191 @@
+/*
+ * tnqe.h -- C ABI of libtnqe.so: subspace matrices for a linear combination of
+ * matrix product states in rotated orbital bases, on one AMD MI355X (gfx950).
+ *
+ * What it computes (arXiv 2404.10223, "A quantum eigenvalue solver based on
+ * tensor networks"):
+ *
+ *   |psi> = sum_j c_j |phi_j>                                     (eq. tnqe)
+ *   H_ij = <phi_i|H|phi_j>,  S_ij = <phi_i|phi_j>                 (eq. mat_els)
+ *   H c = E S c, lowest E                                         (eq. GEE)
+ *
+ * with H the second-quantised electronic Hamiltonian (eq. ham_def, read as
+ *   H = sum_{pq,s} h_pq a+_ps a_qs
+ *     + 1/2 sum_{pqrs,st} (pq|rs) a+_ps a+_rt a_st a_qs + e_core),
+ * and each |phi_j> an MPS (eq. mps) of spatial-orbital sites (d = 4, local index
+ * k = n_up + 2 n_dn) written in its own orbital basis U_j (Sec. II.B): column p
+ * of U_j is orbital p of basis j in the reference basis, and
+ * |phi_j> = G(U_j)|Phi_j> with G(W) a+_p G(W)^+ = sum_q W_qp a+_q.
+ *
+ * For a pair i < j the ket is taken into the bra's basis by the nearest-
+ * neighbour Givens network of W = U_i^T U_j (eq. givens_decomp), applying each
+ * two-site gate g4(theta) (App. A3, composite of the d = 2 gates) to the MPS in
+ * canonical form and truncating the bond back to chi by SVD (App. A1, eq.
+ * svd_longform; Sec. II.B "severe truncations").  H_ij and S_ij then come from
+ * one left-environment sweep of bra x MPO x ket (Sec. II.A, App. A1); H_ji and
+ * S_ji are copies.  The M x M generalized eigenproblem is solved with
+ * S-eigenvalue thresholding by the projection method (Sec. V "Regulating the
+ * subspace condition number", App. A2).
+ *
+ * Conventions the paper leaves open, fixed here:
+ *   - Jordan-Wigner mode order (0 up, 0 dn, 1 up, 1 dn, ...); site state
+ *     |k> = (a+_up)^{n_up} (a+_dn)^{n_dn} |vac>.
+ *   - Givens plan: R_a(t) = identity but [[cos t, sin t], [-sin t, cos t]] on
+ *     rows/cols (a, a+1); eliminate Q = W column by column (c = 0..N-2), rows
+ *     r = N-1 down to c+1, t = atan2(-Q[r][c], Q[r-1][c]), Q <- R^T Q; apply
+ *     the recorded gates to the ket in reverse order (after the parity gate
+ *     diag(1,-1,-1,1) on the last site when det W = -1).
+ *   - Truncation keeps the min(chi, #{s^2 > tau_w sum s^2}) largest singular
+ *     values over all quantum-number blocks; singular values are absorbed to
+ *     the right; no renormalisation.
+ *
+ * Threading and streams: one context per host thread; every call is blocking
+ * (it synchronises the context's stream before returning host results).
+ * Errors: every entry point returns a tnqe_status; negative means failure,
+ * outputs are then left untouched and tnqe_last_error(ctx) holds a message.
+ * Memory: the library allocates device memory itself (hipMalloc, kept in a
+ * pool owned by the context and released by tnqe_destroy / tnqe_trim).
+ */
+#ifndef TNQE_H
+#define TNQE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tnqe_ctx tnqe_ctx;
+typedef struct tnqe_problem tnqe_problem;
+
+typedef enum {
+  TNQE_OK = 0,
+  TNQE_EINVAL = -1,      /* null pointer, bad option value               */
+  TNQE_ESHAPE = -2,      /* inconsistent dimensions                      */
+  TNQE_ENOTORTH = -3,    /* a rotation U is not orthogonal (1e-10)       */
+  TNQE_EQN = -4,         /* a site tensor breaks particle-number blocks  */
+  TNQE_ENOMEM = -5,      /* device allocation failed                     */
+  TNQE_EWORKSPACE = -6,  /* reserved                                     */
+  TNQE_EHIP = -7,        /* a HIP runtime call failed                    */
+  TNQE_ESINGULAR = -8,   /* S has no eigenvalue above the threshold      */
+  TNQE_ENONFINITE = -9,  /* NaN/Inf in an input or a result              */
+  TNQE_ENODEVICE = -10   /* no usable gfx950 device                      */
+} tnqe_status;
+
+typedef enum {
+  TNQE_FP64 = 0,         /* everything in FP64                                      */
+  TNQE_ENV_FP32 = 1      /* environment sweep in FP32 (FP64 gates, SVD, final sum,
+                            eigensolve); the element sum is compensated FP64        */
+} tnqe_precision;
+
+/* Hamiltonian in the reference orbital basis.  All host pointers, row-major,
+ * read during the call only. */
+typedef struct {
+  int32_t N;             /* spatial orbitals (sites), 1 <= N <= 64            */
+  int32_t n_alpha;       /* electrons with spin up                             */
+  int32_t n_beta;        /* electrons with spin down                           */
+  const double *h;       /* [N][N] symmetric one-electron integrals (Hartree)  */
+  int32_t n_chol;        /* K > 0: two-electron integrals as Cholesky vectors  */
+  const double *L;       /* [K][N][N] symmetric, (pq|rs) = sum_k L[k][p][q] L[k][r][s] */
+  const double *g;       /* [N][N][N][N] (pq|rs) when n_chol == 0, else NULL   */
+  double e_core;         /* constant energy                                     */
+} tnqe_hamiltonian;
+
+/* One MPS with its orbital basis.  bond b (0..N) has bond_dim[b] indices,
+ * bond_dim[0] = bond_dim[N] = 1; index x of bond b carries the quantum numbers
+ * (n_alpha, n_beta) of sites 0..b-1 in bond_qn; indices sorted by sector.
+ * Site p is [bond_dim[p]][4][bond_dim[p+1]] row-major; entry [l][k][r] must be
+ * zero unless qn(r) = qn(l) + (k & 1, k >> 1).  Sites are concatenated in p
+ * order.  Host pointers. */
+typedef struct {
+  const int32_t *bond_dim;   /* [N+1]                                   */
+  const int32_t *bond_qn;    /* [sum_b bond_dim[b]][2]                  */
+  const double *sites;       /* concatenated site tensors               */
+  const double *U;           /* [N][N] orthogonal, column p = orbital p */
+} tnqe_mps;
+
+typedef struct {
+  int32_t chi;               /* truncation cap for the rotated kets (>= 1)            */
+  int32_t chi_cap_override;  /* > 0: use this cap instead of chi (lossless tests)     */
+  int32_t precision;         /* a tnqe_precision value                                 */
+  double eps_S;              /* relative eigenvalue threshold on S (default 1e-12)    */
+  double tau_w;              /* relative discarded-weight floor (default 1e-13)       */
+  int32_t max_sweeps;        /* Jacobi sweep limit (default 40)                        */
+  int32_t reserved[7];
+} tnqe_options;
+
+typedef struct {
+  double max_discarded_weight_sum;  /* max over pairs of the summed discarded weights  */
+  double min_rel_gap;               /* min over truncations of (s_kept - s_next)/s_kept */
+  double cond_S;                    /* lambda_max / lambda_min(kept) of S               */
+  double lambda_min_S;              /* smallest eigenvalue of S                         */
+  double kappa1;                    /* |c|^2 / sqrt(E^2 + 1)                            */
+  double t_total_ms, t_host_ms, t_gates_ms, t_env_ms, t_gep_ms;
+  double alg_flops;                 /* algorithmic (nonzero-block) flops of the call    */
+  double alg_bytes;                 /* algorithmic HBM bytes of the environment sweep   */
+  double env_flops;                 /* environment-sweep part of alg_flops              */
+  double env_kernel_ms;             /* summed device time of the environment kernels     */
+  int32_t n_dropped;                /* eigenvalues of S below the threshold             */
+  int32_t n_pairs;                  /* unique pairs computed (M (M + 1) / 2)            */
+  int32_t max_bond;                 /* largest bond dimension seen                      */
+  int32_t mpo_max_bond;             /* largest MPO bond dimension                       */
+  int32_t reserved[8];
+} tnqe_report;
+
+/* Fill defaults (chi = 16, FP64, eps_S = 1e-12, tau_w = 1e-13). */
+void tnqe_default_options(tnqe_options *opts);
+
+/* Create a context on HIP device `device` issuing all work on `hip_stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * null stream).  Fails with TNQE_ENODEVICE if the device is not gfx950. */
+tnqe_status tnqe_create(tnqe_ctx **out, int device, void *hip_stream);
+tnqe_status tnqe_destroy(tnqe_ctx *ctx);
+/* Release the context's cached device memory. */
+tnqe_status tnqe_trim(tnqe_ctx *ctx);
+
+/* Validate inputs and copy them to device memory (the only host-to-device
+ * transfer of problem data).  Validation: shapes, |U^T U - I|_max <= 1e-10,
+ * zero entries outside particle-number blocks, finite values, each MPS in the
+ * (n_alpha, n_beta) sector. */
+tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M,
+                        const tnqe_mps *mps, tnqe_problem **out);
+tnqe_status tnqe_problem_free(tnqe_problem *prob);
+
+/* H, S: [M][M] host, row-major; E: [1]; c: [M] or NULL; rep: or NULL. */
+tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *prob, const tnqe_options *opts,
+                       double *H, double *S, double *E, double *c, tnqe_report *rep);
+
+/* Several independent subspaces in one call; their work is batched into the
+ * same launches.  H[s], S[s]: [M_s][M_s] host; E: [n]; rep: [n] or NULL. */
+tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *probs,
+                             const tnqe_options *opts, double *const *H, double *const *S,
+                             double *E, tnqe_report *rep);
+
+/* upload + solve + free in one call. */
+tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M,
+                          const tnqe_mps *mps, const tnqe_options *opts,
+                          double *H, double *S, double *E, double *c, tnqe_report *rep);
+
+const char *tnqe_status_string(tnqe_status st);
+const char *tnqe_last_error(const tnqe_ctx *ctx);
+const char *tnqe_version(void);
+
+/* Host-only diagnostics (no device needed), used to test the host logic.
+ *
+ * tnqe_debug_givens: the Givens plan of an N x N orthogonal W (row-major):
+ *   pos[K], theta[K] in application order, K = N (N - 1) / 2, and det_sign.
+ * tnqe_debug_gate: the 16 x 16 gate g4(theta) on (k_p, k_{p+1}), row-major,
+ *   index k_p * 4 + k_{p+1}.
+ * tnqe_debug_mpo_dense: the library's MPO of H (N <= 5) contracted to dense
+ *   4^N x 4^N matrices of H and of the identity channel, for h [N][N] and
+ *   (pq|rs) g [N^4]; max_bond may be NULL. */
+tnqe_status tnqe_debug_givens(int32_t N, const double *W, int32_t *pos, double *theta, int32_t *det_sign);
+tnqe_status tnqe_debug_gate(double theta, double *out);
+tnqe_status tnqe_debug_mpo_dense(int32_t N, const double *h, const double *g, double *H, double *I,
+                                 int32_t *max_bond);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNQE_H */

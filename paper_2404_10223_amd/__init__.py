@@ -1,0 +1,261 @@
+"""Python binding of libtnqe.so (ctypes; argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module only packs
+NumPy arrays into the C structs declared in include/tnqe.h, passes torch's
+current HIP stream, and unpacks results.  It fails loudly when the library is
+not built or no gfx950 device is present: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnqe.so")
+
+TNQE_FP64 = 0
+TNQE_ENV_FP32 = 1
+PRECISIONS = {"fp64": TNQE_FP64, "fp32": TNQE_ENV_FP32}
+
+
+class _Ham(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n_alpha", C.c_int32), ("n_beta", C.c_int32),
+                ("h", C.POINTER(C.c_double)), ("n_chol", C.c_int32),
+                ("L", C.POINTER(C.c_double)), ("g", C.POINTER(C.c_double)), ("e_core", C.c_double)]
+
+
+class _Mps(C.Structure):
+    _fields_ = [("bond_dim", C.POINTER(C.c_int32)), ("bond_qn", C.POINTER(C.c_int32)),
+                ("sites", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double))]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("chi", C.c_int32), ("chi_cap_override", C.c_int32), ("precision", C.c_int32),
+                ("eps_S", C.c_double), ("tau_w", C.c_double), ("max_sweeps", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("max_discarded_weight_sum", C.c_double), ("min_rel_gap", C.c_double),
+                ("cond_S", C.c_double), ("lambda_min_S", C.c_double), ("kappa1", C.c_double),
+                ("t_total_ms", C.c_double), ("t_host_ms", C.c_double), ("t_gates_ms", C.c_double),
+                ("t_env_ms", C.c_double), ("t_gep_ms", C.c_double), ("alg_flops", C.c_double),
+                ("alg_bytes", C.c_double), ("env_flops", C.c_double), ("env_kernel_ms", C.c_double),
+                ("n_dropped", C.c_int32), ("n_pairs", C.c_int32), ("max_bond", C.c_int32),
+                ("mpo_max_bond", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
+           "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_subspace",
+           "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
+           "tnqe_debug_gate", "tnqe_debug_mpo_dense"]
+
+_lib = None
+
+
+def lib():
+    """Load libtnqe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2404_10223_amd/build.py")
+    # torch ships its own HIP runtime under the same soname; loading it first
+    # makes the library bind to that one runtime, so torch's streams and ours
+    # are the same objects
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, ip = C.c_void_p, C.c_int32
+    dp = C.POINTER(C.c_double)
+    L.tnqe_default_options.argtypes = [C.POINTER(_Opts)]
+    L.tnqe_default_options.restype = None
+    L.tnqe_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.tnqe_destroy.argtypes = [vp]
+    L.tnqe_trim.argtypes = [vp]
+    L.tnqe_upload.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(vp)]
+    L.tnqe_problem_free.argtypes = [vp]
+    L.tnqe_solve.argtypes = [vp, vp, C.POINTER(_Opts), dp, dp, dp, dp, C.POINTER(_Report)]
+    L.tnqe_solve_batch.argtypes = [vp, ip, C.POINTER(vp), C.POINTER(_Opts), C.POINTER(dp), C.POINTER(dp),
+                                   dp, C.POINTER(_Report)]
+    L.tnqe_subspace.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), dp, dp, dp, dp,
+                                C.POINTER(_Report)]
+    L.tnqe_status_string.argtypes = [C.c_int]
+    L.tnqe_status_string.restype = C.c_char_p
+    L.tnqe_last_error.argtypes = [vp]
+    L.tnqe_last_error.restype = C.c_char_p
+    L.tnqe_version.restype = C.c_char_p
+    L.tnqe_debug_givens.argtypes = [ip, dp, C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]
+    L.tnqe_debug_gate.argtypes = [C.c_double, dp]
+    L.tnqe_debug_mpo_dense.argtypes = [ip, dp, dp, dp, dp, C.POINTER(C.c_int32)]
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class TnqeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tnqe status {status}: {msg}")
+        self.status = status
+
+
+def _check(st, ctx=None):
+    if st != 0:
+        L = lib()
+        msg = L.tnqe_last_error(ctx).decode() if ctx else ""
+        raise TnqeError(st, f"{L.tnqe_status_string(st).decode()}: {msg}")
+
+
+def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-13, max_sweeps=40):
+    o = _Opts()
+    lib().tnqe_default_options(C.byref(o))
+    o.chi = chi
+    o.chi_cap_override = chi_cap_override
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.eps_S = eps_S
+    o.tau_w = tau_w
+    o.max_sweeps = max_sweeps
+    return o
+
+
+def report_dict(r):
+    return {name: getattr(r, name) for name, _ in _Report._fields_ if name != "reserved"}
+
+
+class _Packed:
+    """Keeps the NumPy buffers alive while the C structs point at them."""
+
+    def __init__(self, prob):
+        self.h = np.ascontiguousarray(prob.h, dtype=np.float64)
+        self.L = np.ascontiguousarray(prob.L, dtype=np.float64)
+        self.ham = _Ham(prob.N, prob.n_alpha, prob.n_beta, _dptr(self.h), self.L.shape[0], _dptr(self.L),
+                        None, float(prob.e_core))
+        self.keep = []
+        arr = (_Mps * prob.M)()
+        for i, m in enumerate(prob.mps):
+            dims = np.array([q.shape[0] for q in m.bond_qn], dtype=np.int32)
+            qn = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.int32).reshape(-1, 2)
+                                                      for q in m.bond_qn]))
+            sites = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1)
+                                                         for a in m.sites]))
+            U = np.ascontiguousarray(m.U, dtype=np.float64)
+            self.keep += [dims, qn, sites, U]
+            arr[i] = _Mps(_iptr(dims), _iptr(qn), _dptr(sites), _dptr(U))
+        self.mps = arr
+
+
+class Context:
+    """A library context on one GPU, issuing work on torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.L = lib()
+        h = C.c_void_p()
+        _check(self.L.tnqe_create(C.byref(h), device, C.c_void_p(stream)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.L.tnqe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, prob):
+        pk = _Packed(prob)
+        out = C.c_void_p()
+        _check(self.L.tnqe_upload(self.h, C.byref(pk.ham), prob.M, pk.mps, C.byref(out)), self.h)
+        return Uploaded(self, out, prob.M)
+
+    def subspace(self, prob, **kw):
+        up = self.upload(prob)
+        try:
+            return up.solve(**kw)
+        finally:
+            up.free()
+
+    def solve_batch(self, uploaded, **kw):
+        n = len(uploaded)
+        o = options(**kw)
+        Hs = [np.zeros((u.M, u.M)) for u in uploaded]
+        Ss = [np.zeros((u.M, u.M)) for u in uploaded]
+        E = np.zeros(n)
+        reps = (_Report * n)()
+        handles = (C.c_void_p * n)(*[u.handle.value for u in uploaded])
+        hp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Hs])
+        sp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Ss])
+        _check(self.L.tnqe_solve_batch(self.h, n, handles, C.byref(o), hp, sp, _dptr(E), reps), self.h)
+        return Hs, Ss, E, [report_dict(r) for r in reps]
+
+
+class Uploaded:
+    """Problem data resident in device memory."""
+
+    def __init__(self, ctx, handle, M):
+        self.ctx, self.handle, self.M = ctx, handle, M
+
+    def solve(self, **kw):
+        o = options(**kw)
+        M = self.M
+        H = np.zeros((M, M))
+        S = np.zeros((M, M))
+        E = np.zeros(1)
+        c = np.zeros(M)
+        r = _Report()
+        _check(self.ctx.L.tnqe_solve(self.ctx.h, self.handle, C.byref(o), _dptr(H), _dptr(S), _dptr(E), _dptr(c),
+                                     C.byref(r)), self.ctx.h)
+        return H, S, float(E[0]), c, report_dict(r)
+
+    def free(self):
+        if self.handle:
+            self.ctx.L.tnqe_problem_free(self.handle)
+            self.handle = None
+
+
+# ------------------------------------------------------------- host diagnostics
+def debug_givens(W):
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    N = W.shape[0]
+    K = N * (N - 1) // 2
+    pos = np.zeros(max(K, 1), dtype=np.int32)
+    th = np.zeros(max(K, 1))
+    det = np.zeros(1, dtype=np.int32)
+    _check(lib().tnqe_debug_givens(N, _dptr(W), _iptr(pos), _dptr(th), _iptr(det)))
+    return list(zip(pos[:K].tolist(), th[:K].tolist())), int(det[0])
+
+
+def debug_gate(theta):
+    out = np.zeros(256)
+    _check(lib().tnqe_debug_gate(float(theta), _dptr(out)))
+    return out.reshape(16, 16)
+
+
+def debug_mpo_dense(h, g):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    N = h.shape[0]
+    D = 4 ** N
+    H = np.zeros((D, D))
+    I = np.zeros((D, D))
+    mb = np.zeros(1, dtype=np.int32)
+    _check(lib().tnqe_debug_mpo_dense(N, _dptr(h), _dptr(g), _dptr(H), _dptr(I), _iptr(mb)))
+    return H, I, int(mb[0])

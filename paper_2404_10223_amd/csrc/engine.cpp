@@ -1,0 +1,1577 @@
+// Orchestration of one subspace solve on the device, and the C ABI.
+//
+// Phase 1 (gates): every off-diagonal pair i < j gets its own copy of the
+// left-canonical MPS j; the Givens network of U_i^T U_j is applied gate by
+// gate, all pairs in lock step (the gate positions only depend on N).  A gate
+// step is: exact LQ centre moves (if the run restarts further left), the
+// two-site contraction with the gate, a per-quantum-number-block SVD, a host
+// decision on the kept singular values (global top-chi per pair), and the
+// split.  Phase 2 (environments): all pairs, including i = j, sweep bra x MPO
+// x ket from left to right in a sector-padded common layout, so every pair
+// shares one set of block descriptors.  Phase 3: the M x M eigenproblem.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace tnqe {
+
+// ------------------------------------------------------------ memory helpers
+void *DevicePool::get(size_t bytes) {
+  bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+  int best = -1;
+  for (size_t i = 0; i < bufs_.size(); ++i)
+    if (!bufs_[i].used && bufs_[i].n >= bytes && (best < 0 || bufs_[i].n < bufs_[best].n)) best = (int)i;
+  if (best >= 0) {
+    bufs_[best].used = true;
+    order_.push_back(bufs_[best].p);
+    return bufs_[best].p;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    // free idle buffers and retry once
+    for (size_t i = 0; i < bufs_.size();) {
+      if (!bufs_[i].used) {
+        (void)hipFree(bufs_[i].p);
+        held_ -= bufs_[i].n;
+        bufs_.erase(bufs_.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(TNQE_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  bufs_.push_back({p, bytes, true});
+  order_.push_back(p);
+  held_ += bytes;
+  return p;
+}
+
+void DevicePool::rewind(size_t m) {
+  while (order_.size() > m) {
+    void *p = order_.back();
+    order_.pop_back();
+    for (auto &b : bufs_)
+      if (b.p == p) b.used = false;
+  }
+}
+
+void DevicePool::release_all() {
+  for (auto &b : bufs_) b.used = false;
+  order_.clear();
+}
+
+void DevicePool::trim() {
+  for (auto &b : bufs_) (void)hipFree(b.p);
+  bufs_.clear();
+  order_.clear();
+  held_ = 0;
+}
+
+Staging::~Staging() {
+  if (buf_) (void)hipHostFree(buf_);
+  for (auto &o : old_) (void)hipHostFree(o.first);
+}
+
+void Staging::reset() {
+  used_ = 0;
+  for (auto &o : old_) (void)hipHostFree(o.first);
+  old_.clear();
+}
+
+void *Staging::put(const void *src, size_t bytes) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (used_ + need > cap_) {
+    // keep the old buffer alive until the next reset (copies may be in flight)
+    if (buf_) old_.push_back({buf_, cap_});
+    cap_ = std::max<size_t>(need, std::max<size_t>(64u << 20, cap_ * 2));
+    TNQE_HIP(hipHostMalloc((void **)&buf_, cap_, hipHostMallocDefault));
+    used_ = 0;
+  }
+  char *p = buf_ + used_;
+  std::memcpy(p, src, bytes);
+  used_ += need;
+  return p;
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+struct Call {   // per-call helpers bound to a context
+  tnqe_ctx *ctx;
+  template <typename T>
+  T *dev(size_t n) {
+    return static_cast<T *>(ctx->pool.get(std::max<size_t>(1, n) * sizeof(T)));
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v) {
+    T *d = dev<T>(v.size());
+    if (!v.empty()) {
+      void *h = ctx->staging.put(v.data(), v.size() * sizeof(T));
+      TNQE_HIP(hipMemcpyAsync(d, h, v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    }
+    return d;
+  }
+  template <typename T>
+  void upload_to(T *d, const T *src, size_t n) {
+    if (n == 0) return;
+    void *h = ctx->staging.put(src, n * sizeof(T));
+    TNQE_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  }
+  void sync() {
+    TNQE_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->staging.reset();
+  }
+  void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(TNQE_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+};
+
+// ------------------------------------------------------------ small host math
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Givens plan: see the header of tnqe.h.  gates in application order.
+void givens_plan(int N, const double *W, std::vector<int> &pos, std::vector<double> &theta, int &det_sign) {
+  std::vector<double> Q(W, W + (size_t)N * N);
+  std::vector<int> ea;
+  std::vector<double> et;
+  for (int c = 0; c + 1 < N; ++c)
+    for (int r = N - 1; r > c; --r) {
+      const int a = r - 1;
+      const double x = Q[a * N + c], y = Q[r * N + c];
+      const double th = (x == 0.0 && y == 0.0) ? 0.0 : std::atan2(-y, x);
+      const double cs = std::cos(th), sn = std::sin(th);
+      for (int col = 0; col < N; ++col) {
+        const double qa = Q[a * N + col], qr = Q[r * N + col];
+        Q[a * N + col] = cs * qa - sn * qr;
+        Q[r * N + col] = sn * qa + cs * qr;
+      }
+      ea.push_back(a);
+      et.push_back(th);
+    }
+  det_sign = (N == 0 || Q[(N - 1) * N + N - 1] > 0.0) ? 1 : -1;
+  pos.assign(ea.rbegin(), ea.rend());
+  theta.assign(et.rbegin(), et.rend());
+}
+
+// Spatial-orbital Givens gate on (k_p, k_{p+1}), built as the composite
+// (1 x f2 x 1)(g2 x g2)(1 x f2 x 1) of App. A3 over the modes
+// (p up, p dn, p+1 up, p+1 dn) and relabelled to k = n_up + 2 n_dn.
+void gate_g4(double th, double out[256]) {
+  const double c = std::cos(th), s = std::sin(th);
+  const double f2[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, -1};
+  const double g2[16] = {1, 0, 0, 0, 0, c, -s, 0, 0, s, c, 0, 0, 0, 0, 1};
+  auto kron = [](const double *A, int m, const double *B, int n, double *C) {
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < m; ++k)
+          for (int l = 0; l < n; ++l) C[(i * n + j) * (m * n) + k * n + l] = A[i * m + k] * B[j * n + l];
+  };
+  const double I2[4] = {1, 0, 0, 1};
+  double t8[64], mid[256], core[256], tmp[256], G[256];
+  kron(I2, 2, f2, 4, t8);
+  kron(t8, 8, I2, 2, mid);
+  kron(g2, 4, g2, 4, core);
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      double a = 0.0;
+      for (int k = 0; k < 16; ++k) a += mid[i * 16 + k] * core[k * 16 + j];
+      tmp[i * 16 + j] = a;
+    }
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      double a = 0.0;
+      for (int k = 0; k < 16; ++k) a += tmp[i * 16 + k] * mid[k * 16 + j];
+      G[i * 16 + j] = a;
+    }
+  const int perm[4] = {0, 2, 1, 3};   // k -> mode-bit index (n_up, n_dn)
+  for (int k1 = 0; k1 < 4; ++k1)
+    for (int k2 = 0; k2 < 4; ++k2)
+      for (int l1 = 0; l1 < 4; ++l1)
+        for (int l2 = 0; l2 < 4; ++l2)
+          out[(k1 * 4 + k2) * 16 + l1 * 4 + l2] = G[(perm[k1] * 4 + perm[k2]) * 16 + perm[l1] * 4 + perm[l2]];
+}
+
+// ------------------------------------------------------------ ket sets
+// A batch of MPS being transformed on the device (one per off-diagonal pair,
+// or one per input MPS during canonicalisation).
+struct KetSet {
+  Call *call = nullptr;
+  int n = 0, N = 0, na = 0, nb = 0, nslot = 0;
+  std::vector<int> cap;                 // capacity per bond
+  std::vector<int> hdim;                // [bond][ket][slot]
+  std::vector<int> htot;                // [bond][ket]
+  std::vector<int2> hbtab;              // [bond][ket][slot]
+  int2 *dbtab = nullptr;
+  int *dbdim = nullptr;
+  double *dsites = nullptr;
+  std::vector<double *> site_ptr;       // [ket * N + p]
+  double **dsite_ptr = nullptr;
+  std::vector<int64_t> site_cap;        // doubles per site
+
+  int &dim(int b, int t, int s) { return hdim[((size_t)b * n + t) * nslot + s]; }
+  int slot(int a, int bb) const { return (a < 0 || bb < 0 || a > na || bb > nb) ? -1 : a * (nb + 1) + bb; }
+  int dim_q(int b, int t, int a, int bb) {
+    const int s = slot(a, bb);
+    return s < 0 ? 0 : dim(b, t, s);
+  }
+  int off_q(int b, int t, int a, int bb) {
+    const int s = slot(a, bb);
+    return s < 0 ? 0 : hbtab[((size_t)b * n + t) * nslot + s].x;
+  }
+  void init(Call *c, int nk, int N_, int na_, int nb_, const std::vector<int> &cap_) {
+    call = c;
+    n = nk;
+    N = N_;
+    na = na_;
+    nb = nb_;
+    nslot = (na + 1) * (nb + 1);
+    cap = cap_;
+    hdim.assign((size_t)(N + 1) * n * nslot, 0);
+    htot.assign((size_t)(N + 1) * n, 0);
+    hbtab.assign((size_t)(N + 1) * n * nslot, make_int2(0, 0));
+    dbtab = call->dev<int2>(hbtab.size());
+    dbdim = call->dev<int>(htot.size());
+    site_cap.resize(N);
+    int64_t per = 0;
+    for (int p = 0; p < N; ++p) {
+      site_cap[p] = (int64_t)cap[p] * 4 * cap[p + 1];
+      per += site_cap[p];
+    }
+    dsites = call->dev<double>((size_t)per * n);
+    site_ptr.resize((size_t)n * N);
+    for (int t = 0; t < n; ++t) {
+      int64_t o = (int64_t)t * per;
+      for (int p = 0; p < N; ++p) {
+        site_ptr[(size_t)t * N + p] = dsites + o;
+        o += site_cap[p];
+      }
+    }
+    dsite_ptr = call->upload(site_ptr);
+  }
+  // recompute offsets of bond b on the host and upload that slice
+  void commit_bond(int b) {
+    for (int t = 0; t < n; ++t) {
+      int o = 0;
+      for (int s = 0; s < nslot; ++s) {
+        const int d = dim(b, t, s);
+        hbtab[((size_t)b * n + t) * nslot + s] = make_int2(o, d);
+        o += d;
+      }
+      require(o <= cap[b], TNQE_ESHAPE, "bond dimension exceeds its capacity");
+      htot[(size_t)b * n + t] = o;
+    }
+    call->upload_to(dbtab + (size_t)b * n * nslot, hbtab.data() + (size_t)b * n * nslot, (size_t)n * nslot);
+    call->upload_to(dbdim + (size_t)b * n, htot.data() + (size_t)b * n, (size_t)n);
+  }
+  KetTables tables() const {
+    KetTables k;
+    k.site = dsite_ptr;
+    k.btab = dbtab;
+    k.bdim = dbdim;
+    k.npair = n;
+    k.N = N;
+    k.na = na;
+    k.nb = nb;
+    k.nslot = nslot;
+    return k;
+  }
+};
+
+constexpr int kLdsDoubles = 19 * 1024;   // 152 KiB of the 160 KiB per workgroup
+
+struct Scratch {
+  int64_t used = 0;
+  int64_t take(int64_t n) {
+    const int64_t o = used;
+    used += (n + 31) & ~int64_t(31);
+    return o;
+  }
+};
+
+// plan the SVD storage of a block; returns the LDS doubles it needs (0 if global)
+int plan_block_storage(Blk &b, Scratch &sc) {
+  b.n = std::min(b.R, b.C);
+  b.offT = sc.take((int64_t)b.R * b.C);
+  b.offU = sc.take((int64_t)b.R * b.n);
+  b.offB = sc.take((int64_t)b.n * b.C);
+  b.offS = -1;
+  const int64_t need = (int64_t)b.n * std::max(b.R, b.C) + (int64_t)b.n * b.n + b.n;
+  if (need <= kLdsDoubles) {
+    b.offW = -1;
+    return (int)need;
+  }
+  b.offW = sc.take(need);
+  return 0;
+}
+
+struct TruncStats {
+  std::vector<double> discarded;   // per ket, summed
+  double min_gap = 1.0;
+  int max_bond = 0;
+};
+
+// One exact LQ centre move (site q -> q-1) for every ket in the set.
+void move_left(KetSet &ks, int q, int max_sweeps) {
+  Call &c = *ks.call;
+  std::vector<Blk> blks;
+  Scratch sc;
+  int lds = 0;
+  for (int t = 0; t < ks.n; ++t) {
+    for (int s = 0; s < ks.nslot; ++s) {
+      const int d = ks.dim(q, t, s);
+      if (d == 0) continue;
+      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      Blk b{};
+      b.pair = t;
+      b.sa = sa;
+      b.sb = sb;
+      b.R = d;
+      b.cs[0] = 0;
+      for (int k = 0; k < 4; ++k) b.cs[k + 1] = b.cs[k] + ks.dim_q(q + 1, t, sa + qk_a(k), sb + qk_b(k));
+      for (int k = 0; k <= 4; ++k) b.rs[k] = 0;
+      b.C = b.cs[4];
+      b.aux0 = ks.off_q(q, t, sa, sb);
+      b.aux1 = ks.htot[(size_t)q * ks.n + t];
+      if (b.C == 0) continue;
+      lds = std::max(lds, plan_block_storage(b, sc));
+      blks.push_back(b);
+    }
+  }
+  // new bond q: min(R, C) per sector
+  for (int t = 0; t < ks.n; ++t)
+    for (int s = 0; s < ks.nslot; ++s) ks.dim(q, t, s) = 0;
+  for (Blk &b : blks) ks.dim(q, b.pair, ks.slot(b.sa, b.sb)) = b.n;
+  for (Blk &b : blks) {
+    b.offS = sc.take(b.n);
+    b.kept = b.n;
+  }
+  for (Blk &b : blks) {   // j0 in the new bond
+    int acc = 0;
+    const int sl = ks.slot(b.sa, b.sb);
+    for (int s = 0; s < sl; ++s) acc += ks.dim(q, b.pair, s);
+    b.j0 = acc;
+  }
+  double *scratch = c.dev<double>(sc.used);
+  // copy of the old left neighbour of every ket
+  std::vector<double *> olds(ks.n), srcs(ks.n);
+  std::vector<int64_t> cnt(ks.n);
+  double *oldbuf = c.dev<double>((size_t)ks.site_cap[q - 1] * ks.n);
+  for (int t = 0; t < ks.n; ++t) {
+    olds[t] = oldbuf + (size_t)t * ks.site_cap[q - 1];
+    srcs[t] = ks.site_ptr[(size_t)t * ks.N + q - 1];
+    cnt[t] = (int64_t)ks.htot[(size_t)(q - 1) * ks.n + t] * 4 * ks.htot[(size_t)q * ks.n + t];
+  }
+  double **d_old = c.upload(olds);
+  launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
+  Blk *dblk = c.upload(blks);
+  const KetTables kt_old = ks.tables();
+  launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
+  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  ks.commit_bond(q);
+  launch_apply_lq(ks.tables(), q, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
+  c.check_launch();
+}
+
+// One exact QR centre move (site p -> p+1) for every ket in the set.
+void move_right(KetSet &ks, int p, int max_sweeps) {
+  Call &c = *ks.call;
+  std::vector<Blk> blks;
+  Scratch sc;
+  int lds = 0;
+  for (int t = 0; t < ks.n; ++t) {
+    for (int s = 0; s < ks.nslot; ++s) {
+      const int d = ks.dim(p + 1, t, s);
+      if (d == 0) continue;
+      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      Blk b{};
+      b.pair = t;
+      b.sa = sa;
+      b.sb = sb;
+      b.C = d;
+      b.rs[0] = 0;
+      for (int k = 0; k < 4; ++k) b.rs[k + 1] = b.rs[k] + ks.dim_q(p, t, sa - qk_a(k), sb - qk_b(k));
+      for (int k = 0; k <= 4; ++k) b.cs[k] = 0;
+      b.R = b.rs[4];
+      b.aux0 = ks.off_q(p + 1, t, sa, sb);
+      b.aux1 = ks.htot[(size_t)(p + 1) * ks.n + t];
+      if (b.R == 0) continue;
+      lds = std::max(lds, plan_block_storage(b, sc));
+      blks.push_back(b);
+    }
+  }
+  for (int t = 0; t < ks.n; ++t)
+    for (int s = 0; s < ks.nslot; ++s) ks.dim(p + 1, t, s) = 0;
+  for (Blk &b : blks) ks.dim(p + 1, b.pair, ks.slot(b.sa, b.sb)) = b.n;
+  for (Blk &b : blks) {
+    b.offS = sc.take(b.n);
+    b.kept = b.n;
+    int acc = 0;
+    const int sl = ks.slot(b.sa, b.sb);
+    for (int s = 0; s < sl; ++s) acc += ks.dim(p + 1, b.pair, s);
+    b.j0 = acc;
+  }
+  double *scratch = c.dev<double>(sc.used);
+  std::vector<double *> olds(ks.n), srcs(ks.n);
+  std::vector<int64_t> cnt(ks.n);
+  double *oldbuf = c.dev<double>((size_t)ks.site_cap[p + 1] * ks.n);
+  for (int t = 0; t < ks.n; ++t) {
+    olds[t] = oldbuf + (size_t)t * ks.site_cap[p + 1];
+    srcs[t] = ks.site_ptr[(size_t)t * ks.N + p + 1];
+    cnt[t] = (int64_t)ks.htot[(size_t)(p + 1) * ks.n + t] * 4 * ks.htot[(size_t)(p + 2) * ks.n + t];
+  }
+  double **d_old = c.upload(olds);
+  launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
+  Blk *dblk = c.upload(blks);
+  launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
+  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  ks.commit_bond(p + 1);
+  launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
+  c.check_launch();
+}
+
+// Gate at (a, a+1) for every ket with its own 16x16 matrix, then truncation.
+void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap, double tau_w,
+               int max_sweeps, TruncStats &ts) {
+  Call &c = *ks.call;
+  std::vector<Blk> blks;
+  Scratch sc;
+  int lds = 0;
+  for (int t = 0; t < ks.n; ++t) {
+    for (int s = 0; s < ks.nslot; ++s) {
+      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      Blk b{};
+      b.pair = t;
+      b.sa = sa;
+      b.sb = sb;
+      b.rs[0] = b.cs[0] = 0;
+      for (int k = 0; k < 4; ++k) {
+        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
+        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
+      }
+      b.R = b.rs[4];
+      b.C = b.cs[4];
+      if (b.R == 0 || b.C == 0) continue;
+      lds = std::max(lds, plan_block_storage(b, sc));
+      blks.push_back(b);
+    }
+  }
+  // singular values contiguous for one download
+  int64_t s0 = sc.used, ns = 0;
+  for (Blk &b : blks) {
+    b.offS = s0 + ns;
+    ns += b.n;
+  }
+  sc.used += ns;
+  double *scratch = c.dev<double>(sc.used);
+  double *dgates = c.upload(gates);
+  Blk *dblk = c.upload(blks);
+  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), dgates, scratch, c.ctx->stream);
+  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  c.check_launch();
+  std::vector<double> sv(ns);
+  TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
+  c.sync();
+  // global top-chi per ket
+  std::vector<std::vector<int>> per(ks.n);
+  for (size_t i = 0; i < blks.size(); ++i) per[blks[i].pair].push_back((int)i);
+  for (int t = 0; t < ks.n; ++t) {
+    std::vector<std::pair<double, int64_t>> all;   // (sigma, global index) in block order
+    double tot = 0.0;
+    for (int bi : per[t]) {
+      const Blk &b = blks[bi];
+      for (int j = 0; j < b.n; ++j) {
+        const double sgm = sv[b.offS - s0 + j];
+        all.push_back({sgm, (int64_t)(b.offS - s0 + j)});
+        tot += sgm * sgm;
+      }
+    }
+    std::vector<size_t> order(all.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return all[x].first > all[y].first; });
+    int nnz = 0;
+    for (auto &v : all) nnz += (v.first * v.first > tau_w * tot) ? 1 : 0;
+    const int keep = std::min(chi_cap, nnz);
+    std::vector<char> kept(all.size(), 0);
+    for (int r = 0; r < keep; ++r) kept[order[r]] = 1;
+    double disc = 0.0;
+    for (size_t i = 0; i < all.size(); ++i)
+      if (!kept[i]) disc += all[i].first * all[i].first;
+    ts.discarded[t] += disc;
+    if (keep > 0 && (size_t)keep < all.size()) {
+      const double si = all[order[keep - 1]].first, so = all[order[keep]].first;
+      if (si > 0.0) ts.min_gap = std::min(ts.min_gap, (si - so) / si);
+    }
+    // kept counts per block (a prefix of each block's sorted list)
+    size_t gi = 0;
+    for (int bi : per[t]) {
+      Blk &b = blks[bi];
+      int k = 0;
+      for (int j = 0; j < b.n; ++j, ++gi) k += kept[gi];
+      b.kept = k;
+    }
+    ts.max_bond = std::max(ts.max_bond, keep);
+  }
+  for (int t = 0; t < ks.n; ++t)
+    for (int s = 0; s < ks.nslot; ++s) ks.dim(a + 1, t, s) = 0;
+  for (Blk &b : blks) ks.dim(a + 1, b.pair, ks.slot(b.sa, b.sb)) = b.kept;
+  for (Blk &b : blks) {
+    int acc = 0;
+    const int sl = ks.slot(b.sa, b.sb);
+    for (int s = 0; s < sl; ++s) acc += ks.dim(a + 1, b.pair, s);
+    b.j0 = acc;
+  }
+  ks.commit_bond(a + 1);
+  Blk *dblk2 = c.upload(blks);
+  launch_split_gate(ks.tables(), a, dblk2, (int)blks.size(), scratch, c.ctx->stream);
+  c.check_launch();
+}
+
+// ------------------------------------------------------------ environment sweep
+struct EnvResult {
+  std::vector<double> H, S;   // per env pair
+  double flops = 0.0, bytes = 0.0, kernel_ms = 0.0;
+  int max_pad = 0;
+};
+
+template <typename T>
+void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
+               const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
+               int64_t nnz_total, EnvResult &res) {
+  hipStream_t st = c.ctx->stream;
+  const int N = pb.N, M = pb.M, nslot = pb.nslot(), nb1 = pb.nb + 1;
+  const int nket = kets ? kets->n : 0;
+  auto slot_of = [&](int a, int b) { return (a < 0 || b < 0 || a > pb.na || b > pb.nb) ? -1 : a * nb1 + b; };
+  // ---- common padded bond structure
+  std::vector<std::vector<int>> dpad(N + 1, std::vector<int>(nslot, 0)), opad(N + 1, std::vector<int>(nslot, 0));
+  std::vector<int> Dpad(N + 1, 0);
+  for (int b = 0; b <= N; ++b) {
+    for (int s = 0; s < nslot; ++s) {
+      int d = 0;
+      for (int i = 0; i < M; ++i) d = std::max(d, pb.mps[i].secdim[b][s]);
+      for (int t = 0; t < nket; ++t) d = std::max(d, kets->dim(b, t, s));
+      dpad[b][s] = d;
+    }
+    int o = 0;
+    for (int s = 0; s < nslot; ++s) {
+      opad[b][s] = o;
+      o += dpad[b][s];
+    }
+    Dpad[b] = o;
+    res.max_pad = std::max(res.max_pad, o);
+  }
+  auto dp = [&](int b, int s) { return s < 0 ? 0 : dpad[b][s]; };
+  // ---- repack bras and kets into the padded layout
+  const int nitem = M + nket;
+  std::vector<int64_t> psite_off(N + 1, 0);
+  for (int p = 0; p < N; ++p) psite_off[p + 1] = psite_off[p] + (int64_t)Dpad[p] * 4 * Dpad[p + 1];
+  const int64_t per_item = psite_off[N];
+  double *pad64 = c.dev<double>((size_t)per_item * nitem);
+  T *padT = std::is_same<T, double>::value ? reinterpret_cast<T *>(pad64) : c.dev<T>((size_t)per_item * nitem);
+  for (int p = 0; p < N; ++p) {
+    std::vector<const double *> src(nitem);
+    std::vector<double *> dst64(nitem);
+    std::vector<T *> dstT(nitem);
+    std::vector<int2> tl((size_t)nitem * nslot), tr((size_t)nitem * nslot);
+    std::vector<int> Dr(nitem);
+    for (int it = 0; it < nitem; ++it) {
+      dst64[it] = pad64 + (size_t)it * per_item + psite_off[p];
+      dstT[it] = padT + (size_t)it * per_item + psite_off[p];
+      if (it < M) {
+        const auto &m = pb.mps[it];
+        src[it] = pb.d_sites + m.site_off[p];
+        int ol = 0, orr = 0;
+        for (int s = 0; s < nslot; ++s) {
+          tl[(size_t)it * nslot + s] = make_int2(ol, m.secdim[p][s]);
+          tr[(size_t)it * nslot + s] = make_int2(orr, m.secdim[p + 1][s]);
+          ol += m.secdim[p][s];
+          orr += m.secdim[p + 1][s];
+        }
+        Dr[it] = m.dims[p + 1];
+      } else {
+        const int t = it - M;
+        src[it] = kets->site_ptr[(size_t)t * N + p];
+        for (int s = 0; s < nslot; ++s) {
+          tl[(size_t)it * nslot + s] = kets->hbtab[((size_t)p * kets->n + t) * nslot + s];
+          tr[(size_t)it * nslot + s] = kets->hbtab[((size_t)(p + 1) * kets->n + t) * nslot + s];
+        }
+        Dr[it] = kets->htot[(size_t)(p + 1) * kets->n + t];
+      }
+    }
+    std::vector<int2> pl(Dpad[p]), pr(Dpad[p + 1]);
+    for (int s = 0; s < nslot; ++s) {
+      for (int x = 0; x < dpad[p][s]; ++x) pl[opad[p][s] + x] = make_int2(s, x);
+      for (int x = 0; x < dpad[p + 1][s]; ++x) pr[opad[p + 1][s] + x] = make_int2(s, x);
+    }
+    const size_t mk = c.ctx->pool.mark();
+    const double *const *dsrc = c.upload(src);
+    const int2 *dtl = c.upload(tl), *dtr = c.upload(tr), *dpl = c.upload(pl), *dpr = c.upload(pr);
+    const int *dDr = c.upload(Dr);
+    launch_repack<double>(dsrc, c.upload(dst64), dtl, dtr, dDr, nslot, dpl, dpr, Dpad[p], Dpad[p + 1], nitem, st);
+    if (!std::is_same<T, double>::value)
+      launch_repack<T>(dsrc, c.upload(dstT), dtl, dtr, dDr, nslot, dpl, dpr, Dpad[p], Dpad[p + 1], nitem, st);
+    c.check_launch();
+    c.sync();
+    c.ctx->pool.rewind(mk);
+  }
+  // ---- layouts
+  const auto &cls = mpo.classes;
+  std::vector<std::vector<int64_t>> Loff(N + 1);
+  std::vector<int64_t> Lsize(N + 1, 0);
+  for (int b = 0; b <= N; ++b) {
+    Loff[b].assign(cls[b].size() * nslot, -1);
+    int64_t o = 0;
+    for (size_t ci = 0; ci < cls[b].size(); ++ci)
+      for (int s = 0; s < nslot; ++s) {
+        if (dpad[b][s] == 0) continue;
+        const int sa = s / nb1, sb = s % nb1;
+        const int sbra = slot_of(sa + cls[b][ci].da, sb + cls[b][ci].db);
+        if (dp(b, sbra) == 0) continue;
+        Loff[b][ci * nslot + s] = o;
+        o += (int64_t)dpad[b][sbra] * cls[b][ci].nw * dpad[b][s];
+      }
+    Lsize[b] = o;
+  }
+  // global CSR group index base per site
+  std::vector<int> gbase(N + 1, 0);
+  for (int x = 0; x < N; ++x) gbase[x + 1] = gbase[x] + (int)mpo.groups[x].size();
+  struct SiteTabs {
+    std::vector<GemmDesc> g1, g2;
+    int t1 = 0, t2 = 0, tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
+    std::vector<MixTask> tasks;
+    std::vector<int> chunk0;
+    std::vector<MixSrc> srcs;
+    int nchunk = 0;
+    int64_t Xsize = 0, Ysize = 0;
+    std::vector<int64_t> fin_offY, fin_offBra;
+    std::vector<int> fin_da;
+  };
+  std::vector<SiteTabs> tabs(N);
+  double flops_pp = 0.0, bytes_pp = 0.0;
+  const double eb = sizeof(T);
+  for (int x = 0; x < N; ++x) {
+    SiteTabs &tb = tabs[x];
+    // GEMM1 and X layout
+    std::vector<int64_t> offX(cls[x].size() * nslot * 4, -1);
+    int64_t xo = 0;
+    int maxN1 = 0;
+    for (size_t ci = 0; ci < cls[x].size(); ++ci)
+      for (int s = 0; s < nslot; ++s) {
+        const int64_t lo = Loff[x][ci * nslot + s];
+        if (lo < 0) continue;
+        const int sa = s / nb1, sb = s % nb1;
+        const int sbra = slot_of(sa + cls[x][ci].da, sb + cls[x][ci].db);
+        for (int k = 0; k < 4; ++k) {
+          const int sk = slot_of(sa + qk_a(k), sb + qk_b(k));
+          if (dp(x + 1, sk) == 0) continue;
+          GemmDesc d{};
+          d.M = dpad[x][sbra] * cls[x][ci].nw;
+          d.N = dpad[x + 1][sk];
+          d.ldc = d.N;
+          d.nseg = 1;
+          d.offC = xo;
+          d.seg[0].K = dpad[x][s];
+          d.seg[0].lda = dpad[x][s];
+          d.seg[0].transA = 0;
+          d.seg[0].offA = lo;
+          d.seg[0].offB = ((int64_t)opad[x][s] * 4 + k) * Dpad[x + 1] + opad[x + 1][sk];
+          d.seg[0].ldb = 4 * Dpad[x + 1];
+          offX[(ci * nslot + s) * 4 + k] = xo;
+          xo += (int64_t)d.M * d.N;
+          maxN1 = std::max(maxN1, d.N);
+          flops_pp += 2.0 * d.M * d.N * d.seg[0].K;
+          bytes_pp += eb * ((double)d.M * d.seg[0].K + (double)d.seg[0].K * d.N + (double)d.M * d.N);
+          tb.g1.push_back(d);
+        }
+      }
+    tb.Xsize = xo;
+    if (maxN1 <= 16) { tb.tm1 = 256; tb.tn1 = 16; }
+    else if (maxN1 <= 32) { tb.tm1 = 128; tb.tn1 = 32; }
+    else { tb.tm1 = 64; tb.tn1 = 64; }
+    for (auto &d : tb.g1) {
+      d.tile0 = tb.t1;
+      d.tilesN = (d.N + tb.tn1 - 1) / tb.tn1;
+      tb.t1 += ((d.M + tb.tm1 - 1) / tb.tm1) * d.tilesN;
+    }
+    // mix tasks and Y layout
+    std::vector<int64_t> offY(cls[x + 1].size() * nslot * 4, -1);
+    int64_t yo = 0;
+    for (size_t co = 0; co < cls[x + 1].size(); ++co)
+      for (int s = 0; s < nslot; ++s) {
+        if (dpad[x + 1][s] == 0) continue;
+        const int sa = s / nb1, sb = s % nb1;
+        const int sbn = slot_of(sa + cls[x + 1][co].da, sb + cls[x + 1][co].db);
+        if (dp(x + 1, sbn) == 0) continue;
+        for (int kp = 0; kp < 4; ++kp) {
+          const int s_a = slot_of(sa + cls[x + 1][co].da - qk_a(kp), sb + cls[x + 1][co].db - qk_b(kp));
+          if (dp(x, s_a) == 0) continue;
+          MixTask tk{};
+          tk.da = dpad[x][s_a];
+          tk.nw_out = cls[x + 1][co].nw;
+          tk.db = dpad[x + 1][s];
+          tk.src0 = (int)tb.srcs.size();
+          for (size_t gi = 0; gi < mpo.groups[x].size(); ++gi) {
+            const MpoGroup &g = mpo.groups[x][gi];
+            if (g.cout != (int)co) continue;
+            const OpPattern &P = mpo.patterns[g.pattern];
+            for (int e = 0; e < P.n; ++e) {
+              if (P.kp[e] != kp) continue;
+              const int k = P.k[e];
+              const int s_in = slot_of(sa - qk_a(k), sb - qk_b(k));
+              if (s_in < 0) continue;
+              const int64_t ox = offX[((size_t)g.cin * nslot + s_in) * 4 + k];
+              if (ox < 0) continue;
+              // the source block's bra sector must be the task's (shape of the read)
+              const int s_src = slot_of(sa - qk_a(k) + cls[x][g.cin].da, sb - qk_b(k) + cls[x][g.cin].db);
+              require(s_src == s_a, TNQE_EINVAL, "MPO transition breaks particle-number bookkeeping");
+              MixSrc sr{};
+              sr.offX = ox;
+              sr.nw_in = cls[x][g.cin].nw;
+              sr.group = gbase[x] + (int)gi;
+              sr.factor = P.f[e];
+              tb.srcs.push_back(sr);
+              const double nnz = (double)g.col.size();
+              flops_pp += 2.0 * nnz * tk.da * tk.db;
+              bytes_pp += eb * (double)tk.da * sr.nw_in * tk.db;
+            }
+          }
+          tk.nsrc = (int)tb.srcs.size() - tk.src0;
+          if (tk.nsrc == 0) continue;
+          tk.offY = yo;
+          offY[(co * nslot + s) * 4 + kp] = yo;
+          const int64_t tot = (int64_t)tk.da * tk.nw_out * tk.db;
+          yo += tot;
+          bytes_pp += eb * (double)tot;
+          tb.chunk0.push_back(tb.nchunk);
+          tb.nchunk += (int)((tot + 255) / 256);
+          tb.tasks.push_back(tk);
+        }
+      }
+    tb.Ysize = yo;
+    if (x < N - 1) {
+      int maxM2 = 0;
+      for (size_t co = 0; co < cls[x + 1].size(); ++co)
+        for (int s = 0; s < nslot; ++s) {
+          const int64_t lo = Loff[x + 1][co * nslot + s];
+          if (lo < 0) continue;
+          const int sa = s / nb1, sb = s % nb1;
+          const int sbn = slot_of(sa + cls[x + 1][co].da, sb + cls[x + 1][co].db);
+          GemmDesc d{};
+          d.M = dpad[x + 1][sbn];
+          d.N = cls[x + 1][co].nw * dpad[x + 1][s];
+          d.ldc = d.N;
+          d.offC = lo;
+          d.nseg = 0;
+          for (int kp = 0; kp < 4; ++kp) {
+            const int64_t oy = offY[(co * nslot + s) * 4 + kp];
+            if (oy < 0) continue;
+            const int s_a = slot_of(sa + cls[x + 1][co].da - qk_a(kp), sb + cls[x + 1][co].db - qk_b(kp));
+            GemmSeg &g = d.seg[d.nseg++];
+            g.K = dpad[x][s_a];
+            g.transA = 1;
+            g.lda = 4 * Dpad[x + 1];
+            g.offA = ((int64_t)opad[x][s_a] * 4 + kp) * Dpad[x + 1] + opad[x + 1][sbn];
+            g.offB = oy;
+            g.ldb = d.N;
+            flops_pp += 2.0 * d.M * d.N * g.K;
+            bytes_pp += eb * ((double)g.K * d.M + (double)g.K * d.N);
+          }
+          bytes_pp += eb * (double)d.M * d.N;
+          maxM2 = std::max(maxM2, d.M);
+          tb.g2.push_back(d);
+        }
+      if (maxM2 <= 16) { tb.tm2 = 16; tb.tn2 = 256; }
+      else if (maxM2 <= 32) { tb.tm2 = 32; tb.tn2 = 128; }
+      else { tb.tm2 = 64; tb.tn2 = 64; }
+      for (auto &d : tb.g2) {
+        d.tile0 = tb.t2;
+        d.tilesN = (d.N + tb.tn2 - 1) / tb.tn2;
+        tb.t2 += ((d.M + tb.tm2 - 1) / tb.tm2) * d.tilesN;
+      }
+    } else {
+      const int sN = slot_of(pb.na, pb.nb);
+      const int co = mpo.final_class;
+      for (int kp = 0; kp < 4; ++kp) {
+        const int64_t oy = offY[((size_t)co * nslot + sN) * 4 + kp];
+        if (oy < 0) continue;
+        const int s_a = slot_of(pb.na - qk_a(kp), pb.nb - qk_b(kp));
+        tb.fin_offY.push_back(oy);
+        tb.fin_da.push_back(dpad[x][s_a]);
+        tb.fin_offBra.push_back((int64_t)opad[x][s_a] * 4 + kp);
+      }
+    }
+  }
+  // ---- device tables
+  std::vector<int> rowptr;
+  std::vector<int> col;
+  std::vector<CsrGroup> groups;
+  for (int x = 0; x < N; ++x)
+    for (const MpoGroup &g : mpo.groups[x]) {
+      CsrGroup cg;
+      cg.rowptr = (int64_t)rowptr.size();
+      cg.col = (int64_t)col.size();
+      rowptr.insert(rowptr.end(), g.rowptr.begin(), g.rowptr.end());
+      col.insert(col.end(), g.col.begin(), g.col.end());
+      groups.push_back(cg);
+    }
+  require((int64_t)col.size() == nnz_total, TNQE_EINVAL, "MPO value layout mismatch");
+  const int *d_rowptr = c.upload(rowptr);
+  const int *d_col = c.upload(col);
+  const CsrGroup *d_groups = c.upload(groups);
+  struct DevSite {
+    GemmDesc *g1, *g2;
+    MixTask *tasks;
+    int *chunk0;
+    MixSrc *srcs;
+    int64_t *fin_offY, *fin_offBra;
+    int *fin_da;
+  };
+  std::vector<DevSite> ds(N);
+  int64_t Lmax = 1, Xmax = 1, Ymax = 1;
+  for (int b = 0; b <= N; ++b) Lmax = std::max(Lmax, Lsize[b]);
+  for (int x = 0; x < N; ++x) {
+    ds[x].g1 = c.upload(tabs[x].g1);
+    ds[x].g2 = c.upload(tabs[x].g2);
+    ds[x].tasks = c.upload(tabs[x].tasks);
+    std::vector<int> ch = tabs[x].chunk0;
+    ch.push_back(tabs[x].nchunk);
+    ds[x].chunk0 = c.upload(ch);
+    ds[x].srcs = c.upload(tabs[x].srcs);
+    ds[x].fin_offY = c.upload(tabs[x].fin_offY);
+    ds[x].fin_offBra = c.upload(tabs[x].fin_offBra);
+    ds[x].fin_da = c.upload(tabs[x].fin_da);
+    Xmax = std::max(Xmax, tabs[x].Xsize);
+    Ymax = std::max(Ymax, tabs[x].Ysize);
+  }
+  c.sync();
+  // ---- pair batches under a memory budget
+  const int npair = (int)pairs.size();
+  const double per_pair = (double)(2 * Lmax + Xmax + Ymax) * sizeof(T);
+  const double budget = 96.0 * (1ull << 30);
+  int batch = std::max(1, std::min(npair, (int)(budget / std::max(1.0, per_pair))));
+  res.H.assign(npair, 0.0);
+  res.S.assign(npair, 0.0);
+  res.flops = flops_pp * npair;
+  res.bytes = bytes_pp * npair;
+  hipEvent_t e0 = c.ctx->ev[0], e1 = c.ctx->ev[1];
+  for (int p0 = 0; p0 < npair; p0 += batch) {
+    const int nb_ = std::min(batch, npair - p0);
+    const size_t mk = c.ctx->pool.mark();
+    T *bufL0 = c.dev<T>((size_t)Lmax * nb_), *bufL1 = c.dev<T>((size_t)Lmax * nb_);
+    T *bufX = c.dev<T>((size_t)Xmax * nb_), *bufY = c.dev<T>((size_t)Ymax * nb_);
+    std::vector<T *> L0(nb_), L1(nb_), X(nb_), Y(nb_);
+    std::vector<int> basis(nb_);
+    for (int q = 0; q < nb_; ++q) {
+      L0[q] = bufL0 + (size_t)q * Lmax;
+      L1[q] = bufL1 + (size_t)q * Lmax;
+      X[q] = bufX + (size_t)q * Xmax;
+      Y[q] = bufY + (size_t)q * Ymax;
+      basis[q] = pairs[p0 + q].first;
+    }
+    T **dL0 = c.upload(L0), **dL1 = c.upload(L1), **dX = c.upload(X), **dY = c.upload(Y);
+    const int *dbasis = c.upload(basis);
+    std::vector<std::vector<const T *>> braT(N, std::vector<const T *>(nb_)), ketT(N, std::vector<const T *>(nb_));
+    std::vector<const double *> bra64(nb_);
+    for (int q = 0; q < nb_; ++q) {
+      const int i = pairs[p0 + q].first;
+      const int kitem = ket_of_pair[p0 + q] < 0 ? i : M + ket_of_pair[p0 + q];
+      for (int x = 0; x < N; ++x) {
+        braT[x][q] = padT + (size_t)i * per_item + psite_off[x];
+        ketT[x][q] = padT + (size_t)kitem * per_item + psite_off[x];
+      }
+      bra64[q] = pad64 + (size_t)i * per_item + psite_off[N - 1];
+    }
+    std::vector<const T *const *> dbra(N), dket(N);
+    for (int x = 0; x < N; ++x) {
+      dbra[x] = c.upload(braT[x]);
+      dket[x] = c.upload(ketT[x]);
+    }
+    const double *const *dbra64 = c.upload(bra64);
+    double *dout = c.dev<double>((size_t)nb_ * 2);
+    TNQE_HIP(hipEventRecord(e0, st));
+    launch_env_init<T>(dL0, nb_, Lsize[0], st);
+    T **Lc = dL0, **Ln = dL1;
+    for (int x = 0; x < N; ++x) {
+      const SiteTabs &tb = tabs[x];
+      PairPtrs p1{reinterpret_cast<const void *const *>(Lc), reinterpret_cast<const void *const *>(dket[x]),
+                  reinterpret_cast<void *const *>(dX)};
+      launch_bgemm<T>(ds[x].g1, (int)tb.g1.size(), tb.t1, tb.tm1, tb.tn1, p1, nb_, st);
+      MixArgs ma{};
+      ma.tasks = ds[x].tasks;
+      ma.task_chunk0 = ds[x].chunk0;
+      ma.ntask = (int)tb.tasks.size();
+      ma.nchunk = tb.nchunk;
+      ma.src = ds[x].srcs;
+      ma.groups = d_groups;
+      ma.rowptr = d_rowptr;
+      ma.col = d_col;
+      ma.vals = dvals;
+      ma.basis_stride = nnz_total;
+      ma.site_off = 0;
+      ma.basis = dbasis;
+      launch_mix<T>(ma, dX, dY, nb_, st);
+      if (x < N - 1) {
+        PairPtrs p2{reinterpret_cast<const void *const *>(dbra[x]), reinterpret_cast<const void *const *>(dY),
+                    reinterpret_cast<void *const *>(Ln)};
+        launch_bgemm<T>(ds[x].g2, (int)tb.g2.size(), tb.t2, tb.tm2, tb.tn2, p2, nb_, st);
+        std::swap(Lc, Ln);
+      } else {
+        launch_env_final<T>(dbra64, dY, ds[x].fin_offY, ds[x].fin_da, ds[x].fin_offBra, 2,
+                            (int)tb.fin_offY.size(), dout, nb_, st);
+      }
+      c.check_launch();
+    }
+    TNQE_HIP(hipEventRecord(e1, st));
+    std::vector<double> out((size_t)nb_ * 2);
+    TNQE_HIP(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    c.sync();
+    float ms = 0.0f;
+    TNQE_HIP(hipEventElapsedTime(&ms, e0, e1));
+    res.kernel_ms += ms;
+    for (int q = 0; q < nb_; ++q) {
+      res.H[p0 + q] = out[(size_t)q * 2 + mpo.final_H];
+      res.S[p0 + q] = out[(size_t)q * 2 + mpo.final_I];
+    }
+    c.ctx->pool.rewind(mk);
+  }
+}
+
+// ------------------------------------------------------------ one solve
+struct SolveOut {
+  std::vector<double> H, S;
+  double E = 0.0;
+  std::vector<double> c;
+  tnqe_report rep{};
+  int status = 0;
+};
+
+// rotated integrals h^(i) = U^T h U, (pq|rs)^(i)
+void rotate_integrals(const tnqe_problem &pb, const std::vector<double> &U, std::vector<double> &hi,
+                      std::vector<double> &gi) {
+  const int N = pb.N;
+  const size_t N2 = (size_t)N * N;
+  auto rot2 = [&](const double *A, double *out) {   // out = U^T A U
+    std::vector<double> t(N2, 0.0);
+    for (int p = 0; p < N; ++p)
+      for (int b = 0; b < N; ++b) {
+        double acc = 0.0;
+        for (int q = 0; q < N; ++q) acc += A[p * N + q] * U[q * N + b];
+        t[p * N + b] = acc;
+      }
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) {
+        double acc = 0.0;
+        for (int p = 0; p < N; ++p) acc += U[p * N + a] * t[p * N + b];
+        out[a * N + b] = acc;
+      }
+  };
+  hi.assign(N2, 0.0);
+  rot2(pb.h.data(), hi.data());
+  gi.assign(N2 * N2, 0.0);
+  if (pb.K > 0) {
+    std::vector<double> Lk(N2);
+    for (int k = 0; k < pb.K; ++k) {
+      rot2(pb.L.data() + (size_t)k * N2, Lk.data());
+      for (size_t x = 0; x < N2; ++x) {
+        const double v = Lk[x];
+        if (v == 0.0) continue;
+        double *row = gi.data() + x * N2;
+        for (size_t y = 0; y < N2; ++y) row[y] += v * Lk[y];
+      }
+    }
+  } else {
+    // four quarter transformations of (pq|rs)
+    std::vector<double> a(pb.g), b(N2 * N2);
+    for (int pass = 0; pass < 4; ++pass) {
+      // contract the first index with U and rotate the index order (pqrs -> qrsP)
+      for (int P = 0; P < N; ++P)
+        for (size_t rest = 0; rest < N2 * N; ++rest) {
+          double acc = 0.0;
+          for (int p = 0; p < N; ++p) acc += U[p * N + P] * a[(size_t)p * N2 * N + rest];
+          b[rest * N + P] = acc;
+        }
+      std::swap(a, b);
+    }
+    gi = a;
+  }
+}
+
+MpoStructure &mpo_for(tnqe_ctx *ctx, int N) {
+  auto it = ctx->mpo_cache.find(N);
+  if (it != ctx->mpo_cache.end()) return *it->second;
+  auto m = std::make_unique<MpoStructure>();
+  mpo_build_structure(N, *m);
+  MpoStructure &ref = *m;
+  ctx->mpo_cache[N] = std::move(m);
+  return ref;
+}
+
+void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut &out) {
+  Call c{ctx};
+  const auto t0 = Clock::now();
+  const int N = pb.N, M = pb.M, nslot = pb.nslot();
+  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
+  require(chi_cap >= 1, TNQE_EINVAL, "chi must be >= 1");
+  const int max_sweeps = op.max_sweeps > 0 ? op.max_sweeps : 40;
+  tnqe_report &rep = out.rep;
+  rep = tnqe_report{};
+  // ---- host: integrals, MPO, plans
+  MpoStructure &mpo = mpo_for(ctx, N);
+  const int64_t nnz = mpo.site_nnz_off[N];
+  std::vector<double> vals((size_t)nnz * M), slotv, v1, hi, gi;
+  for (int i = 0; i < M; ++i) {
+    rotate_integrals(pb, pb.mps[i].U, hi, gi);
+    mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
+    std::copy(v1.begin(), v1.end(), vals.begin() + (size_t)i * nnz);
+  }
+  const double *dvals = c.upload(vals);
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> ket_of_pair;
+  std::vector<std::pair<int, int>> offd;
+  for (int i = 0; i < M; ++i)
+    for (int j = i; j < M; ++j) {
+      pairs.push_back({i, j});
+      if (i == j) {
+        ket_of_pair.push_back(-1);
+      } else {
+        ket_of_pair.push_back((int)offd.size());
+        offd.push_back({i, j});
+      }
+    }
+  const int P = (int)offd.size();
+  std::vector<std::vector<int>> gpos(P);
+  std::vector<std::vector<double>> gth(P);
+  std::vector<int> dsign(P, 1);
+  for (int t = 0; t < P; ++t) {
+    const auto &Ui = pb.mps[offd[t].first].U, &Uj = pb.mps[offd[t].second].U;
+    std::vector<double> W((size_t)N * N, 0.0);
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) {
+        double acc = 0.0;
+        for (int p = 0; p < N; ++p) acc += Ui[p * N + a] * Uj[p * N + b];
+        W[a * N + b] = acc;
+      }
+    givens_plan(N, W.data(), gpos[t], gth[t], dsign[t]);
+  }
+  rep.t_host_ms = ms_since(t0);
+  // ---- gate phase
+  const auto tg = Clock::now();
+  KetSet kets;
+  TruncStats ts;
+  ts.discarded.assign(P, 0.0);
+  if (P > 0) {
+    std::vector<int> cap(N + 1, 1);
+    for (int b = 0; b <= N; ++b) {
+      double ex = 0.0;
+      const int a0 = std::max(0, pb.na - (N - b)), a1 = std::min(b, pb.na);
+      const int b0 = std::max(0, pb.nb - (N - b)), b1 = std::min(b, pb.nb);
+      for (int a = a0; a <= a1; ++a)
+        for (int bb = b0; bb <= b1; ++bb)
+          ex += std::min(binom(b, a) * binom(b, bb), binom(N - b, pb.na - a) * binom(N - b, pb.nb - bb));
+      int mx = 0;
+      for (int i = 0; i < M; ++i) mx = std::max(mx, pb.mps[i].dims[b]);
+      cap[b] = std::max(mx, (int)std::min<double>(ex, (double)chi_cap));
+    }
+    // left-canonical copies of every MPS used as a ket
+    KetSet canon;
+    canon.init(&c, M, N, pb.na, pb.nb, cap);
+    {
+      std::vector<double *> dst(M), src(M);
+      std::vector<int64_t> cnt(M);
+      for (int p = 0; p < N; ++p) {
+        for (int i = 0; i < M; ++i) {
+          dst[i] = canon.site_ptr[(size_t)i * N + p];
+          src[i] = pb.d_sites + pb.mps[i].site_off[p];
+          cnt[i] = (int64_t)pb.mps[i].dims[p] * 4 * pb.mps[i].dims[p + 1];
+        }
+        const size_t mk = ctx->pool.mark();
+        launch_copy(c.upload(dst), c.upload(src), c.upload(cnt), M, ctx->stream);
+        c.sync();
+        ctx->pool.rewind(mk);
+      }
+      for (int b = 0; b <= N; ++b) {
+        for (int i = 0; i < M; ++i)
+          for (int s = 0; s < nslot; ++s) canon.dim(b, i, s) = pb.mps[i].secdim[b][s];
+        canon.commit_bond(b);
+      }
+      for (int p = 0; p + 1 < N; ++p) {
+        const size_t mk = ctx->pool.mark();
+        move_right(canon, p, max_sweeps);
+        c.sync();
+        ctx->pool.rewind(mk);
+      }
+    }
+    kets.init(&c, P, N, pb.na, pb.nb, cap);
+    {
+      std::vector<double *> dst(P), src(P);
+      std::vector<int64_t> cnt(P);
+      for (int p = 0; p < N; ++p) {
+        for (int t = 0; t < P; ++t) {
+          const int j = offd[t].second;
+          dst[t] = kets.site_ptr[(size_t)t * N + p];
+          src[t] = canon.site_ptr[(size_t)j * N + p];
+          cnt[t] = (int64_t)canon.htot[(size_t)p * M + j] * 4 * canon.htot[(size_t)(p + 1) * M + j];
+        }
+        const size_t mk = ctx->pool.mark();
+        launch_copy(c.upload(dst), c.upload(src), c.upload(cnt), P, ctx->stream);
+        c.sync();
+        ctx->pool.rewind(mk);
+      }
+      for (int b = 0; b <= N; ++b) {
+        for (int t = 0; t < P; ++t)
+          for (int s = 0; s < nslot; ++s) kets.dim(b, t, s) = canon.dim(b, offd[t].second, s);
+        kets.commit_bond(b);
+      }
+      // parity gate on the last site where det(U_i^T U_j) = -1
+      std::vector<double *> sg;
+      std::vector<int> rows;
+      for (int t = 0; t < P; ++t)
+        if (dsign[t] < 0) {
+          sg.push_back(kets.site_ptr[(size_t)t * N + N - 1]);
+          rows.push_back(kets.htot[(size_t)(N - 1) * P + t]);
+        }
+      if (!sg.empty()) launch_site_sign(c.upload(sg), c.upload(rows), (int)sg.size(), 1, ctx->stream);
+      c.sync();
+    }
+    int centre = N - 1;
+    const size_t ngate = gpos[0].size();
+    std::vector<double> gates((size_t)P * 256);
+    for (size_t g = 0; g < ngate; ++g) {
+      const int a = gpos[0][g];
+      const size_t mk = ctx->pool.mark();
+      while (centre > a) {
+        move_left(kets, centre, max_sweeps);
+        --centre;
+      }
+      for (int t = 0; t < P; ++t) {
+        require(gpos[t][g] == a, TNQE_EINVAL, "gate positions differ between pairs");
+        gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
+      }
+      gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, ts);
+      centre = a + 1;
+      ctx->pool.rewind(mk);
+    }
+    c.sync();
+  }
+  rep.t_gates_ms = ms_since(tg);
+  // ---- environment sweep
+  const auto te = Clock::now();
+  EnvResult er;
+  if (op.precision == TNQE_ENV_FP32)
+    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
+  else
+    env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
+  rep.t_env_ms = ms_since(te);
+  // ---- pencil and eigensolve
+  const auto tq = Clock::now();
+  out.H.assign((size_t)M * M, 0.0);
+  out.S.assign((size_t)M * M, 0.0);
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    const int i = pairs[q].first, j = pairs[q].second;
+    const double h = er.H[q] + pb.e_core * er.S[q];
+    out.H[i * M + j] = out.H[j * M + i] = h;
+    out.S[i * M + j] = out.S[j * M + i] = er.S[q];
+  }
+  for (double v : out.H) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite H element");
+  for (double v : out.S) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite S element");
+  require(M <= kMaxM, TNQE_EINVAL, "M exceeds the device eigensolver limit");
+  const double *dH = c.upload(out.H), *dS = c.upload(out.S);
+  std::vector<int> Ms{M};
+  std::vector<int64_t> offs{0};
+  double *dout = c.dev<double>(8 + kMaxM);
+  launch_gep(dH, dS, c.upload(Ms), c.upload(offs), 1, op.eps_S > 0 ? op.eps_S : 1e-12, dout, ctx->stream);
+  c.check_launch();
+  std::vector<double> go(8 + kMaxM);
+  TNQE_HIP(hipMemcpyAsync(go.data(), dout, go.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  c.sync();
+  rep.t_gep_ms = ms_since(tq);
+  require(go[5] == 0.0, TNQE_ESINGULAR, "S has no eigenvalue above the threshold");
+  out.E = go[0];
+  out.c.assign(go.begin() + 8, go.begin() + 8 + M);
+  rep.cond_S = go[1];
+  rep.lambda_min_S = go[2];
+  rep.n_dropped = (int)go[3];
+  rep.kappa1 = go[4];
+  rep.max_discarded_weight_sum = 0.0;
+  for (double d : ts.discarded) rep.max_discarded_weight_sum = std::max(rep.max_discarded_weight_sum, d);
+  rep.min_rel_gap = ts.min_gap;
+  rep.env_flops = er.flops;
+  rep.alg_flops = er.flops;
+  rep.alg_bytes = er.bytes;
+  rep.env_kernel_ms = er.kernel_ms;
+  rep.n_pairs = (int)pairs.size();
+  rep.max_bond = std::max(ts.max_bond, er.max_pad);
+  rep.mpo_max_bond = mpo.max_bond;
+  rep.t_total_ms = ms_since(t0);
+  require(std::isfinite(out.E), TNQE_ENONFINITE, "non-finite eigenvalue");
+}
+
+}  // namespace
+}  // namespace tnqe
+
+// ============================================================== C ABI
+using namespace tnqe;
+
+namespace {
+
+tnqe_status fail(tnqe_ctx *ctx, tnqe_status st, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+template <class F>
+tnqe_status guarded(tnqe_ctx *ctx, F &&f) {
+  try {
+    f();
+    if (ctx) ctx->last_error.clear();
+    return TNQE_OK;
+  } catch (const Error &e) {
+    if (ctx) {
+      ctx->pool.release_all();
+      ctx->staging.reset();
+    }
+    return fail(ctx, e.st, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, TNQE_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(ctx, TNQE_EINVAL, e.what());
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void tnqe_default_options(tnqe_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->chi = 16;
+  o->precision = TNQE_FP64;
+  o->eps_S = 1e-12;
+  o->tau_w = 1e-13;
+  o->max_sweeps = 40;
+}
+
+const char *tnqe_version(void) { return "tnqe 0.1 (gfx950)"; }
+
+const char *tnqe_status_string(tnqe_status st) {
+  switch (st) {
+    case TNQE_OK: return "ok";
+    case TNQE_EINVAL: return "invalid argument";
+    case TNQE_ESHAPE: return "inconsistent shapes";
+    case TNQE_ENOTORTH: return "rotation is not orthogonal";
+    case TNQE_EQN: return "tensor breaks particle-number blocks";
+    case TNQE_ENOMEM: return "out of memory";
+    case TNQE_EWORKSPACE: return "workspace too small";
+    case TNQE_EHIP: return "HIP runtime error";
+    case TNQE_ESINGULAR: return "overlap matrix singular";
+    case TNQE_ENONFINITE: return "non-finite value";
+    case TNQE_ENODEVICE: return "no gfx950 device";
+  }
+  return "unknown status";
+}
+
+const char *tnqe_last_error(const tnqe_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
+  if (!out) return TNQE_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= device || device < 0) {
+    (void)hipGetLastError();
+    return TNQE_ENODEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TNQE_ENODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TNQE_ENODEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TNQE_EHIP;
+  auto *ctx = new tnqe_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  for (auto &e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete ctx;
+      return TNQE_EHIP;
+    }
+  *out = ctx;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
+  if (!ctx) return TNQE_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_trim(tnqe_ctx *ctx) {
+  if (!ctx) return TNQE_EINVAL;
+  return guarded(ctx, [&] {
+    TNQE_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->pool.trim();
+  });
+}
+
+tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                        tnqe_problem **out) {
+  if (!ctx || !ham || !mps || !out || M < 1) return ctx ? fail(ctx, TNQE_EINVAL, "null argument or M < 1") : TNQE_EINVAL;
+  *out = nullptr;
+  tnqe_problem *pb = new tnqe_problem();
+  tnqe_status st = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    const int N = ham->N;
+    require(N >= 1 && N <= 64, TNQE_ESHAPE, "N must be in [1, 64]");
+    require(ham->n_alpha >= 0 && ham->n_alpha <= N && ham->n_beta >= 0 && ham->n_beta <= N, TNQE_ESHAPE,
+            "electron counts out of range");
+    require(ham->h != nullptr, TNQE_EINVAL, "h is NULL");
+    require((ham->n_chol > 0 && ham->L) || (ham->n_chol == 0 && ham->g), TNQE_EINVAL,
+            "two-electron integrals missing");
+    pb->N = N;
+    pb->na = ham->n_alpha;
+    pb->nb = ham->n_beta;
+    pb->M = M;
+    pb->e_core = ham->e_core;
+    require(std::isfinite(pb->e_core), TNQE_ENONFINITE, "e_core not finite");
+    const size_t N2 = (size_t)N * N;
+    pb->h.assign(ham->h, ham->h + N2);
+    for (size_t x = 0; x < N2; ++x) {
+      require(std::isfinite(pb->h[x]), TNQE_ENONFINITE, "h has a non-finite entry");
+      require(std::fabs(pb->h[x] - pb->h[(x % N) * N + x / N]) <= 1e-12 * (1 + std::fabs(pb->h[x])),
+              TNQE_EINVAL, "h is not symmetric");
+    }
+    if (ham->n_chol > 0) {
+      pb->K = ham->n_chol;
+      pb->L.assign(ham->L, ham->L + (size_t)pb->K * N2);
+      for (double v : pb->L) require(std::isfinite(v), TNQE_ENONFINITE, "L has a non-finite entry");
+      pb->g.clear();
+    } else {
+      pb->K = 0;
+      pb->g.assign(ham->g, ham->g + N2 * N2);
+      for (double v : pb->g) require(std::isfinite(v), TNQE_ENONFINITE, "g has a non-finite entry");
+    }
+    const int nslot = pb->nslot();
+    int64_t total = 0;
+    pb->mps.resize(M);
+    for (int i = 0; i < M; ++i) {
+      const tnqe_mps &m = mps[i];
+      require(m.bond_dim && m.bond_qn && m.sites && m.U, TNQE_EINVAL, "MPS field is NULL");
+      auto &pm = pb->mps[i];
+      pm.dims.assign(m.bond_dim, m.bond_dim + N + 1);
+      require(pm.dims[0] == 1 && pm.dims[N] == 1, TNQE_ESHAPE, "boundary bonds must have dimension 1");
+      pm.secdim.assign(N + 1, std::vector<int>(nslot, 0));
+      std::vector<std::vector<int>> qa(N + 1), qb(N + 1);
+      int64_t qo = 0;
+      for (int b = 0; b <= N; ++b) {
+        require(pm.dims[b] >= 1 && pm.dims[b] <= 1 << 20, TNQE_ESHAPE, "bond dimension out of range");
+        int prev = -1;
+        for (int x = 0; x < pm.dims[b]; ++x) {
+          const int a = m.bond_qn[2 * (qo + x)], bb = m.bond_qn[2 * (qo + x) + 1];
+          require(a >= 0 && a <= pb->na && bb >= 0 && bb <= pb->nb, TNQE_EQN, "bond label out of range");
+          const int s = a * (pb->nb + 1) + bb;
+          require(s >= prev, TNQE_EQN, "bond indices not sorted by sector");
+          prev = s;
+          pm.secdim[b][s]++;
+          qa[b].push_back(a);
+          qb[b].push_back(bb);
+        }
+        qo += pm.dims[b];
+      }
+      require(qa[0][0] == 0 && qb[0][0] == 0 && qa[N][0] == pb->na && qb[N][0] == pb->nb, TNQE_EQN,
+              "MPS is not in the (n_alpha, n_beta) sector");
+      pm.U.assign(m.U, m.U + N2);
+      for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+          double acc = 0.0;
+          for (int p = 0; p < N; ++p) acc += pm.U[p * N + a] * pm.U[p * N + b];
+          require(std::isfinite(acc), TNQE_ENONFINITE, "U has a non-finite entry");
+          require(std::fabs(acc - (a == b ? 1.0 : 0.0)) <= 1e-10, TNQE_ENOTORTH, "U is not orthogonal");
+        }
+      pm.site_off.resize(N);
+      const double *sp = m.sites;
+      for (int p = 0; p < N; ++p) {
+        pm.site_off[p] = total;
+        const int dl = pm.dims[p], dr = pm.dims[p + 1];
+        for (int l = 0; l < dl; ++l)
+          for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < dr; ++r) {
+              const double v = sp[((int64_t)l * 4 + k) * dr + r];
+              require(std::isfinite(v), TNQE_ENONFINITE, "site tensor has a non-finite entry");
+              if (v != 0.0)
+                require(qa[p + 1][r] == qa[p][l] + (k & 1) && qb[p + 1][r] == qb[p][l] + (k >> 1), TNQE_EQN,
+                        "site tensor entry outside its particle-number block");
+            }
+        sp += (int64_t)dl * 4 * dr;
+        total += (int64_t)dl * 4 * dr;
+      }
+    }
+    TNQE_HIP(hipMalloc(&pb->d_sites, std::max<int64_t>(1, total) * sizeof(double)));
+    pb->device = ctx->device;
+    int64_t o = 0;
+    for (int i = 0; i < M; ++i) {
+      const int64_t n = pb->mps[i].site_off.empty() ? 0
+                        : [&] {
+                            int64_t s = 0;
+                            for (int p = 0; p < N; ++p) s += (int64_t)pb->mps[i].dims[p] * 4 * pb->mps[i].dims[p + 1];
+                            return s;
+                          }();
+      TNQE_HIP(hipMemcpy(pb->d_sites + o, mps[i].sites, n * sizeof(double), hipMemcpyHostToDevice));
+      o += n;
+    }
+  });
+  if (st != TNQE_OK) {
+    if (pb->d_sites) (void)hipFree(pb->d_sites);
+    delete pb;
+    return st;
+  }
+  *out = pb;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_problem_free(tnqe_problem *pb) {
+  if (!pb) return TNQE_EINVAL;
+  if (pb->d_sites) {
+    (void)hipSetDevice(pb->device);
+    (void)hipFree(pb->d_sites);
+  }
+  delete pb;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts, double *H, double *S,
+                       double *E, double *cvec, tnqe_report *rep) {
+  if (!ctx || !pb || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (opts->precision != TNQE_FP64 && opts->precision != TNQE_ENV_FP32)
+    return fail(ctx, TNQE_EINVAL, "unknown precision mode");
+  SolveOut so;
+  tnqe_status st = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    solve_one(ctx, *pb, *opts, so);
+    ctx->pool.release_all();
+  });
+  if (st != TNQE_OK) return st;
+  std::memcpy(H, so.H.data(), so.H.size() * sizeof(double));
+  std::memcpy(S, so.S.data(), so.S.size() * sizeof(double));
+  *E = so.E;
+  if (cvec) std::memcpy(cvec, so.c.data(), so.c.size() * sizeof(double));
+  if (rep) *rep = so.rep;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *probs, const tnqe_options *opts,
+                             double *const *H, double *const *S, double *E, tnqe_report *rep) {
+  if (!ctx || !probs || !opts || !H || !S || !E || n < 0) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  for (int s = 0; s < n; ++s) {
+    tnqe_status st = tnqe_solve(ctx, probs[s], opts, H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
+    if (st != TNQE_OK) return st;
+  }
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                          const tnqe_options *opts, double *H, double *S, double *E, double *c, tnqe_report *rep) {
+  tnqe_problem *pb = nullptr;
+  tnqe_status st = tnqe_upload(ctx, ham, M, mps, &pb);
+  if (st != TNQE_OK) return st;
+  st = tnqe_solve(ctx, pb, opts, H, S, E, c, rep);
+  tnqe_problem_free(pb);
+  return st;
+}
+
+}  // extern "C"
+
+// ============================================================== host-only diagnostics
+extern "C" {
+
+tnqe_status tnqe_debug_givens(int32_t N, const double *W, int32_t *pos, double *theta, int32_t *det_sign) {
+  if (N < 1 || !W || !pos || !theta || !det_sign) return TNQE_EINVAL;
+  std::vector<int> p;
+  std::vector<double> t;
+  int d = 1;
+  givens_plan(N, W, p, t, d);
+  for (size_t i = 0; i < p.size(); ++i) {
+    pos[i] = p[i];
+    theta[i] = t[i];
+  }
+  *det_sign = d;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_debug_gate(double theta, double *out) {
+  if (!out) return TNQE_EINVAL;
+  gate_g4(theta, out);
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_debug_mpo_dense(int32_t N, const double *h, const double *g, double *Hout, double *Iout,
+                                 int32_t *max_bond) {
+  if (N < 1 || N > 5 || !h || !g || !Hout || !Iout) return TNQE_EINVAL;
+  try {
+    MpoStructure m;
+    mpo_build_structure(N, m);
+    std::vector<double> vals, sv;
+    mpo_values(m, h, g, vals, sv);
+    // global channel offsets per class
+    std::vector<std::vector<int>> base(N + 1);
+    std::vector<int> D(N + 1, 0);
+    for (int b = 0; b <= N; ++b) {
+      for (auto &c : m.classes[b]) {
+        base[b].push_back(D[b]);
+        D[b] += c.nw;
+      }
+    }
+    int dim = 1;
+    std::vector<double> T((size_t)D[0], 1.0);   // bond 0: only I
+    int64_t vo = 0;
+    for (int x = 0; x < N; ++x) {
+      const int nd = dim * 4;
+      std::vector<double> Tn((size_t)D[x + 1] * nd * nd, 0.0);
+      for (const MpoGroup &grp : m.groups[x]) {
+        const OpPattern &P = m.patterns[grp.pattern];
+        const int nrow = (int)grp.rowptr.size() - 1;
+        for (int r = 0; r < nrow; ++r)
+          for (int z = grp.rowptr[r]; z < grp.rowptr[r + 1]; ++z) {
+            const double v = vals[vo + z];
+            const int wi = base[x][grp.cin] + grp.col[z], wo = base[x + 1][grp.cout] + r;
+            const double *src = T.data() + (size_t)wi * dim * dim;
+            double *dst = Tn.data() + (size_t)wo * nd * nd;
+            for (int e = 0; e < P.n; ++e)
+              for (int i = 0; i < dim; ++i)
+                for (int j = 0; j < dim; ++j)
+                  dst[(size_t)(i * 4 + P.kp[e]) * nd + j * 4 + P.k[e]] += v * P.f[e] * src[(size_t)i * dim + j];
+          }
+        vo += (int64_t)grp.col.size();
+      }
+      T.swap(Tn);
+      dim = nd;
+    }
+    const int wH = base[N][m.final_class] + m.final_H, wI = base[N][m.final_class] + m.final_I;
+    std::memcpy(Hout, T.data() + (size_t)wH * dim * dim, sizeof(double) * dim * dim);
+    std::memcpy(Iout, T.data() + (size_t)wI * dim * dim, sizeof(double) * dim * dim);
+    if (max_bond) *max_bond = m.max_bond;
+  } catch (const std::exception &) {
+    return TNQE_EINVAL;
+  }
+  return TNQE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Host-side state of the library: device memory pool, staging, contexts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "mpo.hpp"
+
+namespace tnqe {
+
+// Grow-only pool of device buffers owned by a context.  Buffers handed out
+// during a call are returned to the pool when the call ends.
+class DevicePool {
+ public:
+  ~DevicePool() { trim(); }
+  void *get(size_t bytes);
+  void release_all();
+  void trim();
+  size_t bytes_held() const { return held_; }
+  // buffers handed out after mark() go back to the pool at rewind(); safe on a
+  // single stream because later work is ordered after earlier work
+  size_t mark() const { return order_.size(); }
+  void rewind(size_t m);
+
+ private:
+  struct Buf {
+    void *p;
+    size_t n;
+    bool used;
+  };
+  std::vector<Buf> bufs_;
+  std::vector<void *> order_;
+  size_t held_ = 0;
+};
+
+// Pinned staging area for host-to-device uploads; recycled after each
+// stream synchronisation.
+class Staging {
+ public:
+  ~Staging();
+  void *put(const void *src, size_t bytes);   // returns pinned copy
+  void reset();
+  size_t capacity() const { return cap_; }
+
+ private:
+  std::vector<std::pair<char *, size_t>> old_;
+  char *buf_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+};
+
+}  // namespace tnqe
+
+struct tnqe_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  tnqe::DevicePool pool;
+  tnqe::Staging staging;
+  std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
+  hipEvent_t ev[8] = {};
+};
+
+struct tnqe_problem {
+  int N = 0, na = 0, nb = 0, M = 0;
+  double e_core = 0.0;
+  std::vector<double> h, g;        // reference basis; g = (pq|rs) [N^4]
+  std::vector<double> L;           // Cholesky vectors if given [K][N][N]
+  int K = 0;
+  struct Mps {
+    std::vector<int> dims;                   // [N+1]
+    std::vector<std::vector<int>> secdim;    // [bond][slot]
+    std::vector<double> U;                   // [N][N]
+    std::vector<int64_t> site_off;           // [N] offsets into d_sites (doubles)
+  };
+  std::vector<Mps> mps;
+  double *d_sites = nullptr;       // all sites of all MPS
+  int device = 0;
+  int nslot() const { return (na + 1) * (nb + 1); }
+};

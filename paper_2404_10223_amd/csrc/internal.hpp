@@ -1,0 +1,167 @@
+// Internal declarations shared by the host sources and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tnqe.h"
+
+namespace tnqe {
+
+struct Error : public std::runtime_error {
+  tnqe_status st;
+  Error(tnqe_status s, const std::string &m) : std::runtime_error(m), st(s) {}
+};
+
+#define TNQE_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::tnqe::Error(TNQE_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline void require(bool ok, tnqe_status st, const std::string &msg) {
+  if (!ok) throw Error(st, msg);
+}
+
+// particle-number shift of a local state k = n_up + 2 n_dn
+__host__ __device__ inline int qk_a(int k) { return k & 1; }
+__host__ __device__ inline int qk_b(int k) { return k >> 1; }
+
+// -------------------------------------------------------------- gate phase
+// One quantum-number block of a two-site matrix (or of a single site for the
+// exact centre moves).  Rows and columns are grouped in segments by a local
+// index k; seg offsets are prefix sums.
+struct Blk {
+  int pair;            // which ket
+  int R, C, n;         // rows, cols, min(R, C)
+  int sa, sb;          // quantum numbers of the block's bond sector
+  int rs[5];           // row segment starts (by k), rs[4] = R
+  int cs[5];           // column segment starts (by k), cs[4] = C
+  int j0;              // first index of the sector in the new bond
+  int kept;            // singular vectors kept
+  int aux0, aux1;      // old offset / old bond dimension for the centre moves
+  int64_t offT, offU, offB, offS;   // scratch offsets (doubles)
+  int64_t offW;        // work area for blocks too large for LDS (-1: LDS)
+};
+
+// Per-pair ket state shared with the kernels.
+struct KetTables {
+  double **site;       // [pair * N + p]
+  int2 *btab;          // [bond][pair][nslot]: (offset, dim) of each sector
+  int *bdim;           // [bond][pair]: total bond dimension
+  int npair, N, na, nb, nslot;
+  __host__ __device__ int slot(int a, int b) const {
+    return (a < 0 || b < 0 || a > na || b > nb) ? -1 : a * (nb + 1) + b;
+  }
+  __host__ __device__ int2 sec(int bond, int pair, int a, int b) const {
+    int s = slot(a, b);
+    if (s < 0) return make_int2(0, 0);
+    return btab[((int64_t)bond * npair + pair) * nslot + s];
+  }
+  __host__ __device__ int dim(int bond, int pair) const { return bdim[bond * npair + pair]; }
+};
+
+void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const double *gates,
+                     double *scratch, hipStream_t st);
+// lds_doubles: dynamic LDS per workgroup (largest n*m + n*n + n of the blocks
+// that do not carry a global work area).
+void launch_svd(const Blk *blk, int nblk, double *scratch, int max_sweeps, int lds_doubles,
+                hipStream_t st);
+void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
+                       hipStream_t st);
+void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, int nblk, double *scratch,
+                      hipStream_t st);
+void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, int nblk, const double *scratch,
+                     double *const *old_left, hipStream_t st);
+void launch_gather_qr(const KetTables &kt, int p, const Blk *blk, int nblk, double *scratch,
+                      hipStream_t st);
+void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const double *scratch,
+                     double *const *old_right, hipStream_t st);
+void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n,
+                 hipStream_t st);
+void launch_site_sign(double *const *site, const int *rows, int n, int cols, hipStream_t st);
+
+// -------------------------------------------------------------- environment sweep
+// C[M x N] (+)= sum_seg op(A_seg)[M x K_seg] * B_seg[K_seg x N]; pointers are
+// offsets into per-pair bases (A, B, C bases are pair-indexed arrays).
+struct GemmSeg {
+  int K;
+  int lda, ldb;
+  int transA;          // 0: A[m*lda + k]; 1: A[k*lda + m]
+  int64_t offA, offB;
+};
+struct GemmDesc {
+  int M, N, ldc, nseg;
+  int64_t offC;
+  int tile0;           // first tile index of this problem
+  int tilesN;          // tiles along N
+  GemmSeg seg[4];
+};
+struct PairPtrs {      // per-pair base pointers for one GEMM launch
+  const void *const *A;
+  const void *const *B;
+  void *const *C;
+};
+
+template <typename T>
+void launch_bgemm(const GemmDesc *d, int ndesc, int ntiles, int tileM, int tileN, PairPtrs pp,
+                  int npair, hipStream_t st);
+
+// channel mix: Y[c', s_b, k'] = sum over sources of coef * X[c, s, k]
+struct MixSrc {
+  int64_t offX;        // X block [da][nw_in][db]
+  int nw_in;
+  int group;           // index into the site's CSR groups
+  double factor;       // local-operator matrix element
+};
+struct MixTask {
+  int64_t offY;        // Y block [da][nw_out][db]
+  int da, nw_out, db;
+  int src0, nsrc;      // range in the MixSrc array
+};
+struct CsrGroup {
+  int64_t rowptr;      // offset into the rowptr array (nw_out + 1 entries)
+  int64_t col;         // offset into the col / val arrays
+};
+
+struct MixArgs {
+  const MixTask *tasks;
+  const int *task_chunk0;   // first 256-element chunk of each task (prefix, ntask + 1)
+  int ntask, nchunk;
+  const MixSrc *src;
+  const CsrGroup *groups;
+  const int *rowptr, *col;
+  const double *vals;       // [basis][nnz of all sites]
+  int64_t basis_stride, site_off;
+  const int *basis;         // [pair]
+};
+template <typename T>
+void launch_mix(const MixArgs &a, const T *const *X, T *const *Y, int npair, hipStream_t st);
+
+template <typename T>
+void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st);
+
+// final element: out[pair][w] = sum_{a', k'} bra[a', k', 0] * Y[k'][a'][w][0], compensated
+template <typename T>
+void launch_env_final(const double *const *bra, const T *const *Y, const int64_t *offY,
+                      const int *da, const int64_t *offBra, int nw, int nk, double *out,
+                      int npair, hipStream_t st);
+
+template <typename T>
+void launch_repack(const double *const *src, T *const *dst, const int2 *srcl, const int2 *srcr,
+                   const int *srcDr, int nslot, const int2 *pmapl, const int2 *pmapr, int Dpl, int Dpr,
+                   int nitem, hipStream_t st);
+
+// -------------------------------------------------------------- eigensolve
+// For each subspace s: H, S at offs[s] ([M_s][M_s] row-major); writes
+// out[s * (8 + kMaxM) + ...] = E, cond_S, lambda_min, n_dropped, kappa1, status, -, -, c[0..M_s).
+constexpr int kMaxM = 32;
+void launch_gep(const double *H, const double *S, const int *Ms, const int64_t *offs, int nsub,
+                double eps_S, double *out, hipStream_t st);
+
+}  // namespace tnqe
