@@ -79,8 +79,14 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
   double *X = b.offW < 0 ? lds : scratch + b.offW;
   double *Vt = X + (int64_t)n * m;             // Vt[i*n + r] = V[r][i]
   double *sig = Vt + (int64_t)n * n;
-  __shared__ int s_rot;
+  // convergence flags, one per sweep parity: a flag is cleared only after every
+  // thread has read it (at least one barrier separates the read and the clear)
+  __shared__ int s_rot[2];
   const double *T = scratch + b.offT;
+  if (threadIdx.x == 0) {
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
   for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += kThreads) {
     const int i = e / m, l = e - (int64_t)i * m;
     X[e] = rows ? T[(int64_t)i * C + l] : T[(int64_t)l * C + i];
@@ -89,10 +95,10 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int np = n + (n & 1);
-  const double tol = 1e-15;
+  // rounding floor of a length-m dot product relative to the norms
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
-    if (threadIdx.x == 0) s_rot = 0;
-    __syncthreads();
+    const int fl = sweep & 1;
     int rotated = 0;
     for (int rd = 0; rd < np - 1; ++rd) {
       for (int k = wave; k < np / 2; k += kWaves) {
@@ -136,9 +142,11 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
       }
       __syncthreads();
     }
-    if (rotated && lane == 0) atomicOr(&s_rot, 1);
+    if (rotated && lane == 0) atomicOr(&s_rot[fl], 1);
     __syncthreads();
-    if (s_rot == 0) break;
+    const int any = s_rot[fl];
+    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
+    if (any == 0) break;
   }
   // singular values and their ranks
   for (int i = wave; i < n; i += kWaves) {
