@@ -32,9 +32,11 @@
  *     |k> = (a+_up)^{n_up} (a+_dn)^{n_dn} |vac>.
  *   - Givens plan: R_a(t) = identity but [[cos t, sin t], [-sin t, cos t]] on
  *     rows/cols (a, a+1); eliminate Q = W column by column (c = 0..N-2), rows
- *     r = N-1 down to c+1, t = atan2(-Q[r][c], Q[r-1][c]), Q <- R^T Q; apply
- *     the recorded gates to the ket in reverse order (after the parity gate
- *     diag(1,-1,-1,1) on the last site when det W = -1).
+ *     r = N-1 down to c+1, t = atan2(-Q[r][c], Q[r-1][c]), Q <- R^T Q (an
+ *     entry with |Q[r][c]| <= 1e-14 is left alone: t = 0, or pi at the pivot
+ *     row r-1 = c when Q[c][c] < 0); apply the recorded gates to the ket in
+ *     reverse order (after the parity gate diag(1,-1,-1,1) on the last site
+ *     when det W = -1).
  *   - Truncation keeps the min(chi, #{s^2 > tau_w sum s^2}) largest singular
  *     values over all quantum-number blocks; singular values are absorbed to
  *     the right; no renormalisation.

@@ -12,14 +12,19 @@ library follow this text, not shared code):
   - a+_{a+1} a_a)] (summed over spin).
 
   Q <- W.  For column c = 0..N-2 and row r = N-1 down to c+1: a = r-1,
-  theta = atan2(-Q[r, c], Q[a, c]) (atan2(0, 0) = 0), Q <- R_a(theta)^T Q,
-  record (a, theta).  Then Q = diag(1, .., 1, det W) and
-  W = R_(1) R_(2) ... R_(K) D.
+  theta = atan2(-Q[r, c], Q[a, c]), Q <- R_a(theta)^T Q, record (a, theta).
+  An entry already zero to rounding (|Q[r, c]| <= 1e-14) is not rotated
+  away: theta = 0, except pi at the pivot row (a = c) when Q[a, c] < 0, so
+  that the pivot ends non-negative.  Without this, rounding noise in a W close
+  to a permutation or the identity would pick arbitrary angles.  Then
+  Q = diag(1, .., 1, det W) and W = R_(1) R_(2) ... R_(K) D.
 
   Gates are applied to a ket in the reverse of the recorded order, after the
   parity gate D (only needed when det W = -1).
 """
 import numpy as np
+
+ZERO = 1e-14   # entries of an orthogonal matrix at or below this are rounding noise
 
 
 def rot(N, a, theta):
@@ -41,8 +46,8 @@ def plan(W):
     for c in range(N - 1):
         for r in range(N - 1, c, -1):
             a = r - 1
-            if Q[r, c] == 0.0 and Q[a, c] == 0.0:
-                theta = 0.0
+            if abs(Q[r, c]) <= ZERO:
+                theta = float(np.pi) if (a == c and Q[a, c] < 0.0) else 0.0
             else:
                 theta = float(np.arctan2(-Q[r, c], Q[a, c]))
             Q = rot(N, a, theta).T @ Q

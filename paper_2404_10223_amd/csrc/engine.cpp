@@ -156,7 +156,14 @@ void givens_plan(int N, const double *W, std::vector<int> &pos, std::vector<doub
     for (int r = N - 1; r > c; --r) {
       const int a = r - 1;
       const double x = Q[a * N + c], y = Q[r * N + c];
-      const double th = (x == 0.0 && y == 0.0) ? 0.0 : std::atan2(-y, x);
+      // an entry that is zero to rounding is not rotated away (only the sign
+      // of a negative pivot is fixed), so near-identity rotations plan as
+      // near-identity networks instead of noise-driven angles
+      double th;
+      if (std::fabs(y) <= 1e-14)
+        th = (a == c && x < 0.0) ? M_PI : 0.0;
+      else
+        th = std::atan2(-y, x);
       const double cs = std::cos(th), sn = std::sin(th);
       for (int col = 0; col < N; ++col) {
         const double qa = Q[a * N + col], qr = Q[r * N + col];
@@ -295,7 +302,7 @@ struct KetSet {
   }
 };
 
-constexpr int kLdsDoubles = 19 * 1024;   // 152 KiB of the 160 KiB per workgroup
+constexpr int kLdsDoubles = 19 * 1024;   // 152 KiB of dynamic LDS (the kernel adds ~4 KiB static)
 
 struct Scratch {
   int64_t used = 0;
@@ -306,20 +313,43 @@ struct Scratch {
   }
 };
 
-// plan the SVD storage of a block; returns the LDS doubles it needs (0 if global)
-int plan_block_storage(Blk &b, Scratch &sc) {
+// working set of the SVD of a block: the rotated vectors and their norms
+int64_t svd_need(const Blk &b) { return (int64_t)std::min(b.R, b.C) * std::max(b.R, b.C) + std::min(b.R, b.C); }
+
+// plan the SVD storage of a block (global work area only if it exceeds LDS)
+void plan_block_storage(Blk &b, Scratch &sc) {
   b.n = std::min(b.R, b.C);
+  require(b.n <= 1024, TNQE_ESHAPE, "quantum-number block larger than 1024 singular values");
   b.offT = sc.take((int64_t)b.R * b.C);
   b.offU = sc.take((int64_t)b.R * b.n);
   b.offB = sc.take((int64_t)b.n * b.C);
   b.offS = -1;
-  const int64_t need = (int64_t)b.n * std::max(b.R, b.C) + (int64_t)b.n * b.n + b.n;
-  if (need <= kLdsDoubles) {
-    b.offW = -1;
-    return (int)need;
+  const int64_t need = svd_need(b);
+  b.offW = need <= kLdsDoubles ? -1 : sc.take(need);
+}
+
+// Launch the SVDs of all blocks, grouped by working-set size so small blocks
+// do not reserve a whole CU's LDS; within a group the largest go first.
+void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scratch, int max_sweeps) {
+  struct Cls { int64_t limit; int threads; };
+  const Cls cls[4] = {{2048, 256}, {8192, 512}, {kLdsDoubles, 1024}, {INT64_MAX, 1024}};
+  std::vector<std::vector<int>> idx(4);
+  std::vector<int64_t> lds(4, 0);
+  for (size_t i = 0; i < blks.size(); ++i) {
+    const int64_t need = svd_need(blks[i]);
+    int k = 0;
+    while (need > cls[k].limit) ++k;
+    idx[k].push_back((int)i);
+    if (k < 3) lds[k] = std::max(lds[k], need);
   }
-  b.offW = sc.take(need);
-  return 0;
+  for (int k = 3; k >= 0; --k) {
+    if (idx[k].empty()) continue;
+    std::stable_sort(idx[k].begin(), idx[k].end(),
+                     [&](int x, int y) { return svd_need(blks[x]) > svd_need(blks[y]); });
+    launch_svd(dblk, c.upload(idx[k]), (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps,
+               c.ctx->stream);
+  }
+  c.check_launch();
 }
 
 struct TruncStats {
@@ -333,7 +363,6 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
   Call &c = *ks.call;
   std::vector<Blk> blks;
   Scratch sc;
-  int lds = 0;
   for (int t = 0; t < ks.n; ++t) {
     for (int s = 0; s < ks.nslot; ++s) {
       const int d = ks.dim(q, t, s);
@@ -351,7 +380,7 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
       b.aux0 = ks.off_q(q, t, sa, sb);
       b.aux1 = ks.htot[(size_t)q * ks.n + t];
       if (b.C == 0) continue;
-      lds = std::max(lds, plan_block_storage(b, sc));
+      plan_block_storage(b, sc);
       blks.push_back(b);
     }
   }
@@ -384,7 +413,7 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
   Blk *dblk = c.upload(blks);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  run_svd(c, dblk, blks, scratch, max_sweeps);
   ks.commit_bond(q);
   launch_apply_lq(ks.tables(), q, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
   c.check_launch();
@@ -395,7 +424,6 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
   Call &c = *ks.call;
   std::vector<Blk> blks;
   Scratch sc;
-  int lds = 0;
   for (int t = 0; t < ks.n; ++t) {
     for (int s = 0; s < ks.nslot; ++s) {
       const int d = ks.dim(p + 1, t, s);
@@ -413,7 +441,7 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
       b.aux0 = ks.off_q(p + 1, t, sa, sb);
       b.aux1 = ks.htot[(size_t)(p + 1) * ks.n + t];
       if (b.R == 0) continue;
-      lds = std::max(lds, plan_block_storage(b, sc));
+      plan_block_storage(b, sc);
       blks.push_back(b);
     }
   }
@@ -441,7 +469,7 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
   launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
   Blk *dblk = c.upload(blks);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  run_svd(c, dblk, blks, scratch, max_sweeps);
   ks.commit_bond(p + 1);
   launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
   c.check_launch();
@@ -453,7 +481,6 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   Call &c = *ks.call;
   std::vector<Blk> blks;
   Scratch sc;
-  int lds = 0;
   for (int t = 0; t < ks.n; ++t) {
     for (int s = 0; s < ks.nslot; ++s) {
       const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
@@ -469,7 +496,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
       b.R = b.rs[4];
       b.C = b.cs[4];
       if (b.R == 0 || b.C == 0) continue;
-      lds = std::max(lds, plan_block_storage(b, sc));
+      plan_block_storage(b, sc);
       blks.push_back(b);
     }
   }
@@ -484,7 +511,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   double *dgates = c.upload(gates);
   Blk *dblk = c.upload(blks);
   launch_two_site(ks.tables(), a, dblk, (int)blks.size(), dgates, scratch, c.ctx->stream);
-  launch_svd(dblk, (int)blks.size(), scratch, max_sweeps, lds, c.ctx->stream);
+  run_svd(c, dblk, blks, scratch, max_sweeps);
   c.check_launch();
   std::vector<double> sv(ns);
   TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));

@@ -65,20 +65,28 @@ __global__ void __launch_bounds__(kThreads) k_two_site(KetTables kt, int a, cons
   }
 }
 
-// One-sided Jacobi SVD of an R x C block.  The min(R, C) shorter vectors (rows
-// if R <= C, else columns) are rotated pairwise in round-robin order until
-// mutually orthogonal; V accumulates the rotations.  Output, sorted by
-// decreasing singular value: U [R x n], B = U^T T [n x C], S [n].
-__global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scratch, int max_sweeps) {
+// One-sided Jacobi SVD of an R x C block, T = U B with U orthonormal columns
+// and B = diag(s) V^T, sorted by decreasing singular value s.
+//
+// The shorter side is orthogonalised: if R >= C the C columns (length R), else
+// the R rows (length C), rotated pairwise in round-robin order until mutually
+// orthogonal to rounding.  No rotation matrix is accumulated: in the column
+// case U = x / s and B = U^T T; in the row case B = x and U = T B^T / s^2.
+// Either way the factor that is not the rotated vectors comes from one
+// product with the block, which keeps the working set at R x C doubles (LDS
+// when it fits, else a global work area).  idx lists the blocks of this launch.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, double *scratch,
+                                            int max_sweeps) {
+  constexpr int NW = NT / 64;
   extern __shared__ double lds[];
-  const Blk b = blks[blockIdx.x];
+  const Blk b = blks[idx[blockIdx.x]];
   const int R = b.R, C = b.C;
-  const bool rows = R <= C;
-  const int n = rows ? R : C, m = rows ? C : R;
+  const bool cols = R >= C;
+  const int n = cols ? C : R, m = cols ? R : C;
   if (n == 0) return;
-  double *X = b.offW < 0 ? lds : scratch + b.offW;
-  double *Vt = X + (int64_t)n * m;             // Vt[i*n + r] = V[r][i]
-  double *sig = Vt + (int64_t)n * n;
+  double *X = b.offW < 0 ? lds : scratch + b.offW;     // X[i*m + l]: vector i
+  double *sig = X + (int64_t)n * m;
   // convergence flags, one per sweep parity: a flag is cleared only after every
   // thread has read it (at least one barrier separates the read and the clear)
   __shared__ int s_rot[2];
@@ -87,11 +95,10 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
     s_rot[0] = 0;
     s_rot[1] = 0;
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += kThreads) {
+  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
     const int i = e / m, l = e - (int64_t)i * m;
-    X[e] = rows ? T[(int64_t)i * C + l] : T[(int64_t)l * C + i];
+    X[e] = cols ? T[(int64_t)l * C + i] : T[(int64_t)i * C + l];
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kThreads) Vt[e] = (e / n == e % n) ? 1.0 : 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int np = n + (n & 1);
@@ -101,7 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
     const int fl = sweep & 1;
     int rotated = 0;
     for (int rd = 0; rd < np - 1; ++rd) {
-      for (int k = wave; k < np / 2; k += kWaves) {
+      for (int k = wave; k < np / 2; k += NW) {
         int i, j;
         if (k == 0) {
           i = np - 1;
@@ -132,12 +139,6 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
           xi[l] = c * u - s * v;
           xj[l] = s * u + c * v;
         }
-        double *vi = Vt + (int64_t)i * n, *vj = Vt + (int64_t)j * n;
-        for (int r = lane; r < n; r += 64) {
-          const double u = vi[r], v = vj[r];
-          vi[r] = c * u - s * v;
-          vj[r] = s * u + c * v;
-        }
         rotated = 1;
       }
       __syncthreads();
@@ -148,31 +149,62 @@ __global__ void __launch_bounds__(kThreads) k_svd(const Blk *blks, double *scrat
     if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
     if (any == 0) break;
   }
-  // singular values and their ranks
-  for (int i = wave; i < n; i += kWaves) {
+  // singular values
+  for (int i = wave; i < n; i += NW) {
     double s2 = 0.0;
     for (int l = lane; l < m; l += 64) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
     s2 = wave_sum(s2);
     if (lane == 0) sig[i] = sqrt(s2);
   }
   __syncthreads();
+  __shared__ int s_rank[1024];
   double *U = scratch + b.offU, *Bo = scratch + b.offB, *S = scratch + b.offS;
-  for (int i = wave; i < n; i += kWaves) {
+  for (int i = threadIdx.x; i < n; i += NT) {
     const double si = sig[i];
     int rank = 0;
-    for (int j = lane; j < n; j += 64) {
+    for (int j = 0; j < n; ++j) {
       const double sj = sig[j];
       rank += (sj > si || (sj == si && j < i)) ? 1 : 0;
     }
-    for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);
-    if (lane == 0) S[rank] = si;
-    if (rows) {
-      for (int l = lane; l < C; l += 64) Bo[(int64_t)rank * C + l] = X[(int64_t)i * m + l];
-      for (int r = lane; r < R; r += 64) U[(int64_t)r * n + rank] = Vt[(int64_t)i * n + r];
-    } else {
-      const double inv = si > 0.0 ? 1.0 / si : 0.0;
-      for (int l = lane; l < R; l += 64) U[(int64_t)l * n + rank] = X[(int64_t)i * m + l] * inv;
-      for (int c = lane; c < C; c += 64) Bo[(int64_t)rank * C + c] = si * Vt[(int64_t)i * n + c];
+    if (i < 1024) s_rank[i] = rank;
+    S[rank] = si;
+  }
+  __syncthreads();
+  if (cols) {
+    // U[:, rank_i] = x_i / s_i;  B[rank_i, :] = U[:, rank_i]^T T
+    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
+      const int i = e / m, l = e - (int64_t)i * m;
+      const double si = sig[i];
+      U[(int64_t)l * n + s_rank[i]] = si > 0.0 ? X[e] / si : 0.0;
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)n * C; e += NT) {
+      const int i = e / C, c = e - (int64_t)i * C;
+      const double si = sig[i];
+      double acc = 0.0;
+      if (si > 0.0) {
+        const double *xi = X + (int64_t)i * m;
+        for (int r = 0; r < R; ++r) acc += xi[r] * T[(int64_t)r * C + c];
+        acc /= si;
+      }
+      Bo[(int64_t)s_rank[i] * C + c] = acc;
+    }
+  } else {
+    // B[rank_i, :] = x_i;  U[:, rank_i] = T x_i / s_i^2
+    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
+      const int i = e / m, l = e - (int64_t)i * m;
+      Bo[(int64_t)s_rank[i] * C + l] = X[e];
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)n * R; e += NT) {
+      const int i = e / R, r = e - (int64_t)i * R;
+      const double si = sig[i];
+      double acc = 0.0;
+      if (si > 0.0) {
+        const double *xi = X + (int64_t)i * m;
+        const double *tr = T + (int64_t)r * C;
+        for (int c = 0; c < C; ++c) acc += tr[c] * xi[c];
+        acc /= si * si;
+      }
+      U[(int64_t)r * n + s_rank[i]] = acc;
     }
   }
 }
@@ -338,18 +370,28 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const
   hipLaunchKernelGGL(k_two_site, dim3(nblk), dim3(kThreads), 0, st, kt, a, blk, gates, scratch);
 }
 
-void launch_svd(const Blk *blk, int nblk, double *scratch, int max_sweeps, int lds_doubles,
-                hipStream_t st) {
+void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_doubles,
+                double *scratch, int max_sweeps, hipStream_t st) {
   if (nblk == 0) return;
   const size_t bytes = (size_t)lds_doubles * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
     // allow the full LDS of a CU for one workgroup
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+    const int cap = 160 * 1024 - 8 * 1024;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<512>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<1024>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_svd, dim3(nblk), dim3(kThreads), bytes, st, blk, scratch, max_sweeps);
+  if (threads >= 1024)
+    hipLaunchKernelGGL(k_svd<1024>, dim3(nblk), dim3(1024), bytes, st, blk, idx, scratch, max_sweeps);
+  else if (threads >= 512)
+    hipLaunchKernelGGL(k_svd<512>, dim3(nblk), dim3(512), bytes, st, blk, idx, scratch, max_sweeps);
+  else
+    hipLaunchKernelGGL(k_svd<256>, dim3(nblk), dim3(256), bytes, st, blk, idx, scratch, max_sweeps);
 }
 
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,

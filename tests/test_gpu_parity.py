@@ -1,0 +1,143 @@
+"""HIP path vs the FP64 oracle, through the C ABI (MI355X only).
+
+Tolerances (FP64 path): max_ij |dH_ij| / max_ij |H_ij| <= 1e-10, max |dS| <= 1e-10,
+|dE| <= 1e-10 (1 + |E|).  These hold while the smallest relative singular-value
+gap at a truncation cut stays well above the rounding level; every workload
+below has its gap printed by the oracle (>= 1e-7).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2404_10223_amd as T
+import tnqe_synth as synth
+from oracle import fock
+from oracle.subspace import subspace as oracle_subspace
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _assert_pencil(H, S, E, Ho, So, Eo, tol=RTOL):
+    dH = np.abs(H - Ho).max() / np.abs(Ho).max()
+    dS = np.abs(S - So).max()
+    print(f"dH_rel={dH:.2e} dS={dS:.2e} dE={abs(E - Eo):.2e}", flush=True)
+    assert dH <= tol
+    assert dS <= tol
+    assert abs(E - Eo) <= tol * (1 + abs(Eo))
+    np.testing.assert_array_equal(H, H.T)
+    np.testing.assert_array_equal(S, S.T)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_config_parity_fp64(ctx, k):
+    prob = synth.make_config(k)
+    g = np.load(os.path.join(GOLD, f"oracle_config{k}.npz"))
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi)
+    _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]))
+    assert abs(rep["max_discarded_weight_sum"] - float(g["max_discarded"])) < 1e-10
+    np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
+    assert abs(c @ S @ c - 1.0) < 1e-10
+
+
+def test_lossless_matches_brute_force(ctx):
+    prob = synth.make_config(1)
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, chi_cap_override=10 ** 6)
+    Ho, So, Eo, co, _ = oracle_subspace(prob, chi_cap=10 ** 6)
+    _assert_pencil(H, S, E, Ho, So, Eo, 1e-12)
+    # against the 4^N Fock space directly
+    Hx = np.zeros((2, 2))
+    for i in range(2):
+        for j in range(2):
+            bi, bj = prob.mps[i], prob.mps[j]
+            hi = bi.U.T @ prob.h @ bi.U
+            Li = np.einsum("pa,kpq,qb->kab", bi.U, prob.L, bi.U)
+            Hf = fock.hamiltonian_fock(hi, np.einsum("kpq,krs->pqrs", Li, Li))
+            vj = fock.rotation_matrix_fock(bi.U.T @ bj.U) @ fock.mps_to_vector(bj.sites)
+            Hx[i, j] = fock.mps_to_vector(bi.sites) @ (Hf @ vj)
+    assert np.abs(H - Hx).max() <= 1e-12 * np.abs(Hx).max()
+
+
+def _with(prob, **kw):
+    d = dict(prob.__dict__)
+    d.update(kw)
+    return synth.Problem(**d)
+
+
+def test_edge_cases(ctx):
+    base = synth.make_problem(5, 3, 1, 6, 3, 4, (31,))      # odd N, uneven spins
+    # one MPS flipped to det U = -1 exercises the parity gate of the plan
+    m2 = base.mps[2]
+    U = m2.U.copy()
+    U[:, 0] *= -1
+    prob = _with(base, mps=[base.mps[0], base.mps[1], synth.MPS(m2.sites, m2.bond_qn, U)], e_core=1.25)
+    for chi in (1, 2, 6):
+        H, S, E, c, rep = ctx.subspace(prob, chi=chi)
+        Ho, So, Eo, co, _ = oracle_subspace(prob, chi_cap=chi)
+        _assert_pencil(H, S, E, Ho, So, Eo)
+    # M = 1: Rayleigh quotient, no gates
+    one = _with(base, mps=[base.mps[1]])
+    H, S, E, c, rep = ctx.subspace(one, chi=4)
+    assert abs(E - H[0, 0] / S[0, 0]) < 1e-12
+    # duplicated MPS: S singular, the duplicate is dropped
+    dup = _with(base, mps=[base.mps[0], base.mps[1], base.mps[1]])
+    H3, S3, E3, _, r3 = ctx.subspace(dup, chi=6)
+    H2, S2, E2, _, r2 = ctx.subspace(_with(base, mps=[base.mps[0], base.mps[1]]), chi=6)
+    assert r3["n_dropped"] == 1 and r2["n_dropped"] == 0
+    assert abs(E3 - E2) < 1e-9
+
+
+def test_input_validation(ctx):
+    base = synth.make_problem(4, 2, 2, 4, 2, 3, (32,))
+    bad_u = _with(base, mps=[base.mps[0], synth.MPS(base.mps[1].sites, base.mps[1].bond_qn, base.mps[1].U * 1.01)])
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(bad_u, chi=4)
+    assert e.value.status == -3
+    sites = [a.copy() for a in base.mps[0].sites]
+    sites[1][0, 0, :] = 1.0                                        # breaks the blocks
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(_with(base, mps=[synth.MPS(sites, base.mps[0].bond_qn, base.mps[0].U)]), chi=4)
+    assert e.value.status == -4
+    h = base.h.copy()
+    h[0, 0] = np.nan
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(_with(base, h=h), chi=4)
+    assert e.value.status in (-1, -9)
+    # the context still works after errors
+    H, S, E, c, rep = ctx.subspace(base, chi=4)
+    assert np.isfinite(E)
+
+
+def test_fp32_environments(ctx):
+    prob = synth.make_config(3)
+    g = np.load(os.path.join(GOLD, "oracle_config3.npz"))
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, precision="fp32")
+    dE = abs(E - float(g["E"]))
+    dH = np.abs(H - g["H"]).max() / np.abs(g["H"]).max()
+    print(f"fp32: dE={dE:.2e} dH_rel={dH:.2e}")
+    assert dH < 1e-6
+    assert dE < 1e-5
+
+
+def test_full_size_sampled_pairs(ctx):
+    """N = 24, chi = 256, M = 16: the benchmark workload, checked on sampled pairs."""
+    prob = synth.make_config(5)
+    g = np.load(os.path.join(GOLD, "oracle_config5_pairs.npz"))
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi)
+    for key in g.files:
+        i, j = map(int, key.split("_"))
+        h, s = g[key][0], g[key][1]
+        print(f"pair {i},{j}: dH={abs(H[i, j] - h):.2e} dS={abs(S[i, j] - s):.2e}")
+        assert abs(H[i, j] - h) <= RTOL * np.abs(np.diag(H)).max()
+        assert abs(S[i, j] - s) <= RTOL
+    np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
+    assert rep["max_discarded_weight_sum"] <= 1.0 + 1e-9

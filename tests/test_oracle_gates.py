@@ -139,3 +139,17 @@ def test_determinant_formula_is_a_representation():
     G = fock.rotation_matrix_fock(givens.rot(N, 1, th))
     v = np.random.default_rng(3).normal(size=4 ** N)
     np.testing.assert_allclose(G @ v, fock.apply_two_site_gate(v, N, 1, gates.g4(th)), atol=1e-14)
+
+
+def test_plan_ignores_rounding_noise():
+    # W = I + noise plans as an identity network; a signed permutation still reproduces W
+    r = np.random.default_rng(9)
+    N = 6
+    W = np.eye(N) + 1e-16 * r.normal(size=(N, N))
+    gl, ds = givens.plan(W)
+    assert ds == 1 and all(th == 0.0 for _, th in gl)
+    P = np.eye(N)[[2, 0, 1, 5, 3, 4]]
+    P[:, 1] *= -1
+    P[:, 4] *= -1
+    gl, ds = givens.plan(P)
+    np.testing.assert_allclose(givens.compose(N, gl, ds), P, atol=1e-13)
