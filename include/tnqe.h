@@ -128,11 +128,14 @@ typedef struct {
   double alg_bytes;                 /* algorithmic HBM bytes of the environment sweep   */
   double env_flops;                 /* environment-sweep part of alg_flops              */
   double env_kernel_ms;             /* summed device time of the environment kernels     */
+  double svd_kernel_ms;             /* summed device time of the truncation SVD launches */
+  double svd_flops;                 /* their algorithmic flops (4 n^2 m + 9 n^3 a block) */
   int32_t n_dropped;                /* eigenvalues of S below the threshold             */
   int32_t n_pairs;                  /* unique pairs computed (M (M + 1) / 2)            */
   int32_t max_bond;                 /* largest bond dimension seen                      */
   int32_t mpo_max_bond;             /* largest MPO bond dimension                       */
-  int32_t reserved[8];
+  int32_t svd_launches;             /* truncation SVD launches timed                    */
+  int32_t reserved[7];
 } tnqe_report;
 
 /* Fill defaults (chi = 16, FP64, eps_S = 1e-12, tau_w = 1e-13). */

@@ -43,8 +43,9 @@ class _Report(C.Structure):
                 ("t_total_ms", C.c_double), ("t_host_ms", C.c_double), ("t_gates_ms", C.c_double),
                 ("t_env_ms", C.c_double), ("t_gep_ms", C.c_double), ("alg_flops", C.c_double),
                 ("alg_bytes", C.c_double), ("env_flops", C.c_double), ("env_kernel_ms", C.c_double),
+                ("svd_kernel_ms", C.c_double), ("svd_flops", C.c_double),
                 ("n_dropped", C.c_int32), ("n_pairs", C.c_int32), ("max_bond", C.c_int32),
-                ("mpo_max_bond", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",

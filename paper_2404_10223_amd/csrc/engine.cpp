@@ -328,9 +328,35 @@ void plan_block_storage(Blk &b, Scratch &sc) {
   b.offW = need <= kLdsDoubles ? -1 : sc.take(need);
 }
 
+// Algorithmic flops of the SVD of an R x C block (n = min, m = max): the
+// Gram-plus-symmetric-eigensolver count 2 n^2 m + 9 n^3 + 2 n^2 m.
+double svd_flops(const Blk &b) {
+  const double n = std::min(b.R, b.C), m = std::max(b.R, b.C);
+  return 4.0 * n * n * m + 9.0 * n * n * n;
+}
+
+// Device time of timed SVD launches, collected after the next stream sync.
+struct SvdTimer {
+  int npending = 0;
+  double pending_flops[4] = {0, 0, 0, 0};
+  double ms = 0.0, flops = 0.0;
+  int launches = 0;
+  void collect(tnqe_ctx *ctx) {
+    for (int k = 0; k < npending; ++k) {
+      float t = 0.0f;
+      TNQE_HIP(hipEventElapsedTime(&t, ctx->svd_ev[2 * k], ctx->svd_ev[2 * k + 1]));
+      ms += t;
+      flops += pending_flops[k];
+      ++launches;
+    }
+    npending = 0;
+  }
+};
+
 // Launch the SVDs of all blocks, grouped by working-set size so small blocks
 // do not reserve a whole CU's LDS; within a group the largest go first.
-void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scratch, int max_sweeps) {
+void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scratch, int max_sweeps,
+             SvdTimer *timer = nullptr) {
   struct Cls { int64_t limit; int threads; };
   const Cls cls[4] = {{2048, 256}, {8192, 512}, {kLdsDoubles, 1024}, {INT64_MAX, 1024}};
   std::vector<std::vector<int>> idx(4);
@@ -346,8 +372,19 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scr
     if (idx[k].empty()) continue;
     std::stable_sort(idx[k].begin(), idx[k].end(),
                      [&](int x, int y) { return svd_need(blks[x]) > svd_need(blks[y]); });
-    launch_svd(dblk, c.upload(idx[k]), (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps,
-               c.ctx->stream);
+    const int *didx = c.upload(idx[k]);
+    const int slot = timer ? timer->npending : 0;
+    if (timer) {
+      double f = 0.0;
+      for (int i : idx[k]) f += svd_flops(blks[i]);
+      timer->pending_flops[slot] = f;
+      TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot], c.ctx->stream));
+    }
+    launch_svd(dblk, didx, (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps, c.ctx->stream);
+    if (timer) {
+      TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot + 1], c.ctx->stream));
+      timer->npending++;
+    }
   }
   c.check_launch();
 }
@@ -356,6 +393,7 @@ struct TruncStats {
   std::vector<double> discarded;   // per ket, summed
   double min_gap = 1.0;
   int max_bond = 0;
+  SvdTimer svd;                    // truncation SVDs of the gate steps
 };
 
 // One exact LQ centre move (site q -> q-1) for every ket in the set.
@@ -511,11 +549,12 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   double *dgates = c.upload(gates);
   Blk *dblk = c.upload(blks);
   launch_two_site(ks.tables(), a, dblk, (int)blks.size(), dgates, scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, scratch, max_sweeps);
+  run_svd(c, dblk, blks, scratch, max_sweeps, &ts.svd);
   c.check_launch();
   std::vector<double> sv(ns);
   TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
   c.sync();
+  ts.svd.collect(c.ctx);
   // global top-chi per ket
   std::vector<std::vector<int>> per(ks.n);
   for (size_t i = 0; i < blks.size(); ++i) per[blks[i].pair].push_back((int)i);
@@ -572,6 +611,40 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
 }
 
 // ------------------------------------------------------------ environment sweep
+// tile shape for a list of problems and the tile index ranges of each
+void assign_tiles(std::vector<GemmDesc> &v, bool long_m, int &tm, int &tn, int &ntiles) {
+  int maxM = 0, maxN = 0;
+  for (auto &d : v) {
+    maxM = std::max(maxM, d.M);
+    maxN = std::max(maxN, d.N);
+  }
+  if (long_m) {
+    if (maxN <= 16) { tm = 256; tn = 16; }
+    else if (maxN <= 32) { tm = 128; tn = 32; }
+    else { tm = 64; tn = 64; }
+  } else {
+    if (maxM <= 16) { tm = 16; tn = 256; }
+    else if (maxM <= 32) { tm = 32; tn = 128; }
+    else { tm = 64; tn = 64; }
+  }
+  ntiles = 0;
+  for (auto &d : v) {
+    d.tile0 = ntiles;
+    d.tilesN = (d.N + tn - 1) / tn;
+    d.tilesM = (d.M + tm - 1) / tm;
+    if (d.nbatch < 1) d.nbatch = 1;
+    ntiles += d.tilesM * d.tilesN * d.nbatch;
+  }
+}
+
+GemmDesc plain_desc() {
+  GemmDesc d{};
+  d.nbatch = 1;
+  d.alpha = 1.0;
+  d.beta = 0;
+  return d;
+}
+
 struct EnvResult {
   std::vector<double> H, S;   // per env pair
   double flops = 0.0, bytes = 0.0, kernel_ms = 0.0;
@@ -682,6 +755,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   struct SiteTabs {
     std::vector<GemmDesc> g1, g2;
     int t1 = 0, t2 = 0, tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
+    std::vector<std::vector<GemmDesc>> dense;   // dense channel mixing, one level per launch
+    std::vector<int> td, tmd, tnd;
     std::vector<MixTask> tasks;
     std::vector<int> chunk0;
     std::vector<MixSrc> srcs;
@@ -708,7 +783,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         for (int k = 0; k < 4; ++k) {
           const int sk = slot_of(sa + qk_a(k), sb + qk_b(k));
           if (dp(x + 1, sk) == 0) continue;
-          GemmDesc d{};
+          GemmDesc d = plain_desc();
           d.M = dpad[x][sbra] * cls[x][ci].nw;
           d.N = dpad[x + 1][sk];
           d.ldc = d.N;
@@ -729,14 +804,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         }
       }
     tb.Xsize = xo;
-    if (maxN1 <= 16) { tb.tm1 = 256; tb.tn1 = 16; }
-    else if (maxN1 <= 32) { tb.tm1 = 128; tb.tn1 = 32; }
-    else { tb.tm1 = 64; tb.tn1 = 64; }
-    for (auto &d : tb.g1) {
-      d.tile0 = tb.t1;
-      d.tilesN = (d.N + tb.tn1 - 1) / tb.tn1;
-      tb.t1 += ((d.M + tb.tm1 - 1) / tb.tm1) * d.tilesN;
-    }
+    (void)maxN1;
+    assign_tiles(tb.g1, true, tb.tm1, tb.tn1, tb.t1);
     // mix tasks and Y layout
     std::vector<int64_t> offY(cls[x + 1].size() * nslot * 4, -1);
     int64_t yo = 0;
@@ -754,6 +823,13 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           tk.nw_out = cls[x + 1][co].nw;
           tk.db = dpad[x + 1][s];
           tk.src0 = (int)tb.srcs.size();
+          struct DenseSrc {
+            int gi;
+            int64_t offX;
+            int nw_in;
+            double f;
+          };
+          std::vector<DenseSrc> dsrc;
           for (size_t gi = 0; gi < mpo.groups[x].size(); ++gi) {
             const MpoGroup &g = mpo.groups[x][gi];
             if (g.cout != (int)co) continue;
@@ -768,6 +844,10 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               // the source block's bra sector must be the task's (shape of the read)
               const int s_src = slot_of(sa - qk_a(k) + cls[x][g.cin].da, sb - qk_b(k) + cls[x][g.cin].db);
               require(s_src == s_a, TNQE_EINVAL, "MPO transition breaks particle-number bookkeeping");
+              if (g.dense) {
+                dsrc.push_back({(int)gi, ox, cls[x][g.cin].nw, P.f[e]});
+                continue;
+              }
               MixSrc sr{};
               sr.offX = ox;
               sr.nw_in = cls[x][g.cin].nw;
@@ -780,18 +860,52 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
             }
           }
           tk.nsrc = (int)tb.srcs.size() - tk.src0;
-          if (tk.nsrc == 0) continue;
+          if (tk.nsrc == 0 && dsrc.empty()) continue;
           tk.offY = yo;
           offY[(co * nslot + s) * 4 + kp] = yo;
           const int64_t tot = (int64_t)tk.da * tk.nw_out * tk.db;
           yo += tot;
           bytes_pp += eb * (double)tot;
+          // dense sources accumulate after the sparse pass, one source of a
+          // block per launch so no two problems of a launch share an output
+          for (size_t q = 0; q < dsrc.size(); ++q) {
+            const MpoGroup &g = mpo.groups[x][dsrc[q].gi];
+            GemmDesc d = plain_desc();
+            d.M = g.nr;
+            d.N = tk.db;
+            d.ldc = tk.db;
+            d.nseg = 1;
+            d.nbatch = tk.da;
+            d.offC = tk.offY + (int64_t)g.r0 * tk.db;
+            d.sC = (int64_t)tk.nw_out * tk.db;
+            d.alpha = dsrc[q].f;
+            d.beta = 1;
+            d.seg[0].K = g.nc;
+            d.seg[0].lda = g.nc;
+            d.seg[0].transA = 0;
+            d.seg[0].offA = mpo.site_nnz_off[x] + g.val_off;
+            d.sA = 0;
+            d.seg[0].offB = dsrc[q].offX + (int64_t)g.c0 * tk.db;
+            d.seg[0].ldb = tk.db;
+            d.sB = (int64_t)dsrc[q].nw_in * tk.db;
+            if (tb.dense.size() <= q) tb.dense.resize(q + 1);
+            tb.dense[q].push_back(d);
+            flops_pp += 2.0 * g.nr * g.nc * tk.db * tk.da;
+            bytes_pp += eb * ((double)g.nc * tk.db * tk.da + 2.0 * g.nr * tk.db * tk.da);
+          }
           tb.chunk0.push_back(tb.nchunk);
           tb.nchunk += (int)((tot + 255) / 256);
           tb.tasks.push_back(tk);
         }
       }
     tb.Ysize = yo;
+    for (auto &lv : tb.dense) {
+      int tm, tn, nt;
+      assign_tiles(lv, true, tm, tn, nt);
+      tb.td.push_back(nt);
+      tb.tmd.push_back(tm);
+      tb.tnd.push_back(tn);
+    }
     if (x < N - 1) {
       int maxM2 = 0;
       for (size_t co = 0; co < cls[x + 1].size(); ++co)
@@ -800,7 +914,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           if (lo < 0) continue;
           const int sa = s / nb1, sb = s % nb1;
           const int sbn = slot_of(sa + cls[x + 1][co].da, sb + cls[x + 1][co].db);
-          GemmDesc d{};
+          GemmDesc d = plain_desc();
           d.M = dpad[x + 1][sbn];
           d.N = cls[x + 1][co].nw * dpad[x + 1][s];
           d.ldc = d.N;
@@ -824,14 +938,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           maxM2 = std::max(maxM2, d.M);
           tb.g2.push_back(d);
         }
-      if (maxM2 <= 16) { tb.tm2 = 16; tb.tn2 = 256; }
-      else if (maxM2 <= 32) { tb.tm2 = 32; tb.tn2 = 128; }
-      else { tb.tm2 = 64; tb.tn2 = 64; }
-      for (auto &d : tb.g2) {
-        d.tile0 = tb.t2;
-        d.tilesN = (d.N + tb.tn2 - 1) / tb.tn2;
-        tb.t2 += ((d.M + tb.tm2 - 1) / tb.tm2) * d.tilesN;
-      }
+      (void)maxM2;
+      assign_tiles(tb.g2, false, tb.tm2, tb.tn2, tb.t2);
     } else {
       const int sN = slot_of(pb.na, pb.nb);
       const int co = mpo.final_class;
@@ -854,15 +962,26 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       CsrGroup cg;
       cg.rowptr = (int64_t)rowptr.size();
       cg.col = (int64_t)col.size();
+      cg.val = mpo.site_nnz_off[x] + g.val_off;
       rowptr.insert(rowptr.end(), g.rowptr.begin(), g.rowptr.end());
       col.insert(col.end(), g.col.begin(), g.col.end());
       groups.push_back(cg);
     }
-  require((int64_t)col.size() == nnz_total, TNQE_EINVAL, "MPO value layout mismatch");
+  require(mpo.site_nnz_off[N] == nnz_total, TNQE_EINVAL, "MPO value layout mismatch");
+  // coefficient values in the environment precision for the dense mixing GEMMs
+  const T *dvalsT = reinterpret_cast<const T *>(dvals);
+  if (!std::is_same<T, double>::value) {
+    std::vector<double> h((size_t)nnz_total * M);
+    TNQE_HIP(hipMemcpyAsync(h.data(), dvals, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    c.sync();
+    std::vector<T> hf(h.begin(), h.end());
+    dvalsT = c.upload(hf);
+  }
   const int *d_rowptr = c.upload(rowptr);
   const int *d_col = c.upload(col);
   const CsrGroup *d_groups = c.upload(groups);
   struct DevSite {
+    std::vector<GemmDesc *> dense;
     GemmDesc *g1, *g2;
     MixTask *tasks;
     int *chunk0;
@@ -884,6 +1003,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     ds[x].fin_offY = c.upload(tabs[x].fin_offY);
     ds[x].fin_offBra = c.upload(tabs[x].fin_offBra);
     ds[x].fin_da = c.upload(tabs[x].fin_da);
+    for (auto &lv : tabs[x].dense) ds[x].dense.push_back(c.upload(lv));
     Xmax = std::max(Xmax, tabs[x].Xsize);
     Ymax = std::max(Ymax, tabs[x].Ysize);
   }
@@ -914,6 +1034,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     }
     T **dL0 = c.upload(L0), **dL1 = c.upload(L1), **dX = c.upload(X), **dY = c.upload(Y);
     const int *dbasis = c.upload(basis);
+    std::vector<const T *> vptr(nb_);
+    for (int q = 0; q < nb_; ++q) vptr[q] = dvalsT + (size_t)basis[q] * nnz_total;
+    const T *const *dvptr = c.upload(vptr);
     std::vector<std::vector<const T *>> braT(N, std::vector<const T *>(nb_)), ketT(N, std::vector<const T *>(nb_));
     std::vector<const double *> bra64(nb_);
     for (int q = 0; q < nb_; ++q) {
@@ -954,6 +1077,11 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       ma.site_off = 0;
       ma.basis = dbasis;
       launch_mix<T>(ma, dX, dY, nb_, st);
+      for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
+        PairPtrs pd{reinterpret_cast<const void *const *>(dvptr), reinterpret_cast<const void *const *>(dX),
+                    reinterpret_cast<void *const *>(dY)};
+        launch_bgemm<T>(ds[x].dense[lv], (int)tb.dense[lv].size(), tb.td[lv], tb.tmd[lv], tb.tnd[lv], pd, nb_, st);
+      }
       if (x < N - 1) {
         PairPtrs p2{reinterpret_cast<const void *const *>(dbra[x]), reinterpret_cast<const void *const *>(dY),
                     reinterpret_cast<void *const *>(Ln)};
@@ -1240,9 +1368,12 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   for (double d : ts.discarded) rep.max_discarded_weight_sum = std::max(rep.max_discarded_weight_sum, d);
   rep.min_rel_gap = ts.min_gap;
   rep.env_flops = er.flops;
-  rep.alg_flops = er.flops;
   rep.alg_bytes = er.bytes;
   rep.env_kernel_ms = er.kernel_ms;
+  rep.svd_kernel_ms = ts.svd.ms;
+  rep.svd_flops = ts.svd.flops;
+  rep.svd_launches = ts.svd.launches;
+  rep.alg_flops = er.flops + ts.svd.flops;
   rep.n_pairs = (int)pairs.size();
   rep.max_bond = std::max(ts.max_bond, er.max_pad);
   rep.mpo_max_bond = mpo.max_bond;
@@ -1337,6 +1468,11 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
       delete ctx;
       return TNQE_EHIP;
     }
+  for (auto &e : ctx->svd_ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete ctx;
+      return TNQE_EHIP;
+    }
   *out = ctx;
   return TNQE_OK;
 }
@@ -1346,6 +1482,8 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : ctx->svd_ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
   return TNQE_OK;
@@ -1568,25 +1706,29 @@ tnqe_status tnqe_debug_mpo_dense(int32_t N, const double *h, const double *g, do
     }
     int dim = 1;
     std::vector<double> T((size_t)D[0], 1.0);   // bond 0: only I
-    int64_t vo = 0;
     for (int x = 0; x < N; ++x) {
       const int nd = dim * 4;
       std::vector<double> Tn((size_t)D[x + 1] * nd * nd, 0.0);
       for (const MpoGroup &grp : m.groups[x]) {
         const OpPattern &P = m.patterns[grp.pattern];
-        const int nrow = (int)grp.rowptr.size() - 1;
-        for (int r = 0; r < nrow; ++r)
-          for (int z = grp.rowptr[r]; z < grp.rowptr[r + 1]; ++z) {
-            const double v = vals[vo + z];
-            const int wi = base[x][grp.cin] + grp.col[z], wo = base[x + 1][grp.cout] + r;
-            const double *src = T.data() + (size_t)wi * dim * dim;
-            double *dst = Tn.data() + (size_t)wo * nd * nd;
-            for (int e = 0; e < P.n; ++e)
-              for (int i = 0; i < dim; ++i)
-                for (int j = 0; j < dim; ++j)
-                  dst[(size_t)(i * 4 + P.kp[e]) * nd + j * 4 + P.k[e]] += v * P.f[e] * src[(size_t)i * dim + j];
-          }
-        vo += (int64_t)grp.col.size();
+        const double *gv = vals.data() + m.site_nnz_off[x] + grp.val_off;
+        auto add = [&](int r, int col, double v) {
+          const int wi = base[x][grp.cin] + col, wo = base[x + 1][grp.cout] + r;
+          const double *src = T.data() + (size_t)wi * dim * dim;
+          double *dst = Tn.data() + (size_t)wo * nd * nd;
+          for (int e = 0; e < P.n; ++e)
+            for (int i = 0; i < dim; ++i)
+              for (int j = 0; j < dim; ++j)
+                dst[(size_t)(i * 4 + P.kp[e]) * nd + j * 4 + P.k[e]] += v * P.f[e] * src[(size_t)i * dim + j];
+        };
+        if (grp.dense) {
+          for (int r = 0; r < grp.nr; ++r)
+            for (int cc = 0; cc < grp.nc; ++cc) add(grp.r0 + r, grp.c0 + cc, gv[(int64_t)r * grp.nc + cc]);
+        } else {
+          const int nrow = (int)grp.rowptr.size() - 1;
+          for (int r = 0; r < nrow; ++r)
+            for (int z = grp.rowptr[r]; z < grp.rowptr[r + 1]; ++z) add(r, grp.col[z], gv[z]);
+        }
       }
       T.swap(Tn);
       dim = nd;

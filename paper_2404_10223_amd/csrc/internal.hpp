@@ -100,6 +100,11 @@ struct GemmDesc {
   int64_t offC;
   int tile0;           // first tile index of this problem
   int tilesN;          // tiles along N
+  int tilesM;          // tiles along M
+  int nbatch;          // independent problems at strides sA, sB, sC (>= 1)
+  int64_t sA, sB, sC;
+  double alpha;        // C = alpha * sum + beta * C, beta in {0, 1}
+  int beta;
   GemmSeg seg[4];
 };
 struct PairPtrs {      // per-pair base pointers for one GEMM launch
@@ -126,7 +131,8 @@ struct MixTask {
 };
 struct CsrGroup {
   int64_t rowptr;      // offset into the rowptr array (nw_out + 1 entries)
-  int64_t col;         // offset into the col / val arrays
+  int64_t col;         // offset into the col array
+  int64_t val;         // offset of the group's values in one basis' value array
 };
 
 struct MixArgs {

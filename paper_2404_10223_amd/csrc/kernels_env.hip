@@ -34,11 +34,14 @@ __global__ void __launch_bounds__(256) k_bgemm(const GemmDesc *descs, int ndesc,
     if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
   }
   const GemmDesc &d = descs[lo];
-  const int t = tile - d.tile0;
+  const int per = d.tilesM * d.tilesN;
+  const int t0 = tile - d.tile0;
+  const int bt = t0 / per, t = t0 - bt * per;
   const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
-  const T *Abase = static_cast<const T *>(pp.A[pair]);
-  const T *Bbase = static_cast<const T *>(pp.B[pair]);
-  T *Cb = static_cast<T *>(pp.C[pair]) + d.offC;
+  const T *Abase = static_cast<const T *>(pp.A[pair]) + bt * d.sA;
+  const T *Bbase = static_cast<const T *>(pp.B[pair]) + bt * d.sB;
+  T *Cb = static_cast<T *>(pp.C[pair]) + d.offC + bt * d.sC;
+  const T alpha = (T)d.alpha;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   T acc[RM][RN];
 #pragma unroll
@@ -87,7 +90,10 @@ __global__ void __launch_bounds__(256) k_bgemm(const GemmDesc *descs, int ndesc,
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
       const int gn = n0 + tx + j * TX;
-      if (gn < d.N) Cb[(int64_t)gm * d.ldc + gn] = acc[i][j];
+      if (gn < d.N) {
+        T *c = Cb + (int64_t)gm * d.ldc + gn;
+        *c = d.beta ? *c + alpha * acc[i][j] : alpha * acc[i][j];
+      }
     }
   }
 }
@@ -118,7 +124,7 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, const T *const *X, T *co
     const int r0 = a.rowptr[g.rowptr + w], r1 = a.rowptr[g.rowptr + w + 1];
     const T *xb = Xp + s.offX + ((int64_t)ap * s.nw_in) * tk.db + b;
     double part = 0.0;
-    for (int z = r0; z < r1; ++z) part += vals[g.col + z] * (double)xb[(int64_t)a.col[g.col + z] * tk.db];
+    for (int z = r0; z < r1; ++z) part += vals[g.val + z] * (double)xb[(int64_t)a.col[g.col + z] * tk.db];
     acc += s.factor * part;
   }
   Y[pair][tk.offY + e] = (T)acc;

@@ -20,6 +20,12 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// sum over an aligned group of g lanes (g a power of two dividing 64)
+__device__ inline double group_sum(double v, int g) {
+  for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ inline int seg_of(const int *s, int x) {
   int k = 0;
   while (k < 3 && x >= s[k + 1]) ++k;
@@ -101,14 +107,26 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // a rotation pair is handled by a group of G lanes (G | 64); short vectors
+  // use small groups so more pairs of a round proceed in parallel
+  const int G = m <= 48 ? 16 : (m <= 160 ? 32 : 64);
+  const int ngroup = NT / G, grp = threadIdx.x / G, gl = threadIdx.x % G;
   const int np = n + (n & 1);
   // rounding floor of a length-m dot product relative to the norms
   const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
     const int fl = sweep & 1;
     int rotated = 0;
+    // squared norms, recomputed each sweep and updated exactly per rotation
+    for (int i = grp; i < n; i += ngroup) {
+      double s2 = 0.0;
+      for (int l = gl; l < m; l += G) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
+      s2 = group_sum(s2, G);
+      if (gl == 0) sig[i] = s2;
+    }
+    __syncthreads();
     for (int rd = 0; rd < np - 1; ++rd) {
-      for (int k = wave; k < np / 2; k += NW) {
+      for (int k = grp; k < np / 2; k += ngroup) {
         int i, j;
         if (k == 0) {
           i = np - 1;
@@ -120,30 +138,28 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
         if (i >= n || j >= n) continue;
         if (i > j) { const int t = i; i = j; j = t; }
         double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int l = lane; l < m; l += 64) {
-          const double u = xi[l], v = xj[l];
-          al += u * u;
-          be += v * v;
-          ga += u * v;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+        double ga = 0.0;
+        for (int l = gl; l < m; l += G) ga += xi[l] * xj[l];
+        ga = group_sum(ga, G);
+        const double al = sig[i], be = sig[j];
+        if (al <= 0.0 || be <= 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int l = lane; l < m; l += 64) {
+        for (int l = gl; l < m; l += G) {
           const double u = xi[l], v = xj[l];
           xi[l] = c * u - s * v;
           xj[l] = s * u + c * v;
+        }
+        if (gl == 0) {
+          sig[i] = fmax(al - t * ga, 0.0);
+          sig[j] = be + t * ga;
         }
         rotated = 1;
       }
       __syncthreads();
     }
-    if (rotated && lane == 0) atomicOr(&s_rot[fl], 1);
+    if (rotated) atomicOr(&s_rot[fl], 1);
     __syncthreads();
     const int any = s_rot[fl];
     if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;

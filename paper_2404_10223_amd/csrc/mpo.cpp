@@ -16,6 +16,8 @@
 #include "mpo.hpp"
 
 #include <algorithm>
+#include <climits>
+#include <cstdlib>
 #include <map>
 #include <stdexcept>
 #include <unordered_map>
@@ -112,6 +114,12 @@ void enumerate_terms(int N, F &&f) {
 }
 
 int64_t term_count(int N) { return (int64_t)N * N * 2 + (int64_t)N * N * N * N * 4; }
+
+// smallest coupling block stored dense (TNQE_DENSE_MIN_AREA overrides, for tests)
+int64_t dense_min_area() {
+  const char *e = std::getenv("TNQE_DENSE_MIN_AREA");
+  return e ? std::max<int64_t>(1, std::atoll(e)) : 1024;
+}
 
 }  // namespace
 
@@ -317,17 +325,37 @@ void mpo_build_structure(int N, MpoStructure &m) {
       grp.pattern = kv.first[2];
       auto &v = kv.second;
       std::sort(v.begin(), v.end());
-      const int nrow = m.classes[x + 1][grp.cout].nw;
-      grp.rowptr.assign(nrow + 1, 0);
-      for (auto &e : v) grp.rowptr[e[0] + 1]++;
-      for (int r = 0; r < nrow; ++r) grp.rowptr[r + 1] += grp.rowptr[r];
-      grp.col.reserve(v.size());
-      grp.slot.reserve(v.size());
+      int rmin = INT32_MAX, rmax = -1, cmin = INT32_MAX, cmax = -1;
       for (auto &e : v) {
-        grp.col.push_back(e[1]);
-        grp.slot.push_back(e[2]);
+        rmin = std::min(rmin, e[0]);
+        rmax = std::max(rmax, e[0]);
+        cmin = std::min(cmin, e[1]);
+        cmax = std::max(cmax, e[1]);
       }
-      m.site_nnz[x] += (int64_t)v.size();
+      const int64_t area = (int64_t)(rmax - rmin + 1) * (cmax - cmin + 1);
+      if (area >= dense_min_area() && (int64_t)v.size() * 3 >= area) {
+        // a coefficient coupling between channel ranges: store it dense
+        grp.dense = true;
+        grp.r0 = rmin;
+        grp.nr = rmax - rmin + 1;
+        grp.c0 = cmin;
+        grp.nc = cmax - cmin + 1;
+        grp.dslot.assign(area, -1);
+        for (auto &e : v) grp.dslot[(int64_t)(e[0] - rmin) * grp.nc + (e[1] - cmin)] = e[2] >= 0 ? e[2] : -2;
+      } else {
+        const int nrow = m.classes[x + 1][grp.cout].nw;
+        grp.rowptr.assign(nrow + 1, 0);
+        for (auto &e : v) grp.rowptr[e[0] + 1]++;
+        for (int r = 0; r < nrow; ++r) grp.rowptr[r + 1] += grp.rowptr[r];
+        grp.col.reserve(v.size());
+        grp.slot.reserve(v.size());
+        for (auto &e : v) {
+          grp.col.push_back(e[1]);
+          grp.slot.push_back(e[2]);
+        }
+      }
+      grp.val_off = m.site_nnz[x];
+      m.site_nnz[x] += grp.nvals();
       m.groups[x].push_back(std::move(grp));
     }
     m.site_nnz_off[x + 1] = m.site_nnz_off[x] + m.site_nnz[x];
@@ -346,10 +374,18 @@ void mpo_values(const MpoStructure &m, const double *h, const double *g, std::ve
     slotval[slot] += m.term_factor[t] * c;
   });
   vals.resize(m.site_nnz_off[N]);
-  int64_t o = 0;
   for (int x = 0; x < N; ++x)
-    for (const MpoGroup &grp : m.groups[x])
-      for (size_t z = 0; z < grp.slot.size(); ++z) vals[o++] = grp.slot[z] >= 0 ? slotval[grp.slot[z]] : 1.0;
+    for (const MpoGroup &grp : m.groups[x]) {
+      double *o = vals.data() + m.site_nnz_off[x] + grp.val_off;
+      if (grp.dense) {
+        for (size_t z = 0; z < grp.dslot.size(); ++z) {
+          const int sl = grp.dslot[z];
+          o[z] = sl >= 0 ? slotval[sl] : (sl == -2 ? 1.0 : 0.0);
+        }
+      } else {
+        for (size_t z = 0; z < grp.slot.size(); ++z) o[z] = grp.slot[z] >= 0 ? slotval[grp.slot[z]] : 1.0;
+      }
+    }
 }
 
 }  // namespace tnqe

@@ -21,7 +21,15 @@ struct OpPattern {
 // (1) or a coefficient slot filled per basis.
 struct MpoGroup {
   int cin = 0, cout = 0, pattern = 0;
-  std::vector<int> rowptr, col, slot;   // slot < 0: fixed value 1
+  std::vector<int> rowptr, col, slot;   // sparse form; slot < 0: fixed value 1
+  // dense form (coefficient couplings between whole channel ranges): a block
+  // of rows [r0, r0 + nr) x columns [c0, c0 + nc), row-major, slot per entry
+  // (-1: zero, -2: fixed value 1); when dense, rowptr/col/slot are empty
+  bool dense = false;
+  int r0 = 0, nr = 0, c0 = 0, nc = 0;
+  std::vector<int> dslot;
+  int64_t val_off = 0;                  // offset of the group's values in its site
+  int64_t nvals() const { return dense ? (int64_t)nr * nc : (int64_t)slot.size(); }
 };
 
 struct MpoClass {

@@ -79,3 +79,13 @@ def test_host_mpo_contracts_to_fock_hamiltonian(lib, N):
     np.testing.assert_allclose(H, fock.hamiltonian_fock(prob.h, g).toarray(), atol=1e-12)
     np.testing.assert_array_equal(I, np.eye(4 ** N))
     assert mb <= 2 + 4 * N + 8 * (N // 2) ** 2 + 2 * N
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_host_mpo_dense_coupling_blocks(lib, N, monkeypatch):
+    # every coupling stored as a dense block: the same Hamiltonian
+    monkeypatch.setenv("TNQE_DENSE_MIN_AREA", "1")
+    prob = synth.make_problem(N, 1, 1, 2, 1, 3, (78, N))
+    g = prob.g()
+    H, I, _ = T.debug_mpo_dense(prob.h, g)
+    np.testing.assert_allclose(H, fock.hamiltonian_fock(prob.h, g).toarray(), atol=1e-12)

@@ -141,3 +141,17 @@ def test_full_size_sampled_pairs(ctx):
         assert abs(S[i, j] - s) <= RTOL
     np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
     assert rep["max_discarded_weight_sum"] <= 1.0 + 1e-9
+
+
+def test_dense_coupling_path(monkeypatch):
+    """Every MPO coupling routed through the dense mixing GEMMs (N = 7)."""
+    monkeypatch.setenv("TNQE_DENSE_MIN_AREA", "1")
+    c = T.Context(0)
+    try:
+        prob = synth.make_config(2)
+        g = np.load(os.path.join(GOLD, "oracle_config2.npz"))
+        for prec, tol in (("fp64", RTOL), ("fp32", 1e-5)):
+            H, S, E, cv, rep = c.subspace(prob, chi=prob.chi, precision=prec)
+            _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), tol)
+    finally:
+        c.close()
