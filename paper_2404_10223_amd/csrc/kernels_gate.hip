@@ -114,17 +114,26 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
   const int np = n + (n & 1);
   // rounding floor of a length-m dot product relative to the norms
   const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  __shared__ unsigned long long s_amax;
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
     const int fl = sweep & 1;
     int rotated = 0;
+    if (threadIdx.x == 0) s_amax = 0ull;
+    __syncthreads();
     // squared norms, recomputed each sweep and updated exactly per rotation
     for (int i = grp; i < n; i += ngroup) {
       double s2 = 0.0;
       for (int l = gl; l < m; l += G) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
       s2 = group_sum(s2, G);
-      if (gl == 0) sig[i] = s2;
+      if (gl == 0) {
+        sig[i] = s2;
+        atomicMax(&s_amax, (unsigned long long)__double_as_longlong(s2));   // s2 >= 0 orders as an integer
+      }
     }
     __syncthreads();
+    // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
+    // block: they are not rotated (they never survive a truncation)
+    const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
     for (int rd = 0; rd < np - 1; ++rd) {
       for (int k = grp; k < np / 2; k += ngroup) {
         int i, j;
@@ -137,12 +146,13 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
         }
         if (i >= n || j >= n) continue;
         if (i > j) { const int t = i; i = j; j = t; }
+        const double al = sig[i], be = sig[j];
+        if (al <= tiny || be <= tiny) continue;
         double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
         double ga = 0.0;
         for (int l = gl; l < m; l += G) ga += xi[l] * xj[l];
         ga = group_sum(ga, G);
-        const double al = sig[i], be = sig[j];
-        if (al <= 0.0 || be <= 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+        if (fabs(ga) <= tol * sqrt(al * be)) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
