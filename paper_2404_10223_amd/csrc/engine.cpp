@@ -14,8 +14,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace tnqe {
 
@@ -361,6 +364,9 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scr
   const Cls cls[4] = {{2048, 256}, {8192, 512}, {kLdsDoubles, 1024}, {INT64_MAX, 1024}};
   std::vector<std::vector<int>> idx(4);
   std::vector<int64_t> lds(4, 0);
+  // TNQE_DEBUG_SVD=1: print the Jacobi sweep counts of every launch (diagnostics)
+  static const bool dbg = std::getenv("TNQE_DEBUG_SVD") != nullptr;
+  int *dsweeps = dbg ? c.dev<int>(blks.size()) : nullptr;
   for (size_t i = 0; i < blks.size(); ++i) {
     const int64_t need = svd_need(blks[i]);
     int k = 0;
@@ -380,13 +386,30 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scr
       timer->pending_flops[slot] = f;
       TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot], c.ctx->stream));
     }
-    launch_svd(dblk, didx, (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps, c.ctx->stream);
+    launch_svd(dblk, didx, (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps, dsweeps,
+               c.ctx->stream);
     if (timer) {
       TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot + 1], c.ctx->stream));
       timer->npending++;
     }
   }
   c.check_launch();
+  if (dbg) {
+    std::vector<int> sw(blks.size());
+    TNQE_HIP(hipMemcpyAsync(sw.data(), dsweeps, sw.size() * sizeof(int), hipMemcpyDeviceToHost, c.ctx->stream));
+    TNQE_HIP(hipStreamSynchronize(c.ctx->stream));
+    for (int k = 0; k < 4; ++k) {
+      if (idx[k].empty()) continue;
+      int mx = 0, at = 0;
+      double mean = 0.0;
+      for (int i : idx[k]) {
+        mean += sw[i];
+        if (sw[i] > mx) { mx = sw[i]; at = i; }
+      }
+      std::fprintf(stderr, "svd class %d: %zu blocks, sweeps mean %.1f max %d (block %dx%d)\n", k, idx[k].size(),
+                   mean / idx[k].size(), mx, blks[at].R, blks[at].C);
+    }
+  }
 }
 
 struct TruncStats {
@@ -1190,11 +1213,27 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   // ---- host: integrals, MPO, plans
   MpoStructure &mpo = mpo_for(ctx, N);
   const int64_t nnz = mpo.site_nnz_off[N];
-  std::vector<double> vals((size_t)nnz * M), slotv, v1, hi, gi;
-  for (int i = 0; i < M; ++i) {
-    rotate_integrals(pb, pb.mps[i].U, hi, gi);
-    mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
-    std::copy(v1.begin(), v1.end(), vals.begin() + (size_t)i * nnz);
+  std::vector<double> vals((size_t)nnz * M);
+  {
+    // one basis per host thread: rotated integrals and MPO coefficients
+    const int nth = std::max(1, std::min<int>(M, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    std::vector<std::string> errs(nth);
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&, w] {
+        try {
+          std::vector<double> slotv, v1, hi, gi;
+          for (int i = w; i < M; i += nth) {
+            rotate_integrals(pb, pb.mps[i].U, hi, gi);
+            mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
+            std::copy(v1.begin(), v1.end(), vals.begin() + (size_t)i * nnz);
+          }
+        } catch (const std::exception &e) {
+          errs[w] = e.what();
+        }
+      });
+    for (auto &t : pool) t.join();
+    for (auto &e : errs) require(e.empty(), TNQE_EINVAL, e);
   }
   const double *dvals = c.upload(vals);
   std::vector<std::pair<int, int>> pairs;

@@ -71,7 +71,7 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const
 // SVD of the blocks idx[0..nblk) of blk with `threads` per workgroup and
 // lds_doubles of dynamic LDS (blocks with offW >= 0 work in global memory).
 void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_doubles,
-                double *scratch, int max_sweeps, hipStream_t st);
+                double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st);
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
                        hipStream_t st);
 void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, int nblk, double *scratch,

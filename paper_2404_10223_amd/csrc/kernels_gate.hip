@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kThreads) k_two_site(KetTables kt, int a, cons
 // when it fits, else a global work area).  idx lists the blocks of this launch.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, double *scratch,
-                                            int max_sweeps) {
+                                            int max_sweeps, int *sweeps_out) {
   constexpr int NW = NT / 64;
   extern __shared__ double lds[];
   const Blk b = blks[idx[blockIdx.x]];
@@ -115,7 +115,8 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
   // rounding floor of a length-m dot product relative to the norms
   const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
   __shared__ unsigned long long s_amax;
-  for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+  int sweep = 0;
+  for (; sweep < max_sweeps && n > 1; ++sweep) {
     const int fl = sweep & 1;
     int rotated = 0;
     if (threadIdx.x == 0) s_amax = 0ull;
@@ -175,6 +176,7 @@ __global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, dou
     if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
     if (any == 0) break;
   }
+  if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
   // singular values
   for (int i = wave; i < n; i += NW) {
     double s2 = 0.0;
@@ -397,7 +399,7 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const
 }
 
 void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_doubles,
-                double *scratch, int max_sweeps, hipStream_t st) {
+                double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st) {
   if (nblk == 0) return;
   const size_t bytes = (size_t)lds_doubles * sizeof(double);
   static bool attr_set = false;
@@ -413,11 +415,11 @@ void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_d
     attr_set = true;
   }
   if (threads >= 1024)
-    hipLaunchKernelGGL(k_svd<1024>, dim3(nblk), dim3(1024), bytes, st, blk, idx, scratch, max_sweeps);
+    hipLaunchKernelGGL(k_svd<1024>, dim3(nblk), dim3(1024), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
   else if (threads >= 512)
-    hipLaunchKernelGGL(k_svd<512>, dim3(nblk), dim3(512), bytes, st, blk, idx, scratch, max_sweeps);
+    hipLaunchKernelGGL(k_svd<512>, dim3(nblk), dim3(512), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
   else
-    hipLaunchKernelGGL(k_svd<256>, dim3(nblk), dim3(256), bytes, st, blk, idx, scratch, max_sweeps);
+    hipLaunchKernelGGL(k_svd<256>, dim3(nblk), dim3(256), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
 }
 
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
