@@ -130,11 +130,15 @@ typedef struct {
   double env_kernel_ms;             /* summed device time of the environment kernels     */
   double svd_kernel_ms;             /* summed device time of the truncation SVD launches */
   double svd_flops;                 /* their algorithmic flops (4 n^2 m + 9 n^3 a block) */
+  double svd_kind_ms[8];            /* the same split by SVD kernel: entry k < 6 for    */
+  double svd_kind_flops[8];         /*   4 (k + 1) vector elements per lane, entry 6 for */
+                                    /*   the global-memory fallback, entry 7 unused      */
   int32_t n_dropped;                /* eigenvalues of S below the threshold             */
   int32_t n_pairs;                  /* unique pairs computed (M (M + 1) / 2)            */
   int32_t max_bond;                 /* largest bond dimension seen                      */
   int32_t mpo_max_bond;             /* largest MPO bond dimension                       */
   int32_t svd_launches;             /* truncation SVD launches timed                    */
+  int32_t svd_kind_launches[8];     /* the same split by SVD kernel                     */
   int32_t reserved[7];
 } tnqe_report;
 

@@ -44,8 +44,10 @@ class _Report(C.Structure):
                 ("t_env_ms", C.c_double), ("t_gep_ms", C.c_double), ("alg_flops", C.c_double),
                 ("alg_bytes", C.c_double), ("env_flops", C.c_double), ("env_kernel_ms", C.c_double),
                 ("svd_kernel_ms", C.c_double), ("svd_flops", C.c_double),
+                ("svd_kind_ms", C.c_double * 8), ("svd_kind_flops", C.c_double * 8),
                 ("n_dropped", C.c_int32), ("n_pairs", C.c_int32), ("max_bond", C.c_int32),
-                ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32),
+                ("svd_kind_launches", C.c_int32 * 8), ("reserved", C.c_int32 * 7)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
@@ -130,7 +132,13 @@ def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-
 
 
 def report_dict(r):
-    return {name: getattr(r, name) for name, _ in _Report._fields_ if name != "reserved"}
+    out = {}
+    for name, _ in _Report._fields_:
+        if name == "reserved":
+            continue
+        v = getattr(r, name)
+        out[name] = list(v) if isinstance(v, C.Array) else v
+    return out
 
 
 class _Packed:

@@ -305,8 +305,6 @@ struct KetSet {
   }
 };
 
-constexpr int kLdsDoubles = 19 * 1024;   // 152 KiB of dynamic LDS (the kernel adds ~4 KiB static)
-
 struct Scratch {
   int64_t used = 0;
   int64_t take(int64_t n) {
@@ -316,19 +314,61 @@ struct Scratch {
   }
 };
 
-// working set of the SVD of a block: the rotated vectors and their norms
-int64_t svd_need(const Blk &b) { return (int64_t)std::min(b.R, b.C) * std::max(b.R, b.C) + std::min(b.R, b.C); }
+// Launch shape of the Jacobi SVD of an n-vector block with vectors of length
+// m: ceil(n/2) processors of G lanes, E vector components per lane in
+// registers (G E >= m), floor(n/2) traveller vectors in LDS rows of
+// G (E | 1) doubles.
+struct JacobiPlan {
+  int kind = kJacobiGlobal, grp = 64, threads = 1024, mpad = 0;
+  int64_t lds = 0;
+};
 
-// plan the SVD storage of a block (global work area only if it exceeds LDS)
+JacobiPlan jacobi_plan(int n, int m) {
+  JacobiPlan jp;
+  const int P = (n + 1) / 2, NTr = n / 2;
+  // preferred components per lane (tuning: TNQE_JACOBI_E = 8 ... 24)
+  static const int target = [] {
+    const char *e = std::getenv("TNQE_JACOBI_E");
+    const int v = e ? std::atoi(e) : 16;
+    return std::min(kJacobiMaxE, std::max(4, v / 4 * 4));
+  }();
+  int best = -1;
+  for (int pass = 0; pass < 2 && best < 0; ++pass) {
+    // first the smallest group with at most `target` components per lane,
+    // else the smallest group that fits at all (fewest threads)
+    const int cap = pass == 0 ? target : kJacobiMaxE;
+    for (int G = 1; G <= 64; G *= 2) {
+      const int E = ((m + G - 1) / G + 3) / 4 * 4;
+      if (E > cap) continue;
+      if (P * G > jacobi_max_threads(E)) break;
+      const int64_t lds = ((int64_t)NTr * G * (E | 1) + NTr + n) * 8 + (int64_t)n * 4;
+      if (lds > kJacobiLdsBytes) break;
+      best = G;
+      jp.kind = E / 4 - 1;
+      jp.grp = G;
+      jp.threads = (P * G + 63) / 64 * 64;
+      jp.mpad = G * (E | 1);
+      jp.lds = lds;
+      break;
+    }
+  }
+  return jp;
+}
+
+// plan the SVD of a block: launch shape and scratch (a global work area only
+// for blocks the register/LDS kernels cannot hold)
 void plan_block_storage(Blk &b, Scratch &sc) {
   b.n = std::min(b.R, b.C);
   require(b.n <= 1024, TNQE_ESHAPE, "quantum-number block larger than 1024 singular values");
+  const int m = std::max(b.R, b.C);
+  const JacobiPlan jp = jacobi_plan(b.n, m);
+  b.grp = jp.grp;
+  b.mpad = jp.mpad;
   b.offT = sc.take((int64_t)b.R * b.C);
   b.offU = sc.take((int64_t)b.R * b.n);
   b.offB = sc.take((int64_t)b.n * b.C);
   b.offS = -1;
-  const int64_t need = svd_need(b);
-  b.offW = need <= kLdsDoubles ? -1 : sc.take(need);
+  b.offW = jp.kind == kJacobiGlobal ? sc.take((int64_t)b.n * m + b.n) : -1;
 }
 
 // Algorithmic flops of the SVD of an R x C block (n = min, m = max): the
@@ -338,12 +378,17 @@ double svd_flops(const Blk &b) {
   return 4.0 * n * n * m + 9.0 * n * n * n;
 }
 
-// Device time of timed SVD launches, collected after the next stream sync.
+// Device time of timed SVD launches (per kernel), collected after the next
+// stream sync.
 struct SvdTimer {
+  static constexpr int kMaxPending = 32;
   int npending = 0;
-  double pending_flops[4] = {0, 0, 0, 0};
+  int pending_kind[kMaxPending] = {};
+  double pending_flops[kMaxPending] = {};
   double ms = 0.0, flops = 0.0;
   int launches = 0;
+  double kind_ms[kJacobiKinds] = {}, kind_flops[kJacobiKinds] = {};
+  int kind_launches[kJacobiKinds] = {};
   void collect(tnqe_ctx *ctx) {
     for (int k = 0; k < npending; ++k) {
       float t = 0.0f;
@@ -351,44 +396,56 @@ struct SvdTimer {
       ms += t;
       flops += pending_flops[k];
       ++launches;
+      kind_ms[pending_kind[k]] += t;
+      kind_flops[pending_kind[k]] += pending_flops[k];
+      kind_launches[pending_kind[k]]++;
     }
     npending = 0;
   }
 };
 
-// Launch the SVDs of all blocks, grouped by working-set size so small blocks
-// do not reserve a whole CU's LDS; within a group the largest go first.
-void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scratch, int max_sweeps,
+// Launch the SVDs of all blocks, grouped by kernel and workgroup size; within
+// a launch the largest blocks go first.
+void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_sweeps, double *scratch,
              SvdTimer *timer = nullptr) {
-  struct Cls { int64_t limit; int threads; };
-  const Cls cls[4] = {{2048, 256}, {8192, 512}, {kLdsDoubles, 1024}, {INT64_MAX, 1024}};
-  std::vector<std::vector<int>> idx(4);
-  std::vector<int64_t> lds(4, 0);
+  static const int kThreadSteps[6] = {64, 128, 256, 512, 768, 1024};
+  std::map<std::pair<int, int>, std::vector<int>> groups;   // (kind, threads) -> blocks
+  std::map<std::pair<int, int>, int64_t> lds;
   // TNQE_DEBUG_SVD=1: print the Jacobi sweep counts of every launch (diagnostics)
   static const bool dbg = std::getenv("TNQE_DEBUG_SVD") != nullptr;
   int *dsweeps = dbg ? c.dev<int>(blks.size()) : nullptr;
+  std::vector<int64_t> work(blks.size());
   for (size_t i = 0; i < blks.size(); ++i) {
-    const int64_t need = svd_need(blks[i]);
-    int k = 0;
-    while (need > cls[k].limit) ++k;
-    idx[k].push_back((int)i);
-    if (k < 3) lds[k] = std::max(lds[k], need);
+    const Blk &b = blks[i];
+    const int m = std::max(b.R, b.C);
+    const JacobiPlan jp = jacobi_plan(b.n, m);
+    int thr = 1024;
+    for (int t : kThreadSteps)
+      if (t >= jp.threads) {
+        thr = t;
+        break;
+      }
+    const auto key = std::make_pair(jp.kind, jp.kind == kJacobiGlobal ? 1024 : thr);
+    groups[key].push_back((int)i);
+    lds[key] = std::max(lds[key], jp.lds);
+    work[i] = (int64_t)b.n * b.n * m;
   }
-  for (int k = 3; k >= 0; --k) {
-    if (idx[k].empty()) continue;
-    std::stable_sort(idx[k].begin(), idx[k].end(),
-                     [&](int x, int y) { return svd_need(blks[x]) > svd_need(blks[y]); });
-    const int *didx = c.upload(idx[k]);
-    const int slot = timer ? timer->npending : 0;
-    if (timer) {
+  for (auto &kv : groups) {
+    std::vector<int> &idx = kv.second;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return work[x] > work[y]; });
+    const int *didx = c.upload(idx);
+    const bool timed = timer && timer->npending < SvdTimer::kMaxPending;
+    const int slot = timed ? timer->npending : 0;
+    if (timed) {
       double f = 0.0;
-      for (int i : idx[k]) f += svd_flops(blks[i]);
+      for (int i : idx) f += svd_flops(blks[i]);
       timer->pending_flops[slot] = f;
+      timer->pending_kind[slot] = kv.first.first;
       TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot], c.ctx->stream));
     }
-    launch_svd(dblk, didx, (int)idx[k].size(), cls[k].threads, (int)lds[k], scratch, max_sweeps, dsweeps,
-               c.ctx->stream);
-    if (timer) {
+    launch_jacobi(dblk, didx, (int)idx.size(), kv.first.first, kv.first.second, (int)lds[kv.first], scratch,
+                  max_sweeps, dsweeps, c.ctx->stream);
+    if (timed) {
       TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot + 1], c.ctx->stream));
       timer->npending++;
     }
@@ -398,16 +455,16 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, double *scr
     std::vector<int> sw(blks.size());
     TNQE_HIP(hipMemcpyAsync(sw.data(), dsweeps, sw.size() * sizeof(int), hipMemcpyDeviceToHost, c.ctx->stream));
     TNQE_HIP(hipStreamSynchronize(c.ctx->stream));
-    for (int k = 0; k < 4; ++k) {
-      if (idx[k].empty()) continue;
-      int mx = 0, at = 0;
+    for (auto &kv : groups) {
+      int mx = 0, at = kv.second[0];
       double mean = 0.0;
-      for (int i : idx[k]) {
+      for (int i : kv.second) {
         mean += sw[i];
         if (sw[i] > mx) { mx = sw[i]; at = i; }
       }
-      std::fprintf(stderr, "svd class %d: %zu blocks, sweeps mean %.1f max %d (block %dx%d)\n", k, idx[k].size(),
-                   mean / idx[k].size(), mx, blks[at].R, blks[at].C);
+      std::fprintf(stderr, "svd kind %d threads %d: %zu blocks, sweeps mean %.1f max %d (block %dx%d)\n",
+                   kv.first.first, kv.first.second, kv.second.size(), mean / kv.second.size(), mx, blks[at].R,
+                   blks[at].C);
     }
   }
 }
@@ -474,7 +531,8 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
   Blk *dblk = c.upload(blks);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, scratch, max_sweeps);
+  run_svd(c, dblk, blks, max_sweeps, scratch);
+  launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
   ks.commit_bond(q);
   launch_apply_lq(ks.tables(), q, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
   c.check_launch();
@@ -530,7 +588,8 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
   launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
   Blk *dblk = c.upload(blks);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, scratch, max_sweeps);
+  run_svd(c, dblk, blks, max_sweeps, scratch);
+  launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
   ks.commit_bond(p + 1);
   launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
   c.check_launch();
@@ -572,7 +631,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   double *dgates = c.upload(gates);
   Blk *dblk = c.upload(blks);
   launch_two_site(ks.tables(), a, dblk, (int)blks.size(), dgates, scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, scratch, max_sweeps, &ts.svd);
+  run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
   c.check_launch();
   std::vector<double> sv(ns);
   TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
@@ -629,6 +688,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   }
   ks.commit_bond(a + 1);
   Blk *dblk2 = c.upload(blks);
+  launch_svd_factor(dblk2, (int)blks.size(), scratch, c.ctx->stream);
   launch_split_gate(ks.tables(), a, dblk2, (int)blks.size(), scratch, c.ctx->stream);
   c.check_launch();
 }
@@ -1412,6 +1472,11 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   rep.svd_kernel_ms = ts.svd.ms;
   rep.svd_flops = ts.svd.flops;
   rep.svd_launches = ts.svd.launches;
+  for (int k = 0; k < kJacobiKinds; ++k) {
+    rep.svd_kind_ms[k] = ts.svd.kind_ms[k];
+    rep.svd_kind_flops[k] = ts.svd.kind_flops[k];
+    rep.svd_kind_launches[k] = ts.svd.kind_launches[k];
+  }
   rep.alg_flops = er.flops + ts.svd.flops;
   rep.n_pairs = (int)pairs.size();
   rep.max_bond = std::max(ts.max_bond, er.max_pad);

@@ -63,7 +63,7 @@ struct tnqe_ctx {
   tnqe::Staging staging;
   std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
   hipEvent_t ev[8] = {};
-  hipEvent_t svd_ev[8] = {};   // timing of the truncation SVD launches
+  hipEvent_t svd_ev[64] = {};  // timing of the truncation SVD launches of one gate step
 };
 
 struct tnqe_problem {

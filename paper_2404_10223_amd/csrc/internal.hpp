@@ -45,7 +45,8 @@ struct Blk {
   int j0;              // first index of the sector in the new bond
   int kept;            // singular vectors kept
   int aux0, aux1;      // old offset / old bond dimension for the centre moves
-  int64_t offT, offU, offB, offS;   // scratch offsets (doubles)
+  int grp, mpad;       // Jacobi: lanes per vector pair, padded LDS row length
+  int64_t offT, offU, offB, offS;   // scratch offsets (doubles); U is [n][R], B is [n][C]
   int64_t offW;        // work area for blocks too large for LDS (-1: LDS)
 };
 
@@ -68,10 +69,18 @@ struct KetTables {
 
 void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const double *gates,
                      double *scratch, hipStream_t st);
-// SVD of the blocks idx[0..nblk) of blk with `threads` per workgroup and
-// lds_doubles of dynamic LDS (blocks with offW >= 0 work in global memory).
-void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_doubles,
-                double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st);
+// Jacobi SVD of the blocks idx[0..nblk) of blk: sorted singular values (offS)
+// and sorted rotated vectors (U = x / s in the columns case, B = x in the rows
+// case).  kind k < kJacobiGlobal selects the register-resident kernel with
+// E = 4 (k + 1) vector elements per lane (threads and lds_bytes per
+// workgroup); kJacobiGlobal is the global-memory fallback.
+constexpr int kJacobiMaxE = 24, kJacobiGlobal = kJacobiMaxE / 4, kJacobiKinds = kJacobiGlobal + 1;
+constexpr int jacobi_max_threads(int E) { return E > 20 ? 768 : 1024; }
+constexpr int kJacobiLdsBytes = 160 * 1024 - 1024;   // dynamic LDS cap per workgroup
+void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,
+                   double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st);
+// the other factor of the first `kept` sorted vectors of every block
+void launch_svd_factor(const Blk *blk, int nblk, double *scratch, hipStream_t st);
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
                        hipStream_t st);
 void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, int nblk, double *scratch,

@@ -1,5 +1,5 @@
-// Gate phase on gfx950: two-site gate contraction, per-block one-sided Jacobi
-// SVD in LDS, split of the truncated factors, and exact centre moves.
+// Gate phase on gfx950: two-site gate contraction, split of the truncated
+// factors, and exact centre moves (the SVDs are in kernels_svd.hip).
 //
 // Every kernel works on a list of quantum-number blocks (one workgroup per
 // block).  Blocks of all kets in flight are launched together, so one launch
@@ -14,17 +14,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// sum over an aligned group of g lanes (g a power of two dividing 64)
-__device__ inline double group_sum(double v, int g) {
-  for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ inline int seg_of(const int *s, int x) {
   int k = 0;
@@ -71,172 +60,6 @@ __global__ void __launch_bounds__(kThreads) k_two_site(KetTables kt, int a, cons
   }
 }
 
-// One-sided Jacobi SVD of an R x C block, T = U B with U orthonormal columns
-// and B = diag(s) V^T, sorted by decreasing singular value s.
-//
-// The shorter side is orthogonalised: if R >= C the C columns (length R), else
-// the R rows (length C), rotated pairwise in round-robin order until mutually
-// orthogonal to rounding.  No rotation matrix is accumulated: in the column
-// case U = x / s and B = U^T T; in the row case B = x and U = T B^T / s^2.
-// Either way the factor that is not the rotated vectors comes from one
-// product with the block, which keeps the working set at R x C doubles (LDS
-// when it fits, else a global work area).  idx lists the blocks of this launch.
-template <int NT>
-__global__ void __launch_bounds__(NT) k_svd(const Blk *blks, const int *idx, double *scratch,
-                                            int max_sweeps, int *sweeps_out) {
-  constexpr int NW = NT / 64;
-  extern __shared__ double lds[];
-  const Blk b = blks[idx[blockIdx.x]];
-  const int R = b.R, C = b.C;
-  const bool cols = R >= C;
-  const int n = cols ? C : R, m = cols ? R : C;
-  if (n == 0) return;
-  double *X = b.offW < 0 ? lds : scratch + b.offW;     // X[i*m + l]: vector i
-  double *sig = X + (int64_t)n * m;
-  // convergence flags, one per sweep parity: a flag is cleared only after every
-  // thread has read it (at least one barrier separates the read and the clear)
-  __shared__ int s_rot[2];
-  const double *T = scratch + b.offT;
-  if (threadIdx.x == 0) {
-    s_rot[0] = 0;
-    s_rot[1] = 0;
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
-    const int i = e / m, l = e - (int64_t)i * m;
-    X[e] = cols ? T[(int64_t)l * C + i] : T[(int64_t)i * C + l];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // a rotation pair is handled by a group of G lanes (G | 64); short vectors
-  // use small groups so more pairs of a round proceed in parallel
-  const int G = m <= 48 ? 16 : (m <= 160 ? 32 : 64);
-  const int ngroup = NT / G, grp = threadIdx.x / G, gl = threadIdx.x % G;
-  const int np = n + (n & 1);
-  // rounding floor of a length-m dot product relative to the norms
-  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
-  __shared__ unsigned long long s_amax;
-  int sweep = 0;
-  for (; sweep < max_sweeps && n > 1; ++sweep) {
-    const int fl = sweep & 1;
-    int rotated = 0;
-    if (threadIdx.x == 0) s_amax = 0ull;
-    __syncthreads();
-    // squared norms, recomputed each sweep and updated exactly per rotation
-    for (int i = grp; i < n; i += ngroup) {
-      double s2 = 0.0;
-      for (int l = gl; l < m; l += G) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
-      s2 = group_sum(s2, G);
-      if (gl == 0) {
-        sig[i] = s2;
-        atomicMax(&s_amax, (unsigned long long)__double_as_longlong(s2));   // s2 >= 0 orders as an integer
-      }
-    }
-    __syncthreads();
-    // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
-    // block: they are not rotated (they never survive a truncation)
-    const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
-    for (int rd = 0; rd < np - 1; ++rd) {
-      for (int k = grp; k < np / 2; k += ngroup) {
-        int i, j;
-        if (k == 0) {
-          i = np - 1;
-          j = rd;
-        } else {
-          i = (rd + k) % (np - 1);
-          j = (rd - k + np - 1) % (np - 1);
-        }
-        if (i >= n || j >= n) continue;
-        if (i > j) { const int t = i; i = j; j = t; }
-        const double al = sig[i], be = sig[j];
-        if (al <= tiny || be <= tiny) continue;
-        double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
-        double ga = 0.0;
-        for (int l = gl; l < m; l += G) ga += xi[l] * xj[l];
-        ga = group_sum(ga, G);
-        if (fabs(ga) <= tol * sqrt(al * be)) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int l = gl; l < m; l += G) {
-          const double u = xi[l], v = xj[l];
-          xi[l] = c * u - s * v;
-          xj[l] = s * u + c * v;
-        }
-        if (gl == 0) {
-          sig[i] = fmax(al - t * ga, 0.0);
-          sig[j] = be + t * ga;
-        }
-        rotated = 1;
-      }
-      __syncthreads();
-    }
-    if (rotated) atomicOr(&s_rot[fl], 1);
-    __syncthreads();
-    const int any = s_rot[fl];
-    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
-    if (any == 0) break;
-  }
-  if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
-  // singular values
-  for (int i = wave; i < n; i += NW) {
-    double s2 = 0.0;
-    for (int l = lane; l < m; l += 64) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
-    s2 = wave_sum(s2);
-    if (lane == 0) sig[i] = sqrt(s2);
-  }
-  __syncthreads();
-  __shared__ int s_rank[1024];
-  double *U = scratch + b.offU, *Bo = scratch + b.offB, *S = scratch + b.offS;
-  for (int i = threadIdx.x; i < n; i += NT) {
-    const double si = sig[i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double sj = sig[j];
-      rank += (sj > si || (sj == si && j < i)) ? 1 : 0;
-    }
-    if (i < 1024) s_rank[i] = rank;
-    S[rank] = si;
-  }
-  __syncthreads();
-  if (cols) {
-    // U[:, rank_i] = x_i / s_i;  B[rank_i, :] = U[:, rank_i]^T T
-    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
-      const int i = e / m, l = e - (int64_t)i * m;
-      const double si = sig[i];
-      U[(int64_t)l * n + s_rank[i]] = si > 0.0 ? X[e] / si : 0.0;
-    }
-    for (int64_t e = threadIdx.x; e < (int64_t)n * C; e += NT) {
-      const int i = e / C, c = e - (int64_t)i * C;
-      const double si = sig[i];
-      double acc = 0.0;
-      if (si > 0.0) {
-        const double *xi = X + (int64_t)i * m;
-        for (int r = 0; r < R; ++r) acc += xi[r] * T[(int64_t)r * C + c];
-        acc /= si;
-      }
-      Bo[(int64_t)s_rank[i] * C + c] = acc;
-    }
-  } else {
-    // B[rank_i, :] = x_i;  U[:, rank_i] = T x_i / s_i^2
-    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
-      const int i = e / m, l = e - (int64_t)i * m;
-      Bo[(int64_t)s_rank[i] * C + l] = X[e];
-    }
-    for (int64_t e = threadIdx.x; e < (int64_t)n * R; e += NT) {
-      const int i = e / R, r = e - (int64_t)i * R;
-      const double si = sig[i];
-      double acc = 0.0;
-      if (si > 0.0) {
-        const double *xi = X + (int64_t)i * m;
-        const double *tr = T + (int64_t)r * C;
-        for (int c = 0; c < C; ++c) acc += tr[c] * xi[c];
-        acc /= si * si;
-      }
-      U[(int64_t)r * n + s_rank[i]] = acc;
-    }
-  }
-}
-
 // New A_a columns and A_{a+1} rows of one kept block (zero, then scatter).
 __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, const Blk *blks,
                                                          const double *scratch) {
@@ -259,7 +82,7 @@ __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, co
     const int row = e / kept, jj = e - (int64_t)row * kept;
     const int k = seg_of(b.rs, row);
     const int l = kt.sec(a, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x + (row - b.rs[k]);
-    A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)row * b.n + jj];
+    A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)jj * b.R + row];
   }
   for (int64_t e = threadIdx.x; e < (int64_t)kept * b.C; e += kThreads) {
     const int jj = e / b.C, col = e - (int64_t)jj * b.C;
@@ -318,7 +141,8 @@ __global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, cons
       const int li = e / n, jj = e - (int64_t)li * n;
       const double *prow = Po + ((int64_t)(ls.x + li) * 4 + k) * Dold + b.aux0;
       double acc = 0.0;
-      for (int mm = 0; mm < b.R; ++mm) acc += prow[mm] * U[(int64_t)mm * n + jj];
+      const double *ucol = U + (int64_t)jj * b.R;
+      for (int mm = 0; mm < b.R; ++mm) acc += prow[mm] * ucol[mm];
       P[((int64_t)(ls.x + li) * 4 + k) * Dn + b.j0 + jj] = acc * S[jj];
     }
   }
@@ -363,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_qr(KetTables kt, int p, cons
     const int row = e / n, jj = e - (int64_t)row * n;
     const int k = seg_of(b.rs, row);
     const int l = kt.sec(p, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x + (row - b.rs[k]);
-    A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)row * n + jj];
+    A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)jj * b.R + row];
   }
   const int W = 4 * Drr;
   for (int64_t e = threadIdx.x; e < (int64_t)n * W; e += kThreads) {
@@ -396,30 +220,6 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const
                      double *scratch, hipStream_t st) {
   if (nblk == 0) return;
   hipLaunchKernelGGL(k_two_site, dim3(nblk), dim3(kThreads), 0, st, kt, a, blk, gates, scratch);
-}
-
-void launch_svd(const Blk *blk, const int *idx, int nblk, int threads, int lds_doubles,
-                double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st) {
-  if (nblk == 0) return;
-  const size_t bytes = (size_t)lds_doubles * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    // allow the full LDS of a CU for one workgroup
-    const int cap = 160 * 1024 - 8 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<256>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<512>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_svd<1024>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    attr_set = true;
-  }
-  if (threads >= 1024)
-    hipLaunchKernelGGL(k_svd<1024>, dim3(nblk), dim3(1024), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
-  else if (threads >= 512)
-    hipLaunchKernelGGL(k_svd<512>, dim3(nblk), dim3(512), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
-  else
-    hipLaunchKernelGGL(k_svd<256>, dim3(nblk), dim3(256), bytes, st, blk, idx, scratch, max_sweeps, sweeps_out);
 }
 
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,

@@ -1,0 +1,524 @@
+// Singular value decomposition of the quantum-number blocks on gfx950.
+//
+// One-sided Jacobi: the shorter side of an R x C block (columns if R >= C,
+// else rows) is rotated pairwise until the vectors are mutually orthogonal to
+// rounding; their norms are the singular values.  No rotation matrix is
+// accumulated.  The kernels write the rotated vectors sorted by decreasing
+// norm (columns case: U = x / s, rows case: B = x = s v^T) and the singular
+// values; k_svd_factor then forms the other factor of the kept vectors from
+// one product with the block (B = U^T T, or U = T B^T / s^2).
+//
+// Pair ordering (k_jacobi).  n vectors are held by P = ceil(n/2) processors
+// (aligned groups of G lanes of one wave).  Each processor keeps one resident
+// vector in registers; the other floor(n/2) vectors are travellers in LDS
+// slots.  A node of the ordering has r residents and t travellers
+// (|r - t| <= 1) and pairs every resident with every traveller in max(r, t)
+// rounds (resident k meets traveller (k + round) mod max(r, t)).  It then
+// splits: the residents form one child, the travellers the other, and x of
+// the processors swap their resident with one traveller slot each, so that
+// every child again has residents in registers and travellers in LDS.  After
+// ceil(log2 n) levels every pair has met exactly once (one sweep) with about
+// n rounds; per rotation only the traveller moves through LDS.  Lane gl of a
+// processor holds the E components gl*E .. gl*E+E-1 of a vector (zero past
+// the end), so every inner loop has a compile-time trip count.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace tnqe {
+
+namespace {
+
+// one 64-bit value moved by a DPP lane permutation (two 32-bit moves)
+template <int CTRL>
+__device__ inline double dpp64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64).  Every lane
+// of the group ends with the same bits: each step adds two lanes' partial
+// sums, and the two lanes of a step add the same operands.
+__device__ inline double group_sum(double v, int G) {
+  if (G >= 2) v += dpp64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  if (G >= 4) v += dpp64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  if (G >= 8) v += dpp64<0x141>(v);   // row_half_mirror: the other quad of 8
+  if (G >= 16) v += dpp64<0x140>(v);  // row_mirror: the other half of 16
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Rotation that orthogonalises (x, y) with squared norms al, be and product
+// ga: x' = c x - s y, y' = s x + c y; returns tan (for the norm updates).
+__device__ inline double jacobi_angle(double al, double be, double ga, double &c, double &s) {
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = c * t;
+  return t;
+}
+
+// rank of value i among n (descending, ties by index)
+__device__ inline int rank_of(const double *sig, int n, int i) {
+  const double si = sig[i];
+  int r = 0;
+  for (int j = 0; j < n; ++j) {
+    const double sj = sig[j];
+    r += (sj > si || (sj == si && j < i)) ? 1 : 0;
+  }
+  return r;
+}
+
+// at most 1024 threads (E <= 20) or 768 (E = 24, for the register budget)
+template <int E>
+__global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks, const int *idx, double *scratch,
+                                                                int max_sweeps, int *sweeps_out) {
+  extern __shared__ double lds[];
+  const Blk b = blks[idx[blockIdx.x]];
+  const int R = b.R, C = b.C;
+  const bool cols = R >= C;
+  const int n = b.n, m = cols ? R : C;
+  if (n == 0) return;
+  // in an LDS row the chunk of lane gl starts at gl*SL (SL odd: the lanes of
+  // a wave reading consecutive rows touch distinct banks)
+  constexpr int SL = E | 1;
+  const int G = b.grp, mp = G * SL;
+  const int P = (n + 1) >> 1, NTr = n >> 1;
+  double *X = lds;                              // traveller rows [NTr][mp]
+  double *tnrm = X + (int64_t)NTr * mp;         // traveller squared norms
+  double *sig = tnrm + NTr;                     // singular values [n]
+  int *rnk = reinterpret_cast<int *>(sig + n);  // ranks [n]
+  __shared__ int s_rot[2];
+  __shared__ unsigned long long s_amax;
+  const double *T = scratch + b.offT;
+  const int p = threadIdx.x / G, gl = threadIdx.x - p * G;
+  const bool act = p < P;
+  const int l0 = gl * E;
+  double *Xl = X + gl * SL;                     // this lane's chunk of row 0
+  double res[E], trv[E];
+  // vector i of the block: component l at T[i * vs + l * ls]
+  const int64_t vs = cols ? 1 : C, ls = cols ? C : 1;
+  if (act) {
+    const double *src = T + (int64_t)p * vs + (int64_t)l0 * ls;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      res[e] = l0 + e < m ? src[e * ls] : 0.0;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (p < NTr) {
+      const double *tsrc = T + (int64_t)(P + p) * vs + (int64_t)l0 * ls;
+      for (int e = 0; e < E; ++e) Xl[p * mp + e] = l0 + e < m ? tsrc[e * ls] : 0.0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
+  __syncthreads();
+  // rounding floor of a length-m dot product relative to the norms
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  double rn = 0.0;   // squared norm of the resident (same in all lanes of the group)
+  int sweep = 0;
+  for (; sweep < max_sweeps && n > 1; ++sweep) {
+    const int fl = sweep & 1;
+    if (threadIdx.x == 0) s_amax = 0ull;
+    __syncthreads();
+    // squared norms, recomputed each sweep and updated exactly per rotation
+    if (act) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) s2 += res[e] * res[e];
+      rn = group_sum(s2, G);
+      double mx = rn;
+      if (p < NTr) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double v = Xl[p * mp + e];
+          t2 += v * v;
+        }
+        t2 = group_sum(t2, G);
+        if (gl == 0) tnrm[p] = t2;
+        mx = fmax(mx, t2);
+      }
+      if (gl == 0) atomicMax(&s_amax, (unsigned long long)__double_as_longlong(mx));   // >= 0 orders as an integer
+    }
+    __syncthreads();
+    // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
+    // block: they are not rotated (they never survive a truncation)
+    const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
+    int rotated = 0;
+    int pb = 0, sb = 0, r = P, t = NTr;   // this processor's node
+    for (int lv = 0;; ++lv) {
+      if (((n + (1 << lv) - 1) >> lv) <= 1) break;            // largest node has one vector
+      const int rounds = (n + (2 << lv) - 1) >> (lv + 1);      // = max over nodes of max(r, t)
+      const int k = p - pb, q = max(r, t);
+      for (int rho = 0; rho < rounds; ++rho) {
+        if (act && rho < q) {
+          int j = k + rho;
+          if (j >= q) j -= q;
+          if (j < t) {
+            double *xs = Xl + (sb + j) * mp;
+#pragma unroll
+            for (int e = 0; e < E; ++e) trv[e] = xs[e];
+            const double al = rn, be = tnrm[sb + j];
+            if (al > tiny && be > tiny) {
+              double ga = 0.0;
+#pragma unroll
+              for (int e = 0; e < E; ++e) ga += res[e] * trv[e];
+              ga = group_sum(ga, G);
+              if (fabs(ga) > tol * sqrt(al * be)) {
+                double c, s;
+                const double tn = jacobi_angle(al, be, ga, c, s);
+                // one component at a time (keeps the live registers at the
+                // two vectors; the stores retire the traveller as it goes)
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                  const double u = res[e], v = trv[e];
+                  res[e] = c * u - s * v;
+                  xs[e] = s * u + c * v;
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                rn = fmax(al - tn * ga, 0.0);
+                if (gl == 0) tnrm[sb + j] = be + tn * ga;
+                rotated = 1;
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // split the node: residents (pb .. pb+rA) stay, the next x processors
+      // swap their resident with the traveller in slot sb + (k - rA)
+      const int x = (t == r + 1) ? (r + 1) >> 1 : r >> 1;
+      const int rA = r - x;
+      const bool sw = act && k >= rA && k < r;
+      double *xw = Xl + (sb + (k - rA)) * mp;
+      double nn = 0.0;
+      if (sw) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) trv[e] = xw[e];
+        nn = tnrm[sb + (k - rA)];
+      }
+      __syncthreads();
+      if (sw) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          xw[e] = res[e];
+          res[e] = trv[e];
+        }
+        if (gl == 0) tnrm[sb + (k - rA)] = rn;
+        rn = nn;
+      }
+      __syncthreads();
+      if (k < rA) {
+        r = rA;
+        t = x;
+      } else {
+        pb += rA;
+        sb += x;
+        t = t - x;
+        r = x;
+      }
+    }
+    if (rotated && gl == 0) atomicOr(&s_rot[fl], 1);
+    __syncthreads();
+    const int any = s_rot[fl];
+    // the other flag is cleared only after every thread has read this one
+    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
+    if (any == 0) break;
+  }
+  if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
+  // singular values from the final vectors (residents 0..P, travellers P..n)
+  if (act) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) s2 += res[e] * res[e];
+    s2 = group_sum(s2, G);
+    if (gl == 0) sig[p] = sqrt(s2);
+    if (p < NTr) {
+      double t2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double v = Xl[p * mp + e];
+        t2 += v * v;
+      }
+      t2 = group_sum(t2, G);
+      if (gl == 0) sig[P + p] = sqrt(t2);
+    }
+  }
+  __syncthreads();
+  double *S = scratch + b.offS;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int rk = rank_of(sig, n, i);
+    rnk[i] = rk;
+    S[rk] = sig[i];
+  }
+  __syncthreads();
+  // sorted vectors: U[rank] = x / s (columns), B[rank] = x (rows); U is stored
+  // by column ([n][R]), B by row ([n][C]), so both are rows of length m here
+  double *out = scratch + (cols ? b.offU : b.offB);
+  if (act) {
+    const int rk = rnk[p];
+    const double sp = sig[p];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int l = l0 + e;
+      if (l < m) out[(int64_t)rk * m + l] = cols ? (sp > 0.0 ? res[e] / sp : 0.0) : res[e];
+    }
+    if (p < NTr) {
+      const int rt = rnk[P + p];
+      const double st = sig[P + p];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int l = l0 + e;
+        if (l < m) {
+          const double v = Xl[p * mp + e];
+          out[(int64_t)rt * m + l] = cols ? (st > 0.0 ? v / st : 0.0) : v;
+        }
+      }
+    }
+  }
+}
+
+// Blocks too large for k_jacobi: the vectors live in a global work area and
+// are rotated in cyclic round-robin order by groups of G lanes (same output).
+__global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const int *idx, double *scratch,
+                                                        int max_sweeps, int *sweeps_out) {
+  constexpr int NT = 1024, NW = NT / 64;
+  const Blk b = blks[idx[blockIdx.x]];
+  const int R = b.R, C = b.C;
+  const bool cols = R >= C;
+  const int n = b.n, m = cols ? R : C;
+  if (n == 0) return;
+  double *X = scratch + b.offW;                 // X[i*m + l]: vector i
+  double *sig = X + (int64_t)n * m;
+  __shared__ int s_rot[2];
+  __shared__ unsigned long long s_amax;
+  const double *T = scratch + b.offT;
+  if (threadIdx.x == 0) {
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
+    const int i = e / m, l = e - (int64_t)i * m;
+    X[e] = cols ? T[(int64_t)l * C + i] : T[(int64_t)i * C + l];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = 64, ngroup = NT / G, grp = threadIdx.x / G, gl = threadIdx.x % G;
+  const int np = n + (n & 1);
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  int sweep = 0;
+  for (; sweep < max_sweeps && n > 1; ++sweep) {
+    const int fl = sweep & 1;
+    int rotated = 0;
+    if (threadIdx.x == 0) s_amax = 0ull;
+    __syncthreads();
+    for (int i = grp; i < n; i += ngroup) {
+      double s2 = 0.0;
+      for (int l = gl; l < m; l += G) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
+      s2 = wave_sum(s2);
+      if (gl == 0) {
+        sig[i] = s2;
+        atomicMax(&s_amax, (unsigned long long)__double_as_longlong(s2));
+      }
+    }
+    __syncthreads();
+    const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
+    for (int rd = 0; rd < np - 1; ++rd) {
+      for (int k = grp; k < np / 2; k += ngroup) {
+        int i, j;
+        if (k == 0) {
+          i = np - 1;
+          j = rd;
+        } else {
+          i = (rd + k) % (np - 1);
+          j = (rd - k + np - 1) % (np - 1);
+        }
+        if (i >= n || j >= n) continue;
+        const double al = sig[i], be = sig[j];
+        if (al <= tiny || be <= tiny) continue;
+        double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
+        double ga = 0.0;
+        for (int l = gl; l < m; l += G) ga += xi[l] * xj[l];
+        ga = wave_sum(ga);
+        if (fabs(ga) <= tol * sqrt(al * be)) continue;
+        double c, s;
+        const double tn = jacobi_angle(al, be, ga, c, s);
+        for (int l = gl; l < m; l += G) {
+          const double u = xi[l], v = xj[l];
+          xi[l] = c * u - s * v;
+          xj[l] = s * u + c * v;
+        }
+        if (gl == 0) {
+          sig[i] = fmax(al - tn * ga, 0.0);
+          sig[j] = be + tn * ga;
+        }
+        rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (rotated) atomicOr(&s_rot[fl], 1);
+    __syncthreads();
+    const int any = s_rot[fl];
+    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
+    if (any == 0) break;
+  }
+  if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
+  for (int i = wave; i < n; i += NW) {
+    double s2 = 0.0;
+    for (int l = lane; l < m; l += 64) s2 += X[(int64_t)i * m + l] * X[(int64_t)i * m + l];
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[i] = sqrt(s2);
+  }
+  __syncthreads();
+  __shared__ int s_rank[1024];
+  double *S = scratch + b.offS;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const int rk = rank_of(sig, n, i);
+    s_rank[i] = rk;
+    S[rk] = sig[i];
+  }
+  __syncthreads();
+  double *out = scratch + (cols ? b.offU : b.offB);
+  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
+    const int i = e / m, l = e - (int64_t)i * m;
+    const double si = sig[i];
+    out[(int64_t)s_rank[i] * m + l] = cols ? (si > 0.0 ? X[e] / si : 0.0) : X[e];
+  }
+}
+
+// The factor not produced by the Jacobi kernels, for the first `kept` sorted
+// vectors: columns case B[j][c] = sum_r U[j][r] T[r][c]; rows case
+// U[j][r] = sum_c B[j][c] T[r][c] / s_j^2.  64 x 64 output tiles, 4 x 4 per
+// thread, K staged through LDS in steps of 16.
+constexpr int kFT = 64, kFK = 16;
+__global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, double *scratch) {
+  const Blk b = blks[blockIdx.x];
+  const int I = b.kept;
+  if (I == 0) return;
+  const bool cols = b.R >= b.C;
+  const double *T = scratch + b.offT;
+  const double *S = scratch + b.offS;
+  // out[i][j] = sc_i * sum_k A[i][k] * Bm(k, j)
+  const double *A = scratch + (cols ? b.offU : b.offB);
+  double *out = scratch + (cols ? b.offB : b.offU);
+  const int K = cols ? b.R : b.C, J = cols ? b.C : b.R;
+  // Bm(k, j) = T[k][j] (columns case) or T[j][k] (rows case)
+  const int64_t bk = cols ? b.C : 1, bj = cols ? 1 : b.C;
+  __shared__ double As[kFK][kFT + 1];
+  __shared__ double Bs[kFK][kFT + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tilesJ = (J + kFT - 1) / kFT, tilesI = (I + kFT - 1) / kFT;
+  for (int tile = 0; tile < tilesI * tilesJ; ++tile) {
+    const int i0 = (tile / tilesJ) * kFT, j0 = (tile % tilesJ) * kFT;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += kFK) {
+      for (int e = threadIdx.x; e < kFK * kFT; e += 256) {
+        // A tile: 64 rows i x 16 k (k fastest: A rows are contiguous in k)
+        const int ii = e / kFK, kk = e % kFK;
+        const int gi = i0 + ii, gk = k0 + kk;
+        As[kk][ii] = (gi < I && gk < K) ? A[(int64_t)gi * K + gk] : 0.0;
+        // B tile: 16 k x 64 j, with the contiguous index fastest
+        int jj, kb;
+        if (cols) {
+          kb = e / kFT;
+          jj = e % kFT;
+        } else {
+          jj = e / kFK;
+          kb = e % kFK;
+        }
+        const int gj = j0 + jj, gk2 = k0 + kb;
+        Bs[kb][jj] = (gj < J && gk2 < K) ? T[(int64_t)gk2 * bk + (int64_t)gj * bj] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kFK; ++kk) {
+        double a[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = As[kk][ty + 16 * u];
+          bv[u] = Bs[kk][tx + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gi = i0 + ty + 16 * u;
+      if (gi >= I) continue;
+      double sc = 1.0;
+      if (!cols) {
+        const double s = S[gi];
+        sc = s > 0.0 ? 1.0 / (s * s) : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gj = j0 + tx + 16 * v;
+        if (gj < J) out[(int64_t)gi * J + gj] = acc[u][v] * sc;
+      }
+    }
+  }
+}
+
+template <int E>
+void set_lds_cap() {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jacobi<E>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLdsBytes);
+}
+
+template <int E>
+void launch_e(const Blk *blk, const int *idx, int nblk, int threads, int lds_bytes, double *scratch,
+              int max_sweeps, int *sweeps_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi<E>, dim3(nblk), dim3(threads), lds_bytes, st, blk, idx, scratch, max_sweeps,
+                     sweeps_out);
+}
+
+}  // namespace
+
+void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,
+                   double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st) {
+  if (nblk == 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    set_lds_cap<4>();
+    set_lds_cap<8>();
+    set_lds_cap<12>();
+    set_lds_cap<16>();
+    set_lds_cap<20>();
+    set_lds_cap<24>();
+    attr_set = true;
+  }
+  switch (kind) {
+    case 0: launch_e<4>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    case 1: launch_e<8>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    case 2: launch_e<12>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    case 3: launch_e<16>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    case 4: launch_e<20>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    case 5: launch_e<24>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
+    default:
+      hipLaunchKernelGGL(k_jacobi_global, dim3(nblk), dim3(1024), 0, st, blk, idx, scratch, max_sweeps,
+                         sweeps_out);
+      break;
+  }
+}
+
+void launch_svd_factor(const Blk *blk, int nblk, double *scratch, hipStream_t st) {
+  if (nblk == 0) return;
+  hipLaunchKernelGGL(k_svd_factor, dim3(nblk), dim3(256), 0, st, blk, scratch);
+}
+
+}  // namespace tnqe
