@@ -694,13 +694,8 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
 }
 
 // ------------------------------------------------------------ environment sweep
-// tile shape for a list of problems and the tile index ranges of each
-void assign_tiles(std::vector<GemmDesc> &v, bool long_m, int &tm, int &tn, int &ntiles) {
-  int maxM = 0, maxN = 0;
-  for (auto &d : v) {
-    maxM = std::max(maxM, d.M);
-    maxN = std::max(maxN, d.N);
-  }
+// Tile shape for a list of problems with largest extents maxM x maxN.
+void pick_tile(int maxM, int maxN, bool long_m, int &tm, int &tn) {
   if (long_m) {
     if (maxN <= 16) { tm = 256; tn = 16; }
     else if (maxN <= 32) { tm = 128; tn = 32; }
@@ -710,22 +705,6 @@ void assign_tiles(std::vector<GemmDesc> &v, bool long_m, int &tm, int &tn, int &
     else if (maxM <= 32) { tm = 32; tn = 128; }
     else { tm = 64; tn = 64; }
   }
-  ntiles = 0;
-  for (auto &d : v) {
-    d.tile0 = ntiles;
-    d.tilesN = (d.N + tn - 1) / tn;
-    d.tilesM = (d.M + tm - 1) / tm;
-    if (d.nbatch < 1) d.nbatch = 1;
-    ntiles += d.tilesM * d.tilesN * d.nbatch;
-  }
-}
-
-GemmDesc plain_desc() {
-  GemmDesc d{};
-  d.nbatch = 1;
-  d.alpha = 1.0;
-  d.beta = 0;
-  return d;
 }
 
 struct EnvResult {
@@ -734,90 +713,80 @@ struct EnvResult {
   int max_pad = 0;
 };
 
+// Environment sweeps of all pairs.  Items are the M bra MPS followed by the
+// rotated kets; pair q contracts bra item pairs[q].first with its ket item.
+// Block slots are sized by the largest dimensions over the items (one
+// descriptor list for all pairs); the kernels use each pair's own extents.
 template <typename T>
 void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
                const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
                int64_t nnz_total, EnvResult &res) {
   hipStream_t st = c.ctx->stream;
-  const int N = pb.N, M = pb.M, nslot = pb.nslot(), nb1 = pb.nb + 1;
+  const int N = pb.N, M = pb.M, nslot = pb.nslot(), nb1 = pb.nb + 1, nbond = N + 1;
   const int nket = kets ? kets->n : 0;
-  auto slot_of = [&](int a, int b) { return (a < 0 || b < 0 || a > pb.na || b > pb.nb) ? -1 : a * nb1 + b; };
-  // ---- common padded bond structure
-  std::vector<std::vector<int>> dpad(N + 1, std::vector<int>(nslot, 0)), opad(N + 1, std::vector<int>(nslot, 0));
-  std::vector<int> Dpad(N + 1, 0);
-  for (int b = 0; b <= N; ++b) {
-    for (int s = 0; s < nslot; ++s) {
-      int d = 0;
-      for (int i = 0; i < M; ++i) d = std::max(d, pb.mps[i].secdim[b][s]);
-      for (int t = 0; t < nket; ++t) d = std::max(d, kets->dim(b, t, s));
-      dpad[b][s] = d;
-    }
-    int o = 0;
-    for (int s = 0; s < nslot; ++s) {
-      opad[b][s] = o;
-      o += dpad[b][s];
-    }
-    Dpad[b] = o;
-    res.max_pad = std::max(res.max_pad, o);
-  }
-  auto dp = [&](int b, int s) { return s < 0 ? 0 : dpad[b][s]; };
-  // ---- repack bras and kets into the padded layout
   const int nitem = M + nket;
-  std::vector<int64_t> psite_off(N + 1, 0);
-  for (int p = 0; p < N; ++p) psite_off[p + 1] = psite_off[p] + (int64_t)Dpad[p] * 4 * Dpad[p + 1];
-  const int64_t per_item = psite_off[N];
-  double *pad64 = c.dev<double>((size_t)per_item * nitem);
-  T *padT = std::is_same<T, double>::value ? reinterpret_cast<T *>(pad64) : c.dev<T>((size_t)per_item * nitem);
-  for (int p = 0; p < N; ++p) {
-    std::vector<const double *> src(nitem);
-    std::vector<double *> dst64(nitem);
-    std::vector<T *> dstT(nitem);
-    std::vector<int2> tl((size_t)nitem * nslot), tr((size_t)nitem * nslot);
-    std::vector<int> Dr(nitem);
-    for (int it = 0; it < nitem; ++it) {
-      dst64[it] = pad64 + (size_t)it * per_item + psite_off[p];
-      dstT[it] = padT + (size_t)it * per_item + psite_off[p];
+  auto slot_of = [&](int a, int b) { return (a < 0 || b < 0 || a > pb.na || b > pb.nb) ? -1 : a * nb1 + b; };
+  // ---- item sector tables
+  std::vector<int2> itab((size_t)nitem * nbond * nslot, make_int2(0, 0));
+  std::vector<int> iD((size_t)nitem * nbond, 0);
+  for (int it = 0; it < nitem; ++it)
+    for (int b = 0; b <= N; ++b) {
+      int2 *row = itab.data() + ((size_t)it * nbond + b) * nslot;
       if (it < M) {
         const auto &m = pb.mps[it];
-        src[it] = pb.d_sites + m.site_off[p];
-        int ol = 0, orr = 0;
+        int o = 0;
         for (int s = 0; s < nslot; ++s) {
-          tl[(size_t)it * nslot + s] = make_int2(ol, m.secdim[p][s]);
-          tr[(size_t)it * nslot + s] = make_int2(orr, m.secdim[p + 1][s]);
-          ol += m.secdim[p][s];
-          orr += m.secdim[p + 1][s];
+          row[s] = make_int2(o, m.secdim[b][s]);
+          o += m.secdim[b][s];
         }
-        Dr[it] = m.dims[p + 1];
+        iD[(size_t)it * nbond + b] = m.dims[b];
       } else {
         const int t = it - M;
-        src[it] = kets->site_ptr[(size_t)t * N + p];
-        for (int s = 0; s < nslot; ++s) {
-          tl[(size_t)it * nslot + s] = kets->hbtab[((size_t)p * kets->n + t) * nslot + s];
-          tr[(size_t)it * nslot + s] = kets->hbtab[((size_t)(p + 1) * kets->n + t) * nslot + s];
-        }
-        Dr[it] = kets->htot[(size_t)(p + 1) * kets->n + t];
+        for (int s = 0; s < nslot; ++s) row[s] = kets->hbtab[((size_t)b * kets->n + t) * nslot + s];
+        iD[(size_t)it * nbond + b] = kets->htot[(size_t)b * kets->n + t];
       }
     }
-    std::vector<int2> pl(Dpad[p]), pr(Dpad[p + 1]);
-    for (int s = 0; s < nslot; ++s) {
-      for (int x = 0; x < dpad[p][s]; ++x) pl[opad[p][s] + x] = make_int2(s, x);
-      for (int x = 0; x < dpad[p + 1][s]; ++x) pr[opad[p + 1][s] + x] = make_int2(s, x);
-    }
-    const size_t mk = c.ctx->pool.mark();
-    const double *const *dsrc = c.upload(src);
-    const int2 *dtl = c.upload(tl), *dtr = c.upload(tr), *dpl = c.upload(pl), *dpr = c.upload(pr);
-    const int *dDr = c.upload(Dr);
-    launch_repack<double>(dsrc, c.upload(dst64), dtl, dtr, dDr, nslot, dpl, dpr, Dpad[p], Dpad[p + 1], nitem, st);
-    if (!std::is_same<T, double>::value)
-      launch_repack<T>(dsrc, c.upload(dstT), dtl, dtr, dDr, nslot, dpl, dpr, Dpad[p], Dpad[p + 1], nitem, st);
-    c.check_launch();
-    c.sync();
-    c.ctx->pool.rewind(mk);
+  auto idim = [&](int it, int b, int s) { return s < 0 ? 0 : itab[((size_t)it * nbond + b) * nslot + s].y; };
+  // largest sector dimensions over the items (block slot sizes)
+  std::vector<std::vector<int>> dpad(nbond, std::vector<int>(nslot, 0));
+  for (int b = 0; b <= N; ++b) {
+    for (int s = 0; s < nslot; ++s)
+      for (int it = 0; it < nitem; ++it) dpad[b][s] = std::max(dpad[b][s], idim(it, b, s));
+    for (int it = 0; it < nitem; ++it) res.max_pad = std::max(res.max_pad, iD[(size_t)it * nbond + b]);
   }
-  // ---- layouts
+  auto dp = [&](int b, int s) { return s < 0 ? 0 : dpad[b][s]; };
+  // ---- site tensors of every item in the environment precision
+  std::vector<const double *> site64((size_t)nitem * N);
+  for (int it = 0; it < nitem; ++it)
+    for (int p = 0; p < N; ++p)
+      site64[(size_t)it * N + p] = it < M ? pb.d_sites + pb.mps[it].site_off[p]
+                                          : kets->site_ptr[(size_t)(it - M) * N + p];
+  std::vector<const T *> siteT((size_t)nitem * N);
+  if (std::is_same<T, double>::value) {
+    for (size_t i = 0; i < site64.size(); ++i) siteT[i] = reinterpret_cast<const T *>(site64[i]);
+  } else {
+    std::vector<int64_t> cnt(site64.size());
+    int64_t tot = 0;
+    for (int it = 0; it < nitem; ++it)
+      for (int p = 0; p < N; ++p) {
+        cnt[(size_t)it * N + p] = (int64_t)iD[(size_t)it * nbond + p] * 4 * iD[(size_t)it * nbond + p + 1];
+        tot += cnt[(size_t)it * N + p];
+      }
+    float *buf = c.dev<float>((size_t)tot);
+    std::vector<float *> dst(site64.size());
+    int64_t o = 0;
+    for (size_t i = 0; i < site64.size(); ++i) {
+      dst[i] = buf + o;
+      o += cnt[i];
+      siteT[i] = reinterpret_cast<const T *>(dst[i]);
+    }
+    launch_cast(c.upload(site64), c.upload(dst), c.upload(cnt), (int)site64.size(), st);
+    c.check_launch();
+  }
+  // ---- block slots
   const auto &cls = mpo.classes;
-  std::vector<std::vector<int64_t>> Loff(N + 1);
-  std::vector<int64_t> Lsize(N + 1, 0);
+  std::vector<std::vector<int64_t>> Loff(nbond);
+  std::vector<int64_t> Lsize(nbond, 0);
   for (int b = 0; b <= N; ++b) {
     Loff[b].assign(cls[b].size() * nslot, -1);
     int64_t o = 0;
@@ -836,27 +805,26 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   std::vector<int> gbase(N + 1, 0);
   for (int x = 0; x < N; ++x) gbase[x + 1] = gbase[x] + (int)mpo.groups[x].size();
   struct SiteTabs {
-    std::vector<GemmDesc> g1, g2;
+    std::vector<EnvG1> g1;
+    std::vector<EnvG2> g2;
     int t1 = 0, t2 = 0, tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
-    std::vector<std::vector<GemmDesc>> dense;   // dense channel mixing, one level per launch
+    std::vector<std::vector<EnvGD>> dense;   // dense channel mixing, one level per launch
     std::vector<int> td, tmd, tnd;
     std::vector<MixTask> tasks;
     std::vector<int> chunk0;
     std::vector<MixSrc> srcs;
+    std::vector<int> src_nnz;                // stored couplings of each source (work count)
     int nchunk = 0;
     int64_t Xsize = 0, Ysize = 0;
-    std::vector<int64_t> fin_offY, fin_offBra;
-    std::vector<int> fin_da;
+    std::vector<EnvFinal> fin;
   };
   std::vector<SiteTabs> tabs(N);
-  double flops_pp = 0.0, bytes_pp = 0.0;
-  const double eb = sizeof(T);
   for (int x = 0; x < N; ++x) {
     SiteTabs &tb = tabs[x];
-    // GEMM1 and X layout
+    // GEMM1 and X slots
     std::vector<int64_t> offX(cls[x].size() * nslot * 4, -1);
     int64_t xo = 0;
-    int maxN1 = 0;
+    int maxM1 = 0, maxN1 = 0;
     for (size_t ci = 0; ci < cls[x].size(); ++ci)
       for (int s = 0; s < nslot; ++s) {
         const int64_t lo = Loff[x][ci * nslot + s];
@@ -866,30 +834,32 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         for (int k = 0; k < 4; ++k) {
           const int sk = slot_of(sa + qk_a(k), sb + qk_b(k));
           if (dp(x + 1, sk) == 0) continue;
-          GemmDesc d = plain_desc();
-          d.M = dpad[x][sbra] * cls[x][ci].nw;
-          d.N = dpad[x + 1][sk];
-          d.ldc = d.N;
-          d.nseg = 1;
-          d.offC = xo;
-          d.seg[0].K = dpad[x][s];
-          d.seg[0].lda = dpad[x][s];
-          d.seg[0].transA = 0;
-          d.seg[0].offA = lo;
-          d.seg[0].offB = ((int64_t)opad[x][s] * 4 + k) * Dpad[x + 1] + opad[x + 1][sk];
-          d.seg[0].ldb = 4 * Dpad[x + 1];
+          EnvG1 d{};
+          d.x = x;
+          d.nw = cls[x][ci].nw;
+          d.sbra = sbra;
+          d.s = s;
+          d.k = k;
+          d.sk = sk;
+          d.offL = lo;
+          d.offX = xo;
           offX[(ci * nslot + s) * 4 + k] = xo;
-          xo += (int64_t)d.M * d.N;
-          maxN1 = std::max(maxN1, d.N);
-          flops_pp += 2.0 * d.M * d.N * d.seg[0].K;
-          bytes_pp += eb * ((double)d.M * d.seg[0].K + (double)d.seg[0].K * d.N + (double)d.M * d.N);
+          const int Mp = dpad[x][sbra] * d.nw, Np = dpad[x + 1][sk];
+          xo += (int64_t)Mp * Np;
+          maxM1 = std::max(maxM1, Mp);
+          maxN1 = std::max(maxN1, Np);
           tb.g1.push_back(d);
         }
       }
     tb.Xsize = xo;
-    (void)maxN1;
-    assign_tiles(tb.g1, true, tb.tm1, tb.tn1, tb.t1);
-    // mix tasks and Y layout
+    pick_tile(maxM1, maxN1, true, tb.tm1, tb.tn1);
+    for (EnvG1 &d : tb.g1) {
+      d.tile0 = tb.t1;
+      d.tilesM = (dpad[x][d.sbra] * d.nw + tb.tm1 - 1) / tb.tm1;
+      d.tilesN = (dpad[x + 1][d.sk] + tb.tn1 - 1) / tb.tn1;
+      tb.t1 += d.tilesM * d.tilesN;
+    }
+    // mix tasks and Y slots
     std::vector<int64_t> offY(cls[x + 1].size() * nslot * 4, -1);
     int64_t yo = 0;
     for (size_t co = 0; co < cls[x + 1].size(); ++co)
@@ -902,9 +872,10 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           const int s_a = slot_of(sa + cls[x + 1][co].da - qk_a(kp), sb + cls[x + 1][co].db - qk_b(kp));
           if (dp(x, s_a) == 0) continue;
           MixTask tk{};
-          tk.da = dpad[x][s_a];
+          tk.x = x;
+          tk.sa = s_a;
+          tk.s = s;
           tk.nw_out = cls[x + 1][co].nw;
-          tk.db = dpad[x + 1][s];
           tk.src0 = (int)tb.srcs.size();
           struct DenseSrc {
             int gi;
@@ -937,44 +908,35 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               sr.group = gbase[x] + (int)gi;
               sr.factor = P.f[e];
               tb.srcs.push_back(sr);
-              const double nnz = (double)g.col.size();
-              flops_pp += 2.0 * nnz * tk.da * tk.db;
-              bytes_pp += eb * (double)tk.da * sr.nw_in * tk.db;
+              tb.src_nnz.push_back((int)g.col.size());
             }
           }
           tk.nsrc = (int)tb.srcs.size() - tk.src0;
           if (tk.nsrc == 0 && dsrc.empty()) continue;
           tk.offY = yo;
           offY[(co * nslot + s) * 4 + kp] = yo;
-          const int64_t tot = (int64_t)tk.da * tk.nw_out * tk.db;
+          const int64_t tot = (int64_t)dpad[x][s_a] * tk.nw_out * dpad[x + 1][s];
           yo += tot;
-          bytes_pp += eb * (double)tot;
           // dense sources accumulate after the sparse pass, one source of a
           // block per launch so no two problems of a launch share an output
           for (size_t q = 0; q < dsrc.size(); ++q) {
             const MpoGroup &g = mpo.groups[x][dsrc[q].gi];
-            GemmDesc d = plain_desc();
-            d.M = g.nr;
-            d.N = tk.db;
-            d.ldc = tk.db;
-            d.nseg = 1;
-            d.nbatch = tk.da;
-            d.offC = tk.offY + (int64_t)g.r0 * tk.db;
-            d.sC = (int64_t)tk.nw_out * tk.db;
-            d.alpha = dsrc[q].f;
-            d.beta = 1;
-            d.seg[0].K = g.nc;
-            d.seg[0].lda = g.nc;
-            d.seg[0].transA = 0;
-            d.seg[0].offA = mpo.site_nnz_off[x] + g.val_off;
-            d.sA = 0;
-            d.seg[0].offB = dsrc[q].offX + (int64_t)g.c0 * tk.db;
-            d.seg[0].ldb = tk.db;
-            d.sB = (int64_t)dsrc[q].nw_in * tk.db;
+            EnvGD d{};
+            d.x = x;
+            d.sa = s_a;
+            d.s = s;
+            d.nr = g.nr;
+            d.nc = g.nc;
+            d.r0 = g.r0;
+            d.c0 = g.c0;
+            d.nw_in = dsrc[q].nw_in;
+            d.nw_out = tk.nw_out;
+            d.offY = tk.offY;
+            d.offX = dsrc[q].offX;
+            d.valoff = mpo.site_nnz_off[x] + g.val_off;
+            d.f = dsrc[q].f;
             if (tb.dense.size() <= q) tb.dense.resize(q + 1);
             tb.dense[q].push_back(d);
-            flops_pp += 2.0 * g.nr * g.nc * tk.db * tk.da;
-            bytes_pp += eb * ((double)g.nc * tk.db * tk.da + 2.0 * g.nr * tk.db * tk.da);
           }
           tb.chunk0.push_back(tb.nchunk);
           tb.nchunk += (int)((tot + 255) / 256);
@@ -983,59 +945,120 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     tb.Ysize = yo;
     for (auto &lv : tb.dense) {
-      int tm, tn, nt;
-      assign_tiles(lv, true, tm, tn, nt);
+      int maxM = 0, maxN = 0;
+      for (auto &d : lv) {
+        maxM = std::max(maxM, d.nr);
+        maxN = std::max(maxN, dpad[x + 1][d.s]);
+      }
+      int tm, tn, nt = 0;
+      pick_tile(maxM, maxN, true, tm, tn);
+      for (auto &d : lv) {
+        d.tile0 = nt;
+        d.tilesM = (d.nr + tm - 1) / tm;
+        d.tilesN = (dpad[x + 1][d.s] + tn - 1) / tn;
+        nt += d.tilesM * d.tilesN * dpad[x][d.sa];
+      }
       tb.td.push_back(nt);
       tb.tmd.push_back(tm);
       tb.tnd.push_back(tn);
     }
     if (x < N - 1) {
-      int maxM2 = 0;
+      int maxM2 = 0, maxN2 = 0;
       for (size_t co = 0; co < cls[x + 1].size(); ++co)
         for (int s = 0; s < nslot; ++s) {
           const int64_t lo = Loff[x + 1][co * nslot + s];
           if (lo < 0) continue;
           const int sa = s / nb1, sb = s % nb1;
           const int sbn = slot_of(sa + cls[x + 1][co].da, sb + cls[x + 1][co].db);
-          GemmDesc d = plain_desc();
-          d.M = dpad[x + 1][sbn];
-          d.N = cls[x + 1][co].nw * dpad[x + 1][s];
-          d.ldc = d.N;
-          d.offC = lo;
+          EnvG2 d{};
+          d.x = x;
+          d.nw = cls[x + 1][co].nw;
+          d.sbn = sbn;
+          d.s = s;
+          d.offL = lo;
           d.nseg = 0;
           for (int kp = 0; kp < 4; ++kp) {
             const int64_t oy = offY[(co * nslot + s) * 4 + kp];
             if (oy < 0) continue;
-            const int s_a = slot_of(sa + cls[x + 1][co].da - qk_a(kp), sb + cls[x + 1][co].db - qk_b(kp));
-            GemmSeg &g = d.seg[d.nseg++];
-            g.K = dpad[x][s_a];
-            g.transA = 1;
-            g.lda = 4 * Dpad[x + 1];
-            g.offA = ((int64_t)opad[x][s_a] * 4 + kp) * Dpad[x + 1] + opad[x + 1][sbn];
-            g.offB = oy;
-            g.ldb = d.N;
-            flops_pp += 2.0 * d.M * d.N * g.K;
-            bytes_pp += eb * ((double)g.K * d.M + (double)g.K * d.N);
+            d.sa[d.nseg] = slot_of(sa + cls[x + 1][co].da - qk_a(kp), sb + cls[x + 1][co].db - qk_b(kp));
+            d.kp[d.nseg] = kp;
+            d.offY[d.nseg] = oy;
+            d.nseg++;
           }
-          bytes_pp += eb * (double)d.M * d.N;
-          maxM2 = std::max(maxM2, d.M);
+          maxM2 = std::max(maxM2, dpad[x + 1][sbn]);
+          maxN2 = std::max(maxN2, d.nw * dpad[x + 1][s]);
           tb.g2.push_back(d);
         }
-      (void)maxM2;
-      assign_tiles(tb.g2, false, tb.tm2, tb.tn2, tb.t2);
+      pick_tile(maxM2, maxN2, false, tb.tm2, tb.tn2);
+      for (EnvG2 &d : tb.g2) {
+        d.tile0 = tb.t2;
+        d.tilesM = (dpad[x + 1][d.sbn] + tb.tm2 - 1) / tb.tm2;
+        d.tilesN = (d.nw * dpad[x + 1][d.s] + tb.tn2 - 1) / tb.tn2;
+        tb.t2 += d.tilesM * d.tilesN;
+      }
     } else {
       const int sN = slot_of(pb.na, pb.nb);
       const int co = mpo.final_class;
       for (int kp = 0; kp < 4; ++kp) {
         const int64_t oy = offY[((size_t)co * nslot + sN) * 4 + kp];
         if (oy < 0) continue;
-        const int s_a = slot_of(pb.na - qk_a(kp), pb.nb - qk_b(kp));
-        tb.fin_offY.push_back(oy);
-        tb.fin_da.push_back(dpad[x][s_a]);
-        tb.fin_offBra.push_back((int64_t)opad[x][s_a] * 4 + kp);
+        EnvFinal f{};
+        f.sa = slot_of(pb.na - qk_a(kp), pb.nb - qk_b(kp));
+        f.kp = kp;
+        f.offY = oy;
+        tb.fin.push_back(f);
       }
     }
   }
+  // ---- algorithmic work with every pair's own block shapes (on a host
+  // thread, overlapping the sweeps)
+  const double eb = sizeof(T);
+  std::thread work_thread([&] {
+    double fl = 0.0, by = 0.0;
+    for (const auto &pr : pairs) {
+      const int q = (int)(&pr - pairs.data());
+      const int bi = pr.first, ki = ket_of_pair[q] < 0 ? pr.first : M + ket_of_pair[q];
+      for (int x = 0; x < N; ++x) {
+        const SiteTabs &tb = tabs[x];
+        for (const EnvG1 &d : tb.g1) {
+          const double m = (double)idim(bi, x, d.sbra) * d.nw, k = idim(ki, x, d.s), n = idim(ki, x + 1, d.sk);
+          fl += 2.0 * m * n * k;
+          by += eb * (m * k + k * n + m * n);
+        }
+        for (const MixTask &tk : tb.tasks) {
+          const double da = idim(bi, x, tk.sa), db = idim(ki, x + 1, tk.s);
+          for (int i = 0; i < tk.nsrc; ++i) {
+            fl += 2.0 * tb.src_nnz[tk.src0 + i] * da * db;
+            by += eb * da * tb.srcs[tk.src0 + i].nw_in * db;
+          }
+          by += eb * da * tk.nw_out * db;
+        }
+        for (const auto &lv : tb.dense)
+          for (const EnvGD &d : lv) {
+            const double da = idim(bi, x, d.sa), db = idim(ki, x + 1, d.s);
+            fl += 2.0 * d.nr * d.nc * db * da;
+            by += eb * ((double)d.nc * db * da + 2.0 * d.nr * db * da);
+          }
+        for (const EnvG2 &d : tb.g2) {
+          const double m = idim(bi, x + 1, d.sbn), n = (double)d.nw * idim(ki, x + 1, d.s);
+          for (int g = 0; g < d.nseg; ++g) {
+            const double k = idim(bi, x, d.sa[g]);
+            fl += 2.0 * m * n * k;
+            by += eb * (k * m + k * n);
+          }
+          by += eb * m * n;
+        }
+      }
+    }
+    res.flops = fl;
+    res.bytes = by;
+  });
+  struct JoinGuard {
+    std::thread &t;
+    ~JoinGuard() {
+      if (t.joinable()) t.join();
+    }
+  } join_guard{work_thread};
   // ---- device tables
   std::vector<int> rowptr;
   std::vector<int> col;
@@ -1063,14 +1086,16 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   const int *d_rowptr = c.upload(rowptr);
   const int *d_col = c.upload(col);
   const CsrGroup *d_groups = c.upload(groups);
+  const int2 *d_itab = c.upload(itab);
+  const int *d_iD = c.upload(iD);
   struct DevSite {
-    std::vector<GemmDesc *> dense;
-    GemmDesc *g1, *g2;
+    std::vector<EnvGD *> dense;
+    EnvG1 *g1;
+    EnvG2 *g2;
     MixTask *tasks;
     int *chunk0;
     MixSrc *srcs;
-    int64_t *fin_offY, *fin_offBra;
-    int *fin_da;
+    EnvFinal *fin;
   };
   std::vector<DevSite> ds(N);
   int64_t Lmax = 1, Xmax = 1, Ymax = 1;
@@ -1083,9 +1108,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     ch.push_back(tabs[x].nchunk);
     ds[x].chunk0 = c.upload(ch);
     ds[x].srcs = c.upload(tabs[x].srcs);
-    ds[x].fin_offY = c.upload(tabs[x].fin_offY);
-    ds[x].fin_offBra = c.upload(tabs[x].fin_offBra);
-    ds[x].fin_da = c.upload(tabs[x].fin_da);
+    ds[x].fin = c.upload(tabs[x].fin);
     for (auto &lv : tabs[x].dense) ds[x].dense.push_back(c.upload(lv));
     Xmax = std::max(Xmax, tabs[x].Xsize);
     Ymax = std::max(Ymax, tabs[x].Ysize);
@@ -1098,8 +1121,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   int batch = std::max(1, std::min(npair, (int)(budget / std::max(1.0, per_pair))));
   res.H.assign(npair, 0.0);
   res.S.assign(npair, 0.0);
-  res.flops = flops_pp * npair;
-  res.bytes = bytes_pp * npair;
   hipEvent_t e0 = c.ctx->ev[0], e1 = c.ctx->ev[1];
   for (int p0 = 0; p0 < npair; p0 += batch) {
     const int nb_ = std::min(batch, npair - p0);
@@ -1107,35 +1128,35 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     T *bufL0 = c.dev<T>((size_t)Lmax * nb_), *bufL1 = c.dev<T>((size_t)Lmax * nb_);
     T *bufX = c.dev<T>((size_t)Xmax * nb_), *bufY = c.dev<T>((size_t)Ymax * nb_);
     std::vector<T *> L0(nb_), L1(nb_), X(nb_), Y(nb_);
-    std::vector<int> basis(nb_);
+    std::vector<int> basis(nb_), bra_item(nb_), ket_item(nb_);
     for (int q = 0; q < nb_; ++q) {
       L0[q] = bufL0 + (size_t)q * Lmax;
       L1[q] = bufL1 + (size_t)q * Lmax;
       X[q] = bufX + (size_t)q * Xmax;
       Y[q] = bufY + (size_t)q * Ymax;
-      basis[q] = pairs[p0 + q].first;
+      const int i = pairs[p0 + q].first;
+      basis[q] = i;
+      bra_item[q] = i;
+      ket_item[q] = ket_of_pair[p0 + q] < 0 ? i : M + ket_of_pair[p0 + q];
     }
     T **dL0 = c.upload(L0), **dL1 = c.upload(L1), **dX = c.upload(X), **dY = c.upload(Y);
     const int *dbasis = c.upload(basis);
+    EnvGeom geom{d_itab, d_iD, c.upload(bra_item), c.upload(ket_item), nbond, nslot};
     std::vector<const T *> vptr(nb_);
     for (int q = 0; q < nb_; ++q) vptr[q] = dvalsT + (size_t)basis[q] * nnz_total;
     const T *const *dvptr = c.upload(vptr);
-    std::vector<std::vector<const T *>> braT(N, std::vector<const T *>(nb_)), ketT(N, std::vector<const T *>(nb_));
-    std::vector<const double *> bra64(nb_);
-    for (int q = 0; q < nb_; ++q) {
-      const int i = pairs[p0 + q].first;
-      const int kitem = ket_of_pair[p0 + q] < 0 ? i : M + ket_of_pair[p0 + q];
-      for (int x = 0; x < N; ++x) {
-        braT[x][q] = padT + (size_t)i * per_item + psite_off[x];
-        ketT[x][q] = padT + (size_t)kitem * per_item + psite_off[x];
-      }
-      bra64[q] = pad64 + (size_t)i * per_item + psite_off[N - 1];
-    }
     std::vector<const T *const *> dbra(N), dket(N);
     for (int x = 0; x < N; ++x) {
-      dbra[x] = c.upload(braT[x]);
-      dket[x] = c.upload(ketT[x]);
+      std::vector<const T *> bp(nb_), kp(nb_);
+      for (int q = 0; q < nb_; ++q) {
+        bp[q] = siteT[(size_t)bra_item[q] * N + x];
+        kp[q] = siteT[(size_t)ket_item[q] * N + x];
+      }
+      dbra[x] = c.upload(bp);
+      dket[x] = c.upload(kp);
     }
+    std::vector<const double *> bra64(nb_);
+    for (int q = 0; q < nb_; ++q) bra64[q] = site64[(size_t)bra_item[q] * N + N - 1];
     const double *const *dbra64 = c.upload(bra64);
     double *dout = c.dev<double>((size_t)nb_ * 2);
     TNQE_HIP(hipEventRecord(e0, st));
@@ -1143,9 +1164,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     T **Lc = dL0, **Ln = dL1;
     for (int x = 0; x < N; ++x) {
       const SiteTabs &tb = tabs[x];
-      PairPtrs p1{reinterpret_cast<const void *const *>(Lc), reinterpret_cast<const void *const *>(dket[x]),
-                  reinterpret_cast<void *const *>(dX)};
-      launch_bgemm<T>(ds[x].g1, (int)tb.g1.size(), tb.t1, tb.tm1, tb.tn1, p1, nb_, st);
+      launch_env_g1<T>(ds[x].g1, (int)tb.g1.size(), tb.t1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, nb_, st);
       MixArgs ma{};
       ma.tasks = ds[x].tasks;
       ma.task_chunk0 = ds[x].chunk0;
@@ -1159,20 +1178,15 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       ma.basis_stride = nnz_total;
       ma.site_off = 0;
       ma.basis = dbasis;
-      launch_mix<T>(ma, dX, dY, nb_, st);
-      for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
-        PairPtrs pd{reinterpret_cast<const void *const *>(dvptr), reinterpret_cast<const void *const *>(dX),
-                    reinterpret_cast<void *const *>(dY)};
-        launch_bgemm<T>(ds[x].dense[lv], (int)tb.dense[lv].size(), tb.td[lv], tb.tmd[lv], tb.tnd[lv], pd, nb_, st);
-      }
+      launch_mix<T>(ma, geom, dX, dY, nb_, st);
+      for (size_t lv = 0; lv < tb.dense.size(); ++lv)
+        launch_env_gd<T>(ds[x].dense[lv], (int)tb.dense[lv].size(), tb.td[lv], tb.tmd[lv], tb.tnd[lv], geom, dvptr,
+                         dX, dY, nb_, st);
       if (x < N - 1) {
-        PairPtrs p2{reinterpret_cast<const void *const *>(dbra[x]), reinterpret_cast<const void *const *>(dY),
-                    reinterpret_cast<void *const *>(Ln)};
-        launch_bgemm<T>(ds[x].g2, (int)tb.g2.size(), tb.t2, tb.tm2, tb.tn2, p2, nb_, st);
+        launch_env_g2<T>(ds[x].g2, (int)tb.g2.size(), tb.t2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, nb_, st);
         std::swap(Lc, Ln);
       } else {
-        launch_env_final<T>(dbra64, dY, ds[x].fin_offY, ds[x].fin_da, ds[x].fin_offBra, 2,
-                            (int)tb.fin_offY.size(), dout, nb_, st);
+        launch_env_final<T>(geom, x, dbra64, dY, ds[x].fin, (int)tb.fin.size(), 2, dout, nb_, st);
       }
       c.check_launch();
     }

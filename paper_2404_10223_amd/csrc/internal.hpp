@@ -96,37 +96,58 @@ void launch_copy(double *const *dst, double *const *src, const int64_t *count, i
 void launch_site_sign(double *const *site, const int *rows, int n, int cols, hipStream_t st);
 
 // -------------------------------------------------------------- environment sweep
-// C[M x N] (+)= sum_seg op(A_seg)[M x K_seg] * B_seg[K_seg x N]; pointers are
-// offsets into per-pair bases (A, B, C bases are pair-indexed arrays).
-struct GemmSeg {
-  int K;
-  int lda, ldb;
-  int transA;          // 0: A[m*lda + k]; 1: A[k*lda + m]
-  int64_t offA, offB;
+// Sector tables of the items (bra MPS and rotated kets) and the bra/ket item
+// of every pair in a launch.
+struct EnvGeom {
+  const int2 *tab;     // [item][bond][slot]: (offset, dim) of the sector in the bond
+  const int *D;        // [item][bond]: bond dimension
+  const int *bra;      // [pair] bra item
+  const int *ket;      // [pair] ket item
+  int nbond, nslot;
+  __host__ __device__ int2 sec(int item, int b, int s) const {
+    return s < 0 ? make_int2(0, 0) : tab[((int64_t)item * nbond + b) * nslot + s];
+  }
+  __host__ __device__ int dim(int item, int b) const { return D[item * nbond + b]; }
 };
-struct GemmDesc {
-  int M, N, ldc, nseg;
-  int64_t offC;
-  int tile0;           // first tile index of this problem
-  int tilesN;          // tiles along N
-  int tilesM;          // tiles along M
-  int nbatch;          // independent problems at strides sA, sB, sC (>= 1)
-  int64_t sA, sB, sC;
-  double alpha;        // C = alpha * sum + beta * C, beta in {0, 1}
-  int beta;
-  GemmSeg seg[4];
+
+// X[(c, s, k)] = L[(c, s)] x ket site x block (s, k, sk); bra sector sbra = s + shift(c)
+struct EnvG1 {
+  int tile0, tilesM, tilesN;
+  int x, nw, sbra, s, k, sk;
+  int64_t offL, offX;
 };
-struct PairPtrs {      // per-pair base pointers for one GEMM launch
-  const void *const *A;
-  const void *const *B;
-  void *const *C;
+// L_{x+1}[(c, s)] = sum_q bra site x block (sa[q], kp[q], sbn)^T Y[offY[q]]
+struct EnvG2 {
+  int tile0, tilesM, tilesN;
+  int x, nw, sbn, s, nseg;
+  int sa[4], kp[4];
+  int64_t offY[4], offL;
+};
+// dense coupling: Y[a][r0..r0+nr][b] += f W[nr][nc] X[a][c0..c0+nc][b], one
+// batch per bra row a of the block (bra sector sa at bond x, ket sector s at x+1)
+struct EnvGD {
+  int tile0, tilesM, tilesN;
+  int x, sa, s, nr, nc, r0, c0, nw_in, nw_out;
+  int64_t offY, offX, valoff;
+  double f;
+};
+// one (bra sector, local state) term of the final element
+struct EnvFinal {
+  int sa, kp;
+  int64_t offY;
 };
 
 template <typename T>
-void launch_bgemm(const GemmDesc *d, int ndesc, int ntiles, int tileM, int tileN, PairPtrs pp,
-                  int npair, hipStream_t st);
+void launch_env_g1(const EnvG1 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *L, const T *const *ket, T *const *X, int npair, hipStream_t st);
+template <typename T>
+void launch_env_g2(const EnvG2 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *bra, const T *const *Y, T *const *Ln, int npair, hipStream_t st);
+template <typename T>
+void launch_env_gd(const EnvGD *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *vals, const T *const *X, T *const *Y, int npair, hipStream_t st);
 
-// channel mix: Y[c', s_b, k'] = sum over sources of coef * X[c, s, k]
+// channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k]
 struct MixSrc {
   int64_t offX;        // X block [da][nw_in][db]
   int nw_in;
@@ -134,8 +155,8 @@ struct MixSrc {
   double factor;       // local-operator matrix element
 };
 struct MixTask {
-  int64_t offY;        // Y block [da][nw_out][db]
-  int da, nw_out, db;
+  int64_t offY;        // Y block [da][nw_out][db], da = dim_bra(x, sa), db = dim_ket(x + 1, s)
+  int x, sa, s, nw_out;
   int src0, nsrc;      // range in the MixSrc array
 };
 struct CsrGroup {
@@ -156,21 +177,18 @@ struct MixArgs {
   const int *basis;         // [pair]
 };
 template <typename T>
-void launch_mix(const MixArgs &a, const T *const *X, T *const *Y, int npair, hipStream_t st);
+void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, int npair, hipStream_t st);
 
 template <typename T>
 void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st);
 
-// final element: out[pair][w] = sum_{a', k'} bra[a', k', 0] * Y[k'][a'][w][0], compensated
+// final element at the last site x: out[pair][w] = sum_{a', k'} bra[a', k', 0] Y[k'][a'][w][0], compensated
 template <typename T>
-void launch_env_final(const double *const *bra, const T *const *Y, const int64_t *offY,
-                      const int *da, const int64_t *offBra, int nw, int nk, double *out,
-                      int npair, hipStream_t st);
+void launch_env_final(const EnvGeom &g, int x, const double *const *bra, const T *const *Y, const EnvFinal *fin,
+                      int nk, int nw, double *out, int npair, hipStream_t st);
 
-template <typename T>
-void launch_repack(const double *const *src, T *const *dst, const int2 *srcl, const int2 *srcr,
-                   const int *srcDr, int nslot, const int2 *pmapl, const int2 *pmapr, int Dpl, int Dpr,
-                   int nitem, hipStream_t st);
+// FP32 copies of FP64 arrays
+void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st);
 
 // -------------------------------------------------------------- eigensolve
 // For each subspace s: H, S at offs[s] ([M_s][M_s] row-major); writes

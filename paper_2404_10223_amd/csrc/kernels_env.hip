@@ -1,11 +1,15 @@
-// Environment sweep on gfx950: re-layout of site tensors into a common
-// sector-padded layout, grouped block GEMMs (bra^T x Y and L x ket), the
-// channel mix with the MPO, and the compensated final element.
+// Environment sweep on gfx950: block GEMMs (L x ket and bra^T x Y), the
+// channel mix with the MPO (sparse rows and dense coupling GEMMs), and the
+// compensated final element.
 //
-// Environment layout at bond b, per MPO channel class c (shift d = bra sector -
-// ket sector) and ket sector s: a dense block [dim_bra(s + d)][n_channels(c)]
-// [dim_ket(s)] ("bra-major"), so both contractions of a site are plain GEMMs
-// whose long dimension runs over (bra index, channel) or (channel, ket index).
+// Every pair keeps its own exact sector dimensions.  A block of the
+// environment at bond b, for MPO channel class c (shift d = bra sector - ket
+// sector) and ket sector s, is dense [dim_bra(s + d)][n_channels(c)]
+// [dim_ket(s)] with the pair's dimensions; its slot in the pair's buffer is
+// sized for the largest dimensions over all pairs, so one descriptor list
+// (and one offset per block) serves every pair.  A workgroup resolves its
+// pair's extents from the item tables and leaves at once when its tile lies
+// outside them.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -14,58 +18,52 @@ namespace tnqe {
 
 namespace {
 
-// ------------------------------------------------------------------ GEMM
-// One workgroup computes a TM x TN tile of C for one problem and one pair.
-// Each of the 256 threads owns an RM x RN micro-tile; K is staged through LDS
-// in chunks of KC.
-template <typename T, int TM, int TN, int RM, int RN>
-__global__ void __launch_bounds__(256) k_bgemm(const GemmDesc *descs, int ndesc, PairPtrs pp) {
+template <typename T>
+struct Seg {
+  const T *A;
+  const T *B;
+  int K, lda, ldb, transA;   // A[m*lda + k] (transA 0) or A[k*lda + m]; B[k*ldb + n]
+};
+
+// C tile (m0, n0) of sum_seg op(A) B: 256 threads, an RM x RN micro-tile
+// each, K staged through LDS in chunks of KC.  C = alpha * sum (+ C if beta).
+template <typename T, int TM, int TN, int RM, int RN, int NSEG>
+__device__ void tile_gemm(int M, int N, int m0, int n0, const Seg<T> (&sg)[NSEG], int nseg, T *C, int ldc,
+                          T alpha, int beta) {
   constexpr int KC = 16;
-  constexpr int TX = TN / RN;   // threads along N
+  constexpr int TX = TN / RN;
   static_assert((TM / RM) * (TN / RN) == 256, "tile");
   __shared__ T sA[KC][TM + 1];
   __shared__ T sB[KC][TN];
-  const int pair = blockIdx.y;
-  // locate the problem owning this tile
-  int lo = 0, hi = ndesc - 1;
-  const int tile = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc &d = descs[lo];
-  const int per = d.tilesM * d.tilesN;
-  const int t0 = tile - d.tile0;
-  const int bt = t0 / per, t = t0 - bt * per;
-  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
-  const T *Abase = static_cast<const T *>(pp.A[pair]) + bt * d.sA;
-  const T *Bbase = static_cast<const T *>(pp.B[pair]) + bt * d.sB;
-  T *Cb = static_cast<T *>(pp.C[pair]) + d.offC + bt * d.sC;
-  const T alpha = (T)d.alpha;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   T acc[RM][RN];
 #pragma unroll
   for (int i = 0; i < RM; ++i)
 #pragma unroll
     for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
-  for (int sgi = 0; sgi < d.nseg; ++sgi) {
-    const GemmSeg sg = d.seg[sgi];
-    const T *A = Abase + sg.offA;
-    const T *B = Bbase + sg.offB;
-    for (int k0 = 0; k0 < sg.K; k0 += KC) {
+#pragma unroll
+  for (int q = 0; q < NSEG; ++q) {
+    if (q >= nseg) break;
+    const Seg<T> s = sg[q];
+    for (int k0 = 0; k0 < s.K; k0 += KC) {
       for (int e = threadIdx.x; e < KC * TM; e += 256) {
         int kk, mm;
-        if (sg.transA) { mm = e % TM; kk = e / TM; } else { kk = e % KC; mm = e / KC; }
+        if (s.transA) {
+          mm = e % TM;
+          kk = e / TM;
+        } else {
+          kk = e % KC;
+          mm = e / KC;
+        }
         const int gm = m0 + mm, gk = k0 + kk;
         T v = T(0);
-        if (gm < d.M && gk < sg.K)
-          v = sg.transA ? A[(int64_t)gk * sg.lda + gm] : A[(int64_t)gm * sg.lda + gk];
+        if (gm < M && gk < s.K) v = s.transA ? s.A[(int64_t)gk * s.lda + gm] : s.A[(int64_t)gm * s.lda + gk];
         sA[kk][mm] = v;
       }
       for (int e = threadIdx.x; e < KC * TN; e += 256) {
         const int kk = e / TN, nn = e % TN;
         const int gn = n0 + nn, gk = k0 + kk;
-        sB[kk][nn] = (gn < d.N && gk < sg.K) ? B[(int64_t)gk * sg.ldb + gn] : T(0);
+        sB[kk][nn] = (gn < N && gk < s.K) ? s.B[(int64_t)gk * s.ldb + gn] : T(0);
       }
       __syncthreads();
 #pragma unroll
@@ -86,21 +84,108 @@ __global__ void __launch_bounds__(256) k_bgemm(const GemmDesc *descs, int ndesc,
 #pragma unroll
   for (int i = 0; i < RM; ++i) {
     const int gm = m0 + ty * RM + i;
-    if (gm >= d.M) continue;
+    if (gm >= M) continue;
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
       const int gn = n0 + tx + j * TX;
-      if (gn < d.N) {
-        T *c = Cb + (int64_t)gm * d.ldc + gn;
-        *c = d.beta ? *c + alpha * acc[i][j] : alpha * acc[i][j];
+      if (gn < N) {
+        T *c = C + (int64_t)gm * ldc + gn;
+        *c = beta ? *c + alpha * acc[i][j] : alpha * acc[i][j];
       }
     }
   }
 }
 
+// the problem owning a tile: last descriptor with tile0 <= tile
+template <typename D>
+__device__ inline int find_desc(const D *descs, int ndesc, int tile) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// X[(c, s, k)] = L[(c, s)] A_ket[s, k, s + q(k)]
+template <typename T, int TM, int TN, int RM, int RN>
+__global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, int ndesc, EnvGeom g, const T *const *L,
+                                                const T *const *ket, T *const *X) {
+  const int pair = blockIdx.y;
+  const EnvG1 d = descs[find_desc(descs, ndesc, blockIdx.x)];
+  const int bi = g.bra[pair], ki = g.ket[pair];
+  const int dbra = g.sec(bi, d.x, d.sbra).y;
+  const int2 sk = g.sec(ki, d.x, d.s), sn = g.sec(ki, d.x + 1, d.sk);
+  const int M = dbra * d.nw, N = sn.y;
+  const int t = blockIdx.x - d.tile0;
+  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
+  if (m0 >= M || n0 >= N) return;
+  const int Dr = g.dim(ki, d.x + 1);
+  Seg<T> sg[1];
+  sg[0].A = L[pair] + d.offL;
+  sg[0].lda = sk.y;
+  sg[0].transA = 0;
+  sg[0].B = ket[pair] + ((int64_t)sk.x * 4 + d.k) * Dr + sn.x;
+  sg[0].ldb = 4 * Dr;
+  sg[0].K = sk.y;
+  tile_gemm<T, TM, TN, RM, RN, 1>(M, N, m0, n0, sg, 1, X[pair] + d.offX, N, T(1), 0);
+}
+
+// L'[(c, s)] = sum_k' A_bra[s_a(k'), k', s + d]^T Y[(c, s, k')]
+template <typename T, int TM, int TN, int RM, int RN>
+__global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, int ndesc, EnvGeom g, const T *const *bra,
+                                                const T *const *Y, T *const *Ln) {
+  const int pair = blockIdx.y;
+  const EnvG2 d = descs[find_desc(descs, ndesc, blockIdx.x)];
+  const int bi = g.bra[pair], ki = g.ket[pair];
+  const int2 sbn = g.sec(bi, d.x + 1, d.sbn);
+  const int M = sbn.y, N = d.nw * g.sec(ki, d.x + 1, d.s).y;
+  const int t = blockIdx.x - d.tile0;
+  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
+  if (m0 >= M || n0 >= N) return;
+  const int Dr = g.dim(bi, d.x + 1);
+  Seg<T> sg[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int2 sa = g.sec(bi, d.x, q < d.nseg ? d.sa[q] : -1);
+    sg[q].A = bra[pair] + ((int64_t)sa.x * 4 + d.kp[q]) * Dr + sbn.x;
+    sg[q].lda = 4 * Dr;
+    sg[q].transA = 1;
+    sg[q].B = Y[pair] + d.offY[q];
+    sg[q].ldb = N;
+    sg[q].K = q < d.nseg ? sa.y : 0;
+  }
+  tile_gemm<T, TM, TN, RM, RN, 4>(M, N, m0, n0, sg, d.nseg, Ln[pair] + d.offL, N, T(1), 0);
+}
+
+// dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b]
+// for every bra row a of the block (one batch each)
+template <typename T, int TM, int TN, int RM, int RN>
+__global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, EnvGeom g, const T *const *vals,
+                                                const T *const *X, T *const *Y) {
+  const int pair = blockIdx.y;
+  const EnvGD d = descs[find_desc(descs, ndesc, blockIdx.x)];
+  const int bi = g.bra[pair], ki = g.ket[pair];
+  const int da = g.sec(bi, d.x, d.sa).y, db = g.sec(ki, d.x + 1, d.s).y;
+  const int per = d.tilesM * d.tilesN;
+  const int t0 = blockIdx.x - d.tile0;
+  const int a = t0 / per, t = t0 - a * per;
+  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
+  if (a >= da || m0 >= d.nr || n0 >= db) return;
+  Seg<T> sg[1];
+  sg[0].A = vals[pair] + d.valoff;
+  sg[0].lda = d.nc;
+  sg[0].transA = 0;
+  sg[0].B = X[pair] + d.offX + ((int64_t)a * d.nw_in + d.c0) * db;
+  sg[0].ldb = db;
+  sg[0].K = d.nc;
+  tile_gemm<T, TM, TN, RM, RN, 1>(d.nr, db, m0, n0, sg, 1, Y[pair] + d.offY + ((int64_t)a * d.nw_out + d.r0) * db,
+                                  db, (T)d.f, 1);
+}
+
 // ------------------------------------------------------------------ channel mix
 template <typename T>
-__global__ void __launch_bounds__(256) k_mix(MixArgs a, const T *const *X, T *const *Y) {
+__global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
   const int pair = blockIdx.y;
   int lo = 0, hi = a.ntask - 1;
   const int chunk = blockIdx.x;
@@ -109,22 +194,23 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, const T *const *X, T *co
     if (a.task_chunk0[mid] <= chunk) lo = mid; else hi = mid - 1;
   }
   const MixTask tk = a.tasks[lo];
+  const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
   const int64_t e = (int64_t)(chunk - a.task_chunk0[lo]) * 256 + threadIdx.x;
-  const int64_t total = (int64_t)tk.da * tk.nw_out * tk.db;
+  const int64_t total = (int64_t)da * tk.nw_out * db;
   if (e >= total) return;
-  const int b = e % tk.db;
-  const int w = (e / tk.db) % tk.nw_out;
-  const int ap = e / ((int64_t)tk.db * tk.nw_out);
+  const int b = e % db;
+  const int w = (e / db) % tk.nw_out;
+  const int ap = e / ((int64_t)db * tk.nw_out);
   const double *vals = a.vals + a.basis[pair] * a.basis_stride + a.site_off;
   const T *Xp = X[pair];
   double acc = 0.0;
   for (int si = 0; si < tk.nsrc; ++si) {
     const MixSrc s = a.src[tk.src0 + si];
-    const CsrGroup g = a.groups[s.group];
-    const int r0 = a.rowptr[g.rowptr + w], r1 = a.rowptr[g.rowptr + w + 1];
-    const T *xb = Xp + s.offX + ((int64_t)ap * s.nw_in) * tk.db + b;
+    const CsrGroup cg = a.groups[s.group];
+    const int r0 = a.rowptr[cg.rowptr + w], r1 = a.rowptr[cg.rowptr + w + 1];
+    const T *xb = Xp + s.offX + ((int64_t)ap * s.nw_in) * db + b;
     double part = 0.0;
-    for (int z = r0; z < r1; ++z) part += vals[g.val + z] * (double)xb[(int64_t)a.col[g.col + z] * tk.db];
+    for (int z = r0; z < r1; ++z) part += vals[cg.val + z] * (double)xb[(int64_t)a.col[cg.col + z] * db];
     acc += s.factor * part;
   }
   Y[pair][tk.offY + e] = (T)acc;
@@ -144,21 +230,22 @@ __device__ inline void two_sum(double a, double b, double &s, double &e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-// last site: out[pair * nw + w] = sum_{k', a'} bra[a', k', 0] Y_k'[a'][w][0]
+// last site: out[pair * nw + w] = sum_{k', a'} bra[a', k', 0] Y_k'[a'][w][0],
+// accumulated with TwoSum and a compensated tree
 template <typename T>
-__global__ void __launch_bounds__(256) k_env_final(const double *const *bra, const T *const *Y,
-                                                   const int64_t *offY, const int *da,
-                                                   const int64_t *offBra, int nw, int nk,
-                                                   double *out) {
+__global__ void __launch_bounds__(256) k_env_final(EnvGeom g, int x, const double *const *bra, const T *const *Y,
+                                                   const EnvFinal *fin, int nk, int nw, double *out) {
   const int pair = blockIdx.x;
+  const int bi = g.bra[pair];
   __shared__ double ss[256], se[256];
   for (int w = 0; w < nw; ++w) {
     double s = 0.0, c = 0.0;
     for (int k = 0; k < nk; ++k) {
-      const T *y = Y[pair] + offY[k];
-      const double *bp = bra[pair] + offBra[k];
-      for (int i = threadIdx.x; i < da[k]; i += 256) {
-        // bra index i of the sector, local state k: bra[(off + i) * 4 + k]
+      const int2 sa = g.sec(bi, x, fin[k].sa);
+      const T *y = Y[pair] + fin[k].offY;
+      // bra index i of the sector, local state k': bra[(off + i) * 4 + k'] (right bond 1)
+      const double *bp = bra[pair] + (int64_t)sa.x * 4 + fin[k].kp;
+      for (int i = threadIdx.x; i < sa.y; i += 256) {
         const double p = bp[(int64_t)i * 4] * (double)y[(int64_t)i * nw + w];
         double t, e;
         two_sum(s, p, t, e);
@@ -183,52 +270,55 @@ __global__ void __launch_bounds__(256) k_env_final(const double *const *bra, con
   }
 }
 
-// padded re-layout of one site for many MPS: dst[lp][k][rp] from src[l][k][r]
-template <typename T>
-__global__ void k_repack(const double *const *src, T *const *dst, const int2 *srcl, const int2 *srcr,
-                         const int *srcDr, int nslot, const int2 *pmapl, const int2 *pmapr, int Dpl,
-                         int Dpr) {
-  const int it = blockIdx.y;
-  const int64_t total = (int64_t)Dpl * 4 * Dpr;
-  const double *S = src[it];
-  T *D = dst[it];
-  const int2 *tl = srcl + (int64_t)it * nslot, *tr = srcr + (int64_t)it * nslot;
-  const int Dr = srcDr[it];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int rp = e % Dpr;
-    const int k = (e / Dpr) % 4;
-    const int lp = e / (4 * (int64_t)Dpr);
-    const int2 ml = pmapl[lp], mr = pmapr[rp];     // (slot, index within sector)
-    const int2 sl = tl[ml.x], sr = tr[mr.x];       // (offset, dim) in the source
-    T v = T(0);
-    if (ml.y < sl.y && mr.y < sr.y) v = (T)S[((int64_t)(sl.x + ml.y) * 4 + k) * Dr + sr.x + mr.y];
-    D[e] = v;
-  }
+// dst[i][e] = (float) src[i][e] for e < count[i]
+__global__ void k_cast(const double *const *src, float *const *dst, const int64_t *count) {
+  const int i = blockIdx.y;
+  const int64_t n = count[i];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[i][e] = (float)src[i][e];
 }
 
 }  // namespace
 
+#define TNQE_TILE_SWITCH(KERNEL, T, tileM, tileN, grid, ...)                                   \
+  do {                                                                                         \
+    if (tileM == 256 && tileN == 16)                                                           \
+      hipLaunchKernelGGL((KERNEL<T, 256, 16, 16, 1>), grid, dim3(256), 0, __VA_ARGS__);        \
+    else if (tileM == 16 && tileN == 256)                                                      \
+      hipLaunchKernelGGL((KERNEL<T, 16, 256, 1, 16>), grid, dim3(256), 0, __VA_ARGS__);        \
+    else if (tileM == 128 && tileN == 32)                                                      \
+      hipLaunchKernelGGL((KERNEL<T, 128, 32, 8, 2>), grid, dim3(256), 0, __VA_ARGS__);         \
+    else if (tileM == 32 && tileN == 128)                                                      \
+      hipLaunchKernelGGL((KERNEL<T, 32, 128, 2, 8>), grid, dim3(256), 0, __VA_ARGS__);         \
+    else                                                                                       \
+      hipLaunchKernelGGL((KERNEL<T, 64, 64, 4, 4>), grid, dim3(256), 0, __VA_ARGS__);          \
+  } while (0)
+
 template <typename T>
-void launch_bgemm(const GemmDesc *d, int ndesc, int ntiles, int tileM, int tileN, PairPtrs pp,
-                  int npair, hipStream_t st) {
+void launch_env_g1(const EnvG1 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *L, const T *const *ket, T *const *X, int npair, hipStream_t st) {
   if (ndesc == 0 || ntiles == 0 || npair == 0) return;
-  dim3 grid(ntiles, npair);
-  if (tileM == 256 && tileN == 16)
-    hipLaunchKernelGGL((k_bgemm<T, 256, 16, 16, 1>), grid, dim3(256), 0, st, d, ndesc, pp);
-  else if (tileM == 16 && tileN == 256)
-    hipLaunchKernelGGL((k_bgemm<T, 16, 256, 1, 16>), grid, dim3(256), 0, st, d, ndesc, pp);
-  else if (tileM == 128 && tileN == 32)
-    hipLaunchKernelGGL((k_bgemm<T, 128, 32, 8, 2>), grid, dim3(256), 0, st, d, ndesc, pp);
-  else if (tileM == 32 && tileN == 128)
-    hipLaunchKernelGGL((k_bgemm<T, 32, 128, 2, 8>), grid, dim3(256), 0, st, d, ndesc, pp);
-  else
-    hipLaunchKernelGGL((k_bgemm<T, 64, 64, 4, 4>), grid, dim3(256), 0, st, d, ndesc, pp);
+  TNQE_TILE_SWITCH(k_env_g1, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, L, ket, X);
 }
 
 template <typename T>
-void launch_mix(const MixArgs &a, const T *const *X, T *const *Y, int npair, hipStream_t st) {
+void launch_env_g2(const EnvG2 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *bra, const T *const *Y, T *const *Ln, int npair, hipStream_t st) {
+  if (ndesc == 0 || ntiles == 0 || npair == 0) return;
+  TNQE_TILE_SWITCH(k_env_g2, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, bra, Y, Ln);
+}
+
+template <typename T>
+void launch_env_gd(const EnvGD *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
+                   const T *const *vals, const T *const *X, T *const *Y, int npair, hipStream_t st) {
+  if (ndesc == 0 || ntiles == 0 || npair == 0) return;
+  TNQE_TILE_SWITCH(k_env_gd, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, vals, X, Y);
+}
+
+template <typename T>
+void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, int npair, hipStream_t st) {
   if (a.ntask == 0 || a.nchunk == 0 || npair == 0) return;
-  hipLaunchKernelGGL(k_mix<T>, dim3(a.nchunk, npair), dim3(256), 0, st, a, X, Y);
+  hipLaunchKernelGGL(k_mix<T>, dim3(a.nchunk, npair), dim3(256), 0, st, a, g, X, Y);
 }
 
 template <typename T>
@@ -238,39 +328,30 @@ void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st) {
 }
 
 template <typename T>
-void launch_env_final(const double *const *bra, const T *const *Y, const int64_t *offY,
-                      const int *da, const int64_t *offBra, int nw, int nk, double *out,
-                      int npair, hipStream_t st) {
+void launch_env_final(const EnvGeom &g, int x, const double *const *bra, const T *const *Y, const EnvFinal *fin,
+                      int nk, int nw, double *out, int npair, hipStream_t st) {
   if (npair == 0) return;
-  hipLaunchKernelGGL(k_env_final<T>, dim3(npair), dim3(256), 0, st, bra, Y, offY, da, offBra, nw, nk, out);
+  hipLaunchKernelGGL(k_env_final<T>, dim3(npair), dim3(256), 0, st, g, x, bra, Y, fin, nk, nw, out);
 }
 
-template <typename T>
-void launch_repack(const double *const *src, T *const *dst, const int2 *srcl, const int2 *srcr,
-                   const int *srcDr, int nslot, const int2 *pmapl, const int2 *pmapr, int Dpl, int Dpr,
-                   int nitem, hipStream_t st) {
-  if (nitem == 0) return;
-  const int64_t total = (int64_t)Dpl * 4 * Dpr;
-  int bx = (int)((total + 255) / 256);
-  if (bx > 1024) bx = 1024;
-  if (bx < 1) bx = 1;
-  hipLaunchKernelGGL(k_repack<T>, dim3(bx, nitem), dim3(256), 0, st, src, dst, srcl, srcr, srcDr, nslot,
-                     pmapl, pmapr, Dpl, Dpr);
+void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_cast, dim3(64, n), dim3(256), 0, st, src, dst, count);
 }
 
-template void launch_bgemm<double>(const GemmDesc *, int, int, int, int, PairPtrs, int, hipStream_t);
-template void launch_bgemm<float>(const GemmDesc *, int, int, int, int, PairPtrs, int, hipStream_t);
-template void launch_mix<double>(const MixArgs &, const double *const *, double *const *, int, hipStream_t);
-template void launch_mix<float>(const MixArgs &, const float *const *, float *const *, int, hipStream_t);
-template void launch_env_init<double>(double *const *, int, int64_t, hipStream_t);
-template void launch_env_init<float>(float *const *, int, int64_t, hipStream_t);
-template void launch_env_final<double>(const double *const *, const double *const *, const int64_t *,
-                                       const int *, const int64_t *, int, int, double *, int, hipStream_t);
-template void launch_env_final<float>(const double *const *, const float *const *, const int64_t *,
-                                      const int *, const int64_t *, int, int, double *, int, hipStream_t);
-template void launch_repack<double>(const double *const *, double *const *, const int2 *, const int2 *,
-                                    const int *, int, const int2 *, const int2 *, int, int, int, hipStream_t);
-template void launch_repack<float>(const double *const *, float *const *, const int2 *, const int2 *,
-                                   const int *, int, const int2 *, const int2 *, int, int, int, hipStream_t);
+#define TNQE_ENV_INST(T)                                                                                     \
+  template void launch_env_g1<T>(const EnvG1 *, int, int, int, int, const EnvGeom &, const T *const *,      \
+                                 const T *const *, T *const *, int, hipStream_t);                           \
+  template void launch_env_g2<T>(const EnvG2 *, int, int, int, int, const EnvGeom &, const T *const *,      \
+                                 const T *const *, T *const *, int, hipStream_t);                           \
+  template void launch_env_gd<T>(const EnvGD *, int, int, int, int, const EnvGeom &, const T *const *,      \
+                                 const T *const *, T *const *, int, hipStream_t);                           \
+  template void launch_mix<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, int,          \
+                              hipStream_t);                                                                 \
+  template void launch_env_init<T>(T *const *, int, int64_t, hipStream_t);                                  \
+  template void launch_env_final<T>(const EnvGeom &, int, const double *const *, const T *const *,          \
+                                    const EnvFinal *, int, int, double *, int, hipStream_t);
+TNQE_ENV_INST(double)
+TNQE_ENV_INST(float)
 
 }  // namespace tnqe
