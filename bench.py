@@ -117,7 +117,10 @@ def main():
                                    "24 Cholesky vectors, FP64 path", "N": prob.N, "chi": prob.chi, "M": prob.M,
                        "pairs": n_pairs, "parallelism": "single GPU"},
             "E": E, "report": {k: rep[k] for k in ("t_host_ms", "t_gates_ms", "t_env_ms", "t_gep_ms",
-                                                   "max_discarded_weight_sum", "min_rel_gap", "max_bond")},
+                                                   "max_discarded_weight_sum", "min_rel_gap", "max_bond",
+                                                   "svd_kernel_ms", "svd_flops", "env_kernel_ms", "env_flops",
+                                                   "alg_bytes", "svd_kind_ms", "svd_kind_flops",
+                                                   "svd_kind_launches")},
             "mixed": mixed, "roofline": roof, "cpu_baseline": cpu}
     up.free()
     ctx.close()

@@ -430,25 +430,46 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     lds[key] = std::max(lds[key], jp.lds);
     work[i] = (int64_t)b.n * b.n * m;
   }
+  // heaviest launches first, spread over the side streams so that launches
+  // of few large blocks run beside launches of many small ones
+  std::vector<std::pair<double, std::pair<int, int>>> order;
   for (auto &kv : groups) {
     std::vector<int> &idx = kv.second;
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return work[x] > work[y]; });
-    const int *didx = c.upload(idx);
+    double w = 0.0;
+    for (int i : idx) w += (double)work[i];
+    order.push_back({-(double)work[idx[0]] * 1e3 - w, kv.first});
+  }
+  std::sort(order.begin(), order.end());
+  tnqe_ctx *ctx = c.ctx;
+  const int nstream = std::min<int>(tnqe_ctx::kAux, (int)order.size());
+  std::vector<const int *> didx(order.size());
+  for (size_t g = 0; g < order.size(); ++g) didx[g] = c.upload(groups[order[g].second]);
+  TNQE_HIP(hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int i = 0; i < nstream; ++i) TNQE_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+  for (size_t g = 0; g < order.size(); ++g) {
+    const auto key = order[g].second;
+    const std::vector<int> &idx = groups[key];
+    hipStream_t s = ctx->aux[g % nstream];
     const bool timed = timer && timer->npending < SvdTimer::kMaxPending;
     const int slot = timed ? timer->npending : 0;
     if (timed) {
       double f = 0.0;
       for (int i : idx) f += svd_flops(blks[i]);
       timer->pending_flops[slot] = f;
-      timer->pending_kind[slot] = kv.first.first;
-      TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot], c.ctx->stream));
+      timer->pending_kind[slot] = key.first;
+      TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot], s));
     }
-    launch_jacobi(dblk, didx, (int)idx.size(), kv.first.first, kv.first.second, (int)lds[kv.first], scratch,
-                  max_sweeps, dsweeps, c.ctx->stream);
+    launch_jacobi(dblk, didx[g], (int)idx.size(), key.first, key.second, (int)lds[key], scratch, max_sweeps,
+                  dsweeps, s);
     if (timed) {
-      TNQE_HIP(hipEventRecord(c.ctx->svd_ev[2 * slot + 1], c.ctx->stream));
+      TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot + 1], s));
       timer->npending++;
     }
+  }
+  for (int i = 0; i < nstream; ++i) {
+    TNQE_HIP(hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
+    TNQE_HIP(hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
   }
   c.check_launch();
   if (dbg) {
@@ -1591,6 +1612,14 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
       delete ctx;
       return TNQE_EHIP;
     }
+  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < tnqe_ctx::kAux && ok; ++i)
+    ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    tnqe_destroy(ctx);
+    return TNQE_EHIP;
+  }
   *out = ctx;
   return TNQE_OK;
 }
@@ -1603,6 +1632,12 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
     if (e) (void)hipEventDestroy(e);
   for (auto &e : ctx->svd_ev)
     if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < tnqe_ctx::kAux; ++i) {
+    if (ctx->aux[i]) (void)hipStreamSynchronize(ctx->aux[i]);
+    if (ctx->aux[i]) (void)hipStreamDestroy(ctx->aux[i]);
+    if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   delete ctx;
   return TNQE_OK;
 }

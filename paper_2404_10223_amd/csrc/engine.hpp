@@ -64,6 +64,11 @@ struct tnqe_ctx {
   std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
   hipEvent_t ev[8] = {};
   hipEvent_t svd_ev[64] = {};  // timing of the truncation SVD launches of one gate step
+  // side streams (default priority) that run independent SVD launches side by
+  // side; forked from and joined back into `stream` with events
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kAux] = {};
 };
 
 struct tnqe_problem {
