@@ -641,6 +641,30 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
       blks.push_back(b);
     }
   }
+  // two-site products per old middle sector (bond a+1 before the gate)
+  std::vector<Blk> th;
+  std::vector<int> thidx((size_t)ks.n * ks.nslot, -1);
+  for (int t = 0; t < ks.n; ++t) {
+    for (int s = 0; s < ks.nslot; ++s) {
+      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      if (ks.dim_q(a + 1, t, sa, sb) == 0) continue;
+      Blk b{};
+      b.pair = t;
+      b.sa = sa;
+      b.sb = sb;
+      b.rs[0] = b.cs[0] = 0;
+      for (int k = 0; k < 4; ++k) {
+        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
+        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
+      }
+      b.R = b.rs[4];
+      b.C = b.cs[4];
+      if (b.R == 0 || b.C == 0) continue;
+      b.offT = sc.take((int64_t)b.R * b.C);
+      thidx[(size_t)t * ks.nslot + s] = (int)th.size();
+      th.push_back(b);
+    }
+  }
   // singular values contiguous for one download
   int64_t s0 = sc.used, ns = 0;
   for (Blk &b : blks) {
@@ -651,7 +675,8 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   double *scratch = c.dev<double>(sc.used);
   double *dgates = c.upload(gates);
   Blk *dblk = c.upload(blks);
-  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), dgates, scratch, c.ctx->stream);
+  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), c.upload(th), (int)th.size(), c.upload(thidx), dgates,
+                  scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
   c.check_launch();
   std::vector<double> sv(ns);

@@ -67,8 +67,10 @@ struct KetTables {
   __host__ __device__ int dim(int bond, int pair) const { return bdim[bond * npair + pair]; }
 };
 
-void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const double *gates,
-                     double *scratch, hipStream_t st);
+// two-site products per old middle sector (th[0..nth)), then the gate into
+// the blocks of the new middle bond (thidx[pair * nslot + slot]: Theta block)
+void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const Blk *th, int nth,
+                     const int *thidx, const double *gates, double *scratch, hipStream_t st);
 // Jacobi SVD of the blocks idx[0..nblk) of blk: sorted singular values (offS)
 // and sorted rotated vectors (U = x / s in the columns case, B = x in the rows
 // case).  kind k < kJacobiGlobal selects the register-resident kernel with

@@ -21,39 +21,133 @@ __device__ inline int seg_of(const int *s, int x) {
   return k;
 }
 
-// T'[row, col] = sum_{k1,k2} G[(k1',k2'),(k1,k2)] sum_m A_a[l,k1,m] A_{a+1}[m,k2,r]
-__global__ void __launch_bounds__(kThreads) k_two_site(KetTables kt, int a, const Blk *blks,
-                                                       const double *gates, double *scratch) {
-  const Blk b = blks[blockIdx.x];
+// Two-site product per old middle sector ms = (sa, sb) of bond a+1:
+// Theta[(k1, l)][(k2, r)] = sum_m A_a[l, k1, m] A_{a+1}[m, k2, r], with l in
+// the left sector ms - q(k1) and r in the right sector ms + q(k2).  A tiled
+// GEMM (64 x 64 outputs per step, 4 x 4 per thread, K through LDS by 16).
+__global__ void __launch_bounds__(kThreads) k_theta(KetTables kt, int a, const Blk *th, double *scratch) {
+  constexpr int TT = 64, KC = 16;
+  const Blk b = th[blockIdx.x];
   const int pair = b.pair;
   const double *A = kt.site[pair * kt.N + a];
   const double *B = kt.site[pair * kt.N + a + 1];
   const int Dm = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
-  const double *G = gates + (int64_t)pair * 256;
-  double *T = scratch + b.offT;
-  __shared__ double sG[256];
-  for (int i = threadIdx.x; i < 256; i += kThreads) sG[i] = G[i];
+  const int2 mid = kt.sec(a + 1, pair, b.sa, b.sb);
+  __shared__ int s_lo[4], s_ro[4];
+  __shared__ double sA[KC][TT + 1];
+  __shared__ double sB[KC][TT];
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    s_lo[k] = kt.sec(a, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x;
+    s_ro[k] = kt.sec(a + 2, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x;
+  }
   __syncthreads();
+  double *Th = scratch + b.offT;
+  const int K = mid.y, R = b.R, C = b.C;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tilesC = (C + TT - 1) / TT;
+  for (int tile = 0; tile < ((R + TT - 1) / TT) * tilesC; ++tile) {
+    const int m0 = (tile / tilesC) * TT, n0 = (tile % tilesC) * TT;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
+        // A tile: row (k1, l), middle index along the fast direction
+        {
+          const int mm = e / KC, kk = e % KC;
+          const int row = m0 + mm, m = k0 + kk;
+          double v = 0.0;
+          if (row < R && m < K) {
+            const int k1 = seg_of(b.rs, row);
+            v = A[((int64_t)(s_lo[k1] + row - b.rs[k1]) * 4 + k1) * Dm + mid.x + m];
+          }
+          sA[kk][mm] = v;
+        }
+        // B tile: column (k2, r) along the fast direction
+        {
+          const int kk = e / TT, nn = e % TT;
+          const int col = n0 + nn, m = k0 + kk;
+          double v = 0.0;
+          if (col < C && m < K) {
+            const int k2 = seg_of(b.cs, col);
+            v = B[((int64_t)(mid.x + m) * 4 + k2) * Dr + s_ro[k2] + col - b.cs[k2]];
+          }
+          sB[kk][nn] = v;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = sA[kk][ty + 16 * u];
+          bv[u] = sB[kk][tx + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = m0 + ty + 16 * u;
+      if (row >= R) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = n0 + tx + 16 * v;
+        if (col < C) Th[(int64_t)row * C + col] = acc[u][v];
+      }
+    }
+  }
+}
+
+// T'[(k1', l)][(k2', r)] = sum_{k1,k2} G[(k1',k2'),(k1,k2)] Theta_ms[(k1, l)][(k2, r)]
+// with ms = s - q(k1') + q(k1) (the gate conserves both particle numbers, so
+// the row and column sectors of the two sides agree).  thidx[pair][slot] is
+// the Theta block of a middle sector (-1: none, the product is empty).
+__global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Blk *blks, const Blk *th,
+                                                          const int *thidx, const double *gates,
+                                                          double *scratch) {
+  const Blk b = blks[blockIdx.x];
+  const int pair = b.pair;
+  __shared__ double sG[256];
+  __shared__ int64_t s_off[16];
+  __shared__ int s_C[16], s_rs[16][5], s_cs[16][5];
+  for (int i = threadIdx.x; i < 256; i += kThreads) sG[i] = gates[(int64_t)pair * 256 + i];
+  if (threadIdx.x < 16) {
+    const int k1p = threadIdx.x >> 2, k1 = threadIdx.x & 3;
+    const int slot = kt.slot(b.sa - qk_a(k1p) + qk_a(k1), b.sb - qk_b(k1p) + qk_b(k1));
+    const int ti = slot < 0 ? -1 : thidx[pair * kt.nslot + slot];
+    s_off[threadIdx.x] = -1;
+    if (ti >= 0) {
+      const Blk &t = th[ti];
+      s_off[threadIdx.x] = t.offT;
+      s_C[threadIdx.x] = t.C;
+      for (int k = 0; k < 5; ++k) {
+        s_rs[threadIdx.x][k] = t.rs[k];
+        s_cs[threadIdx.x][k] = t.cs[k];
+      }
+    }
+  }
+  __syncthreads();
+  double *T = scratch + b.offT;
   const int total = b.R * b.C;
   for (int idx = threadIdx.x; idx < total; idx += kThreads) {
     const int row = idx / b.C, col = idx - row * b.C;
     const int k1p = seg_of(b.rs, row), k2p = seg_of(b.cs, col);
-    const int la = b.sa - qk_a(k1p), lb = b.sb - qk_b(k1p);
-    const int ra = b.sa + qk_a(k2p), rb = b.sb + qk_b(k2p);
-    const int l = kt.sec(a, pair, la, lb).x + (row - b.rs[k1p]);
-    const int r = kt.sec(a + 2, pair, ra, rb).x + (col - b.cs[k2p]);
+    const int l = row - b.rs[k1p], r = col - b.cs[k2p];
     double acc = 0.0;
     for (int k1 = 0; k1 < 4; ++k1) {
-      const int2 mid = kt.sec(a + 1, pair, la + qk_a(k1), lb + qk_b(k1));
-      if (mid.y == 0) continue;
-      const double *arow = A + ((int64_t)l * 4 + k1) * Dm + mid.x;
+      const int q = k1p * 4 + k1;
+      const int64_t off = s_off[q];
+      if (off < 0 || l >= s_rs[q][k1 + 1] - s_rs[q][k1]) continue;
+      const double *Th = scratch + off + (int64_t)(s_rs[q][k1] + l) * s_C[q] + r;
       for (int k2 = 0; k2 < 4; ++k2) {
         const double g = sG[(k1p * 4 + k2p) * 16 + k1 * 4 + k2];
-        if (g == 0.0) continue;
-        const double *bcol = B + ((int64_t)mid.x * 4 + k2) * Dr + r;
-        double s = 0.0;
-        for (int m = 0; m < mid.y; ++m) s += arow[m] * bcol[(int64_t)m * 4 * Dr];
-        acc += g * s;
+        if (g == 0.0 || r >= s_cs[q][k2 + 1] - s_cs[q][k2]) continue;
+        acc += g * Th[s_cs[q][k2]];
       }
     }
     T[idx] = acc;
@@ -216,10 +310,11 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 
 }  // namespace
 
-void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const double *gates,
-                     double *scratch, hipStream_t st) {
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(k_two_site, dim3(nblk), dim3(kThreads), 0, st, kt, a, blk, gates, scratch);
+void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const Blk *th, int nth,
+                     const int *thidx, const double *gates, double *scratch, hipStream_t st) {
+  if (nth > 0) hipLaunchKernelGGL(k_theta, dim3(nth), dim3(kThreads), 0, st, kt, a, th, scratch);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_gate_gather, dim3(nblk), dim3(kThreads), 0, st, kt, blk, th, thidx, gates, scratch);
 }
 
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
