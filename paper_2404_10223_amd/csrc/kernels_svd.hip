@@ -58,12 +58,23 @@ __device__ inline double wave_sum(double v) {
 
 // Rotation that orthogonalises (x, y) with squared norms al, be and product
 // ga: x' = c x - s y, y' = s x + c y; returns tan (for the norm updates).
+// tan is the smaller root of t^2 ga + t (al - be) - ga = 0, written without
+// cancellation (one division, one square root).
 __device__ inline double jacobi_angle(double al, double be, double ga, double &c, double &s) {
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double d = be - al;
+  const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
   c = 1.0 / sqrt(1.0 + t * t);
   s = c * t;
   return t;
+}
+
+// sum of squares / dot product of E register elements, four partial sums
+template <int E>
+__device__ inline double dot_e(const double (&x)[E], const double (&y)[E]) {
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < E; ++e) p[e & 3] = fma(x[e], y[e], p[e & 3]);
+  return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
 // rank of value i among n (descending, ties by index)
@@ -123,8 +134,8 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
     s_rot[1] = 0;
   }
   __syncthreads();
-  // rounding floor of a length-m dot product relative to the norms
-  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  // rounding floor of a length-m dot product relative to the norms (squared)
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m)), tol2 = tol * tol;
   double rn = 0.0;   // squared norm of the resident (same in all lanes of the group)
   int sweep = 0;
   for (; sweep < max_sweeps && n > 1; ++sweep) {
@@ -133,19 +144,12 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
     __syncthreads();
     // squared norms, recomputed each sweep and updated exactly per rotation
     if (act) {
-      double s2 = 0.0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) s2 += res[e] * res[e];
-      rn = group_sum(s2, G);
+      rn = group_sum(dot_e(res, res), G);
       double mx = rn;
       if (p < NTr) {
-        double t2 = 0.0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const double v = Xl[p * mp + e];
-          t2 += v * v;
-        }
-        t2 = group_sum(t2, G);
+        for (int e = 0; e < E; ++e) trv[e] = Xl[p * mp + e];
+        const double t2 = group_sum(dot_e(trv, trv), G);
         if (gl == 0) tnrm[p] = t2;
         mx = fmax(mx, t2);
       }
@@ -171,11 +175,8 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
             for (int e = 0; e < E; ++e) trv[e] = xs[e];
             const double al = rn, be = tnrm[sb + j];
             if (al > tiny && be > tiny) {
-              double ga = 0.0;
-#pragma unroll
-              for (int e = 0; e < E; ++e) ga += res[e] * trv[e];
-              ga = group_sum(ga, G);
-              if (fabs(ga) > tol * sqrt(al * be)) {
+              const double ga = group_sum(dot_e(res, trv), G);
+              if (ga * ga > tol2 * (al * be)) {
                 double c, s;
                 const double tn = jacobi_angle(al, be, ga, c, s);
                 // one component at a time (keeps the live registers at the
