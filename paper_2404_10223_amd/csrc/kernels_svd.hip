@@ -56,14 +56,32 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// 1/sqrt(x) and 1/x for normal positive x: hardware estimate refined by two
+// Newton steps (a few ulps; the Jacobi rotation needs no correct rounding)
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 // Rotation that orthogonalises (x, y) with squared norms al, be and product
-// ga: x' = c x - s y, y' = s x + c y; returns tan (for the norm updates).
-// tan is the smaller root of t^2 ga + t (al - be) - ga = 0, written without
-// cancellation (one division, one square root).
+// ga != 0: x' = c x - s y, y' = s x + c y; returns tan (for the norm updates).
+// tan is the smaller root of t^2 ga + t (be - al) - ga = 0, written without
+// cancellation; c = 1/sqrt(1 + t^2), s = c t.
 __device__ inline double jacobi_angle(double al, double be, double ga, double &c, double &s) {
   const double d = be - al;
-  const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
-  c = 1.0 / sqrt(1.0 + t * t);
+  const double q = fma(d, d, 4.0 * ga * ga);
+  const double r = q * rsqrt_nr(q);   // sqrt(d^2 + 4 ga^2)
+  const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * rcp_nr(fabs(d) + r);
+  c = rsqrt_nr(fma(t, t, 1.0));
   s = c * t;
   return t;
 }
