@@ -130,15 +130,21 @@ typedef struct {
   double env_kernel_ms;             /* summed device time of the environment kernels     */
   double svd_kernel_ms;             /* summed device time of the truncation SVD launches */
   double svd_flops;                 /* their algorithmic flops (4 n^2 m + 9 n^3 a block) */
-  double svd_kind_ms[8];            /* the same split by SVD kernel: entry k < 6 for    */
-  double svd_kind_flops[8];         /*   4 (k + 1) vector elements per lane, entry 6 for */
-                                    /*   the global-memory fallback, entry 7 unused      */
+  double svd_kind_ms[16];           /* the same split by SVD kernel: entry k < 6 for    */
+  double svd_kind_flops[16];        /*   4 (k + 1) vector elements per lane, entry 6 for */
+                                    /*   the global-memory fallback, 7 + j for the unit */
+                                    /*   kernels with 4 (j + 1) elements per lane       */
+  double env_kind_ms[8];            /* environment kernels: 0 L x ket GEMM, 1 sparse    */
+  double env_kind_flops[8];         /*   channel mix, 2 dense coupling GEMMs, 3 bra^T x */
+  double env_kind_bytes[8];         /*   Y GEMM, 4 final element; device time, flops    */
+                                    /*   and algorithmic bytes, entries 5-7 unused      */
   int32_t n_dropped;                /* eigenvalues of S below the threshold             */
   int32_t n_pairs;                  /* unique pairs computed (M (M + 1) / 2)            */
   int32_t max_bond;                 /* largest bond dimension seen                      */
   int32_t mpo_max_bond;             /* largest MPO bond dimension                       */
   int32_t svd_launches;             /* truncation SVD launches timed                    */
-  int32_t svd_kind_launches[8];     /* the same split by SVD kernel                     */
+  int32_t svd_kind_launches[16];    /* the same split by SVD kernel                     */
+  int32_t env_kind_launches[8];     /* launches of each environment kernel              */
   int32_t reserved[7];
 } tnqe_report;
 

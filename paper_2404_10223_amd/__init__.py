@@ -44,10 +44,13 @@ class _Report(C.Structure):
                 ("t_env_ms", C.c_double), ("t_gep_ms", C.c_double), ("alg_flops", C.c_double),
                 ("alg_bytes", C.c_double), ("env_flops", C.c_double), ("env_kernel_ms", C.c_double),
                 ("svd_kernel_ms", C.c_double), ("svd_flops", C.c_double),
-                ("svd_kind_ms", C.c_double * 8), ("svd_kind_flops", C.c_double * 8),
+                ("svd_kind_ms", C.c_double * 16), ("svd_kind_flops", C.c_double * 16),
+                ("env_kind_ms", C.c_double * 8), ("env_kind_flops", C.c_double * 8),
+                ("env_kind_bytes", C.c_double * 8),
                 ("n_dropped", C.c_int32), ("n_pairs", C.c_int32), ("max_bond", C.c_int32),
                 ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32),
-                ("svd_kind_launches", C.c_int32 * 8), ("reserved", C.c_int32 * 7)]
+                ("svd_kind_launches", C.c_int32 * 16), ("env_kind_launches", C.c_int32 * 8),
+                ("reserved", C.c_int32 * 7)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",

@@ -17,6 +17,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -317,7 +319,7 @@ struct Scratch {
 // Launch shape of the Jacobi SVD of an n-vector block with vectors of length
 // m: ceil(n/2) processors of G lanes, E vector components per lane in
 // registers (G E >= m), floor(n/2) traveller vectors in LDS rows of
-// G (E | 1) doubles.
+// G (E + 2) doubles.
 struct JacobiPlan {
   int kind = kJacobiGlobal, grp = 64, threads = 1024, mpad = 0;
   int64_t lds = 0;
@@ -341,13 +343,13 @@ JacobiPlan jacobi_plan(int n, int m) {
       const int E = ((m + G - 1) / G + 3) / 4 * 4;
       if (E > cap) continue;
       if (P * G > jacobi_max_threads(E)) break;
-      const int64_t lds = ((int64_t)NTr * G * (E | 1) + NTr + n) * 8 + (int64_t)n * 4;
+      const int64_t lds = ((int64_t)NTr * G * (E + 2) + NTr + n) * 8 + (int64_t)n * 4;
       if (lds > kJacobiLdsBytes) break;
       best = G;
       jp.kind = E / 4 - 1;
       jp.grp = G;
       jp.threads = (P * G + 63) / 64 * 64;
-      jp.mpad = G * (E | 1);
+      jp.mpad = G * (E + 2);
       jp.lds = lds;
       break;
     }
@@ -376,6 +378,21 @@ void plan_block_storage(Blk &b, Scratch &sc) {
 double svd_flops(const Blk &b) {
   const double n = std::min(b.R, b.C), m = std::max(b.R, b.C);
   return 4.0 * n * n * m + 9.0 * n * n * n;
+}
+
+// TNQE_DEBUG_TIMING=1: host-side time split of the gate phase (diagnostics)
+struct GateHostTiming {
+  double sync_ms = 0.0, select_ms = 0.0, step_ms = 0.0, move_ms = 0.0;
+  double build_ms = 0.0, two_site_ms = 0.0, svd_host_ms = 0.0, post_ms = 0.0;
+  int steps = 0;
+};
+double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+GateHostTiming g_gate_timing;
+bool debug_timing() {
+  static const bool on = std::getenv("TNQE_DEBUG_TIMING") != nullptr;
+  return on;
 }
 
 // Device time of timed SVD launches (per kernel), collected after the next
@@ -619,6 +636,7 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
 // Gate at (a, a+1) for every ket with its own 16x16 matrix, then truncation.
 void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap, double tau_w,
                int max_sweeps, TruncStats &ts) {
+  const auto tb0 = Clock::now();
   Call &c = *ks.call;
   std::vector<Blk> blks;
   Scratch sc;
@@ -672,56 +690,84 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
     ns += b.n;
   }
   sc.used += ns;
+  const auto tb1 = Clock::now();
   double *scratch = c.dev<double>(sc.used);
   double *dgates = c.upload(gates);
   Blk *dblk = c.upload(blks);
   launch_two_site(ks.tables(), a, dblk, (int)blks.size(), c.upload(th), (int)th.size(), c.upload(thidx), dgates,
                   scratch, c.ctx->stream);
+  const auto tb2 = Clock::now();
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
+  const auto tb3 = Clock::now();
   c.check_launch();
   std::vector<double> sv(ns);
   TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
+  const auto ts0 = Clock::now();
   c.sync();
+  const auto ts1 = Clock::now();
   ts.svd.collect(c.ctx);
-  // global top-chi per ket
+  // global top-chi per ket: the `keep` largest singular values, ties taken in
+  // block order (lower index first)
   std::vector<std::vector<int>> per(ks.n);
   for (size_t i = 0; i < blks.size(); ++i) per[blks[i].pair].push_back((int)i);
+  std::vector<double> vals, tmp;
   for (int t = 0; t < ks.n; ++t) {
-    std::vector<std::pair<double, int64_t>> all;   // (sigma, global index) in block order
+    vals.clear();
     double tot = 0.0;
     for (int bi : per[t]) {
       const Blk &b = blks[bi];
       for (int j = 0; j < b.n; ++j) {
         const double sgm = sv[b.offS - s0 + j];
-        all.push_back({sgm, (int64_t)(b.offS - s0 + j)});
+        vals.push_back(sgm);
         tot += sgm * sgm;
       }
     }
-    std::vector<size_t> order(all.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return all[x].first > all[y].first; });
     int nnz = 0;
-    for (auto &v : all) nnz += (v.first * v.first > tau_w * tot) ? 1 : 0;
+    for (double v : vals) nnz += (v * v > tau_w * tot) ? 1 : 0;
     const int keep = std::min(chi_cap, nnz);
-    std::vector<char> kept(all.size(), 0);
-    for (int r = 0; r < keep; ++r) kept[order[r]] = 1;
-    double disc = 0.0;
-    for (size_t i = 0; i < all.size(); ++i)
-      if (!kept[i]) disc += all[i].first * all[i].first;
-    ts.discarded[t] += disc;
-    if (keep > 0 && (size_t)keep < all.size()) {
-      const double si = all[order[keep - 1]].first, so = all[order[keep]].first;
-      if (si > 0.0) ts.min_gap = std::min(ts.min_gap, (si - so) / si);
+    const size_t ntot = vals.size();
+    double th = -1.0;   // keep-th largest value (every value kept when keep == ntot)
+    int need_eq = 0;
+    if (keep == 0) {
+      th = std::numeric_limits<double>::infinity();
+    } else if ((size_t)keep < ntot) {
+      tmp = vals;
+      std::nth_element(tmp.begin(), tmp.begin() + (keep - 1), tmp.end(), std::greater<double>());
+      th = tmp[keep - 1];
+      const double so = *std::max_element(tmp.begin() + keep, tmp.end());
+      if (th > 0.0) ts.min_gap = std::min(ts.min_gap, (th - so) / th);
+      int gt = 0;
+      for (double v : vals) gt += v > th ? 1 : 0;
+      need_eq = keep - gt;
     }
     // kept counts per block (a prefix of each block's sorted list)
+    double disc = 0.0;
     size_t gi = 0;
     for (int bi : per[t]) {
       Blk &b = blks[bi];
       int k = 0;
-      for (int j = 0; j < b.n; ++j, ++gi) k += kept[gi];
+      for (int j = 0; j < b.n; ++j, ++gi) {
+        const double v = vals[gi];
+        bool kp = v > th;
+        if (!kp && v == th && need_eq > 0) {
+          kp = true;
+          --need_eq;
+        }
+        if (kp) ++k; else disc += v * v;
+      }
       b.kept = k;
     }
+    ts.discarded[t] += disc;
     ts.max_bond = std::max(ts.max_bond, keep);
+  }
+  const auto ts2 = Clock::now();
+  if (debug_timing()) {
+    g_gate_timing.build_ms += ms_between(tb0, tb1);
+    g_gate_timing.two_site_ms += ms_between(tb1, tb2);
+    g_gate_timing.svd_host_ms += ms_between(tb2, tb3);
+    g_gate_timing.sync_ms += ms_between(ts0, ts1);
+    g_gate_timing.select_ms += ms_between(ts1, ts2);
+    g_gate_timing.steps++;
   }
   for (int t = 0; t < ks.n; ++t)
     for (int s = 0; s < ks.nslot; ++s) ks.dim(a + 1, t, s) = 0;
@@ -737,6 +783,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   launch_svd_factor(dblk2, (int)blks.size(), scratch, c.ctx->stream);
   launch_split_gate(ks.tables(), a, dblk2, (int)blks.size(), scratch, c.ctx->stream);
   c.check_launch();
+  if (debug_timing()) g_gate_timing.post_ms += ms_between(ts2, Clock::now());
 }
 
 // ------------------------------------------------------------ environment sweep
@@ -753,9 +800,13 @@ void pick_tile(int maxM, int maxN, bool long_m, int &tm, int &tn) {
   }
 }
 
+enum { kEnvG1 = 0, kEnvMix = 1, kEnvDense = 2, kEnvG2 = 3, kEnvFinal = 4, kEnvKinds = 5 };
+
 struct EnvResult {
   std::vector<double> H, S;   // per env pair
   double flops = 0.0, bytes = 0.0, kernel_ms = 0.0;
+  double kind_ms[kEnvKinds] = {}, kind_flops[kEnvKinds] = {}, kind_bytes[kEnvKinds] = {};
+  int kind_launches[kEnvKinds] = {};
   int max_pad = 0;
 };
 
@@ -1060,7 +1111,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   // thread, overlapping the sweeps)
   const double eb = sizeof(T);
   std::thread work_thread([&] {
-    double fl = 0.0, by = 0.0;
+    double fl[kEnvKinds] = {}, by[kEnvKinds] = {};
     for (const auto &pr : pairs) {
       const int q = (int)(&pr - pairs.data());
       const int bi = pr.first, ki = ket_of_pair[q] < 0 ? pr.first : M + ket_of_pair[q];
@@ -1068,36 +1119,40 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         const SiteTabs &tb = tabs[x];
         for (const EnvG1 &d : tb.g1) {
           const double m = (double)idim(bi, x, d.sbra) * d.nw, k = idim(ki, x, d.s), n = idim(ki, x + 1, d.sk);
-          fl += 2.0 * m * n * k;
-          by += eb * (m * k + k * n + m * n);
+          fl[kEnvG1] += 2.0 * m * n * k;
+          by[kEnvG1] += eb * (m * k + k * n + m * n);
         }
         for (const MixTask &tk : tb.tasks) {
           const double da = idim(bi, x, tk.sa), db = idim(ki, x + 1, tk.s);
           for (int i = 0; i < tk.nsrc; ++i) {
-            fl += 2.0 * tb.src_nnz[tk.src0 + i] * da * db;
-            by += eb * da * tb.srcs[tk.src0 + i].nw_in * db;
+            fl[kEnvMix] += 2.0 * tb.src_nnz[tk.src0 + i] * da * db;
+            by[kEnvMix] += eb * da * tb.srcs[tk.src0 + i].nw_in * db;
           }
-          by += eb * da * tk.nw_out * db;
+          by[kEnvMix] += eb * da * tk.nw_out * db;
         }
         for (const auto &lv : tb.dense)
           for (const EnvGD &d : lv) {
             const double da = idim(bi, x, d.sa), db = idim(ki, x + 1, d.s);
-            fl += 2.0 * d.nr * d.nc * db * da;
-            by += eb * ((double)d.nc * db * da + 2.0 * d.nr * db * da);
+            fl[kEnvDense] += 2.0 * d.nr * d.nc * db * da;
+            by[kEnvDense] += eb * ((double)d.nc * db * da + 2.0 * d.nr * db * da);
           }
         for (const EnvG2 &d : tb.g2) {
           const double m = idim(bi, x + 1, d.sbn), n = (double)d.nw * idim(ki, x + 1, d.s);
           for (int g = 0; g < d.nseg; ++g) {
             const double k = idim(bi, x, d.sa[g]);
-            fl += 2.0 * m * n * k;
-            by += eb * (k * m + k * n);
+            fl[kEnvG2] += 2.0 * m * n * k;
+            by[kEnvG2] += eb * (k * m + k * n);
           }
-          by += eb * m * n;
+          by[kEnvG2] += eb * m * n;
         }
       }
     }
-    res.flops = fl;
-    res.bytes = by;
+    for (int k = 0; k < kEnvKinds; ++k) {
+      res.kind_flops[k] = fl[k];
+      res.kind_bytes[k] = by[k];
+      res.flops += fl[k];
+      res.bytes += by[k];
+    }
   });
   struct JoinGuard {
     std::thread &t;
@@ -1205,11 +1260,24 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     for (int q = 0; q < nb_; ++q) bra64[q] = site64[(size_t)bra_item[q] * N + N - 1];
     const double *const *dbra64 = c.upload(bra64);
     double *dout = c.dev<double>((size_t)nb_ * 2);
+    // one event between consecutive launches: launch i runs from tick i to i + 1
+    std::vector<int> tick_kind;
+    auto tick = [&](int kind) {
+      const size_t i = tick_kind.size();
+      if (i >= c.ctx->env_ev.size()) {
+        hipEvent_t e;
+        TNQE_HIP(hipEventCreate(&e));
+        c.ctx->env_ev.push_back(e);
+      }
+      TNQE_HIP(hipEventRecord(c.ctx->env_ev[i], st));
+      tick_kind.push_back(kind);
+    };
     TNQE_HIP(hipEventRecord(e0, st));
     launch_env_init<T>(dL0, nb_, Lsize[0], st);
     T **Lc = dL0, **Ln = dL1;
     for (int x = 0; x < N; ++x) {
       const SiteTabs &tb = tabs[x];
+      tick(kEnvG1);
       launch_env_g1<T>(ds[x].g1, (int)tb.g1.size(), tb.t1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, nb_, st);
       MixArgs ma{};
       ma.tasks = ds[x].tasks;
@@ -1224,18 +1292,24 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       ma.basis_stride = nnz_total;
       ma.site_off = 0;
       ma.basis = dbasis;
+      tick(kEnvMix);
       launch_mix<T>(ma, geom, dX, dY, nb_, st);
-      for (size_t lv = 0; lv < tb.dense.size(); ++lv)
+      for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
+        tick(kEnvDense);
         launch_env_gd<T>(ds[x].dense[lv], (int)tb.dense[lv].size(), tb.td[lv], tb.tmd[lv], tb.tnd[lv], geom, dvptr,
                          dX, dY, nb_, st);
+      }
       if (x < N - 1) {
+        tick(kEnvG2);
         launch_env_g2<T>(ds[x].g2, (int)tb.g2.size(), tb.t2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, nb_, st);
         std::swap(Lc, Ln);
       } else {
+        tick(kEnvFinal);
         launch_env_final<T>(geom, x, dbra64, dY, ds[x].fin, (int)tb.fin.size(), 2, dout, nb_, st);
       }
       c.check_launch();
     }
+    tick(-1);
     TNQE_HIP(hipEventRecord(e1, st));
     std::vector<double> out((size_t)nb_ * 2);
     TNQE_HIP(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1243,6 +1317,12 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     float ms = 0.0f;
     TNQE_HIP(hipEventElapsedTime(&ms, e0, e1));
     res.kernel_ms += ms;
+    for (size_t i = 0; i + 1 < tick_kind.size(); ++i) {
+      float t = 0.0f;
+      TNQE_HIP(hipEventElapsedTime(&t, c.ctx->env_ev[i], c.ctx->env_ev[i + 1]));
+      res.kind_ms[tick_kind[i]] += t;
+      res.kind_launches[tick_kind[i]]++;
+    }
     for (int q = 0; q < nb_; ++q) {
       res.H[p0 + q] = out[(size_t)q * 2 + mpo.final_H];
       res.S[p0 + q] = out[(size_t)q * 2 + mpo.final_I];
@@ -1470,10 +1550,12 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     for (size_t g = 0; g < ngate; ++g) {
       const int a = gpos[0][g];
       const size_t mk = ctx->pool.mark();
+      const auto tm0 = Clock::now();
       while (centre > a) {
         move_left(kets, centre, max_sweeps);
         --centre;
       }
+      const auto tm1 = Clock::now();
       for (int t = 0; t < P; ++t) {
         require(gpos[t][g] == a, TNQE_EINVAL, "gate positions differ between pairs");
         gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
@@ -1481,8 +1563,21 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, ts);
       centre = a + 1;
       ctx->pool.rewind(mk);
+      if (debug_timing()) {
+        g_gate_timing.move_ms += std::chrono::duration<double, std::milli>(tm1 - tm0).count();
+        g_gate_timing.step_ms += std::chrono::duration<double, std::milli>(Clock::now() - tm1).count();
+      }
     }
     c.sync();
+    if (debug_timing()) {
+      std::fprintf(stderr,
+                   "gate phase host: %d steps, move %.1f ms, gate step %.1f ms (build %.1f, two-site %.1f, "
+                   "svd launches %.1f, sync wait %.1f, selection %.1f, split %.1f)\n",
+                   g_gate_timing.steps, g_gate_timing.move_ms, g_gate_timing.step_ms, g_gate_timing.build_ms,
+                   g_gate_timing.two_site_ms, g_gate_timing.svd_host_ms, g_gate_timing.sync_ms,
+                   g_gate_timing.select_ms, g_gate_timing.post_ms);
+      g_gate_timing = GateHostTiming{};
+    }
   }
   rep.t_gates_ms = ms_since(tg);
   // ---- environment sweep
@@ -1527,6 +1622,12 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   for (double d : ts.discarded) rep.max_discarded_weight_sum = std::max(rep.max_discarded_weight_sum, d);
   rep.min_rel_gap = ts.min_gap;
   rep.env_flops = er.flops;
+  for (int k = 0; k < kEnvKinds; ++k) {
+    rep.env_kind_ms[k] = er.kind_ms[k];
+    rep.env_kind_flops[k] = er.kind_flops[k];
+    rep.env_kind_bytes[k] = er.kind_bytes[k];
+    rep.env_kind_launches[k] = er.kind_launches[k];
+  }
   rep.alg_bytes = er.bytes;
   rep.env_kernel_ms = er.kernel_ms;
   rep.svd_kernel_ms = ts.svd.ms;
@@ -1663,6 +1764,7 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
     if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
   }
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  for (auto &e : ctx->env_ev) (void)hipEventDestroy(e);
   delete ctx;
   return TNQE_OK;
 }

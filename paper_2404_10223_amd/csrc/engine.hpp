@@ -69,6 +69,7 @@ struct tnqe_ctx {
   static constexpr int kAux = 4;
   hipStream_t aux[kAux] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kAux] = {};
+  std::vector<hipEvent_t> env_ev;   // per-launch timing of the environment kernels (grown on demand)
 };
 
 struct tnqe_problem {
