@@ -28,7 +28,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-SVD_KERNELS = ["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global", None]
+SVD_KERNELS = (["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global"]
+               + ["k_jacobi_u<4, %d>" % (4 * (j + 1)) for j in range(4)] + [None] * 5)
+KERNEL_SOURCE = {"k_jacobi": "kernels_svd.hip", "k_env": "kernels_env.hip", "k_mix": "kernels_env.hip"}
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.md")
 ENV_KERNELS = ["k_env_g1", "k_mix", "k_env_gd", "k_env_g2", "k_env_final", None, None, None]
 MACHINE_BALANCE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte
 
@@ -56,6 +59,7 @@ def roofline(rep):
     ms, name, flops, nbytes, launches = max(cands)
     sec = ms * 1e-3
     out = {"kernel": name, "launches": launches, "avg_launch_us": ms * 1e3 / launches}
+    traffic = measured_traffic(name)
     if nbytes is None or (nbytes > 0 and flops / nbytes >= MACHINE_BALANCE):
         out.update({"bound": "alu", "achieved": flops / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "work_per_launch": flops / launches, "work_unit": "flop"})
@@ -63,11 +67,51 @@ def roofline(rep):
         out.update({"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "work_per_launch": nbytes / launches, "work_unit": "byte"})
     out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = None
+    out["traffic"] = traffic["bytes_per_launch"] if traffic else None
+    out["traffic_unit"] = "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE scaled by a copy kernel)"
+    out["traffic_detail"] = traffic
     return out
 
 
-def cpu_baseline(prob, n_gates=40):
+def source_digest(kernel):
+    import hashlib
+    for prefix, f in KERNEL_SOURCE.items():
+        if kernel.startswith(prefix):
+            with open(os.path.join(HERE, "paper_2404_10223_amd", "csrc", f), "rb") as fh:
+                return hashlib.sha256(fh.read()).hexdigest()
+    return None
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    covers this kernel and its source file is unchanged since (else None)."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(blob)
+    except (OSError, IndexError, ValueError):
+        return None
+    entry = rec.get("kernels", {}).get(kernel)
+    if not entry or entry.get("source_sha256") != source_digest(kernel):
+        return None
+    return {"bytes_per_launch": entry["fetch_bytes_per_launch"] + entry["write_bytes_per_launch"],
+            "fetch_bytes_per_launch": entry["fetch_bytes_per_launch"],
+            "write_bytes_per_launch": entry["write_bytes_per_launch"], "source": "profiles/traffic.md"}
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b = a.clone()
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "ok": bool(b[0].item() == 1)}))
+
+
+def cpu_baseline(prob, n_gates=60):
     """FP64 oracle on a bounded sample: the first gates of pair (0, 1)."""
     import numpy as np
     from oracle import gates as og, givens as ogv, mps as om
@@ -103,8 +147,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-gates", type=int, default=40)
+    ap.add_argument("--cpu-gates", type=int, default=60)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the pair set shards "
                                    "across GPUs by design, see DESIGN.md, but no multi-GPU path is built)"}))
@@ -152,8 +201,7 @@ def main():
             "E": E, "report": {k: rep[k] for k in ("t_host_ms", "t_gates_ms", "t_env_ms", "t_gep_ms",
                                                    "max_discarded_weight_sum", "min_rel_gap", "max_bond",
                                                    "svd_kernel_ms", "svd_flops", "env_kernel_ms", "env_flops",
-                                                   "alg_bytes", "svd_kind_ms", "svd_kind_flops",
-                                                   "svd_kind_launches")},
+                                                   "alg_bytes")},
             "mixed": mixed, "roofline": roof, "cpu_baseline": cpu}
     up.free()
     ctx.close()
