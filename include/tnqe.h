@@ -171,8 +171,11 @@ tnqe_status tnqe_problem_free(tnqe_problem *prob);
 tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *prob, const tnqe_options *opts,
                        double *H, double *S, double *E, double *c, tnqe_report *rep);
 
-/* Several independent subspaces in one call; their work is batched into the
- * same launches.  H[s], S[s]: [M_s][M_s] host; E: [n]; rep: [n] or NULL. */
+/* Several independent subspaces in one call, solved one after another on the
+ * context's stream (inside each subspace every pair shares the same
+ * launches).  opts: [n], one per subspace (each with its own chi).  H[s],
+ * S[s]: [M_s][M_s] host; E: [n]; rep: [n] or NULL.  Stops at the first
+ * failing subspace and returns its status; later outputs are untouched. */
 tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *probs,
                              const tnqe_options *opts, double *const *H, double *const *S,
                              double *E, tnqe_report *rep);

@@ -205,9 +205,10 @@ class Context:
         finally:
             up.free()
 
-    def solve_batch(self, uploaded, **kw):
+    def solve_batch(self, uploaded, chis, **kw):
+        """Solve several uploaded subspaces; chis[s] is subspace s's bond cap."""
         n = len(uploaded)
-        o = options(**kw)
+        o = (_Opts * n)(*[options(chi=int(ch), **kw) for ch in chis])
         Hs = [np.zeros((u.M, u.M)) for u in uploaded]
         Ss = [np.zeros((u.M, u.M)) for u in uploaded]
         E = np.zeros(n)
@@ -215,7 +216,7 @@ class Context:
         handles = (C.c_void_p * n)(*[u.handle.value for u in uploaded])
         hp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Hs])
         sp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Ss])
-        _check(self.L.tnqe_solve_batch(self.h, n, handles, C.byref(o), hp, sp, _dptr(E), reps), self.h)
+        _check(self.L.tnqe_solve_batch(self.h, n, handles, o, hp, sp, _dptr(E), reps), self.h)
         return Hs, Ss, E, [report_dict(r) for r in reps]
 
 

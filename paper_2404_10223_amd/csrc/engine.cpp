@@ -1042,18 +1042,19 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     tb.Ysize = yo;
     for (auto &lv : tb.dense) {
+      // N runs over (bra row, ket index) of the block
       int maxM = 0, maxN = 0;
       for (auto &d : lv) {
         maxM = std::max(maxM, d.nr);
-        maxN = std::max(maxN, dpad[x + 1][d.s]);
+        maxN = std::max(maxN, dpad[x][d.sa] * dpad[x + 1][d.s]);
       }
       int tm, tn, nt = 0;
-      pick_tile(maxM, maxN, true, tm, tn);
+      pick_tile(maxM, maxN, false, tm, tn);
       for (auto &d : lv) {
         d.tile0 = nt;
         d.tilesM = (d.nr + tm - 1) / tm;
-        d.tilesN = (dpad[x + 1][d.s] + tn - 1) / tn;
-        nt += d.tilesM * d.tilesN * dpad[x][d.sa];
+        d.tilesN = (dpad[x][d.sa] * dpad[x + 1][d.s] + tn - 1) / tn;
+        nt += d.tilesM * d.tilesN;
       }
       tb.td.push_back(nt);
       tb.tmd.push_back(tm);
@@ -1926,7 +1927,7 @@ tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *prob
                              double *const *H, double *const *S, double *E, tnqe_report *rep) {
   if (!ctx || !probs || !opts || !H || !S || !E || n < 0) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
   for (int s = 0; s < n; ++s) {
-    tnqe_status st = tnqe_solve(ctx, probs[s], opts, H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
+    tnqe_status st = tnqe_solve(ctx, probs[s], opts + s, H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
     if (st != TNQE_OK) return st;
   }
   return TNQE_OK;

@@ -158,8 +158,61 @@ __global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, int ndesc, E
   tile_gemm<T, TM, TN, RM, RN, 4>(M, N, m0, n0, sg, d.nseg, Ln[pair] + d.offL, N, T(1), 0);
 }
 
-// dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b]
-// for every bra row a of the block (one batch each)
+// C tile (m0, n0) of A B with element loaders (A: m x k, B: k x n) and an
+// accumulating store; same tiling as tile_gemm.
+template <typename T, int TM, int TN, int RM, int RN, class LA, class LB, class SC>
+__device__ void tile_gemm_f(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc) {
+  constexpr int KC = 16;
+  constexpr int TX = TN / RN;
+  static_assert((TM / RM) * (TN / RN) == 256, "tile");
+  __shared__ T sA[KC][TM + 1];
+  __shared__ T sB[KC][TN];
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  T acc[RM][RN];
+#pragma unroll
+  for (int i = 0; i < RM; ++i)
+#pragma unroll
+    for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * TM; e += 256) {
+      const int kk = e % KC, mm = e / KC;
+      const int gm = m0 + mm, gk = k0 + kk;
+      sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : T(0);
+    }
+    for (int e = threadIdx.x; e < KC * TN; e += 256) {
+      const int kk = e / TN, nn = e % TN;
+      const int gn = n0 + nn, gk = k0 + kk;
+      sB[kk][nn] = (gn < N && gk < K) ? lb(gk, gn) : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      T av[RM], bv[RN];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) av[i] = sA[kk][ty * RM + i];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) bv[j] = sB[kk][tx + j * TX];
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    const int gm = m0 + ty * RM + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+      const int gn = n0 + tx + j * TX;
+      if (gn < N) sc(gm, gn, acc[i][j]);
+    }
+  }
+}
+
+// dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b],
+// one GEMM over all bra rows a of the block: M = nr, K = nc, N = (a, b)
 template <typename T, int TM, int TN, int RM, int RN>
 __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, EnvGeom g, const T *const *vals,
                                                 const T *const *X, T *const *Y) {
@@ -167,23 +220,31 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, E
   const EnvGD d = descs[find_desc(descs, ndesc, blockIdx.x)];
   const int bi = g.bra[pair], ki = g.ket[pair];
   const int da = g.sec(bi, d.x, d.sa).y, db = g.sec(ki, d.x + 1, d.s).y;
-  const int per = d.tilesM * d.tilesN;
-  const int t0 = blockIdx.x - d.tile0;
-  const int a = t0 / per, t = t0 - a * per;
+  const int t = blockIdx.x - d.tile0;
   const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
-  if (a >= da || m0 >= d.nr || n0 >= db) return;
-  Seg<T> sg[1];
-  sg[0].A = vals[pair] + d.valoff;
-  sg[0].lda = d.nc;
-  sg[0].transA = 0;
-  sg[0].B = X[pair] + d.offX + ((int64_t)a * d.nw_in + d.c0) * db;
-  sg[0].ldb = db;
-  sg[0].K = d.nc;
-  tile_gemm<T, TM, TN, RM, RN, 1>(d.nr, db, m0, n0, sg, 1, Y[pair] + d.offY + ((int64_t)a * d.nw_out + d.r0) * db,
-                                  db, (T)d.f, 1);
+  const int N = da * db;
+  if (m0 >= d.nr || n0 >= N) return;
+  const T *W = vals[pair] + d.valoff;
+  const T *Xb = X[pair] + d.offX + (int64_t)d.c0 * db;
+  T *Yb = Y[pair] + d.offY + (int64_t)d.r0 * db;
+  const int nc = d.nc, xs = d.nw_in * db, ys = d.nw_out * db;
+  const T f = (T)d.f;
+  tile_gemm_f<T, TM, TN, RM, RN>(
+      d.nr, N, nc, m0, n0, [&](int m, int k) { return W[(int64_t)m * nc + k]; },
+      [&](int k, int n) {
+        const int a = n / db, b = n - a * db;
+        return Xb[(int64_t)a * xs + (int64_t)k * db + b];
+      },
+      [&](int m, int n, T v) {
+        const int a = n / db, b = n - a * db;
+        T *y = Yb + (int64_t)a * ys + (int64_t)m * db + b;
+        *y += f * v;
+      });
 }
 
 // ------------------------------------------------------------------ channel mix
+// Y[a][w'][b] = sum_src f_src sum_{(w', c) in CSR} v[w'][c] X_src[a][c][b],
+// one output element per thread (32-bit index arithmetic within a task).
 template <typename T>
 __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
   const int pair = blockIdx.y;
@@ -195,12 +256,11 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
   }
   const MixTask tk = a.tasks[lo];
   const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
-  const int64_t e = (int64_t)(chunk - a.task_chunk0[lo]) * 256 + threadIdx.x;
-  const int64_t total = (int64_t)da * tk.nw_out * db;
-  if (e >= total) return;
-  const int b = e % db;
-  const int w = (e / db) % tk.nw_out;
-  const int ap = e / ((int64_t)db * tk.nw_out);
+  const int e = (chunk - a.task_chunk0[lo]) * 256 + threadIdx.x;
+  if (e >= da * tk.nw_out * db) return;
+  const int rowi = e / db;
+  const int b = e - rowi * db;
+  const int ap = rowi / tk.nw_out, w = rowi - ap * tk.nw_out;
   const double *vals = a.vals + a.basis[pair] * a.basis_stride + a.site_off;
   const T *Xp = X[pair];
   double acc = 0.0;
@@ -208,7 +268,7 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
     const MixSrc s = a.src[tk.src0 + si];
     const CsrGroup cg = a.groups[s.group];
     const int r0 = a.rowptr[cg.rowptr + w], r1 = a.rowptr[cg.rowptr + w + 1];
-    const T *xb = Xp + s.offX + ((int64_t)ap * s.nw_in) * db + b;
+    const T *xb = Xp + s.offX + (int64_t)(ap * s.nw_in) * db + b;
     double part = 0.0;
     for (int z = r0; z < r1; ++z) part += vals[cg.val + z] * (double)xb[(int64_t)a.col[cg.col + z] * db];
     acc += s.factor * part;

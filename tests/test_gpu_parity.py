@@ -162,3 +162,25 @@ def test_dense_coupling_path(monkeypatch):
             _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), tol)
     finally:
         c.close()
+
+
+def test_batch_of_subspaces(ctx):
+    """64 independent subspaces (N in 8..16, chi in {16..128}, M in 2..8) in one
+    batched call; sampled subspaces against the stored oracle values."""
+    probs = synth.make_batch()
+    g = np.load(os.path.join(GOLD, "oracle_batch.npz"))
+    ups = [ctx.upload(p) for p in probs]
+    try:
+        Hs, Ss, Es, reps = ctx.solve_batch(ups, [p.chi for p in probs])
+    finally:
+        for u in ups:
+            u.free()
+    assert len(Hs) == len(probs)
+    for s_ in range(len(probs)):
+        assert np.isfinite(Es[s_])
+        np.testing.assert_allclose(np.diag(Ss[s_]), 1.0, atol=1e-12)
+    sampled = sorted({int(k[1:]) for k in g.files if k.startswith("E")})
+    assert sampled
+    for s_ in sampled:
+        print(f"subspace {s_}: N={probs[s_].N} chi={probs[s_].chi} M={probs[s_].M}", flush=True)
+        _assert_pencil(Hs[s_], Ss[s_], Es[s_], g[f"H{s_}"], g[f"S{s_}"], float(g[f"E{s_}"]), elementwise=True)
