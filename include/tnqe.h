@@ -77,8 +77,12 @@ typedef enum {
 
 typedef enum {
   TNQE_FP64 = 0,         /* everything in FP64                                      */
-  TNQE_ENV_FP32 = 1      /* environment sweep in FP32 (FP64 gates, SVD, final sum,
+  TNQE_ENV_FP32 = 1,     /* environment sweep in FP32 (FP64 gates, SVD, final sum,
                             eigensolve); the element sum is compensated FP64        */
+  TNQE_ENV_MIXED = 2     /* per pair: FP32 environments where the rotated ket keeps
+                            at most 1e-6 of its squared norm (the element and its
+                            FP32 rounding error are then bounded by the ket norm),
+                            FP64 for every other pair (all diagonal pairs)          */
 } tnqe_precision;
 
 /* Hamiltonian in the reference orbital basis.  All host pointers, row-major,
@@ -145,6 +149,7 @@ typedef struct {
   int32_t svd_launches;             /* truncation SVD launches timed                    */
   int32_t svd_kind_launches[16];    /* the same split by SVD kernel                     */
   int32_t env_kind_launches[8];     /* launches of each environment kernel              */
+  int32_t n_fp32_pairs;             /* pairs contracted in FP32 (precision modes 1, 2)  */
   int32_t reserved[7];
 } tnqe_report;
 

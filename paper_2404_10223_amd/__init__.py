@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libtnqe.so")
 
 TNQE_FP64 = 0
 TNQE_ENV_FP32 = 1
-PRECISIONS = {"fp64": TNQE_FP64, "fp32": TNQE_ENV_FP32}
+TNQE_ENV_MIXED = 2
+PRECISIONS = {"fp64": TNQE_FP64, "fp32": TNQE_ENV_FP32, "mixed": TNQE_ENV_MIXED}
 
 
 class _Ham(C.Structure):
@@ -50,6 +51,7 @@ class _Report(C.Structure):
                 ("n_dropped", C.c_int32), ("n_pairs", C.c_int32), ("max_bond", C.c_int32),
                 ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32),
                 ("svd_kind_launches", C.c_int32 * 16), ("env_kind_launches", C.c_int32 * 8),
+                ("n_fp32_pairs", C.c_int32),
                 ("reserved", C.c_int32 * 7)]
 
 

@@ -1584,10 +1584,54 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   // ---- environment sweep
   const auto te = Clock::now();
   EnvResult er;
-  if (op.precision == TNQE_ENV_FP32)
+  if (op.precision == TNQE_ENV_FP32) {
     env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
-  else
+    rep.n_fp32_pairs = (int)pairs.size();
+  } else if (op.precision == TNQE_ENV_MIXED) {
+    // FP32 for pairs whose rotated ket kept at most kMixedNorm2 of its squared
+    // norm (1 - summed discarded weight), FP64 for the rest
+    constexpr double kMixedNorm2 = 1e-6;
+    std::vector<std::pair<int, int>> p64, p32;
+    std::vector<int> k64, k32, q64, q32;
+    for (size_t q = 0; q < pairs.size(); ++q) {
+      const int t = ket_of_pair[q];
+      if (t >= 0 && 1.0 - ts.discarded[t] <= kMixedNorm2) {
+        p32.push_back(pairs[q]);
+        k32.push_back(t);
+        q32.push_back((int)q);
+      } else {
+        p64.push_back(pairs[q]);
+        k64.push_back(t);
+        q64.push_back((int)q);
+      }
+    }
+    EnvResult e64, e32;
+    if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64);
+    if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32);
+    er.H.assign(pairs.size(), 0.0);
+    er.S.assign(pairs.size(), 0.0);
+    for (size_t q = 0; q < q64.size(); ++q) {
+      er.H[q64[q]] = e64.H[q];
+      er.S[q64[q]] = e64.S[q];
+    }
+    for (size_t q = 0; q < q32.size(); ++q) {
+      er.H[q32[q]] = e32.H[q];
+      er.S[q32[q]] = e32.S[q];
+    }
+    er.flops = e64.flops + e32.flops;
+    er.bytes = e64.bytes + e32.bytes;
+    er.kernel_ms = e64.kernel_ms + e32.kernel_ms;
+    er.max_pad = std::max(e64.max_pad, e32.max_pad);
+    for (int k = 0; k < kEnvKinds; ++k) {
+      er.kind_ms[k] = e64.kind_ms[k] + e32.kind_ms[k];
+      er.kind_flops[k] = e64.kind_flops[k] + e32.kind_flops[k];
+      er.kind_bytes[k] = e64.kind_bytes[k] + e32.kind_bytes[k];
+      er.kind_launches[k] = e64.kind_launches[k] + e32.kind_launches[k];
+    }
+    rep.n_fp32_pairs = (int)p32.size();
+  } else {
     env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
+  }
   rep.t_env_ms = ms_since(te);
   // ---- pencil and eigensolve
   const auto tq = Clock::now();
@@ -1906,7 +1950,7 @@ tnqe_status tnqe_problem_free(tnqe_problem *pb) {
 tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts, double *H, double *S,
                        double *E, double *cvec, tnqe_report *rep) {
   if (!ctx || !pb || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
-  if (opts->precision != TNQE_FP64 && opts->precision != TNQE_ENV_FP32)
+  if (opts->precision != TNQE_FP64 && opts->precision != TNQE_ENV_FP32 && opts->precision != TNQE_ENV_MIXED)
     return fail(ctx, TNQE_EINVAL, "unknown precision mode");
   SolveOut so;
   tnqe_status st = guarded(ctx, [&] {

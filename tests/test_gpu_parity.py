@@ -184,3 +184,22 @@ def test_batch_of_subspaces(ctx):
     for s_ in sampled:
         print(f"subspace {s_}: N={probs[s_].N} chi={probs[s_].chi} M={probs[s_].M}", flush=True)
         _assert_pencil(Hs[s_], Ss[s_], Es[s_], g[f"H{s_}"], g[f"S{s_}"], float(g[f"E{s_}"]), elementwise=True)
+
+
+def test_mixed_precision_full_size(ctx):
+    """Mixed mode at N = 24: FP32 environments for the pairs whose rotated ket
+    keeps <= 1e-6 of its squared norm; E within 1e-6 Ha of the FP64 path."""
+    prob = synth.make_config(5)
+    up = ctx.upload(prob)
+    try:
+        H, S, E, c, rep = up.solve(chi=prob.chi)
+        Hm, Sm, Em, cm, repm = up.solve(chi=prob.chi, precision="mixed")
+    finally:
+        up.free()
+    print(f"mixed: {repm['n_fp32_pairs']} FP32 pairs, dE={abs(Em - E):.2e}", flush=True)
+    assert repm["n_fp32_pairs"] > 0
+    assert abs(Em - E) <= 1e-6
+    # FP64 pairs (the diagonal) agree to the FP64 tolerance, FP32 ones to FP32 rounding
+    np.testing.assert_allclose(np.diag(Hm), np.diag(H), rtol=1e-12)
+    np.testing.assert_allclose(Sm, S, rtol=1e-4, atol=0)
+    np.testing.assert_allclose(Hm, H, rtol=1e-4, atol=0)
