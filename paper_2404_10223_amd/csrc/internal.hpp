@@ -153,32 +153,34 @@ void launch_env_gd(const EnvGD *d, int ndesc, int ntiles, int tileM, int tileN, 
                    const T *const *vals, const T *const *X, T *const *Y, int npair, hipStream_t st);
 
 // channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k]
-struct MixSrc {
+struct MixSrc {        // host-side bookkeeping of a task's sources
   int64_t offX;        // X block [da][nw_in][db]
   int nw_in;
-  int group;           // index into the site's CSR groups
+  int group;           // index into the site's MPO groups
   double factor;       // local-operator matrix element
+};
+// one coupling of an output channel row: Y[a][w'][b] += factor * vals[val] * X[offX + (a nw_in + col) db + b]
+struct MixEnt {
+  int64_t offX;
+  int nw_in, col;
+  int64_t val;         // index of the MPO coefficient in one basis' value array
+  double factor;
 };
 struct MixTask {
   int64_t offY;        // Y block [da][nw_out][db], da = dim_bra(x, sa), db = dim_ket(x + 1, s)
   int x, sa, s, nw_out;
-  int src0, nsrc;      // range in the MixSrc array
+  int src0, nsrc;      // host bookkeeping: range in the MixSrc array
+  int row0;            // first of the nw_out + 1 entry offsets of this task's rows
 };
-struct CsrGroup {
-  int64_t rowptr;      // offset into the rowptr array (nw_out + 1 entries)
-  int64_t col;         // offset into the col array
-  int64_t val;         // offset of the group's values in one basis' value array
-};
-
 struct MixArgs {
   const MixTask *tasks;
-  const int *task_chunk0;   // first 256-element chunk of each task (prefix, ntask + 1)
+  const int *task_chunk0;   // first 256-item chunk of each task
+  const int *chunk_task;    // task of each chunk
   int ntask, nchunk;
-  const MixSrc *src;
-  const CsrGroup *groups;
-  const int *rowptr, *col;
+  const int *rowptr;        // entry offsets per task row (see MixTask::row0)
+  const MixEnt *ents;
   const double *vals;       // [basis][nnz of all sites]
-  int64_t basis_stride, site_off;
+  int64_t basis_stride;
   const int *basis;         // [pair]
 };
 template <typename T>

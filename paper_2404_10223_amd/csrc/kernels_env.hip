@@ -243,37 +243,38 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, E
 }
 
 // ------------------------------------------------------------------ channel mix
-// Y[a][w'][b] = sum_src f_src sum_{(w', c) in CSR} v[w'][c] X_src[a][c][b],
-// one output element per thread (32-bit index arithmetic within a task).
+// Y[a][w'][b] = sum over the couplings of row w' of factor * v * X[a][c][b].
+// A thread takes four consecutive b of one row (a, w'); the couplings of the
+// row are a short list shared by all threads of the row.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
   const int pair = blockIdx.y;
-  int lo = 0, hi = a.ntask - 1;
   const int chunk = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.task_chunk0[mid] <= chunk) lo = mid; else hi = mid - 1;
-  }
-  const MixTask tk = a.tasks[lo];
+  const int ti = a.chunk_task[chunk];
+  const MixTask tk = a.tasks[ti];
   const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
-  const int e = (chunk - a.task_chunk0[lo]) * 256 + threadIdx.x;
-  if (e >= da * tk.nw_out * db) return;
-  const int rowi = e / db;
-  const int b = e - rowi * db;
-  const int ap = rowi / tk.nw_out, w = rowi - ap * tk.nw_out;
-  const double *vals = a.vals + a.basis[pair] * a.basis_stride + a.site_off;
+  const int qpr = (db + 3) >> 2;
+  const int item = (chunk - a.task_chunk0[ti]) * 256 + threadIdx.x;
+  if (item >= da * tk.nw_out * qpr) return;
+  const int row = item / qpr, b0 = (item - row * qpr) * 4;
+  const int ap = row / tk.nw_out, w = row - ap * tk.nw_out;
+  const int e0 = a.rowptr[tk.row0 + w], e1 = a.rowptr[tk.row0 + w + 1];
+  const double *vals = a.vals + a.basis[pair] * a.basis_stride;
   const T *Xp = X[pair];
-  double acc = 0.0;
-  for (int si = 0; si < tk.nsrc; ++si) {
-    const MixSrc s = a.src[tk.src0 + si];
-    const CsrGroup cg = a.groups[s.group];
-    const int r0 = a.rowptr[cg.rowptr + w], r1 = a.rowptr[cg.rowptr + w + 1];
-    const T *xb = Xp + s.offX + (int64_t)(ap * s.nw_in) * db + b;
-    double part = 0.0;
-    for (int z = r0; z < r1; ++z) part += vals[cg.val + z] * (double)xb[(int64_t)a.col[cg.col + z] * db];
-    acc += s.factor * part;
+  const int nb = min(4, db - b0);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = e0; e < e1; ++e) {
+    const MixEnt en = a.ents[e];
+    const double cf = en.factor * vals[en.val];
+    const T *xr = Xp + en.offX + ((int64_t)ap * en.nw_in + en.col) * db + b0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nb) acc[j] += cf * (double)xr[j];
   }
-  Y[pair][tk.offY + e] = (T)acc;
+  T *yr = Y[pair] + tk.offY + ((int64_t)ap * tk.nw_out + w) * db + b0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j < nb) yr[j] = (T)acc[j];
 }
 
 template <typename T>
