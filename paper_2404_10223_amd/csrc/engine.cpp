@@ -80,6 +80,73 @@ void DevicePool::trim() {
   held_ = 0;
 }
 
+ThreadPool::ThreadPool(int workers) {
+  for (int i = 0; i < workers; ++i)
+    threads_.emplace_back([this] {
+      unsigned long long seen = 0;
+      for (;;) {
+        const std::function<void(int)> *f;
+        int n;
+        {
+          std::unique_lock<std::mutex> lk(m_);
+          cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+          if (stop_) return;
+          seen = gen_;
+          f = job_;
+          n = n_;
+          ++busy_;
+        }
+        work(f, n);
+        std::lock_guard<std::mutex> lk(m_);
+        if (--busy_ == 0) done_cv_.notify_all();
+      }
+    });
+}
+
+ThreadPool::~ThreadPool() {
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto &t : threads_) t.join();
+}
+
+void ThreadPool::work(const std::function<void(int)> *f, int n) {
+  for (;;) {
+    const int i = next_.fetch_add(1);
+    if (i >= n) return;
+    try {
+      (*f)(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(m_);
+      if (!err_) err_ = std::current_exception();
+    }
+  }
+}
+
+void ThreadPool::parallel_for(int n, const std::function<void(int)> &f) {
+  if (n <= 0) return;
+  if (threads_.empty() || n == 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    job_ = &f;
+    n_ = n;
+    next_.store(0);
+    err_ = nullptr;
+    ++gen_;
+  }
+  cv_.notify_all();
+  work(&f, n);
+  std::unique_lock<std::mutex> lk(m_);
+  done_cv_.wait(lk, [&] { return busy_ == 0 && next_.load() >= n_; });
+  job_ = nullptr;
+  if (err_) std::rethrow_exception(err_);
+}
+
 Staging::~Staging() {
   if (buf_) (void)hipHostFree(buf_);
   for (auto &o : old_) (void)hipHostFree(o.first);
@@ -395,6 +462,14 @@ bool debug_timing() {
   return on;
 }
 
+ThreadPool &host_pool(tnqe_ctx *ctx) {
+  if (!ctx->pool_threads) {
+    const int hw = (int)std::thread::hardware_concurrency();
+    ctx->pool_threads = std::make_unique<ThreadPool>(std::max(0, std::min(15, hw - 1)));
+  }
+  return *ctx->pool_threads;
+}
+
 // Device time of timed SVD launches (per kernel), collected after the next
 // stream sync.
 struct SvdTimer {
@@ -707,12 +782,13 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   const auto ts1 = Clock::now();
   ts.svd.collect(c.ctx);
   // global top-chi per ket: the `keep` largest singular values, ties taken in
-  // block order (lower index first)
+  // block order (lower index first); kets in parallel on the host workers
   std::vector<std::vector<int>> per(ks.n);
   for (size_t i = 0; i < blks.size(); ++i) per[blks[i].pair].push_back((int)i);
-  std::vector<double> vals, tmp;
-  for (int t = 0; t < ks.n; ++t) {
-    vals.clear();
+  std::vector<double> gap_t(ks.n, 1.0);
+  std::vector<int> keep_t(ks.n, 0);
+  host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
+    std::vector<double> vals, tmp;
     double tot = 0.0;
     for (int bi : per[t]) {
       const Blk &b = blks[bi];
@@ -735,7 +811,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
       std::nth_element(tmp.begin(), tmp.begin() + (keep - 1), tmp.end(), std::greater<double>());
       th = tmp[keep - 1];
       const double so = *std::max_element(tmp.begin() + keep, tmp.end());
-      if (th > 0.0) ts.min_gap = std::min(ts.min_gap, (th - so) / th);
+      if (th > 0.0) gap_t[t] = (th - so) / th;
       int gt = 0;
       for (double v : vals) gt += v > th ? 1 : 0;
       need_eq = keep - gt;
@@ -758,7 +834,11 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
       b.kept = k;
     }
     ts.discarded[t] += disc;
-    ts.max_bond = std::max(ts.max_bond, keep);
+    keep_t[t] = keep;
+  });
+  for (int t = 0; t < ks.n; ++t) {
+    ts.min_gap = std::min(ts.min_gap, gap_t[t]);
+    ts.max_bond = std::max(ts.max_bond, keep_t[t]);
   }
   const auto ts2 = Clock::now();
   if (debug_timing()) {
@@ -898,9 +978,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     Lsize[b] = o;
   }
-  // global CSR group index base per site
-  std::vector<int> gbase(N + 1, 0);
-  for (int x = 0; x < N; ++x) gbase[x + 1] = gbase[x] + (int)mpo.groups[x].size();
   struct SiteTabs {
     std::vector<EnvG1> g1;
     std::vector<EnvG2> g2;
@@ -908,15 +985,18 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     std::vector<std::vector<EnvGD>> dense;   // dense channel mixing, one level per launch
     std::vector<int> td, tmd, tnd;
     std::vector<MixTask> tasks;
-    std::vector<int> chunk0;
+    std::vector<int> chunk0, chunk_task;
     std::vector<MixSrc> srcs;
     std::vector<int> src_nnz;                // stored couplings of each source (work count)
+    std::vector<int> mrow;                   // entry offsets of every task row
+    std::vector<MixEnt> ents;
     int nchunk = 0;
     int64_t Xsize = 0, Ysize = 0;
     std::vector<EnvFinal> fin;
   };
   std::vector<SiteTabs> tabs(N);
-  for (int x = 0; x < N; ++x) {
+  // sites are independent: their tables are built on the host workers
+  host_pool(c.ctx).parallel_for(N, [&](int x) {
     SiteTabs &tb = tabs[x];
     // GEMM1 and X slots
     std::vector<int64_t> offX(cls[x].size() * nslot * 4, -1);
@@ -1002,7 +1082,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               MixSrc sr{};
               sr.offX = ox;
               sr.nw_in = cls[x][g.cin].nw;
-              sr.group = gbase[x] + (int)gi;
+              sr.group = (int)gi;
               sr.factor = P.f[e];
               tb.srcs.push_back(sr);
               tb.src_nnz.push_back((int)g.col.size());
@@ -1010,6 +1090,25 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           }
           tk.nsrc = (int)tb.srcs.size() - tk.src0;
           if (tk.nsrc == 0 && dsrc.empty()) continue;
+          // the couplings of every output row, gathered from the sources' CSR rows
+          tk.row0 = (int)tb.mrow.size();
+          for (int w = 0; w < tk.nw_out; ++w) {
+            tb.mrow.push_back((int)tb.ents.size());
+            for (int si = tk.src0; si < tk.src0 + tk.nsrc; ++si) {
+              const MixSrc &sr = tb.srcs[si];
+              const MpoGroup &gg = mpo.groups[x][sr.group];
+              for (int z = gg.rowptr[w]; z < gg.rowptr[w + 1]; ++z) {
+                MixEnt en{};
+                en.offX = sr.offX;
+                en.nw_in = sr.nw_in;
+                en.col = gg.col[z];
+                en.val = mpo.site_nnz_off[x] + gg.val_off + z;
+                en.factor = sr.factor;
+                tb.ents.push_back(en);
+              }
+            }
+          }
+          tb.mrow.push_back((int)tb.ents.size());
           tk.offY = yo;
           offY[(co * nslot + s) * 4 + kp] = yo;
           const int64_t tot = (int64_t)dpad[x][s_a] * tk.nw_out * dpad[x + 1][s];
@@ -1036,7 +1135,10 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
             tb.dense[q].push_back(d);
           }
           tb.chunk0.push_back(tb.nchunk);
-          tb.nchunk += (int)((tot + 255) / 256);
+          const int64_t items = (int64_t)dpad[x][s_a] * tk.nw_out * ((dpad[x + 1][s] + 3) / 4);
+          const int nch = (int)((items + 255) / 256);
+          for (int q = 0; q < nch; ++q) tb.chunk_task.push_back((int)tb.tasks.size());
+          tb.nchunk += nch;
           tb.tasks.push_back(tk);
         }
       }
@@ -1107,7 +1209,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         tb.fin.push_back(f);
       }
     }
-  }
+  });
   // ---- algorithmic work with every pair's own block shapes (on a host
   // thread, overlapping the sweeps)
   const double eb = sizeof(T);
@@ -1162,19 +1264,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     }
   } join_guard{work_thread};
   // ---- device tables
-  std::vector<int> rowptr;
-  std::vector<int> col;
-  std::vector<CsrGroup> groups;
-  for (int x = 0; x < N; ++x)
-    for (const MpoGroup &g : mpo.groups[x]) {
-      CsrGroup cg;
-      cg.rowptr = (int64_t)rowptr.size();
-      cg.col = (int64_t)col.size();
-      cg.val = mpo.site_nnz_off[x] + g.val_off;
-      rowptr.insert(rowptr.end(), g.rowptr.begin(), g.rowptr.end());
-      col.insert(col.end(), g.col.begin(), g.col.end());
-      groups.push_back(cg);
-    }
   require(mpo.site_nnz_off[N] == nnz_total, TNQE_EINVAL, "MPO value layout mismatch");
   // coefficient values in the environment precision for the dense mixing GEMMs
   const T *dvalsT = reinterpret_cast<const T *>(dvals);
@@ -1185,9 +1274,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     std::vector<T> hf(h.begin(), h.end());
     dvalsT = c.upload(hf);
   }
-  const int *d_rowptr = c.upload(rowptr);
-  const int *d_col = c.upload(col);
-  const CsrGroup *d_groups = c.upload(groups);
   const int2 *d_itab = c.upload(itab);
   const int *d_iD = c.upload(iD);
   struct DevSite {
@@ -1195,8 +1281,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     EnvG1 *g1;
     EnvG2 *g2;
     MixTask *tasks;
-    int *chunk0;
-    MixSrc *srcs;
+    int *chunk0, *chunk_task, *mrow;
+    MixEnt *ents;
     EnvFinal *fin;
   };
   std::vector<DevSite> ds(N);
@@ -1209,7 +1295,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     std::vector<int> ch = tabs[x].chunk0;
     ch.push_back(tabs[x].nchunk);
     ds[x].chunk0 = c.upload(ch);
-    ds[x].srcs = c.upload(tabs[x].srcs);
+    ds[x].chunk_task = c.upload(tabs[x].chunk_task);
+    ds[x].mrow = c.upload(tabs[x].mrow);
+    ds[x].ents = c.upload(tabs[x].ents);
     ds[x].fin = c.upload(tabs[x].fin);
     for (auto &lv : tabs[x].dense) ds[x].dense.push_back(c.upload(lv));
     Xmax = std::max(Xmax, tabs[x].Xsize);
@@ -1283,15 +1371,13 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       MixArgs ma{};
       ma.tasks = ds[x].tasks;
       ma.task_chunk0 = ds[x].chunk0;
+      ma.chunk_task = ds[x].chunk_task;
       ma.ntask = (int)tb.tasks.size();
       ma.nchunk = tb.nchunk;
-      ma.src = ds[x].srcs;
-      ma.groups = d_groups;
-      ma.rowptr = d_rowptr;
-      ma.col = d_col;
+      ma.rowptr = ds[x].mrow;
+      ma.ents = ds[x].ents;
       ma.vals = dvals;
       ma.basis_stride = nnz_total;
-      ma.site_off = 0;
       ma.basis = dbasis;
       tick(kEnvMix);
       launch_mix<T>(ma, geom, dX, dY, nb_, st);

@@ -3,9 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -53,6 +58,28 @@ class Staging {
   size_t cap_ = 0, used_ = 0;
 };
 
+// Persistent host worker threads for the per-ket loops of the gate phase.
+class ThreadPool {
+ public:
+  explicit ThreadPool(int workers);
+  ~ThreadPool();
+  // f(i) for i in [0, n) on the workers and the calling thread; returns when
+  // all calls are done; the first exception thrown by f is rethrown here
+  void parallel_for(int n, const std::function<void(int)> &f);
+
+ private:
+  void work(const std::function<void(int)> *f, int n);
+  std::vector<std::thread> threads_;
+  std::mutex m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)> *job_ = nullptr;
+  int n_ = 0, busy_ = 0;
+  unsigned long long gen_ = 0;
+  bool stop_ = false;
+  std::atomic<int> next_{0};
+  std::exception_ptr err_;
+};
+
 }  // namespace tnqe
 
 struct tnqe_ctx {
@@ -70,6 +97,7 @@ struct tnqe_ctx {
   hipStream_t aux[kAux] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kAux] = {};
   std::vector<hipEvent_t> env_ev;   // per-launch timing of the environment kernels (grown on demand)
+  std::unique_ptr<tnqe::ThreadPool> pool_threads;   // created on first use
 };
 
 struct tnqe_problem {
