@@ -21,6 +21,63 @@ __device__ inline int seg_of(const int *s, int x) {
   return k;
 }
 
+// All 64 x 64 tiles of an M x N product C = A B for one workgroup (4 x 4 per
+// thread, K through LDS in steps of 16); la(m, k) and lb(k, n) load operands,
+// sc(m, n, v) stores.  A tiles are filled with k fastest; B tiles with k
+// fastest when BK (B contiguous along k), else with n fastest.
+template <bool BK, class LA, class LB, class SC>
+__device__ void block_gemm(int M, int N, int K, LA la, LB lb, SC sc) {
+  constexpr int TT = 64, KC = 16;
+  __shared__ double sA[KC][TT + 1];
+  __shared__ double sB[KC][TT + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tilesN = (N + TT - 1) / TT, ntile = ((M + TT - 1) / TT) * tilesN;
+  for (int tile = 0; tile < ntile; ++tile) {
+    const int m0 = (tile / tilesN) * TT, n0 = (tile % tilesN) * TT;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
+        const int kk = e % KC, mm = e / KC;
+        const int gm = m0 + mm, gk = k0 + kk;
+        sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : 0.0;
+        if (BK) {
+          const int gn = n0 + mm;
+          sB[kk][mm] = (gn < N && gk < K) ? lb(gk, gn) : 0.0;
+        } else {
+          const int nn = e % TT, kb = e / TT;
+          const int gn = n0 + nn, gkb = k0 + kb;
+          sB[kb][nn] = (gn < N && gkb < K) ? lb(gkb, gn) : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = sA[kk][ty + 16 * u];
+          bv[u] = sB[kk][tx + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gm = m0 + ty + 16 * u;
+      if (gm >= M) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gn = n0 + tx + 16 * v;
+        if (gn < N) sc(gm, gn, acc[u][v]);
+      }
+    }
+  }
+}
+
 // Two-site product per old middle sector ms = (sa, sb) of bond a+1:
 // Theta[(k1, l)][(k2, r)] = sum_m A_a[l, k1, m] A_{a+1}[m, k2, r], with l in
 // the left sector ms - q(k1) and r in the right sector ms + q(k2).  A tiled
@@ -229,16 +286,16 @@ __global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, cons
     const double s = S[jj];
     A[((int64_t)(b.j0 + jj) * 4 + k) * Dr + r] = s > 0.0 ? Bo[(int64_t)jj * b.C + col] / s : 0.0;
   }
+  // P[(l, k)][j0 + jj] = S[jj] sum_mm Po[(l, k)][aux0 + mm] U[jj][mm], one product per k
   for (int k = 0; k < 4; ++k) {
     const int2 ls = kt.sec(q - 1, pair, b.sa - qk_a(k), b.sb - qk_b(k));
-    for (int64_t e = threadIdx.x; e < (int64_t)ls.y * n; e += kThreads) {
-      const int li = e / n, jj = e - (int64_t)li * n;
-      const double *prow = Po + ((int64_t)(ls.x + li) * 4 + k) * Dold + b.aux0;
-      double acc = 0.0;
-      const double *ucol = U + (int64_t)jj * b.R;
-      for (int mm = 0; mm < b.R; ++mm) acc += prow[mm] * ucol[mm];
-      P[((int64_t)(ls.x + li) * 4 + k) * Dn + b.j0 + jj] = acc * S[jj];
-    }
+    const double *Pk = Po + ((int64_t)ls.x * 4 + k) * Dold + b.aux0;
+    double *Ck = P + ((int64_t)ls.x * 4 + k) * Dn + b.j0;
+    const int R = b.R;
+    block_gemm<true>(
+        ls.y, n, R, [&](int li, int mm) { return Pk[(int64_t)li * 4 * Dold + mm]; },
+        [&](int mm, int jj) { return U[(int64_t)jj * R + mm]; },
+        [&](int li, int jj, double v) { Ck[(int64_t)li * 4 * Dn + jj] = v * S[jj]; });
   }
 }
 
@@ -283,13 +340,14 @@ __global__ void __launch_bounds__(kThreads) k_apply_qr(KetTables kt, int p, cons
     const int l = kt.sec(p, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x + (row - b.rs[k]);
     A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)jj * b.R + row];
   }
-  const int W = 4 * Drr;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * W; e += kThreads) {
-    const int jj = e / W, x = e - (int64_t)jj * W;
-    double acc = 0.0;
-    for (int mm = 0; mm < b.C; ++mm) acc += Bo[(int64_t)jj * b.C + mm] * No[(int64_t)(b.aux0 + mm) * W + x];
-    Nx[(int64_t)(b.j0 + jj) * W + x] = acc;
-  }
+  // Nx[j0 + jj][x] = sum_mm B[jj][mm] No[aux0 + mm][x]
+  const int W = 4 * Drr, Cb = b.C;
+  const double *Nb = No + (int64_t)b.aux0 * W;
+  double *Cn = Nx + (int64_t)b.j0 * W;
+  block_gemm<false>(
+      n, W, Cb, [&](int jj, int mm) { return Bo[(int64_t)jj * Cb + mm]; },
+      [&](int mm, int x) { return Nb[(int64_t)mm * W + x]; },
+      [&](int jj, int x, double v) { Cn[(int64_t)jj * W + x] = v; });
 }
 
 __global__ void k_copy(double *const *dst, double *const *src, const int64_t *count) {
