@@ -73,6 +73,23 @@ def roofline(rep):
     return out
 
 
+def kernel_breakdown(rep):
+    """Device time, launches and algorithmic rates of every timed kernel kind."""
+    out = []
+    for k, name in enumerate(SVD_KERNELS):
+        if name and rep["svd_kind_launches"][k] > 0:
+            ms, fl = rep["svd_kind_ms"][k], rep["svd_kind_flops"][k]
+            out.append({"kernel": name, "ms": ms, "launches": rep["svd_kind_launches"][k],
+                        "tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None})
+    for k, name in enumerate(ENV_KERNELS):
+        if name and rep["env_kind_launches"][k] > 0:
+            ms, fl, by = rep["env_kind_ms"][k], rep["env_kind_flops"][k], rep["env_kind_bytes"][k]
+            out.append({"kernel": name, "ms": ms, "launches": rep["env_kind_launches"][k],
+                        "tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
+                        "gbs": by / (ms * 1e-3) / 1e9 if ms > 0 else None})
+    return sorted(out, key=lambda x: -x["ms"])
+
+
 def source_digest(kernel):
     import hashlib
     for prefix, f in KERNEL_SOURCE.items():
@@ -211,7 +228,7 @@ def main():
                                                    "max_discarded_weight_sum", "min_rel_gap", "max_bond",
                                                    "svd_kernel_ms", "svd_flops", "env_kernel_ms", "env_flops",
                                                    "alg_bytes")},
-            "mixed": mixed, "roofline": roof, "cpu_baseline": cpu}
+            "mixed": mixed, "roofline": roof, "kernels": kernel_breakdown(rep), "cpu_baseline": cpu}
     up.free()
     ctx.close()
     print(json.dumps(line))

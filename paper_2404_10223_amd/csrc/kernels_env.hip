@@ -12,6 +12,8 @@
 // outside them.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace tnqe {
@@ -25,11 +27,93 @@ struct Seg {
   int K, lda, ldb, transA;   // A[m*lda + k] (transA 0) or A[k*lda + m]; B[k*ldb + n]
 };
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// FP64 matrix-core tile: the TM x TN tile (m0, n0) of sum over segments of
+// A_q B_q, 256 threads = 4 waves, each wave a (TM / WM) x (TN / WN) sub-tile
+// of 16 x 16 blocks accumulated by v_mfma_f64_16x16x4f64; K staged through
+// LDS in chunks of 16.  Operand layout of the instruction (one double per
+// lane): A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k; lane
+// j + 16 q holds D[4 r + q][j] in element r.  la(q, m, k) / lb(q, k, n) load
+// the operands of segment q (K of segment q: kq(q)); sc(m, n, v) stores.
+template <int TM, int TN, int NSEG, class KQ, class LA, class LB, class SC>
+__device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA la, LB lb, SC sc) {
+  constexpr int KC = 16;
+  constexpr int WM = TM == TN ? 2 : (TM > TN ? 4 : 1), WN = 4 / WM;
+  constexpr int SM = TM / WM, SN = TN / WN, BI = SM / 16, BJ = SN / 16;
+  static_assert(BI >= 1 && BJ >= 1 && SM % 16 == 0 && SN % 16 == 0, "tile");
+  __shared__ double sA[KC][TM + 1];
+  __shared__ double sB[KC][TN + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave / WN) * SM, wn = (wave % WN) * SN;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NSEG; ++q) {
+    if (q >= nseg) break;
+    const int K = kq(q);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      for (int e = threadIdx.x; e < KC * TM; e += 256) {
+        const int kk = e % KC, mm = e / KC;
+        const int gm = m0 + mm, gk = k0 + kk;
+        sA[kk][mm] = (gm < M && gk < K) ? la(q, gm, gk) : 0.0;
+      }
+      for (int e = threadIdx.x; e < KC * TN; e += 256) {
+        const int kk = e / TN, nn = e % TN;
+        const int gn = n0 + nn, gk = k0 + kk;
+        sB[kk][nn] = (gn < N && gk < K) ? lb(q, gk, gn) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 4) {
+        double a[BI], b[BJ];
+#pragma unroll
+        for (int i = 0; i < BI; ++i) a[i] = sA[ks + lk][wm + 16 * i + li];
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) b[j] = sB[ks + lk][wn + 16 * j + li];
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
+        if (gm < M && gn < N) sc(gm, gn, acc[i][j][r]);
+      }
+}
+
 // C tile (m0, n0) of sum_seg op(A) B: 256 threads, an RM x RN micro-tile
 // each, K staged through LDS in chunks of KC.  C = alpha * sum (+ C if beta).
+// FP64 tiles run on the matrix cores (tile_gemm_mfma).
 template <typename T, int TM, int TN, int RM, int RN, int NSEG>
 __device__ void tile_gemm(int M, int N, int m0, int n0, const Seg<T> (&sg)[NSEG], int nseg, T *C, int ldc,
                           T alpha, int beta) {
+  if constexpr (std::is_same<T, double>::value) {
+    tile_gemm_mfma<TM, TN, NSEG>(
+        M, N, m0, n0, nseg, [&](int q) { return sg[q].K; },
+        [&](int q, int m, int k) {
+          const Seg<T> &s = sg[q];
+          return s.transA ? s.A[(int64_t)k * s.lda + m] : s.A[(int64_t)m * s.lda + k];
+        },
+        [&](int q, int k, int n) { return sg[q].B[(int64_t)k * sg[q].ldb + n]; },
+        [&](int m, int n, double v) {
+          T *c = C + (int64_t)m * ldc + n;
+          *c = beta ? *c + alpha * v : alpha * v;
+        });
+    return;
+  }
   constexpr int KC = 16;
   constexpr int TX = TN / RN;
   static_assert((TM / RM) * (TN / RN) == 256, "tile");
@@ -162,6 +246,12 @@ __global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, int ndesc, E
 // accumulating store; same tiling as tile_gemm.
 template <typename T, int TM, int TN, int RM, int RN, class LA, class LB, class SC>
 __device__ void tile_gemm_f(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc) {
+  if constexpr (std::is_same<T, double>::value) {
+    tile_gemm_mfma<TM, TN, 1>(
+        M, N, m0, n0, 1, [&](int) { return K; }, [&](int, int m, int k) { return la(m, k); },
+        [&](int, int k, int n) { return lb(k, n); }, sc);
+    return;
+  }
   constexpr int KC = 16;
   constexpr int TX = TN / RN;
   static_assert((TM / RM) * (TN / RN) == 256, "tile");
