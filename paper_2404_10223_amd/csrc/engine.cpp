@@ -981,16 +981,14 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   struct SiteTabs {
     std::vector<EnvG1> g1;
     std::vector<EnvG2> g2;
-    int t1 = 0, t2 = 0, tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
+    int tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
     std::vector<std::vector<EnvGD>> dense;   // dense channel mixing, one level per launch
-    std::vector<int> td, tmd, tnd;
+    std::vector<int> tmd, tnd;
     std::vector<MixTask> tasks;
-    std::vector<int> chunk0, chunk_task;
     std::vector<MixSrc> srcs;
     std::vector<int> src_nnz;                // stored couplings of each source (work count)
     std::vector<int> mrow;                   // entry offsets of every task row
     std::vector<MixEnt> ents;
-    int nchunk = 0;
     int64_t Xsize = 0, Ysize = 0;
     std::vector<EnvFinal> fin;
   };
@@ -1030,12 +1028,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     tb.Xsize = xo;
     pick_tile(maxM1, maxN1, true, tb.tm1, tb.tn1);
-    for (EnvG1 &d : tb.g1) {
-      d.tile0 = tb.t1;
-      d.tilesM = (dpad[x][d.sbra] * d.nw + tb.tm1 - 1) / tb.tm1;
-      d.tilesN = (dpad[x + 1][d.sk] + tb.tn1 - 1) / tb.tn1;
-      tb.t1 += d.tilesM * d.tilesN;
-    }
     // mix tasks and Y slots
     std::vector<int64_t> offY(cls[x + 1].size() * nslot * 4, -1);
     int64_t yo = 0;
@@ -1134,11 +1126,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
             if (tb.dense.size() <= q) tb.dense.resize(q + 1);
             tb.dense[q].push_back(d);
           }
-          tb.chunk0.push_back(tb.nchunk);
-          const int64_t items = (int64_t)dpad[x][s_a] * tk.nw_out * ((dpad[x + 1][s] + 3) / 4);
-          const int nch = (int)((items + 255) / 256);
-          for (int q = 0; q < nch; ++q) tb.chunk_task.push_back((int)tb.tasks.size());
-          tb.nchunk += nch;
           tb.tasks.push_back(tk);
         }
       }
@@ -1150,15 +1137,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         maxM = std::max(maxM, d.nr);
         maxN = std::max(maxN, dpad[x][d.sa] * dpad[x + 1][d.s]);
       }
-      int tm, tn, nt = 0;
+      int tm, tn;
       pick_tile(maxM, maxN, false, tm, tn);
-      for (auto &d : lv) {
-        d.tile0 = nt;
-        d.tilesM = (d.nr + tm - 1) / tm;
-        d.tilesN = (dpad[x][d.sa] * dpad[x + 1][d.s] + tn - 1) / tn;
-        nt += d.tilesM * d.tilesN;
-      }
-      tb.td.push_back(nt);
       tb.tmd.push_back(tm);
       tb.tnd.push_back(tn);
     }
@@ -1190,12 +1170,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           tb.g2.push_back(d);
         }
       pick_tile(maxM2, maxN2, false, tb.tm2, tb.tn2);
-      for (EnvG2 &d : tb.g2) {
-        d.tile0 = tb.t2;
-        d.tilesM = (dpad[x + 1][d.sbn] + tb.tm2 - 1) / tb.tm2;
-        d.tilesN = (d.nw * dpad[x + 1][d.s] + tb.tn2 - 1) / tb.tn2;
-        tb.t2 += d.tilesM * d.tilesN;
-      }
     } else {
       const int sN = slot_of(pb.na, pb.nb);
       const int co = mpo.final_class;
@@ -1281,7 +1255,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     EnvG1 *g1;
     EnvG2 *g2;
     MixTask *tasks;
-    int *chunk0, *chunk_task, *mrow;
+    int *mrow;
     MixEnt *ents;
     EnvFinal *fin;
   };
@@ -1292,10 +1266,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     ds[x].g1 = c.upload(tabs[x].g1);
     ds[x].g2 = c.upload(tabs[x].g2);
     ds[x].tasks = c.upload(tabs[x].tasks);
-    std::vector<int> ch = tabs[x].chunk0;
-    ch.push_back(tabs[x].nchunk);
-    ds[x].chunk0 = c.upload(ch);
-    ds[x].chunk_task = c.upload(tabs[x].chunk_task);
     ds[x].mrow = c.upload(tabs[x].mrow);
     ds[x].ents = c.upload(tabs[x].ents);
     ds[x].fin = c.upload(tabs[x].fin);
@@ -1345,6 +1315,70 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       dbra[x] = c.upload(bp);
       dket[x] = c.upload(kp);
     }
+    // work lists of the batch: only the tiles (chunks) inside every pair's
+    // own extents; sites in parallel on the host workers
+    struct SiteWork {
+      std::vector<EnvWork> g1, mix, g2;
+      std::vector<std::vector<EnvWork>> dense;
+      int n1 = 0, nmix = 0, n2 = 0;
+      std::vector<int> nd;
+    };
+    std::vector<SiteWork> sw(N);
+    host_pool(c.ctx).parallel_for(N, [&](int x) {
+      const SiteTabs &tb = tabs[x];
+      SiteWork &w = sw[x];
+      auto add = [](std::vector<EnvWork> &list, int &nwg, int desc, int q, int64_t cnt) {
+        if (cnt <= 0) return;
+        require(nwg + cnt < (int64_t)1 << 31, TNQE_ESHAPE, "environment launch exceeds the grid limit");
+        list.push_back(EnvWork{desc, q, nwg});
+        nwg += (int)cnt;
+      };
+      auto tiles = [](int64_t M, int64_t Nn, int tm, int tn) {
+        return (M <= 0 || Nn <= 0) ? (int64_t)0 : ((M + tm - 1) / tm) * ((Nn + tn - 1) / tn);
+      };
+      for (size_t di = 0; di < tb.g1.size(); ++di) {
+        const EnvG1 &d = tb.g1[di];
+        for (int q = 0; q < nb_; ++q)
+          add(w.g1, w.n1, (int)di, q,
+              tiles((int64_t)idim(bra_item[q], x, d.sbra) * d.nw, idim(ket_item[q], x + 1, d.sk), tb.tm1, tb.tn1));
+      }
+      for (size_t ti = 0; ti < tb.tasks.size(); ++ti) {
+        const MixTask &tk = tb.tasks[ti];
+        for (int q = 0; q < nb_; ++q) {
+          const int64_t items =
+              (int64_t)idim(bra_item[q], x, tk.sa) * tk.nw_out * ((idim(ket_item[q], x + 1, tk.s) + 3) / 4);
+          add(w.mix, w.nmix, (int)ti, q, (items + 255) / 256);
+        }
+      }
+      w.dense.resize(tb.dense.size());
+      w.nd.assign(tb.dense.size(), 0);
+      for (size_t lv = 0; lv < tb.dense.size(); ++lv)
+        for (size_t di = 0; di < tb.dense[lv].size(); ++di) {
+          const EnvGD &d = tb.dense[lv][di];
+          for (int q = 0; q < nb_; ++q)
+            add(w.dense[lv], w.nd[lv], (int)di, q,
+                tiles(d.nr, (int64_t)idim(bra_item[q], x, d.sa) * idim(ket_item[q], x + 1, d.s), tb.tmd[lv],
+                      tb.tnd[lv]));
+        }
+      for (size_t di = 0; di < tb.g2.size(); ++di) {
+        const EnvG2 &d = tb.g2[di];
+        for (int q = 0; q < nb_; ++q)
+          add(w.g2, w.n2, (int)di, q,
+              tiles(idim(bra_item[q], x + 1, d.sbn), (int64_t)d.nw * idim(ket_item[q], x + 1, d.s), tb.tm2,
+                    tb.tn2));
+      }
+    });
+    struct DevWork {
+      const EnvWork *g1, *mix, *g2;
+      std::vector<const EnvWork *> dense;
+    };
+    std::vector<DevWork> dw(N);
+    for (int x = 0; x < N; ++x) {
+      dw[x].g1 = c.upload(sw[x].g1);
+      dw[x].mix = c.upload(sw[x].mix);
+      dw[x].g2 = c.upload(sw[x].g2);
+      for (auto &lv : sw[x].dense) dw[x].dense.push_back(c.upload(lv));
+    }
     std::vector<const double *> bra64(nb_);
     for (int q = 0; q < nb_; ++q) bra64[q] = site64[(size_t)bra_item[q] * N + N - 1];
     const double *const *dbra64 = c.upload(bra64);
@@ -1366,29 +1400,29 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     T **Lc = dL0, **Ln = dL1;
     for (int x = 0; x < N; ++x) {
       const SiteTabs &tb = tabs[x];
+      const SiteWork &w = sw[x];
       tick(kEnvG1);
-      launch_env_g1<T>(ds[x].g1, (int)tb.g1.size(), tb.t1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, nb_, st);
+      launch_env_g1<T>(ds[x].g1, dw[x].g1, (int)w.g1.size(), w.n1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, st);
       MixArgs ma{};
       ma.tasks = ds[x].tasks;
-      ma.task_chunk0 = ds[x].chunk0;
-      ma.chunk_task = ds[x].chunk_task;
-      ma.ntask = (int)tb.tasks.size();
-      ma.nchunk = tb.nchunk;
+      ma.work = dw[x].mix;
+      ma.nwork = (int)w.mix.size();
+      ma.nchunk = w.nmix;
       ma.rowptr = ds[x].mrow;
       ma.ents = ds[x].ents;
       ma.vals = dvals;
       ma.basis_stride = nnz_total;
       ma.basis = dbasis;
       tick(kEnvMix);
-      launch_mix<T>(ma, geom, dX, dY, nb_, st);
+      launch_mix<T>(ma, geom, dX, dY, st);
       for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
         tick(kEnvDense);
-        launch_env_gd<T>(ds[x].dense[lv], (int)tb.dense[lv].size(), tb.td[lv], tb.tmd[lv], tb.tnd[lv], geom, dvptr,
-                         dX, dY, nb_, st);
+        launch_env_gd<T>(ds[x].dense[lv], dw[x].dense[lv], (int)w.dense[lv].size(), w.nd[lv], tb.tmd[lv],
+                         tb.tnd[lv], geom, dvptr, dX, dY, st);
       }
       if (x < N - 1) {
         tick(kEnvG2);
-        launch_env_g2<T>(ds[x].g2, (int)tb.g2.size(), tb.t2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, nb_, st);
+        launch_env_g2<T>(ds[x].g2, dw[x].g2, (int)w.g2.size(), w.n2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, st);
         std::swap(Lc, Ln);
       } else {
         tick(kEnvFinal);

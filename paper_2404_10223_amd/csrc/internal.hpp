@@ -115,15 +115,21 @@ struct EnvGeom {
   __host__ __device__ int dim(int item, int b) const { return D[item * nbond + b]; }
 };
 
+// One entry of a launch's work list: problem `desc` of the site's list for
+// pair `pair` of the batch, whose workgroups (output tiles, or 256-item
+// chunks, of that pair's own extents) start at workgroup `first`.  Entries
+// are in increasing `first`; problems with empty extents have no entry.
+struct EnvWork {
+  int desc, pair, first;
+};
+
 // X[(c, s, k)] = L[(c, s)] x ket site x block (s, k, sk); bra sector sbra = s + shift(c)
 struct EnvG1 {
-  int tile0, tilesM, tilesN;
   int x, nw, sbra, s, k, sk;
   int64_t offL, offX;
 };
 // L_{x+1}[(c, s)] = sum_q bra site x block (sa[q], kp[q], sbn)^T Y[offY[q]]
 struct EnvG2 {
-  int tile0, tilesM, tilesN;
   int x, nw, sbn, s, nseg;
   int sa[4], kp[4];
   int64_t offY[4], offL;
@@ -131,7 +137,6 @@ struct EnvG2 {
 // dense coupling: Y[a][r0..r0+nr][b] += f W[nr][nc] X[a][c0..c0+nc][b], one
 // batch per bra row a of the block (bra sector sa at bond x, ket sector s at x+1)
 struct EnvGD {
-  int tile0, tilesM, tilesN;
   int x, sa, s, nr, nc, r0, c0, nw_in, nw_out;
   int64_t offY, offX, valoff;
   double f;
@@ -142,15 +147,16 @@ struct EnvFinal {
   int64_t offY;
 };
 
+// tileM x tileN output tiles; work[0..nwork) covers nwg workgroups
 template <typename T>
-void launch_env_g1(const EnvG1 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *L, const T *const *ket, T *const *X, int npair, hipStream_t st);
+void launch_env_g1(const EnvG1 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st);
 template <typename T>
-void launch_env_g2(const EnvG2 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *bra, const T *const *Y, T *const *Ln, int npair, hipStream_t st);
+void launch_env_g2(const EnvG2 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st);
 template <typename T>
-void launch_env_gd(const EnvGD *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *vals, const T *const *X, T *const *Y, int npair, hipStream_t st);
+void launch_env_gd(const EnvGD *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st);
 
 // channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k]
 struct MixSrc {        // host-side bookkeeping of a task's sources
@@ -174,9 +180,8 @@ struct MixTask {
 };
 struct MixArgs {
   const MixTask *tasks;
-  const int *task_chunk0;   // first 256-item chunk of each task
-  const int *chunk_task;    // task of each chunk
-  int ntask, nchunk;
+  const EnvWork *work;      // (task, pair, first chunk of 256 items)
+  int nwork, nchunk;
   const int *rowptr;        // entry offsets per task row (see MixTask::row0)
   const MixEnt *ents;
   const double *vals;       // [basis][nnz of all sites]
@@ -184,7 +189,7 @@ struct MixArgs {
   const int *basis;         // [pair]
 };
 template <typename T>
-void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, int npair, hipStream_t st);
+void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, hipStream_t st);
 
 template <typename T>
 void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st);

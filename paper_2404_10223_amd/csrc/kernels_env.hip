@@ -7,9 +7,9 @@
 // sector) and ket sector s, is dense [dim_bra(s + d)][n_channels(c)]
 // [dim_ket(s)] with the pair's dimensions; its slot in the pair's buffer is
 // sized for the largest dimensions over all pairs, so one descriptor list
-// (and one offset per block) serves every pair.  A workgroup resolves its
-// pair's extents from the item tables and leaves at once when its tile lies
-// outside them.
+// (and one offset per block) serves every pair.  A launch runs over a work
+// list of (descriptor, pair) entries holding only the tiles inside that
+// pair's extents; a workgroup finds its entry by binary search.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -180,29 +180,29 @@ __device__ void tile_gemm(int M, int N, int m0, int n0, const Seg<T> (&sg)[NSEG]
   }
 }
 
-// the problem owning a tile: last descriptor with tile0 <= tile
-template <typename D>
-__device__ inline int find_desc(const D *descs, int ndesc, int tile) {
-  int lo = 0, hi = ndesc - 1;
+// the work entry owning workgroup wg: last entry with first <= wg
+__device__ inline EnvWork find_work(const EnvWork *work, int nwork, int wg) {
+  int lo = 0, hi = nwork - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    if (work[mid].first <= wg) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return work[lo];
 }
 
 // X[(c, s, k)] = L[(c, s)] A_ket[s, k, s + q(k)]
 template <typename T, int TM, int TN, int RM, int RN>
-__global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, int ndesc, EnvGeom g, const T *const *L,
-                                                const T *const *ket, T *const *X) {
-  const int pair = blockIdx.y;
-  const EnvG1 d = descs[find_desc(descs, ndesc, blockIdx.x)];
+__global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, const EnvWork *work, int nwork, EnvGeom g,
+                                                const T *const *L, const T *const *ket, T *const *X) {
+  const EnvWork w = find_work(work, nwork, blockIdx.x);
+  const int pair = w.pair;
+  const EnvG1 d = descs[w.desc];
   const int bi = g.bra[pair], ki = g.ket[pair];
   const int dbra = g.sec(bi, d.x, d.sbra).y;
   const int2 sk = g.sec(ki, d.x, d.s), sn = g.sec(ki, d.x + 1, d.sk);
   const int M = dbra * d.nw, N = sn.y;
-  const int t = blockIdx.x - d.tile0;
-  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
+  const int t = blockIdx.x - w.first, tilesN = (N + TN - 1) / TN;
+  const int m0 = (t / tilesN) * TM, n0 = (t % tilesN) * TN;
   if (m0 >= M || n0 >= N) return;
   const int Dr = g.dim(ki, d.x + 1);
   Seg<T> sg[1];
@@ -217,15 +217,16 @@ __global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, int ndesc, E
 
 // L'[(c, s)] = sum_k' A_bra[s_a(k'), k', s + d]^T Y[(c, s, k')]
 template <typename T, int TM, int TN, int RM, int RN>
-__global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, int ndesc, EnvGeom g, const T *const *bra,
-                                                const T *const *Y, T *const *Ln) {
-  const int pair = blockIdx.y;
-  const EnvG2 d = descs[find_desc(descs, ndesc, blockIdx.x)];
+__global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, const EnvWork *work, int nwork, EnvGeom g,
+                                                const T *const *bra, const T *const *Y, T *const *Ln) {
+  const EnvWork w = find_work(work, nwork, blockIdx.x);
+  const int pair = w.pair;
+  const EnvG2 d = descs[w.desc];
   const int bi = g.bra[pair], ki = g.ket[pair];
   const int2 sbn = g.sec(bi, d.x + 1, d.sbn);
   const int M = sbn.y, N = d.nw * g.sec(ki, d.x + 1, d.s).y;
-  const int t = blockIdx.x - d.tile0;
-  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
+  const int t = blockIdx.x - w.first, tilesN = (N + TN - 1) / TN;
+  const int m0 = (t / tilesN) * TM, n0 = (t % tilesN) * TN;
   if (m0 >= M || n0 >= N) return;
   const int Dr = g.dim(bi, d.x + 1);
   Seg<T> sg[4];
@@ -304,15 +305,16 @@ __device__ void tile_gemm_f(int M, int N, int K, int m0, int n0, LA la, LB lb, S
 // dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b],
 // one GEMM over all bra rows a of the block: M = nr, K = nc, N = (a, b)
 template <typename T, int TM, int TN, int RM, int RN>
-__global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, EnvGeom g, const T *const *vals,
-                                                const T *const *X, T *const *Y) {
-  const int pair = blockIdx.y;
-  const EnvGD d = descs[find_desc(descs, ndesc, blockIdx.x)];
+__global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, const EnvWork *work, int nwork, EnvGeom g,
+                                                const T *const *vals, const T *const *X, T *const *Y) {
+  const EnvWork w = find_work(work, nwork, blockIdx.x);
+  const int pair = w.pair;
+  const EnvGD d = descs[w.desc];
   const int bi = g.bra[pair], ki = g.ket[pair];
   const int da = g.sec(bi, d.x, d.sa).y, db = g.sec(ki, d.x + 1, d.s).y;
-  const int t = blockIdx.x - d.tile0;
-  const int m0 = (t / d.tilesN) * TM, n0 = (t % d.tilesN) * TN;
   const int N = da * db;
+  const int t = blockIdx.x - w.first, tilesN = (N + TN - 1) / TN;
+  const int m0 = (t / tilesN) * TM, n0 = (t % tilesN) * TN;
   if (m0 >= d.nr || n0 >= N) return;
   const T *W = vals[pair] + d.valoff;
   const T *Xb = X[pair] + d.offX + (int64_t)d.c0 * db;
@@ -338,13 +340,12 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, int ndesc, E
 // row are a short list shared by all threads of the row.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
-  const int pair = blockIdx.y;
-  const int chunk = blockIdx.x;
-  const int ti = a.chunk_task[chunk];
-  const MixTask tk = a.tasks[ti];
+  const EnvWork wk = find_work(a.work, a.nwork, blockIdx.x);
+  const int pair = wk.pair;
+  const MixTask tk = a.tasks[wk.desc];
   const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
   const int qpr = (db + 3) >> 2;
-  const int item = (chunk - a.task_chunk0[ti]) * 256 + threadIdx.x;
+  const int item = (blockIdx.x - wk.first) * 256 + threadIdx.x;
   if (item >= da * tk.nw_out * qpr) return;
   const int row = item / qpr, b0 = (item - row * qpr) * 4;
   const int ap = row / tk.nw_out, w = row - ap * tk.nw_out;
@@ -446,30 +447,30 @@ __global__ void k_cast(const double *const *src, float *const *dst, const int64_
   } while (0)
 
 template <typename T>
-void launch_env_g1(const EnvG1 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *L, const T *const *ket, T *const *X, int npair, hipStream_t st) {
-  if (ndesc == 0 || ntiles == 0 || npair == 0) return;
-  TNQE_TILE_SWITCH(k_env_g1, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, L, ket, X);
+void launch_env_g1(const EnvG1 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st) {
+  if (nwork == 0 || nwg == 0) return;
+  TNQE_TILE_SWITCH(k_env_g1, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, L, ket, X);
 }
 
 template <typename T>
-void launch_env_g2(const EnvG2 *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *bra, const T *const *Y, T *const *Ln, int npair, hipStream_t st) {
-  if (ndesc == 0 || ntiles == 0 || npair == 0) return;
-  TNQE_TILE_SWITCH(k_env_g2, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, bra, Y, Ln);
+void launch_env_g2(const EnvG2 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st) {
+  if (nwork == 0 || nwg == 0) return;
+  TNQE_TILE_SWITCH(k_env_g2, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, bra, Y, Ln);
 }
 
 template <typename T>
-void launch_env_gd(const EnvGD *d, int ndesc, int ntiles, int tileM, int tileN, const EnvGeom &g,
-                   const T *const *vals, const T *const *X, T *const *Y, int npair, hipStream_t st) {
-  if (ndesc == 0 || ntiles == 0 || npair == 0) return;
-  TNQE_TILE_SWITCH(k_env_gd, T, tileM, tileN, dim3(ntiles, npair), st, d, ndesc, g, vals, X, Y);
+void launch_env_gd(const EnvGD *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
+                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st) {
+  if (nwork == 0 || nwg == 0) return;
+  TNQE_TILE_SWITCH(k_env_gd, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, vals, X, Y);
 }
 
 template <typename T>
-void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, int npair, hipStream_t st) {
-  if (a.ntask == 0 || a.nchunk == 0 || npair == 0) return;
-  hipLaunchKernelGGL(k_mix<T>, dim3(a.nchunk, npair), dim3(256), 0, st, a, g, X, Y);
+void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, hipStream_t st) {
+  if (a.nwork == 0 || a.nchunk == 0) return;
+  hipLaunchKernelGGL(k_mix<T>, dim3(a.nchunk), dim3(256), 0, st, a, g, X, Y);
 }
 
 template <typename T>
@@ -491,14 +492,13 @@ void launch_cast(const double *const *src, float *const *dst, const int64_t *cou
 }
 
 #define TNQE_ENV_INST(T)                                                                                     \
-  template void launch_env_g1<T>(const EnvG1 *, int, int, int, int, const EnvGeom &, const T *const *,      \
-                                 const T *const *, T *const *, int, hipStream_t);                           \
-  template void launch_env_g2<T>(const EnvG2 *, int, int, int, int, const EnvGeom &, const T *const *,      \
-                                 const T *const *, T *const *, int, hipStream_t);                           \
-  template void launch_env_gd<T>(const EnvGD *, int, int, int, int, const EnvGeom &, const T *const *,      \
-                                 const T *const *, T *const *, int, hipStream_t);                           \
-  template void launch_mix<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, int,          \
-                              hipStream_t);                                                                 \
+  template void launch_env_g1<T>(const EnvG1 *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
+                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+  template void launch_env_g2<T>(const EnvG2 *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
+                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+  template void launch_env_gd<T>(const EnvGD *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
+                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+  template void launch_mix<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, hipStream_t); \
   template void launch_env_init<T>(T *const *, int, int64_t, hipStream_t);                                  \
   template void launch_env_final<T>(const EnvGeom &, int, const double *const *, const T *const *,          \
                                     const EnvFinal *, int, int, double *, int, hipStream_t);
