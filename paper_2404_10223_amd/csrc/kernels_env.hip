@@ -354,7 +354,28 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
   const T *Xp = X[pair];
   const int nb = min(4, db - b0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = e0; e < e1; ++e) {
+  // four couplings at a time: their descriptor loads, then their coefficient
+  // and X loads, are issued together (two memory latencies per four terms);
+  // the terms are added in coupling order
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    MixEnt en[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) en[u] = a.ents[e + u];
+    double cf[4], xv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cf[u] = en[u].factor * vals[en[u].val];
+      const T *xr = Xp + en[u].offX + ((int64_t)ap * en[u].nw_in + en[u].col) * db + b0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[u][j] = j < nb ? (double)xr[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += cf[u] * xv[u][j];
+  }
+  for (; e < e1; ++e) {
     const MixEnt en = a.ents[e];
     const double cf = en.factor * vals[en.val];
     const T *xr = Xp + en.offX + ((int64_t)ap * en.nw_in + en.col) * db + b0;
