@@ -122,6 +122,9 @@ __device__ inline int rank_of(const double *sig, int n, int i) {
   return r;
 }
 
+// squared relative inner product above which a rotation keeps the sweeps going
+constexpr double kBig2 = 1e-20;
+
 // at most 1024 threads (E <= 20) or 768 (E = 24, for the register budget)
 template <int E>
 __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks, const int *idx, double *scratch,
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
   double *tnrm = X + (int64_t)NTr * mp;         // traveller squared norms
   double *sig = tnrm + NTr;                     // singular values [n]
   int *rnk = reinterpret_cast<int *>(sig + n);  // ranks [n]
-  __shared__ int s_rot[2];
+  __shared__ int s_rot[2], s_big[2];
   __shared__ unsigned long long s_amax;
   const double *T = scratch + b.offT;
   const int p = threadIdx.x / G, gl = threadIdx.x - p * G;
@@ -166,8 +169,8 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
     }
   }
   if (threadIdx.x == 0) {
-    s_rot[0] = 0;
-    s_rot[1] = 0;
+    s_rot[0] = s_rot[1] = 0;
+    s_big[0] = s_big[1] = 0;
   }
   __syncthreads();
   // rounding floor of a length-m dot product relative to the norms (squared)
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
     // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
     // block: they are not rotated (they never survive a truncation)
     const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
-    int rotated = 0;
+    int rotated = 0, big = 0;
     int pb = 0, sb = 0, r = P, t = NTr;   // this processor's node
     for (int lv = 0;; ++lv) {
       if (((n + (1 << lv) - 1) >> lv) <= 1) break;            // largest node has one vector
@@ -211,6 +214,7 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
             if (al > tiny && be > tiny) {
               const double ga = group_sum(dot_e(res, trv), G);
               if (ga * ga > tol2 * (al * be)) {
+                big |= ga * ga > kBig2 * (al * be) ? 1 : 0;
                 double c, s;
                 const double tn = jacobi_angle(al, be, ga, c, s);
                 // one component at a time (keeps the live registers at the
@@ -263,11 +267,14 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
       }
     }
     if (rotated && gl == 0) atomicOr(&s_rot[fl], 1);
+    if (big && gl == 0) atomicOr(&s_big[fl], 1);
     __syncthreads();
-    const int any = s_rot[fl];
-    // the other flag is cleared only after every thread has read this one
-    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
-    if (any == 0) break;
+    const int any = s_rot[fl], any_big = s_big[fl];
+    // the other flags are cleared only after every thread has read these
+    if (threadIdx.x == 0) s_rot[fl ^ 1] = s_big[fl ^ 1] = 0;
+    // converged: no rotation, or only rotations of pairs already orthogonal
+    // to 1e-10 (what they leave is of second order, ~1e-20, far below tol)
+    if (any == 0 || any_big == 0) break;
   }
   if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
   // singular values from the final vectors (residents 0..P, travellers P..n)
