@@ -28,8 +28,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-SVD_KERNELS = (["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global"]
-               + ["k_jacobi_u<4, %d>" % (4 * (j + 1)) for j in range(4)] + [None] * 5)
+SVD_KERNELS = ["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global"] + [None] * 9
 KERNEL_SOURCE = {"k_jacobi": "kernels_svd.hip", "k_env": "kernels_env.hip", "k_mix": "kernels_env.hip"}
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.md")
 ENV_KERNELS = ["k_env_g1", "k_mix", "k_env_gd", "k_env_g2", "k_env_final", None, None, None]

@@ -76,10 +76,7 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const
 // case).  kind k < kJacobiGlobal selects the register-resident kernel with
 // E = 4 (k + 1) vector elements per lane (threads and lds_bytes per
 // workgroup); kJacobiGlobal is the global-memory fallback.
-// Kinds kJacobiUnit + j (j < 4) are the unit kernels (units of four
-// vectors, E = 4 (j + 1) elements per lane, at most 512 threads).
-constexpr int kJacobiMaxE = 24, kJacobiGlobal = kJacobiMaxE / 4, kJacobiUnit = kJacobiGlobal + 1,
-              kJacobiKinds = kJacobiUnit + 4;
+constexpr int kJacobiMaxE = 24, kJacobiGlobal = kJacobiMaxE / 4, kJacobiKinds = kJacobiGlobal + 1;
 constexpr int jacobi_max_threads(int E) { return E > 20 ? 768 : 1024; }
 constexpr int kJacobiLdsBytes = 160 * 1024 - 1024;   // dynamic LDS cap per workgroup
 void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,

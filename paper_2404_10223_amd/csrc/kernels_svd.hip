@@ -329,290 +329,6 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
   }
 }
 
-// Unit variant.  Vectors are grouped in units of B (zero vectors pad the last
-// unit).  A processor keeps a resident unit in registers and the traveller
-// units live in LDS; a round loads one traveller unit, rotates every
-// (resident, traveller) pair in B stages of B independent rotations
-// (resident i with traveller (i + stage) mod B), and stores the unit back.
-// The pairs inside a unit are rotated once per sweep before the rounds.  The
-// unit ordering is the resident/traveller tree above; per rotation the LDS
-// traffic is 1/B of the one-vector kernel, and the B rotations of a stage are
-// independent instruction streams.
-template <int E, int NV, int NP>
-__device__ __forceinline__ void rot_stage(double (&V)[NV][E], double (&nv)[NV], const int (&pa)[NP],
-                                          const int (&pb)[NP], int G, double tiny, double tol2, int &rotated) {
-  // the NP pairs of a stage are independent: each phase below interleaves
-  // them; scheduling barriers between phases bound the live registers
-  double g[NP];
-#pragma unroll
-  for (int k = 0; k < NP; ++k) g[k] = dot_e(V[pa[k]], V[pb[k]]);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int k = 0; k < NP; ++k) g[k] = group_sum(g[k], G);
-  __builtin_amdgcn_sched_barrier(0);
-  double c[NP], s[NP], t[NP];
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const double al = nv[pa[k]], be = nv[pb[k]];
-    const bool on = al > tiny && be > tiny && g[k] * g[k] > tol2 * (al * be);
-    double ck, sk;
-    const double tk = jacobi_angle(al, be, on ? g[k] : 1.0, ck, sk);
-    c[k] = on ? ck : 1.0;
-    s[k] = on ? sk : 0.0;
-    t[k] = on ? tk : 0.0;
-    rotated |= on ? 1 : 0;
-  }
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-#pragma unroll
-    for (int e = 0; e < E; e += 2) {
-      const double u0 = V[pa[k]][e], v0 = V[pb[k]][e], u1 = V[pa[k]][e + 1], v1 = V[pb[k]][e + 1];
-      V[pa[k]][e] = c[k] * u0 - s[k] * v0;
-      V[pb[k]][e] = s[k] * u0 + c[k] * v0;
-      V[pa[k]][e + 1] = c[k] * u1 - s[k] * v1;
-      V[pb[k]][e + 1] = s[k] * u1 + c[k] * v1;
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    nv[pa[k]] = fmax(nv[pa[k]] - t[k] * g[k], 0.0);
-    nv[pb[k]] = nv[pb[k]] + t[k] * g[k];
-  }
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int B, int E>
-__device__ __forceinline__ void ld_unit(const double *p, int mp, double (&V)[2 * B][E]) {
-#pragma unroll
-  for (int u = 0; u < B; ++u) ld_chunk<E>(p + u * mp, V[B + u]);
-}
-template <int B, int E>
-__device__ __forceinline__ void st_unit(double *p, int mp, const double (&V)[2 * B][E]) {
-#pragma unroll
-  for (int u = 0; u < B; ++u) st_chunk<E>(p + u * mp, V[B + u]);
-}
-
-template <int B, int E>
-__global__ void __launch_bounds__(512) k_jacobi_u(const Blk *blks, const int *idx, double *scratch,
-                                                  int max_sweeps, int *sweeps_out) {
-  static_assert(B == 4, "units of four vectors");
-  extern __shared__ __align__(16) double lds[];
-  const Blk b = blks[idx[blockIdx.x]];
-  const int R = b.R, C = b.C;
-  const bool cols = R >= C;
-  const int n = b.n, m = cols ? R : C;
-  if (n == 0) return;
-  constexpr int SL = E + 2;
-  static_assert(E % 4 == 0, "E");
-  const int G = b.grp, mp = G * SL;
-  const int U = (n + B - 1) / B, P = (U + 1) >> 1, NTr = U >> 1;
-  double *X = lds;                                   // traveller units [NTr][B][mp]
-  double *tnrm = X + (int64_t)NTr * B * mp;          // their squared norms [NTr][B]
-  double *sig = tnrm + NTr * B;                      // singular values [U * B]
-  int *rnk = reinterpret_cast<int *>(sig + U * B);   // ranks [U * B]
-  __shared__ int s_rot[2];
-  __shared__ unsigned long long s_amax;
-  const double *T = scratch + b.offT;
-  const int p = threadIdx.x / G, gl = threadIdx.x - p * G;
-  const bool act = p < P;
-  const int l0 = gl * E;
-  double *Xl = X + gl * SL;
-  // V[0..B): resident unit, V[B..2B): traveller unit in flight; nv: squared norms
-  double V[2 * B][E], nv[2 * B];
-  const int64_t vs = cols ? 1 : C, ls = cols ? C : 1;
-#pragma unroll
-  for (int u = 0; u < 2 * B; ++u) {
-    nv[u] = 0.0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) V[u][e] = 0.0;
-  }
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int v = p * B + u;
-      if (v < n) {
-        const double *src = T + (int64_t)v * vs + (int64_t)l0 * ls;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          V[u][e] = l0 + e < m ? src[e * ls] : 0.0;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-    }
-    if (p < NTr) {
-      for (int u = 0; u < B; ++u) {
-        const int v = (P + p) * B + u;
-        const double *src = T + (int64_t)v * vs + (int64_t)l0 * ls;
-        double *dst = Xl + (p * B + u) * mp;
-        for (int e = 0; e < E; ++e) dst[e] = (v < n && l0 + e < m) ? src[e * ls] : 0.0;
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    s_rot[0] = 0;
-    s_rot[1] = 0;
-  }
-  __syncthreads();
-  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m)), tol2 = tol * tol;
-  // pair tables: the three stages inside a unit (resident and traveller unit
-  // together), and the B cross stages
-  constexpr int ia[3][4] = {{0, 2, B + 0, B + 2}, {0, 1, B + 0, B + 1}, {0, 1, B + 0, B + 1}};
-  constexpr int ib[3][4] = {{1, 3, B + 1, B + 3}, {2, 3, B + 2, B + 3}, {3, 2, B + 3, B + 2}};
-  constexpr int ca[B][B] = {{0, 1, 2, 3}, {0, 1, 2, 3}, {0, 1, 2, 3}, {0, 1, 2, 3}};
-  constexpr int cb[B][B] = {{B + 0, B + 1, B + 2, B + 3}, {B + 1, B + 2, B + 3, B + 0},
-                            {B + 2, B + 3, B + 0, B + 1}, {B + 3, B + 0, B + 1, B + 2}};
-  int sweep = 0;
-  for (; sweep < max_sweeps && n > 1; ++sweep) {
-    const int fl = sweep & 1;
-    if (threadIdx.x == 0) s_amax = 0ull;
-    __syncthreads();
-    if (act) {
-      double mx = 0.0;
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        nv[u] = group_sum(dot_e(V[u], V[u]), G);
-        mx = fmax(mx, nv[u]);
-      }
-      if (p < NTr) {
-        ld_unit<B, E>(Xl + p * B * mp, mp, V);
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          nv[B + u] = group_sum(dot_e(V[B + u], V[B + u]), G);
-          mx = fmax(mx, nv[B + u]);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < B; ++u) nv[B + u] = 0.0;   // no traveller unit: nothing to rotate
-      }
-      if (gl == 0) atomicMax(&s_amax, (unsigned long long)__double_as_longlong(mx));
-    }
-    __syncthreads();
-    // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
-    // block (and the zero padding): they are not rotated
-    const double tiny = __longlong_as_double((long long)s_amax) * 1e-28;
-    int rotated = 0;
-    // pairs inside the resident unit and inside traveller unit p
-    if (act) {
-#pragma unroll
-      for (int st = 0; st < 3; ++st) rot_stage<E, 2 * B, 4>(V, nv, ia[st], ib[st], G, tiny, tol2, rotated);
-      if (p < NTr) {
-        st_unit<B, E>(Xl + p * B * mp, mp, V);
-        if (gl == 0)
-#pragma unroll
-          for (int u = 0; u < B; ++u) tnrm[p * B + u] = nv[B + u];
-      }
-    }
-    __syncthreads();
-    int pb = 0, sb = 0, r = P, t = NTr;   // this processor's node (in units)
-    for (int lv = 0;; ++lv) {
-      if (((U + (1 << lv) - 1) >> lv) <= 1) break;
-      const int rounds = (U + (2 << lv) - 1) >> (lv + 1);
-      const int k = p - pb, q = max(r, t);
-      for (int rho = 0; rho < rounds; ++rho) {
-        if (act && rho < q) {
-          int j = k + rho;
-          if (j >= q) j -= q;
-          if (j < t) {
-            double *xs = Xl + (sb + j) * B * mp;
-            ld_unit<B, E>(xs, mp, V);
-#pragma unroll
-            for (int u = 0; u < B; ++u) nv[B + u] = tnrm[(sb + j) * B + u];
-            int rot = 0;
-#pragma unroll
-            for (int st = 0; st < B; ++st) rot_stage<E, 2 * B, B>(V, nv, ca[st], cb[st], G, tiny, tol2, rot);
-            if (rot) {
-              st_unit<B, E>(xs, mp, V);
-              if (gl == 0)
-#pragma unroll
-                for (int u = 0; u < B; ++u) tnrm[(sb + j) * B + u] = nv[B + u];
-              rotated = 1;
-            }
-          }
-        }
-        __syncthreads();
-      }
-      const int x = (t == r + 1) ? (r + 1) >> 1 : r >> 1;
-      const int rA = r - x;
-      const bool sw = act && k >= rA && k < r;
-      const int slot = sb + (k - rA);
-      if (sw) {
-        ld_unit<B, E>(Xl + slot * B * mp, mp, V);
-#pragma unroll
-        for (int u = 0; u < B; ++u) nv[B + u] = tnrm[slot * B + u];
-      }
-      __syncthreads();
-      if (sw) {
-#pragma unroll
-        for (int u = 0; u < B; ++u) st_chunk<E>(Xl + (slot * B + u) * mp, V[u]);
-        if (gl == 0)
-#pragma unroll
-          for (int u = 0; u < B; ++u) tnrm[slot * B + u] = nv[u];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          nv[u] = nv[B + u];
-#pragma unroll
-          for (int e = 0; e < E; ++e) V[u][e] = V[B + u][e];
-        }
-      }
-      __syncthreads();
-      if (k < rA) {
-        r = rA;
-        t = x;
-      } else {
-        pb += rA;
-        sb += x;
-        t = t - x;
-        r = x;
-      }
-    }
-    if (rotated && gl == 0) atomicOr(&s_rot[fl], 1);
-    __syncthreads();
-    const int any = s_rot[fl];
-    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
-    if (any == 0) break;
-  }
-  if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
-  // singular values (residents: units 0..P, travellers: units P..U)
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const double s2 = group_sum(dot_e(V[u], V[u]), G);
-      if (gl == 0) sig[p * B + u] = sqrt(s2);
-    }
-    if (p < NTr) {
-      ld_unit<B, E>(Xl + p * B * mp, mp, V);
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const double s2 = group_sum(dot_e(V[B + u], V[B + u]), G);
-        if (gl == 0) sig[(P + p) * B + u] = sqrt(s2);
-      }
-    }
-  }
-  __syncthreads();
-  double *S = scratch + b.offS;
-  for (int i = threadIdx.x; i < U * B; i += blockDim.x) {
-    const int rk = rank_of(sig, U * B, i);
-    rnk[i] = rk;
-    if (rk < n) S[rk] = sig[i];
-  }
-  __syncthreads();
-  double *out = scratch + (cols ? b.offU : b.offB);
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < 2 * B; ++u) {
-      if (u >= B && p >= NTr) continue;
-      const int i = u < B ? p * B + u : (P + p) * B + (u - B);
-      const int rk = rnk[i];
-      if (rk >= n) continue;
-      const double si = sig[i];
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int l = l0 + e;
-        if (l < m) out[(int64_t)rk * m + l] = cols ? (si > 0.0 ? V[u][e] / si : 0.0) : V[u][e];
-      }
-    }
-  }
-}
-
 // Blocks too large for k_jacobi: the vectors live in a global work area and
 // are rotated in cyclic round-robin order by groups of G lanes (same output).
 __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const int *idx, double *scratch,
@@ -805,19 +521,6 @@ void set_lds_cap() {
 }
 
 template <int E>
-void set_lds_cap_u() {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jacobi_u<4, E>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLdsBytes);
-}
-
-template <int E>
-void launch_u(const Blk *blk, const int *idx, int nblk, int threads, int lds_bytes, double *scratch,
-              int max_sweeps, int *sweeps_out, hipStream_t st) {
-  hipLaunchKernelGGL((k_jacobi_u<4, E>), dim3(nblk), dim3(threads), lds_bytes, st, blk, idx, scratch, max_sweeps,
-                     sweeps_out);
-}
-
-template <int E>
 void launch_e(const Blk *blk, const int *idx, int nblk, int threads, int lds_bytes, double *scratch,
               int max_sweeps, int *sweeps_out, hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi<E>, dim3(nblk), dim3(threads), lds_bytes, st, blk, idx, scratch, max_sweeps,
@@ -837,10 +540,6 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
     set_lds_cap<16>();
     set_lds_cap<20>();
     set_lds_cap<24>();
-    set_lds_cap_u<4>();
-    set_lds_cap_u<8>();
-    set_lds_cap_u<12>();
-    set_lds_cap_u<16>();
     attr_set = true;
   }
   switch (kind) {
@@ -850,10 +549,6 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
     case 3: launch_e<16>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
     case 4: launch_e<20>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
     case 5: launch_e<24>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
-    case kJacobiUnit + 0: launch_u<4>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
-    case kJacobiUnit + 1: launch_u<8>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
-    case kJacobiUnit + 2: launch_u<12>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
-    case kJacobiUnit + 3: launch_u<16>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
     default:
       hipLaunchKernelGGL(k_jacobi_global, dim3(nblk), dim3(1024), 0, st, blk, idx, scratch, max_sweeps,
                          sweeps_out);
