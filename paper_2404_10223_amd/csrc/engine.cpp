@@ -866,6 +866,32 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   if (debug_timing()) g_gate_timing.post_ms += ms_between(ts2, Clock::now());
 }
 
+// Device copy of the sparse groups' CSR structure for this MPO (cached).
+const MpoDevice &mpo_dev_for(tnqe_ctx *ctx, const MpoStructure &mpo) {
+  auto it = ctx->mpo_dev.find(mpo.N);
+  if (it != ctx->mpo_dev.end()) return *it->second;
+  auto d = std::make_unique<MpoDevice>();
+  std::vector<int> rp, cl;
+  d->rp_off.resize(mpo.N);
+  d->col_off.resize(mpo.N);
+  for (int x = 0; x < mpo.N; ++x)
+    for (const MpoGroup &g : mpo.groups[x]) {
+      d->rp_off[x].push_back((int64_t)rp.size());
+      d->col_off[x].push_back((int64_t)cl.size());
+      rp.insert(rp.end(), g.rowptr.begin(), g.rowptr.end());
+      cl.insert(cl.end(), g.col.begin(), g.col.end());
+    }
+  rp.push_back(0);
+  cl.push_back(0);
+  TNQE_HIP(hipMalloc(&d->rowptr, rp.size() * sizeof(int)));
+  TNQE_HIP(hipMalloc(&d->col, cl.size() * sizeof(int)));
+  TNQE_HIP(hipMemcpy(d->rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
+  TNQE_HIP(hipMemcpy(d->col, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice));
+  const MpoDevice &ref = *d;
+  ctx->mpo_dev[mpo.N] = std::move(d);
+  return ref;
+}
+
 // ------------------------------------------------------------ environment sweep
 // Tile shape for a list of problems with largest extents maxM x maxN.
 void pick_tile(int maxM, int maxN, bool long_m, int &tm, int &tn) {
@@ -899,6 +925,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
                const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
                int64_t nnz_total, EnvResult &res) {
   hipStream_t st = c.ctx->stream;
+  const auto tq0 = Clock::now();
   const int N = pb.N, M = pb.M, nslot = pb.nslot(), nb1 = pb.nb + 1, nbond = N + 1;
   const int nket = kets ? kets->n : 0;
   const int nitem = M + nket;
@@ -987,12 +1014,12 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     std::vector<MixTask> tasks;
     std::vector<MixSrc> srcs;
     std::vector<int> src_nnz;                // stored couplings of each source (work count)
-    std::vector<int> mrow;                   // entry offsets of every task row
-    std::vector<MixEnt> ents;
     int64_t Xsize = 0, Ysize = 0;
     std::vector<EnvFinal> fin;
   };
   std::vector<SiteTabs> tabs(N);
+  const MpoDevice &mdev = mpo_dev_for(c.ctx, mpo);
+  const auto tq1 = Clock::now();
   // sites are independent: their tables are built on the host workers
   host_pool(c.ctx).parallel_for(N, [&](int x) {
     SiteTabs &tb = tabs[x];
@@ -1073,6 +1100,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               }
               MixSrc sr{};
               sr.offX = ox;
+              sr.vbase = mpo.site_nnz_off[x] + g.val_off;
+              sr.rp = mdev.rp_off[x][gi];
+              sr.cp = mdev.col_off[x][gi];
               sr.nw_in = cls[x][g.cin].nw;
               sr.group = (int)gi;
               sr.factor = P.f[e];
@@ -1082,25 +1112,6 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           }
           tk.nsrc = (int)tb.srcs.size() - tk.src0;
           if (tk.nsrc == 0 && dsrc.empty()) continue;
-          // the couplings of every output row, gathered from the sources' CSR rows
-          tk.row0 = (int)tb.mrow.size();
-          for (int w = 0; w < tk.nw_out; ++w) {
-            tb.mrow.push_back((int)tb.ents.size());
-            for (int si = tk.src0; si < tk.src0 + tk.nsrc; ++si) {
-              const MixSrc &sr = tb.srcs[si];
-              const MpoGroup &gg = mpo.groups[x][sr.group];
-              for (int z = gg.rowptr[w]; z < gg.rowptr[w + 1]; ++z) {
-                MixEnt en{};
-                en.offX = sr.offX;
-                en.nw_in = sr.nw_in;
-                en.col = gg.col[z];
-                en.val = mpo.site_nnz_off[x] + gg.val_off + z;
-                en.factor = sr.factor;
-                tb.ents.push_back(en);
-              }
-            }
-          }
-          tb.mrow.push_back((int)tb.ents.size());
           tk.offY = yo;
           offY[(co * nslot + s) * 4 + kp] = yo;
           const int64_t tot = (int64_t)dpad[x][s_a] * tk.nw_out * dpad[x + 1][s];
@@ -1184,6 +1195,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     }
   });
+  const auto tq2 = Clock::now();
   // ---- algorithmic work with every pair's own block shapes (on a host
   // thread, overlapping the sweeps)
   const double eb = sizeof(T);
@@ -1255,8 +1267,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     EnvG1 *g1;
     EnvG2 *g2;
     MixTask *tasks;
-    int *mrow;
-    MixEnt *ents;
+    MixSrc *srcs;
     EnvFinal *fin;
   };
   std::vector<DevSite> ds(N);
@@ -1266,14 +1277,15 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     ds[x].g1 = c.upload(tabs[x].g1);
     ds[x].g2 = c.upload(tabs[x].g2);
     ds[x].tasks = c.upload(tabs[x].tasks);
-    ds[x].mrow = c.upload(tabs[x].mrow);
-    ds[x].ents = c.upload(tabs[x].ents);
+    ds[x].srcs = c.upload(tabs[x].srcs);
     ds[x].fin = c.upload(tabs[x].fin);
     for (auto &lv : tabs[x].dense) ds[x].dense.push_back(c.upload(lv));
     Xmax = std::max(Xmax, tabs[x].Xsize);
     Ymax = std::max(Ymax, tabs[x].Ysize);
   }
   c.sync();
+  const auto tq3 = Clock::now();
+  double t_work = 0.0, t_launch = 0.0, t_wait = 0.0;
   // ---- pair batches under a memory budget
   const int npair = (int)pairs.size();
   const double per_pair = (double)(2 * Lmax + Xmax + Ymax) * sizeof(T);
@@ -1315,6 +1327,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       dbra[x] = c.upload(bp);
       dket[x] = c.upload(kp);
     }
+    const auto tb0 = Clock::now();
     // work lists of the batch: only the tiles (chunks) inside every pair's
     // own extents; sites in parallel on the host workers
     struct SiteWork {
@@ -1379,6 +1392,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       dw[x].g2 = c.upload(sw[x].g2);
       for (auto &lv : sw[x].dense) dw[x].dense.push_back(c.upload(lv));
     }
+    const auto tb1 = Clock::now();
+    t_work += ms_between(tb0, tb1);
     std::vector<const double *> bra64(nb_);
     for (int q = 0; q < nb_; ++q) bra64[q] = site64[(size_t)bra_item[q] * N + N - 1];
     const double *const *dbra64 = c.upload(bra64);
@@ -1408,8 +1423,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       ma.work = dw[x].mix;
       ma.nwork = (int)w.mix.size();
       ma.nchunk = w.nmix;
-      ma.rowptr = ds[x].mrow;
-      ma.ents = ds[x].ents;
+      ma.srcs = ds[x].srcs;
+      ma.rowptr = mdev.rowptr;
+      ma.col = mdev.col;
       ma.vals = dvals;
       ma.basis_stride = nnz_total;
       ma.basis = dbasis;
@@ -1434,7 +1450,10 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     TNQE_HIP(hipEventRecord(e1, st));
     std::vector<double> out((size_t)nb_ * 2);
     TNQE_HIP(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    const auto tb2 = Clock::now();
+    t_launch += ms_between(tb1, tb2);
     c.sync();
+    t_wait += ms_between(tb2, Clock::now());
     float ms = 0.0f;
     TNQE_HIP(hipEventElapsedTime(&ms, e0, e1));
     res.kernel_ms += ms;
@@ -1449,6 +1468,21 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       res.S[p0 + q] = out[(size_t)q * 2 + mpo.final_I];
     }
     c.ctx->pool.rewind(mk);
+  }
+  if (debug_timing()) {
+    double mb[6] = {};
+    for (int x = 0; x < N; ++x) {
+      mb[0] += tabs[x].g1.size() * sizeof(EnvG1) / 1e6;
+      mb[1] += tabs[x].g2.size() * sizeof(EnvG2) / 1e6;
+      mb[2] += tabs[x].tasks.size() * sizeof(MixTask) / 1e6;
+      mb[3] += tabs[x].srcs.size() * sizeof(MixSrc) / 1e6;
+      for (auto &lv : tabs[x].dense) mb[5] += lv.size() * sizeof(EnvGD) / 1e6;
+    }
+    std::fprintf(stderr,
+                 "env phase host: items %.1f ms, site tables %.1f ms, device tables %.1f ms (MB: g1 %.1f g2 %.1f "
+                 "tasks %.1f sources %.1f dense %.1f), work lists %.1f ms, launches %.1f ms, wait %.1f ms\n",
+                 ms_between(tq0, tq1), ms_between(tq1, tq2), ms_between(tq2, tq3), mb[0], mb[1], mb[2], mb[3], mb[5],
+                 t_work, t_launch, t_wait);
   }
 }
 

@@ -80,6 +80,20 @@ class ThreadPool {
   std::exception_ptr err_;
 };
 
+// Row pointers and column indices of every sparse MPO group of one
+// structure, on the device (built once per context and site count).
+struct MpoDevice {
+  int *rowptr = nullptr, *col = nullptr;
+  std::vector<std::vector<int64_t>> rp_off, col_off;   // [site][group]
+  MpoDevice() = default;
+  MpoDevice(const MpoDevice &) = delete;
+  MpoDevice &operator=(const MpoDevice &) = delete;
+  ~MpoDevice() {
+    if (rowptr) (void)hipFree(rowptr);
+    if (col) (void)hipFree(col);
+  }
+};
+
 }  // namespace tnqe
 
 struct tnqe_ctx {
@@ -89,6 +103,7 @@ struct tnqe_ctx {
   tnqe::DevicePool pool;
   tnqe::Staging staging;
   std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
+  std::map<int, std::unique_ptr<tnqe::MpoDevice>> mpo_dev;        // by N
   hipEvent_t ev[8] = {};
   hipEvent_t svd_ev[64] = {};  // timing of the truncation SVD launches of one gate step
   // side streams (default priority) that run independent SVD launches side by

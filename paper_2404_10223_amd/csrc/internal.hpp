@@ -155,32 +155,30 @@ template <typename T>
 void launch_env_gd(const EnvGD *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
                    const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st);
 
-// channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k]
-struct MixSrc {        // host-side bookkeeping of a task's sources
+// channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k].
+// One source of a task: a sparse MPO group (CSR over output x input channel,
+// kept on the device once per structure) applied to one X block:
+// Y[a][w'][b] += factor sum_z vals[vbase + z] X[offX + (a nw_in + col[cp + z]) db + b]
+// for z in [rowptr[rp + w'], rowptr[rp + w' + 1]).
+struct MixSrc {
   int64_t offX;        // X block [da][nw_in][db]
+  int64_t vbase;       // value index of the group's first nonzero
+  int64_t rp, cp;      // offsets of the group's row pointers and column indices
   int nw_in;
-  int group;           // index into the site's MPO groups
+  int group;           // host bookkeeping: index into the site's MPO groups
   double factor;       // local-operator matrix element
-};
-// one coupling of an output channel row: Y[a][w'][b] += factor * vals[val] * X[offX + (a nw_in + col) db + b]
-struct MixEnt {
-  int64_t offX;
-  int nw_in, col;
-  int64_t val;         // index of the MPO coefficient in one basis' value array
-  double factor;
 };
 struct MixTask {
   int64_t offY;        // Y block [da][nw_out][db], da = dim_bra(x, sa), db = dim_ket(x + 1, s)
   int x, sa, s, nw_out;
-  int src0, nsrc;      // host bookkeeping: range in the MixSrc array
-  int row0;            // first of the nw_out + 1 entry offsets of this task's rows
+  int src0, nsrc;      // range in the site's source array
 };
 struct MixArgs {
   const MixTask *tasks;
   const EnvWork *work;      // (task, pair, first chunk of 256 items)
   int nwork, nchunk;
-  const int *rowptr;        // entry offsets per task row (see MixTask::row0)
-  const MixEnt *ents;
+  const MixSrc *srcs;
+  const int *rowptr, *col;  // CSR structure of the MPO groups
   const double *vals;       // [basis][nnz of all sites]
   int64_t basis_stride;
   const int *basis;         // [pair]

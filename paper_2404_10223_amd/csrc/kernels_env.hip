@@ -335,9 +335,10 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, const EnvWor
 }
 
 // ------------------------------------------------------------------ channel mix
-// Y[a][w'][b] = sum over the couplings of row w' of factor * v * X[a][c][b].
-// A thread takes four consecutive b of one row (a, w'); the couplings of the
-// row are a short list shared by all threads of the row.
+// Y[a][w'][b] = sum over the task's sources and the nonzeros z of row w' of
+// each source's MPO group of factor * v_z * X[a][col_z][b].  A thread takes
+// four consecutive b of one row (a, w'); a row's couplings are shared by all
+// threads of the row.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
   const EnvWork wk = find_work(a.work, a.nwork, blockIdx.x);
@@ -349,39 +350,40 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
   if (item >= da * tk.nw_out * qpr) return;
   const int row = item / qpr, b0 = (item - row * qpr) * 4;
   const int ap = row / tk.nw_out, w = row - ap * tk.nw_out;
-  const int e0 = a.rowptr[tk.row0 + w], e1 = a.rowptr[tk.row0 + w + 1];
   const double *vals = a.vals + a.basis[pair] * a.basis_stride;
   const T *Xp = X[pair];
   const int nb = min(4, db - b0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // four couplings at a time: their descriptor loads, then their coefficient
-  // and X loads, are issued together (two memory latencies per four terms);
-  // the terms are added in coupling order
-  int e = e0;
-  for (; e + 4 <= e1; e += 4) {
-    MixEnt en[4];
+  for (int si = tk.src0; si < tk.src0 + tk.nsrc; ++si) {
+    const MixSrc sr = a.srcs[si];
+    const int z0 = a.rowptr[sr.rp + w], z1 = a.rowptr[sr.rp + w + 1];
+    const int *col = a.col + sr.cp;
+    const double *v = vals + sr.vbase;
+    const T *xb = Xp + sr.offX + (int64_t)ap * sr.nw_in * db + b0;
+    // four couplings at a time: their loads are issued together; the terms
+    // are added in coupling order
+    int z = z0;
+    for (; z + 4 <= z1; z += 4) {
+      double cf[4], xv[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) en[u] = a.ents[e + u];
-    double cf[4], xv[4][4];
+      for (int u = 0; u < 4; ++u) {
+        cf[u] = sr.factor * v[z + u];
+        const T *xr = xb + (int64_t)col[z + u] * db;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      cf[u] = en[u].factor * vals[en[u].val];
-      const T *xr = Xp + en[u].offX + ((int64_t)ap * en[u].nw_in + en[u].col) * db + b0;
+        for (int j = 0; j < 4; ++j) xv[u][j] = j < nb ? (double)xr[j] : 0.0;
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xv[u][j] = j < nb ? (double)xr[j] : 0.0;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += cf[u] * xv[u][j];
     }
+    for (; z < z1; ++z) {
+      const double cf = sr.factor * v[z];
+      const T *xr = xb + (int64_t)col[z] * db;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += cf[u] * xv[u][j];
-  }
-  for (; e < e1; ++e) {
-    const MixEnt en = a.ents[e];
-    const double cf = en.factor * vals[en.val];
-    const T *xr = Xp + en.offX + ((int64_t)ap * en.nw_in + en.col) * db + b0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j < nb) acc[j] += cf * (double)xr[j];
+      for (int j = 0; j < 4; ++j)
+        if (j < nb) acc[j] += cf * (double)xr[j];
+    }
   }
   T *yr = Y[pair] + tk.offY + ((int64_t)ap * tk.nw_out + w) * db + b0;
 #pragma unroll
