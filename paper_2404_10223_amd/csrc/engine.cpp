@@ -426,18 +426,30 @@ JacobiPlan jacobi_plan(int n, int m) {
 
 // plan the SVD of a block: launch shape and scratch (a global work area only
 // for blocks the register/LDS kernels cannot hold)
-void plan_block_storage(Blk &b, Scratch &sc) {
+// launch shape of a block (offW >= 0 marks the global-memory variant until
+// its storage is assigned)
+void plan_block(Blk &b) {
   b.n = std::min(b.R, b.C);
   require(b.n <= 1024, TNQE_ESHAPE, "quantum-number block larger than 1024 singular values");
-  const int m = std::max(b.R, b.C);
-  const JacobiPlan jp = jacobi_plan(b.n, m);
+  const JacobiPlan jp = jacobi_plan(b.n, std::max(b.R, b.C));
   b.grp = jp.grp;
   b.mpad = jp.mpad;
+  b.offW = jp.kind == kJacobiGlobal ? 0 : -1;
+}
+
+// scratch of a planned block: T, U, B (and the work area of the global variant)
+void take_block_storage(Blk &b, Scratch &sc) {
+  const int m = std::max(b.R, b.C);
   b.offT = sc.take((int64_t)b.R * b.C);
   b.offU = sc.take((int64_t)b.R * b.n);
   b.offB = sc.take((int64_t)b.n * b.C);
   b.offS = -1;
-  b.offW = jp.kind == kJacobiGlobal ? sc.take((int64_t)b.n * m + b.n) : -1;
+  b.offW = b.offW >= 0 ? sc.take((int64_t)b.n * m + b.n) : -1;
+}
+
+void plan_block_storage(Blk &b, Scratch &sc) {
+  plan_block(b);
+  take_block_storage(b, sc);
 }
 
 // Algorithmic flops of the SVD of an R x C block (n = min, m = max): the
@@ -592,9 +604,8 @@ struct TruncStats {
 // One exact LQ centre move (site q -> q-1) for every ket in the set.
 void move_left(KetSet &ks, int q, int max_sweeps) {
   Call &c = *ks.call;
-  std::vector<Blk> blks;
-  Scratch sc;
-  for (int t = 0; t < ks.n; ++t) {
+  std::vector<std::vector<Blk>> pblk(ks.n);
+  host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
     for (int s = 0; s < ks.nslot; ++s) {
       const int d = ks.dim(q, t, s);
       if (d == 0) continue;
@@ -611,10 +622,17 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
       b.aux0 = ks.off_q(q, t, sa, sb);
       b.aux1 = ks.htot[(size_t)q * ks.n + t];
       if (b.C == 0) continue;
-      plan_block_storage(b, sc);
+      plan_block(b);
+      pblk[t].push_back(b);
+    }
+  });
+  std::vector<Blk> blks;
+  Scratch sc;
+  for (int t = 0; t < ks.n; ++t)
+    for (Blk &b : pblk[t]) {
+      take_block_storage(b, sc);
       blks.push_back(b);
     }
-  }
   // new bond q: min(R, C) per sector
   for (int t = 0; t < ks.n; ++t)
     for (int s = 0; s < ks.nslot; ++s) ks.dim(q, t, s) = 0;
@@ -713,51 +731,45 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
                int max_sweeps, TruncStats &ts) {
   const auto tb0 = Clock::now();
   Call &c = *ks.call;
+  // blocks of the new middle sectors (gated Theta) and of the old middle
+  // sectors (two-site products), per ket on the host workers; scratch is then
+  // assigned in ket order
+  std::vector<std::vector<Blk>> pblk(ks.n), pth(ks.n);
+  host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
+    for (int s = 0; s < ks.nslot; ++s) {
+      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      Blk b{};
+      b.pair = t;
+      b.sa = sa;
+      b.sb = sb;
+      b.rs[0] = b.cs[0] = 0;
+      for (int k = 0; k < 4; ++k) {
+        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
+        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
+      }
+      b.R = b.rs[4];
+      b.C = b.cs[4];
+      if (b.R == 0 || b.C == 0) continue;
+      if (ks.dim_q(a + 1, t, sa, sb) > 0) pth[t].push_back(b);
+      plan_block(b);
+      pblk[t].push_back(b);
+    }
+  });
   std::vector<Blk> blks;
   Scratch sc;
-  for (int t = 0; t < ks.n; ++t) {
-    for (int s = 0; s < ks.nslot; ++s) {
-      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
-      Blk b{};
-      b.pair = t;
-      b.sa = sa;
-      b.sb = sb;
-      b.rs[0] = b.cs[0] = 0;
-      for (int k = 0; k < 4; ++k) {
-        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
-        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
-      }
-      b.R = b.rs[4];
-      b.C = b.cs[4];
-      if (b.R == 0 || b.C == 0) continue;
-      plan_block_storage(b, sc);
+  for (int t = 0; t < ks.n; ++t)
+    for (Blk &b : pblk[t]) {
+      take_block_storage(b, sc);
       blks.push_back(b);
     }
-  }
-  // two-site products per old middle sector (bond a+1 before the gate)
   std::vector<Blk> th;
   std::vector<int> thidx((size_t)ks.n * ks.nslot, -1);
-  for (int t = 0; t < ks.n; ++t) {
-    for (int s = 0; s < ks.nslot; ++s) {
-      const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
-      if (ks.dim_q(a + 1, t, sa, sb) == 0) continue;
-      Blk b{};
-      b.pair = t;
-      b.sa = sa;
-      b.sb = sb;
-      b.rs[0] = b.cs[0] = 0;
-      for (int k = 0; k < 4; ++k) {
-        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
-        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
-      }
-      b.R = b.rs[4];
-      b.C = b.cs[4];
-      if (b.R == 0 || b.C == 0) continue;
+  for (int t = 0; t < ks.n; ++t)
+    for (Blk &b : pth[t]) {
       b.offT = sc.take((int64_t)b.R * b.C);
-      thidx[(size_t)t * ks.nslot + s] = (int)th.size();
+      thidx[(size_t)t * ks.nslot + ks.slot(b.sa, b.sb)] = (int)th.size();
       th.push_back(b);
     }
-  }
   // singular values contiguous for one download
   int64_t s0 = sc.used, ns = 0;
   for (Blk &b : blks) {
