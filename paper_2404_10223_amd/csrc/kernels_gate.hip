@@ -3,7 +3,10 @@
 //
 // Every kernel works on a list of quantum-number blocks (one workgroup per
 // block).  Blocks of all kets in flight are launched together, so one launch
-// covers every pair of the subspace at the same gate position.
+// covers every pair of the subspace at the same gate position.  Site tensors
+// are stored dense, but every kernel (and the environment sweep) addresses
+// them by quantum-number block, so entries outside the blocks are never read
+// and are not cleared when a bond changes.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -219,16 +222,9 @@ __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, co
   const int pair = b.pair;
   double *A = kt.site[pair * kt.N + a];
   double *B = kt.site[pair * kt.N + a + 1];
-  const int Dl = kt.dim(a, pair), Dn = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
+  const int Dn = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
   const double *U = scratch + b.offU, *Bo = scratch + b.offB;
   const int kept = b.kept;
-  for (int64_t e = threadIdx.x; e < (int64_t)Dl * 4 * kept; e += kThreads) {
-    const int64_t row = e / kept;
-    A[row * Dn + b.j0 + (e - row * kept)] = 0.0;
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)kept * 4 * Dr; e += kThreads)
-    B[(int64_t)b.j0 * 4 * Dr + e] = 0.0;
-  __syncthreads();
   for (int64_t e = threadIdx.x; e < (int64_t)b.R * kept; e += kThreads) {
     const int row = e / kept, jj = e - (int64_t)row * kept;
     const int k = seg_of(b.rs, row);
@@ -270,15 +266,9 @@ __global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, cons
   double *A = kt.site[pair * kt.N + q];
   double *P = kt.site[pair * kt.N + q - 1];
   const double *Po = old_left[pair];
-  const int Dr = kt.dim(q + 1, pair), Dn = kt.dim(q, pair), Dl = kt.dim(q - 1, pair);
+  const int Dr = kt.dim(q + 1, pair), Dn = kt.dim(q, pair);
   const int Dold = b.aux1, n = b.n;
   const double *U = scratch + b.offU, *Bo = scratch + b.offB, *S = scratch + b.offS;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * 4 * Dr; e += kThreads) A[(int64_t)b.j0 * 4 * Dr + e] = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)Dl * 4 * n; e += kThreads) {
-    const int64_t row = e / n;
-    P[row * Dn + b.j0 + (e - row * n)] = 0.0;
-  }
-  __syncthreads();
   for (int64_t e = threadIdx.x; e < (int64_t)n * b.C; e += kThreads) {
     const int jj = e / b.C, col = e - (int64_t)jj * b.C;
     const int k = seg_of(b.cs, col);
@@ -326,14 +316,9 @@ __global__ void __launch_bounds__(kThreads) k_apply_qr(KetTables kt, int p, cons
   double *A = kt.site[pair * kt.N + p];
   double *Nx = kt.site[pair * kt.N + p + 1];
   const double *No = old_right[pair];
-  const int Dn = kt.dim(p + 1, pair), Dl = kt.dim(p, pair), Drr = kt.dim(p + 2, pair);
+  const int Dn = kt.dim(p + 1, pair), Drr = kt.dim(p + 2, pair);
   const int n = b.n;
   const double *U = scratch + b.offU, *Bo = scratch + b.offB;
-  for (int64_t e = threadIdx.x; e < (int64_t)Dl * 4 * n; e += kThreads) {
-    const int64_t row = e / n;
-    A[row * Dn + b.j0 + (e - row * n)] = 0.0;
-  }
-  __syncthreads();
   for (int64_t e = threadIdx.x; e < (int64_t)b.R * n; e += kThreads) {
     const int row = e / n, jj = e - (int64_t)row * n;
     const int k = seg_of(b.rs, row);
