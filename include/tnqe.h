@@ -202,11 +202,17 @@ const char *tnqe_version(void);
  *   index k_p * 4 + k_{p+1}.
  * tnqe_debug_mpo_dense: the library's MPO of H (N <= 5) contracted to dense
  *   4^N x 4^N matrices of H and of the identity channel, for h [N][N] and
- *   (pq|rs) g [N^4]; max_bond may be NULL. */
+ *   (pq|rs) g [N^4]; max_bond may be NULL.
+ * tnqe_debug_host_pool: runs `jobs` back-to-back parallel loops of 1..5
+ *   items on a pool of `workers` host threads (the pool the gate and
+ *   environment phases use) and checks that every item of every loop ran
+ *   exactly once; *calls receives the total number of item calls.  Returns
+ *   TNQE_EINVAL on bad arguments or when an item ran zero or several times. */
 tnqe_status tnqe_debug_givens(int32_t N, const double *W, int32_t *pos, double *theta, int32_t *det_sign);
 tnqe_status tnqe_debug_gate(double theta, double *out);
 tnqe_status tnqe_debug_mpo_dense(int32_t N, const double *h, const double *g, double *H, double *I,
                                  int32_t *max_bond);
+tnqe_status tnqe_debug_host_pool(int32_t workers, int32_t jobs, int64_t *calls);
 
 #ifdef __cplusplus
 }

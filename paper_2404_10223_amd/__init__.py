@@ -58,7 +58,7 @@ class _Report(C.Structure):
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
            "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_subspace",
            "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
-           "tnqe_debug_gate", "tnqe_debug_mpo_dense"]
+           "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool"]
 
 _lib = None
 
@@ -97,6 +97,7 @@ def lib():
     L.tnqe_debug_givens.argtypes = [ip, dp, C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]
     L.tnqe_debug_gate.argtypes = [C.c_double, dp]
     L.tnqe_debug_mpo_dense.argtypes = [ip, dp, dp, dp, dp, C.POINTER(C.c_int32)]
+    L.tnqe_debug_host_pool.argtypes = [ip, ip, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -262,6 +263,14 @@ def debug_gate(theta):
     out = np.zeros(256)
     _check(lib().tnqe_debug_gate(float(theta), _dptr(out)))
     return out.reshape(16, 16)
+
+
+def debug_host_pool(workers, jobs):
+    """Back-to-back parallel loops on the library's host worker pool; returns
+    the number of item calls (raises if an item ran zero or several times)."""
+    calls = C.c_int64(0)
+    _check(lib().tnqe_debug_host_pool(int(workers), int(jobs), C.byref(calls)))
+    return calls.value
 
 
 def debug_mpo_dense(h, g):

@@ -92,6 +92,9 @@ ThreadPool::ThreadPool(int workers) {
           cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
           if (stop_) return;
           seen = gen_;
+          // a job that has already returned (its caller cleared job_) is
+          // skipped: its index counter may belong to the next job by now
+          if (!job_) continue;
           f = job_;
           n = n_;
           ++busy_;
@@ -534,15 +537,21 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     lds[key] = std::max(lds[key], jp.lds);
     work[i] = (int64_t)b.n * b.n * m;
   }
-  // heaviest launches first, spread over the side streams so that launches
-  // of few large blocks run beside launches of many small ones
+  // launches in decreasing estimated duration, each on the side stream with
+  // the least estimated work so far (longest processing time first): the
+  // launch of the few largest blocks runs beside launches of many small ones.
+  // Duration estimate: the largest block's n m (rounds x vector length) or
+  // the launch's total n^2 m spread over the chip, whichever is larger.
   std::vector<std::pair<double, std::pair<int, int>>> order;
   for (auto &kv : groups) {
     std::vector<int> &idx = kv.second;
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return work[x] > work[y]; });
-    double w = 0.0;
-    for (int i : idx) w += (double)work[i];
-    order.push_back({-(double)work[idx[0]] * 1e3 - w, kv.first});
+    double w = 0.0, lat = 0.0;
+    for (int i : idx) {
+      w += (double)work[i];
+      lat = std::max(lat, (double)blks[i].n * std::max(blks[i].R, blks[i].C));
+    }
+    order.push_back({-std::max(lat, w / 2e4), kv.first});
   }
   std::sort(order.begin(), order.end());
   tnqe_ctx *ctx = c.ctx;
@@ -551,10 +560,15 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   for (size_t g = 0; g < order.size(); ++g) didx[g] = c.upload(groups[order[g].second]);
   TNQE_HIP(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int i = 0; i < nstream; ++i) TNQE_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+  double load[tnqe_ctx::kAux] = {};
   for (size_t g = 0; g < order.size(); ++g) {
     const auto key = order[g].second;
     const std::vector<int> &idx = groups[key];
-    hipStream_t s = ctx->aux[g % nstream];
+    int si = 0;
+    for (int i = 1; i < nstream; ++i)
+      if (load[i] < load[si]) si = i;
+    load[si] += -order[g].first;
+    hipStream_t s = ctx->aux[si];
     const bool timed = timer && timer->npending < SvdTimer::kMaxPending;
     const int slot = timed ? timer->npending : 0;
     if (timed) {
@@ -2170,6 +2184,29 @@ tnqe_status tnqe_debug_givens(int32_t N, const double *W, int32_t *pos, double *
   }
   *det_sign = d;
   return TNQE_OK;
+}
+
+tnqe_status tnqe_debug_host_pool(int32_t workers, int32_t jobs, int64_t *calls) {
+  if (workers < 0 || workers > 256 || jobs < 0 || !calls) return TNQE_EINVAL;
+  try {
+    tnqe::ThreadPool pool(workers);
+    std::atomic<int64_t> total{0};
+    for (int j = 0; j < jobs; ++j) {
+      const int n = 1 + j % 5;
+      std::vector<std::atomic<int>> hit(n);
+      for (auto &h : hit) h.store(0);
+      pool.parallel_for(n, [&](int i) {
+        hit[i].fetch_add(1);
+        total.fetch_add(1);
+      });
+      for (auto &h : hit)
+        if (h.load() != 1) return TNQE_EINVAL;
+    }
+    *calls = total.load();
+    return TNQE_OK;
+  } catch (...) {
+    return TNQE_EINVAL;
+  }
 }
 
 tnqe_status tnqe_debug_gate(double theta, double *out) {

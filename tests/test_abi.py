@@ -89,3 +89,13 @@ def test_host_mpo_dense_coupling_blocks(lib, N, monkeypatch):
     g = prob.g()
     H, I, _ = T.debug_mpo_dense(prob.h, g)
     np.testing.assert_allclose(H, fock.hamiltonian_fock(prob.h, g).toarray(), atol=1e-12)
+
+
+def test_host_pool_back_to_back_jobs():
+    """The host worker pool under many short back-to-back loops: a worker that
+    wakes after its loop has returned must not run the next loop's items with
+    the old function (every item runs exactly once)."""
+    jobs = 20000
+    assert T.debug_host_pool(7, jobs) == sum(1 + j % 5 for j in range(jobs))
+    assert T.debug_host_pool(0, 100) == sum(1 + j % 5 for j in range(100))
+
