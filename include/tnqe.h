@@ -132,12 +132,12 @@ typedef struct {
   double alg_bytes;                 /* algorithmic HBM bytes of the environment sweep   */
   double env_flops;                 /* environment-sweep part of alg_flops              */
   double env_kernel_ms;             /* summed device time of the environment kernels     */
-  double svd_kernel_ms;             /* summed device time of the truncation SVD launches */
+  double svd_kernel_ms;             /* summed device time of the block SVD launches     */
+                                    /*   (truncations and centre moves)                 */
   double svd_flops;                 /* their algorithmic flops (4 n^2 m + 9 n^3 a block) */
   double svd_kind_ms[16];           /* the same split by SVD kernel: entry k < 6 for    */
   double svd_kind_flops[16];        /*   4 (k + 1) vector elements per lane, entry 6 for */
-                                    /*   the global-memory fallback, 7 + j for the unit */
-                                    /*   kernels with 4 (j + 1) elements per lane       */
+                                    /*   the global-memory fallback, 7-15 unused        */
   double env_kind_ms[8];            /* environment kernels: 0 L x ket GEMM, 1 sparse    */
   double env_kind_flops[8];         /*   channel mix, 2 dense coupling GEMMs, 3 bra^T x */
   double env_kind_bytes[8];         /*   Y GEMM, 4 final element; device time, flops    */
@@ -146,7 +146,7 @@ typedef struct {
   int32_t n_pairs;                  /* unique pairs computed (M (M + 1) / 2)            */
   int32_t max_bond;                 /* largest bond dimension seen                      */
   int32_t mpo_max_bond;             /* largest MPO bond dimension                       */
-  int32_t svd_launches;             /* truncation SVD launches timed                    */
+  int32_t svd_launches;             /* block SVD launches timed                         */
   int32_t svd_kind_launches[16];    /* the same split by SVD kernel                     */
   int32_t env_kind_launches[8];     /* launches of each environment kernel              */
   int32_t n_fp32_pairs;             /* pairs contracted in FP32 (precision modes 1, 2)  */

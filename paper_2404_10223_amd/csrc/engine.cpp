@@ -496,9 +496,11 @@ struct SvdTimer {
   int launches = 0;
   double kind_ms[kJacobiKinds] = {}, kind_flops[kJacobiKinds] = {};
   int kind_launches[kJacobiKinds] = {};
+  // waits for the pending end events
   void collect(tnqe_ctx *ctx) {
     for (int k = 0; k < npending; ++k) {
       float t = 0.0f;
+      TNQE_HIP(hipEventSynchronize(ctx->svd_ev[2 * k + 1]));
       TNQE_HIP(hipEventElapsedTime(&t, ctx->svd_ev[2 * k], ctx->svd_ev[2 * k + 1]));
       ms += t;
       flops += pending_flops[k];
@@ -555,6 +557,7 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   }
   std::sort(order.begin(), order.end());
   tnqe_ctx *ctx = c.ctx;
+  if (timer && timer->npending + (int)order.size() > SvdTimer::kMaxPending) timer->collect(ctx);
   const int nstream = std::min<int>(tnqe_ctx::kAux, (int)order.size());
   std::vector<const int *> didx(order.size());
   for (size_t g = 0; g < order.size(); ++g) didx[g] = c.upload(groups[order[g].second]);
@@ -616,7 +619,7 @@ struct TruncStats {
 };
 
 // One exact LQ centre move (site q -> q-1) for every ket in the set.
-void move_left(KetSet &ks, int q, int max_sweeps) {
+void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
   Call &c = *ks.call;
   std::vector<std::vector<Blk>> pblk(ks.n);
   host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
@@ -676,7 +679,7 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
   Blk *dblk = c.upload(blks);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, max_sweeps, scratch);
+  run_svd(c, dblk, blks, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
   ks.commit_bond(q);
   launch_apply_lq(ks.tables(), q, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
@@ -684,7 +687,7 @@ void move_left(KetSet &ks, int q, int max_sweeps) {
 }
 
 // One exact QR centre move (site p -> p+1) for every ket in the set.
-void move_right(KetSet &ks, int p, int max_sweeps) {
+void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
   Call &c = *ks.call;
   std::vector<Blk> blks;
   Scratch sc;
@@ -733,7 +736,7 @@ void move_right(KetSet &ks, int p, int max_sweeps) {
   launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
   Blk *dblk = c.upload(blks);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, max_sweeps, scratch);
+  run_svd(c, dblk, blks, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
   ks.commit_bond(p + 1);
   launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
@@ -1688,7 +1691,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       }
       for (int p = 0; p + 1 < N; ++p) {
         const size_t mk = ctx->pool.mark();
-        move_right(canon, p, max_sweeps);
+        move_right(canon, p, max_sweeps, &ts.svd);
         c.sync();
         ctx->pool.rewind(mk);
       }
@@ -1733,7 +1736,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       const size_t mk = ctx->pool.mark();
       const auto tm0 = Clock::now();
       while (centre > a) {
-        move_left(kets, centre, max_sweeps);
+        move_left(kets, centre, max_sweeps, &ts.svd);
         --centre;
       }
       const auto tm1 = Clock::now();
@@ -1750,6 +1753,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       }
     }
     c.sync();
+    ts.svd.collect(ctx);
     if (debug_timing()) {
       std::fprintf(stderr,
                    "gate phase host: %d steps, move %.1f ms, gate step %.1f ms (build %.1f, two-site %.1f, "
