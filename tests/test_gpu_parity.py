@@ -101,6 +101,41 @@ def test_edge_cases(ctx):
     assert abs(E3 - E2) < 1e-9
 
 
+def test_determinants_match_slater_condon_full_size(ctx):
+    """chi = 1 determinants at N = 24 sharing one basis (U = I, so every gate
+    angle is zero and nothing is truncated): the pencil equals the
+    Slater-Condon closed forms, independently of the oracle's MPO -- the
+    diagonal, single and double excitations of both spin patterns."""
+    from test_oracle_mpo import _det_mps, _slater_condon
+    N = 24
+    base = synth.make_problem(N, N // 2, N // 2, 4, 1, 8, (9, N))
+    r = np.random.default_rng(N)
+    occ = set(r.choice(np.arange(0, 2 * N, 2), N // 2, replace=False)) | \
+        set(r.choice(np.arange(1, 2 * N, 2), N // 2, replace=False))
+    occ = {int(x) for x in occ}
+    up_occ = sorted(m for m in occ if m % 2 == 0)
+    up_vir = sorted(m for m in range(0, 2 * N, 2) if m not in occ)
+    dn_occ = sorted(m for m in occ if m % 2 == 1)
+    dn_vir = sorted(m for m in range(1, 2 * N, 2) if m not in occ)
+    dets = [occ,
+            (occ - {up_occ[0]}) | {up_vir[-1]},
+            (occ - {dn_occ[-1]}) | {dn_vir[0]},
+            (occ - {up_occ[1], dn_occ[0]}) | {up_vir[0], dn_vir[-1]},
+            (occ - {up_occ[0], up_occ[-1]}) | {up_vir[0], up_vir[-1]}]
+    mps = []
+    for d in dets:
+        sites, qn = _det_mps(N, d)
+        mps.append(synth.MPS(sites=sites, bond_qn=qn, U=np.eye(N)))
+    prob = _with(base, mps=mps, chi=1)
+    H, S, E, c, rep = ctx.subspace(prob, chi=1)
+    h, g = prob.h, prob.g()
+    for i in range(len(dets)):
+        for j in range(len(dets)):
+            want = _slater_condon(h, g, sorted(dets[i]), sorted(dets[j]))
+            assert abs(H[i, j] - want) <= 1e-11 * max(1.0, abs(want)), (i, j, H[i, j], want)
+    np.testing.assert_allclose(S, np.eye(len(dets)), rtol=0, atol=1e-13)
+
+
 def test_input_validation(ctx):
     base = synth.make_problem(4, 2, 2, 4, 2, 3, (32,))
     bad_u = _with(base, mps=[base.mps[0], synth.MPS(base.mps[1].sites, base.mps[1].bond_qn, base.mps[1].U * 1.01)])
