@@ -198,6 +198,22 @@ struct Call {   // per-call helpers bound to a context
     }
     return d;
   }
+  // several host arrays in one upload: add() returns each array's byte offset
+  struct Blob {
+    std::vector<char> bytes;
+    template <typename T>
+    size_t add(const std::vector<T> &v) {
+      const size_t off = (bytes.size() + 255) & ~size_t(255);
+      bytes.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+      if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+      return off;
+    }
+  };
+  char *upload(const Blob &b) { return upload(b.bytes); }
+  template <typename T>
+  static T *at(char *base, size_t off) {
+    return reinterpret_cast<T *>(base + off);
+  }
   template <typename T>
   void upload_to(T *d, const T *src, size_t n) {
     if (n == 0) return;
@@ -560,7 +576,13 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   if (timer && timer->npending + (int)order.size() > SvdTimer::kMaxPending) timer->collect(ctx);
   const int nstream = std::min<int>(tnqe_ctx::kAux, (int)order.size());
   std::vector<const int *> didx(order.size());
-  for (size_t g = 0; g < order.size(); ++g) didx[g] = c.upload(groups[order[g].second]);
+  {
+    Call::Blob bl;
+    std::vector<size_t> off(order.size());
+    for (size_t g = 0; g < order.size(); ++g) off[g] = bl.add(groups[order[g].second]);
+    char *base = c.upload(bl);
+    for (size_t g = 0; g < order.size(); ++g) didx[g] = Call::at<const int>(base, off[g]);
+  }
   TNQE_HIP(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int i = 0; i < nstream; ++i) TNQE_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
   double load[tnqe_ctx::kAux] = {};
@@ -674,9 +696,12 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
     srcs[t] = ks.site_ptr[(size_t)t * ks.N + q - 1];
     cnt[t] = (int64_t)ks.htot[(size_t)(q - 1) * ks.n + t] * 4 * ks.htot[(size_t)q * ks.n + t];
   }
-  double **d_old = c.upload(olds);
-  launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
-  Blk *dblk = c.upload(blks);
+  Call::Blob bl;
+  const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
+  char *base = c.upload(bl);
+  double **d_old = Call::at<double *>(base, o_old);
+  launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
+  Blk *dblk = Call::at<Blk>(base, o_blk);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, timer);
@@ -732,9 +757,12 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
     srcs[t] = ks.site_ptr[(size_t)t * ks.N + p + 1];
     cnt[t] = (int64_t)ks.htot[(size_t)(p + 1) * ks.n + t] * 4 * ks.htot[(size_t)(p + 2) * ks.n + t];
   }
-  double **d_old = c.upload(olds);
-  launch_copy(d_old, c.upload(srcs), c.upload(cnt), ks.n, c.ctx->stream);
-  Blk *dblk = c.upload(blks);
+  Call::Blob bl;
+  const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
+  char *base = c.upload(bl);
+  double **d_old = Call::at<double *>(base, o_old);
+  launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
+  Blk *dblk = Call::at<Blk>(base, o_blk);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
@@ -796,9 +824,13 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   sc.used += ns;
   const auto tb1 = Clock::now();
   double *scratch = c.dev<double>(sc.used);
-  double *dgates = c.upload(gates);
-  Blk *dblk = c.upload(blks);
-  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), c.upload(th), (int)th.size(), c.upload(thidx), dgates,
+  Call::Blob bl;
+  const size_t o_g = bl.add(gates), o_b = bl.add(blks), o_t = bl.add(th), o_i = bl.add(thidx);
+  char *base = c.upload(bl);
+  const double *dgates = Call::at<const double>(base, o_g);
+  Blk *dblk = Call::at<Blk>(base, o_b);
+  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), Call::at<const Blk>(base, o_t), (int)th.size(),
+                  Call::at<const int>(base, o_i), dgates,
                   scratch, c.ctx->stream);
   const auto tb2 = Clock::now();
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
