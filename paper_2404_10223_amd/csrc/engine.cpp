@@ -402,6 +402,18 @@ struct Scratch {
   }
 };
 
+// Work-unit prefix of a block list for the gate-phase kernels (first[0] = 0,
+// first[n] = total units); units(b) gives a block's count.
+template <class F>
+std::vector<int> unit_prefix(const std::vector<Blk> &blks, F units) {
+  std::vector<int> f(blks.size() + 1, 0);
+  for (size_t i = 0; i < blks.size(); ++i) f[i + 1] = f[i] + units(blks[i]);
+  return f;
+}
+Units units_at(char *base, size_t off, const std::vector<int> &f) {
+  return Units{Call::at<const int>(base, off), (int)f.size() - 1, f.back()};
+}
+
 // Launch shape of the Jacobi SVD of an n-vector block with vectors of length
 // m: ceil(n/2) processors of G lanes, E vector components per lane in
 // registers (G E >= m), floor(n/2) traveller vectors in LDS rows of
@@ -696,18 +708,29 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
     srcs[t] = ks.site_ptr[(size_t)t * ks.N + q - 1];
     cnt[t] = (int64_t)ks.htot[(size_t)(q - 1) * ks.n + t] * 4 * ks.htot[(size_t)q * ks.n + t];
   }
+  const std::vector<int> u_gather =
+      unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
+  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
+  // the new rows of A_q, then the tiles of the left neighbour's products
+  // (bond q-1 is not changed by the move)
+  const std::vector<int> u_apply = unit_prefix(blks, [&](const Blk &b) {
+    int u = gate_chunks((int64_t)b.n * b.C);
+    for (int k = 0; k < 4; ++k) u += gate_tiles(ks.dim_q(q - 1, b.pair, b.sa - qk_a(k), b.sb - qk_b(k)), b.n);
+    return u;
+  });
   Call::Blob bl;
   const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
+  const size_t o_ug = bl.add(u_gather), o_uf = bl.add(u_factor), o_ua = bl.add(u_apply);
   char *base = c.upload(bl);
   double **d_old = Call::at<double *>(base, o_old);
   launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
   Blk *dblk = Call::at<Blk>(base, o_blk);
   const KetTables kt_old = ks.tables();
-  launch_gather_lq(kt_old, q, dblk, (int)blks.size(), scratch, c.ctx->stream);
+  launch_gather_lq(kt_old, q, dblk, units_at(base, o_ug, u_gather), scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, timer);
-  launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
+  launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, c.ctx->stream);
   ks.commit_bond(q);
-  launch_apply_lq(ks.tables(), q, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
+  launch_apply_lq(ks.tables(), q, dblk, units_at(base, o_ua, u_apply), scratch, d_old, c.ctx->stream);
   c.check_launch();
 }
 
@@ -757,15 +780,17 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
     srcs[t] = ks.site_ptr[(size_t)t * ks.N + p + 1];
     cnt[t] = (int64_t)ks.htot[(size_t)(p + 1) * ks.n + t] * 4 * ks.htot[(size_t)(p + 2) * ks.n + t];
   }
+  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
   Call::Blob bl;
   const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
+  const size_t o_uf = bl.add(u_factor);
   char *base = c.upload(bl);
   double **d_old = Call::at<double *>(base, o_old);
   launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
   Blk *dblk = Call::at<Blk>(base, o_blk);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, timer);
-  launch_svd_factor(dblk, (int)blks.size(), scratch, c.ctx->stream);
+  launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, c.ctx->stream);
   ks.commit_bond(p + 1);
   launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
   c.check_launch();
@@ -824,14 +849,18 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   sc.used += ns;
   const auto tb1 = Clock::now();
   double *scratch = c.dev<double>(sc.used);
+  const std::vector<int> u_gate =
+      unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
+  const std::vector<int> u_theta = unit_prefix(th, [](const Blk &b) { return gate_tiles(b.R, b.C); });
   Call::Blob bl;
   const size_t o_g = bl.add(gates), o_b = bl.add(blks), o_t = bl.add(th), o_i = bl.add(thidx);
+  const size_t o_ug = bl.add(u_gate), o_ut = bl.add(u_theta);
   char *base = c.upload(bl);
   const double *dgates = Call::at<const double>(base, o_g);
   Blk *dblk = Call::at<Blk>(base, o_b);
-  launch_two_site(ks.tables(), a, dblk, (int)blks.size(), Call::at<const Blk>(base, o_t), (int)th.size(),
-                  Call::at<const int>(base, o_i), dgates,
-                  scratch, c.ctx->stream);
+  launch_two_site(ks.tables(), a, dblk, units_at(base, o_ug, u_gate), Call::at<const Blk>(base, o_t),
+                  units_at(base, o_ut, u_theta), Call::at<const int>(base, o_i), dgates, scratch,
+                  c.ctx->stream);
   const auto tb2 = Clock::now();
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
   const auto tb3 = Clock::now();
@@ -920,9 +949,14 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
     b.j0 = acc;
   }
   ks.commit_bond(a + 1);
-  Blk *dblk2 = c.upload(blks);
-  launch_svd_factor(dblk2, (int)blks.size(), scratch, c.ctx->stream);
-  launch_split_gate(ks.tables(), a, dblk2, (int)blks.size(), scratch, c.ctx->stream);
+  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
+  const std::vector<int> u_split = unit_prefix(blks, split_units);
+  Call::Blob bl2;
+  const size_t o_b2 = bl2.add(blks), o_uf = bl2.add(u_factor), o_us = bl2.add(u_split);
+  char *base2 = c.upload(bl2);
+  Blk *dblk2 = Call::at<Blk>(base2, o_b2);
+  launch_svd_factor(dblk2, units_at(base2, o_uf, u_factor), scratch, c.ctx->stream);
+  launch_split_gate(ks.tables(), a, dblk2, units_at(base2, o_us, u_split), scratch, c.ctx->stream);
   c.check_launch();
   if (debug_timing()) g_gate_timing.post_ms += ms_between(ts2, Clock::now());
 }

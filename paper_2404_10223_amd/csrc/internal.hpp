@@ -67,9 +67,45 @@ struct KetTables {
   __host__ __device__ int dim(int bond, int pair) const { return bdim[bond * npair + pair]; }
 };
 
-// two-site products per old middle sector (th[0..nth)), then the gate into
-// the blocks of the new middle bond (thidx[pair * nslot + slot]: Theta block)
-void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const Blk *th, int nth,
+// Work units of the gate-phase kernels.  A launch over a block list runs one
+// workgroup per unit (a 64 x 64 output tile of a product, or a chunk of
+// kGateChunk elements of a gather or scatter), so a large block is spread over
+// many compute units instead of looping in one workgroup.  first[i] is the
+// first unit of block i (prefix sums, first[n] = total); the host computes the
+// counts with the same functions the kernels use to split a unit index.
+constexpr int kGateTile = 64, kGateChunk = 2048;
+__host__ __device__ inline int gate_tiles(int M, int N) {
+  return M <= 0 || N <= 0 ? 0 : ((M + kGateTile - 1) / kGateTile) * ((N + kGateTile - 1) / kGateTile);
+}
+__host__ __device__ inline int gate_chunks(int64_t n) { return (int)((n + kGateChunk - 1) / kGateChunk); }
+// block of unit x: first[i] <= x < first[i + 1] (blocks without units skipped)
+__host__ __device__ inline int find_unit(const int *first, int n, int x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+struct Units {
+  const int *first;   // device prefix array [n + 1]
+  int n, total;
+};
+// units per block of the split of a truncated two-site block (new A_a
+// columns, then new A_{a+1} rows) and of an LQ move's gather
+__host__ __device__ inline int split_units(const Blk &b) {
+  return b.kept == 0 ? 0 : gate_chunks((int64_t)b.R * b.kept) + gate_chunks((int64_t)b.kept * b.C);
+}
+// units of the factor product (the kept vectors times the block)
+__host__ __device__ inline int factor_units(const Blk &b) {
+  return b.kept == 0 ? 0 : gate_tiles(b.kept, b.R >= b.C ? b.C : b.R);
+}
+
+// two-site products per old middle sector (th[0..nth), units: output tiles),
+// then the gate into the blocks of the new middle bond (units: element
+// chunks; thidx[pair * nslot + slot]: Theta block)
+void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const Blk *th, Units ut,
                      const int *thidx, const double *gates, double *scratch, hipStream_t st);
 // Jacobi SVD of the blocks idx[0..nblk) of blk: sorted singular values (offS)
 // and sorted rotated vectors (U = x / s in the columns case, B = x in the rows
@@ -81,13 +117,19 @@ constexpr int jacobi_max_threads(int E) { return E > 20 ? 768 : 1024; }
 constexpr int kJacobiLdsBytes = 160 * 1024 - 1024;   // dynamic LDS cap per workgroup
 void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,
                    double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st);
-// the other factor of the first `kept` sorted vectors of every block
-void launch_svd_factor(const Blk *blk, int nblk, double *scratch, hipStream_t st);
-void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
+// the other factor of the first `kept` sorted vectors of every block (units:
+// factor_units)
+void launch_svd_factor(const Blk *blk, Units u, double *scratch, hipStream_t st);
+// units: split_units
+void launch_split_gate(const KetTables &kt, int a, const Blk *blk, Units u, const double *scratch,
                        hipStream_t st);
-void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, int nblk, double *scratch,
+// units: gate_chunks(R C)
+void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, Units u, double *scratch,
                       hipStream_t st);
-void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, int nblk, const double *scratch,
+// units: gate_chunks(n C) for the new A_q rows, then for k = 0..3 the tiles
+// gate_tiles(d_k, n) of the left neighbour's product, d_k the dimension of
+// the bond q-1 sector that feeds the block through local state k
+void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, Units u, const double *scratch,
                      double *const *old_left, hipStream_t st);
 void launch_gather_qr(const KetTables &kt, int p, const Blk *blk, int nblk, double *scratch,
                       hipStream_t st);

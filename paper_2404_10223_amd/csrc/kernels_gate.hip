@@ -1,9 +1,11 @@
 // Gate phase on gfx950: two-site gate contraction, split of the truncated
 // factors, and exact centre moves (the SVDs are in kernels_svd.hip).
 //
-// Every kernel works on a list of quantum-number blocks (one workgroup per
-// block).  Blocks of all kets in flight are launched together, so one launch
-// covers every pair of the subspace at the same gate position.  Site tensors
+// Every kernel works on a list of quantum-number blocks.  Blocks of all kets
+// in flight are launched together, so one launch covers every pair of the
+// subspace at the same gate position; the blocks are cut into work units
+// (output tiles or element chunks, one workgroup each) so that the few large
+// blocks of a launch do not leave most compute units idle.  Site tensors
 // are stored dense, but every kernel (and the environment sweep) addresses
 // them by quantum-number block, so entries outside the blocks are never read
 // and are not cleared when a bond changes.
@@ -18,84 +20,108 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
+// The block descriptor of a workgroup, staged in LDS: the segment tables are
+// indexed with run-time indices, which would put a register copy of the
+// descriptor in per-lane scratch memory.
+__device__ const Blk &stage_block(const Blk *blks, int i) {
+  __shared__ Blk s_blk;
+  if (threadIdx.x == 0) s_blk = blks[i];
+  __syncthreads();
+  return s_blk;
+}
+
 __device__ inline int seg_of(const int *s, int x) {
   int k = 0;
   while (k < 3 && x >= s[k + 1]) ++k;
   return k;
 }
 
-// All 64 x 64 tiles of an M x N product C = A B for one workgroup (4 x 4 per
-// thread, K through LDS in steps of 16); la(m, k) and lb(k, n) load operands,
-// sc(m, n, v) stores.  A tiles are filled with k fastest; B tiles with k
-// fastest when BK (B contiguous along k), else with n fastest.
+// One 64 x 64 tile (rows m0.., columns n0..) of an M x N product C = A B
+// (4 x 4 per thread, K through LDS in steps of 16); la(m, k) and lb(k, n)
+// load operands, sc(m, n, v) stores.  A tiles are filled with k fastest; B
+// tiles with k fastest when BK (B contiguous along k), else with n fastest.
+constexpr int kKC = 16;
+typedef double GemmTile[kKC][kGateTile + 1];
 template <bool BK, class LA, class LB, class SC>
-__device__ void block_gemm(int M, int N, int K, LA la, LB lb, SC sc) {
-  constexpr int TT = 64, KC = 16;
-  __shared__ double sA[KC][TT + 1];
-  __shared__ double sB[KC][TT + 1];
+__device__ void gemm_tile(GemmTile &sA, GemmTile &sB, int M, int N, int K, int m0, int n0, LA la, LB lb,
+                          SC sc) {
+  constexpr int TT = kGateTile, KC = kKC;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int tilesN = (N + TT - 1) / TT, ntile = ((M + TT - 1) / TT) * tilesN;
-  for (int tile = 0; tile < ntile; ++tile) {
-    const int m0 = (tile / tilesN) * TT, n0 = (tile % tilesN) * TT;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
-        const int kk = e % KC, mm = e / KC;
-        const int gm = m0 + mm, gk = k0 + kk;
-        sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : 0.0;
-        if (BK) {
-          const int gn = n0 + mm;
-          sB[kk][mm] = (gn < N && gk < K) ? lb(gk, gn) : 0.0;
-        } else {
-          const int nn = e % TT, kb = e / TT;
-          const int gn = n0 + nn, gkb = k0 + kb;
-          sB[kb][nn] = (gn < N && gkb < K) ? lb(gkb, gn) : 0.0;
-        }
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
+      const int kk = e % KC, mm = e / KC;
+      const int gm = m0 + mm, gk = k0 + kk;
+      sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : 0.0;
+      if (BK) {
+        const int gn = n0 + mm;
+        sB[kk][mm] = (gn < N && gk < K) ? lb(gk, gn) : 0.0;
+      } else {
+        const int nn = e % TT, kb = e / TT;
+        const int gn = n0 + nn, gkb = k0 + kb;
+        sB[kb][nn] = (gn < N && gkb < K) ? lb(gkb, gn) : 0.0;
       }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          av[u] = sA[kk][ty + 16 * u];
-          bv[u] = sB[kk][tx + 16 * u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-      }
-      __syncthreads();
     }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int gm = m0 + ty + 16 * u;
-      if (gm >= M) continue;
+    for (int kk = 0; kk < KC; ++kk) {
+      double av[4], bv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gn = n0 + tx + 16 * v;
-        if (gn < N) sc(gm, gn, acc[u][v]);
+      for (int u = 0; u < 4; ++u) {
+        av[u] = sA[kk][ty + 16 * u];
+        bv[u] = sB[kk][tx + 16 * u];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int gm = m0 + ty + 16 * u;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gn = n0 + tx + 16 * v;
+      if (gn < N) sc(gm, gn, acc[u][v]);
     }
   }
 }
 
+// tile t of an M x N product (row-major tile order)
+template <bool BK, class LA, class LB, class SC>
+__device__ void gemm_tile_at(GemmTile &sA, GemmTile &sB, int M, int N, int K, int t, LA la, LB lb, SC sc) {
+  const int tilesN = (N + kGateTile - 1) / kGateTile;
+  gemm_tile<BK>(sA, sB, M, N, K, (t / tilesN) * kGateTile, (t % tilesN) * kGateTile, la, lb, sc);
+}
+
+// All tiles of a product in one workgroup (used where a launch has few,
+// small blocks: the QR moves of the initial canonical form).
+template <bool BK, class LA, class LB, class SC>
+__device__ void block_gemm(int M, int N, int K, LA la, LB lb, SC sc) {
+  __shared__ GemmTile sA, sB;
+  const int nt = gate_tiles(M, N);
+  for (int t = 0; t < nt; ++t) gemm_tile_at<BK>(sA, sB, M, N, K, t, la, lb, sc);
+}
+
 // Two-site product per old middle sector ms = (sa, sb) of bond a+1:
 // Theta[(k1, l)][(k2, r)] = sum_m A_a[l, k1, m] A_{a+1}[m, k2, r], with l in
-// the left sector ms - q(k1) and r in the right sector ms + q(k2).  A tiled
-// GEMM (64 x 64 outputs per step, 4 x 4 per thread, K through LDS by 16).
-__global__ void __launch_bounds__(kThreads) k_theta(KetTables kt, int a, const Blk *th, double *scratch) {
-  constexpr int TT = 64, KC = 16;
-  const Blk b = th[blockIdx.x];
+// the left sector ms - q(k1) and r in the right sector ms + q(k2).  One
+// 64 x 64 output tile per workgroup.
+__global__ void __launch_bounds__(kThreads) k_theta(KetTables kt, int a, const Blk *th, Units un,
+                                                    double *scratch) {
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const int t = blockIdx.x - un.first[bi];
+  const Blk &b = stage_block(th, bi);
   const int pair = b.pair;
   const double *A = kt.site[pair * kt.N + a];
   const double *B = kt.site[pair * kt.N + a + 1];
   const int Dm = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
   const int2 mid = kt.sec(a + 1, pair, b.sa, b.sb);
   __shared__ int s_lo[4], s_ro[4];
-  __shared__ double sA[KC][TT + 1];
-  __shared__ double sB[KC][TT];
+  __shared__ GemmTile sA, sB;
   if (threadIdx.x < 4) {
     const int k = threadIdx.x;
     s_lo[k] = kt.sec(a, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x;
@@ -103,74 +129,32 @@ __global__ void __launch_bounds__(kThreads) k_theta(KetTables kt, int a, const B
   }
   __syncthreads();
   double *Th = scratch + b.offT;
-  const int K = mid.y, R = b.R, C = b.C;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int tilesC = (C + TT - 1) / TT;
-  for (int tile = 0; tile < ((R + TT - 1) / TT) * tilesC; ++tile) {
-    const int m0 = (tile / tilesC) * TT, n0 = (tile % tilesC) * TT;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
-        // A tile: row (k1, l), middle index along the fast direction
-        {
-          const int mm = e / KC, kk = e % KC;
-          const int row = m0 + mm, m = k0 + kk;
-          double v = 0.0;
-          if (row < R && m < K) {
-            const int k1 = seg_of(b.rs, row);
-            v = A[((int64_t)(s_lo[k1] + row - b.rs[k1]) * 4 + k1) * Dm + mid.x + m];
-          }
-          sA[kk][mm] = v;
-        }
-        // B tile: column (k2, r) along the fast direction
-        {
-          const int kk = e / TT, nn = e % TT;
-          const int col = n0 + nn, m = k0 + kk;
-          double v = 0.0;
-          if (col < C && m < K) {
-            const int k2 = seg_of(b.cs, col);
-            v = B[((int64_t)(mid.x + m) * 4 + k2) * Dr + s_ro[k2] + col - b.cs[k2]];
-          }
-          sB[kk][nn] = v;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          av[u] = sA[kk][ty + 16 * u];
-          bv[u] = sB[kk][tx + 16 * u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int row = m0 + ty + 16 * u;
-      if (row >= R) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = n0 + tx + 16 * v;
-        if (col < C) Th[(int64_t)row * C + col] = acc[u][v];
-      }
-    }
-  }
+  const int C = b.C;
+  // A rows (k1, l) are contiguous along the middle index; B columns (k2, r)
+  // along the right index
+  gemm_tile_at<false>(
+      sA, sB, b.R, C, mid.y, t,
+      [&](int row, int m) {
+        const int k1 = seg_of(b.rs, row);
+        return A[((int64_t)(s_lo[k1] + row - b.rs[k1]) * 4 + k1) * Dm + mid.x + m];
+      },
+      [&](int m, int col) {
+        const int k2 = seg_of(b.cs, col);
+        return B[((int64_t)(mid.x + m) * 4 + k2) * Dr + s_ro[k2] + col - b.cs[k2]];
+      },
+      [&](int row, int col, double v) { Th[(int64_t)row * C + col] = v; });
 }
 
 // T'[(k1', l)][(k2', r)] = sum_{k1,k2} G[(k1',k2'),(k1,k2)] Theta_ms[(k1, l)][(k2, r)]
 // with ms = s - q(k1') + q(k1) (the gate conserves both particle numbers, so
 // the row and column sectors of the two sides agree).  thidx[pair][slot] is
 // the Theta block of a middle sector (-1: none, the product is empty).
-__global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Blk *blks, const Blk *th,
-                                                          const int *thidx, const double *gates,
-                                                          double *scratch) {
-  const Blk b = blks[blockIdx.x];
+__global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Blk *blks, Units un,
+                                                          const Blk *th, const int *thidx,
+                                                          const double *gates, double *scratch) {
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const Blk &b = stage_block(blks, bi);
+  const int64_t e0 = (int64_t)(blockIdx.x - un.first[bi]) * kGateChunk;
   const int pair = b.pair;
   __shared__ double sG[256];
   __shared__ int64_t s_off[16];
@@ -193,8 +177,8 @@ __global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Bl
   }
   __syncthreads();
   double *T = scratch + b.offT;
-  const int total = b.R * b.C;
-  for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+  const int total = (int)min<int64_t>((int64_t)b.R * b.C, e0 + kGateChunk);
+  for (int idx = (int)e0 + threadIdx.x; idx < total; idx += kThreads) {
     const int row = idx / b.C, col = idx - row * b.C;
     const int k1p = seg_of(b.rs, row), k2p = seg_of(b.cs, col);
     const int l = row - b.rs[k1p], r = col - b.cs[k2p];
@@ -214,24 +198,31 @@ __global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Bl
   }
 }
 
-// New A_a columns and A_{a+1} rows of one kept block (zero, then scatter).
-__global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, const Blk *blks,
+// New A_a columns and A_{a+1} rows of one kept block (scatter); units: the
+// chunks of the R x kept columns, then those of the kept x C rows.
+__global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, const Blk *blks, Units un,
                                                          const double *scratch) {
-  const Blk b = blks[blockIdx.x];
-  if (b.kept == 0) return;
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const Blk &b = stage_block(blks, bi);
   const int pair = b.pair;
   double *A = kt.site[pair * kt.N + a];
   double *B = kt.site[pair * kt.N + a + 1];
   const int Dn = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
   const double *U = scratch + b.offU, *Bo = scratch + b.offB;
   const int kept = b.kept;
-  for (int64_t e = threadIdx.x; e < (int64_t)b.R * kept; e += kThreads) {
-    const int row = e / kept, jj = e - (int64_t)row * kept;
-    const int k = seg_of(b.rs, row);
-    const int l = kt.sec(a, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x + (row - b.rs[k]);
-    A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)jj * b.R + row];
+  const int u = blockIdx.x - un.first[bi], u1 = gate_chunks((int64_t)b.R * kept);
+  if (u < u1) {
+    const int64_t e0 = (int64_t)u * kGateChunk, e1 = min<int64_t>((int64_t)b.R * kept, e0 + kGateChunk);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+      const int row = e / kept, jj = e - (int64_t)row * kept;
+      const int k = seg_of(b.rs, row);
+      const int l = kt.sec(a, pair, b.sa - qk_a(k), b.sb - qk_b(k)).x + (row - b.rs[k]);
+      A[((int64_t)l * 4 + k) * Dn + b.j0 + jj] = U[(int64_t)jj * b.R + row];
+    }
+    return;
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)kept * b.C; e += kThreads) {
+  const int64_t e0 = (int64_t)(u - u1) * kGateChunk, e1 = min<int64_t>((int64_t)kept * b.C, e0 + kGateChunk);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
     const int jj = e / b.C, col = e - (int64_t)jj * b.C;
     const int k = seg_of(b.cs, col);
     const int r = kt.sec(a + 2, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x + (col - b.cs[k]);
@@ -241,14 +232,17 @@ __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, co
 
 // LQ move at site q: block = rows of sector s of bond q, columns (k, r).
 // aux0 = offset of the sector in the (old) bond q.
-__global__ void __launch_bounds__(kThreads) k_gather_lq(KetTables kt, int q, const Blk *blks,
+__global__ void __launch_bounds__(kThreads) k_gather_lq(KetTables kt, int q, const Blk *blks, Units un,
                                                         double *scratch) {
-  const Blk b = blks[blockIdx.x];
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const Blk &b = stage_block(blks, bi);
   const int pair = b.pair;
   const double *A = kt.site[pair * kt.N + q];
   const int Dr = kt.dim(q + 1, pair);
   double *T = scratch + b.offT;
-  for (int64_t e = threadIdx.x; e < (int64_t)b.R * b.C; e += kThreads) {
+  const int64_t e0 = (int64_t)(blockIdx.x - un.first[bi]) * kGateChunk;
+  const int64_t e1 = min<int64_t>((int64_t)b.R * b.C, e0 + kGateChunk);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
     const int row = e / b.C, col = e - (int64_t)row * b.C;
     const int k = seg_of(b.cs, col);
     const int r = kt.sec(q + 1, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x + (col - b.cs[k]);
@@ -258,10 +252,13 @@ __global__ void __launch_bounds__(kThreads) k_gather_lq(KetTables kt, int q, con
 
 // A_q rows <- V^T rows; A_{q-1} columns <- old A_{q-1} U Sigma.
 // aux0 = old offset of the sector in bond q, aux1 = old dimension of bond q.
-__global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, const Blk *blks,
+// Units: chunks of the n x C new rows, then per local state k the tiles of
+// the left neighbour's d_k x n product.
+__global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, const Blk *blks, Units un,
                                                        const double *scratch,
                                                        double *const *old_left) {
-  const Blk b = blks[blockIdx.x];
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const Blk &b = stage_block(blks, bi);
   const int pair = b.pair;
   double *A = kt.site[pair * kt.N + q];
   double *P = kt.site[pair * kt.N + q - 1];
@@ -269,23 +266,37 @@ __global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, cons
   const int Dr = kt.dim(q + 1, pair), Dn = kt.dim(q, pair);
   const int Dold = b.aux1, n = b.n;
   const double *U = scratch + b.offU, *Bo = scratch + b.offB, *S = scratch + b.offS;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * b.C; e += kThreads) {
-    const int jj = e / b.C, col = e - (int64_t)jj * b.C;
-    const int k = seg_of(b.cs, col);
-    const int r = kt.sec(q + 1, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x + (col - b.cs[k]);
-    const double s = S[jj];
-    A[((int64_t)(b.j0 + jj) * 4 + k) * Dr + r] = s > 0.0 ? Bo[(int64_t)jj * b.C + col] / s : 0.0;
+  int u = blockIdx.x - un.first[bi];
+  const int u1 = gate_chunks((int64_t)n * b.C);
+  if (u < u1) {
+    const int64_t e0 = (int64_t)u * kGateChunk, e1 = min<int64_t>((int64_t)n * b.C, e0 + kGateChunk);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+      const int jj = e / b.C, col = e - (int64_t)jj * b.C;
+      const int k = seg_of(b.cs, col);
+      const int r = kt.sec(q + 1, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x + (col - b.cs[k]);
+      const double s = S[jj];
+      A[((int64_t)(b.j0 + jj) * 4 + k) * Dr + r] = s > 0.0 ? Bo[(int64_t)jj * b.C + col] / s : 0.0;
+    }
+    return;
   }
-  // P[(l, k)][j0 + jj] = S[jj] sum_mm Po[(l, k)][aux0 + mm] U[jj][mm], one product per k
+  u -= u1;
+  // P[(l, k)][j0 + jj] = S[jj] sum_mm Po[(l, k)][aux0 + mm] U[jj][mm]
+  __shared__ GemmTile sA, sB;
   for (int k = 0; k < 4; ++k) {
     const int2 ls = kt.sec(q - 1, pair, b.sa - qk_a(k), b.sb - qk_b(k));
+    const int nt = gate_tiles(ls.y, n);
+    if (u >= nt) {
+      u -= nt;
+      continue;
+    }
     const double *Pk = Po + ((int64_t)ls.x * 4 + k) * Dold + b.aux0;
     double *Ck = P + ((int64_t)ls.x * 4 + k) * Dn + b.j0;
     const int R = b.R;
-    block_gemm<true>(
-        ls.y, n, R, [&](int li, int mm) { return Pk[(int64_t)li * 4 * Dold + mm]; },
+    gemm_tile_at<true>(
+        sA, sB, ls.y, n, R, u, [&](int li, int mm) { return Pk[(int64_t)li * 4 * Dold + mm]; },
         [&](int mm, int jj) { return U[(int64_t)jj * R + mm]; },
         [&](int li, int jj, double v) { Ck[(int64_t)li * 4 * Dn + jj] = v * S[jj]; });
+    return;
   }
 }
 
@@ -293,7 +304,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_lq(KetTables kt, int q, cons
 // aux0 = offset of the sector in the (old) bond p+1.
 __global__ void __launch_bounds__(kThreads) k_gather_qr(KetTables kt, int p, const Blk *blks,
                                                         double *scratch) {
-  const Blk b = blks[blockIdx.x];
+  const Blk &b = stage_block(blks, blockIdx.x);
   const int pair = b.pair;
   const double *A = kt.site[pair * kt.N + p];
   const int Dr = kt.dim(p + 1, pair);
@@ -311,7 +322,7 @@ __global__ void __launch_bounds__(kThreads) k_gather_qr(KetTables kt, int p, con
 __global__ void __launch_bounds__(kThreads) k_apply_qr(KetTables kt, int p, const Blk *blks,
                                                        const double *scratch,
                                                        double *const *old_right) {
-  const Blk b = blks[blockIdx.x];
+  const Blk &b = stage_block(blks, blockIdx.x);
   const int pair = b.pair;
   double *A = kt.site[pair * kt.N + p];
   double *Nx = kt.site[pair * kt.N + p + 1];
@@ -353,29 +364,30 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 
 }  // namespace
 
-void launch_two_site(const KetTables &kt, int a, const Blk *blk, int nblk, const Blk *th, int nth,
+void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const Blk *th, Units ut,
                      const int *thidx, const double *gates, double *scratch, hipStream_t st) {
-  if (nth > 0) hipLaunchKernelGGL(k_theta, dim3(nth), dim3(kThreads), 0, st, kt, a, th, scratch);
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_gate_gather, dim3(nblk), dim3(kThreads), 0, st, kt, blk, th, thidx, gates, scratch);
+  if (ut.total > 0) hipLaunchKernelGGL(k_theta, dim3(ut.total), dim3(kThreads), 0, st, kt, a, th, ut, scratch);
+  if (ug.total > 0)
+    hipLaunchKernelGGL(k_gate_gather, dim3(ug.total), dim3(kThreads), 0, st, kt, blk, ug, th, thidx, gates,
+                       scratch);
 }
 
-void launch_split_gate(const KetTables &kt, int a, const Blk *blk, int nblk, const double *scratch,
+void launch_split_gate(const KetTables &kt, int a, const Blk *blk, Units u, const double *scratch,
                        hipStream_t st) {
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(k_split_gate, dim3(nblk), dim3(kThreads), 0, st, kt, a, blk, scratch);
+  if (u.total == 0) return;
+  hipLaunchKernelGGL(k_split_gate, dim3(u.total), dim3(kThreads), 0, st, kt, a, blk, u, scratch);
 }
 
-void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, int nblk, double *scratch,
+void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, Units u, double *scratch,
                       hipStream_t st) {
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(k_gather_lq, dim3(nblk), dim3(kThreads), 0, st, kt, q, blk, scratch);
+  if (u.total == 0) return;
+  hipLaunchKernelGGL(k_gather_lq, dim3(u.total), dim3(kThreads), 0, st, kt, q, blk, u, scratch);
 }
 
-void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, int nblk, const double *scratch,
+void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, Units u, const double *scratch,
                      double *const *old_left, hipStream_t st) {
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(k_apply_lq, dim3(nblk), dim3(kThreads), 0, st, kt, q, blk, scratch, old_left);
+  if (u.total == 0) return;
+  hipLaunchKernelGGL(k_apply_lq, dim3(u.total), dim3(kThreads), 0, st, kt, q, blk, u, scratch, old_left);
 }
 
 void launch_gather_qr(const KetTables &kt, int p, const Blk *blk, int nblk, double *scratch,

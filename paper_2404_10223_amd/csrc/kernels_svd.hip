@@ -445,13 +445,13 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
 
 // The factor not produced by the Jacobi kernels, for the first `kept` sorted
 // vectors: columns case B[j][c] = sum_r U[j][r] T[r][c]; rows case
-// U[j][r] = sum_c B[j][c] T[r][c] / s_j^2.  64 x 64 output tiles, 4 x 4 per
-// thread, K staged through LDS in steps of 16.
+// U[j][r] = sum_c B[j][c] T[r][c] / s_j^2.  One 64 x 64 output tile per
+// workgroup, 4 x 4 per thread, K staged through LDS in steps of 16.
 constexpr int kFT = 64, kFK = 16;
-__global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, double *scratch) {
-  const Blk b = blks[blockIdx.x];
+__global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, double *scratch) {
+  const int bi = find_unit(un.first, un.n, blockIdx.x);
+  const Blk b = blks[bi];
   const int I = b.kept;
-  if (I == 0) return;
   const bool cols = b.R >= b.C;
   const double *T = scratch + b.offT;
   const double *S = scratch + b.offS;
@@ -464,8 +464,10 @@ __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, double *scr
   __shared__ double As[kFK][kFT + 1];
   __shared__ double Bs[kFK][kFT + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int tilesJ = (J + kFT - 1) / kFT, tilesI = (I + kFT - 1) / kFT;
-  for (int tile = 0; tile < tilesI * tilesJ; ++tile) {
+  static_assert(kFT == kGateTile, "tile");
+  const int tilesJ = (J + kFT - 1) / kFT;
+  {
+    const int tile = blockIdx.x - un.first[bi];
     const int i0 = (tile / tilesJ) * kFT, j0 = (tile % tilesJ) * kFT;
     double acc[4][4] = {};
     for (int k0 = 0; k0 < K; k0 += kFK) {
@@ -562,9 +564,9 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
   }
 }
 
-void launch_svd_factor(const Blk *blk, int nblk, double *scratch, hipStream_t st) {
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(k_svd_factor, dim3(nblk), dim3(256), 0, st, blk, scratch);
+void launch_svd_factor(const Blk *blk, Units u, double *scratch, hipStream_t st) {
+  if (u.total == 0) return;
+  hipLaunchKernelGGL(k_svd_factor, dim3(u.total), dim3(256), 0, st, blk, u, scratch);
 }
 
 }  // namespace tnqe
