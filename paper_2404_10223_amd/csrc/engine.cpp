@@ -80,6 +80,18 @@ void DevicePool::trim() {
   held_ = 0;
 }
 
+// How long a waiting thread polls before it blocks: the per-ket loops of the
+// gate phase come a fraction of a millisecond apart, and a wake-up through a
+// condition variable costs tens of microseconds each time.
+constexpr auto kPoolSpin = std::chrono::microseconds(200);
+
+template <class Pred>
+void spin_until(Pred done) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; !done(); ++i)
+    if ((i & 63) == 63 && std::chrono::steady_clock::now() - t0 > kPoolSpin) return;
+}
+
 ThreadPool::ThreadPool(int workers) {
   for (int i = 0; i < workers; ++i)
     threads_.emplace_back([this] {
@@ -87,6 +99,7 @@ ThreadPool::ThreadPool(int workers) {
       for (;;) {
         const std::function<void(int)> *f;
         int n;
+        spin_until([&] { return stop_.load() || gen_.load() != seen; });
         {
           std::unique_lock<std::mutex> lk(m_);
           cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
@@ -144,6 +157,7 @@ void ThreadPool::parallel_for(int n, const std::function<void(int)> &f) {
   }
   cv_.notify_all();
   work(&f, n);
+  spin_until([&] { return busy_.load() == 0 && next_.load() >= n; });
   std::unique_lock<std::mutex> lk(m_);
   done_cv_.wait(lk, [&] { return busy_ == 0 && next_.load() >= n_; });
   job_ = nullptr;
@@ -364,6 +378,19 @@ struct KetSet {
     }
     dsite_ptr = call->upload(site_ptr);
   }
+  // offsets of the sectors of bond b from the current host dimensions,
+  // [ket][slot] (prefix sums over the slots)
+  std::vector<int> offsets(int b) {
+    std::vector<int> o((size_t)n * nslot);
+    for (int t = 0; t < n; ++t) {
+      int acc = 0;
+      for (int s = 0; s < nslot; ++s) {
+        o[(size_t)t * nslot + s] = acc;
+        acc += dim(b, t, s);
+      }
+    }
+    return o;
+  }
   // recompute offsets of bond b on the host and upload that slice
   void commit_bond(int b) {
     for (int t = 0; t < n; ++t) {
@@ -478,6 +505,20 @@ void take_block_storage(Blk &b, Scratch &sc) {
   b.offW = b.offW >= 0 ? sc.take((int64_t)b.n * m + b.n) : -1;
 }
 
+// the launch shape plan_block chose, recovered from the block's group size
+JacobiPlan planned_shape(const Blk &b) {
+  JacobiPlan jp;
+  if (b.offW >= 0) return jp;   // global-memory variant
+  const int n = b.n, m = std::max(b.R, b.C), G = b.grp;
+  const int E = ((m + G - 1) / G + 3) / 4 * 4, P = (n + 1) / 2, NTr = n / 2;
+  jp.kind = E / 4 - 1;
+  jp.grp = G;
+  jp.threads = (P * G + 63) / 64 * 64;
+  jp.mpad = b.mpad;
+  jp.lds = ((int64_t)NTr * G * (E + 2) + NTr + n) * 8 + (int64_t)n * 4;
+  return jp;
+}
+
 void plan_block_storage(Blk &b, Scratch &sc) {
   plan_block(b);
   take_block_storage(b, sc);
@@ -494,6 +535,7 @@ double svd_flops(const Blk &b) {
 struct GateHostTiming {
   double sync_ms = 0.0, select_ms = 0.0, step_ms = 0.0, move_ms = 0.0;
   double build_ms = 0.0, two_site_ms = 0.0, svd_host_ms = 0.0, post_ms = 0.0;
+  double plan_par_ms = 0.0, caller_ms = 0.0;
   int steps = 0;
 };
 double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
@@ -516,7 +558,7 @@ ThreadPool &host_pool(tnqe_ctx *ctx) {
 // Device time of timed SVD launches (per kernel), collected after the next
 // stream sync.
 struct SvdTimer {
-  static constexpr int kMaxPending = 32;
+  static constexpr int kMaxPending = 64;
   int npending = 0;
   int pending_kind[kMaxPending] = {};
   double pending_flops[kMaxPending] = {};
@@ -524,9 +566,11 @@ struct SvdTimer {
   int launches = 0;
   double kind_ms[kJacobiKinds] = {}, kind_flops[kJacobiKinds] = {};
   int kind_launches[kJacobiKinds] = {};
-  // waits for the pending end events
-  void collect(tnqe_ctx *ctx) {
-    for (int k = 0; k < npending; ++k) {
+  // waits for the end events of the first `upto` pending launches, adds their
+  // times, and moves the later ones (and their events) to the front
+  void collect(tnqe_ctx *ctx, int upto = kMaxPending) {
+    upto = std::min(upto, npending);
+    for (int k = 0; k < upto; ++k) {
       float t = 0.0f;
       TNQE_HIP(hipEventSynchronize(ctx->svd_ev[2 * k + 1]));
       TNQE_HIP(hipEventElapsedTime(&t, ctx->svd_ev[2 * k], ctx->svd_ev[2 * k + 1]));
@@ -537,7 +581,13 @@ struct SvdTimer {
       kind_flops[pending_kind[k]] += pending_flops[k];
       kind_launches[pending_kind[k]]++;
     }
-    npending = 0;
+    for (int k = upto; k < npending; ++k) {
+      std::swap(ctx->svd_ev[2 * (k - upto)], ctx->svd_ev[2 * k]);
+      std::swap(ctx->svd_ev[2 * (k - upto) + 1], ctx->svd_ev[2 * k + 1]);
+      pending_kind[k - upto] = pending_kind[k];
+      pending_flops[k - upto] = pending_flops[k];
+    }
+    npending -= upto;
   }
 };
 
@@ -555,7 +605,7 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   for (size_t i = 0; i < blks.size(); ++i) {
     const Blk &b = blks[i];
     const int m = std::max(b.R, b.C);
-    const JacobiPlan jp = jacobi_plan(b.n, m);
+    const JacobiPlan jp = planned_shape(b);
     int thr = 1024;
     for (int t : kThreadSteps)
       if (t >= jp.threads) {
@@ -586,6 +636,7 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   std::sort(order.begin(), order.end());
   tnqe_ctx *ctx = c.ctx;
   if (timer && timer->npending + (int)order.size() > SvdTimer::kMaxPending) timer->collect(ctx);
+  const int earlier = timer ? timer->npending : 0;
   const int nstream = std::min<int>(tnqe_ctx::kAux, (int)order.size());
   std::vector<const int *> didx(order.size());
   {
@@ -627,6 +678,9 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     TNQE_HIP(hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
   }
   c.check_launch();
+  // times of the earlier launches, while these run (the host would wait for
+  // them anyway)
+  if (timer) timer->collect(ctx, earlier);
   if (dbg) {
     std::vector<int> sw(blks.size());
     TNQE_HIP(hipMemcpyAsync(sw.data(), dsweeps, sw.size() * sizeof(int), hipMemcpyDeviceToHost, c.ctx->stream));
@@ -692,11 +746,9 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
     b.offS = sc.take(b.n);
     b.kept = b.n;
   }
-  for (Blk &b : blks) {   // j0 in the new bond
-    int acc = 0;
-    const int sl = ks.slot(b.sa, b.sb);
-    for (int s = 0; s < sl; ++s) acc += ks.dim(q, b.pair, s);
-    b.j0 = acc;
+  {   // j0 in the new bond
+    const std::vector<int> off = ks.offsets(q);
+    for (Blk &b : blks) b.j0 = off[(size_t)b.pair * ks.nslot + ks.slot(b.sa, b.sb)];
   }
   double *scratch = c.dev<double>(sc.used);
   // copy of the old left neighbour of every ket
@@ -766,10 +818,10 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
   for (Blk &b : blks) {
     b.offS = sc.take(b.n);
     b.kept = b.n;
-    int acc = 0;
-    const int sl = ks.slot(b.sa, b.sb);
-    for (int s = 0; s < sl; ++s) acc += ks.dim(p + 1, b.pair, s);
-    b.j0 = acc;
+  }
+  {   // j0 in the new bond
+    const std::vector<int> off = ks.offsets(p + 1);
+    for (Blk &b : blks) b.j0 = off[(size_t)b.pair * ks.nslot + ks.slot(b.sa, b.sb)];
   }
   double *scratch = c.dev<double>(sc.used);
   std::vector<double *> olds(ks.n), srcs(ks.n);
@@ -825,6 +877,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
       pblk[t].push_back(b);
     }
   });
+  const auto tbp = Clock::now();
   std::vector<Blk> blks;
   Scratch sc;
   for (int t = 0; t < ks.n; ++t)
@@ -865,12 +918,35 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
   const auto tb3 = Clock::now();
   c.check_launch();
-  std::vector<double> sv(ns);
-  TNQE_HIP(hipMemcpyAsync(sv.data(), scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
+  // singular values into pinned memory; the host polls for the copy's end
+  // (it has nothing else to do, and a blocking wait adds a wake-up latency)
+  tnqe_ctx *ctx = c.ctx;
+  if (ctx->sv_cap < (size_t)ns) {
+    if (ctx->sv_host) TNQE_HIP(hipHostFree(ctx->sv_host));
+    ctx->sv_host = nullptr;
+    ctx->sv_cap = 0;
+    const size_t cap = std::max<size_t>((size_t)ns * 2, 1 << 16);
+    TNQE_HIP(hipHostMalloc((void **)&ctx->sv_host, cap * sizeof(double), hipHostMallocDefault));
+    ctx->sv_cap = cap;
+  }
+  auto poll = [](hipEvent_t e) {
+    for (;;) {
+      const hipError_t q = hipEventQuery(e);
+      if (q == hipSuccess) return;
+      if (q != hipErrorNotReady) TNQE_HIP(q);
+    }
+  };
   const auto ts0 = Clock::now();
-  c.sync();
+  // every side stream done (so is all earlier work: the SVDs were forked
+  // after it); the copy runs on a side stream, not behind the main stream's
+  // join, and the staged uploads of this step have all been consumed
+  for (int i = 0; i < tnqe_ctx::kAux; ++i) poll(ctx->join_ev[i]);
+  TNQE_HIP(hipMemcpyAsync(ctx->sv_host, scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->aux[0]));
+  TNQE_HIP(hipEventRecord(ctx->sv_ev, ctx->aux[0]));
+  poll(ctx->sv_ev);
+  ctx->staging.reset();
   const auto ts1 = Clock::now();
-  ts.svd.collect(c.ctx);
+  const double *sv = ctx->sv_host;
   // global top-chi per ket: the `keep` largest singular values, ties taken in
   // block order (lower index first); kets in parallel on the host workers
   std::vector<std::vector<int>> per(ks.n);
@@ -933,6 +1009,7 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   const auto ts2 = Clock::now();
   if (debug_timing()) {
     g_gate_timing.build_ms += ms_between(tb0, tb1);
+    g_gate_timing.plan_par_ms += ms_between(tb0, tbp);
     g_gate_timing.two_site_ms += ms_between(tb1, tb2);
     g_gate_timing.svd_host_ms += ms_between(tb2, tb3);
     g_gate_timing.sync_ms += ms_between(ts0, ts1);
@@ -942,11 +1019,9 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   for (int t = 0; t < ks.n; ++t)
     for (int s = 0; s < ks.nslot; ++s) ks.dim(a + 1, t, s) = 0;
   for (Blk &b : blks) ks.dim(a + 1, b.pair, ks.slot(b.sa, b.sb)) = b.kept;
-  for (Blk &b : blks) {
-    int acc = 0;
-    const int sl = ks.slot(b.sa, b.sb);
-    for (int s = 0; s < sl; ++s) acc += ks.dim(a + 1, b.pair, s);
-    b.j0 = acc;
+  {   // j0 in the new bond
+    const std::vector<int> off = ks.offsets(a + 1);
+    for (Blk &b : blks) b.j0 = off[(size_t)b.pair * ks.nslot + ks.slot(b.sa, b.sb)];
   }
   ks.commit_bond(a + 1);
   const std::vector<int> u_factor = unit_prefix(blks, factor_units);
@@ -1797,6 +1872,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     int centre = N - 1;
     const size_t ngate = gpos[0].size();
     std::vector<double> gates((size_t)P * 256);
+    Clock::time_point t_prev_end = Clock::now();
     for (size_t g = 0; g < ngate; ++g) {
       const int a = gpos[0][g];
       const size_t mk = ctx->pool.mark();
@@ -1806,6 +1882,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
         --centre;
       }
       const auto tm1 = Clock::now();
+      if (debug_timing() && g > 0) g_gate_timing.caller_ms += ms_between(t_prev_end, tm0);
       for (int t = 0; t < P; ++t) {
         require(gpos[t][g] == a, TNQE_EINVAL, "gate positions differ between pairs");
         gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
@@ -1816,17 +1893,19 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       if (debug_timing()) {
         g_gate_timing.move_ms += std::chrono::duration<double, std::milli>(tm1 - tm0).count();
         g_gate_timing.step_ms += std::chrono::duration<double, std::milli>(Clock::now() - tm1).count();
+        t_prev_end = Clock::now();
       }
     }
     c.sync();
     ts.svd.collect(ctx);
     if (debug_timing()) {
       std::fprintf(stderr,
-                   "gate phase host: %d steps, move %.1f ms, gate step %.1f ms (build %.1f, two-site %.1f, "
-                   "svd launches %.1f, sync wait %.1f, selection %.1f, split %.1f)\n",
+                   "gate phase host: %d steps, move %.1f ms, gate step %.1f ms (build %.1f [parallel %.1f], "
+                   "two-site %.1f, svd launches %.1f, sync wait %.1f, selection %.1f, split %.1f), between "
+                   "steps %.1f\n",
                    g_gate_timing.steps, g_gate_timing.move_ms, g_gate_timing.step_ms, g_gate_timing.build_ms,
-                   g_gate_timing.two_site_ms, g_gate_timing.svd_host_ms, g_gate_timing.sync_ms,
-                   g_gate_timing.select_ms, g_gate_timing.post_ms);
+                   g_gate_timing.plan_par_ms, g_gate_timing.two_site_ms, g_gate_timing.svd_host_ms,
+                   g_gate_timing.sync_ms, g_gate_timing.select_ms, g_gate_timing.post_ms, g_gate_timing.caller_ms);
       g_gate_timing = GateHostTiming{};
     }
   }
@@ -2033,7 +2112,8 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
       delete ctx;
       return TNQE_EHIP;
     }
-  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->sv_ev, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < tnqe_ctx::kAux && ok; ++i)
     ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -2059,6 +2139,8 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
     if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
   }
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->sv_ev) (void)hipEventDestroy(ctx->sv_ev);
+  if (ctx->sv_host) (void)hipHostFree(ctx->sv_host);
   for (auto &e : ctx->env_ev) (void)hipEventDestroy(e);
   delete ctx;
   return TNQE_OK;

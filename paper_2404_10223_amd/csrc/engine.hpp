@@ -73,9 +73,12 @@ class ThreadPool {
   std::mutex m_;
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)> *job_ = nullptr;
-  int n_ = 0, busy_ = 0;
-  unsigned long long gen_ = 0;
-  bool stop_ = false;
+  int n_ = 0;
+  // written under m_; atomic so that waiting threads can poll them briefly
+  // before they block on a condition variable
+  std::atomic<int> busy_{0};
+  std::atomic<unsigned long long> gen_{0};
+  std::atomic<bool> stop_{false};
   std::atomic<int> next_{0};
   std::exception_ptr err_;
 };
@@ -105,7 +108,11 @@ struct tnqe_ctx {
   std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
   std::map<int, std::unique_ptr<tnqe::MpoDevice>> mpo_dev;        // by N
   hipEvent_t ev[8] = {};
-  hipEvent_t svd_ev[64] = {};  // timing of the truncation SVD launches of one gate step
+  hipEvent_t svd_ev[128] = {};  // timing of the SVD launches not yet collected
+  // pinned host copy of a gate step's singular values, and its completion event
+  double *sv_host = nullptr;
+  size_t sv_cap = 0;
+  hipEvent_t sv_ev = nullptr;
   // side streams (default priority) that run independent SVD launches side by
   // side; forked from and joined back into `stream` with events
   static constexpr int kAux = 4;
