@@ -1528,8 +1528,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       for (size_t ti = 0; ti < tb.tasks.size(); ++ti) {
         const MixTask &tk = tb.tasks[ti];
         for (int q = 0; q < nb_; ++q) {
-          const int64_t items =
-              (int64_t)idim(bra_item[q], x, tk.sa) * tk.nw_out * ((idim(ket_item[q], x + 1, tk.s) + 3) / 4);
+          const int64_t items = (int64_t)((idim(bra_item[q], x, tk.sa) + kMixRows - 1) / kMixRows) * tk.nw_out *
+                                ((idim(ket_item[q], x + 1, tk.s) + 3) / 4);
           add(w.mix, w.nmix, (int)ti, q, (items + 255) / 256);
         }
       }
