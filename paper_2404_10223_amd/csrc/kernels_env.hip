@@ -35,7 +35,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // LDS in chunks of 16.  Operand layout of the instruction (one double per
 // lane): A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k; lane
 // j + 16 q holds D[4 r + q][j] in element r.  la(q, m, k) / lb(q, k, n) load
-// the operands of segment q (K of segment q: kq(q)); sc(m, n, v) stores.
+// the operands of segment q (K of segment q: kq(q)); sc(m, n, v) stores.  The
+// loads of the next K chunk are issued before the current chunk's products.
 template <int TM, int TN, int NSEG, class KQ, class LA, class LB, class SC>
 __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA la, LB lb, SC sc) {
   constexpr int KC = 16;
@@ -52,22 +53,43 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
   for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < BJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  // the next K chunk is loaded into registers while the current one is
+  // multiplied (one chunk of global loads in flight per thread)
+  constexpr int RA = KC * TM / 256, RB = KC * TN / 256;
+  static_assert(RA * 256 == KC * TM && RB * 256 == KC * TN, "tile");
+  double ra[RA], rb[RB];
+  auto fetch = [&](int q, int K, int k0) {
+#pragma unroll
+    for (int u = 0; u < RA; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e % KC, mm = e / KC;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[u] = (gm < M && gk < K) ? la(q, gm, gk) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e / TN, nn = e % TN;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[u] = (gn < N && gk < K) ? lb(q, gk, gn) : 0.0;
+    }
+  };
 #pragma unroll
   for (int q = 0; q < NSEG; ++q) {
     if (q >= nseg) break;
     const int K = kq(q);
+    if (K > 0) fetch(q, K, 0);
     for (int k0 = 0; k0 < K; k0 += KC) {
-      for (int e = threadIdx.x; e < KC * TM; e += 256) {
-        const int kk = e % KC, mm = e / KC;
-        const int gm = m0 + mm, gk = k0 + kk;
-        sA[kk][mm] = (gm < M && gk < K) ? la(q, gm, gk) : 0.0;
+#pragma unroll
+      for (int u = 0; u < RA; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        sA[e % KC][e / KC] = ra[u];
       }
-      for (int e = threadIdx.x; e < KC * TN; e += 256) {
-        const int kk = e / TN, nn = e % TN;
-        const int gn = n0 + nn, gk = k0 + kk;
-        sB[kk][nn] = (gn < N && gk < K) ? lb(q, gk, gn) : 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        sB[e / TN][e % TN] = rb[u];
       }
       __syncthreads();
+      if (k0 + KC < K) fetch(q, K, k0 + KC);
 #pragma unroll
       for (int ks = 0; ks < KC; ks += 4) {
         double a[BI], b[BJ];
