@@ -37,32 +37,49 @@ __device__ inline int seg_of(const int *s, int x) {
 }
 
 // One 64 x 64 tile (rows m0.., columns n0..) of an M x N product C = A B
-// (4 x 4 per thread, K through LDS in steps of 16); la(m, k) and lb(k, n)
-// load operands, sc(m, n, v) stores.  A tiles are filled with k fastest; B
-// tiles with k fastest when BK (B contiguous along k), else with n fastest.
+// (4 x 4 per thread, K through LDS in steps of 16, the next step's loads
+// issued before the current step's products); la(m, k) and lb(k, n) load
+// operands, sc(m, n, v) stores.  A tiles are filled with k fastest; B tiles
+// with k fastest when BK (B contiguous along k), else with n fastest.
 constexpr int kKC = 16;
 typedef double GemmTile[kKC][kGateTile + 1];
 template <bool BK, class LA, class LB, class SC>
 __device__ void gemm_tile(GemmTile &sA, GemmTile &sB, int M, int N, int K, int m0, int n0, LA la, LB lb,
                           SC sc) {
-  constexpr int TT = kGateTile, KC = kKC;
+  constexpr int TT = kGateTile, KC = kKC, R = KC * TT / kThreads;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * TT; e += kThreads) {
+  // operands of the next K chunk are loaded into registers while the
+  // current chunk is multiplied
+  double ra[R], rb[R];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int e = threadIdx.x + kThreads * u;
       const int kk = e % KC, mm = e / KC;
       const int gm = m0 + mm, gk = k0 + kk;
-      sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : 0.0;
+      ra[u] = (gm < M && gk < K) ? la(gm, gk) : 0.0;
       if (BK) {
         const int gn = n0 + mm;
-        sB[kk][mm] = (gn < N && gk < K) ? lb(gk, gn) : 0.0;
+        rb[u] = (gn < N && gk < K) ? lb(gk, gn) : 0.0;
       } else {
         const int nn = e % TT, kb = e / TT;
         const int gn = n0 + nn, gkb = k0 + kb;
-        sB[kb][nn] = (gn < N && gkb < K) ? lb(gkb, gn) : 0.0;
+        rb[u] = (gn < N && gkb < K) ? lb(gkb, gn) : 0.0;
       }
     }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int e = threadIdx.x + kThreads * u;
+      sA[e % KC][e / KC] = ra[u];
+      if (BK) sB[e % KC][e / KC] = rb[u];
+      else sB[e / TT][e % TT] = rb[u];
+    }
     __syncthreads();
+    if (k0 + KC < K) fetch(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       double av[4], bv[4];

@@ -446,7 +446,8 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
 // The factor not produced by the Jacobi kernels, for the first `kept` sorted
 // vectors: columns case B[j][c] = sum_r U[j][r] T[r][c]; rows case
 // U[j][r] = sum_c B[j][c] T[r][c] / s_j^2.  One 64 x 64 output tile per
-// workgroup, 4 x 4 per thread, K staged through LDS in steps of 16.
+// workgroup, 4 x 4 per thread, K staged through LDS in steps of 16 (the next
+// step's loads issued before the current step's products).
 constexpr int kFT = 64, kFK = 16;
 __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, double *scratch) {
   const int bi = find_unit(un.first, un.n, blockIdx.x);
@@ -470,25 +471,35 @@ __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, d
     const int tile = blockIdx.x - un.first[bi];
     const int i0 = (tile / tilesJ) * kFT, j0 = (tile % tilesJ) * kFT;
     double acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += kFK) {
-      for (int e = threadIdx.x; e < kFK * kFT; e += 256) {
+    // the next K chunk's operands are loaded into registers while the
+    // current chunk is multiplied
+    constexpr int RF = kFK * kFT / 256;
+    double ra[RF], rb[RF];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < RF; ++u) {
+        const int e = threadIdx.x + 256 * u;
         // A tile: 64 rows i x 16 k (k fastest: A rows are contiguous in k)
         const int ii = e / kFK, kk = e % kFK;
         const int gi = i0 + ii, gk = k0 + kk;
-        As[kk][ii] = (gi < I && gk < K) ? A[(int64_t)gi * K + gk] : 0.0;
+        ra[u] = (gi < I && gk < K) ? A[(int64_t)gi * K + gk] : 0.0;
         // B tile: 16 k x 64 j, with the contiguous index fastest
-        int jj, kb;
-        if (cols) {
-          kb = e / kFT;
-          jj = e % kFT;
-        } else {
-          jj = e / kFK;
-          kb = e % kFK;
-        }
+        const int kb = cols ? e / kFT : e % kFK, jj = cols ? e % kFT : e / kFK;
         const int gj = j0 + jj, gk2 = k0 + kb;
-        Bs[kb][jj] = (gj < J && gk2 < K) ? T[(int64_t)gk2 * bk + (int64_t)gj * bj] : 0.0;
+        rb[u] = (gj < J && gk2 < K) ? T[(int64_t)gk2 * bk + (int64_t)gj * bj] : 0.0;
+      }
+    };
+    if (K > 0) fetch(0);
+    for (int k0 = 0; k0 < K; k0 += kFK) {
+#pragma unroll
+      for (int u = 0; u < RF; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        As[e % kFK][e / kFK] = ra[u];
+        if (cols) Bs[e / kFT][e % kFT] = rb[u];
+        else Bs[e % kFK][e / kFK] = rb[u];
       }
       __syncthreads();
+      if (k0 + kFK < K) fetch(k0 + kFK);
 #pragma unroll
       for (int kk = 0; kk < kFK; ++kk) {
         double a[4], bv[4];
