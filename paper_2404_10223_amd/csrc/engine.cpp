@@ -336,6 +336,10 @@ struct KetSet {
   double *dsites = nullptr;
   std::vector<double *> site_ptr;       // [ket * N + p]
   double **dsite_ptr = nullptr;
+  // one free site buffer per ket: a centre move writes the new left
+  // neighbour there and frees the old one (all site buffers have the size of
+  // the largest site)
+  std::vector<double *> spare;
   std::vector<int64_t> site_cap;        // doubles per site
 
   int &dim(int b, int t, int s) { return hdim[((size_t)b * n + t) * nslot + s]; }
@@ -362,19 +366,17 @@ struct KetSet {
     dbtab = call->dev<int2>(hbtab.size());
     dbdim = call->dev<int>(htot.size());
     site_cap.resize(N);
-    int64_t per = 0;
+    int64_t stride = 0;
     for (int p = 0; p < N; ++p) {
       site_cap[p] = (int64_t)cap[p] * 4 * cap[p + 1];
-      per += site_cap[p];
+      stride = std::max(stride, (site_cap[p] + 31) & ~int64_t(31));
     }
-    dsites = call->dev<double>((size_t)per * n);
+    dsites = call->dev<double>((size_t)stride * (N + 1) * n);
     site_ptr.resize((size_t)n * N);
+    spare.resize(n);
     for (int t = 0; t < n; ++t) {
-      int64_t o = (int64_t)t * per;
-      for (int p = 0; p < N; ++p) {
-        site_ptr[(size_t)t * N + p] = dsites + o;
-        o += site_cap[p];
-      }
+      for (int p = 0; p < N; ++p) site_ptr[(size_t)t * N + p] = dsites + ((size_t)t * (N + 1) + p) * stride;
+      spare[t] = dsites + ((size_t)t * (N + 1) + N) * stride;
     }
     dsite_ptr = call->upload(site_ptr);
   }
@@ -751,14 +753,14 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
     for (Blk &b : blks) b.j0 = off[(size_t)b.pair * ks.nslot + ks.slot(b.sa, b.sb)];
   }
   double *scratch = c.dev<double>(sc.used);
-  // copy of the old left neighbour of every ket
-  std::vector<double *> olds(ks.n), srcs(ks.n);
-  std::vector<int64_t> cnt(ks.n);
-  double *oldbuf = c.dev<double>((size_t)ks.site_cap[q - 1] * ks.n);
+  // the new left neighbour goes to each ket's spare site buffer and the old
+  // one (read by the products, not copied) becomes the spare
+  std::vector<double *> olds(ks.n);
   for (int t = 0; t < ks.n; ++t) {
-    olds[t] = oldbuf + (size_t)t * ks.site_cap[q - 1];
-    srcs[t] = ks.site_ptr[(size_t)t * ks.N + q - 1];
-    cnt[t] = (int64_t)ks.htot[(size_t)(q - 1) * ks.n + t] * 4 * ks.htot[(size_t)q * ks.n + t];
+    double *&cur = ks.site_ptr[(size_t)t * ks.N + q - 1];
+    olds[t] = cur;
+    cur = ks.spare[t];
+    ks.spare[t] = olds[t];
   }
   const std::vector<int> u_gather =
       unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
@@ -771,17 +773,19 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
     return u;
   });
   Call::Blob bl;
-  const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
+  const size_t o_old = bl.add(olds), o_blk = bl.add(blks);
   const size_t o_ug = bl.add(u_gather), o_uf = bl.add(u_factor), o_ua = bl.add(u_apply);
   char *base = c.upload(bl);
   double **d_old = Call::at<double *>(base, o_old);
-  launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
   Blk *dblk = Call::at<Blk>(base, o_blk);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, units_at(base, o_ug, u_gather), scratch, c.ctx->stream);
   run_svd(c, dblk, blks, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, c.ctx->stream);
   ks.commit_bond(q);
+  // the site table with the swapped buffers, in stream order before the
+  // kernel that writes the new neighbour
+  c.upload_to(ks.dsite_ptr, ks.site_ptr.data(), ks.site_ptr.size());
   launch_apply_lq(ks.tables(), q, dblk, units_at(base, o_ua, u_apply), scratch, d_old, c.ctx->stream);
   c.check_launch();
 }
