@@ -393,8 +393,9 @@ struct KetSet {
     }
     return o;
   }
-  // recompute offsets of bond b on the host and upload that slice
-  void commit_bond(int b) {
+  // recompute offsets of bond b on the host and upload that slice (unless
+  // the device table was already written by a kernel)
+  void commit_bond(int b, bool upload = true) {
     for (int t = 0; t < n; ++t) {
       int o = 0;
       for (int s = 0; s < nslot; ++s) {
@@ -405,6 +406,7 @@ struct KetSet {
       require(o <= cap[b], TNQE_ESHAPE, "bond dimension exceeds its capacity");
       htot[(size_t)b * n + t] = o;
     }
+    if (!upload) return;
     call->upload_to(dbtab + (size_t)b * n * nslot, hbtab.data() + (size_t)b * n * nslot, (size_t)n * nslot);
     call->upload_to(dbdim + (size_t)b * n, htot.data() + (size_t)b * n, (size_t)n);
   }
@@ -909,9 +911,27 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   const std::vector<int> u_gate =
       unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
   const std::vector<int> u_theta = unit_prefix(th, [](const Blk &b) { return gate_tiles(b.R, b.C); });
+  // launch shapes of the factor and split kernels before the kept counts are
+  // known (counted for all vectors), and each ket's first block
+  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
+  const std::vector<int> u_split = unit_prefix(blks, split_units);
+  std::vector<int> kfirst(ks.n + 1, 0);
+  for (const Blk &b : blks) kfirst[b.pair + 1]++;
+  int maxv = 0;
+  {
+    std::vector<int> nv(ks.n, 0);
+    for (const Blk &b : blks) nv[b.pair] += b.n;
+    for (int t = 0; t < ks.n; ++t) {
+      kfirst[t + 1] += kfirst[t];
+      maxv = std::max(maxv, nv[t]);
+    }
+  }
+  require(select_lds_bytes(maxv, ks.nslot) <= (size_t)kSelectLdsBytes, TNQE_ESHAPE,
+          "too many singular values per ket for the truncation kernel");
   Call::Blob bl;
   const size_t o_g = bl.add(gates), o_b = bl.add(blks), o_t = bl.add(th), o_i = bl.add(thidx);
-  const size_t o_ug = bl.add(u_gate), o_ut = bl.add(u_theta);
+  const size_t o_ug = bl.add(u_gate), o_ut = bl.add(u_theta), o_uf = bl.add(u_factor), o_us = bl.add(u_split);
+  const size_t o_kf = bl.add(kfirst);
   char *base = c.upload(bl);
   const double *dgates = Call::at<const double>(base, o_g);
   Blk *dblk = Call::at<Blk>(base, o_b);
@@ -922,122 +942,65 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
   const auto tb3 = Clock::now();
   c.check_launch();
-  // singular values into pinned memory; the host polls for the copy's end
-  // (it has nothing else to do, and a blocking wait adds a wake-up latency)
+  // truncation on the device, then the factor and split kernels, queued
+  // without a round trip through the host
   tnqe_ctx *ctx = c.ctx;
-  if (ctx->sv_cap < (size_t)ns) {
+  const int nblk = (int)blks.size();
+  int *dkept = c.dev<int>(nblk);
+  double *dstats = c.dev<double>((size_t)3 * ks.n);
+  const KetTables kt_new = ks.tables();
+  launch_select(dblk, Call::at<const int>(base, o_kf), ks.n, maxv, scratch, chi_cap, tau_w, kt_new, a + 1, dkept,
+                dstats, ctx->stream);
+  TNQE_HIP(hipEventRecord(ctx->sel_ev, ctx->stream));
+  launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, ctx->stream);
+  launch_split_gate(kt_new, a, dblk, units_at(base, o_us, u_split), scratch, ctx->stream);
+  c.check_launch();
+  // kept counts and per-ket statistics to pinned host memory on a side
+  // stream (the main stream goes on with the factor and split); the host
+  // polls for them, then mirrors the new bond for the next step's planning
+  const size_t need = (size_t)3 * ks.n + ((size_t)nblk + 1) / 2;
+  if (ctx->sv_cap < need) {
     if (ctx->sv_host) TNQE_HIP(hipHostFree(ctx->sv_host));
     ctx->sv_host = nullptr;
     ctx->sv_cap = 0;
-    const size_t cap = std::max<size_t>((size_t)ns * 2, 1 << 16);
+    const size_t cap = std::max<size_t>(need * 2, 1 << 16);
     TNQE_HIP(hipHostMalloc((void **)&ctx->sv_host, cap * sizeof(double), hipHostMallocDefault));
     ctx->sv_cap = cap;
   }
-  auto poll = [](hipEvent_t e) {
-    for (;;) {
-      const hipError_t q = hipEventQuery(e);
-      if (q == hipSuccess) return;
-      if (q != hipErrorNotReady) TNQE_HIP(q);
-    }
-  };
-  const auto ts0 = Clock::now();
-  // every side stream done (so is all earlier work: the SVDs were forked
-  // after it); the copy runs on a side stream, not behind the main stream's
-  // join, and the staged uploads of this step have all been consumed
-  for (int i = 0; i < tnqe_ctx::kAux; ++i) poll(ctx->join_ev[i]);
-  TNQE_HIP(hipMemcpyAsync(ctx->sv_host, scratch + s0, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->aux[0]));
+  double *hstats = ctx->sv_host;
+  int *hkept = reinterpret_cast<int *>(ctx->sv_host + (size_t)3 * ks.n);
+  TNQE_HIP(hipStreamWaitEvent(ctx->aux[0], ctx->sel_ev, 0));
+  TNQE_HIP(hipMemcpyAsync(hstats, dstats, (size_t)3 * ks.n * sizeof(double), hipMemcpyDeviceToHost, ctx->aux[0]));
+  TNQE_HIP(hipMemcpyAsync(hkept, dkept, (size_t)nblk * sizeof(int), hipMemcpyDeviceToHost, ctx->aux[0]));
   TNQE_HIP(hipEventRecord(ctx->sv_ev, ctx->aux[0]));
-  poll(ctx->sv_ev);
+  const auto ts0 = Clock::now();
+  for (;;) {
+    const hipError_t q = hipEventQuery(ctx->sv_ev);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) TNQE_HIP(q);
+  }
+  // every upload of this step has been consumed (the truncation ran after
+  // all of them)
   ctx->staging.reset();
   const auto ts1 = Clock::now();
-  const double *sv = ctx->sv_host;
-  // global top-chi per ket: the `keep` largest singular values, ties taken in
-  // block order (lower index first); kets in parallel on the host workers
-  std::vector<std::vector<int>> per(ks.n);
-  for (size_t i = 0; i < blks.size(); ++i) per[blks[i].pair].push_back((int)i);
-  std::vector<double> gap_t(ks.n, 1.0);
-  std::vector<int> keep_t(ks.n, 0);
-  host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
-    std::vector<double> vals, tmp;
-    double tot = 0.0;
-    for (int bi : per[t]) {
-      const Blk &b = blks[bi];
-      for (int j = 0; j < b.n; ++j) {
-        const double sgm = sv[b.offS - s0 + j];
-        vals.push_back(sgm);
-        tot += sgm * sgm;
-      }
-    }
-    int nnz = 0;
-    for (double v : vals) nnz += (v * v > tau_w * tot) ? 1 : 0;
-    const int keep = std::min(chi_cap, nnz);
-    const size_t ntot = vals.size();
-    double th = -1.0;   // keep-th largest value (every value kept when keep == ntot)
-    int need_eq = 0;
-    if (keep == 0) {
-      th = std::numeric_limits<double>::infinity();
-    } else if ((size_t)keep < ntot) {
-      tmp = vals;
-      std::nth_element(tmp.begin(), tmp.begin() + (keep - 1), tmp.end(), std::greater<double>());
-      th = tmp[keep - 1];
-      const double so = *std::max_element(tmp.begin() + keep, tmp.end());
-      if (th > 0.0) gap_t[t] = (th - so) / th;
-      int gt = 0;
-      for (double v : vals) gt += v > th ? 1 : 0;
-      need_eq = keep - gt;
-    }
-    // kept counts per block (a prefix of each block's sorted list)
-    double disc = 0.0;
-    size_t gi = 0;
-    for (int bi : per[t]) {
-      Blk &b = blks[bi];
-      int k = 0;
-      for (int j = 0; j < b.n; ++j, ++gi) {
-        const double v = vals[gi];
-        bool kp = v > th;
-        if (!kp && v == th && need_eq > 0) {
-          kp = true;
-          --need_eq;
-        }
-        if (kp) ++k; else disc += v * v;
-      }
-      b.kept = k;
-    }
-    ts.discarded[t] += disc;
-    keep_t[t] = keep;
-  });
+  for (int t = 0; t < ks.n; ++t)
+    for (int s = 0; s < ks.nslot; ++s) ks.dim(a + 1, t, s) = 0;
+  for (int i = 0; i < nblk; ++i) ks.dim(a + 1, blks[i].pair, ks.slot(blks[i].sa, blks[i].sb)) = hkept[i];
+  ks.commit_bond(a + 1, false);
   for (int t = 0; t < ks.n; ++t) {
-    ts.min_gap = std::min(ts.min_gap, gap_t[t]);
-    ts.max_bond = std::max(ts.max_bond, keep_t[t]);
+    ts.discarded[t] += hstats[3 * t + 1];
+    ts.min_gap = std::min(ts.min_gap, hstats[3 * t + 2]);
+    ts.max_bond = std::max(ts.max_bond, (int)hstats[3 * t]);
   }
-  const auto ts2 = Clock::now();
   if (debug_timing()) {
     g_gate_timing.build_ms += ms_between(tb0, tb1);
     g_gate_timing.plan_par_ms += ms_between(tb0, tbp);
     g_gate_timing.two_site_ms += ms_between(tb1, tb2);
     g_gate_timing.svd_host_ms += ms_between(tb2, tb3);
     g_gate_timing.sync_ms += ms_between(ts0, ts1);
-    g_gate_timing.select_ms += ms_between(ts1, ts2);
+    g_gate_timing.select_ms += ms_between(ts1, Clock::now());
     g_gate_timing.steps++;
   }
-  for (int t = 0; t < ks.n; ++t)
-    for (int s = 0; s < ks.nslot; ++s) ks.dim(a + 1, t, s) = 0;
-  for (Blk &b : blks) ks.dim(a + 1, b.pair, ks.slot(b.sa, b.sb)) = b.kept;
-  {   // j0 in the new bond
-    const std::vector<int> off = ks.offsets(a + 1);
-    for (Blk &b : blks) b.j0 = off[(size_t)b.pair * ks.nslot + ks.slot(b.sa, b.sb)];
-  }
-  ks.commit_bond(a + 1);
-  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
-  const std::vector<int> u_split = unit_prefix(blks, split_units);
-  Call::Blob bl2;
-  const size_t o_b2 = bl2.add(blks), o_uf = bl2.add(u_factor), o_us = bl2.add(u_split);
-  char *base2 = c.upload(bl2);
-  Blk *dblk2 = Call::at<Blk>(base2, o_b2);
-  launch_svd_factor(dblk2, units_at(base2, o_uf, u_factor), scratch, c.ctx->stream);
-  launch_split_gate(ks.tables(), a, dblk2, units_at(base2, o_us, u_split), scratch, c.ctx->stream);
-  c.check_launch();
-  if (debug_timing()) g_gate_timing.post_ms += ms_between(ts2, Clock::now());
 }
 
 // Device copy of the sparse groups' CSR structure for this MPO (cached).
@@ -2117,7 +2080,8 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
       return TNQE_EHIP;
     }
   bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&ctx->sv_ev, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&ctx->sv_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->sel_ev, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < tnqe_ctx::kAux && ok; ++i)
     ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -2144,6 +2108,7 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
   }
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->sv_ev) (void)hipEventDestroy(ctx->sv_ev);
+  if (ctx->sel_ev) (void)hipEventDestroy(ctx->sel_ev);
   if (ctx->sv_host) (void)hipHostFree(ctx->sv_host);
   for (auto &e : ctx->env_ev) (void)hipEventDestroy(e);
   delete ctx;

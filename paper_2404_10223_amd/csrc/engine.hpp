@@ -112,7 +112,7 @@ struct tnqe_ctx {
   // pinned host copy of a gate step's singular values, and its completion event
   double *sv_host = nullptr;
   size_t sv_cap = 0;
-  hipEvent_t sv_ev = nullptr;
+  hipEvent_t sv_ev = nullptr, sel_ev = nullptr;
   // side streams (default priority) that run independent SVD launches side by
   // side; forked from and joined back into `stream` with events
   static constexpr int kAux = 4;

@@ -93,14 +93,14 @@ struct Units {
   int n, total;
 };
 // units per block of the split of a truncated two-site block (new A_a
-// columns, then new A_{a+1} rows) and of an LQ move's gather
+// columns, then new A_{a+1} rows), counted for all n vectors: the launch is
+// shaped before the kept counts are known (units past them do nothing)
 __host__ __device__ inline int split_units(const Blk &b) {
-  return b.kept == 0 ? 0 : gate_chunks((int64_t)b.R * b.kept) + gate_chunks((int64_t)b.kept * b.C);
+  return gate_chunks((int64_t)b.R * b.n) + gate_chunks((int64_t)b.n * b.C);
 }
-// units of the factor product (the kept vectors times the block)
-__host__ __device__ inline int factor_units(const Blk &b) {
-  return b.kept == 0 ? 0 : gate_tiles(b.kept, b.R >= b.C ? b.C : b.R);
-}
+// units of the factor product (the kept vectors times the block), counted
+// for all n vectors
+__host__ __device__ inline int factor_units(const Blk &b) { return gate_tiles(b.n, b.R >= b.C ? b.C : b.R); }
 
 // two-site products per old middle sector (th[0..nth), units: output tiles),
 // then the gate into the blocks of the new middle bond (units: element
@@ -120,6 +120,16 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
 // the other factor of the first `kept` sorted vectors of every block (units:
 // factor_units)
 void launch_svd_factor(const Blk *blk, Units u, double *scratch, hipStream_t st);
+// Truncation of every ket of a gate step on the device (one workgroup per
+// ket, whose maxv or fewer singular values are staged in LDS): kept counts
+// and offsets into blk, the sector table of `bond` into kt, kept counts into
+// kept_out[block] and (keep, discarded weight, gap) into stats[3 ket ..].
+constexpr int kSelectLdsBytes = 150 * 1024;
+inline size_t select_lds_bytes(int maxv, int nslot) {
+  return (size_t)maxv * sizeof(double) + (3 * (size_t)nslot + 1) * sizeof(int);
+}
+void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double *scratch, int chi, double tau,
+                   const KetTables &kt, int bond, int *kept_out, double *stats, hipStream_t st);
 // units: split_units
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, Units u, const double *scratch,
                        hipStream_t st);

@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Bl
 }
 
 // New A_a columns and A_{a+1} rows of one kept block (scatter); units: the
-// chunks of the R x kept columns, then those of the kept x C rows.
+// chunks of the R x n columns, then those of the n x C rows, of which the
+// first `kept` columns (rows) are written.
 __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, const Blk *blks, Units un,
                                                          const double *scratch) {
   const int bi = find_unit(un.first, un.n, blockIdx.x);
@@ -227,7 +228,8 @@ __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, co
   const int Dn = kt.dim(a + 1, pair), Dr = kt.dim(a + 2, pair);
   const double *U = scratch + b.offU, *Bo = scratch + b.offB;
   const int kept = b.kept;
-  const int u = blockIdx.x - un.first[bi], u1 = gate_chunks((int64_t)b.R * kept);
+  // units are counted for n kept vectors (the most a block can keep)
+  const int u = blockIdx.x - un.first[bi], u1 = gate_chunks((int64_t)b.R * b.n);
   if (u < u1) {
     const int64_t e0 = (int64_t)u * kGateChunk, e1 = min<int64_t>((int64_t)b.R * kept, e0 + kGateChunk);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
@@ -363,6 +365,141 @@ __global__ void __launch_bounds__(kThreads) k_apply_qr(KetTables kt, int p, cons
       [&](int jj, int x, double v) { Cn[(int64_t)jj * W + x] = v; });
 }
 
+// Truncation of one ket per workgroup (App. A1: the largest singular values
+// over all quantum-number blocks of the two-site matrix are kept).  With
+// tot = sum s^2 over the ket's blocks, keep = min(chi, #{s^2 > tau tot}); a
+// value is kept when its rank (larger values first, equal values in block
+// order, then in order within the block) is below keep.  Each block's list
+// is sorted, so its kept values are a prefix: the count and the block's
+// offset j0 in the new bond go into the block, the kept counts per slot and
+// their prefix sums into the bond's sector table, and (keep, discarded
+// weight, relative gap at the cut) into stats[3 t ..].  The blocks of ket t
+// are blks[kfirst[t] .. kfirst[t + 1]), in slot order.
+constexpr int kSelThreads = 1024, kSelVals = 1;   // values per thread per pass
+__device__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kSelThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_select(Blk *blks, const int *kfirst, int maxv,
+                                                     const double *scratch, int chi, double tau, KetTables kt,
+                                                     int bond, int *kept_out, double *stats) {
+  extern __shared__ __align__(16) double sel_lds[];
+  __shared__ double red[kSelThreads];
+  __shared__ double s_th, s_so;
+  const int t = blockIdx.x, i0 = kfirst[t], nb = kfirst[t + 1] - i0;
+  double *v = sel_lds;                                    // [maxv] values in block order
+  int *pre = reinterpret_cast<int *>(sel_lds + maxv);     // [nb + 1] value offsets of the blocks
+  int *cnt = pre + nb + 1;                                // [nb] kept counts
+  int *blk_of = cnt + nb;                                 // [nslot] block of a slot (-1: none)
+  for (int i = threadIdx.x; i < nb; i += kSelThreads) {
+    pre[i + 1] = blks[i0 + i].n;
+    cnt[i] = 0;
+  }
+  for (int sl = threadIdx.x; sl < kt.nslot; sl += kSelThreads) blk_of[sl] = -1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kSelThreads) blk_of[kt.slot(blks[i0 + i].sa, blks[i0 + i].sb)] = i;
+  if (threadIdx.x == 0) {
+    pre[0] = 0;
+    for (int i = 0; i < nb; ++i) pre[i + 1] += pre[i];
+    s_th = 0.0;
+    s_so = 0.0;
+  }
+  __syncthreads();
+  const int ntot = pre[nb];
+  for (int e = threadIdx.x; e < ntot; e += kSelThreads) {
+    int lo = 0, hi = nb;   // block of value e: pre[lo] <= e < pre[lo + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    v[e] = scratch[blks[i0 + lo].offS + (e - pre[lo])];
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int e = threadIdx.x; e < ntot; e += kSelThreads) part += v[e] * v[e];
+  const double tot = block_sum(part, red);
+  double big = 0.0;
+  for (int e = threadIdx.x; e < ntot; e += kSelThreads) big += (v[e] * v[e] > tau * tot) ? 1.0 : 0.0;
+  const int keep = min(chi, (int)block_sum(big, red));
+  // ranks: each thread takes kSelVals values per pass over all values
+  double disc = 0.0;
+  for (int e0 = 0; e0 < ntot; e0 += kSelVals * kSelThreads) {
+    double x[kSelVals];
+    int r[kSelVals];
+#pragma unroll
+    for (int u = 0; u < kSelVals; ++u) {
+      const int e = e0 + u * kSelThreads + threadIdx.x;
+      x[u] = e < ntot ? v[e] : 0.0;
+      r[u] = 0;
+    }
+    const int eu = e0 + threadIdx.x;
+    int f = 0;
+    for (; f + 8 <= ntot; f += 8) {   // eight values per step: their LDS reads overlap
+      double y[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) y[k] = v[f + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int u = 0; u < kSelVals; ++u) r[u] += (y[k] > x[u] || (y[k] == x[u] && f + k < eu + u * kSelThreads)) ? 1 : 0;
+    }
+    for (; f < ntot; ++f) {
+      const double y = v[f];
+#pragma unroll
+      for (int u = 0; u < kSelVals; ++u) r[u] += (y > x[u] || (y == x[u] && f < eu + u * kSelThreads)) ? 1 : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSelVals; ++u) {
+      const int e = e0 + u * kSelThreads + threadIdx.x;
+      if (e >= ntot) continue;
+      if (r[u] < keep) {
+        int lo = 0, hi = nb;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pre[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        atomicAdd(&cnt[lo], 1);
+      } else {
+        disc += x[u] * x[u];
+      }
+      if (r[u] == keep - 1) s_th = x[u];
+      if (r[u] == keep) s_so = x[u];
+    }
+  }
+  disc = block_sum(disc, red);
+  // kept counts by slot and their prefix sums: the new bond's sector table
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int sl = 0; sl < kt.nslot; ++sl) {
+      const int i = blk_of[sl];
+      const int d = i >= 0 ? cnt[i] : 0;
+      if (i >= 0) pre[i] = off;   // reused: offset j0 of block i
+      kt.btab[((int64_t)bond * kt.npair + t) * kt.nslot + sl] = make_int2(off, d);
+      off += d;
+    }
+    kt.bdim[bond * kt.npair + t] = off;
+    stats[3 * t] = keep;
+    stats[3 * t + 1] = disc;
+    stats[3 * t + 2] = (keep > 0 && keep < ntot && s_th > 0.0) ? (s_th - s_so) / s_th : 1.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kSelThreads) {
+    blks[i0 + i].kept = cnt[i];
+    blks[i0 + i].j0 = pre[i];
+    kept_out[i0 + i] = cnt[i];
+  }
+}
+
 __global__ void k_copy(double *const *dst, double *const *src, const int64_t *count) {
   const int i = blockIdx.y;
   const int64_t n = count[i];
@@ -417,6 +554,20 @@ void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const
                      double *const *old_right, hipStream_t st) {
   if (nblk == 0) return;
   hipLaunchKernelGGL(k_apply_qr, dim3(nblk), dim3(kThreads), 0, st, kt, p, blk, scratch, old_right);
+}
+
+void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double *scratch, int chi, double tau,
+                   const KetTables &kt, int bond, int *kept_out, double *stats, hipStream_t st) {
+  if (nket == 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kSelectLdsBytes);
+    attr_set = true;
+  }
+  const size_t lds = select_lds_bytes(maxv, kt.nslot);
+  hipLaunchKernelGGL(k_select, dim3(nket), dim3(kSelThreads), lds, st, blk, kfirst, maxv, scratch, chi, tau, kt,
+                     bond, kept_out, stats);
 }
 
 void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n, hipStream_t st) {

@@ -470,6 +470,7 @@ __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, d
   {
     const int tile = blockIdx.x - un.first[bi];
     const int i0 = (tile / tilesJ) * kFT, j0 = (tile % tilesJ) * kFT;
+    if (i0 >= I) return;   // units are counted for all n vectors
     double acc[4][4] = {};
     // the next K chunk's operands are loaded into registers while the
     // current chunk is multiplied
