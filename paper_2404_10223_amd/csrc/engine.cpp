@@ -12,6 +12,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,6 +22,7 @@
 #include <functional>
 #include <numeric>
 #include <thread>
+#include <utility>
 
 namespace tnqe {
 
@@ -176,6 +178,12 @@ void Staging::reset() {
 }
 
 void *Staging::put(const void *src, size_t bytes) {
+  void *p = reserve(bytes);
+  std::memcpy(p, src, bytes);
+  return p;
+}
+
+void *Staging::reserve(size_t bytes) {
   const size_t need = (bytes + 255) & ~size_t(255);
   if (used_ + need > cap_) {
     // keep the old buffer alive until the next reset (copies may be in flight)
@@ -185,7 +193,6 @@ void *Staging::put(const void *src, size_t bytes) {
     used_ = 0;
   }
   char *p = buf_ + used_;
-  std::memcpy(p, src, bytes);
   used_ += need;
   return p;
 }
@@ -213,17 +220,33 @@ struct Call {   // per-call helpers bound to a context
     return d;
   }
   // several host arrays in one upload: add() returns each array's byte offset
+  // (the arrays are copied once, straight into the pinned staging area, when
+  // the blob is uploaded; they must live until then)
   struct Blob {
-    std::vector<char> bytes;
+    struct Part {
+      const void *src;
+      size_t bytes, off;
+    };
+    std::vector<Part> parts;
+    size_t size = 0;
     template <typename T>
     size_t add(const std::vector<T> &v) {
-      const size_t off = (bytes.size() + 255) & ~size_t(255);
-      bytes.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
-      if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+      const size_t off = (size + 255) & ~size_t(255);
+      parts.push_back(Part{v.data(), v.size() * sizeof(T), off});
+      size = off + std::max<size_t>(1, v.size()) * sizeof(T);
       return off;
     }
+    template <typename T>
+    size_t add(const std::vector<T> &&) = delete;   // the array must outlive the upload
   };
-  char *upload(const Blob &b) { return upload(b.bytes); }
+  char *upload(const Blob &b) {
+    char *d = dev<char>(b.size);
+    char *h = static_cast<char *>(ctx->staging.reserve(b.size));
+    for (const Blob::Part &p : b.parts)
+      if (p.bytes) std::memcpy(h + p.off, p.src, p.bytes);
+    TNQE_HIP(hipMemcpyAsync(d, h, b.size, hipMemcpyHostToDevice, ctx->stream));
+    return d;
+  }
   template <typename T>
   static T *at(char *base, size_t off) {
     return reinterpret_cast<T *>(base + off);
@@ -288,30 +311,32 @@ void givens_plan(int N, const double *W, std::vector<int> &pos, std::vector<doub
 // (p up, p dn, p+1 up, p+1 dn) and relabelled to k = n_up + 2 n_dn.
 void gate_g4(double th, double out[256]) {
   const double c = std::cos(th), s = std::sin(th);
-  const double f2[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, -1};
   const double g2[16] = {1, 0, 0, 0, 0, c, -s, 0, 0, s, c, 0, 0, 0, 0, 1};
-  auto kron = [](const double *A, int m, const double *B, int n, double *C) {
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < n; ++j)
-        for (int k = 0; k < m; ++k)
-          for (int l = 0; l < n; ++l) C[(i * n + j) * (m * n) + k * n + l] = A[i * m + k] * B[j * n + l];
-  };
-  const double I2[4] = {1, 0, 0, 1};
-  double t8[64], mid[256], core[256], tmp[256], G[256];
-  kron(I2, 2, f2, 4, t8);
-  kron(t8, 8, I2, 2, mid);
-  kron(g2, 4, g2, 4, core);
-  for (int i = 0; i < 16; ++i)
-    for (int j = 0; j < 16; ++j) {
-      double a = 0.0;
-      for (int k = 0; k < 16; ++k) a += mid[i * 16 + k] * core[k * 16 + j];
-      tmp[i * 16 + j] = a;
+  // mid = I2 (x) f2 (x) I2 (f2: the fermionic swap with the sign on |11>) is
+  // a symmetric signed permutation: mid[i][col[i]] = sgn[i] is its only
+  // entry in row i, so mid core mid = sgn[i] sgn[j] core[col[i]][col[j]]
+  static const auto perm_of_mid = [] {
+    const double f2[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, -1};
+    std::pair<std::array<int, 16>, std::array<double, 16>> m;
+    for (int i = 0; i < 16; ++i) {
+      const int hi = i >> 3, q = (i >> 1) & 3, lo = i & 1;   // mid row (hi, q, lo)
+      for (int q2 = 0; q2 < 4; ++q2)
+        if (f2[q * 4 + q2] != 0.0) {
+          m.first[i] = (hi << 3) | (q2 << 1) | lo;
+          m.second[i] = f2[q * 4 + q2];
+        }
     }
+    return m;
+  }();
+  const auto &col = perm_of_mid.first;
+  const auto &sgn = perm_of_mid.second;
+  double G[256];
   for (int i = 0; i < 16; ++i)
     for (int j = 0; j < 16; ++j) {
-      double a = 0.0;
-      for (int k = 0; k < 16; ++k) a += tmp[i * 16 + k] * mid[k * 16 + j];
-      G[i * 16 + j] = a;
+      // core = g2 (x) g2: core[(a, b)][(d, e)] = g2[a][d] g2[b][e]
+      const int k = col[i], l = col[j];
+      const double core = g2[(k >> 2) * 4 + (l >> 2)] * g2[(k & 3) * 4 + (l & 3)];
+      G[i * 16 + j] = sgn[i] * core * sgn[j] + 0.0;
     }
   const int perm[4] = {0, 2, 1, 3};   // k -> mode-bit index (n_up, n_dn)
   for (int k1 = 0; k1 < 4; ++k1)

@@ -49,6 +49,7 @@ class Staging {
  public:
   ~Staging();
   void *put(const void *src, size_t bytes);   // returns pinned copy
+  void *reserve(size_t bytes);                // pinned space to fill
   void reset();
   size_t capacity() const { return cap_; }
 
