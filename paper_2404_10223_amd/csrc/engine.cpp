@@ -204,6 +204,8 @@ double ms_since(Clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
+ThreadPool &host_pool(tnqe_ctx *ctx);
+
 struct Call {   // per-call helpers bound to a context
   tnqe_ctx *ctx;
   template <typename T>
@@ -242,8 +244,20 @@ struct Call {   // per-call helpers bound to a context
   char *upload(const Blob &b) {
     char *d = dev<char>(b.size);
     char *h = static_cast<char *>(ctx->staging.reserve(b.size));
-    for (const Blob::Part &p : b.parts)
-      if (p.bytes) std::memcpy(h + p.off, p.src, p.bytes);
+    // large blobs are copied in 128 KiB pieces by the host workers
+    constexpr size_t kPiece = 128 << 10;
+    std::vector<std::pair<size_t, size_t>> pieces;   // (part, byte offset in the part)
+    for (size_t i = 0; i < b.parts.size(); ++i)
+      for (size_t o = 0; o < b.parts[i].bytes; o += kPiece) pieces.push_back({i, o});
+    auto copy = [&](int k) {
+      const Blob::Part &p = b.parts[pieces[k].first];
+      const size_t o = pieces[k].second;
+      std::memcpy(h + p.off + o, static_cast<const char *>(p.src) + o, std::min(kPiece, p.bytes - o));
+    };
+    if (pieces.size() > 2)
+      host_pool(ctx).parallel_for((int)pieces.size(), copy);
+    else
+      for (size_t k = 0; k < pieces.size(); ++k) copy((int)k);
     TNQE_HIP(hipMemcpyAsync(d, h, b.size, hipMemcpyHostToDevice, ctx->stream));
     return d;
   }
@@ -885,72 +899,88 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   const auto tb0 = Clock::now();
   Call &c = *ks.call;
   // blocks of the new middle sectors (gated Theta) and of the old middle
-  // sectors (two-site products), per ket on the host workers; scratch is then
-  // assigned in ket order
-  std::vector<std::vector<Blk>> pblk(ks.n), pth(ks.n);
+  // sectors (two-site products) with their scratch, per ket on the host
+  // workers (offsets relative to the ket's part of the scratch area)
+  struct KetPlan {
+    std::vector<Blk> blk, th;
+    int64_t used = 0;
+    int nv = 0;   // singular values of the ket
+  };
+  std::vector<KetPlan> kp(ks.n);
   host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
+    KetPlan &P = kp[t];
+    Scratch sc;
     for (int s = 0; s < ks.nslot; ++s) {
       const int sa = s / (ks.nb + 1), sb = s % (ks.nb + 1);
+      int rs[5] = {0, 0, 0, 0, 0};
+      for (int k = 0; k < 4; ++k) rs[k + 1] = rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
+      if (rs[4] == 0) continue;
+      int cs[5] = {0, 0, 0, 0, 0};
+      for (int k = 0; k < 4; ++k) cs[k + 1] = cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
+      if (cs[4] == 0) continue;
       Blk b{};
       b.pair = t;
       b.sa = sa;
       b.sb = sb;
-      b.rs[0] = b.cs[0] = 0;
-      for (int k = 0; k < 4; ++k) {
-        b.rs[k + 1] = b.rs[k] + ks.dim_q(a, t, sa - qk_a(k), sb - qk_b(k));
-        b.cs[k + 1] = b.cs[k] + ks.dim_q(a + 2, t, sa + qk_a(k), sb + qk_b(k));
+      std::copy(rs, rs + 5, b.rs);
+      std::copy(cs, cs + 5, b.cs);
+      b.R = rs[4];
+      b.C = cs[4];
+      if (ks.dim_q(a + 1, t, sa, sb) > 0) {
+        Blk bt = b;
+        bt.offT = sc.take((int64_t)b.R * b.C);
+        P.th.push_back(bt);
       }
-      b.R = b.rs[4];
-      b.C = b.cs[4];
-      if (b.R == 0 || b.C == 0) continue;
-      if (ks.dim_q(a + 1, t, sa, sb) > 0) pth[t].push_back(b);
       plan_block(b);
-      pblk[t].push_back(b);
+      take_block_storage(b, sc);
+      b.offS = sc.take(b.n);
+      P.nv += b.n;
+      P.blk.push_back(b);
     }
+    P.used = sc.used;
   });
   const auto tbp = Clock::now();
-  std::vector<Blk> blks;
-  Scratch sc;
-  for (int t = 0; t < ks.n; ++t)
-    for (Blk &b : pblk[t]) {
-      take_block_storage(b, sc);
-      blks.push_back(b);
-    }
-  std::vector<Blk> th;
-  std::vector<int> thidx((size_t)ks.n * ks.nslot, -1);
-  for (int t = 0; t < ks.n; ++t)
-    for (Blk &b : pth[t]) {
-      b.offT = sc.take((int64_t)b.R * b.C);
-      thidx[(size_t)t * ks.nslot + ks.slot(b.sa, b.sb)] = (int)th.size();
-      th.push_back(b);
-    }
-  // singular values contiguous for one download
-  int64_t s0 = sc.used, ns = 0;
-  for (Blk &b : blks) {
-    b.offS = s0 + ns;
-    ns += b.n;
+  // the kets' parts of the scratch area, block lists and first blocks
+  std::vector<int64_t> kbase(ks.n + 1, 0);
+  std::vector<int> kfirst(ks.n + 1, 0), tfirst(ks.n + 1, 0);
+  int maxv = 0;
+  for (int t = 0; t < ks.n; ++t) {
+    kbase[t + 1] = kbase[t] + kp[t].used;
+    kfirst[t + 1] = kfirst[t] + (int)kp[t].blk.size();
+    tfirst[t + 1] = tfirst[t] + (int)kp[t].th.size();
+    maxv = std::max(maxv, kp[t].nv);
   }
-  sc.used += ns;
+  std::vector<Blk> blks(kfirst[ks.n]), th(tfirst[ks.n]);
+  std::vector<int> thidx((size_t)ks.n * ks.nslot, -1);
+  host_pool(c.ctx).parallel_for(ks.n, [&](int t) {
+    const int64_t o = kbase[t];
+    for (size_t i = 0; i < kp[t].blk.size(); ++i) {
+      Blk b = kp[t].blk[i];
+      b.offT += o;
+      b.offU += o;
+      b.offB += o;
+      b.offS += o;
+      if (b.offW >= 0) b.offW += o;
+      blks[kfirst[t] + i] = b;
+    }
+    for (size_t j = 0; j < kp[t].th.size(); ++j) {
+      Blk b = kp[t].th[j];
+      b.offT += o;
+      th[tfirst[t] + j] = b;
+      thidx[(size_t)t * ks.nslot + ks.slot(b.sa, b.sb)] = tfirst[t] + (int)j;
+    }
+  });
+  Scratch sc;
+  sc.used = kbase[ks.n];
   const auto tb1 = Clock::now();
   double *scratch = c.dev<double>(sc.used);
   const std::vector<int> u_gate =
       unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
   const std::vector<int> u_theta = unit_prefix(th, [](const Blk &b) { return gate_tiles(b.R, b.C); });
   // launch shapes of the factor and split kernels before the kept counts are
-  // known (counted for all vectors), and each ket's first block
+  // known (counted for all vectors)
   const std::vector<int> u_factor = unit_prefix(blks, factor_units);
   const std::vector<int> u_split = unit_prefix(blks, split_units);
-  std::vector<int> kfirst(ks.n + 1, 0);
-  for (const Blk &b : blks) kfirst[b.pair + 1]++;
-  int maxv = 0;
-  {
-    std::vector<int> nv(ks.n, 0);
-    for (const Blk &b : blks) nv[b.pair] += b.n;
-    for (int t = 0; t < ks.n; ++t) {
-      kfirst[t + 1] += kfirst[t];
-      maxv = std::max(maxv, nv[t]);
-    }
-  }
   require(select_lds_bytes(maxv, ks.nslot) <= (size_t)kSelectLdsBytes, TNQE_ESHAPE,
           "too many singular values per ket for the truncation kernel");
   Call::Blob bl;
