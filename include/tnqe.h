@@ -214,6 +214,24 @@ tnqe_status tnqe_debug_mpo_dense(int32_t N, const double *h, const double *g, do
                                  int32_t *max_bond);
 tnqe_status tnqe_debug_host_pool(int32_t workers, int32_t jobs, int64_t *calls);
 
+/* Device diagnostic (needs the context's GPU), used to test the truncation
+ * rule of the gate step (App. A1: the largest singular values over all
+ * quantum-number blocks of a two-site matrix are kept).
+ *
+ * tnqe_debug_select: runs the device selection on nket kets.  Ket t has
+ *   nblk[t] blocks; block i (kets in order, blocks in order) has n[i] values,
+ *   sorted in decreasing order, taken in turn from the host array sv.  Per
+ *   ket, keep = min(chi, #{s^2 > tau * sum s^2}) values with the largest
+ *   ranks are kept (larger values first; equal values in block order, then in
+ *   order within the block).  Outputs (host arrays): kept[i] per block and,
+ *   per ket, stats[3 t ..] = (keep, discarded weight sum over the values not
+ *   kept of s^2, relative gap (s_in - s_out) / s_in at the cut, 1 when
+ *   nothing was cut).  Returns TNQE_EINVAL on bad arguments (unsorted lists
+ *   included) and TNQE_ESHAPE when a ket has more values than the kernel's
+ *   local memory holds. */
+tnqe_status tnqe_debug_select(tnqe_ctx *ctx, int32_t nket, const int32_t *nblk, const int32_t *n,
+                              const double *sv, int32_t chi, double tau, int32_t *kept, double *stats);
+
 #ifdef __cplusplus
 }
 #endif

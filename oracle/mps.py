@@ -112,6 +112,30 @@ def move_centre(sites, qn, centre, target):
     return centre
 
 
+def select_kept(allsv, chi_cap, tau_w):
+    """Truncation rule of App. A1 over the singular values of all blocks of a
+    two-site matrix (concatenated in block order): the keep = min(chi_cap,
+    #{s^2 > tau_w sum s^2}) largest are kept, equal values taken in the order
+    of allsv.
+
+    Returns (kept mask, keep, number above the threshold, relative gap at the
+    cut or None, discarded weight, total weight).
+    """
+    w2 = allsv ** 2
+    total = w2.sum()
+    nnz = int((w2 > tau_w * total).sum())
+    keep = min(chi_cap, nnz)
+    order = np.argsort(-allsv, kind="stable")
+    kept_mask = np.zeros(len(allsv), dtype=bool)
+    kept_mask[order[:keep]] = True
+    gap = None
+    if keep < len(allsv) and keep > 0:
+        s_in, s_out = allsv[order[keep - 1]], allsv[order[keep]]
+        gap = (s_in - s_out) / s_in
+    discarded = float(w2[~kept_mask].sum())
+    return kept_mask, keep, nnz, gap, discarded, float(total)
+
+
 def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w):
     """Apply a 16x16 gate to sites (p, p+1) (centre at p), split by truncated SVD.
 
@@ -135,18 +159,7 @@ def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w):
         u, sv, vt = np.linalg.svd(Tm[np.ix_(rows, cols)], full_matrices=False)
         blocks.append((s, rows, cols, u, sv))
     allsv = np.concatenate([b[4] for b in blocks]) if blocks else np.zeros(0)
-    w2 = allsv ** 2
-    total = w2.sum()
-    nnz = int((w2 > tau_w * total).sum())
-    keep = min(chi_cap, nnz)
-    order = np.argsort(-allsv, kind="stable")
-    kept_mask = np.zeros(len(allsv), dtype=bool)
-    kept_mask[order[:keep]] = True
-    gap = None
-    if keep < len(allsv) and keep > 0:
-        s_in, s_out = allsv[order[keep - 1]], allsv[order[keep]]
-        gap = (s_in - s_out) / s_in
-    discarded = float(w2[~kept_mask].sum())
+    kept_mask, keep, nnz, gap, discarded, total = select_kept(allsv, chi_cap, tau_w)
     # new bond, sorted by sector; inside a sector, singular vectors by decreasing value
     newq, cols_u = [], []
     o = 0
@@ -170,7 +183,7 @@ def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w):
     sites[p] = U.reshape(dl, 4, dn)
     sites[p + 1] = (U.T @ Tm).reshape(dn, 4, dr)
     qn[p + 1] = np.array(newq, dtype=np.int64).reshape(-1, 2)
-    return dict(discarded=discarded, kept=dn, nonzero=nnz, gap=gap, total=float(total))
+    return dict(discarded=discarded, kept=dn, nonzero=nnz, gap=gap, total=total)
 
 
 def apply_site_op(sites, p, G4):

@@ -98,6 +98,8 @@ def lib():
     L.tnqe_debug_gate.argtypes = [C.c_double, dp]
     L.tnqe_debug_mpo_dense.argtypes = [ip, dp, dp, dp, dp, C.POINTER(C.c_int32)]
     L.tnqe_debug_host_pool.argtypes = [ip, ip, C.POINTER(C.c_int64)]
+    L.tnqe_debug_select.argtypes = [vp, ip, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, ip, C.c_double,
+                                    C.POINTER(C.c_int32), dp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -207,6 +209,20 @@ class Context:
             return up.solve(**kw)
         finally:
             up.free()
+
+    def debug_select(self, blocks, chi, tau):
+        """Device truncation rule on given singular values: blocks[t] is the
+        list of ket t's blocks, each a 1-D array sorted in decreasing order.
+        Returns (kept counts per block, per ket: [keep, discarded, gap])."""
+        nblk = np.array([len(b) for b in blocks], dtype=np.int32)
+        n = np.array([len(x) for b in blocks for x in b], dtype=np.int32)
+        flat = [np.asarray(x, dtype=np.float64) for b in blocks for x in b]
+        sv = np.ascontiguousarray(np.concatenate(flat) if flat else np.zeros(1))
+        kept = np.zeros(max(1, len(n)), dtype=np.int32)
+        stats = np.zeros((len(blocks), 3))
+        _check(self.L.tnqe_debug_select(self.h, len(blocks), _iptr(nblk), _iptr(n if len(n) else kept), _dptr(sv),
+                                        int(chi), float(tau), _iptr(kept), _dptr(stats)), self.h)
+        return kept[:len(n)], stats
 
     def solve_batch(self, uploaded, chis, **kw):
         """Solve several uploaded subspaces; chis[s] is subspace s's bond cap."""

@@ -2385,6 +2385,74 @@ tnqe_status tnqe_debug_host_pool(int32_t workers, int32_t jobs, int64_t *calls) 
   }
 }
 
+tnqe_status tnqe_debug_select(tnqe_ctx *ctx, int32_t nket, const int32_t *nblk, const int32_t *n,
+                              const double *sv, int32_t chi, double tau, int32_t *kept, double *stats) {
+  if (!ctx) return TNQE_EINVAL;
+  if (nket < 1 || !nblk || !n || !sv || chi < 0 || !(tau >= 0.0) || !kept || !stats)
+    return fail(ctx, TNQE_EINVAL, "bad argument to tnqe_debug_select");
+  return guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    Call c{ctx};
+    const size_t mk = ctx->pool.mark();
+    int nbt = 0, maxb = 1, maxv = 0;
+    for (int t = 0; t < nket; ++t) {
+      require(nblk[t] >= 0, TNQE_EINVAL, "negative block count");
+      nbt += nblk[t];
+      maxb = std::max(maxb, (int)nblk[t]);
+    }
+    std::vector<Blk> blks(nbt);
+    std::vector<int> kfirst(nket + 1, 0);
+    int64_t off = 0;
+    for (int t = 0, i = 0; t < nket; ++t) {
+      kfirst[t] = i;
+      int nv = 0;
+      for (int j = 0; j < nblk[t]; ++j, ++i) {
+        require(n[i] >= 0, TNQE_EINVAL, "negative value count");
+        for (int k = 0; k < n[i]; ++k) {
+          const double x = sv[off + k];
+          require(std::isfinite(x) && x >= 0.0 && (k == 0 || x <= sv[off + k - 1]), TNQE_EINVAL,
+                  "singular values must be finite, non-negative and sorted in decreasing order per block");
+        }
+        Blk b{};
+        b.pair = t;
+        b.n = n[i];
+        b.sa = j;   // block j of the ket in slot j
+        b.sb = 0;
+        b.offS = off;
+        off += n[i];
+        nv += n[i];
+        blks[i] = b;
+      }
+      kfirst[t + 1] = i;
+      maxv = std::max(maxv, nv);
+    }
+    require(select_lds_bytes(maxv, maxb) <= (size_t)kSelectLdsBytes, TNQE_ESHAPE,
+            "too many singular values per ket for the truncation kernel");
+    KetTables kt{};
+    kt.npair = nket;
+    kt.N = 1;
+    kt.na = maxb - 1;
+    kt.nb = 0;
+    kt.nslot = maxb;
+    kt.btab = c.dev<int2>((size_t)nket * maxb);
+    kt.bdim = c.dev<int>(nket);
+    const std::vector<double> hsv(sv, sv + off);
+    double *dsv = c.upload(hsv);
+    Blk *dblk = c.upload(blks);
+    const int *dkf = c.upload(kfirst);
+    int *dkept = c.dev<int>(std::max(1, nbt));
+    double *dstats = c.dev<double>((size_t)3 * nket);
+    launch_select(dblk, dkf, nket, maxv, dsv, chi, tau, kt, 0, dkept, dstats, ctx->stream);
+    c.check_launch();
+    std::vector<int> hk(std::max(1, nbt));
+    TNQE_HIP(hipMemcpyAsync(hk.data(), dkept, hk.size() * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TNQE_HIP(hipMemcpyAsync(stats, dstats, (size_t)3 * nket * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    c.sync();
+    for (int i = 0; i < nbt; ++i) kept[i] = hk[i];
+    ctx->pool.rewind(mk);
+  });
+}
+
 tnqe_status tnqe_debug_gate(double theta, double *out) {
   if (!out) return TNQE_EINVAL;
   gate_g4(theta, out);
