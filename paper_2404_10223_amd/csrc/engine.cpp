@@ -1800,7 +1800,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   std::vector<std::vector<int>> gpos(P);
   std::vector<std::vector<double>> gth(P);
   std::vector<int> dsign(P, 1);
-  for (int t = 0; t < P; ++t) {
+  host_pool(ctx).parallel_for(P, [&](int t) {
     const auto &Ui = pb.mps[offd[t].first].U, &Uj = pb.mps[offd[t].second].U;
     std::vector<double> W((size_t)N * N, 0.0);
     for (int a = 0; a < N; ++a)
@@ -1810,7 +1810,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
         W[a * N + b] = acc;
       }
     givens_plan(N, W.data(), gpos[t], gth[t], dsign[t]);
-  }
+  });
   rep.t_host_ms = ms_since(t0);
   // ---- gate phase
   const auto tg = Clock::now();
