@@ -2,7 +2,8 @@
 
 Workload: N = 24 spatial orbitals, chi = 256, M = 16 MPS (136 unique pairs),
 12 + 12 electrons, 24 Cholesky vectors: the seeded synthetic stand-in for the
-paper's molecular workloads (see the design doc for the recipe).  One step = one
+paper's molecular workloads (integrals, rotations and MPS drawn by
+tnqe_synth from fixed seeds).  One step = one
 complete solve (Givens networks with SVD truncation for the 120 off-diagonal
 pairs, environment sweeps for all 136 pairs, the 16 x 16 generalized
 eigenproblem) with the problem data already resident in HBM.
@@ -174,8 +175,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the pair set shards "
-                                   "across GPUs by design, see DESIGN.md, but no multi-GPU path is built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (the pairs would be "
+                                   "sharded over GPUs by estimated cost; no multi-GPU path is built)"}))
         sys.exit(2)
 
     import numpy as np
