@@ -168,6 +168,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--rotations", choices=["expm", "perm", "identity"], default="expm",
+                    help="orbital rotations of the MPS: random (TNQE, the headline workload), "
+                         "permutations (fermionic-swap networks, TNQE-F) or none (LC-MPS)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -184,7 +187,7 @@ def main():
     import paper_2404_10223_amd as T
     import tnqe_synth as synth
 
-    prob = synth.make_config(5)
+    prob = synth.make_config(5, args.rotations)
     ctx = T.Context(0)
     torch.cuda.synchronize()
     t_up = time.perf_counter()
@@ -226,7 +229,10 @@ def main():
             "warmup": args.warmup, "ms_per_step": t64 * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "N=24 orbitals, chi=256, M=16 MPS (136 pairs), 12+12 electrons, "
-                                   "24 Cholesky vectors, FP64 path", "N": prob.N, "chi": prob.chi, "M": prob.M,
+                                   "24 Cholesky vectors, FP64 path"
+                                   + {"expm": "", "perm": ", orbital permutations (fermionic-swap networks)",
+                                      "identity": ", no orbital rotations (LC-MPS)"}[args.rotations],
+                       "N": prob.N, "chi": prob.chi, "M": prob.M,
                        "pairs": n_pairs, "parallelism": "single GPU"},
             "E": E, "report": {k: rep[k] for k in ("t_host_ms", "t_gates_ms", "t_env_ms", "t_gep_ms",
                                                    "max_discarded_weight_sum", "min_rel_gap", "max_bond",

@@ -1897,18 +1897,28 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     Clock::time_point t_prev_end = Clock::now();
     for (size_t g = 0; g < ngate; ++g) {
       const int a = gpos[0][g];
+      // a gate of angle 0 for every pair is the identity; while no pair's
+      // bond a+1 exceeds chi its truncation could only drop weight below the
+      // tau_w cut, so it is not applied (no network at all for unrotated MPS)
+      bool identity = true;
+      for (int t = 0; t < P; ++t) {
+        require(gpos[t][g] == a, TNQE_EINVAL, "gate positions differ between pairs");
+        identity = identity && gth[t][g] == 0.0 && kets.htot[(size_t)(a + 1) * P + t] <= chi_cap;
+      }
+      if (identity) continue;
       const size_t mk = ctx->pool.mark();
       const auto tm0 = Clock::now();
       while (centre > a) {
         move_left(kets, centre, max_sweeps, &ts.svd);
         --centre;
       }
+      while (centre < a) {
+        move_right(kets, centre, max_sweeps, &ts.svd);
+        ++centre;
+      }
       const auto tm1 = Clock::now();
       if (debug_timing() && g > 0) g_gate_timing.caller_ms += ms_between(t_prev_end, tm0);
-      for (int t = 0; t < P; ++t) {
-        require(gpos[t][g] == a, TNQE_EINVAL, "gate positions differ between pairs");
-        gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
-      }
+      for (int t = 0; t < P; ++t) gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
       gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, ts);
       centre = a + 1;
       ctx->pool.rewind(mk);

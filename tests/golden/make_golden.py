@@ -22,15 +22,22 @@ C5_PAIRS = [(0, 0), (0, 1), (3, 11), (14, 15)]
 def digests():
     out = {f"config{k}": synth.problem_digest(synth.make_config(k)) for k in (1, 2, 3, 5)}
     out["batch"] = [synth.problem_digest(p) for p in synth.make_batch()[:8]]
+    for rot in VARIANTS.values():
+        for k in (2, 3):
+            p = synth.make_config(k, rot)
+            out[p.name] = synth.problem_digest(p)
     with open(os.path.join(HERE, "digests.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 
-def full(k):
-    prob = synth.make_config(k)
+VARIANTS = {"f": "perm", "lc": "identity"}   # fermionic-swap networks (TNQE-F), no rotations (LC-MPS)
+
+
+def full(k, rotations="expm"):
+    prob = synth.make_config(k, rotations)
     t = time.time()
     H, S, E, c, rep = subspace(prob)
-    np.savez(os.path.join(HERE, f"oracle_config{k}.npz"), H=H, S=S, E=E, c=c,
+    np.savez(os.path.join(HERE, f"oracle_{prob.name}.npz"), H=H, S=S, E=E, c=c,
              min_rel_gap=rep["min_rel_gap"] or 1.0, max_discarded=rep["max_discarded_weight_sum"],
              seconds=time.time() - t)
     print(k, E, rep, time.time() - t, flush=True)
@@ -65,7 +72,7 @@ def batch():
 
 
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["digests", "1", "2", "3", "c5", "batch"]
+    todo = sys.argv[1:] or ["digests", "1", "2", "3", "c5", "batch", "f2", "f3", "lc2", "lc3"]
     for name in todo:
         if name == "digests":
             digests()
@@ -73,5 +80,8 @@ if __name__ == "__main__":
             c5_pairs()
         elif name == "batch":
             batch()
+        elif name.rstrip("0123456789") in VARIANTS:
+            v = name.rstrip("0123456789")
+            full(int(name[len(v):]), VARIANTS[v])
         else:
             full(int(name))

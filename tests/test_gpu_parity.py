@@ -54,6 +54,20 @@ def test_config_parity_fp64(ctx, k):
     assert abs(c @ S @ c - 1.0) < 1e-10
 
 
+@pytest.mark.parametrize("rot", ["perm", "identity"])
+@pytest.mark.parametrize("k", [2, 3])
+def test_variant_workloads_parity_fp64(ctx, k, rot):
+    """Fermionic-swap networks (orbital permutations, TNQE-F; det = -1 cases
+    take the parity gate) and no rotations at all (LC-MPS) on the same path."""
+    prob = synth.make_config(k, rot)
+    g = np.load(os.path.join(GOLD, f"oracle_{prob.name}.npz"))
+    print(prob.name, "oracle min_rel_gap", float(g["min_rel_gap"]), flush=True)
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi)
+    _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), elementwise=True)
+    assert abs(rep["max_discarded_weight_sum"] - float(g["max_discarded"])) < 1e-10
+    np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
+
+
 def test_lossless_matches_brute_force(ctx):
     prob = synth.make_config(1)
     H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, chi_cap_override=10 ** 6)

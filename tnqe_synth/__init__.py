@@ -196,21 +196,45 @@ CONFIGS = {
 }
 
 
-def make_problem(N, na, nb, chi, M, K, base, name=""):
+def make_permutation(N, base, j):
+    """An orbital permutation matrix U[p, perm[p]] = 1 (a network of fermionic
+    swaps only: the TNQE-F variant)."""
+    perm = _rng(*base, 5, j).permutation(N)
+    U = np.zeros((N, N))
+    U[np.arange(N), perm] = 1.0
+    return U
+
+
+ROTATIONS = ("expm", "perm", "identity")
+
+
+def make_problem(N, na, nb, chi, M, K, base, name="", rotations="expm"):
+    """rotations: "expm" (random orbital rotations, TNQE), "perm" (orbital
+    permutations: fermionic-swap networks, TNQE-F) or "identity" (no
+    rotations: a linear combination of MPS, LC-MPS)."""
+    assert rotations in ROTATIONS
     base = tuple(base) if isinstance(base, (tuple, list)) else (base,)
     h, L = make_integrals(N, K, base)
     mps = []
     for j in range(M):
-        U = make_rotation(N, base, j)
+        if rotations == "expm":
+            U = make_rotation(N, base, j)
+        elif rotations == "perm":
+            U = make_permutation(N, base, j)
+        else:
+            U = np.eye(N)
         sites, qn = make_mps(N, na, nb, chi, base, j)
         mps.append(MPS(sites=sites, bond_qn=qn, U=U))
     return Problem(N=N, n_alpha=na, n_beta=nb, h=h, L=L, e_core=0.0, chi=chi, mps=mps, name=name)
 
 
-def make_config(k):
-    """Workload k: 1 (N=4), 2 (N=7), 3 (N=12), 5 (N=24)."""
+def make_config(k, rotations="expm"):
+    """Workload k: 1 (N=4), 2 (N=7), 3 (N=12), 5 (N=24); rotations as in
+    make_problem (the integrals and MPS do not depend on it)."""
     c = CONFIGS[k]
-    return make_problem(c["N"], c["na"], c["nb"], c["chi"], c["M"], c["K"], c["base"], name=f"config{k}")
+    name = f"config{k}" if rotations == "expm" else f"config{k}_{rotations}"
+    return make_problem(c["N"], c["na"], c["nb"], c["chi"], c["M"], c["K"], c["base"], name=name,
+                        rotations=rotations)
 
 
 def batch_shapes(base=1004, n_sub=64):
