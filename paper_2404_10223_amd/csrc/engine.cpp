@@ -12,7 +12,6 @@
 #include "engine.hpp"
 
 #include <algorithm>
-#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -22,7 +21,6 @@
 #include <functional>
 #include <numeric>
 #include <thread>
-#include <utility>
 
 namespace tnqe {
 
@@ -325,39 +323,7 @@ void givens_plan(int N, const double *W, std::vector<int> &pos, std::vector<doub
 // (p up, p dn, p+1 up, p+1 dn) and relabelled to k = n_up + 2 n_dn.
 void gate_g4(double th, double out[256]) {
   const double c = std::cos(th), s = std::sin(th);
-  const double g2[16] = {1, 0, 0, 0, 0, c, -s, 0, 0, s, c, 0, 0, 0, 0, 1};
-  // mid = I2 (x) f2 (x) I2 (f2: the fermionic swap with the sign on |11>) is
-  // a symmetric signed permutation: mid[i][col[i]] = sgn[i] is its only
-  // entry in row i, so mid core mid = sgn[i] sgn[j] core[col[i]][col[j]]
-  static const auto perm_of_mid = [] {
-    const double f2[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, -1};
-    std::pair<std::array<int, 16>, std::array<double, 16>> m;
-    for (int i = 0; i < 16; ++i) {
-      const int hi = i >> 3, q = (i >> 1) & 3, lo = i & 1;   // mid row (hi, q, lo)
-      for (int q2 = 0; q2 < 4; ++q2)
-        if (f2[q * 4 + q2] != 0.0) {
-          m.first[i] = (hi << 3) | (q2 << 1) | lo;
-          m.second[i] = f2[q * 4 + q2];
-        }
-    }
-    return m;
-  }();
-  const auto &col = perm_of_mid.first;
-  const auto &sgn = perm_of_mid.second;
-  double G[256];
-  for (int i = 0; i < 16; ++i)
-    for (int j = 0; j < 16; ++j) {
-      // core = g2 (x) g2: core[(a, b)][(d, e)] = g2[a][d] g2[b][e]
-      const int k = col[i], l = col[j];
-      const double core = g2[(k >> 2) * 4 + (l >> 2)] * g2[(k & 3) * 4 + (l & 3)];
-      G[i * 16 + j] = sgn[i] * core * sgn[j] + 0.0;
-    }
-  const int perm[4] = {0, 2, 1, 3};   // k -> mode-bit index (n_up, n_dn)
-  for (int k1 = 0; k1 < 4; ++k1)
-    for (int k2 = 0; k2 < 4; ++k2)
-      for (int l1 = 0; l1 < 4; ++l1)
-        for (int l2 = 0; l2 < 4; ++l2)
-          out[(k1 * 4 + k2) * 16 + l1 * 4 + l2] = G[(perm[k1] * 4 + perm[k2]) * 16 + perm[l1] * 4 + perm[l2]];
+  for (int x = 0; x < 256; ++x) out[x] = gate4_entry(c, s, x);
 }
 
 // ------------------------------------------------------------ ket sets
@@ -991,7 +957,8 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   const double *dgates = Call::at<const double>(base, o_g);
   Blk *dblk = Call::at<Blk>(base, o_b);
   launch_two_site(ks.tables(), a, dblk, units_at(base, o_ug, u_gate), Call::at<const Blk>(base, o_t),
-                  units_at(base, o_ut, u_theta), Call::at<const int>(base, o_i), dgates, scratch,
+                  units_at(base, o_ut, u_theta), Call::at<const int>(base, o_i), dgates,
+                  c.dev<double>((size_t)ks.n * 256), scratch,
                   c.ctx->stream);
   const auto tb2 = Clock::now();
   run_svd(c, dblk, blks, max_sweeps, scratch, &ts.svd);
@@ -1893,7 +1860,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     }
     int centre = N - 1;
     const size_t ngate = gpos[0].size();
-    std::vector<double> gates((size_t)P * 256);
+    std::vector<double> gates((size_t)P * 2);   // (cos, sin) of every pair's angle
     Clock::time_point t_prev_end = Clock::now();
     for (size_t g = 0; g < ngate; ++g) {
       const int a = gpos[0][g];
@@ -1918,7 +1885,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       }
       const auto tm1 = Clock::now();
       if (debug_timing() && g > 0) g_gate_timing.caller_ms += ms_between(t_prev_end, tm0);
-      for (int t = 0; t < P; ++t) gate_g4(gth[t][g], gates.data() + (size_t)t * 256);
+      for (int t = 0; t < P; ++t) {
+        gates[2 * t] = std::cos(gth[t][g]);
+        gates[2 * t + 1] = std::sin(gth[t][g]);
+      }
       gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, ts);
       centre = a + 1;
       ctx->pool.rewind(mk);

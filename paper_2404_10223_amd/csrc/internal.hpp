@@ -32,6 +32,26 @@ inline void require(bool ok, tnqe_status st, const std::string &msg) {
 __host__ __device__ inline int qk_a(int k) { return k & 1; }
 __host__ __device__ inline int qk_b(int k) { return k >> 1; }
 
+// Entry x = (k1 * 4 + k2) * 16 + l1 * 4 + l2 of the two-site gate g4(theta)
+// on local states (k1, k2) <- (l1, l2) of sites (p, p+1), from c = cos theta,
+// s = sin theta (App. A3): on the four modes (p up, p dn, p+1 up, p+1 dn) the
+// gate is mid (g2 (x) g2) mid, g2 the single-particle rotation on a mode pair
+// and mid = I2 (x) f2 (x) I2 with f2 the fermionic swap (sign on |11>).  mid
+// is a symmetric signed permutation, so the entry is one product of two g2
+// entries and two signs (the same arithmetic on the host and the device).
+__host__ __device__ inline double gate4_entry(double c, double s, int x) {
+  const int kq[4] = {0, 2, 1, 3};   // local state k -> mode-bit index (n_up, n_dn)
+  const int I = kq[x >> 6] * 4 + kq[(x >> 4) & 3], J = kq[(x >> 2) & 3] * 4 + kq[x & 3];
+  // f2 row q: its one nonzero column and sign
+  const int f2c[4] = {0, 2, 1, 3};
+  const double f2s[4] = {1.0, 1.0, 1.0, -1.0};
+  const int ci = (I & 8) | (f2c[(I >> 1) & 3] << 1) | (I & 1), cj = (J & 8) | (f2c[(J >> 1) & 3] << 1) | (J & 1);
+  const double si = f2s[(I >> 1) & 3], sj = f2s[(J >> 1) & 3];
+  const double g2[16] = {1, 0, 0, 0, 0, c, -s, 0, 0, s, c, 0, 0, 0, 0, 1};
+  const double core = g2[(ci >> 2) * 4 + (cj >> 2)] * g2[(ci & 3) * 4 + (cj & 3)];
+  return si * core * sj + 0.0;
+}
+
 // -------------------------------------------------------------- gate phase
 // One quantum-number block of a two-site matrix (or of a single site for the
 // exact centre moves).  Rows and columns are grouped in segments by a local
@@ -104,9 +124,10 @@ __host__ __device__ inline int factor_units(const Blk &b) { return gate_tiles(b.
 
 // two-site products per old middle sector (th[0..nth), units: output tiles),
 // then the gate into the blocks of the new middle bond (units: element
-// chunks; thidx[pair * nslot + slot]: Theta block)
+// chunks; thidx[pair * nslot + slot]: Theta block; cs[2 pair ..] = cos, sin
+// of the pair's angle; gates: room for the 16 x 16 gates [pair][256])
 void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const Blk *th, Units ut,
-                     const int *thidx, const double *gates, double *scratch, hipStream_t st);
+                     const int *thidx, const double *cs, double *gates, double *scratch, hipStream_t st);
 // Jacobi SVD of the blocks idx[0..nblk) of blk: sorted singular values (offS)
 // and sorted rotated vectors (U = x / s in the columns case, B = x in the rows
 // case).  kind k < kJacobiGlobal selects the register-resident kernel with

@@ -162,6 +162,13 @@ __global__ void __launch_bounds__(kThreads) k_theta(KetTables kt, int a, const B
       [&](int row, int col, double v) { Th[(int64_t)row * C + col] = v; });
 }
 
+// The 16 x 16 gate of every pair from (cos, sin) of its angle (one
+// workgroup of 256 threads per pair).
+__global__ void __launch_bounds__(256) k_gates(const double *cs, double *gates) {
+  const int pair = blockIdx.x;
+  gates[(int64_t)pair * 256 + threadIdx.x] = gate4_entry(cs[2 * pair], cs[2 * pair + 1], threadIdx.x);
+}
+
 // T'[(k1', l)][(k2', r)] = sum_{k1,k2} G[(k1',k2'),(k1,k2)] Theta_ms[(k1, l)][(k2, r)]
 // with ms = s - q(k1') + q(k1) (the gate conserves both particle numbers, so
 // the row and column sectors of the two sides agree).  thidx[pair][slot] is
@@ -519,7 +526,8 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 }  // namespace
 
 void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const Blk *th, Units ut,
-                     const int *thidx, const double *gates, double *scratch, hipStream_t st) {
+                     const int *thidx, const double *cs, double *gates, double *scratch, hipStream_t st) {
+  hipLaunchKernelGGL(k_gates, dim3(kt.npair), dim3(256), 0, st, cs, gates);
   if (ut.total > 0) hipLaunchKernelGGL(k_theta, dim3(ut.total), dim3(kThreads), 0, st, kt, a, th, ut, scratch);
   if (ug.total > 0)
     hipLaunchKernelGGL(k_gate_gather, dim3(ug.total), dim3(kThreads), 0, st, kt, blk, ug, th, thidx, gates,
