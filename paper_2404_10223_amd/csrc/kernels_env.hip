@@ -28,48 +28,65 @@ struct Seg {
 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-// FP64 matrix-core tile: the TM x TN tile (m0, n0) of sum over segments of
-// A_q B_q, 256 threads = 4 waves, each wave a (TM / WM) x (TN / WN) sub-tile
-// of 16 x 16 blocks accumulated by v_mfma_f64_16x16x4f64; K staged through
-// LDS in chunks of 16.  Operand layout of the instruction (one double per
-// lane): A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k; lane
-// j + 16 q holds D[4 r + q][j] in element r.  la(q, m, k) / lb(q, k, n) load
-// the operands of segment q (K of segment q: kq(q)); sc(m, n, v) stores.  The
-// loads of the next K chunk are issued before the current chunk's products.
-template <int TM, int TN, int NSEG, class KQ, class LA, class LB, class SC>
+// 16 x 16 x 4 matrix-core step in FP64 or FP32 and the row of accumulator
+// element r in lane j + 16 q: D[4 r + q][j] for v_mfma_f64_16x16x4f64,
+// D[4 q + r][j] for v_mfma_f32_16x16x4f32 (both read A[i][k] from lane
+// i + 16 k and B[k][j] from lane j + 16 k; layouts checked on gfx950).
+template <typename V> struct Mfma;
+template <> struct Mfma<double> {
+  typedef v4d Acc;
+  __device__ static Acc step(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int r, int q) { return 4 * r + q; }
+};
+template <> struct Mfma<float> {
+  typedef v4f Acc;
+  __device__ static Acc step(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int r, int q) { return 4 * q + r; }
+};
+
+// Matrix-core tile (FP64 or FP32, V): the TM x TN tile (m0, n0) of sum over
+// segments of A_q B_q, 256 threads = 4 waves, each wave a (TM / WM) x
+// (TN / WN) sub-tile of 16 x 16 blocks accumulated by the 16 x 16 x 4
+// instruction; K staged through LDS in chunks of 16.  la(q, m, k) /
+// lb(q, k, n) load the operands of segment q (K of segment q: kq(q));
+// sc(m, n, v) stores.  The loads of the next K chunk are issued before the
+// current chunk's products.
+template <typename V, int TM, int TN, int NSEG, class KQ, class LA, class LB, class SC>
 __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA la, LB lb, SC sc) {
   constexpr int KC = 16;
+  typedef typename Mfma<V>::Acc Acc;
   constexpr int WM = TM == TN ? 2 : (TM > TN ? 4 : 1), WN = 4 / WM;
   constexpr int SM = TM / WM, SN = TN / WN, BI = SM / 16, BJ = SN / 16;
   static_assert(BI >= 1 && BJ >= 1 && SM % 16 == 0 && SN % 16 == 0, "tile");
-  __shared__ double sA[KC][TM + 1];
-  __shared__ double sB[KC][TN + 1];
+  __shared__ V sA[KC][TM + 1];
+  __shared__ V sB[KC][TN + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / WN) * SM, wn = (wave % WN) * SN;
   const int li = lane & 15, lk = lane >> 4;
-  v4d acc[BI][BJ];
+  Acc acc[BI][BJ];
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < BJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < BJ; ++j) acc[i][j] = Acc{V(0), V(0), V(0), V(0)};
   // the next K chunk is loaded into registers while the current one is
   // multiplied (one chunk of global loads in flight per thread)
   constexpr int RA = KC * TM / 256, RB = KC * TN / 256;
   static_assert(RA * 256 == KC * TM && RB * 256 == KC * TN, "tile");
-  double ra[RA], rb[RB];
+  V ra[RA], rb[RB];
   auto fetch = [&](int q, int K, int k0) {
 #pragma unroll
     for (int u = 0; u < RA; ++u) {
       const int e = threadIdx.x + 256 * u, kk = e % KC, mm = e / KC;
       const int gm = m0 + mm, gk = k0 + kk;
-      ra[u] = (gm < M && gk < K) ? la(q, gm, gk) : 0.0;
+      ra[u] = (gm < M && gk < K) ? la(q, gm, gk) : V(0);
     }
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
       const int e = threadIdx.x + 256 * u, kk = e / TN, nn = e % TN;
       const int gn = n0 + nn, gk = k0 + kk;
-      rb[u] = (gn < N && gk < K) ? lb(q, gk, gn) : 0.0;
+      rb[u] = (gn < N && gk < K) ? lb(q, gk, gn) : V(0);
     }
   };
 #pragma unroll
@@ -92,7 +109,7 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
       if (k0 + KC < K) fetch(q, K, k0 + KC);
 #pragma unroll
       for (int ks = 0; ks < KC; ks += 4) {
-        double a[BI], b[BJ];
+        V a[BI], b[BJ];
 #pragma unroll
         for (int i = 0; i < BI; ++i) a[i] = sA[ks + lk][wm + 16 * i + li];
 #pragma unroll
@@ -100,7 +117,7 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
 #pragma unroll
         for (int i = 0; i < BI; ++i)
 #pragma unroll
-          for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < BJ; ++j) acc[i][j] = Mfma<V>::step(a[i], b[j], acc[i][j]);
       }
       __syncthreads();
     }
@@ -111,95 +128,27 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
     for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
+        const int gm = m0 + wm + 16 * i + Mfma<V>::row(r, lk), gn = n0 + wn + 16 * j + li;
         if (gm < M && gn < N) sc(gm, gn, acc[i][j][r]);
       }
 }
 
-// C tile (m0, n0) of sum_seg op(A) B: 256 threads, an RM x RN micro-tile
-// each, K staged through LDS in chunks of KC.  C = alpha * sum (+ C if beta).
-// FP64 tiles run on the matrix cores (tile_gemm_mfma).
+// C tile (m0, n0) of sum_seg op(A) B on the matrix cores (tile_gemm_mfma, in
+// the precision of T).  C = alpha * sum (+ C if beta).
 template <typename T, int TM, int TN, int RM, int RN, int NSEG>
 __device__ void tile_gemm(int M, int N, int m0, int n0, const Seg<T> (&sg)[NSEG], int nseg, T *C, int ldc,
                           T alpha, int beta) {
-  if constexpr (std::is_same<T, double>::value) {
-    tile_gemm_mfma<TM, TN, NSEG>(
-        M, N, m0, n0, nseg, [&](int q) { return sg[q].K; },
-        [&](int q, int m, int k) {
-          const Seg<T> &s = sg[q];
-          return s.transA ? s.A[(int64_t)k * s.lda + m] : s.A[(int64_t)m * s.lda + k];
-        },
-        [&](int q, int k, int n) { return sg[q].B[(int64_t)k * sg[q].ldb + n]; },
-        [&](int m, int n, double v) {
-          T *c = C + (int64_t)m * ldc + n;
-          *c = beta ? *c + alpha * v : alpha * v;
-        });
-    return;
-  }
-  constexpr int KC = 16;
-  constexpr int TX = TN / RN;
-  static_assert((TM / RM) * (TN / RN) == 256, "tile");
-  __shared__ T sA[KC][TM + 1];
-  __shared__ T sB[KC][TN];
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  T acc[RM][RN];
-#pragma unroll
-  for (int i = 0; i < RM; ++i)
-#pragma unroll
-    for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
-#pragma unroll
-  for (int q = 0; q < NSEG; ++q) {
-    if (q >= nseg) break;
-    const Seg<T> s = sg[q];
-    for (int k0 = 0; k0 < s.K; k0 += KC) {
-      for (int e = threadIdx.x; e < KC * TM; e += 256) {
-        int kk, mm;
-        if (s.transA) {
-          mm = e % TM;
-          kk = e / TM;
-        } else {
-          kk = e % KC;
-          mm = e / KC;
-        }
-        const int gm = m0 + mm, gk = k0 + kk;
-        T v = T(0);
-        if (gm < M && gk < s.K) v = s.transA ? s.A[(int64_t)gk * s.lda + gm] : s.A[(int64_t)gm * s.lda + gk];
-        sA[kk][mm] = v;
-      }
-      for (int e = threadIdx.x; e < KC * TN; e += 256) {
-        const int kk = e / TN, nn = e % TN;
-        const int gn = n0 + nn, gk = k0 + kk;
-        sB[kk][nn] = (gn < N && gk < s.K) ? s.B[(int64_t)gk * s.ldb + gn] : T(0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        T a[RM], b[RN];
-#pragma unroll
-        for (int i = 0; i < RM; ++i) a[i] = sA[kk][ty * RM + i];
-#pragma unroll
-        for (int j = 0; j < RN; ++j) b[j] = sB[kk][tx + j * TX];
-#pragma unroll
-        for (int i = 0; i < RM; ++i)
-#pragma unroll
-          for (int j = 0; j < RN; ++j) acc[i][j] += a[i] * b[j];
-      }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < RM; ++i) {
-    const int gm = m0 + ty * RM + i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < RN; ++j) {
-      const int gn = n0 + tx + j * TX;
-      if (gn < N) {
-        T *c = C + (int64_t)gm * ldc + gn;
-        *c = beta ? *c + alpha * acc[i][j] : alpha * acc[i][j];
-      }
-    }
-  }
+  tile_gemm_mfma<T, TM, TN, NSEG>(
+      M, N, m0, n0, nseg, [&](int q) { return sg[q].K; },
+      [&](int q, int m, int k) {
+        const Seg<T> &s = sg[q];
+        return s.transA ? s.A[(int64_t)k * s.lda + m] : s.A[(int64_t)m * s.lda + k];
+      },
+      [&](int q, int k, int n) { return sg[q].B[(int64_t)k * sg[q].ldb + n]; },
+      [&](int m, int n, T v) {
+        T *c = C + (int64_t)m * ldc + n;
+        *c = beta ? *c + alpha * v : alpha * v;
+      });
 }
 
 // the work entry owning workgroup wg: last entry with first <= wg
@@ -269,59 +218,9 @@ __global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, const EnvWor
 // accumulating store; same tiling as tile_gemm.
 template <typename T, int TM, int TN, int RM, int RN, class LA, class LB, class SC>
 __device__ void tile_gemm_f(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc) {
-  if constexpr (std::is_same<T, double>::value) {
-    tile_gemm_mfma<TM, TN, 1>(
-        M, N, m0, n0, 1, [&](int) { return K; }, [&](int, int m, int k) { return la(m, k); },
-        [&](int, int k, int n) { return lb(k, n); }, sc);
-    return;
-  }
-  constexpr int KC = 16;
-  constexpr int TX = TN / RN;
-  static_assert((TM / RM) * (TN / RN) == 256, "tile");
-  __shared__ T sA[KC][TM + 1];
-  __shared__ T sB[KC][TN];
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  T acc[RM][RN];
-#pragma unroll
-  for (int i = 0; i < RM; ++i)
-#pragma unroll
-    for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * TM; e += 256) {
-      const int kk = e % KC, mm = e / KC;
-      const int gm = m0 + mm, gk = k0 + kk;
-      sA[kk][mm] = (gm < M && gk < K) ? la(gm, gk) : T(0);
-    }
-    for (int e = threadIdx.x; e < KC * TN; e += 256) {
-      const int kk = e / TN, nn = e % TN;
-      const int gn = n0 + nn, gk = k0 + kk;
-      sB[kk][nn] = (gn < N && gk < K) ? lb(gk, gn) : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      T av[RM], bv[RN];
-#pragma unroll
-      for (int i = 0; i < RM; ++i) av[i] = sA[kk][ty * RM + i];
-#pragma unroll
-      for (int j = 0; j < RN; ++j) bv[j] = sB[kk][tx + j * TX];
-#pragma unroll
-      for (int i = 0; i < RM; ++i)
-#pragma unroll
-        for (int j = 0; j < RN; ++j) acc[i][j] += av[i] * bv[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < RM; ++i) {
-    const int gm = m0 + ty * RM + i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < RN; ++j) {
-      const int gn = n0 + tx + j * TX;
-      if (gn < N) sc(gm, gn, acc[i][j]);
-    }
-  }
+  tile_gemm_mfma<T, TM, TN, 1>(
+      M, N, m0, n0, 1, [&](int) { return K; }, [&](int, int m, int k) { return la(m, k); },
+      [&](int, int k, int n) { return lb(k, n); }, sc);
 }
 
 // dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b],
