@@ -1678,6 +1678,8 @@ void rotate_integrals(const tnqe_problem &pb, const std::vector<double> &U, std:
   rot2(pb.h.data(), hi.data());
   gi.assign(N2 * N2, 0.0);
   if (pb.K > 0) {
+    // (pq|rs) = sum_k L^k_pq L^k_rs is symmetric under pq <-> rs: the upper
+    // triangle is accumulated (in the same k order) and mirrored
     std::vector<double> Lk(N2);
     for (int k = 0; k < pb.K; ++k) {
       rot2(pb.L.data() + (size_t)k * N2, Lk.data());
@@ -1685,9 +1687,11 @@ void rotate_integrals(const tnqe_problem &pb, const std::vector<double> &U, std:
         const double v = Lk[x];
         if (v == 0.0) continue;
         double *row = gi.data() + x * N2;
-        for (size_t y = 0; y < N2; ++y) row[y] += v * Lk[y];
+        for (size_t y = x; y < N2; ++y) row[y] += v * Lk[y];
       }
     }
+    for (size_t x = 0; x < N2; ++x)
+      for (size_t y = x + 1; y < N2; ++y) gi[y * N2 + x] = gi[x * N2 + y];
   } else {
     // four quarter transformations of (pq|rs)
     std::vector<double> a(pb.g), b(N2 * N2);
@@ -1727,7 +1731,8 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   // ---- host: integrals, MPO, plans
   MpoStructure &mpo = mpo_for(ctx, N);
   const int64_t nnz = mpo.site_nnz_off[N];
-  std::vector<double> vals((size_t)nnz * M);
+  // the coefficients of all bases go straight into pinned staging memory
+  double *vals = static_cast<double *>(ctx->staging.reserve((size_t)nnz * M * sizeof(double)));
   {
     // one basis per host thread: rotated integrals and MPO coefficients
     const int nth = std::max(1, std::min<int>(M, (int)std::thread::hardware_concurrency()));
@@ -1740,7 +1745,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
           for (int i = w; i < M; i += nth) {
             rotate_integrals(pb, pb.mps[i].U, hi, gi);
             mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
-            std::copy(v1.begin(), v1.end(), vals.begin() + (size_t)i * nnz);
+            std::copy(v1.begin(), v1.end(), vals + (size_t)i * nnz);
           }
         } catch (const std::exception &e) {
           errs[w] = e.what();
@@ -1749,7 +1754,8 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     for (auto &t : pool) t.join();
     for (auto &e : errs) require(e.empty(), TNQE_EINVAL, e);
   }
-  const double *dvals = c.upload(vals);
+  double *dvals = c.dev<double>((size_t)nnz * M);
+  TNQE_HIP(hipMemcpyAsync(dvals, vals, (size_t)nnz * M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   std::vector<std::pair<int, int>> pairs;
   std::vector<int> ket_of_pair;
   std::vector<std::pair<int, int>> offd;
