@@ -2204,6 +2204,9 @@ tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, c
     const int nslot = pb->nslot();
     int64_t total = 0;
     pb->mps.resize(M);
+    // bond labels per MPS, kept for the scan of the site tensors, which runs
+    // on the host workers (the labels and U are checked serially first)
+    std::vector<std::vector<std::vector<int>>> lab_a(M), lab_b(M);
     for (int i = 0; i < M; ++i) {
       const tnqe_mps &m = mps[i];
       require(m.bond_dim && m.bond_qn && m.sites && m.U, TNQE_EINVAL, "MPS field is NULL");
@@ -2239,9 +2242,20 @@ tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, c
           require(std::fabs(acc - (a == b ? 1.0 : 0.0)) <= 1e-10, TNQE_ENOTORTH, "U is not orthogonal");
         }
       pm.site_off.resize(N);
-      const double *sp = m.sites;
       for (int p = 0; p < N; ++p) {
         pm.site_off[p] = total;
+        total += (int64_t)pm.dims[p] * 4 * pm.dims[p + 1];
+      }
+      lab_a[i] = std::move(qa);
+      lab_b[i] = std::move(qb);
+    }
+    // site tensors: finite, and nonzero only inside their particle-number
+    // blocks (one MPS per worker)
+    host_pool(ctx).parallel_for(M, [&](int i) {
+      const auto &pm = pb->mps[i];
+      const auto &qa = lab_a[i], &qb = lab_b[i];
+      const double *sp = mps[i].sites;
+      for (int p = 0; p < N; ++p) {
         const int dl = pm.dims[p], dr = pm.dims[p + 1];
         for (int l = 0; l < dl; ++l)
           for (int k = 0; k < 4; ++k)
@@ -2253,9 +2267,8 @@ tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, c
                         "site tensor entry outside its particle-number block");
             }
         sp += (int64_t)dl * 4 * dr;
-        total += (int64_t)dl * 4 * dr;
       }
-    }
+    });
     TNQE_HIP(hipMalloc(&pb->d_sites, std::max<int64_t>(1, total) * sizeof(double)));
     pb->device = ctx->device;
     int64_t o = 0;
