@@ -161,6 +161,17 @@ def test_input_validation(ctx):
     with pytest.raises(T.TnqeError) as e:
         ctx.subspace(_with(base, mps=[synth.MPS(sites, base.mps[0].bond_qn, base.mps[0].U)]), chi=4)
     assert e.value.status == -4
+    # the same checks on the second MPS of two (scanned by another host worker)
+    sites = [a.copy() for a in base.mps[1].sites]
+    sites[2][0, 0, :] = 1.0
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(_with(base, mps=[base.mps[0], synth.MPS(sites, base.mps[1].bond_qn, base.mps[1].U)]), chi=4)
+    assert e.value.status == -4
+    sites = [a.copy() for a in base.mps[1].sites]
+    sites[-1].flat[0] = np.inf
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(_with(base, mps=[base.mps[0], synth.MPS(sites, base.mps[1].bond_qn, base.mps[1].U)]), chi=4)
+    assert e.value.status == -9
     h = base.h.copy()
     h[0, 0] = np.nan
     with pytest.raises(T.TnqeError) as e:
