@@ -170,3 +170,38 @@ def test_app_d_maximal_entanglement(N):
     st = M.gate_and_truncate(sites, qn, N // 2 - 1, np.eye(16), chi, 1e-13)
     assert abs(st["discarded"] - (1 - chi * 2.0 ** (-N))) < 1e-12
     assert st["gap"] == pytest.approx(0.0, abs=1e-12)     # the all-ties case
+
+
+def test_select_kept_is_best_subset_brute_force():
+    """The truncation rule of App. A1 against exhaustive search on tiny lists:
+    among all index sets of the kept size, the one with the largest retained
+    weight (ties: the lexicographically smallest index set, i.e. equal values
+    kept in list order), the kept size being min(chi, #{s^2 > tau sum s^2})."""
+    from itertools import combinations
+    rng = np.random.default_rng(7)
+    for case in range(300):
+        n = int(rng.integers(1, 8))
+        # few distinct values so that ties are frequent; some exact zeros
+        sv = rng.choice([0.0, 0.1, 0.25, 0.5, 1.0, 2.0], size=n)
+        chi = int(rng.integers(1, n + 2))
+        tau = float(rng.choice([0.0, 1e-3, 0.02, 0.3]))
+        mask, keep, nnz, gap, disc, total = M.select_kept(sv, chi, tau)
+        w2 = sv ** 2
+        assert total == pytest.approx(w2.sum(), abs=0)
+        above = sum(1 for x in w2 if x > tau * w2.sum())
+        assert nnz == above and keep == min(chi, above)
+        best = None
+        for S in combinations(range(n), keep):          # lexicographic order
+            w = sum(w2[i] for i in S)
+            if best is None or w > best[0] + 1e-12:       # ties differ only by rounding
+                best = (w, S)
+        want = np.zeros(n, dtype=bool)
+        want[list(best[1])] = True
+        assert (mask == want).all(), (sv, chi, tau)
+        assert disc == pytest.approx(w2[~want].sum(), abs=1e-15)
+        if 0 < keep < n:
+            s_in = min(sv[want])
+            s_out = max(sv[~want])
+            assert gap == pytest.approx((s_in - s_out) / s_in)
+        else:
+            assert gap is None
