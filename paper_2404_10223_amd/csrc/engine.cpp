@@ -462,10 +462,11 @@ struct JacobiPlan {
 JacobiPlan jacobi_plan(int n, int m) {
   JacobiPlan jp;
   const int P = (n + 1) / 2, NTr = n / 2;
-  // preferred components per lane (tuning: TNQE_JACOBI_E = 8 ... 24)
+  // preferred components per lane (tuning: TNQE_JACOBI_E = 4 ... 24; 8 was
+  // the fastest at N = 24, chi = 256: more lanes per vector, shorter rounds)
   static const int target = [] {
     const char *e = std::getenv("TNQE_JACOBI_E");
-    const int v = e ? std::atoi(e) : 16;
+    const int v = e ? std::atoi(e) : 8;
     return std::min(kJacobiMaxE, std::max(4, v / 4 * 4));
   }();
   int best = -1;
