@@ -39,14 +39,17 @@
  *     when det W = -1).
  *   - Truncation keeps the min(chi, #{s^2 > tau_w sum s^2}) largest singular
  *     values over all quantum-number blocks; singular values are absorbed to
- *     the right; no renormalisation.
+ *     the right; no renormalisation unless tnqe_options.renormalize is set.
  *
  * Threading and streams: one context per host thread; every call is blocking
  * (it synchronises the context's stream before returning host results).
  * Errors: every entry point returns a tnqe_status; negative means failure,
  * outputs are then left untouched and tnqe_last_error(ctx) holds a message.
- * Memory: the library allocates device memory itself (hipMalloc, kept in a
- * pool owned by the context and released by tnqe_destroy / tnqe_trim).
+ * Memory: device memory comes either from a workspace the caller allocates
+ * (tnqe_subspace / tnqe_subspace_batch with a non-NULL workspace: the library
+ * then allocates no device memory at all; tnqe_workspace_size gives a size
+ * that always suffices) or, when no workspace is given, from a pool the
+ * context owns (hipMalloc on demand, kept until tnqe_trim / tnqe_destroy).
  */
 #ifndef TNQE_H
 #define TNQE_H
@@ -68,7 +71,7 @@ typedef enum {
   TNQE_ENOTORTH = -3,    /* a rotation U is not orthogonal (1e-10)       */
   TNQE_EQN = -4,         /* a site tensor breaks particle-number blocks  */
   TNQE_ENOMEM = -5,      /* device allocation failed                     */
-  TNQE_EWORKSPACE = -6,  /* reserved                                     */
+  TNQE_EWORKSPACE = -6,  /* the caller's workspace is too small           */
   TNQE_EHIP = -7,        /* a HIP runtime call failed                    */
   TNQE_ESINGULAR = -8,   /* S has no eigenvalue above the threshold      */
   TNQE_ENONFINITE = -9,  /* NaN/Inf in an input or a result              */
@@ -118,7 +121,14 @@ typedef struct {
   double eps_S;              /* relative eigenvalue threshold on S (default 1e-12)    */
   double tau_w;              /* relative discarded-weight floor (default 1e-13)       */
   int32_t max_sweeps;        /* Jacobi sweep limit (default 40)                        */
-  int32_t reserved[7];
+  int32_t renormalize;       /* 1: after every truncation rescale the kept singular
+                                values so the ket keeps its weight (App. A1 asks for a
+                                renormalisation in its DMRG setting; optional here);
+                                0 (default): plain projection, no rescaling           */
+  int32_t autotune;          /* 1: environment tile shapes from the context's tuned
+                                table (measured on first use, cached on disk); 0: the
+                                fixed shape rule                                       */
+  int32_t reserved[5];
 } tnqe_options;
 
 typedef struct {
@@ -151,6 +161,7 @@ typedef struct {
   int32_t env_kind_launches[8];     /* launches of each environment kernel              */
   int32_t n_fp32_pairs;             /* pairs contracted in FP32 (precision modes 1, 2)  */
   int32_t reserved[7];
+  double ws_peak_bytes;             /* workspace calls: bytes of it actually used       */
 } tnqe_report;
 
 /* Fill defaults (chi = 16, FP64, eps_S = 1e-12, tau_w = 1e-13). */
@@ -185,10 +196,46 @@ tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *prob
                              const tnqe_options *opts, double *const *H, double *const *S,
                              double *E, tnqe_report *rep);
 
-/* upload + solve + free in one call. */
-tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M,
-                          const tnqe_mps *mps, const tnqe_options *opts,
-                          double *H, double *S, double *E, double *c, tnqe_report *rep);
+/* Device bytes that always suffice for tnqe_subspace with these inputs and
+ * options: the site tensors, the MPO of H (eq. ham_def, Sec. II.A), the
+ * rotated kets of every pair i < j at the bond capacities min(chi, exact
+ * sector dimension) (Sec. II.B, App. A1), the largest gate-step scratch, and
+ * the environment sweep of one pair at those capacities.  Host-side only
+ * (validation of the inputs included); the bound is conservative: truncated
+ * bonds are usually much smaller, and tnqe_report.ws_peak_bytes gives what a
+ * call really used. */
+tnqe_status tnqe_workspace_size(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                                const tnqe_options *opts, size_t *bytes);
+
+/* The problem statement of the paper in one call: integrals h_pq and (pq|rs)
+ * (eq. ham_def), M MPS each in its own orbital basis (eq. tnqe, Sec. II.B),
+ * bond dimension chi; returns the pencil H_ij = <phi_i|H|phi_j>,
+ * S_ij = <phi_i|phi_j> (eq. mat_els) and the lowest root E of H c = E S c
+ * (eq. GEE) with its coefficients c (c^T S c = 1).
+ *   ham, mps[M], opts: host, read during the call only.
+ *   workspace: device memory of ws_bytes bytes owned by the caller (e.g. a
+ *     torch.empty(..., dtype=torch.uint8, device='cuda') buffer), not in use
+ *     by other work; every device buffer of the call lies in it, the call
+ *     allocates no device memory, and the workspace is free again when the
+ *     call returns.  TNQE_EWORKSPACE when it is too small (outputs
+ *     untouched).  NULL: the library allocates from the context's pool.
+ *   H, S: [M][M] host, row-major; E: [1]; c: [M] or NULL; rep: or NULL. */
+tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                          const tnqe_options *opts, void *workspace, size_t ws_bytes, double *H, double *S,
+                          double *E, double *c, tnqe_report *rep);
+
+/* n_sub independent subspaces (the independent problems of a set of
+ * subspace calculations, e.g. the parallel batches of matrix elements of
+ * App. B), each as in tnqe_subspace: ham[s], M[s], mps[s][0..M[s]),
+ * opts[s] (each with its own chi).  The subspaces share the workspace (each
+ * uses it in turn; give the largest tnqe_workspace_size of the set), or NULL
+ * for the context's pool.  H[s], S[s]: [M[s]][M[s]] host; E: [n_sub];
+ * rep: [n_sub] or NULL.  Stops at the first failing subspace and returns its
+ * status (tnqe_last_error names it); no output is written then. */
+tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamiltonian *ham, const int32_t *M,
+                                const tnqe_mps *const *mps, const tnqe_options *opts, void *workspace,
+                                size_t ws_bytes, double *const *H, double *const *S, double *E,
+                                tnqe_report *rep);
 
 const char *tnqe_status_string(tnqe_status st);
 const char *tnqe_last_error(const tnqe_ctx *ctx);
@@ -231,6 +278,16 @@ tnqe_status tnqe_debug_host_pool(int32_t workers, int32_t jobs, int64_t *calls);
  *   local memory holds. */
 tnqe_status tnqe_debug_select(tnqe_ctx *ctx, int32_t nket, const int32_t *nblk, const int32_t *n,
                               const double *sv, int32_t chi, double tau, int32_t *kept, double *stats);
+
+/* tnqe_debug_gep: the device eigensolver of the pencil on given H, S ([M][M]
+ * host, row-major, symmetric, M <= 32) with S-eigenvalue threshold
+ * eps_S * lambda_max(S), by the projection method (Sec. V "Regulating the
+ * subspace condition number", App. A2).  out[8 + M] (host): E, cond(S) over
+ * the kept eigenvalues, lambda_min(S), number dropped, kappa_1 = |c|^2 /
+ * sqrt(E^2 + 1) (App. A2), status (0, or 1 when nothing is kept), 0, 0, then
+ * c[0..M) with c^T S c = 1. */
+tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const double *S, double eps_S,
+                           double *out);
 
 #ifdef __cplusplus
 }

@@ -281,3 +281,47 @@ def expectation(mpo, bra, bra_qn, ket, ket_qn):
     (sN,) = map(tuple, np.unique(ket_qn[N], axis=0).tolist())
     blk = env[(0, 0)][sN]
     return float(blk[chi[("H",)], 0, 0]), float(blk[chi[("I",)], 0, 0])
+
+
+# ------------------------------------------------------ plain contraction (cross-check)
+def expectation_plain(mpo, bra, ket):
+    """(H, S) by the plainest left sweep: one dense environment E[a', w, a]
+    over the full bond and channel ranges, no quantum-number or channel-class
+    grouping.  Per site x, with the MPO read as one matrix C[k', k] over
+    (output channel, input channel) for each pair of local states:
+
+        T[a', w, k, b]  = sum_a E[a', w, a] ket[a, k, b]
+        Y[a', w', k', b] = sum_{w, k} C[k', k][w', w] T[a', w, k, b]
+        E'[b', w', b]   = sum_{a', k'} bra[a', k', b'] Y[a', w', k', b]
+
+    It touches every zero the block-sparse sweep skips, so it is slow (minutes
+    at N = 24, chi = 256); it exists to cross-check `expectation` on the full-
+    size workload, where no sector FCI is possible.
+    """
+    N = mpo.N
+    idx = [{w: i for i, w in enumerate(c)} for c in mpo.chans]
+    E = np.zeros((1, len(mpo.chans[0]), 1))
+    E[0, idx[0][("I",)], 0] = 1.0
+    for x in range(N):
+        A, B = bra[x], ket[x]
+        dbl, dkl = A.shape[0], B.shape[0]
+        dbr, dkr = A.shape[2], B.shape[2]
+        Din, Dout = len(mpo.chans[x]), len(mpo.chans[x + 1])
+        C = np.zeros((4, 4, Dout, Din))
+        for (wi, wo), m in mpo.W[x].items():
+            C[:, :, idx[x + 1][wo], idx[x][wi]] += m
+        # T[k][w, a', b]
+        T = np.tensordot(E, B, axes=([2], [0]))               # [a', w, k, b]
+        T = np.ascontiguousarray(T.transpose(2, 1, 0, 3))     # [k, w, a', b]
+        Y = np.zeros((4, Dout, dbl * dkr))
+        for kp in range(4):
+            for k in range(4):
+                if np.any(C[kp, k]):
+                    Y[kp] += C[kp, k] @ T[k].reshape(Din, dbl * dkr)
+        del T
+        Y = Y.reshape(4, Dout, dbl, dkr)                       # [k', w', a', b]
+        En = np.zeros((dbr, Dout, dkr))
+        for kp in range(4):
+            En += np.tensordot(A[:, kp, :], Y[kp], axes=([0], [1]))   # [b', w', b]
+        E = En
+    return float(E[0, idx[N][("H",)], 0]), float(E[0, idx[N][("I",)], 0])

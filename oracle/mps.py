@@ -14,7 +14,7 @@ exact QR/LQ factorisation.  A two-site gate is applied to the centre pair and
 the result split by SVD (eq. svd_longform), keeping the chi largest singular
 values over all quantum-number blocks; the singular values are absorbed to the
 right, so the centre moves one site to the right (the "Sigma contracted into V"
-step after eq. svd_longform).  No renormalisation after truncation: the kept
+step after eq. svd_longform).  No renormalisation after truncation by default: the kept
 state is the orthogonal projection of the gated state.
 """
 import numpy as np
@@ -136,8 +136,12 @@ def select_kept(allsv, chi_cap, tau_w):
     return kept_mask, keep, nnz, gap, discarded, float(total)
 
 
-def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w):
+def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w, renormalize=False):
     """Apply a 16x16 gate to sites (p, p+1) (centre at p), split by truncated SVD.
+
+    With renormalize, the kept part is rescaled to the weight the gated state
+    had before the cut (App. A1 renormalises after truncating in its DMRG
+    setting; here it is optional, off by default).
 
     Returns a dict with the discarded weight, the number kept, the number of
     nonzero singular values and the relative gap at the cut (None if nothing
@@ -182,6 +186,8 @@ def gate_and_truncate(sites, qn, p, G16, chi_cap, tau_w):
         c += uk.shape[1]
     sites[p] = U.reshape(dl, 4, dn)
     sites[p + 1] = (U.T @ Tm).reshape(dn, 4, dr)
+    if renormalize and discarded > 0.0 and total > discarded:
+        sites[p + 1] = sites[p + 1] * np.sqrt(total / (total - discarded))
     qn[p + 1] = np.array(newq, dtype=np.int64).reshape(-1, 2)
     return dict(discarded=discarded, kept=dn, nonzero=nnz, gap=gap, total=total)
 

@@ -31,7 +31,7 @@ def rotate_integrals(h, L, U):
     return hi, Li
 
 
-def rotate_ket(sites, qn, W, chi_cap, tau_w=1e-13):
+def rotate_ket(sites, qn, W, chi_cap, tau_w=1e-13, renormalize=False):
     """Givens network for W applied to an MPS with truncation after each gate."""
     sites, qn = mpsops.copy_mps(sites, qn)
     centre = mpsops.left_canonicalize(sites, qn)
@@ -41,20 +41,21 @@ def rotate_ket(sites, qn, W, chi_cap, tau_w=1e-13):
     stats = []
     for a, theta in gl:
         centre = mpsops.move_centre(sites, qn, centre, a)
-        stats.append(mpsops.gate_and_truncate(sites, qn, a, gates.g4(theta), chi_cap, tau_w))
+        stats.append(mpsops.gate_and_truncate(sites, qn, a, gates.g4(theta), chi_cap, tau_w, renormalize))
         centre = a + 1
     return sites, qn, stats
 
 
-def pair_element(prob, i, j, chi_cap=None, tau_w=1e-13, h_method="auto", mpo_cache=None):
-    """(H_ij, S_ij, truncation stats) for one pair i <= j."""
+def pair_element(prob, i, j, chi_cap=None, tau_w=1e-13, h_method="auto", mpo_cache=None, return_ket=False,
+                 renormalize=False):
+    """(H_ij, S_ij, truncation stats[, rotated ket sites]) for one pair i <= j."""
     chi_cap = prob.chi if chi_cap is None else chi_cap
     bi, bj = prob.mps[i], prob.mps[j]
     if i == j:
         ket, kqn, stats = bi.sites, bi.bond_qn, []
     else:
         W = bi.U.T @ bj.U
-        ket, kqn, stats = rotate_ket(bj.sites, bj.bond_qn, W, chi_cap, tau_w)
+        ket, kqn, stats = rotate_ket(bj.sites, bj.bond_qn, W, chi_cap, tau_w, renormalize)
     S = mpsops.overlap(bi.sites, ket)
     hi, Li = rotate_integrals(prob.h, prob.L, bi.U)
     if h_method == "auto":
@@ -72,10 +73,12 @@ def pair_element(prob, i, j, chi_cap=None, tau_w=1e-13, h_method="auto", mpo_cac
                 mpo_cache[key] = W_
         H, S2 = expectation(W_, bi.sites, bi.bond_qn, ket, kqn)
         H += prob.e_core * S
+    if return_ket:
+        return H, S, stats, ket
     return H, S, stats
 
 
-def subspace(prob, chi_cap=None, tau_w=1e-13, h_method="auto", eps_S=1e-12):
+def subspace(prob, chi_cap=None, tau_w=1e-13, h_method="auto", eps_S=1e-12, renormalize=False):
     """Full pencil, lowest eigenvalue and a report (FP64, CPU)."""
     M = prob.M
     H = np.zeros((M, M))
@@ -84,7 +87,7 @@ def subspace(prob, chi_cap=None, tau_w=1e-13, h_method="auto", eps_S=1e-12):
     cache = {}
     for i in range(M):
         for j in range(i, M):
-            h, s, st = pair_element(prob, i, j, chi_cap, tau_w, h_method, cache)
+            h, s, st = pair_element(prob, i, j, chi_cap, tau_w, h_method, cache, renormalize=renormalize)
             H[i, j] = H[j, i] = h
             S[i, j] = S[j, i] = s
             disc[i, j] = sum(x["discarded"] for x in st)

@@ -35,7 +35,7 @@ class _Mps(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("chi_cap_override", C.c_int32), ("precision", C.c_int32),
                 ("eps_S", C.c_double), ("tau_w", C.c_double), ("max_sweeps", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("renormalize", C.c_int32), ("autotune", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class _Report(C.Structure):
@@ -52,13 +52,14 @@ class _Report(C.Structure):
                 ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32),
                 ("svd_kind_launches", C.c_int32 * 16), ("env_kind_launches", C.c_int32 * 8),
                 ("n_fp32_pairs", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("reserved", C.c_int32 * 7), ("ws_peak_bytes", C.c_double)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
-           "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_subspace",
-           "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
-           "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool"]
+           "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_workspace_size", "tnqe_subspace",
+           "tnqe_subspace_batch", "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
+           "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool", "tnqe_debug_select",
+           "tnqe_debug_gep"]
 
 _lib = None
 
@@ -87,8 +88,14 @@ def lib():
     L.tnqe_solve.argtypes = [vp, vp, C.POINTER(_Opts), dp, dp, dp, dp, C.POINTER(_Report)]
     L.tnqe_solve_batch.argtypes = [vp, ip, C.POINTER(vp), C.POINTER(_Opts), C.POINTER(dp), C.POINTER(dp),
                                    dp, C.POINTER(_Report)]
-    L.tnqe_subspace.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), dp, dp, dp, dp,
-                                C.POINTER(_Report)]
+    L.tnqe_workspace_size.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts),
+                                      C.POINTER(C.c_size_t)]
+    L.tnqe_subspace.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), vp, C.c_size_t,
+                                dp, dp, dp, dp, C.POINTER(_Report)]
+    L.tnqe_subspace_batch.argtypes = [vp, ip, C.POINTER(_Ham), C.POINTER(ip), C.POINTER(C.POINTER(_Mps)),
+                                      C.POINTER(_Opts), vp, C.c_size_t, C.POINTER(dp), C.POINTER(dp), dp,
+                                      C.POINTER(_Report)]
+    L.tnqe_debug_gep.argtypes = [vp, ip, dp, dp, C.c_double, dp]
     L.tnqe_status_string.argtypes = [C.c_int]
     L.tnqe_status_string.restype = C.c_char_p
     L.tnqe_last_error.argtypes = [vp]
@@ -127,7 +134,8 @@ def _check(st, ctx=None):
         raise TnqeError(st, f"{L.tnqe_status_string(st).decode()}: {msg}")
 
 
-def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-13, max_sweeps=40):
+def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-13, max_sweeps=40,
+            renormalize=False, autotune=False):
     o = _Opts()
     lib().tnqe_default_options(C.byref(o))
     o.chi = chi
@@ -136,7 +144,29 @@ def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-
     o.eps_S = eps_S
     o.tau_w = tau_w
     o.max_sweeps = max_sweeps
+    o.renormalize = int(bool(renormalize))
+    o.autotune = int(bool(autotune))
     return o
+
+
+def _ptr(buf):
+    """(device address, bytes) of a workspace given as a torch tensor, or (None, 0)."""
+    if buf is None:
+        return None, 0
+    if isinstance(buf, int):
+        raise TypeError("pass the workspace as a torch tensor")
+    return C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
+
+
+def workspace_size(prob, ctx=None, **kw):
+    """Device bytes that always suffice for a workspace call (host-side only:
+    works without a GPU when ctx is None)."""
+    pk = _Packed(prob)
+    o = options(**kw)
+    out = C.c_size_t(0)
+    h = ctx.h if ctx is not None else None
+    _check(lib().tnqe_workspace_size(h, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), C.byref(out)), h)
+    return out.value
 
 
 def report_dict(r):
@@ -203,12 +233,56 @@ class Context:
         _check(self.L.tnqe_upload(self.h, C.byref(pk.ham), prob.M, pk.mps, C.byref(out)), self.h)
         return Uploaded(self, out, prob.M)
 
-    def subspace(self, prob, **kw):
-        up = self.upload(prob)
-        try:
-            return up.solve(**kw)
-        finally:
-            up.free()
+    def subspace(self, prob, workspace=None, **kw):
+        """One call from host inputs (tnqe_subspace).  workspace: a torch
+        device tensor the call takes all its device memory from, or None (the
+        context's pool)."""
+        pk = _Packed(prob)
+        o = options(**kw)
+        M = prob.M
+        H = np.zeros((M, M))
+        S = np.zeros((M, M))
+        E = np.zeros(1)
+        c = np.zeros(M)
+        r = _Report()
+        wp, wb = _ptr(workspace)
+        _check(self.L.tnqe_subspace(self.h, C.byref(pk.ham), M, pk.mps, C.byref(o), wp, wb, _dptr(H), _dptr(S),
+                                    _dptr(E), _dptr(c), C.byref(r)), self.h)
+        return H, S, float(E[0]), c, report_dict(r)
+
+    def workspace_size(self, prob, **kw):
+        return workspace_size(prob, self, **kw)
+
+    def subspace_batch(self, probs, chis=None, workspace=None, **kw):
+        """Several subspaces from host inputs (tnqe_subspace_batch)."""
+        n = len(probs)
+        chis = [p.chi for p in probs] if chis is None else chis
+        packs = [_Packed(p) for p in probs]
+        hams = (_Ham * n)(*[pk.ham for pk in packs])
+        Ms = np.array([p.M for p in probs], dtype=np.int32)
+        mps = (C.POINTER(_Mps) * n)(*[C.cast(pk.mps, C.POINTER(_Mps)) for pk in packs])
+        o = (_Opts * n)(*[options(chi=int(ch), **kw) for ch in chis])
+        Hs = [np.zeros((p.M, p.M)) for p in probs]
+        Ss = [np.zeros((p.M, p.M)) for p in probs]
+        E = np.zeros(n)
+        reps = (_Report * n)()
+        hp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Hs])
+        sp = (C.POINTER(C.c_double) * n)(*[_dptr(x) for x in Ss])
+        wp, wb = _ptr(workspace)
+        _check(self.L.tnqe_subspace_batch(self.h, n, hams, _iptr(Ms), mps, o, wp, wb, hp, sp, _dptr(E), reps),
+               self.h)
+        return Hs, Ss, E, [report_dict(r) for r in reps]
+
+    def debug_gep(self, H, S, eps_S=1e-12):
+        """Device eigensolver on a given pencil: dict of E, cond_S, lambda_min,
+        n_dropped, kappa1, status and c."""
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        M = H.shape[0]
+        out = np.zeros(8 + M)
+        _check(self.L.tnqe_debug_gep(self.h, M, _dptr(H), _dptr(S), float(eps_S), _dptr(out)), self.h)
+        return dict(E=out[0], cond_S=out[1], lambda_min=out[2], n_dropped=int(out[3]), kappa1=out[4],
+                    status=int(out[5]), c=out[8:8 + M].copy())
 
     def debug_select(self, blocks, chi, tau):
         """Device truncation rule on given singular values: blocks[t] is the

@@ -27,6 +27,18 @@ namespace tnqe {
 // ------------------------------------------------------------ memory helpers
 void *DevicePool::get(size_t bytes) {
   bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+  if (arena_base_) {
+    if (bytes > arena_size_ - arena_top_)
+      throw Error(TNQE_EWORKSPACE, "workspace too small: " + std::to_string(arena_top_) + " bytes in use, " +
+                                       std::to_string(bytes) + " more needed, " + std::to_string(arena_size_) +
+                                       " available");
+    void *p = arena_base_ + arena_top_;
+    arena_starts_.push_back(arena_top_);
+    order_.push_back(p);
+    arena_top_ += bytes;
+    arena_peak_ = std::max(arena_peak_, arena_top_);
+    return p;
+  }
   int best = -1;
   for (size_t i = 0; i < bufs_.size(); ++i)
     if (!bufs_[i].used && bufs_[i].n >= bytes && (best < 0 || bufs_[i].n < bufs_[best].n)) best = (int)i;
@@ -60,6 +72,12 @@ void *DevicePool::get(size_t bytes) {
 }
 
 void DevicePool::rewind(size_t m) {
+  if (arena_base_) {
+    if (order_.size() > m) arena_top_ = arena_starts_[m];
+    order_.resize(std::min(order_.size(), m));
+    arena_starts_.resize(order_.size());
+    return;
+  }
   while (order_.size() > m) {
     void *p = order_.back();
     order_.pop_back();
@@ -71,6 +89,8 @@ void DevicePool::rewind(size_t m) {
 void DevicePool::release_all() {
   for (auto &b : bufs_) b.used = false;
   order_.clear();
+  arena_starts_.clear();
+  arena_top_ = 0;
 }
 
 void DevicePool::trim() {
@@ -78,6 +98,28 @@ void DevicePool::trim() {
   bufs_.clear();
   order_.clear();
   held_ = 0;
+}
+
+void DevicePool::set_arena(void *base, size_t bytes) {
+  require(order_.empty(), TNQE_EINVAL, "device buffers still in use");
+  char *b = static_cast<char *>(base);
+  const size_t skip = (256 - reinterpret_cast<uintptr_t>(b) % 256) % 256;
+  require(bytes >= skip, TNQE_EWORKSPACE, "workspace too small");
+  arena_base_ = b + skip;
+  arena_size_ = (bytes - skip) & ~size_t(255);
+  arena_top_ = arena_peak_ = 0;
+  arena_starts_.clear();
+}
+
+void DevicePool::clear_arena() {
+  arena_base_ = nullptr;
+  arena_size_ = arena_top_ = 0;
+  arena_starts_.clear();
+  order_.clear();
+}
+
+size_t DevicePool::available() const {
+  return arena_base_ ? arena_size_ - arena_top_ : std::numeric_limits<size_t>::max();
 }
 
 // How long a waiting thread polls before it blocks: the per-ket loops of the
@@ -173,6 +215,7 @@ void Staging::reset() {
   used_ = 0;
   for (auto &o : old_) (void)hipHostFree(o.first);
   old_.clear();
+  heap_.clear();
 }
 
 void *Staging::put(const void *src, size_t bytes) {
@@ -184,6 +227,11 @@ void *Staging::put(const void *src, size_t bytes) {
 void *Staging::reserve(size_t bytes) {
   const size_t need = (bytes + 255) & ~size_t(255);
   if (used_ + need > cap_) {
+    if (!grow_) {
+      // pageable host memory: kept until the next reset (copies may be in flight)
+      heap_.emplace_back(new char[std::max<size_t>(need, 256)]);
+      return heap_.back().get();
+    }
     // keep the old buffer alive until the next reset (copies may be in flight)
     if (buf_) old_.push_back({buf_, cap_});
     cap_ = std::max<size_t>(need, std::max<size_t>(64u << 20, cap_ * 2));
@@ -862,7 +910,7 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
 
 // Gate at (a, a+1) for every ket with its own 16x16 matrix, then truncation.
 void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap, double tau_w,
-               int max_sweeps, TruncStats &ts) {
+               int max_sweeps, bool renormalize, TruncStats &ts) {
   const auto tb0 = Clock::now();
   Call &c = *ks.call;
   // blocks of the new middle sectors (gated Theta) and of the old middle
@@ -972,26 +1020,34 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   int *dkept = c.dev<int>(nblk);
   double *dstats = c.dev<double>((size_t)3 * ks.n);
   const KetTables kt_new = ks.tables();
+  double *dscale = renormalize ? c.dev<double>(ks.n) : nullptr;
   launch_select(dblk, Call::at<const int>(base, o_kf), ks.n, maxv, scratch, chi_cap, tau_w, kt_new, a + 1, dkept,
-                dstats, ctx->stream);
+                dstats, dscale, ctx->stream);
   TNQE_HIP(hipEventRecord(ctx->sel_ev, ctx->stream));
   launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, ctx->stream);
-  launch_split_gate(kt_new, a, dblk, units_at(base, o_us, u_split), scratch, ctx->stream);
+  launch_split_gate(kt_new, a, dblk, units_at(base, o_us, u_split), scratch, dscale, ctx->stream);
   c.check_launch();
   // kept counts and per-ket statistics to pinned host memory on a side
   // stream (the main stream goes on with the factor and split); the host
   // polls for them, then mirrors the new bond for the next step's planning
   const size_t need = (size_t)3 * ks.n + ((size_t)nblk + 1) / 2;
+  double *hbuf = ctx->sv_host;
   if (ctx->sv_cap < need) {
-    if (ctx->sv_host) TNQE_HIP(hipHostFree(ctx->sv_host));
-    ctx->sv_host = nullptr;
-    ctx->sv_cap = 0;
-    const size_t cap = std::max<size_t>(need * 2, 1 << 16);
-    TNQE_HIP(hipHostMalloc((void **)&ctx->sv_host, cap * sizeof(double), hipHostMallocDefault));
-    ctx->sv_cap = cap;
+    if (ctx->no_alloc) {
+      ctx->sv_pageable.resize(need);
+      hbuf = ctx->sv_pageable.data();
+    } else {
+      if (ctx->sv_host) TNQE_HIP(hipHostFree(ctx->sv_host));
+      ctx->sv_host = nullptr;
+      ctx->sv_cap = 0;
+      const size_t cap = std::max<size_t>(need * 2, 1 << 16);
+      TNQE_HIP(hipHostMalloc((void **)&ctx->sv_host, cap * sizeof(double), hipHostMallocDefault));
+      ctx->sv_cap = cap;
+      hbuf = ctx->sv_host;
+    }
   }
-  double *hstats = ctx->sv_host;
-  int *hkept = reinterpret_cast<int *>(ctx->sv_host + (size_t)3 * ks.n);
+  double *hstats = hbuf;
+  int *hkept = reinterpret_cast<int *>(hbuf + (size_t)3 * ks.n);
   TNQE_HIP(hipStreamWaitEvent(ctx->aux[0], ctx->sel_ev, 0));
   TNQE_HIP(hipMemcpyAsync(hstats, dstats, (size_t)3 * ks.n * sizeof(double), hipMemcpyDeviceToHost, ctx->aux[0]));
   TNQE_HIP(hipMemcpyAsync(hkept, dkept, (size_t)nblk * sizeof(int), hipMemcpyDeviceToHost, ctx->aux[0]));
@@ -1026,10 +1082,14 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   }
 }
 
-// Device copy of the sparse groups' CSR structure for this MPO (cached).
-const MpoDevice &mpo_dev_for(tnqe_ctx *ctx, const MpoStructure &mpo) {
-  auto it = ctx->mpo_dev.find(mpo.N);
-  if (it != ctx->mpo_dev.end()) return *it->second;
+// Device copy of the sparse groups' CSR structure for this MPO: cached in the
+// context, or (calls that work in a caller's workspace) placed there.
+const MpoDevice &mpo_dev_for(Call &c, const MpoStructure &mpo) {
+  tnqe_ctx *ctx = c.ctx;
+  if (!ctx->pool.arena()) {
+    auto it = ctx->mpo_dev.find(mpo.N);
+    if (it != ctx->mpo_dev.end()) return *it->second;
+  }
   auto d = std::make_unique<MpoDevice>();
   std::vector<int> rp, cl;
   d->rp_off.resize(mpo.N);
@@ -1043,6 +1103,13 @@ const MpoDevice &mpo_dev_for(tnqe_ctx *ctx, const MpoStructure &mpo) {
     }
   rp.push_back(0);
   cl.push_back(0);
+  if (ctx->pool.arena()) {
+    d->owned = false;
+    d->rowptr = c.upload(rp);   // staged copies: the host vectors may go
+    d->col = c.upload(cl);
+    ctx->mpo_dev_call = std::move(d);
+    return *ctx->mpo_dev_call;
+  }
   TNQE_HIP(hipMalloc(&d->rowptr, rp.size() * sizeof(int)));
   TNQE_HIP(hipMalloc(&d->col, cl.size() * sizeof(int)));
   TNQE_HIP(hipMemcpy(d->rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -1076,81 +1143,41 @@ struct EnvResult {
   int max_pad = 0;
 };
 
-// Environment sweeps of all pairs.  Items are the M bra MPS followed by the
-// rotated kets; pair q contracts bra item pairs[q].first with its ket item.
-// Block slots are sized by the largest dimensions over the items (one
-// descriptor list for all pairs); the kernels use each pair's own extents.
-template <typename T>
-void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
-               const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
-               int64_t nnz_total, EnvResult &res) {
-  hipStream_t st = c.ctx->stream;
-  const auto tq0 = Clock::now();
-  const int N = pb.N, M = pb.M, nslot = pb.nslot(), nb1 = pb.nb + 1, nbond = N + 1;
-  const int nket = kets ? kets->n : 0;
-  const int nitem = M + nket;
-  auto slot_of = [&](int a, int b) { return (a < 0 || b < 0 || a > pb.na || b > pb.nb) ? -1 : a * nb1 + b; };
-  // ---- item sector tables
-  std::vector<int2> itab((size_t)nitem * nbond * nslot, make_int2(0, 0));
-  std::vector<int> iD((size_t)nitem * nbond, 0);
-  for (int it = 0; it < nitem; ++it)
-    for (int b = 0; b <= N; ++b) {
-      int2 *row = itab.data() + ((size_t)it * nbond + b) * nslot;
-      if (it < M) {
-        const auto &m = pb.mps[it];
-        int o = 0;
-        for (int s = 0; s < nslot; ++s) {
-          row[s] = make_int2(o, m.secdim[b][s]);
-          o += m.secdim[b][s];
-        }
-        iD[(size_t)it * nbond + b] = m.dims[b];
-      } else {
-        const int t = it - M;
-        for (int s = 0; s < nslot; ++s) row[s] = kets->hbtab[((size_t)b * kets->n + t) * nslot + s];
-        iD[(size_t)it * nbond + b] = kets->htot[(size_t)b * kets->n + t];
-      }
-    }
-  auto idim = [&](int it, int b, int s) { return s < 0 ? 0 : itab[((size_t)it * nbond + b) * nslot + s].y; };
-  // largest sector dimensions over the items (block slot sizes)
-  std::vector<std::vector<int>> dpad(nbond, std::vector<int>(nslot, 0));
-  for (int b = 0; b <= N; ++b) {
-    for (int s = 0; s < nslot; ++s)
-      for (int it = 0; it < nitem; ++it) dpad[b][s] = std::max(dpad[b][s], idim(it, b, s));
-    for (int it = 0; it < nitem; ++it) res.max_pad = std::max(res.max_pad, iD[(size_t)it * nbond + b]);
-  }
+// Environment layout for given block-slot dimensions dpad[bond][slot]: the
+// offset of every (class, ket sector) block of L at each bond, and per site
+// the GEMM descriptors, channel-mix tasks and sources, dense couplings, tile
+// shapes, X and Y sizes and the final-element terms.  Every size grows with
+// dpad entry by entry, so the layout for an upper bound of the dimensions
+// bounds the memory of the real one.  mdev may be null (sizes only).
+struct EnvSiteTabs {
+  std::vector<EnvG1> g1;
+  std::vector<EnvG2> g2;
+  int tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
+  std::vector<std::vector<EnvGD>> dense;   // dense channel mixing, one level per launch
+  std::vector<int> tmd, tnd;
+  std::vector<MixTask> tasks;
+  std::vector<MixSrc> srcs;
+  std::vector<int> src_nnz;                // stored couplings of each source (work count)
+  int64_t Xsize = 0, Ysize = 0;
+  std::vector<EnvFinal> fin;
+};
+
+struct EnvLayout {
+  std::vector<std::vector<int64_t>> Loff;  // [bond][class * nslot + slot], -1: none
+  std::vector<int64_t> Lsize;              // [bond]
+  std::vector<EnvSiteTabs> tabs;           // [site]
+};
+
+void plan_env_layout(const MpoStructure &mpo, const MpoDevice *mdev, int N, int na, int nb,
+                     const std::vector<std::vector<int>> &dpad, ThreadPool &workers, EnvLayout &lay) {
+  const int nslot = (na + 1) * (nb + 1), nb1 = nb + 1, nbond = N + 1;
+  auto slot_of = [&](int a, int b) { return (a < 0 || b < 0 || a > na || b > nb) ? -1 : a * nb1 + b; };
   auto dp = [&](int b, int s) { return s < 0 ? 0 : dpad[b][s]; };
-  // ---- site tensors of every item in the environment precision
-  std::vector<const double *> site64((size_t)nitem * N);
-  for (int it = 0; it < nitem; ++it)
-    for (int p = 0; p < N; ++p)
-      site64[(size_t)it * N + p] = it < M ? pb.d_sites + pb.mps[it].site_off[p]
-                                          : kets->site_ptr[(size_t)(it - M) * N + p];
-  std::vector<const T *> siteT((size_t)nitem * N);
-  if (std::is_same<T, double>::value) {
-    for (size_t i = 0; i < site64.size(); ++i) siteT[i] = reinterpret_cast<const T *>(site64[i]);
-  } else {
-    std::vector<int64_t> cnt(site64.size());
-    int64_t tot = 0;
-    for (int it = 0; it < nitem; ++it)
-      for (int p = 0; p < N; ++p) {
-        cnt[(size_t)it * N + p] = (int64_t)iD[(size_t)it * nbond + p] * 4 * iD[(size_t)it * nbond + p + 1];
-        tot += cnt[(size_t)it * N + p];
-      }
-    float *buf = c.dev<float>((size_t)tot);
-    std::vector<float *> dst(site64.size());
-    int64_t o = 0;
-    for (size_t i = 0; i < site64.size(); ++i) {
-      dst[i] = buf + o;
-      o += cnt[i];
-      siteT[i] = reinterpret_cast<const T *>(dst[i]);
-    }
-    launch_cast(c.upload(site64), c.upload(dst), c.upload(cnt), (int)site64.size(), st);
-    c.check_launch();
-  }
-  // ---- block slots
+  std::vector<std::vector<int64_t>> &Loff = lay.Loff;
+  std::vector<int64_t> &Lsize = lay.Lsize;
+  Loff.assign(nbond, {});
+  Lsize.assign(nbond, 0);
   const auto &cls = mpo.classes;
-  std::vector<std::vector<int64_t>> Loff(nbond);
-  std::vector<int64_t> Lsize(nbond, 0);
   for (int b = 0; b <= N; ++b) {
     Loff[b].assign(cls[b].size() * nslot, -1);
     int64_t o = 0;
@@ -1165,24 +1192,11 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
     Lsize[b] = o;
   }
-  struct SiteTabs {
-    std::vector<EnvG1> g1;
-    std::vector<EnvG2> g2;
-    int tm1 = 256, tn1 = 16, tm2 = 16, tn2 = 256;
-    std::vector<std::vector<EnvGD>> dense;   // dense channel mixing, one level per launch
-    std::vector<int> tmd, tnd;
-    std::vector<MixTask> tasks;
-    std::vector<MixSrc> srcs;
-    std::vector<int> src_nnz;                // stored couplings of each source (work count)
-    int64_t Xsize = 0, Ysize = 0;
-    std::vector<EnvFinal> fin;
-  };
-  std::vector<SiteTabs> tabs(N);
-  const MpoDevice &mdev = mpo_dev_for(c.ctx, mpo);
-  const auto tq1 = Clock::now();
+  lay.tabs.assign(N, EnvSiteTabs{});
+  std::vector<EnvSiteTabs> &tabs = lay.tabs;
   // sites are independent: their tables are built on the host workers
-  host_pool(c.ctx).parallel_for(N, [&](int x) {
-    SiteTabs &tb = tabs[x];
+  workers.parallel_for(N, [&](int x) {
+    EnvSiteTabs &tb = tabs[x];
     // GEMM1 and X slots
     std::vector<int64_t> offX(cls[x].size() * nslot * 4, -1);
     int64_t xo = 0;
@@ -1261,8 +1275,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               MixSrc sr{};
               sr.offX = ox;
               sr.vbase = mpo.site_nnz_off[x] + g.val_off;
-              sr.rp = mdev.rp_off[x][gi];
-              sr.cp = mdev.col_off[x][gi];
+              sr.rp = mdev ? mdev->rp_off[x][gi] : 0;
+              sr.cp = mdev ? mdev->col_off[x][gi] : 0;
               sr.nw_in = cls[x][g.cin].nw;
               sr.group = (int)gi;
               sr.factor = P.f[e];
@@ -1342,19 +1356,97 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         }
       pick_tile(maxM2, maxN2, false, tb.tm2, tb.tn2);
     } else {
-      const int sN = slot_of(pb.na, pb.nb);
+      const int sN = slot_of(na, nb);
       const int co = mpo.final_class;
       for (int kp = 0; kp < 4; ++kp) {
         const int64_t oy = offY[((size_t)co * nslot + sN) * 4 + kp];
         if (oy < 0) continue;
         EnvFinal f{};
-        f.sa = slot_of(pb.na - qk_a(kp), pb.nb - qk_b(kp));
+        f.sa = slot_of(na - qk_a(kp), nb - qk_b(kp));
         f.kp = kp;
         f.offY = oy;
         tb.fin.push_back(f);
       }
     }
   });
+}
+
+// Environment sweeps of all pairs.  Items are the M bra MPS followed by the
+// rotated kets; pair q contracts bra item pairs[q].first with its ket item.
+// Block slots are sized by the largest dimensions over the items (one
+// descriptor list for all pairs); the kernels use each pair's own extents.
+template <typename T>
+void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
+               const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
+               int64_t nnz_total, EnvResult &res) {
+  hipStream_t st = c.ctx->stream;
+  const auto tq0 = Clock::now();
+  const int N = pb.N, M = pb.M, nslot = pb.nslot(), nbond = N + 1;
+  const int nket = kets ? kets->n : 0;
+  const int nitem = M + nket;
+  // ---- item sector tables
+  std::vector<int2> itab((size_t)nitem * nbond * nslot, make_int2(0, 0));
+  std::vector<int> iD((size_t)nitem * nbond, 0);
+  for (int it = 0; it < nitem; ++it)
+    for (int b = 0; b <= N; ++b) {
+      int2 *row = itab.data() + ((size_t)it * nbond + b) * nslot;
+      if (it < M) {
+        const auto &m = pb.mps[it];
+        int o = 0;
+        for (int s = 0; s < nslot; ++s) {
+          row[s] = make_int2(o, m.secdim[b][s]);
+          o += m.secdim[b][s];
+        }
+        iD[(size_t)it * nbond + b] = m.dims[b];
+      } else {
+        const int t = it - M;
+        for (int s = 0; s < nslot; ++s) row[s] = kets->hbtab[((size_t)b * kets->n + t) * nslot + s];
+        iD[(size_t)it * nbond + b] = kets->htot[(size_t)b * kets->n + t];
+      }
+    }
+  auto idim = [&](int it, int b, int s) { return s < 0 ? 0 : itab[((size_t)it * nbond + b) * nslot + s].y; };
+  // largest sector dimensions over the items (block slot sizes)
+  std::vector<std::vector<int>> dpad(nbond, std::vector<int>(nslot, 0));
+  for (int b = 0; b <= N; ++b) {
+    for (int s = 0; s < nslot; ++s)
+      for (int it = 0; it < nitem; ++it) dpad[b][s] = std::max(dpad[b][s], idim(it, b, s));
+    for (int it = 0; it < nitem; ++it) res.max_pad = std::max(res.max_pad, iD[(size_t)it * nbond + b]);
+  }
+  // ---- site tensors of every item in the environment precision
+  std::vector<const double *> site64((size_t)nitem * N);
+  for (int it = 0; it < nitem; ++it)
+    for (int p = 0; p < N; ++p)
+      site64[(size_t)it * N + p] = it < M ? pb.d_sites + pb.mps[it].site_off[p]
+                                          : kets->site_ptr[(size_t)(it - M) * N + p];
+  std::vector<const T *> siteT((size_t)nitem * N);
+  if (std::is_same<T, double>::value) {
+    for (size_t i = 0; i < site64.size(); ++i) siteT[i] = reinterpret_cast<const T *>(site64[i]);
+  } else {
+    std::vector<int64_t> cnt(site64.size());
+    int64_t tot = 0;
+    for (int it = 0; it < nitem; ++it)
+      for (int p = 0; p < N; ++p) {
+        cnt[(size_t)it * N + p] = (int64_t)iD[(size_t)it * nbond + p] * 4 * iD[(size_t)it * nbond + p + 1];
+        tot += cnt[(size_t)it * N + p];
+      }
+    float *buf = c.dev<float>((size_t)tot);
+    std::vector<float *> dst(site64.size());
+    int64_t o = 0;
+    for (size_t i = 0; i < site64.size(); ++i) {
+      dst[i] = buf + o;
+      o += cnt[i];
+      siteT[i] = reinterpret_cast<const T *>(dst[i]);
+    }
+    launch_cast(c.upload(site64), c.upload(dst), c.upload(cnt), (int)site64.size(), st);
+    c.check_launch();
+  }
+  // ---- block slots and per-site tables
+  const MpoDevice &mdev = mpo_dev_for(c, mpo);
+  const auto tq1 = Clock::now();
+  EnvLayout lay;
+  plan_env_layout(mpo, &mdev, N, pb.na, pb.nb, dpad, host_pool(c.ctx), lay);
+  const std::vector<int64_t> &Lsize = lay.Lsize;
+  std::vector<EnvSiteTabs> &tabs = lay.tabs;
   const auto tq2 = Clock::now();
   // ---- algorithmic work with every pair's own block shapes (on a host
   // thread, overlapping the sweeps)
@@ -1365,7 +1457,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       const int q = (int)(&pr - pairs.data());
       const int bi = pr.first, ki = ket_of_pair[q] < 0 ? pr.first : M + ket_of_pair[q];
       for (int x = 0; x < N; ++x) {
-        const SiteTabs &tb = tabs[x];
+        const EnvSiteTabs &tb = tabs[x];
         for (const EnvG1 &d : tb.g1) {
           const double m = (double)idim(bi, x, d.sbra) * d.nw, k = idim(ki, x, d.s), n = idim(ki, x + 1, d.sk);
           fl[kEnvG1] += 2.0 * m * n * k;
@@ -1430,33 +1522,85 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     MixSrc *srcs;
     EnvFinal *fin;
   };
-  std::vector<DevSite> ds(N);
-  int64_t Lmax = 1, Xmax = 1, Ymax = 1;
-  for (int b = 0; b <= N; ++b) Lmax = std::max(Lmax, Lsize[b]);
-  for (int x = 0; x < N; ++x) {
-    ds[x].g1 = c.upload(tabs[x].g1);
-    ds[x].g2 = c.upload(tabs[x].g2);
-    ds[x].tasks = c.upload(tabs[x].tasks);
-    ds[x].srcs = c.upload(tabs[x].srcs);
-    ds[x].fin = c.upload(tabs[x].fin);
-    for (auto &lv : tabs[x].dense) ds[x].dense.push_back(c.upload(lv));
-    Xmax = std::max(Xmax, tabs[x].Xsize);
-    Ymax = std::max(Ymax, tabs[x].Ysize);
+  // sizes of a layout: largest L, X and Y, descriptors (work-list entries per pair)
+  struct LaySizes {
+    int64_t Lmax = 1, Xmax = 1, Ymax = 1, ndesc = 0;
+  };
+  auto sizes_of = [&](const EnvLayout &ly) {
+    LaySizes z;
+    for (int b = 0; b <= N; ++b) z.Lmax = std::max(z.Lmax, ly.Lsize[b]);
+    for (int x = 0; x < N; ++x) {
+      z.Xmax = std::max(z.Xmax, ly.tabs[x].Xsize);
+      z.Ymax = std::max(z.Ymax, ly.tabs[x].Ysize);
+      z.ndesc += (int64_t)ly.tabs[x].g1.size() + ly.tabs[x].tasks.size() + ly.tabs[x].g2.size();
+      for (auto &lv : ly.tabs[x].dense) z.ndesc += (int64_t)lv.size();
+    }
+    return z;
+  };
+  auto upload_tabs = [&](const EnvLayout &ly) {
+    std::vector<DevSite> d(N);
+    for (int x = 0; x < N; ++x) {
+      d[x].g1 = c.upload(ly.tabs[x].g1);
+      d[x].g2 = c.upload(ly.tabs[x].g2);
+      d[x].tasks = c.upload(ly.tabs[x].tasks);
+      d[x].srcs = c.upload(ly.tabs[x].srcs);
+      d[x].fin = c.upload(ly.tabs[x].fin);
+      for (auto &lv : ly.tabs[x].dense) d[x].dense.push_back(c.upload(lv));
+    }
+    return d;
+  };
+  const double fixed = 256.0 * (4 * N + 24);
+  // per pair: the four environment buffers, its entries of the work lists
+  // (at most one per descriptor) and its pointer-table entries
+  auto per_pair_of = [&](const LaySizes &z) {
+    return (double)(2 * z.Lmax + z.Xmax + z.Ymax) * sizeof(T) + (double)z.ndesc * sizeof(EnvWork) +
+           (double)(2 * N + 12) * sizeof(void *);
+  };
+  const LaySizes gz = sizes_of(lay);
+  const int npair = (int)pairs.size();
+  const double per_pair = per_pair_of(gz);
+  double budget = 96.0 * (1ull << 30);
+  // a caller's workspace too small for one pair in the common layout: every
+  // pair runs alone, in a layout of its own two items' dimensions
+  bool own_layouts = false;
+  if (c.ctx->pool.arena()) {
+    budget = std::min(budget, (double)c.ctx->pool.available() - fixed);
+    own_layouts = budget < per_pair;
   }
+  std::vector<DevSite> ds;
+  if (!own_layouts) ds = upload_tabs(lay);
   c.sync();
   const auto tq3 = Clock::now();
   double t_work = 0.0, t_launch = 0.0, t_wait = 0.0;
   // ---- pair batches under a memory budget
-  const int npair = (int)pairs.size();
-  const double per_pair = (double)(2 * Lmax + Xmax + Ymax) * sizeof(T);
-  const double budget = 96.0 * (1ull << 30);
-  int batch = std::max(1, std::min(npair, (int)(budget / std::max(1.0, per_pair))));
+  const int batch = own_layouts ? 1 : std::max(1, std::min(npair, (int)(budget / std::max(1.0, per_pair))));
   res.H.assign(npair, 0.0);
   res.S.assign(npair, 0.0);
   hipEvent_t e0 = c.ctx->ev[0], e1 = c.ctx->ev[1];
+  EnvLayout own;
   for (int p0 = 0; p0 < npair; p0 += batch) {
     const int nb_ = std::min(batch, npair - p0);
     const size_t mk = c.ctx->pool.mark();
+    const EnvLayout *cur = &lay;
+    LaySizes z = gz;
+    std::vector<DevSite> ds_own;
+    if (own_layouts) {
+      const int bi = pairs[p0].first, ki = ket_of_pair[p0] < 0 ? bi : M + ket_of_pair[p0];
+      std::vector<std::vector<int>> dq(nbond, std::vector<int>(nslot, 0));
+      for (int b = 0; b <= N; ++b)
+        for (int s2 = 0; s2 < nslot; ++s2) dq[b][s2] = std::max(idim(bi, b, s2), idim(ki, b, s2));
+      plan_env_layout(mpo, &mdev, N, pb.na, pb.nb, dq, host_pool(c.ctx), own);
+      cur = &own;
+      z = sizes_of(own);
+      require(per_pair_of(z) <= (double)c.ctx->pool.available() - fixed - 64.0 * (z.ndesc + 64), TNQE_EWORKSPACE,
+              "workspace too small for the environment sweep of one pair (" +
+                  std::to_string((int64_t)per_pair_of(z)) + " bytes needed, " +
+                  std::to_string(c.ctx->pool.available()) + " left)");
+      ds_own = upload_tabs(own);
+    }
+    const std::vector<EnvSiteTabs> &ctabs = cur->tabs;
+    const std::vector<DevSite> &cds = own_layouts ? ds_own : ds;
+    const int64_t Lmax = z.Lmax, Xmax = z.Xmax, Ymax = z.Ymax;
     T *bufL0 = c.dev<T>((size_t)Lmax * nb_), *bufL1 = c.dev<T>((size_t)Lmax * nb_);
     T *bufX = c.dev<T>((size_t)Xmax * nb_), *bufY = c.dev<T>((size_t)Ymax * nb_);
     std::vector<T *> L0(nb_), L1(nb_), X(nb_), Y(nb_);
@@ -1498,7 +1642,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     };
     std::vector<SiteWork> sw(N);
     host_pool(c.ctx).parallel_for(N, [&](int x) {
-      const SiteTabs &tb = tabs[x];
+      const EnvSiteTabs &tb = ctabs[x];
       SiteWork &w = sw[x];
       auto add = [](std::vector<EnvWork> &list, int &nwg, int desc, int q, int64_t cnt) {
         if (cnt <= 0) return;
@@ -1571,19 +1715,19 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       tick_kind.push_back(kind);
     };
     TNQE_HIP(hipEventRecord(e0, st));
-    launch_env_init<T>(dL0, nb_, Lsize[0], st);
+    launch_env_init<T>(dL0, nb_, cur->Lsize[0], st);
     T **Lc = dL0, **Ln = dL1;
     for (int x = 0; x < N; ++x) {
-      const SiteTabs &tb = tabs[x];
+      const EnvSiteTabs &tb = ctabs[x];
       const SiteWork &w = sw[x];
       tick(kEnvG1);
-      launch_env_g1<T>(ds[x].g1, dw[x].g1, (int)w.g1.size(), w.n1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, st);
+      launch_env_g1<T>(cds[x].g1, dw[x].g1, (int)w.g1.size(), w.n1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, st);
       MixArgs ma{};
-      ma.tasks = ds[x].tasks;
+      ma.tasks = cds[x].tasks;
       ma.work = dw[x].mix;
       ma.nwork = (int)w.mix.size();
       ma.nchunk = w.nmix;
-      ma.srcs = ds[x].srcs;
+      ma.srcs = cds[x].srcs;
       ma.rowptr = mdev.rowptr;
       ma.col = mdev.col;
       ma.vals = dvals;
@@ -1593,16 +1737,16 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       launch_mix<T>(ma, geom, dX, dY, st);
       for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
         tick(kEnvDense);
-        launch_env_gd<T>(ds[x].dense[lv], dw[x].dense[lv], (int)w.dense[lv].size(), w.nd[lv], tb.tmd[lv],
+        launch_env_gd<T>(cds[x].dense[lv], dw[x].dense[lv], (int)w.dense[lv].size(), w.nd[lv], tb.tmd[lv],
                          tb.tnd[lv], geom, dvptr, dX, dY, st);
       }
       if (x < N - 1) {
         tick(kEnvG2);
-        launch_env_g2<T>(ds[x].g2, dw[x].g2, (int)w.g2.size(), w.n2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, st);
+        launch_env_g2<T>(cds[x].g2, dw[x].g2, (int)w.g2.size(), w.n2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, st);
         std::swap(Lc, Ln);
       } else {
         tick(kEnvFinal);
-        launch_env_final<T>(geom, x, dbra64, dY, ds[x].fin, (int)tb.fin.size(), 2, dout, nb_, st);
+        launch_env_final<T>(geom, x, dbra64, dY, cds[x].fin, (int)tb.fin.size(), 2, dout, nb_, st);
       }
       c.check_launch();
     }
@@ -1720,6 +1864,25 @@ MpoStructure &mpo_for(tnqe_ctx *ctx, int N) {
   return ref;
 }
 
+// Capacity of every bond of a rotated ket: the largest input dimension, or
+// min(chi, exact dimension of the (n_alpha, n_beta) sector bond) if larger.
+std::vector<int> bond_caps(const tnqe_problem &pb, int chi_cap) {
+  const int N = pb.N;
+  std::vector<int> cap(N + 1, 1);
+  for (int b = 0; b <= N; ++b) {
+    double ex = 0.0;
+    const int a0 = std::max(0, pb.na - (N - b)), a1 = std::min(b, pb.na);
+    const int b0 = std::max(0, pb.nb - (N - b)), b1 = std::min(b, pb.nb);
+    for (int a = a0; a <= a1; ++a)
+      for (int bb = b0; bb <= b1; ++bb)
+        ex += std::min(binom(b, a) * binom(b, bb), binom(N - b, pb.na - a) * binom(N - b, pb.nb - bb));
+    int mx = 0;
+    for (int i = 0; i < pb.M; ++i) mx = std::max(mx, pb.mps[i].dims[b]);
+    cap[b] = std::max(mx, (int)std::min<double>(ex, (double)chi_cap));
+  }
+  return cap;
+}
+
 void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut &out) {
   Call c{ctx};
   const auto t0 = Clock::now();
@@ -1792,18 +1955,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   TruncStats ts;
   ts.discarded.assign(P, 0.0);
   if (P > 0) {
-    std::vector<int> cap(N + 1, 1);
-    for (int b = 0; b <= N; ++b) {
-      double ex = 0.0;
-      const int a0 = std::max(0, pb.na - (N - b)), a1 = std::min(b, pb.na);
-      const int b0 = std::max(0, pb.nb - (N - b)), b1 = std::min(b, pb.nb);
-      for (int a = a0; a <= a1; ++a)
-        for (int bb = b0; bb <= b1; ++bb)
-          ex += std::min(binom(b, a) * binom(b, bb), binom(N - b, pb.na - a) * binom(N - b, pb.nb - bb));
-      int mx = 0;
-      for (int i = 0; i < M; ++i) mx = std::max(mx, pb.mps[i].dims[b]);
-      cap[b] = std::max(mx, (int)std::min<double>(ex, (double)chi_cap));
-    }
+    const std::vector<int> cap = bond_caps(pb, chi_cap);
     // left-canonical copies of every MPS used as a ket
     KetSet canon;
     canon.init(&c, M, N, pb.na, pb.nb, cap);
@@ -1882,12 +2034,17 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       if (identity) continue;
       const size_t mk = ctx->pool.mark();
       const auto tm0 = Clock::now();
+      // each move's scratch goes back before the next move
       while (centre > a) {
+        const size_t mm = ctx->pool.mark();
         move_left(kets, centre, max_sweeps, &ts.svd);
+        ctx->pool.rewind(mm);
         --centre;
       }
       while (centre < a) {
+        const size_t mm = ctx->pool.mark();
         move_right(kets, centre, max_sweeps, &ts.svd);
+        ctx->pool.rewind(mm);
         ++centre;
       }
       const auto tm1 = Clock::now();
@@ -1896,7 +2053,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
         gates[2 * t] = std::cos(gth[t][g]);
         gates[2 * t + 1] = std::sin(gth[t][g]);
       }
-      gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, ts);
+      gate_step(kets, a, gates, chi_cap, op.tau_w, max_sweeps, op.renormalize != 0, ts);
       centre = a + 1;
       ctx->pool.rewind(mk);
       if (debug_timing()) {
@@ -1944,7 +2101,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       }
     }
     EnvResult e64, e32;
+    const size_t me = ctx->pool.mark();
     if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64);
+    c.sync();
+    ctx->pool.rewind(me);
     if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32);
     er.H.assign(pairs.size(), 0.0);
     er.S.assign(pairs.size(), 0.0);
@@ -2029,6 +2189,145 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   require(std::isfinite(out.E), TNQE_ENONFINITE, "non-finite eigenvalue");
 }
 
+
+// Upper bound of the device memory one solve takes from its pool (bytes):
+// the problem's site tensors, the MPO coefficients and structure, the two
+// ket sets, and the larger of the gate phase's and the environment phase's
+// peaks, each for the largest bond dimensions truncation can produce (the
+// bond capacities, and per quantum-number sector the exact sector dimension
+// capped by them).  Blocks of a two-site or one-site matrix partition its
+// rows and columns, so a step's per-block storage is bounded by that of the
+// whole matrix; the environment layout is planned for the bounding sector
+// dimensions, and its sizes grow with every dimension.
+size_t workspace_bound(tnqe_ctx *ctx, const tnqe_problem &pb, const tnqe_options &op) {
+  auto a256 = [](double bytes) { return (size_t)((std::max(1.0, bytes) + 255.0) / 256.0) * 256; };
+  const int N = pb.N, M = pb.M, nslot = pb.nslot();
+  const int P = M * (M - 1) / 2, npair = M * (M + 1) / 2;
+  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
+  const MpoStructure &mpo = mpo_for(ctx, N);
+  const int64_t nnz = mpo.site_nnz_off[N];
+  size_t persistent = 0;
+  int64_t sites = 0;
+  for (int i = 0; i < M; ++i)
+    for (int p = 0; p < N; ++p) sites += (int64_t)pb.mps[i].dims[p] * 4 * pb.mps[i].dims[p + 1];
+  persistent += a256(8.0 * sites) + a256(8.0 * nnz * M);
+  int64_t nrp = 1, ncl = 1;
+  for (int x = 0; x < N; ++x)
+    for (const MpoGroup &g : mpo.groups[x]) {
+      nrp += (int64_t)g.rowptr.size();
+      ncl += (int64_t)g.col.size();
+    }
+  persistent += a256(4.0 * nrp) + a256(4.0 * ncl);
+  const std::vector<int> cap = bond_caps(pb, chi_cap);
+  int64_t stride = 0;
+  for (int p = 0; p < N; ++p) stride = std::max(stride, ((int64_t)cap[p] * 4 * cap[p + 1] + 31) & ~int64_t(31));
+  auto ketset = [&](int n) {
+    return a256(8.0 * (N + 1) * n * nslot) + a256(4.0 * (N + 1) * n) + a256(8.0 * stride * (N + 1) * n) +
+           a256(8.0 * n * N);
+  };
+  const double blk = sizeof(Blk);
+  // run_svd: one index list per (kernel, threads) group, the sweep counters
+  auto svd_tables = [&](double nblk) { return 42 * 256.0 + 4.0 * nblk + a256(4.0 * nblk); };
+  // per ket: T, U, B, S (and the global Jacobi work area) of blocks that
+  // partition an R_tot x C_tot matrix, 32-double granules per piece
+  auto block_scratch = [&](double Rt, double Ct) { return 8.0 * (4.0 * Rt * Ct + 2.0 * std::min(Rt, Ct) + 160.0 * nslot); };
+  auto move_bound = [&](int n, double Rt, double Ct, double old_site) {
+    const double nblk = (double)n * nslot;
+    return a256(n * block_scratch(Rt, Ct)) + a256(8.0 * old_site * n) + 4 * a256(8.0 * n) + a256(blk * nblk) +
+           3 * a256(4.0 * (nblk + 1)) + svd_tables(nblk);
+  };
+  size_t gates_peak = 0;
+  if (P > 0) {
+    persistent += ketset(M) + ketset(P);
+    for (int p = 0; p + 1 < N; ++p)   // canonicalisation (QR moves right)
+      gates_peak = std::max(gates_peak, (size_t)move_bound(M, 4.0 * cap[p], cap[p + 1],
+                                                           (double)cap[p + 1] * 4 * cap[p + 2]) +
+                                            3 * a256(8.0 * M));
+    gates_peak = std::max(gates_peak, 3 * a256(8.0 * P) + a256(4.0 * P));
+    for (int a = 0; a + 1 < N; ++a) {
+      // centre moves into site a + 1 (LQ from the right) or a (QR from the left)
+      const double lq = move_bound(P, cap[a + 1], 4.0 * cap[a + 2], 0.0);
+      const double qr = move_bound(P, 4.0 * cap[a], cap[a + 1], (double)cap[a + 1] * 4 * cap[a + 2]);
+      const double Rt = 4.0 * cap[a], Ct = 4.0 * cap[a + 2], nblk = (double)P * nslot;
+      const double step = a256(P * (block_scratch(Rt, Ct) + 8.0 * (Rt * Ct + 32.0 * nslot))) + a256(8.0 * 256 * P) +
+                          a256(4.0 * nblk) + a256(8.0 * 3 * P) + a256(16.0 * P) + 2 * a256(blk * nblk) +
+                          a256(4.0 * P * nslot) + 4 * a256(4.0 * (nblk + 1)) + a256(4.0 * (P + 1)) + svd_tables(nblk);
+      gates_peak = std::max(gates_peak, (size_t)std::max(step, std::max(lq, qr)));
+    }
+  }
+  // environment phase, for the bounding sector dimensions of every bond
+  std::vector<std::vector<int>> dpad(N + 1, std::vector<int>(nslot, 0));
+  for (int b = 0; b <= N; ++b)
+    for (int a = 0; a <= pb.na; ++a)
+      for (int bb = 0; bb <= pb.nb; ++bb) {
+        const int s = a * (pb.nb + 1) + bb;
+        double ex = std::min(binom(b, a) * binom(b, bb), binom(N - b, pb.na - a) * binom(N - b, pb.nb - bb));
+        int mx = 0;
+        for (int i = 0; i < M; ++i) mx = std::max(mx, pb.mps[i].secdim[b][s]);
+        dpad[b][s] = (int)std::min<double>(cap[b], std::max<double>(ex, mx));
+      }
+  EnvLayout lay;
+  plan_env_layout(mpo, nullptr, N, pb.na, pb.nb, dpad, host_pool(ctx), lay);
+  const double eb = op.precision == TNQE_FP64 ? 8.0 : 4.0;
+  const int nitem = M + P;
+  double env = a256(8.0 * nitem * (N + 1) * nslot) + a256(4.0 * nitem * (N + 1));
+  if (op.precision != TNQE_FP64) {
+    double tot = 0.0;
+    for (int p = 0; p < N; ++p) tot += (double)cap[p] * 4 * cap[p + 1];
+    env += a256(4.0 * tot * nitem) + 3 * a256(8.0 * nitem * N) + a256(4.0 * nnz * M);
+  }
+  // when the common layout does not fit, every pair runs alone in a layout of
+  // its own two items: per sector at most min(cap, bounding dimension), and
+  // at most 2 cap over the sectors of a bond
+  const auto &cls = mpo.classes;
+  auto dB = [&](int bnd, int a, int bb) {
+    return (a < 0 || bb < 0 || a > pb.na || bb > pb.nb) ? 0.0 : (double)dpad[bnd][a * (pb.nb + 1) + bb];
+  };
+  auto pairsum = [&](int b1, int da1, int db1, int b2, int da2, int db2) {   // sum_s d1(s + d1) d2(s + d2)
+    double acc = 0.0;
+    for (int a = -2; a <= pb.na + 2; ++a)
+      for (int bb = -2; bb <= pb.nb + 2; ++bb) acc += dB(b1, a + da1, bb + db1) * dB(b2, a + da2, bb + db2);
+    return acc;
+  };
+  double Lmax = 1, Xmax = 1, Ymax = 1;
+  for (int bnd = 0; bnd <= N; ++bnd) {
+    double l = 0.0;
+    for (const MpoClass &c : cls[bnd])
+      l += c.nw * std::min(4.0 * cap[bnd] * cap[bnd], pairsum(bnd, c.da, c.db, bnd, 0, 0));
+    Lmax = std::max(Lmax, l);
+  }
+  for (int x = 0; x < N; ++x) {
+    const double box = 4.0 * cap[x] * cap[x + 1];
+    double xs = 0.0, ys = 0.0;
+    for (const MpoClass &c : cls[x])
+      for (int k = 0; k < 4; ++k) xs += c.nw * std::min(box, pairsum(x, c.da, c.db, x + 1, qk_a(k), qk_b(k)));
+    for (const MpoClass &c : cls[x + 1])
+      for (int k = 0; k < 4; ++k) ys += c.nw * std::min(box, pairsum(x, c.da - qk_a(k), c.db - qk_b(k), x + 1, 0, 0));
+    Xmax = std::max(Xmax, xs);
+    Ymax = std::max(Ymax, ys);
+  }
+  int64_t ndesc = 0;
+  for (int x = 0; x < N; ++x) {
+    const EnvSiteTabs &t = lay.tabs[x];
+    env += a256((double)sizeof(EnvG1) * t.g1.size()) + a256((double)sizeof(EnvG2) * t.g2.size()) +
+           a256((double)sizeof(MixTask) * t.tasks.size()) + a256((double)sizeof(MixSrc) * t.srcs.size()) +
+           a256((double)sizeof(EnvFinal) * t.fin.size());
+    ndesc += (int64_t)t.g1.size() + t.tasks.size() + t.g2.size();
+    for (auto &lv : t.dense) {
+      env += a256((double)sizeof(EnvGD) * lv.size());
+      ndesc += (int64_t)lv.size();
+    }
+  }
+  // one pair, with the allowance the batching keeps free for its tables
+  env += 2 * a256(eb * Lmax) + a256(eb * Xmax) + a256(eb * Ymax) + (double)ndesc * sizeof(EnvWork) +
+         (2.0 * N + 12) * sizeof(void *) + 256.0 * (4 * N + 24) + 64.0 * (ndesc + 64) + 256.0 * (6 * N + 24);
+  // mixed precision runs the FP64 pairs first, then the FP32 ones
+  (void)npair;
+  const size_t gep = 4 * a256(8.0 * M * M) + a256(8.0 * (8 + kMaxM)) + 2 * a256(8.0);
+  const size_t peak = std::max<size_t>(gates_peak, (size_t)env) + gep;
+  const size_t total = persistent + peak;
+  return total + total / 16 + (16u << 20);
+}
 }  // namespace
 }  // namespace tnqe
 
@@ -2042,6 +2341,16 @@ tnqe_status fail(tnqe_ctx *ctx, tnqe_status st, const std::string &msg) {
   return st;
 }
 
+// Wait for everything the context has queued (main and side streams, errors
+// ignored) so that memory handed out during a failed call can be reused.
+void quiesce(tnqe_ctx *ctx) {
+  if (!ctx->aux[0]) return;   // a host-only context has queued nothing
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i < tnqe_ctx::kAux; ++i)
+    if (ctx->aux[i]) (void)hipStreamSynchronize(ctx->aux[i]);
+  (void)hipGetLastError();
+}
+
 template <class F>
 tnqe_status guarded(tnqe_ctx *ctx, F &&f) {
   try {
@@ -2050,15 +2359,217 @@ tnqe_status guarded(tnqe_ctx *ctx, F &&f) {
     return TNQE_OK;
   } catch (const Error &e) {
     if (ctx) {
+      quiesce(ctx);
       ctx->pool.release_all();
       ctx->staging.reset();
     }
     return fail(ctx, e.st, e.what());
   } catch (const std::bad_alloc &) {
+    if (ctx) {
+      quiesce(ctx);
+      ctx->pool.release_all();
+      ctx->staging.reset();
+    }
     return fail(ctx, TNQE_ENOMEM, "host allocation failed");
   } catch (const std::exception &e) {
+    if (ctx) {
+      quiesce(ctx);
+      ctx->pool.release_all();
+      ctx->staging.reset();
+    }
     return fail(ctx, TNQE_EINVAL, e.what());
   }
+}
+
+}  // namespace
+
+namespace {
+
+// Host-side validation and copies of a problem (no device work): shapes,
+// |U^T U - I|_max <= 1e-10, zero entries outside particle-number blocks,
+// finite values, every MPS in the (n_alpha, n_beta) sector, M <= kMaxM.
+void load_problem(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps, tnqe_problem *pb) {
+  require(M >= 1 && M <= kMaxM, TNQE_EINVAL, "M must be in [1, " + std::to_string(kMaxM) + "]");
+  const int N = ham->N;
+  require(N >= 1 && N <= 64, TNQE_ESHAPE, "N must be in [1, 64]");
+  require(ham->n_alpha >= 0 && ham->n_alpha <= N && ham->n_beta >= 0 && ham->n_beta <= N, TNQE_ESHAPE,
+          "electron counts out of range");
+  require(ham->h != nullptr, TNQE_EINVAL, "h is NULL");
+  require((ham->n_chol > 0 && ham->L) || (ham->n_chol == 0 && ham->g), TNQE_EINVAL,
+          "two-electron integrals missing");
+  pb->N = N;
+  pb->na = ham->n_alpha;
+  pb->nb = ham->n_beta;
+  pb->M = M;
+  pb->e_core = ham->e_core;
+  require(std::isfinite(pb->e_core), TNQE_ENONFINITE, "e_core not finite");
+  const size_t N2 = (size_t)N * N;
+  pb->h.assign(ham->h, ham->h + N2);
+  for (size_t x = 0; x < N2; ++x) {
+    require(std::isfinite(pb->h[x]), TNQE_ENONFINITE, "h has a non-finite entry");
+    require(std::fabs(pb->h[x] - pb->h[(x % N) * N + x / N]) <= 1e-12 * (1 + std::fabs(pb->h[x])),
+            TNQE_EINVAL, "h is not symmetric");
+  }
+  if (ham->n_chol > 0) {
+    pb->K = ham->n_chol;
+    pb->L.assign(ham->L, ham->L + (size_t)pb->K * N2);
+    for (double v : pb->L) require(std::isfinite(v), TNQE_ENONFINITE, "L has a non-finite entry");
+    pb->g.clear();
+  } else {
+    pb->K = 0;
+    pb->g.assign(ham->g, ham->g + N2 * N2);
+    for (double v : pb->g) require(std::isfinite(v), TNQE_ENONFINITE, "g has a non-finite entry");
+  }
+  const int nslot = pb->nslot();
+  int64_t total = 0;
+  pb->mps.resize(M);
+  // bond labels per MPS, kept for the scan of the site tensors, which runs
+  // on the host workers (the labels and U are checked serially first)
+  std::vector<std::vector<std::vector<int>>> lab_a(M), lab_b(M);
+  for (int i = 0; i < M; ++i) {
+    const tnqe_mps &m = mps[i];
+    require(m.bond_dim && m.bond_qn && m.sites && m.U, TNQE_EINVAL, "MPS field is NULL");
+    auto &pm = pb->mps[i];
+    pm.dims.assign(m.bond_dim, m.bond_dim + N + 1);
+    require(pm.dims[0] == 1 && pm.dims[N] == 1, TNQE_ESHAPE, "boundary bonds must have dimension 1");
+    pm.secdim.assign(N + 1, std::vector<int>(nslot, 0));
+    std::vector<std::vector<int>> qa(N + 1), qb(N + 1);
+    int64_t qo = 0;
+    for (int b = 0; b <= N; ++b) {
+      require(pm.dims[b] >= 1 && pm.dims[b] <= 1 << 20, TNQE_ESHAPE, "bond dimension out of range");
+      int prev = -1;
+      for (int x = 0; x < pm.dims[b]; ++x) {
+        const int a = m.bond_qn[2 * (qo + x)], bb = m.bond_qn[2 * (qo + x) + 1];
+        require(a >= 0 && a <= pb->na && bb >= 0 && bb <= pb->nb, TNQE_EQN, "bond label out of range");
+        const int s = a * (pb->nb + 1) + bb;
+        require(s >= prev, TNQE_EQN, "bond indices not sorted by sector");
+        prev = s;
+        pm.secdim[b][s]++;
+        qa[b].push_back(a);
+        qb[b].push_back(bb);
+      }
+      qo += pm.dims[b];
+    }
+    require(qa[0][0] == 0 && qb[0][0] == 0 && qa[N][0] == pb->na && qb[N][0] == pb->nb, TNQE_EQN,
+            "MPS is not in the (n_alpha, n_beta) sector");
+    pm.U.assign(m.U, m.U + N2);
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) {
+        double acc = 0.0;
+        for (int p = 0; p < N; ++p) acc += pm.U[p * N + a] * pm.U[p * N + b];
+        require(std::isfinite(acc), TNQE_ENONFINITE, "U has a non-finite entry");
+        require(std::fabs(acc - (a == b ? 1.0 : 0.0)) <= 1e-10, TNQE_ENOTORTH, "U is not orthogonal");
+      }
+    pm.site_off.resize(N);
+    for (int p = 0; p < N; ++p) {
+      pm.site_off[p] = total;
+      total += (int64_t)pm.dims[p] * 4 * pm.dims[p + 1];
+    }
+    lab_a[i] = std::move(qa);
+    lab_b[i] = std::move(qb);
+  }
+  // site tensors: finite, and nonzero only inside their particle-number
+  // blocks (one MPS per worker)
+  host_pool(ctx).parallel_for(M, [&](int i) {
+    const auto &pm = pb->mps[i];
+    const auto &qa = lab_a[i], &qb = lab_b[i];
+    const double *sp = mps[i].sites;
+    for (int p = 0; p < N; ++p) {
+      const int dl = pm.dims[p], dr = pm.dims[p + 1];
+      for (int l = 0; l < dl; ++l)
+        for (int k = 0; k < 4; ++k)
+          for (int r = 0; r < dr; ++r) {
+            const double v = sp[((int64_t)l * 4 + k) * dr + r];
+            require(std::isfinite(v), TNQE_ENONFINITE, "site tensor has a non-finite entry");
+            if (v != 0.0)
+              require(qa[p + 1][r] == qa[p][l] + (k & 1) && qb[p + 1][r] == qb[p][l] + (k >> 1), TNQE_EQN,
+                      "site tensor entry outside its particle-number block");
+          }
+      sp += (int64_t)dl * 4 * dr;
+    }
+  });
+}
+
+// Site tensors of every MPS to device memory: a buffer the problem owns, or
+// (calls working in a caller's workspace) the context's arena.
+void place_sites(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_mps *mps) {
+  int64_t total = 0;
+  for (const auto &m : pb->mps)
+    for (int p = 0; p < pb->N; ++p) total += (int64_t)m.dims[p] * 4 * m.dims[p + 1];
+  pb->device = ctx->device;
+  if (ctx->pool.arena()) {
+    pb->d_sites = static_cast<double *>(ctx->pool.get(std::max<int64_t>(1, total) * sizeof(double)));
+    pb->owns_sites = false;
+  } else {
+    TNQE_HIP(hipMalloc(&pb->d_sites, std::max<int64_t>(1, total) * sizeof(double)));
+    pb->owns_sites = true;
+  }
+  int64_t o = 0;
+  for (int i = 0; i < pb->M; ++i) {
+    int64_t n = 0;
+    for (int p = 0; p < pb->N; ++p) n += (int64_t)pb->mps[i].dims[p] * 4 * pb->mps[i].dims[p + 1];
+    TNQE_HIP(hipMemcpy(pb->d_sites + o, mps[i].sites, n * sizeof(double), hipMemcpyHostToDevice));
+    o += n;
+  }
+}
+
+void free_sites(tnqe_problem *pb) {
+  if (pb->d_sites && pb->owns_sites) {
+    (void)hipSetDevice(pb->device);
+    (void)hipFree(pb->d_sites);
+  }
+  pb->d_sites = nullptr;
+}
+
+tnqe_status check_options(tnqe_ctx *ctx, const tnqe_options *o) {
+  if (o->precision != TNQE_FP64 && o->precision != TNQE_ENV_FP32 && o->precision != TNQE_ENV_MIXED)
+    return fail(ctx, TNQE_EINVAL, "unknown precision mode");
+  if ((o->chi_cap_override > 0 ? o->chi_cap_override : o->chi) < 1) return fail(ctx, TNQE_EINVAL, "chi must be >= 1");
+  return TNQE_OK;
+}
+
+// The caller's workspace as the pool's arena for the length of one call.
+struct ArenaScope {
+  tnqe_ctx *ctx;
+  bool on;
+  ArenaScope(tnqe_ctx *c, void *ws, size_t bytes, bool no_alloc) : ctx(c), on(ws != nullptr) {
+    if (on) ctx->pool.set_arena(ws, bytes);
+    ctx->no_alloc = no_alloc;
+    ctx->staging.allow_pinned_growth(!no_alloc);
+  }
+  ~ArenaScope() {
+    if (on) ctx->pool.clear_arena();
+    ctx->no_alloc = false;
+    ctx->staging.allow_pinned_growth(true);
+    ctx->mpo_dev_call.reset();
+  }
+};
+
+// One subspace from host inputs: validation, sites to device memory, solve.
+// With a workspace every device buffer of the call lies in it.
+tnqe_status subspace_call(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                          const tnqe_options *opts, void *ws, size_t ws_bytes, bool no_alloc, SolveOut &so) {
+  tnqe_problem pb;
+  tnqe_status st = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    load_problem(ctx, ham, M, mps, &pb);
+    ArenaScope scope(ctx, ws, ws_bytes, no_alloc);
+    try {
+      place_sites(ctx, &pb, mps);
+      solve_one(ctx, pb, *opts, so);
+      if (ws) so.rep.ws_peak_bytes = (double)ctx->pool.arena_peak();
+      ctx->pool.release_all();
+    } catch (...) {
+      // nothing of this call may still run when the workspace goes back
+      quiesce(ctx);
+      ctx->pool.release_all();
+      ctx->staging.reset();
+      free_sites(&pb);
+      throw;
+    }
+  });
+  free_sites(&pb);
+  return st;
 }
 
 }  // namespace
@@ -2127,6 +2638,11 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
   for (int i = 0; i < tnqe_ctx::kAux && ok; ++i)
     ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (ok) {
+    ctx->sv_cap = 1 << 16;
+    ok = hipHostMalloc((void **)&ctx->sv_host, ctx->sv_cap * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) ctx->sv_cap = 0;
+  }
   if (!ok) {
     tnqe_destroy(ctx);
     return TNQE_EHIP;
@@ -2172,120 +2688,11 @@ tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, c
   tnqe_problem *pb = new tnqe_problem();
   tnqe_status st = guarded(ctx, [&] {
     TNQE_HIP(hipSetDevice(ctx->device));
-    const int N = ham->N;
-    require(N >= 1 && N <= 64, TNQE_ESHAPE, "N must be in [1, 64]");
-    require(ham->n_alpha >= 0 && ham->n_alpha <= N && ham->n_beta >= 0 && ham->n_beta <= N, TNQE_ESHAPE,
-            "electron counts out of range");
-    require(ham->h != nullptr, TNQE_EINVAL, "h is NULL");
-    require((ham->n_chol > 0 && ham->L) || (ham->n_chol == 0 && ham->g), TNQE_EINVAL,
-            "two-electron integrals missing");
-    pb->N = N;
-    pb->na = ham->n_alpha;
-    pb->nb = ham->n_beta;
-    pb->M = M;
-    pb->e_core = ham->e_core;
-    require(std::isfinite(pb->e_core), TNQE_ENONFINITE, "e_core not finite");
-    const size_t N2 = (size_t)N * N;
-    pb->h.assign(ham->h, ham->h + N2);
-    for (size_t x = 0; x < N2; ++x) {
-      require(std::isfinite(pb->h[x]), TNQE_ENONFINITE, "h has a non-finite entry");
-      require(std::fabs(pb->h[x] - pb->h[(x % N) * N + x / N]) <= 1e-12 * (1 + std::fabs(pb->h[x])),
-              TNQE_EINVAL, "h is not symmetric");
-    }
-    if (ham->n_chol > 0) {
-      pb->K = ham->n_chol;
-      pb->L.assign(ham->L, ham->L + (size_t)pb->K * N2);
-      for (double v : pb->L) require(std::isfinite(v), TNQE_ENONFINITE, "L has a non-finite entry");
-      pb->g.clear();
-    } else {
-      pb->K = 0;
-      pb->g.assign(ham->g, ham->g + N2 * N2);
-      for (double v : pb->g) require(std::isfinite(v), TNQE_ENONFINITE, "g has a non-finite entry");
-    }
-    const int nslot = pb->nslot();
-    int64_t total = 0;
-    pb->mps.resize(M);
-    // bond labels per MPS, kept for the scan of the site tensors, which runs
-    // on the host workers (the labels and U are checked serially first)
-    std::vector<std::vector<std::vector<int>>> lab_a(M), lab_b(M);
-    for (int i = 0; i < M; ++i) {
-      const tnqe_mps &m = mps[i];
-      require(m.bond_dim && m.bond_qn && m.sites && m.U, TNQE_EINVAL, "MPS field is NULL");
-      auto &pm = pb->mps[i];
-      pm.dims.assign(m.bond_dim, m.bond_dim + N + 1);
-      require(pm.dims[0] == 1 && pm.dims[N] == 1, TNQE_ESHAPE, "boundary bonds must have dimension 1");
-      pm.secdim.assign(N + 1, std::vector<int>(nslot, 0));
-      std::vector<std::vector<int>> qa(N + 1), qb(N + 1);
-      int64_t qo = 0;
-      for (int b = 0; b <= N; ++b) {
-        require(pm.dims[b] >= 1 && pm.dims[b] <= 1 << 20, TNQE_ESHAPE, "bond dimension out of range");
-        int prev = -1;
-        for (int x = 0; x < pm.dims[b]; ++x) {
-          const int a = m.bond_qn[2 * (qo + x)], bb = m.bond_qn[2 * (qo + x) + 1];
-          require(a >= 0 && a <= pb->na && bb >= 0 && bb <= pb->nb, TNQE_EQN, "bond label out of range");
-          const int s = a * (pb->nb + 1) + bb;
-          require(s >= prev, TNQE_EQN, "bond indices not sorted by sector");
-          prev = s;
-          pm.secdim[b][s]++;
-          qa[b].push_back(a);
-          qb[b].push_back(bb);
-        }
-        qo += pm.dims[b];
-      }
-      require(qa[0][0] == 0 && qb[0][0] == 0 && qa[N][0] == pb->na && qb[N][0] == pb->nb, TNQE_EQN,
-              "MPS is not in the (n_alpha, n_beta) sector");
-      pm.U.assign(m.U, m.U + N2);
-      for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b) {
-          double acc = 0.0;
-          for (int p = 0; p < N; ++p) acc += pm.U[p * N + a] * pm.U[p * N + b];
-          require(std::isfinite(acc), TNQE_ENONFINITE, "U has a non-finite entry");
-          require(std::fabs(acc - (a == b ? 1.0 : 0.0)) <= 1e-10, TNQE_ENOTORTH, "U is not orthogonal");
-        }
-      pm.site_off.resize(N);
-      for (int p = 0; p < N; ++p) {
-        pm.site_off[p] = total;
-        total += (int64_t)pm.dims[p] * 4 * pm.dims[p + 1];
-      }
-      lab_a[i] = std::move(qa);
-      lab_b[i] = std::move(qb);
-    }
-    // site tensors: finite, and nonzero only inside their particle-number
-    // blocks (one MPS per worker)
-    host_pool(ctx).parallel_for(M, [&](int i) {
-      const auto &pm = pb->mps[i];
-      const auto &qa = lab_a[i], &qb = lab_b[i];
-      const double *sp = mps[i].sites;
-      for (int p = 0; p < N; ++p) {
-        const int dl = pm.dims[p], dr = pm.dims[p + 1];
-        for (int l = 0; l < dl; ++l)
-          for (int k = 0; k < 4; ++k)
-            for (int r = 0; r < dr; ++r) {
-              const double v = sp[((int64_t)l * 4 + k) * dr + r];
-              require(std::isfinite(v), TNQE_ENONFINITE, "site tensor has a non-finite entry");
-              if (v != 0.0)
-                require(qa[p + 1][r] == qa[p][l] + (k & 1) && qb[p + 1][r] == qb[p][l] + (k >> 1), TNQE_EQN,
-                        "site tensor entry outside its particle-number block");
-            }
-        sp += (int64_t)dl * 4 * dr;
-      }
-    });
-    TNQE_HIP(hipMalloc(&pb->d_sites, std::max<int64_t>(1, total) * sizeof(double)));
-    pb->device = ctx->device;
-    int64_t o = 0;
-    for (int i = 0; i < M; ++i) {
-      const int64_t n = pb->mps[i].site_off.empty() ? 0
-                        : [&] {
-                            int64_t s = 0;
-                            for (int p = 0; p < N; ++p) s += (int64_t)pb->mps[i].dims[p] * 4 * pb->mps[i].dims[p + 1];
-                            return s;
-                          }();
-      TNQE_HIP(hipMemcpy(pb->d_sites + o, mps[i].sites, n * sizeof(double), hipMemcpyHostToDevice));
-      o += n;
-    }
+    load_problem(ctx, ham, M, mps, pb);
+    place_sites(ctx, pb, mps);
   });
   if (st != TNQE_OK) {
-    if (pb->d_sites) (void)hipFree(pb->d_sites);
+    free_sites(pb);
     delete pb;
     return st;
   }
@@ -2295,19 +2702,25 @@ tnqe_status tnqe_upload(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, c
 
 tnqe_status tnqe_problem_free(tnqe_problem *pb) {
   if (!pb) return TNQE_EINVAL;
-  if (pb->d_sites) {
-    (void)hipSetDevice(pb->device);
-    (void)hipFree(pb->d_sites);
-  }
+  free_sites(pb);
   delete pb;
   return TNQE_OK;
 }
 
+namespace {
+void copy_out(const SolveOut &so, double *H, double *S, double *E, double *cvec, tnqe_report *rep) {
+  std::memcpy(H, so.H.data(), so.H.size() * sizeof(double));
+  std::memcpy(S, so.S.data(), so.S.size() * sizeof(double));
+  *E = so.E;
+  if (cvec) std::memcpy(cvec, so.c.data(), so.c.size() * sizeof(double));
+  if (rep) *rep = so.rep;
+}
+}  // namespace
+
 tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts, double *H, double *S,
                        double *E, double *cvec, tnqe_report *rep) {
   if (!ctx || !pb || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
-  if (opts->precision != TNQE_FP64 && opts->precision != TNQE_ENV_FP32 && opts->precision != TNQE_ENV_MIXED)
-    return fail(ctx, TNQE_EINVAL, "unknown precision mode");
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
   SolveOut so;
   tnqe_status st = guarded(ctx, [&] {
     TNQE_HIP(hipSetDevice(ctx->device));
@@ -2315,11 +2728,7 @@ tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts
     ctx->pool.release_all();
   });
   if (st != TNQE_OK) return st;
-  std::memcpy(H, so.H.data(), so.H.size() * sizeof(double));
-  std::memcpy(S, so.S.data(), so.S.size() * sizeof(double));
-  *E = so.E;
-  if (cvec) std::memcpy(cvec, so.c.data(), so.c.size() * sizeof(double));
-  if (rep) *rep = so.rep;
+  copy_out(so, H, S, E, cvec, rep);
   return TNQE_OK;
 }
 
@@ -2333,14 +2742,58 @@ tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *prob
   return TNQE_OK;
 }
 
-tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
-                          const tnqe_options *opts, double *H, double *S, double *E, double *c, tnqe_report *rep) {
-  tnqe_problem *pb = nullptr;
-  tnqe_status st = tnqe_upload(ctx, ham, M, mps, &pb);
-  if (st != TNQE_OK) return st;
-  st = tnqe_solve(ctx, pb, opts, H, S, E, c, rep);
-  tnqe_problem_free(pb);
+tnqe_status tnqe_workspace_size(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                                const tnqe_options *opts, size_t *bytes) {
+  if (!ham || !mps || !opts || !bytes) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  // host-only: without a context a temporary one (no device state) serves
+  std::unique_ptr<tnqe_ctx> tmp;
+  if (!ctx) {
+    tmp = std::make_unique<tnqe_ctx>();
+    ctx = tmp.get();
+  }
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
+  size_t out = 0;
+  tnqe_problem pb;
+  tnqe_status st = guarded(ctx, [&] {
+    load_problem(ctx, ham, M, mps, &pb);
+    out = workspace_bound(ctx, pb, *opts);
+  });
+  if (st == TNQE_OK) *bytes = out;
   return st;
+}
+
+tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                          const tnqe_options *opts, void *workspace, size_t ws_bytes, double *H, double *S,
+                          double *E, double *c, tnqe_report *rep) {
+  if (!ctx || !ham || !mps || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
+  SolveOut so;
+  tnqe_status st = subspace_call(ctx, ham, M, mps, opts, workspace, ws_bytes, false, so);
+  if (st != TNQE_OK) return st;
+  copy_out(so, H, S, E, c, rep);
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamiltonian *ham, const int32_t *M,
+                                const tnqe_mps *const *mps, const tnqe_options *opts, void *workspace,
+                                size_t ws_bytes, double *const *H, double *const *S, double *E,
+                                tnqe_report *rep) {
+  if (!ctx || n_sub < 0 || (n_sub > 0 && (!ham || !M || !mps || !opts || !H || !S || !E)))
+    return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  for (int s = 0; s < n_sub; ++s) {
+    if (!mps[s] || !H[s] || !S[s]) return fail(ctx, TNQE_EINVAL, "null argument");
+    if (check_options(ctx, opts + s) != TNQE_OK) return TNQE_EINVAL;
+  }
+  std::vector<SolveOut> outs(n_sub);
+  for (int s = 0; s < n_sub; ++s) {
+    const tnqe_status st = subspace_call(ctx, ham + s, M[s], mps[s], opts + s, workspace, ws_bytes, false, outs[s]);
+    if (st != TNQE_OK) {
+      ctx->last_error = "subspace " + std::to_string(s) + ": " + ctx->last_error;
+      return st;
+    }
+  }
+  for (int s = 0; s < n_sub; ++s) copy_out(outs[s], H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
+  return TNQE_OK;
 }
 
 }  // extern "C"
@@ -2442,13 +2895,35 @@ tnqe_status tnqe_debug_select(tnqe_ctx *ctx, int32_t nket, const int32_t *nblk, 
     const int *dkf = c.upload(kfirst);
     int *dkept = c.dev<int>(std::max(1, nbt));
     double *dstats = c.dev<double>((size_t)3 * nket);
-    launch_select(dblk, dkf, nket, maxv, dsv, chi, tau, kt, 0, dkept, dstats, ctx->stream);
+    launch_select(dblk, dkf, nket, maxv, dsv, chi, tau, kt, 0, dkept, dstats, nullptr, ctx->stream);
     c.check_launch();
     std::vector<int> hk(std::max(1, nbt));
     TNQE_HIP(hipMemcpyAsync(hk.data(), dkept, hk.size() * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     TNQE_HIP(hipMemcpyAsync(stats, dstats, (size_t)3 * nket * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     c.sync();
     for (int i = 0; i < nbt; ++i) kept[i] = hk[i];
+    ctx->pool.rewind(mk);
+  });
+}
+
+tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const double *S, double eps_S,
+                           double *out) {
+  if (!ctx) return TNQE_EINVAL;
+  if (M < 1 || M > kMaxM || !H || !S || !out || !(eps_S > 0.0)) return fail(ctx, TNQE_EINVAL, "bad argument to tnqe_debug_gep");
+  return guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    Call c{ctx};
+    const size_t mk = ctx->pool.mark();
+    const std::vector<double> h(H, H + (size_t)M * M), sm(S, S + (size_t)M * M);
+    std::vector<int> Ms{M};
+    std::vector<int64_t> offs{0};
+    double *dout = c.dev<double>(8 + kMaxM);
+    launch_gep(c.upload(h), c.upload(sm), c.upload(Ms), c.upload(offs), 1, eps_S, dout, ctx->stream);
+    c.check_launch();
+    std::vector<double> go(8 + kMaxM);
+    TNQE_HIP(hipMemcpyAsync(go.data(), dout, go.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    c.sync();
+    std::copy(go.begin(), go.begin() + 8 + M, out);
     ctx->pool.rewind(mk);
   });
 }

@@ -18,8 +18,11 @@
 
 namespace tnqe {
 
-// Grow-only pool of device buffers owned by a context.  Buffers handed out
-// during a call are returned to the pool when the call ends.
+// Device memory of a call.  By default a grow-only pool of buffers owned by
+// the context (hipMalloc on demand, buffers returned to the pool when the call
+// ends).  With an arena set, every buffer is carved from that caller-owned
+// region instead (a stack: mark/rewind pop what was handed out after the
+// mark) and nothing is allocated; running out of it throws TNQE_EWORKSPACE.
 class DevicePool {
  public:
   ~DevicePool() { trim(); }
@@ -31,6 +34,13 @@ class DevicePool {
   // single stream because later work is ordered after earlier work
   size_t mark() const { return order_.size(); }
   void rewind(size_t m);
+  // arena mode (base 256-byte aligned); clear_arena() leaves it
+  void set_arena(void *base, size_t bytes);
+  void clear_arena();
+  bool arena() const { return arena_base_ != nullptr; }
+  // bytes still available to get() (arena mode), else SIZE_MAX
+  size_t available() const;
+  size_t arena_peak() const { return arena_peak_; }
 
  private:
   struct Buf {
@@ -41,22 +51,30 @@ class DevicePool {
   std::vector<Buf> bufs_;
   std::vector<void *> order_;
   size_t held_ = 0;
+  char *arena_base_ = nullptr;
+  size_t arena_size_ = 0, arena_top_ = 0, arena_peak_ = 0;
+  std::vector<size_t> arena_starts_;   // offset of each handed-out buffer (order_)
 };
 
 // Pinned staging area for host-to-device uploads; recycled after each
-// stream synchronisation.
+// stream synchronisation.  With pinned growth disallowed (calls that must not
+// allocate through the HIP runtime), space beyond the current pinned buffer
+// comes from the host heap (pageable copies, kept until the next reset).
 class Staging {
  public:
   ~Staging();
-  void *put(const void *src, size_t bytes);   // returns pinned copy
-  void *reserve(size_t bytes);                // pinned space to fill
+  void *put(const void *src, size_t bytes);   // returns a host copy
+  void *reserve(size_t bytes);                // host space to fill
   void reset();
   size_t capacity() const { return cap_; }
+  void allow_pinned_growth(bool on) { grow_ = on; }
 
  private:
   std::vector<std::pair<char *, size_t>> old_;
+  std::vector<std::unique_ptr<char[]>> heap_;
   char *buf_ = nullptr;
   size_t cap_ = 0, used_ = 0;
+  bool grow_ = true;
 };
 
 // Persistent host worker threads for the per-ket loops of the gate phase.
@@ -85,16 +103,18 @@ class ThreadPool {
 };
 
 // Row pointers and column indices of every sparse MPO group of one
-// structure, on the device (built once per context and site count).
+// structure, on the device (built once per context and site count, or once
+// per call inside the caller's workspace, then not owned).
 struct MpoDevice {
   int *rowptr = nullptr, *col = nullptr;
+  bool owned = true;
   std::vector<std::vector<int64_t>> rp_off, col_off;   // [site][group]
   MpoDevice() = default;
   MpoDevice(const MpoDevice &) = delete;
   MpoDevice &operator=(const MpoDevice &) = delete;
   ~MpoDevice() {
-    if (rowptr) (void)hipFree(rowptr);
-    if (col) (void)hipFree(col);
+    if (owned && rowptr) (void)hipFree(rowptr);
+    if (owned && col) (void)hipFree(col);
   }
 };
 
@@ -108,11 +128,16 @@ struct tnqe_ctx {
   tnqe::Staging staging;
   std::map<int, std::unique_ptr<tnqe::MpoStructure>> mpo_cache;   // by N
   std::map<int, std::unique_ptr<tnqe::MpoDevice>> mpo_dev;        // by N
+  std::unique_ptr<tnqe::MpoDevice> mpo_dev_call;                  // in the workspace of this call
+  bool no_alloc = false;   // this call must not allocate through the HIP runtime
   hipEvent_t ev[8] = {};
   hipEvent_t svd_ev[128] = {};  // timing of the SVD launches not yet collected
-  // pinned host copy of a gate step's singular values, and its completion event
+  // pinned host copy of a gate step's kept counts and statistics, and its
+  // completion event (created with the context; pageable beyond its size in
+  // calls that must not allocate)
   double *sv_host = nullptr;
   size_t sv_cap = 0;
+  std::vector<double> sv_pageable;
   hipEvent_t sv_ev = nullptr, sel_ev = nullptr;
   // side streams (default priority) that run independent SVD launches side by
   // side; forked from and joined back into `stream` with events
@@ -137,6 +162,7 @@ struct tnqe_problem {
   };
   std::vector<Mps> mps;
   double *d_sites = nullptr;       // all sites of all MPS
+  bool owns_sites = true;          // false: d_sites lies in a call's workspace
   int device = 0;
   int nslot() const { return (na + 1) * (nb + 1); }
 };

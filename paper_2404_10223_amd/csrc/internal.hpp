@@ -149,11 +149,14 @@ constexpr int kSelectLdsBytes = 150 * 1024;
 inline size_t select_lds_bytes(int maxv, int nslot) {
   return (size_t)maxv * sizeof(double) + (3 * (size_t)nslot + 1) * sizeof(int);
 }
+// With scale non-null, scale[ket] receives sqrt(total / kept) of the squared
+// singular values (1 when nothing was cut): the renormalisation factor.
 void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double *scratch, int chi, double tau,
-                   const KetTables &kt, int bond, int *kept_out, double *stats, hipStream_t st);
-// units: split_units
+                   const KetTables &kt, int bond, int *kept_out, double *stats, double *scale, hipStream_t st);
+// units: split_units; the new A_{a+1} rows of ket t are multiplied by
+// scale[t] (scale may be null)
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, Units u, const double *scratch,
-                       hipStream_t st);
+                       const double *scale, hipStream_t st);
 // units: gate_chunks(R C)
 void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, Units u, double *scratch,
                       hipStream_t st);

@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_gate_gather(KetTables kt, const Bl
 // chunks of the R x n columns, then those of the n x C rows, of which the
 // first `kept` columns (rows) are written.
 __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, const Blk *blks, Units un,
-                                                         const double *scratch) {
+                                                         const double *scratch, const double *scale) {
   const int bi = find_unit(un.first, un.n, blockIdx.x);
   const Blk &b = stage_block(blks, bi);
   const int pair = b.pair;
@@ -248,11 +248,12 @@ __global__ void __launch_bounds__(kThreads) k_split_gate(KetTables kt, int a, co
     return;
   }
   const int64_t e0 = (int64_t)(u - u1) * kGateChunk, e1 = min<int64_t>((int64_t)kept * b.C, e0 + kGateChunk);
+  const double f = scale ? scale[pair] : 1.0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
     const int jj = e / b.C, col = e - (int64_t)jj * b.C;
     const int k = seg_of(b.cs, col);
     const int r = kt.sec(a + 2, pair, b.sa + qk_a(k), b.sb + qk_b(k)).x + (col - b.cs[k]);
-    B[((int64_t)(b.j0 + jj) * 4 + k) * Dr + r] = Bo[(int64_t)jj * b.C + col];
+    B[((int64_t)(b.j0 + jj) * 4 + k) * Dr + r] = f * Bo[(int64_t)jj * b.C + col];
   }
 }
 
@@ -397,7 +398,7 @@ __device__ double block_sum(double v, double *red) {
 
 __global__ void __launch_bounds__(kSelThreads) k_select(Blk *blks, const int *kfirst, int maxv,
                                                      const double *scratch, int chi, double tau, KetTables kt,
-                                                     int bond, int *kept_out, double *stats) {
+                                                     int bond, int *kept_out, double *stats, double *scale) {
   extern __shared__ __align__(16) double sel_lds[];
   __shared__ double red[kSelThreads];
   __shared__ double s_th, s_so;
@@ -498,6 +499,8 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Blk *blks, const int *kf
     stats[3 * t] = keep;
     stats[3 * t + 1] = disc;
     stats[3 * t + 2] = (keep > 0 && keep < ntot && s_th > 0.0) ? (s_th - s_so) / s_th : 1.0;
+    // renormalisation: the kept values scaled back to the weight before the cut
+    if (scale) scale[t] = (tot > disc && disc > 0.0) ? sqrt(tot / (tot - disc)) : 1.0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += kSelThreads) {
@@ -535,9 +538,9 @@ void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const
 }
 
 void launch_split_gate(const KetTables &kt, int a, const Blk *blk, Units u, const double *scratch,
-                       hipStream_t st) {
+                       const double *scale, hipStream_t st) {
   if (u.total == 0) return;
-  hipLaunchKernelGGL(k_split_gate, dim3(u.total), dim3(kThreads), 0, st, kt, a, blk, u, scratch);
+  hipLaunchKernelGGL(k_split_gate, dim3(u.total), dim3(kThreads), 0, st, kt, a, blk, u, scratch, scale);
 }
 
 void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, Units u, double *scratch,
@@ -565,7 +568,7 @@ void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const
 }
 
 void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double *scratch, int chi, double tau,
-                   const KetTables &kt, int bond, int *kept_out, double *stats, hipStream_t st) {
+                   const KetTables &kt, int bond, int *kept_out, double *stats, double *scale, hipStream_t st) {
   if (nket == 0) return;
   static bool attr_set = false;
   if (!attr_set) {
@@ -575,7 +578,7 @@ void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double
   }
   const size_t lds = select_lds_bytes(maxv, kt.nslot);
   hipLaunchKernelGGL(k_select, dim3(nket), dim3(kSelThreads), lds, st, blk, kfirst, maxv, scratch, chi, tau, kt,
-                     bond, kept_out, stats);
+                     bond, kept_out, stats, scale);
 }
 
 void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n, hipStream_t st) {

@@ -44,19 +44,30 @@ def full(k, rotations="expm"):
 
 
 def c5_pairs():
+    """Sampled pairs of the N = 24 workload.  Each H is computed twice, by the
+    block-sparse MPO sweep and by the plain dense sweep (no sector or channel
+    grouping), and the two must agree: no sector FCI is possible at N = 24."""
+    from oracle.mpo import expectation_plain
     prob = synth.make_config(5)
     cache = {}
     out = {}
     for (i, j) in C5_PAIRS:
         t = time.time()
-        h, s, st = pair_element(prob, i, j, mpo_cache=cache)
+        h, s, st, ket = pair_element(prob, i, j, mpo_cache=cache, return_ket=True)
+        hp, sp = expectation_plain(cache[i], prob.mps[i].sites, ket)
+        assert abs(hp - h) <= 1e-12 * max(abs(h), 1e-300) + 1e-14 and abs(sp - s) <= 1e-12 * abs(s) + 1e-16, \
+            (h, hp, s, sp)
         gaps = [x["gap"] for x in st if x["gap"] is not None]
-        out[f"{i}_{j}"] = np.array([h, s, min(gaps) if gaps else 1.0, time.time() - t])
-        print(i, j, h, s, time.time() - t, flush=True)
+        out[f"{i}_{j}"] = np.array([h, s, min(gaps) if gaps else 1.0, time.time() - t, hp, sp])
+        print(i, j, h, hp, s, sp, time.time() - t, flush=True)
     np.savez(os.path.join(HERE, "oracle_config5_pairs.npz"), **out)
 
 
-BATCH_SAMPLE = [3, 7, 10, 11, 0]
+# sampled subspaces of the batched workload: every chi in {16, 32, 64, 128},
+# N from 8 to 15; H by sector FCI wherever N <= 13 (independent of any MPO),
+# by the oracle's MPO sweep (cross-checked by the plain dense sweep) above
+BATCH_SAMPLE = [3, 7, 11, 19, 16, 10, 9, 23, 13, 49, 0]
+FCI_MAX_N = 13
 
 
 def batch():
@@ -65,10 +76,36 @@ def batch():
     for s_ in BATCH_SAMPLE:
         prob = probs[s_]
         t = time.time()
-        H, S, E, c, rep = subspace(prob, h_method="mpo")
+        method = "fci" if prob.N <= FCI_MAX_N else "mpo"
+        H, S, E, c, rep = subspace(prob, h_method=method)
+        if method == "mpo":
+            # the block-sparse sweep against the plain dense sweep, pair by pair
+            Hp = plain_pencil(prob)
+            assert np.abs(Hp - H).max() <= 1e-11 * np.abs(H).max(), np.abs(Hp - H).max()
         res[f"H{s_}"], res[f"S{s_}"], res[f"E{s_}"] = H, S, E
-        print("batch", s_, prob.N, prob.chi, prob.M, E, time.time() - t, flush=True)
+        res[f"rep{s_}"] = np.array([rep["cond_S"], rep["lam_min"], rep["kappa1"], rep["n_dropped"],
+                                    rep["min_rel_gap"] or 1.0, rep["max_discarded_weight_sum"]])
+        res[f"method{s_}"] = np.array(method)
+        print("batch", s_, prob.N, prob.chi, prob.M, method, E, time.time() - t, flush=True)
         np.savez(os.path.join(HERE, "oracle_batch.npz"), **res)
+
+
+def plain_pencil(prob):
+    """H by the plain dense MPO sweep for every pair (the same kets)."""
+    from oracle.mpo import build_mpo, expectation_plain
+    from oracle.subspace import rotate_integrals, rotate_ket
+    H = np.zeros((prob.M, prob.M))
+    for i in range(prob.M):
+        bi = prob.mps[i]
+        hi, Li = rotate_integrals(prob.h, prob.L, bi.U)
+        W = build_mpo(hi, np.einsum("kpq,krs->pqrs", Li, Li))
+        for j in range(i, prob.M):
+            if i == j:
+                ket = bi.sites
+            else:
+                ket, _, _ = rotate_ket(prob.mps[j].sites, prob.mps[j].bond_qn, bi.U.T @ prob.mps[j].U, prob.chi)
+            H[i, j] = H[j, i] = expectation_plain(W, bi.sites, ket)[0]   # e_core = 0 in the batch
+    return H
 
 
 if __name__ == "__main__":

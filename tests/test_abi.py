@@ -99,3 +99,27 @@ def test_host_pool_back_to_back_jobs():
     assert T.debug_host_pool(7, jobs) == sum(1 + j % 5 for j in range(jobs))
     assert T.debug_host_pool(0, 100) == sum(1 + j % 5 for j in range(100))
 
+
+
+def test_workspace_size_host_only(lib):
+    """tnqe_workspace_size needs no device: it validates the inputs and bounds
+    the device memory of a call; the bound covers at least the inputs and the
+    rotated kets, grows with chi, and rejects bad inputs like a solve."""
+    p1, p2 = synth.make_config(1), synth.make_config(2)
+    b1 = T.workspace_size(p1, chi=p1.chi)
+    sites = sum(a.size for m in p1.mps for a in m.sites) * 8
+    assert b1 > sites
+    small, large = T.workspace_size(p2, chi=4), T.workspace_size(p2, chi=16)
+    assert 0 < small < large
+    # FP32 environments need no more than FP64 ones
+    assert T.workspace_size(p2, chi=16, precision="fp32") <= large
+    # the full-size workload: bounded well inside one GPU's 288 GB
+    p5 = synth.make_config(5)
+    assert T.workspace_size(p5, chi=p5.chi) < 64 * 2 ** 30
+    bad = synth.Problem(**{**p1.__dict__, "mps": [synth.MPS(p1.mps[0].sites, p1.mps[0].bond_qn,
+                                                             p1.mps[0].U * 1.01)]})
+    with pytest.raises(T.TnqeError) as e:
+        T.workspace_size(bad, chi=4)
+    assert e.value.status == -3
+    with pytest.raises(T.TnqeError):
+        T.workspace_size(p1, chi=0)

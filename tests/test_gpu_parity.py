@@ -12,7 +12,7 @@ import pytest
 
 import paper_2404_10223_amd as T
 import tnqe_synth as synth
-from oracle import fock
+from oracle import fock, gep
 from oracle.subspace import subspace as oracle_subspace
 
 pytestmark = pytest.mark.gpu
@@ -43,15 +43,117 @@ def _assert_pencil(H, S, E, Ho, So, Eo, tol=RTOL, elementwise=False):
     np.testing.assert_array_equal(S, S.T)
 
 
+def _assert_report(rep, Ho, So):
+    """cond(S), lambda_min(S), kappa_1 and the dropped count of the library
+    against the oracle's eigensolver on the oracle's pencil (App. A2)."""
+    o = gep.solve_projection(Ho, So)
+    print(f"cond_S={rep['cond_S']:.6e} ({o['cond_S']:.6e}) lambda_min={rep['lambda_min_S']:.6e} "
+          f"({o['lam_min']:.6e}) kappa1={rep['kappa1']:.6e} ({o['kappa1']:.6e})", flush=True)
+    assert rep["n_dropped"] == o["n_dropped"]
+    assert abs(rep["lambda_min_S"] - o["lam_min"]) <= 1e-10 * max(1.0, abs(o["lam_min"]))
+    assert abs(rep["cond_S"] - o["cond_S"]) <= 1e-8 * o["cond_S"]
+    assert abs(rep["kappa1"] - o["kappa1"]) <= 1e-8 * o["kappa1"]
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_config_parity_fp64(ctx, k):
     prob = synth.make_config(k)
     g = np.load(os.path.join(GOLD, f"oracle_config{k}.npz"))
     H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi)
     _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), elementwise=True)
+    _assert_report(rep, g["H"], g["S"])
     assert abs(rep["max_discarded_weight_sum"] - float(g["max_discarded"])) < 1e-10
     np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
     assert abs(c @ S @ c - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_workspace_path(ctx, k):
+    """tnqe_subspace with a caller-allocated device workspace (torch): every
+    device buffer of the call lies in it; same results as the pooled path."""
+    import torch
+    prob = synth.make_config(k)
+    g = np.load(os.path.join(GOLD, f"oracle_config{k}.npz"))
+    n = ctx.workspace_size(prob, chi=prob.chi)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, workspace=ws)
+    print(f"workspace {n / 2 ** 20:.1f} MiB, used {rep['ws_peak_bytes'] / 2 ** 20:.1f} MiB", flush=True)
+    _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), elementwise=True)
+    assert 0 < rep["ws_peak_bytes"] <= n
+    # a workspace below what the call needs is refused cleanly, and the
+    # context goes on working (the environment sweep fills what it is given
+    # with pair batches, so only far smaller sizes fail)
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(T.TnqeError) as e:
+        ctx.subspace(prob, chi=prob.chi, workspace=small)
+    assert e.value.status == -6
+    H2, S2, E2, _, _ = ctx.subspace(prob, chi=prob.chi, workspace=ws)
+    np.testing.assert_array_equal(H2, H)
+    np.testing.assert_array_equal(S2, S)
+
+
+def test_workspace_smaller_than_common_layout(ctx):
+    """A workspace that holds the gate phase but not one pair of the common
+    environment layout: every pair then runs alone in its own layout."""
+    import torch
+    prob = synth.make_config(3)
+    g = np.load(os.path.join(GOLD, "oracle_config3.npz"))
+    big = torch.empty(ctx.workspace_size(prob, chi=prob.chi), dtype=torch.uint8, device="cuda")
+    _, _, _, _, rep = ctx.subspace(prob, chi=prob.chi, workspace=big)
+    lo, hi = 1, int(rep["ws_peak_bytes"])
+    got = None
+    # the smallest workspace (to 1 %) that still works: it takes the own-layout route
+    while hi - lo > hi // 100:
+        mid = (lo + hi) // 2
+        try:
+            got = ctx.subspace(prob, chi=prob.chi, workspace=big[:mid])
+            hi = mid
+        except T.TnqeError as e:
+            assert e.status == -6
+            lo = mid
+    H, S, E, c, rep2 = ctx.subspace(prob, chi=prob.chi, workspace=big[:hi])
+    print(f"smallest workspace {hi / 2 ** 20:.1f} MiB of {rep['ws_peak_bytes'] / 2 ** 20:.1f}", flush=True)
+    _assert_pencil(H, S, E, g["H"], g["S"], float(g["E"]), elementwise=True)
+
+
+def test_device_gep_hand_solved(ctx):
+    """The device eigensolver on pencils solved by hand (App. A2: kappa_1,
+    thresholding of S)."""
+    r = ctx.debug_gep(np.array([[0.0, 1.0], [1.0, 0.0]]), np.array([[1.0, 0.5], [0.5, 1.0]]))
+    assert r["status"] == 0 and abs(r["E"] + 2.0) < 1e-14
+    assert abs(abs(r["c"][0]) - 1.0) < 1e-13 and abs(r["c"][0] + r["c"][1]) < 1e-13
+    assert abs(r["kappa1"] - 2.0 / np.sqrt(5.0)) < 1e-13
+    assert abs(r["cond_S"] - 3.0) < 1e-12 and abs(r["lambda_min"] - 0.5) < 1e-14 and r["n_dropped"] == 0
+    r = ctx.debug_gep(np.diag([-8.0, 1.0, 5.0]), np.diag([4.0, 1e-3, 1e-14]))
+    assert r["n_dropped"] == 1 and abs(r["E"] + 2.0) < 1e-14
+    np.testing.assert_allclose(np.abs(r["c"]), [0.5, 0.0, 0.0], atol=1e-15)
+    assert abs(r["kappa1"] - 0.25 / np.sqrt(5.0)) < 1e-15 and abs(r["cond_S"] - 4e3) < 1e-9
+    assert r["lambda_min"] == 1e-14
+    r = ctx.debug_gep(np.diag([-1.0, 2.0]), np.diag([1.0, -1e-9]))
+    assert r["n_dropped"] == 1 and r["lambda_min"] == -1e-9 and abs(r["E"] + 1.0) < 1e-15
+    # random pencils against the oracle, up to M = 32
+    rng = np.random.default_rng(11)
+    for M in (3, 16, 32):
+        A = rng.normal(size=(M, M))
+        S = A @ A.T / M + np.eye(M)
+        H = rng.normal(size=(M, M))
+        H = H + H.T
+        r = ctx.debug_gep(H, S)
+        o = gep.solve_projection(H, S)
+        assert abs(r["E"] - o["E"]) < 1e-12 * max(1.0, abs(o["E"]))
+        assert abs(r["kappa1"] - o["kappa1"]) < 1e-10 * o["kappa1"]
+        assert abs(r["cond_S"] - o["cond_S"]) < 1e-10 * o["cond_S"]
+
+
+def test_renormalized_truncation(ctx):
+    """renormalize = 1 (the kept part rescaled after every cut) against the
+    oracle with the same option."""
+    prob = synth.make_config(2)
+    Ho, So, Eo, co, rep_o = oracle_subspace(prob, renormalize=True)
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, renormalize=True)
+    _assert_pencil(H, S, E, Ho, So, Eo, elementwise=True)
+    H0, S0, _, _, _ = ctx.subspace(prob, chi=prob.chi)
+    assert np.abs(S - S0).max() > 1e-6          # the option changes the result
 
 
 @pytest.mark.parametrize("rot", ["perm", "identity"])
@@ -183,14 +285,30 @@ def test_input_validation(ctx):
 
 
 def test_fp32_environments(ctx):
+    """All environments in FP32 (every pair): each element against the FP64
+    oracle relative to itself, and the eigenvalue error reported.  Plain FP32
+    storage does not reach the 1e-6 Ha target at this size (the diagonal
+    elements are ~60 Ha and FP32 keeps ~7 digits); see the xfail below."""
     prob = synth.make_config(3)
     g = np.load(os.path.join(GOLD, "oracle_config3.npz"))
     H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, precision="fp32")
     dE = abs(E - float(g["E"]))
-    dH = np.abs(H - g["H"]).max() / np.abs(g["H"]).max()
-    print(f"fp32: dE={dE:.2e} dH_rel={dH:.2e}")
-    assert dH < 1e-6
-    assert dE < 1e-5
+    relH = np.max(np.abs(H - g["H"]) / np.abs(g["H"]))
+    relS = np.max(np.abs(S - g["S"]) / np.abs(g["S"]))
+    print(f"fp32: dE={dE:.2e} max_rel_dH={relH:.2e} max_rel_dS={relS:.2e}", flush=True)
+    assert rep["n_fp32_pairs"] == prob.M * (prob.M + 1) // 2
+    # FP32 rounding over 12 sites of environment contractions: 1e-4 relative
+    # to each element (measured ~1e-6 on the diagonal)
+    assert relH < 1e-4 and relS < 1e-4
+    assert dE < 1e-4
+
+
+@pytest.mark.xfail(strict=True, reason="plain FP32 environments miss |dE| <= 1e-6 Ha (measured ~3e-6 at N = 12)")
+def test_fp32_environments_meet_target(ctx):
+    prob = synth.make_config(3)
+    g = np.load(os.path.join(GOLD, "oracle_config3.npz"))
+    H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, precision="fp32")
+    assert abs(E - float(g["E"])) <= 1e-6
 
 
 def test_full_size_sampled_pairs(ctx):
@@ -225,8 +343,9 @@ def test_dense_coupling_path(monkeypatch):
 
 
 def test_batch_of_subspaces(ctx):
-    """64 independent subspaces (N in 8..16, chi in {16..128}, M in 2..8) in one
-    batched call; sampled subspaces against the stored oracle values."""
+    """64 independent subspaces (N in 8..16, chi in {16..128}, M in 2..8) in
+    one batched call; sampled subspaces (every chi, H by sector FCI up to
+    N = 13) against the stored oracle values, element by element."""
     probs = synth.make_batch()
     g = np.load(os.path.join(GOLD, "oracle_batch.npz"))
     ups = [ctx.upload(p) for p in probs]
@@ -240,10 +359,29 @@ def test_batch_of_subspaces(ctx):
         assert np.isfinite(Es[s_])
         np.testing.assert_allclose(np.diag(Ss[s_]), 1.0, atol=1e-12)
     sampled = sorted({int(k[1:]) for k in g.files if k.startswith("E")})
-    assert sampled
+    assert {probs[s_].chi for s_ in sampled} == {16, 32, 64, 128} and len(sampled) >= 8
     for s_ in sampled:
-        print(f"subspace {s_}: N={probs[s_].N} chi={probs[s_].chi} M={probs[s_].M}", flush=True)
+        print(f"subspace {s_}: N={probs[s_].N} chi={probs[s_].chi} M={probs[s_].M} ({g[f'method{s_}']})",
+              flush=True)
         _assert_pencil(Hs[s_], Ss[s_], Es[s_], g[f"H{s_}"], g[f"S{s_}"], float(g[f"E{s_}"]), elementwise=True)
+        _assert_report(reps[s_], g[f"H{s_}"], g[f"S{s_}"])
+        assert abs(reps[s_]["max_discarded_weight_sum"] - float(g[f"rep{s_}"][5])) < 1e-10
+
+
+def test_subspace_batch_with_workspace(ctx):
+    """tnqe_subspace_batch from host inputs, all subspaces in one caller
+    workspace (the largest bound of the set)."""
+    import torch
+    probs = synth.make_batch()
+    g = np.load(os.path.join(GOLD, "oracle_batch.npz"))
+    sampled = sorted({int(k[1:]) for k in g.files if k.startswith("E")})
+    sel = [probs[s_] for s_ in sampled]
+    n = max(ctx.workspace_size(p, chi=p.chi) for p in sel)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    Hs, Ss, Es, reps = ctx.subspace_batch(sel, workspace=ws)
+    for s_, H, S, E, r in zip(sampled, Hs, Ss, Es, reps):
+        _assert_pencil(H, S, E, g[f"H{s_}"], g[f"S{s_}"], float(g[f"E{s_}"]), elementwise=True)
+        assert 0 < r["ws_peak_bytes"] <= n
 
 
 def test_mixed_precision_full_size(ctx):
@@ -259,11 +397,13 @@ def test_mixed_precision_full_size(ctx):
     print(f"mixed: {repm['n_fp32_pairs']} FP32 pairs, dE={abs(Em - E):.2e}", flush=True)
     assert repm["n_fp32_pairs"] > 0
     assert abs(Em - E) <= 1e-6
-    # FP64 pairs (the diagonal) agree to the FP64 tolerance.  An FP32 pair's
-    # ket keeps at most 1e-6 of its squared norm, so its environment rounding
-    # (24 sites x 2^-24 relative to norms <= 1e-3) is below 1e-9 absolute;
-    # elements are checked to 1e-4 relative plus that floor (a lost or wrong
-    # element of size >= 1e-9 still fails)
+    # FP64 pairs (the diagonal) agree to the FP64 tolerance
     np.testing.assert_allclose(np.diag(Hm), np.diag(H), rtol=1e-12)
-    np.testing.assert_allclose(Sm, S, rtol=1e-4, atol=1e-9)
-    np.testing.assert_allclose(Hm, H, rtol=1e-4, atol=1e-9 * float(np.max(np.abs(np.diag(H)))))
+    np.testing.assert_allclose(np.diag(Sm), np.diag(S), rtol=1e-12)
+    # every FP32 element relative to itself, with no absolute floor: FP32
+    # environments over 24 sites keep ~5 digits (measured <= 7e-5)
+    off = ~np.eye(prob.M, dtype=bool)
+    relH = np.abs(Hm - H)[off] / np.abs(H)[off]
+    relS = np.abs(Sm - S)[off] / np.abs(S)[off]
+    print(f"mixed FP32 elements: max_rel_dH={relH.max():.2e} max_rel_dS={relS.max():.2e}", flush=True)
+    assert relH.max() < 1e-3 and relS.max() < 1e-3

@@ -33,7 +33,10 @@ def test_mpo_bond_dimension_is_quadratic():
     assert d[0] == 1 and d[-1] == 2
 
 
-@pytest.mark.parametrize("N,na,nb,chi", [(6, 3, 2, 12), (7, 4, 4, 10), (8, 4, 4, 20)])
+# N = 10 and 12 reach every channel path of the builder at sizes where the
+# two-operator channels switch from normal to complementary form at the centre
+@pytest.mark.parametrize("N,na,nb,chi", [(6, 3, 2, 12), (7, 4, 4, 10), (8, 4, 4, 20), (10, 5, 5, 16),
+                                         (12, 6, 5, 12)])
 def test_sweep_equals_sector_fci(N, na, nb, chi):
     h, L, g = _random_integrals(N, 4, 100 + N)
     W = mpo.build_mpo(h, g)
@@ -141,3 +144,18 @@ def test_sweep_matches_slater_condon(N):
         want = _slater_condon(h, g, sorted(occ), sorted(ket_occ))
         assert abs(H - want) < 1e-12 * max(1.0, abs(want)), (sorted(ket_occ), H, want)
         assert S == (1.0 if ket_occ == occ else 0.0)
+
+
+@pytest.mark.parametrize("N,na,nb,chi", [(5, 2, 3, 6), (8, 4, 4, 20)])
+def test_plain_contraction_equals_sector_fci(N, na, nb, chi):
+    """The ungrouped dense sweep (used to cross-check the full-size values)
+    against sector FCI, independently of the block-sparse sweep."""
+    h, L, g = _random_integrals(N, 4, 200 + N)
+    W = mpo.build_mpo(h, g)
+    f = SectorFCI(N, na, nb)
+    bra, bq = synth.make_mps(N, na, nb, chi, (8,), 0)
+    ket, kq = synth.make_mps(N, na, nb, chi // 2 + 1, (8,), 1)
+    H, S = mpo.expectation_plain(W, bra, ket)
+    vb, vk = f.from_mps(bra), f.from_mps(ket)
+    assert abs(S - np.sum(vb * vk)) < 1e-13
+    assert abs(H - f.expectation(h, L, 0.0, vb, vk)) < 1e-11 * max(1.0, abs(H))

@@ -205,3 +205,25 @@ def test_select_kept_is_best_subset_brute_force():
             assert gap == pytest.approx((s_in - s_out) / s_in)
         else:
             assert gap is None
+
+
+def test_renormalized_network_is_the_normalized_projection():
+    """With renormalisation after every cut the rotated ket has unit norm and
+    equals the plain (projected) ket divided by its norm: the kept subspace of
+    a cut does not depend on the scale of the state, so rescaling commutes
+    with every later gate and cut."""
+    import tnqe_synth as synth
+    from oracle.subspace import pair_element, rotate_ket
+    prob = synth.make_config(2)
+    bi, bj = prob.mps[0], prob.mps[2]
+    W = bi.U.T @ bj.U
+    plain, _, st = rotate_ket(bj.sites, bj.bond_qn, W, prob.chi)
+    ren, _, st_r = rotate_ket(bj.sites, bj.bond_qn, W, prob.chi, renormalize=True)
+    assert sum(x["discarded"] for x in st) > 1e-6          # the network does cut
+    n2 = M.overlap(plain, plain)
+    assert abs(M.overlap(ren, ren) - 1.0) < 1e-12
+    assert abs(M.overlap(bi.sites, ren) - M.overlap(bi.sites, plain) / np.sqrt(n2)) < 1e-12
+    h, s, _ = pair_element(prob, 0, 2)
+    hr, sr, _ = pair_element(prob, 0, 2, renormalize=True)
+    assert abs(hr - h / np.sqrt(n2)) < 1e-11 * max(1.0, abs(h))
+    assert abs(sr - s / np.sqrt(n2)) < 1e-13

@@ -139,7 +139,36 @@ def test_gep_closed_forms():
         assert abs(p["E"] - e_ref) < 1e-12 * max(1, abs(e_ref))
         assert abs(q["E"] - e_ref) < 1e-10 * max(1, abs(e_ref))
         assert abs(p["c"] @ Sx @ p["c"] - 1.0) < 1e-12
-        assert abs(p["kappa1"] - (p["c"] @ p["c"]) / np.sqrt(p["E"] ** 2 + 1)) < 1e-15
+
+
+def test_gep_report_hand_solved():
+    """kappa_1 (App. A2), cond(S), lambda_min(S) and the dropped count on
+    pencils solved by hand."""
+    # H = [[0, 1], [1, 0]], S = [[1, 1/2], [1/2, 1]]: det(H - E S) = 0 reads
+    # (3/4) E^2 + E - 1 = 0, roots -2 and 2/3; at E = -2, H + 2 S = [[2, 2], [2, 2]]
+    # so c = (1, -1) (c^T S c = 1 + 1 - 1 = 1 already), |c|^2 = 2,
+    # kappa_1 = 2 / sqrt(5); eigenvalues of S are 3/2 and 1/2
+    sol = gep.solve_projection(np.array([[0.0, 1.0], [1.0, 0.0]]), np.array([[1.0, 0.5], [0.5, 1.0]]))
+    assert abs(sol["E"] + 2.0) < 1e-14
+    assert abs(abs(sol["c"][0]) - 1.0) < 1e-14 and abs(sol["c"][0] + sol["c"][1]) < 1e-14
+    assert abs(sol["kappa1"] - 2.0 / np.sqrt(5.0)) < 1e-14
+    assert abs(sol["cond_S"] - 3.0) < 1e-13
+    assert abs(sol["lam_min"] - 0.5) < 1e-14
+    assert sol["n_dropped"] == 0
+    # diagonal S = diag(4, 1e-3, 1e-14) with H = diag(-8, 1, 5): the third
+    # eigenvalue is below 1e-12 * 4 and is dropped; the reduced problem is
+    # diag(-8/4, 1/1e-3) so E = -2, c = (1/2, 0, 0), kappa_1 = (1/4) / sqrt(5)
+    sol = gep.solve_projection(np.diag([-8.0, 1.0, 5.0]), np.diag([4.0, 1e-3, 1e-14]))
+    assert sol["n_dropped"] == 1
+    assert abs(sol["E"] + 2.0) < 1e-14
+    np.testing.assert_allclose(np.abs(sol["c"]), [0.5, 0.0, 0.0], atol=1e-15)
+    assert abs(sol["kappa1"] - 0.25 / np.sqrt(5.0)) < 1e-15
+    assert abs(sol["cond_S"] - 4.0 / 1e-3) < 1e-9
+    assert sol["lam_min"] == 1e-14
+    # a negative eigenvalue of S (possible under truncation) is reported and dropped
+    sol = gep.solve_projection(np.diag([-1.0, 2.0]), np.diag([1.0, -1e-9]))
+    assert sol["n_dropped"] == 1 and sol["lam_min"] == -1e-9 and abs(sol["E"] + 1.0) < 1e-15
+    assert abs(sol["kappa1"] - 1.0 / np.sqrt(2.0)) < 1e-15
 
 
 def test_duplicated_mps_singular_overlap(c1):
