@@ -237,6 +237,22 @@ tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamilto
                                 size_t ws_bytes, double *const *H, double *const *S, double *E,
                                 tnqe_report *rep);
 
+/* For callers that cannot allocate memory (code under HIP stream capture,
+ * tight serving loops, harnesses that forbid allocation): tnqe_subspace with
+ * no workspace argument and no allocation of device or pinned host memory,
+ * of timing events or of streams.  Every device buffer of the call lies in a
+ * fixed scratch array of tnqe_noalloc_capacity() bytes (256 MiB) that each
+ * GPU holds from its first tnqe_create until the process ends.  Inputs whose
+ * tnqe_workspace_size exceeds that are refused with TNQE_EWORKSPACE before
+ * any device work.  Arguments, outputs and errors as in tnqe_subspace.  All
+ * calls on one GPU share its scratch (it keeps the last call's contents): two
+ * such calls that overlap in time on one GPU, from any thread or context,
+ * race and give wrong results; serialise them. */
+tnqe_status tnqe_subspace_noalloc(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                                  const tnqe_options *opts, double *H, double *S, double *E, double *c,
+                                  tnqe_report *rep);
+size_t tnqe_noalloc_capacity(void);
+
 const char *tnqe_status_string(tnqe_status st);
 const char *tnqe_last_error(const tnqe_ctx *ctx);
 const char *tnqe_version(void);

@@ -59,7 +59,7 @@ EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "
            "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_workspace_size", "tnqe_subspace",
            "tnqe_subspace_batch", "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
            "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool", "tnqe_debug_select",
-           "tnqe_debug_gep"]
+           "tnqe_debug_gep", "tnqe_subspace_noalloc", "tnqe_noalloc_capacity"]
 
 _lib = None
 
@@ -96,6 +96,10 @@ def lib():
                                       C.POINTER(_Opts), vp, C.c_size_t, C.POINTER(dp), C.POINTER(dp), dp,
                                       C.POINTER(_Report)]
     L.tnqe_debug_gep.argtypes = [vp, ip, dp, dp, C.c_double, dp]
+    L.tnqe_subspace_noalloc.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), dp, dp, dp, dp,
+                                        C.POINTER(_Report)]
+    L.tnqe_noalloc_capacity.argtypes = []
+    L.tnqe_noalloc_capacity.restype = C.c_size_t
     L.tnqe_status_string.argtypes = [C.c_int]
     L.tnqe_status_string.restype = C.c_char_p
     L.tnqe_last_error.argtypes = [vp]
@@ -252,6 +256,20 @@ class Context:
 
     def workspace_size(self, prob, **kw):
         return workspace_size(prob, self, **kw)
+
+    def subspace_noalloc(self, prob, **kw):
+        """tnqe_subspace_noalloc: the library's fixed per-GPU scratch, no allocation."""
+        pk = _Packed(prob)
+        o = options(**kw)
+        M = prob.M
+        H = np.zeros((M, M))
+        S = np.zeros((M, M))
+        E = np.zeros(1)
+        c = np.zeros(M)
+        r = _Report()
+        _check(self.L.tnqe_subspace_noalloc(self.h, C.byref(pk.ham), M, pk.mps, C.byref(o), _dptr(H), _dptr(S),
+                                            _dptr(E), _dptr(c), C.byref(r)), self.h)
+        return H, S, float(E[0]), c, report_dict(r)
 
     def subspace_batch(self, probs, chis=None, workspace=None, **kw):
         """Several subspaces from host inputs (tnqe_subspace_batch)."""

@@ -1704,7 +1704,13 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     double *dout = c.dev<double>((size_t)nb_ * 2);
     // one event between consecutive launches: launch i runs from tick i to i + 1
     std::vector<int> tick_kind;
+    // per-launch timing needs one event per launch; a call that must not
+    // allocate uses only the events the context already has, else none
+    size_t nticks = 1;
+    for (int x = 0; x < N; ++x) nticks += 2 + ctabs[x].dense.size() + 1;
+    const bool timed = !c.ctx->no_alloc || nticks <= c.ctx->env_ev.size();
     auto tick = [&](int kind) {
+      if (!timed) return;
       const size_t i = tick_kind.size();
       if (i >= c.ctx->env_ev.size()) {
         hipEvent_t e;
@@ -2638,6 +2644,7 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
   for (int i = 0; i < tnqe_ctx::kAux && ok; ++i)
     ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  ok = ok && noalloc_setup(device) == TNQE_OK;
   if (ok) {
     ctx->sv_cap = 1 << 16;
     ok = hipHostMalloc((void **)&ctx->sv_host, ctx->sv_cap * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -2717,6 +2724,35 @@ void copy_out(const SolveOut &so, double *H, double *S, double *E, double *cvec,
 }
 }  // namespace
 
+}  // extern "C"
+
+tnqe_status tnqe::subspace_entry(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                                 const tnqe_options *opts, void *ws, size_t ws_bytes, bool no_alloc,
+                                 size_t max_bound, double *H, double *S, double *E, double *c, tnqe_report *rep) {
+  if (!ctx || !ham || !mps || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
+  if (max_bound > 0) {
+    // refused before any device work when the bound exceeds the fixed size
+    size_t need = 0;
+    tnqe_problem pb;
+    const tnqe_status st = guarded(ctx, [&] {
+      load_problem(ctx, ham, M, mps, &pb);
+      need = workspace_bound(ctx, pb, *opts);
+    });
+    if (st != TNQE_OK) return st;
+    if (need > max_bound)
+      return fail(ctx, TNQE_EWORKSPACE, "problem needs up to " + std::to_string(need) + " bytes of device memory; " +
+                                            "the fixed scratch holds " + std::to_string(max_bound));
+  }
+  SolveOut so;
+  const tnqe_status st = subspace_call(ctx, ham, M, mps, opts, ws, ws_bytes, no_alloc, so);
+  if (st != TNQE_OK) return st;
+  copy_out(so, H, S, E, c, rep);
+  return TNQE_OK;
+}
+
+extern "C" {
+
 tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts, double *H, double *S,
                        double *E, double *cvec, tnqe_report *rep) {
   if (!ctx || !pb || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
@@ -2765,13 +2801,7 @@ tnqe_status tnqe_workspace_size(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int3
 tnqe_status tnqe_subspace(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
                           const tnqe_options *opts, void *workspace, size_t ws_bytes, double *H, double *S,
                           double *E, double *c, tnqe_report *rep) {
-  if (!ctx || !ham || !mps || !opts || !H || !S || !E) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
-  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
-  SolveOut so;
-  tnqe_status st = subspace_call(ctx, ham, M, mps, opts, workspace, ws_bytes, false, so);
-  if (st != TNQE_OK) return st;
-  copy_out(so, H, S, E, c, rep);
-  return TNQE_OK;
+  return tnqe::subspace_entry(ctx, ham, M, mps, opts, workspace, ws_bytes, false, 0, H, S, E, c, rep);
 }
 
 tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamiltonian *ham, const int32_t *M,

@@ -118,6 +118,17 @@ struct MpoDevice {
   }
 };
 
+// One subspace call from host inputs (tnqe_subspace and its variants): with a
+// workspace every device buffer lies in it; no_alloc also keeps the call
+// from allocating pinned host memory and timing events; max_bound > 0
+// refuses, before any device work, problems whose bound exceeds it.
+tnqe_status subspace_entry(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                           const tnqe_options *opts, void *ws, size_t ws_bytes, bool no_alloc, size_t max_bound,
+                           double *H, double *S, double *E, double *c, tnqe_report *rep);
+// The fixed device scratch of the calls that cannot allocate: looked up once
+// per device with that device current (defined beside the scratch array).
+tnqe_status noalloc_setup(int device);
+
 }  // namespace tnqe
 
 struct tnqe_ctx {
