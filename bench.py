@@ -29,7 +29,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-SVD_KERNELS = ["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global"] + [None] * 9
+SVD_KERNELS = ["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global", "k_qr_blocks"] + [None] * 8
 KERNEL_SOURCE = {"k_jacobi": "kernels_svd.hip", "k_env": "kernels_env.hip", "k_mix": "kernels_env.hip"}
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.md")
 ENV_KERNELS = ["k_env_g1", "k_mix", "k_env_gd", "k_env_g2", "k_env_final", None, None, None]
@@ -236,7 +236,8 @@ def main():
                        "pairs": n_pairs, "parallelism": "single GPU"},
             "E": E, "report": {k: rep[k] for k in ("t_host_ms", "t_gates_ms", "t_env_ms", "t_gep_ms",
                                                    "max_discarded_weight_sum", "min_rel_gap", "max_bond",
-                                                   "svd_kernel_ms", "svd_flops", "env_kernel_ms", "env_flops",
+                                                   "svd_kernel_ms", "svd_flops", "move_kernel_ms", "move_flops",
+                                                   "move_launches", "t_moves_ms", "env_kernel_ms", "env_flops",
                                                    "alg_bytes")},
             "mixed": mixed, "roofline": roof, "kernels": kernel_breakdown(rep), "cpu_baseline": cpu,
             "pcie_inclusive": {"upload_ms": upload_s * 1e3, "value": n_pairs / (t64 + upload_s),

@@ -145,9 +145,10 @@ typedef struct {
   double svd_kernel_ms;             /* summed device time of the block SVD launches     */
                                     /*   (truncations and centre moves)                 */
   double svd_flops;                 /* their algorithmic flops (4 n^2 m + 9 n^3 a block) */
-  double svd_kind_ms[16];           /* the same split by SVD kernel: entry k < 6 for    */
-  double svd_kind_flops[16];        /*   4 (k + 1) vector elements per lane, entry 6 for */
-                                    /*   the global-memory fallback, 7-15 unused        */
+  double svd_kind_ms[16];           /* the same split by kernel: entry k < 6 for the    */
+  double svd_kind_flops[16];        /*   Jacobi SVD with 4 (k + 1) vector elements per  */
+                                    /*   lane, 6 its global-memory fallback, 7 the      */
+                                    /*   Householder QR of the centre moves, 8-15 unused */
   double env_kind_ms[8];            /* environment kernels: 0 L x ket GEMM, 1 sparse    */
   double env_kind_flops[8];         /*   channel mix, 2 dense coupling GEMMs, 3 bra^T x */
   double env_kind_bytes[8];         /*   Y GEMM, 4 final element; device time, flops    */
@@ -162,6 +163,11 @@ typedef struct {
   int32_t n_fp32_pairs;             /* pairs contracted in FP32 (precision modes 1, 2)  */
   int32_t reserved[7];
   double ws_peak_bytes;             /* workspace calls: bytes of it actually used       */
+  double move_kernel_ms;            /* device time of the centre-move factorisations    */
+  double move_flops;                /*   and their flops (part of svd_kernel_ms/flops)  */
+  double t_moves_ms;                /* host time issuing the gate phase's centre moves  */
+  int32_t move_launches;            /* centre-move factorisation launches timed         */
+  int32_t reserved2;
 } tnqe_report;
 
 /* Fill defaults (chi = 16, FP64, eps_S = 1e-12, tau_w = 1e-13). */

@@ -52,7 +52,9 @@ class _Report(C.Structure):
                 ("mpo_max_bond", C.c_int32), ("svd_launches", C.c_int32),
                 ("svd_kind_launches", C.c_int32 * 16), ("env_kind_launches", C.c_int32 * 8),
                 ("n_fp32_pairs", C.c_int32),
-                ("reserved", C.c_int32 * 7), ("ws_peak_bytes", C.c_double)]
+                ("reserved", C.c_int32 * 7), ("ws_peak_bytes", C.c_double),
+                ("move_kernel_ms", C.c_double), ("move_flops", C.c_double), ("t_moves_ms", C.c_double),
+                ("move_launches", C.c_int32), ("reserved2", C.c_int32)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
@@ -176,7 +178,7 @@ def workspace_size(prob, ctx=None, **kw):
 def report_dict(r):
     out = {}
     for name, _ in _Report._fields_:
-        if name == "reserved":
+        if name.startswith("reserved"):
             continue
         v = getattr(r, name)
         out[name] = list(v) if isinstance(v, C.Array) else v

@@ -577,10 +577,6 @@ JacobiPlan planned_shape(const Blk &b) {
   return jp;
 }
 
-void plan_block_storage(Blk &b, Scratch &sc) {
-  plan_block(b);
-  take_block_storage(b, sc);
-}
 
 // Algorithmic flops of the SVD of an R x C block (n = min, m = max): the
 // Gram-plus-symmetric-eigensolver count 2 n^2 m + 9 n^3 + 2 n^2 m.
@@ -613,17 +609,22 @@ ThreadPool &host_pool(tnqe_ctx *ctx) {
   return *ctx->pool_threads;
 }
 
-// Device time of timed SVD launches (per kernel), collected after the next
-// stream sync.
+// Device time of timed factorisation launches (per kernel, and per use:
+// truncations or centre moves), collected after the next stream sync.
+constexpr int kQrKind = kJacobiKinds;           // kind index of the Householder QR launches
+constexpr int kFactKinds = kJacobiKinds + 1;
+enum { kCatTrunc = 0, kCatMove = 1 };
 struct SvdTimer {
   static constexpr int kMaxPending = 64;
   int npending = 0;
-  int pending_kind[kMaxPending] = {};
+  int pending_kind[kMaxPending] = {}, pending_cat[kMaxPending] = {};
   double pending_flops[kMaxPending] = {};
   double ms = 0.0, flops = 0.0;
   int launches = 0;
-  double kind_ms[kJacobiKinds] = {}, kind_flops[kJacobiKinds] = {};
-  int kind_launches[kJacobiKinds] = {};
+  double kind_ms[kFactKinds] = {}, kind_flops[kFactKinds] = {};
+  int kind_launches[kFactKinds] = {};
+  double cat_ms[2] = {}, cat_flops[2] = {};
+  int cat_launches[2] = {};
   // waits for the end events of the first `upto` pending launches, adds their
   // times, and moves the later ones (and their events) to the front
   void collect(tnqe_ctx *ctx, int upto = kMaxPending) {
@@ -638,21 +639,40 @@ struct SvdTimer {
       kind_ms[pending_kind[k]] += t;
       kind_flops[pending_kind[k]] += pending_flops[k];
       kind_launches[pending_kind[k]]++;
+      cat_ms[pending_cat[k]] += t;
+      cat_flops[pending_cat[k]] += pending_flops[k];
+      cat_launches[pending_cat[k]]++;
     }
     for (int k = upto; k < npending; ++k) {
       std::swap(ctx->svd_ev[2 * (k - upto)], ctx->svd_ev[2 * k]);
       std::swap(ctx->svd_ev[2 * (k - upto) + 1], ctx->svd_ev[2 * k + 1]);
       pending_kind[k - upto] = pending_kind[k];
+      pending_cat[k - upto] = pending_cat[k];
       pending_flops[k - upto] = pending_flops[k];
     }
     npending -= upto;
+  }
+  // a slot for the next launch, or -1 when all are pending (then untimed)
+  int begin(tnqe_ctx *ctx, hipStream_t s, int kind, int cat, double fl) {
+    if (npending >= kMaxPending) return -1;
+    const int slot = npending;
+    pending_flops[slot] = fl;
+    pending_kind[slot] = kind;
+    pending_cat[slot] = cat;
+    TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot], s));
+    return slot;
+  }
+  void end(tnqe_ctx *ctx, hipStream_t s, int slot) {
+    if (slot < 0) return;
+    TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot + 1], s));
+    npending++;
   }
 };
 
 // Launch the SVDs of all blocks, grouped by kernel and workgroup size; within
 // a launch the largest blocks go first.
 void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_sweeps, double *scratch,
-             SvdTimer *timer = nullptr) {
+             SvdTimer *timer = nullptr, int cat = kCatTrunc, const std::vector<int> *subset = nullptr) {
   static const int kThreadSteps[6] = {64, 128, 256, 512, 768, 1024};
   std::map<std::pair<int, int>, std::vector<int>> groups;   // (kind, threads) -> blocks
   std::map<std::pair<int, int>, int64_t> lds;
@@ -660,7 +680,10 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   static const bool dbg = std::getenv("TNQE_DEBUG_SVD") != nullptr;
   int *dsweeps = dbg ? c.dev<int>(blks.size()) : nullptr;
   std::vector<int64_t> work(blks.size());
-  for (size_t i = 0; i < blks.size(); ++i) {
+  const size_t nsel = subset ? subset->size() : blks.size();
+  if (nsel == 0) return;
+  for (size_t si = 0; si < nsel; ++si) {
+    const size_t i = subset ? (size_t)(*subset)[si] : si;
     const Blk &b = blks[i];
     const int m = std::max(b.R, b.C);
     const JacobiPlan jp = planned_shape(b);
@@ -715,21 +738,15 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
       if (load[i] < load[si]) si = i;
     load[si] += -order[g].first;
     hipStream_t s = ctx->aux[si];
-    const bool timed = timer && timer->npending < SvdTimer::kMaxPending;
-    const int slot = timed ? timer->npending : 0;
-    if (timed) {
+    int slot = -1;
+    if (timer) {
       double f = 0.0;
       for (int i : idx) f += svd_flops(blks[i]);
-      timer->pending_flops[slot] = f;
-      timer->pending_kind[slot] = key.first;
-      TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot], s));
+      slot = timer->begin(ctx, s, key.first, cat, f);
     }
     launch_jacobi(dblk, didx[g], (int)idx.size(), key.first, key.second, (int)lds[key], scratch, max_sweeps,
                   dsweeps, s);
-    if (timed) {
-      TNQE_HIP(hipEventRecord(ctx->svd_ev[2 * slot + 1], s));
-      timer->npending++;
-    }
+    if (timer) timer->end(ctx, s, slot);
   }
   for (int i = 0; i < nstream; ++i) {
     TNQE_HIP(hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
@@ -757,11 +774,44 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   }
 }
 
+// Factorisations of the blocks of a centre move: Householder QR (one
+// workgroup per block, in LDS) for every block that fits, the Jacobi SVD for
+// the rest; blocks carry their choice in Blk::fact (set when planned).
+void plan_move_block(Blk &b) {
+  plan_block(b);
+  b.fact = qr_lds_bytes(b) <= (size_t)kQrLdsBytes ? 1 : 0;
+  if (b.fact) b.offW = -1;
+}
+
+double qr_flops(const Blk &b) {   // factorisation and formation of Q
+  const double m = std::max(b.R, b.C), k = std::min(b.R, b.C);
+  return 4.0 * m * k * k - 4.0 / 3.0 * k * k * k;
+}
+
+void factor_move(Call &c, const Blk *dblk, const std::vector<Blk> &blks, const int *dqr, const std::vector<int> &qr,
+                 const std::vector<int> &svd, bool left, int max_sweeps, double *scratch, SvdTimer *timer) {
+  tnqe_ctx *ctx = c.ctx;
+  if (!qr.empty()) {
+    size_t lds = 0;
+    double fl = 0.0;
+    for (int i : qr) {
+      lds = std::max(lds, qr_lds_bytes(blks[i]));
+      fl += qr_flops(blks[i]);
+    }
+    if (timer && timer->npending >= SvdTimer::kMaxPending) timer->collect(ctx);
+    const int slot = timer ? timer->begin(ctx, ctx->stream, kQrKind, kCatMove, fl) : -1;
+    launch_qr_blocks(dblk, dqr, (int)qr.size(), (int)lds, left, scratch, ctx->stream);
+    if (timer) timer->end(ctx, ctx->stream, slot);
+  }
+  if (!svd.empty()) run_svd(c, dblk, blks, max_sweeps, scratch, timer, kCatMove, &svd);
+}
+
 struct TruncStats {
   std::vector<double> discarded;   // per ket, summed
   double min_gap = 1.0;
   int max_bond = 0;
-  SvdTimer svd;                    // truncation SVDs of the gate steps
+  SvdTimer svd;                    // factorisations of the truncations and centre moves
+  double move_wall_ms = 0.0;       // host time spent issuing centre moves in the gate phase
 };
 
 // One exact LQ centre move (site q -> q-1) for every ket in the set.
@@ -785,7 +835,7 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
       b.aux0 = ks.off_q(q, t, sa, sb);
       b.aux1 = ks.htot[(size_t)q * ks.n + t];
       if (b.C == 0) continue;
-      plan_block(b);
+      plan_move_block(b);
       pblk[t].push_back(b);
     }
   });
@@ -820,7 +870,9 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
   }
   const std::vector<int> u_gather =
       unit_prefix(blks, [](const Blk &b) { return gate_chunks((int64_t)b.R * b.C); });
-  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
+  const std::vector<int> u_factor = unit_prefix(blks, [](const Blk &b) { return b.fact ? 0 : factor_units(b); });
+  std::vector<int> qr, svd;
+  for (size_t i = 0; i < blks.size(); ++i) (blks[i].fact ? qr : svd).push_back((int)i);
   // the new rows of A_q, then the tiles of the left neighbour's products
   // (bond q-1 is not changed by the move)
   const std::vector<int> u_apply = unit_prefix(blks, [&](const Blk &b) {
@@ -831,12 +883,13 @@ void move_left(KetSet &ks, int q, int max_sweeps, SvdTimer *timer) {
   Call::Blob bl;
   const size_t o_old = bl.add(olds), o_blk = bl.add(blks);
   const size_t o_ug = bl.add(u_gather), o_uf = bl.add(u_factor), o_ua = bl.add(u_apply);
+  const size_t o_qr = bl.add(qr);
   char *base = c.upload(bl);
   double **d_old = Call::at<double *>(base, o_old);
   Blk *dblk = Call::at<Blk>(base, o_blk);
   const KetTables kt_old = ks.tables();
   launch_gather_lq(kt_old, q, dblk, units_at(base, o_ug, u_gather), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, max_sweeps, scratch, timer);
+  factor_move(c, dblk, blks, Call::at<const int>(base, o_qr), qr, svd, true, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, c.ctx->stream);
   ks.commit_bond(q);
   // the site table with the swapped buffers, in stream order before the
@@ -868,7 +921,8 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
       b.aux0 = ks.off_q(p + 1, t, sa, sb);
       b.aux1 = ks.htot[(size_t)(p + 1) * ks.n + t];
       if (b.R == 0) continue;
-      plan_block_storage(b, sc);
+      plan_move_block(b);
+      take_block_storage(b, sc);
       blks.push_back(b);
     }
   }
@@ -892,16 +946,18 @@ void move_right(KetSet &ks, int p, int max_sweeps, SvdTimer *timer) {
     srcs[t] = ks.site_ptr[(size_t)t * ks.N + p + 1];
     cnt[t] = (int64_t)ks.htot[(size_t)(p + 1) * ks.n + t] * 4 * ks.htot[(size_t)(p + 2) * ks.n + t];
   }
-  const std::vector<int> u_factor = unit_prefix(blks, factor_units);
+  const std::vector<int> u_factor = unit_prefix(blks, [](const Blk &b) { return b.fact ? 0 : factor_units(b); });
+  std::vector<int> qr, svd;
+  for (size_t i = 0; i < blks.size(); ++i) (blks[i].fact ? qr : svd).push_back((int)i);
   Call::Blob bl;
   const size_t o_old = bl.add(olds), o_src = bl.add(srcs), o_cnt = bl.add(cnt), o_blk = bl.add(blks);
-  const size_t o_uf = bl.add(u_factor);
+  const size_t o_uf = bl.add(u_factor), o_qr = bl.add(qr);
   char *base = c.upload(bl);
   double **d_old = Call::at<double *>(base, o_old);
   launch_copy(d_old, Call::at<double *>(base, o_src), Call::at<int64_t>(base, o_cnt), ks.n, c.ctx->stream);
   Blk *dblk = Call::at<Blk>(base, o_blk);
   launch_gather_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, c.ctx->stream);
-  run_svd(c, dblk, blks, max_sweeps, scratch, timer);
+  factor_move(c, dblk, blks, Call::at<const int>(base, o_qr), qr, svd, false, max_sweeps, scratch, timer);
   launch_svd_factor(dblk, units_at(base, o_uf, u_factor), scratch, c.ctx->stream);
   ks.commit_bond(p + 1);
   launch_apply_qr(ks.tables(), p, dblk, (int)blks.size(), scratch, d_old, c.ctx->stream);
@@ -2041,6 +2097,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       const size_t mk = ctx->pool.mark();
       const auto tm0 = Clock::now();
       // each move's scratch goes back before the next move
+      const auto tmv = Clock::now();
       while (centre > a) {
         const size_t mm = ctx->pool.mark();
         move_left(kets, centre, max_sweeps, &ts.svd);
@@ -2053,6 +2110,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
         ctx->pool.rewind(mm);
         ++centre;
       }
+      ts.move_wall_ms += ms_since(tmv);
       const auto tm1 = Clock::now();
       if (debug_timing() && g > 0) g_gate_timing.caller_ms += ms_between(t_prev_end, tm0);
       for (int t = 0; t < P; ++t) {
@@ -2182,7 +2240,11 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   rep.svd_kernel_ms = ts.svd.ms;
   rep.svd_flops = ts.svd.flops;
   rep.svd_launches = ts.svd.launches;
-  for (int k = 0; k < kJacobiKinds; ++k) {
+  rep.move_kernel_ms = ts.svd.cat_ms[kCatMove];
+  rep.move_flops = ts.svd.cat_flops[kCatMove];
+  rep.move_launches = ts.svd.cat_launches[kCatMove];
+  rep.t_moves_ms = ts.move_wall_ms;
+  for (int k = 0; k < kFactKinds; ++k) {
     rep.svd_kind_ms[k] = ts.svd.kind_ms[k];
     rep.svd_kind_flops[k] = ts.svd.kind_flops[k];
     rep.svd_kind_launches[k] = ts.svd.kind_launches[k];

@@ -68,6 +68,7 @@ struct Blk {
   int grp, mpad;       // Jacobi: lanes per vector pair, padded LDS row length
   int64_t offT, offU, offB, offS;   // scratch offsets (doubles); U is [n][R], B is [n][C]
   int64_t offW;        // work area for blocks too large for LDS (-1: LDS)
+  int fact;            // centre moves: 0 Jacobi SVD, 1 Householder QR
 };
 
 // Per-pair ket state shared with the kernels.
@@ -165,6 +166,18 @@ void launch_gather_lq(const KetTables &kt, int q, const Blk *blk, Units u, doubl
 // the bond q-1 sector that feeds the block through local state k
 void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, Units u, const double *scratch,
                      double *const *old_left, hipStream_t st);
+// Exact centre moves by Householder QR of the gathered blocks idx[0..nblk)
+// of blk (one workgroup each, the block in LDS: qr_lds_bytes(b) <= kQrLdsBytes):
+// left = true factorises T^T (LQ of T, a move to the left), else T.  Writes
+// U [n][R], B [n][C] and S [n] = 1 in the slots the SVD route fills for the
+// apply kernels (U takes L, B takes Q for a left move; U takes Q, B takes R
+// for a right move), so the move kernels apply L (or R) and write Q unscaled.
+constexpr int kQrLdsBytes = 150 * 1024;
+inline size_t qr_lds_bytes(const Blk &b) {
+  return ((size_t)b.R * b.C + (size_t)(b.R < b.C ? b.R : b.C)) * sizeof(double);
+}
+void launch_qr_blocks(const Blk *blk, const int *idx, int nblk, int lds_bytes, bool left, double *scratch,
+                      hipStream_t st);
 void launch_gather_qr(const KetTables &kt, int p, const Blk *blk, int nblk, double *scratch,
                       hipStream_t st);
 void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const double *scratch,

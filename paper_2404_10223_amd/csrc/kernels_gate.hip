@@ -526,6 +526,104 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
   }
 }
 
+
+// Exact centre moves by Householder QR, one workgroup per quantum-number
+// block (App. A1, eq. orth_l / orth_r: a move only regauges the state).  The
+// gathered block T (R x C, row-major) is factorised as X = Q_X R_X with
+// X = T^T for a move to the left (LQ of T: L = R_X^T, rows of Q = Q_X^T) and
+// X = T for a move to the right (QR of T).  X (m x c, k = min(m, c)) sits in
+// LDS column by column; reflector j (H = I - tau v v^T, v_j = 1, LAPACK sign
+// convention) is found by wave 0 and applied to the later columns by all
+// waves, one column per wave at a time with a wave-wide reduction; Q_X is
+// then formed in place from the reflectors (backward accumulation).  Outputs,
+// in the slots the move kernels read: U ([k][R]) and B ([k][C]) take R_X and
+// Q_X^T (left move) or Q_X^T and R_X (right move); the k "singular values"
+// are 1, so the apply kernels multiply by L (R_X) and write Q unscaled.
+constexpr int kQrThreads = 256, kQrWaves = kQrThreads / 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const int *idx, double *scratch,
+                                                          int left) {
+  extern __shared__ __align__(16) double qx[];
+  const Blk &b = stage_block(blks, idx[blockIdx.x]);
+  const int R = b.R, C = b.C;
+  const int m = left ? C : R, c = left ? R : C, k = min(m, c);
+  double *tau = qx + (int64_t)m * c;
+  const double *T = scratch + b.offT;
+  for (int e = threadIdx.x; e < m * c; e += kQrThreads) {
+    const int j = e / m, i = e - j * m;   // X(i, j)
+    qx[e] = left ? T[(int64_t)j * C + i] : T[(int64_t)i * C + j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < k; ++j) {
+    double *x = qx + (int64_t)j * m;
+    if (wave == 0) {
+      double sg = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) sg += x[i] * x[i];
+      sg = wave_sum(sg);
+      const double alpha = x[j];
+      double t = 0.0, beta = alpha, scale = 0.0;
+      if (sg > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sg);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int i = j + 1 + lane; i < m; i += 64) x[i] *= scale;
+      if (lane == 0) {
+        tau[j] = t;
+        x[j] = beta;
+      }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      for (int r = j + 1 + wave; r < c; r += kQrWaves) {
+        double *y = qx + (int64_t)r * m;
+        double w = lane == 0 ? y[j] : 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+        w = wave_sum(w) * tj;
+        if (lane == 0) y[j] -= w;
+        for (int i = j + 1 + lane; i < m; i += 64) y[i] -= w * x[i];
+      }
+    }
+    __syncthreads();
+  }
+  double *Uo = scratch + b.offU, *Bo = scratch + b.offB, *So = scratch + b.offS;
+  double *Rr = left ? Uo : Bo, *Qt = left ? Bo : Uo;
+  for (int e = threadIdx.x; e < k * c; e += kQrThreads) {
+    const int jj = e / c, r = e - jj * c;
+    Rr[e] = r >= jj ? qx[(int64_t)r * m + jj] : 0.0;
+  }
+  for (int e = threadIdx.x; e < k; e += kQrThreads) So[e] = 1.0;
+  __syncthreads();
+  // Q_X (m x k) in place of the first k columns
+  for (int j = k - 1; j >= 0; --j) {
+    double *x = qx + (int64_t)j * m;
+    const double tj = tau[j];
+    for (int r = j + 1 + wave; r < k; r += kQrWaves) {
+      double *y = qx + (int64_t)r * m;
+      double w = lane == 0 ? y[j] : 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      w = wave_sum(w) * tj;
+      if (lane == 0) y[j] -= w;
+      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= w * x[i];
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) x[i] *= -tj;
+    for (int i = threadIdx.x; i < j; i += kQrThreads) x[i] = 0.0;
+    if (threadIdx.x == 0) x[j] = 1.0 - tj;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < k * m; e += kQrThreads) Qt[e] = qx[e];
+}
+
 }  // namespace
 
 void launch_two_site(const KetTables &kt, int a, const Blk *blk, Units ug, const Blk *th, Units ut,
@@ -579,6 +677,18 @@ void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double
   const size_t lds = select_lds_bytes(maxv, kt.nslot);
   hipLaunchKernelGGL(k_select, dim3(nket), dim3(kSelThreads), lds, st, blk, kfirst, maxv, scratch, chi, tau, kt,
                      bond, kept_out, stats, scale);
+}
+
+void launch_qr_blocks(const Blk *blk, const int *idx, int nblk, int lds_bytes, bool left, double *scratch,
+                      hipStream_t st) {
+  if (nblk == 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_qr_blocks),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kQrLdsBytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_qr_blocks, dim3(nblk), dim3(kQrThreads), lds_bytes, st, blk, idx, scratch, left ? 1 : 0);
 }
 
 void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n, hipStream_t st) {
