@@ -128,37 +128,91 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_calibration_bytes": nbytes, "ok": bool(b[0].item() == 1)}))
 
 
-def cpu_baseline(prob, sample_pairs=((0, 1), (1, 2))):
-    """FP64 oracle on a bounded sample: the complete Givens network (centre
-    moves, gates, SVD truncations) of a few off-diagonal pairs."""
-    from oracle import gates as og, givens as ogv, mps as om
+def _host_info():
+    """Host cores this process may use, CPU model, BLAS library and threads."""
+    cores = len(os.sched_getaffinity(0))
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        threads = max((x.get("num_threads") or 1) for x in info) if info else 1
+        blas = [{"api": x.get("user_api"), "library": x.get("internal_api"), "threads": x.get("num_threads")}
+                for x in threadpool_info()]
     except Exception:
-        threads = os.cpu_count()
+        pass
+    return cores, model, blas
+
+
+def cpu_baseline(prob, diag=(0, 0), offd=(0, 1)):
+    """The FP64 oracle on the same scope as the GPU's timed region, on a
+    bounded sample: the MPO of basis i (built once per basis), one diagonal
+    pair (environment sweep) and one off-diagonal pair (centre moves, gates
+    with SVD truncation, environment sweep), and the eigensolve.  The job's
+    time is extrapolated per part: M MPO builds, M diagonal and M (M - 1) / 2
+    off-diagonal elements, one eigensolve.  A plain reference, not a tuned
+    CPU code."""
+    import numpy as np
+    from oracle import gep as ogep
+    from oracle.mpo import build_mpo, expectation
+    from oracle.subspace import rotate_integrals, rotate_ket
+    cores, model, blas = _host_info()
+    i = diag[0]
+    bi = prob.mps[i]
     t0 = time.perf_counter()
-    ngates = 0
-    for (i, j) in sample_pairs:
-        bi, bj = prob.mps[i], prob.mps[j]
-        sites, qn = om.copy_mps(bj.sites, bj.bond_qn)
-        gl, _ = ogv.plan(bi.U.T @ bj.U)
-        centre = om.left_canonicalize(sites, qn)
-        for a, th in gl:
-            centre = om.move_centre(sites, qn, centre, a)
-            om.gate_and_truncate(sites, qn, a, og.g4(th), prob.chi, 1e-13)
-            centre = a + 1
-        ngates += len(gl)
+    hi, Li = rotate_integrals(prob.h, prob.L, bi.U)
+    W = build_mpo(hi, np.einsum("kpq,krs->pqrs", Li, Li))
+    t_mpo = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    expectation(W, bi.sites, bi.bond_qn, bi.sites, bi.bond_qn)
+    t_diag = time.perf_counter() - t0
+    a, b = offd
+    assert a == i
+    bj = prob.mps[b]
+    t0 = time.perf_counter()
+    ket, kqn, _ = rotate_ket(bj.sites, bj.bond_qn, bi.U.T @ bj.U, prob.chi)
+    t_gates = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    expectation(W, bi.sites, bi.bond_qn, ket, kqn)
+    t_env = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(prob.M, prob.M))
+    t0 = time.perf_counter()
+    ogep.solve_projection(A + A.T, A @ A.T + np.eye(prob.M))
+    t_gep = time.perf_counter() - t0
+    M = prob.M
+    n_off, n_pairs = M * (M - 1) // 2, M * (M + 1) // 2
+    total = M * t_mpo + M * t_diag + n_off * (t_gates + t_env) + t_gep
+    sample_s = t_mpo + t_diag + t_gates + t_env + t_gep
+    return {"value": n_pairs / total, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "blas": blas,
+            "sample": f"N={prob.N}, chi={prob.chi}, M={M}: MPO of basis {i} {t_mpo:.1f} s, diagonal pair {diag} "
+                      f"environment sweep {t_diag:.1f} s, off-diagonal pair {offd} Givens network with SVD "
+                      f"truncation {t_gates:.1f} s + environment sweep {t_env:.1f} s, eigensolve {t_gep * 1e3:.2f} ms "
+                      f"({sample_s:.0f} s in all); extrapolated to {M} MPO builds, {M} diagonal and {n_off} "
+                      f"off-diagonal elements: {total:.0f} s for the {n_pairs} elements",
+            "extrapolated_job_s": total}
+
+
+def cpu_single_thread_small():
+    """The oracle's whole pencil for the N = 7, chi = 16, M = 4 workload on one
+    BLAS thread (elements/s)."""
+    import tnqe_synth as synth
+    from oracle.subspace import subspace
+    prob = synth.make_config(2)
+    from threadpoolctl import threadpool_limits
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        subspace(prob)
     dt = time.perf_counter() - t0
-    n_off = prob.M * (prob.M - 1) // 2
-    n_pairs = prob.M * (prob.M + 1) // 2
-    per_pair = dt / len(sample_pairs)
-    value = n_pairs / (per_pair * n_off)       # environment sweeps not counted (favours the CPU)
-    return {"value": value, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"complete Givens networks ({ngates} gates with centre moves and SVD truncation) of pairs "
-                      f"{list(sample_pairs)} at N={prob.N}, chi={prob.chi}: {dt:.1f} s; extrapolated to the "
-                      f"{n_off} off-diagonal pairs; environment sweeps and eigensolve not counted"}
+    n = prob.M * (prob.M + 1) // 2
+    return {"value": n / dt, "unit": "elements/s", "threads": 1,
+            "workload": "N=7, chi=16, M=4 (10 elements), whole pencil with sector-FCI H"}
 
 
 def main():
@@ -224,7 +278,11 @@ def main():
         t32, (H32, S32, E32, c32, rep32) = run(1, "fp32")
         mixed["all_fp32"] = {"ms_per_step": t32 * 1e3, "dE_Ha": abs(E32 - E), "valid": abs(E32 - E) <= 1e-6}
     roof = roofline(rep)
-    cpu = None if args.no_cpu else cpu_baseline(prob)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(prob)
+        cpu["single_thread_small"] = cpu_single_thread_small()
     line = {"metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": t64 * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
