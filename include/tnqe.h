@@ -243,6 +243,29 @@ tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamilto
                                 size_t ws_bytes, double *const *H, double *const *S, double *E,
                                 tnqe_report *rep);
 
+/* The expanded one-hot pencil of one state (Sec. II.E eq. oht_exp and
+ * eq. subs_exp, App. A1, expanding a single reference state i): state i is put
+ * in canonical form centred on sites (p, p+1) (eq. orth_l / orth_r, by exact
+ * QR/LQ with a non-negative diagonal of the triangular factor, which fixes the
+ * gauge); its two-site tensor T[l, k_p, k_{p+1}, r] is expanded over the n
+ * one-hot tensors that conserve the particle numbers, numbered in row-major
+ * order of T, giving the orthonormal one-hot states varphi_m.  Every other
+ * state k is taken into basis i by its Givens network with truncation to chi
+ * (as for the pencil, here for k < i too).  Outputs (host, row-major):
+ *   index [n][4]: (l, k_p, k_{p+1}, r) of one-hot state m;
+ *   Hd, Sd [n][n]: <varphi_m|H|varphi_n>, <varphi_m|varphi_n> (the identity);
+ *   Hc, Sc [n][M]: <varphi_m|H|phi_k>, <varphi_m|phi_k> (column i: phi_i).
+ * H is H^(i) (integrals rotated into basis i), e_core included.
+ * tnqe_onehot_size gives n (host-only; ctx may be NULL); tnqe_onehot_pencil
+ * fails with TNQE_ESHAPE when its n differs.  Device memory from the
+ * context's pool.  rep: t_gates_ms (networks and canonical form), t_env_ms,
+ * env_kernel_ms and env_flops (the one-hot contractions), or NULL. */
+tnqe_status tnqe_onehot_size(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                             const tnqe_options *opts, int32_t i, int32_t p, int32_t *n);
+tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                               const tnqe_options *opts, int32_t i, int32_t p, int32_t n, int32_t *index,
+                               double *Hd, double *Sd, double *Hc, double *Sc, tnqe_report *rep);
+
 /* For callers that cannot allocate memory (code under HIP stream capture,
  * tight serving loops, harnesses that forbid allocation): tnqe_subspace with
  * no workspace argument and no allocation of device or pinned host memory,

@@ -37,6 +37,15 @@ def _where(q, s):
     return np.nonzero((q[:, 0] == s[0]) & (q[:, 1] == s[1]))[0]
 
 
+def _positive_qr(a):
+    """Reduced QR with a non-negative diagonal of R: for a block of full rank
+    this fixes the factors uniquely, so the canonical form (and with it the
+    one-hot states of App. A1) does not depend on the QR routine's signs."""
+    q, r = np.linalg.qr(a)
+    d = np.where(np.diag(r) < 0.0, -1.0, 1.0)
+    return q * d[None, :], r * d[:, None]
+
+
 def _qr_right(sites, qn, p):
     """Exact move of the centre from site p to p+1 (A_p = Q R, R into A_{p+1})."""
     A = sites[p]
@@ -49,7 +58,7 @@ def _qr_right(sites, qn, p):
         rows = _where(rowq, s)
         if len(rows) == 0:
             continue
-        q, r = np.linalg.qr(M[np.ix_(rows, cols)])
+        q, r = _positive_qr(M[np.ix_(rows, cols)])
         qblocks.append((rows, q))
         rblocks.append((cols, r))
         newq += [s] * q.shape[1]
@@ -78,7 +87,7 @@ def _lq_left(sites, qn, p):
         cols = _where(colq, s)
         if len(cols) == 0:
             continue
-        q, r = np.linalg.qr(M[np.ix_(rows, cols)].T)     # M_b = r^T q^T
+        q, r = _positive_qr(M[np.ix_(rows, cols)].T)     # M_b = r^T q^T
         lblocks.append((rows, r.T))
         qblocks.append((cols, q.T))
         newq += [s] * q.shape[1]

@@ -61,7 +61,8 @@ EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "
            "tnqe_problem_free", "tnqe_solve", "tnqe_solve_batch", "tnqe_workspace_size", "tnqe_subspace",
            "tnqe_subspace_batch", "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
            "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool", "tnqe_debug_select",
-           "tnqe_debug_gep", "tnqe_subspace_noalloc", "tnqe_noalloc_capacity"]
+           "tnqe_debug_gep", "tnqe_subspace_noalloc", "tnqe_noalloc_capacity", "tnqe_onehot_size",
+           "tnqe_onehot_pencil"]
 
 _lib = None
 
@@ -100,6 +101,10 @@ def lib():
     L.tnqe_debug_gep.argtypes = [vp, ip, dp, dp, C.c_double, dp]
     L.tnqe_subspace_noalloc.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), dp, dp, dp, dp,
                                         C.POINTER(_Report)]
+    L.tnqe_onehot_size.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), ip, ip,
+                                   C.POINTER(ip)]
+    L.tnqe_onehot_pencil.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), ip, ip, ip,
+                                     C.POINTER(ip), dp, dp, dp, dp, C.POINTER(_Report)]
     L.tnqe_noalloc_capacity.argtypes = []
     L.tnqe_noalloc_capacity.restype = C.c_size_t
     L.tnqe_status_string.argtypes = [C.c_int]
@@ -173,6 +178,15 @@ def workspace_size(prob, ctx=None, **kw):
     h = ctx.h if ctx is not None else None
     _check(lib().tnqe_workspace_size(h, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), C.byref(out)), h)
     return out.value
+
+
+def onehot_size(prob, i, p, **kw):
+    """Number of one-hot states of state i at sites (p, p+1) (host-only)."""
+    pk = _Packed(prob)
+    o = options(**kw)
+    n = C.c_int32(0)
+    _check(lib().tnqe_onehot_size(None, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), int(i), int(p), C.byref(n)))
+    return n.value
 
 
 def report_dict(r):
@@ -258,6 +272,24 @@ class Context:
 
     def workspace_size(self, prob, **kw):
         return workspace_size(prob, self, **kw)
+
+    def onehot_pencil(self, prob, i, p, **kw):
+        """Expanded one-hot pencil of state i at sites (p, p+1): (index [n][4],
+        Hd, Sd [n][n], Hc, Sc [n][M], report)."""
+        pk = _Packed(prob)
+        o = options(**kw)
+        n = C.c_int32(0)
+        _check(self.L.tnqe_onehot_size(self.h, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), int(i), int(p),
+                                       C.byref(n)), self.h)
+        n = n.value
+        index = np.zeros((n, 4), dtype=np.int32)
+        Hd, Sd = np.zeros((n, n)), np.zeros((n, n))
+        Hc, Sc = np.zeros((n, prob.M)), np.zeros((n, prob.M))
+        r = _Report()
+        _check(self.L.tnqe_onehot_pencil(self.h, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), int(i), int(p), n,
+                                         _iptr(index), _dptr(Hd), _dptr(Sd), _dptr(Hc), _dptr(Sc), C.byref(r)),
+               self.h)
+        return index, Hd, Sd, Hc, Sc, report_dict(r)
 
     def subspace_noalloc(self, prob, **kw):
         """tnqe_subspace_noalloc: the library's fixed per-GPU scratch, no allocation."""

@@ -21,6 +21,7 @@
 #include <functional>
 #include <numeric>
 #include <thread>
+#include <tuple>
 
 namespace tnqe {
 
@@ -1945,56 +1946,14 @@ std::vector<int> bond_caps(const tnqe_problem &pb, int chi_cap) {
   return cap;
 }
 
-void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut &out) {
-  Call c{ctx};
-  const auto t0 = Clock::now();
+// The Givens networks of the (basis i, ket j) pairs offd (j != i), all in
+// lock step: canon receives left-canonical copies of all M MPS (centre on the
+// last site) and kets[t] the MPS offd[t].second taken into basis
+// offd[t].first, truncated after every gate (App. A1, App. A3, Sec. II.B).
+void gate_phase(Call &c, tnqe_problem &pb, const std::vector<std::pair<int, int>> &offd, int chi_cap,
+                const tnqe_options &op, int max_sweeps, KetSet &canon, KetSet &kets, TruncStats &ts) {
+  tnqe_ctx *ctx = c.ctx;
   const int N = pb.N, M = pb.M, nslot = pb.nslot();
-  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
-  require(chi_cap >= 1, TNQE_EINVAL, "chi must be >= 1");
-  const int max_sweeps = op.max_sweeps > 0 ? op.max_sweeps : 40;
-  tnqe_report &rep = out.rep;
-  rep = tnqe_report{};
-  // ---- host: integrals, MPO, plans
-  MpoStructure &mpo = mpo_for(ctx, N);
-  const int64_t nnz = mpo.site_nnz_off[N];
-  // the coefficients of all bases go straight into pinned staging memory
-  double *vals = static_cast<double *>(ctx->staging.reserve((size_t)nnz * M * sizeof(double)));
-  {
-    // one basis per host thread: rotated integrals and MPO coefficients
-    const int nth = std::max(1, std::min<int>(M, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    std::vector<std::string> errs(nth);
-    for (int w = 0; w < nth; ++w)
-      pool.emplace_back([&, w] {
-        try {
-          std::vector<double> slotv, v1, hi, gi;
-          for (int i = w; i < M; i += nth) {
-            rotate_integrals(pb, pb.mps[i].U, hi, gi);
-            mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
-            std::copy(v1.begin(), v1.end(), vals + (size_t)i * nnz);
-          }
-        } catch (const std::exception &e) {
-          errs[w] = e.what();
-        }
-      });
-    for (auto &t : pool) t.join();
-    for (auto &e : errs) require(e.empty(), TNQE_EINVAL, e);
-  }
-  double *dvals = c.dev<double>((size_t)nnz * M);
-  TNQE_HIP(hipMemcpyAsync(dvals, vals, (size_t)nnz * M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  std::vector<std::pair<int, int>> pairs;
-  std::vector<int> ket_of_pair;
-  std::vector<std::pair<int, int>> offd;
-  for (int i = 0; i < M; ++i)
-    for (int j = i; j < M; ++j) {
-      pairs.push_back({i, j});
-      if (i == j) {
-        ket_of_pair.push_back(-1);
-      } else {
-        ket_of_pair.push_back((int)offd.size());
-        offd.push_back({i, j});
-      }
-    }
   const int P = (int)offd.size();
   std::vector<std::vector<int>> gpos(P);
   std::vector<std::vector<double>> gth(P);
@@ -2010,16 +1969,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       }
     givens_plan(N, W.data(), gpos[t], gth[t], dsign[t]);
   });
-  rep.t_host_ms = ms_since(t0);
-  // ---- gate phase
-  const auto tg = Clock::now();
-  KetSet kets;
-  TruncStats ts;
   ts.discarded.assign(P, 0.0);
-  if (P > 0) {
+  {
     const std::vector<int> cap = bond_caps(pb, chi_cap);
     // left-canonical copies of every MPS used as a ket
-    KetSet canon;
     canon.init(&c, M, N, pb.na, pb.nb, cap);
     {
       std::vector<double *> dst(M), src(M);
@@ -2046,6 +1999,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
         c.sync();
         ctx->pool.rewind(mk);
       }
+    }
+    if (P == 0) {
+      c.sync();
+      return;
     }
     kets.init(&c, P, N, pb.na, pb.nb, cap);
     {
@@ -2139,6 +2096,65 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       g_gate_timing = GateHostTiming{};
     }
   }
+}
+
+void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut &out) {
+  Call c{ctx};
+  const auto t0 = Clock::now();
+  const int N = pb.N, M = pb.M, nslot = pb.nslot();
+  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
+  require(chi_cap >= 1, TNQE_EINVAL, "chi must be >= 1");
+  const int max_sweeps = op.max_sweeps > 0 ? op.max_sweeps : 40;
+  tnqe_report &rep = out.rep;
+  rep = tnqe_report{};
+  // ---- host: integrals, MPO, plans
+  MpoStructure &mpo = mpo_for(ctx, N);
+  const int64_t nnz = mpo.site_nnz_off[N];
+  // the coefficients of all bases go straight into pinned staging memory
+  double *vals = static_cast<double *>(ctx->staging.reserve((size_t)nnz * M * sizeof(double)));
+  {
+    // one basis per host thread: rotated integrals and MPO coefficients
+    const int nth = std::max(1, std::min<int>(M, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    std::vector<std::string> errs(nth);
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&, w] {
+        try {
+          std::vector<double> slotv, v1, hi, gi;
+          for (int i = w; i < M; i += nth) {
+            rotate_integrals(pb, pb.mps[i].U, hi, gi);
+            mpo_values(mpo, hi.data(), gi.data(), v1, slotv);
+            std::copy(v1.begin(), v1.end(), vals + (size_t)i * nnz);
+          }
+        } catch (const std::exception &e) {
+          errs[w] = e.what();
+        }
+      });
+    for (auto &t : pool) t.join();
+    for (auto &e : errs) require(e.empty(), TNQE_EINVAL, e);
+  }
+  double *dvals = c.dev<double>((size_t)nnz * M);
+  TNQE_HIP(hipMemcpyAsync(dvals, vals, (size_t)nnz * M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> ket_of_pair;
+  std::vector<std::pair<int, int>> offd;
+  for (int i = 0; i < M; ++i)
+    for (int j = i; j < M; ++j) {
+      pairs.push_back({i, j});
+      if (i == j) {
+        ket_of_pair.push_back(-1);
+      } else {
+        ket_of_pair.push_back((int)offd.size());
+        offd.push_back({i, j});
+      }
+    }
+  const int P = (int)offd.size();
+  rep.t_host_ms = ms_since(t0);
+  // ---- gate phase
+  const auto tg = Clock::now();
+  KetSet canon, kets;
+  TruncStats ts;
+  if (P > 0) gate_phase(c, pb, offd, chi_cap, op, max_sweeps, canon, kets, ts);
   rep.t_gates_ms = ms_since(tg);
   // ---- environment sweep
   const auto te = Clock::now();
@@ -2257,6 +2273,321 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   require(std::isfinite(out.E), TNQE_ENONFINITE, "non-finite eigenvalue");
 }
 
+
+// ------------------------------------------------------------ expanded one-hot pencil
+// Bond dimensions per sector of state i after the canonical form used for the
+// expansion: left-canonicalised by exact QR (centre on the last site), then
+// moved by exact LQ to site p (a block of R x C keeps min(R, C) vectors).
+std::vector<std::vector<int>> onehot_dims(const tnqe_problem &pb, int i, int p) {
+  const int N = pb.N, nb1 = pb.nb + 1, nslot = pb.nslot();
+  std::vector<std::vector<int>> d = pb.mps[i].secdim;
+  auto at = [&](int b, int a, int bb) { return (a < 0 || bb < 0 || a > pb.na || bb > pb.nb) ? 0 : d[b][a * nb1 + bb]; };
+  for (int b = 1; b < N; ++b)
+    for (int s = 0; s < nslot; ++s) {
+      const int sa = s / nb1, sb = s % nb1;
+      int R = 0;
+      for (int k = 0; k < 4; ++k) R += at(b - 1, sa - qk_a(k), sb - qk_b(k));
+      d[b][s] = std::min(R, d[b][s]);
+    }
+  for (int q = N - 1; q > p; --q)
+    for (int s = 0; s < nslot; ++s) {
+      const int sa = s / nb1, sb = s % nb1;
+      int C = 0;
+      for (int k = 0; k < 4; ++k) C += at(q + 1, sa + qk_a(k), sb + qk_b(k));
+      d[q][s] = std::min(d[q][s], C);
+    }
+  return d;
+}
+
+// One-hot entries (l, k_p, k_{p+1}, r) of the two-site tensor at (p, p+1)
+// that conserve the particle numbers, in row-major order of T.
+std::vector<int4> onehot_list(const tnqe_problem &pb, const std::vector<std::vector<int>> &d, int p) {
+  const int nb1 = pb.nb + 1, nslot = pb.nslot();
+  std::vector<int> off0(nslot + 1, 0), off2(nslot + 1, 0);
+  for (int s = 0; s < nslot; ++s) {
+    off0[s + 1] = off0[s] + d[p][s];
+    off2[s + 1] = off2[s] + d[p + 2][s];
+  }
+  std::vector<int4> out;
+  for (int s = 0; s < nslot; ++s) {
+    const int sa = s / nb1, sb = s % nb1;
+    for (int l = off0[s]; l < off0[s + 1]; ++l)
+      for (int kp = 0; kp < 4; ++kp)
+        for (int kq = 0; kq < 4; ++kq) {
+          const int a = sa + qk_a(kp) + qk_a(kq), b = sb + qk_b(kp) + qk_b(kq);
+          if (a > pb.na || b > pb.nb) continue;
+          const int s2 = a * nb1 + b;
+          for (int r = off2[s2]; r < off2[s2 + 1]; ++r) out.push_back(make_int4(l, kp, kq, r));
+        }
+  }
+  // sectors are contiguous in every bond, so sorting restores row-major order
+  std::sort(out.begin(), out.end(), [](const int4 &x, const int4 &y) {
+    return std::make_tuple(x.x, x.y, x.z, x.w) < std::make_tuple(y.x, y.y, y.z, y.w);
+  });
+  return out;
+}
+
+struct OneHotOut {
+  std::vector<int4> index;
+  std::vector<double> Hd, Sd, Hc, Sc;
+};
+
+// Expanded pencil of state ei at sites (p, p+1) (App. A1, single expanded
+// state): ei in canonical form centred on p; for every state k the ket is k
+// rotated into basis ei by its Givens network with truncation (k = ei: ei
+// itself); left environments over sites < p and right environments over
+// sites > p + 1 with the dense MPO of H^(ei) (and with the identity for the
+// overlaps), then the two-site blocks.  Every contraction is a matrix-core
+// GEMM (launch_oh_gemm).
+void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei, int p, OneHotOut &out,
+                tnqe_report &rep) {
+  Call c{ctx};
+  const auto t0 = Clock::now();
+  const int N = pb.N, M = pb.M;
+  require(ei >= 0 && ei < M, TNQE_EINVAL, "expanded state out of range");
+  require(p >= 0 && p + 1 < N, TNQE_EINVAL, "two-site position out of range");
+  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
+  const int max_sweeps = op.max_sweeps > 0 ? op.max_sweeps : 40;
+  rep = tnqe_report{};
+  hipStream_t st = ctx->stream;
+  // ---- dense MPO of H^(ei), site by site: W_x[w][w'][k'][k]
+  MpoStructure &mpo = mpo_for(ctx, N);
+  std::vector<double> hi, gi, vals, slotv;
+  rotate_integrals(pb, pb.mps[ei].U, hi, gi);
+  mpo_values(mpo, hi.data(), gi.data(), vals, slotv);
+  std::vector<std::vector<int>> base(N + 1);
+  std::vector<int> D(N + 1, 0);
+  for (int b = 0; b <= N; ++b)
+    for (const MpoClass &cl : mpo.classes[b]) {
+      base[b].push_back(D[b]);
+      D[b] += cl.nw;
+    }
+  std::vector<const double *> dW(N);
+  for (int x = 0; x < N; ++x) {
+    std::vector<double> Wx((size_t)D[x] * D[x + 1] * 16, 0.0);
+    for (const MpoGroup &grp : mpo.groups[x]) {
+      const OpPattern &P = mpo.patterns[grp.pattern];
+      const double *gv = vals.data() + mpo.site_nnz_off[x] + grp.val_off;
+      auto add = [&](int r, int col, double v) {
+        const int64_t wi = base[x][grp.cin] + col, wo = base[x + 1][grp.cout] + r;
+        for (int e = 0; e < P.n; ++e) Wx[((wi * D[x + 1] + wo) * 4 + P.kp[e]) * 4 + P.k[e]] += v * P.f[e];
+      };
+      if (grp.dense) {
+        for (int r = 0; r < grp.nr; ++r)
+          for (int cc = 0; cc < grp.nc; ++cc) add(grp.r0 + r, grp.c0 + cc, gv[(int64_t)r * grp.nc + cc]);
+      } else {
+        for (int r = 0; r + 1 < (int)grp.rowptr.size(); ++r)
+          for (int z = grp.rowptr[r]; z < grp.rowptr[r + 1]; ++z) add(r, grp.col[z], gv[z]);
+      }
+    }
+    dW[x] = c.upload(Wx);
+  }
+  std::vector<double> Wid(16, 0.0);
+  for (int k = 0; k < 4; ++k) Wid[k * 4 + k] = 1.0;
+  const double *dWid = c.upload(Wid);
+  const int wH = base[N][mpo.final_class] + mpo.final_H;
+  const int wIp = base[p][mpo.I_class[p]] + mpo.I_loc[p];
+  // ---- every other state rotated into basis ei; ei centred on p
+  const auto tg = Clock::now();
+  std::vector<std::pair<int, int>> offd;
+  for (int k = 0; k < M; ++k)
+    if (k != ei) offd.push_back({ei, k});
+  const int P = (int)offd.size();
+  KetSet canon, kets;
+  TruncStats ts;
+  gate_phase(c, pb, offd, chi_cap, op, max_sweeps, canon, kets, ts);
+  const std::vector<int> cap = bond_caps(pb, chi_cap);
+  KetSet ci;
+  ci.init(&c, 1, N, pb.na, pb.nb, cap);
+  {
+    std::vector<double *> dst(1), src(1);
+    std::vector<int64_t> cnt(1);
+    for (int x = 0; x < N; ++x) {
+      dst[0] = ci.site_ptr[x];
+      src[0] = canon.site_ptr[(size_t)ei * N + x];
+      cnt[0] = (int64_t)canon.htot[(size_t)x * M + ei] * 4 * canon.htot[(size_t)(x + 1) * M + ei];
+      launch_copy(c.upload(dst), c.upload(src), c.upload(cnt), 1, st);
+    }
+    for (int b = 0; b <= N; ++b) {
+      for (int s2 = 0; s2 < pb.nslot(); ++s2) ci.dim(b, 0, s2) = canon.dim(b, ei, s2);
+      ci.commit_bond(b);
+    }
+    for (int q = N - 1; q > p; --q) {
+      const size_t mm = ctx->pool.mark();
+      move_left(ci, q, max_sweeps, &ts.svd);
+      ctx->pool.rewind(mm);
+    }
+    c.sync();
+  }
+  // the dense contractions below read whole site tensors: clear what lies
+  // outside the quantum-number blocks
+  for (int x = 0; x < N; ++x) {
+    int64_t mx = 0;
+    for (int t = 0; t < P; ++t) mx = std::max<int64_t>(mx, (int64_t)kets.htot[(size_t)x * P + t] * 4 * kets.htot[(size_t)(x + 1) * P + t]);
+    if (P > 0) launch_mask_site(kets.tables(), x, (int)std::min<int64_t>(mx, INT32_MAX), st);
+    launch_mask_site(ci.tables(), x, ci.htot[x] * 4 * ci.htot[x + 1], st);
+  }
+  c.check_launch();
+  c.sync();
+  ts.svd.collect(ctx);
+  rep.t_gates_ms = ms_since(tg);
+  // ---- one-hot entries (the host planned the same dimensions the moves produced)
+  {
+    const std::vector<std::vector<int>> dchk = onehot_dims(pb, ei, p);
+    for (int b : {p, p + 2})
+      for (int s2 = 0; s2 < pb.nslot(); ++s2)
+        require(dchk[b][s2] == ci.dim(b, 0, s2), TNQE_ESHAPE, "canonical bond dimensions differ from the plan");
+  }
+  std::vector<std::vector<int>> dci(N + 1, std::vector<int>(pb.nslot()));
+  for (int b = 0; b <= N; ++b)
+    for (int s2 = 0; s2 < pb.nslot(); ++s2) dci[b][s2] = ci.dim(b, 0, s2);
+  out.index = onehot_list(pb, dci, p);
+  const int n = (int)out.index.size();
+  require(n > 0, TNQE_ESHAPE, "the two-site tensor has no entries in the particle-number sector");
+  const int Dbp = ci.htot[p], Dbm = ci.htot[p + 1], Dbq = ci.htot[p + 2];
+  std::vector<int> dense_of(n), dmap((size_t)Dbp * 16 * Dbq, -1);
+  for (int m = 0; m < n; ++m) {
+    const int4 &e = out.index[m];
+    dense_of[m] = ((e.x * 4 + e.y) * 4 + e.z) * Dbq + e.w;
+    dmap[dense_of[m]] = m;
+  }
+  const int *d_dense = c.upload(dense_of);
+  const int *d_map = c.upload(dmap);
+  const int4 *d_oh = c.upload(out.index);
+  double *dHc = c.dev<double>((size_t)n * M), *dSc = c.dev<double>((size_t)n * M);
+  double *dHd = c.dev<double>((size_t)n * n), *dSd = c.dev<double>((size_t)n * n);
+  (void)Dbm;
+  // ---- environments and blocks, pair by pair
+  const auto te = Clock::now();
+  double flops = 0.0;
+  auto gemm = [&](int kind, int Mm, int Nn, int Kk, const double *A, const double *B, double *C, int d0 = 0,
+                  int d1 = 0, int d2 = 0, const int *map = nullptr) {
+    OhGemm g{};
+    g.kind = kind;
+    g.M = Mm;
+    g.N = Nn;
+    g.K = Kk;
+    g.A = A;
+    g.B = B;
+    g.C = C;
+    g.d0 = d0;
+    g.d1 = d1;
+    g.d2 = d2;
+    g.map = map;
+    g.n_oh = n;
+    launch_oh_gemm(g, st);
+    flops += 2.0 * Mm * Nn * Kk;
+  };
+  TNQE_HIP(hipEventRecord(ctx->ev[2], st));
+  for (int k = 0; k < M; ++k) {
+    const size_t mk = ctx->pool.mark();
+    const int t = k < ei ? k : k - 1;
+    auto ket = [&](int x) -> const double * { return k == ei ? ci.site_ptr[x] : kets.site_ptr[(size_t)t * N + x]; };
+    auto Dk = [&](int b) { return k == ei ? ci.htot[b] : kets.htot[(size_t)b * P + t]; };
+    auto Db = [&](int b) { return ci.htot[b]; };
+    // buffer sizes over the sweep
+    int64_t envmax = 1, xmax = 1;
+    for (int x = 0; x < N; ++x) {
+      envmax = std::max(envmax, (int64_t)D[x] * Db(x) * Dk(x));
+      xmax = std::max(xmax, (int64_t)std::max(D[x], D[x + 1]) * 4 * std::max(Db(x), Db(x + 1)) *
+                                std::max(Dk(x), Dk(x + 1)));
+    }
+    envmax = std::max(envmax, (int64_t)D[N]);
+    double *E0 = c.dev<double>(envmax), *E1 = c.dev<double>(envmax);
+    double *X = c.dev<double>(xmax), *Y = c.dev<double>(xmax);
+    // left environment at bond p
+    {
+      std::vector<double> L0(D[0], 0.0);
+      L0[base[0][mpo.I_class[0]] + mpo.I_loc[0]] = 1.0;
+      c.upload_to(E0, L0.data(), L0.size());
+    }
+    double *Lc = E0, *Ln = E1;
+    for (int x = 0; x < p; ++x) {
+      gemm(kOhPlain, D[x] * Db(x), 4 * Dk(x + 1), Dk(x), Lc, ket(x), X);
+      gemm(kOhWX, D[x + 1] * 4, Db(x) * Dk(x + 1), D[x] * 4, dW[x], X, Y, D[x + 1], Db(x), Dk(x + 1));
+      gemm(kOhBraL, Db(x + 1), D[x + 1] * Dk(x + 1), 4 * Db(x), ci.site_ptr[x], Y, Ln, Db(x), Dk(x + 1));
+      std::swap(Lc, Ln);
+    }
+    double *Lp = c.dev<double>((size_t)D[p] * Db(p) * Dk(p));
+    TNQE_HIP(hipMemcpyAsync(Lp, Lc, sizeof(double) * D[p] * Db(p) * Dk(p), hipMemcpyDeviceToDevice, st));
+    // right environments at bond p + 2: H (boundary: the final H channel) and
+    // the overlap (identity operator)
+    double *Rq[2] = {c.dev<double>((size_t)D[p + 2] * Db(p + 2) * Dk(p + 2)),
+                     c.dev<double>((size_t)Db(p + 2) * Dk(p + 2))};
+    for (int which = 0; which < 2; ++which) {
+      auto Dw = [&](int b) { return which == 0 ? D[b] : 1; };
+      std::vector<double> RN(Dw(N), 0.0);
+      RN[which == 0 ? wH : 0] = 1.0;
+      c.upload_to(E0, RN.data(), RN.size());
+      double *Rc = E0, *Rn = E1;
+      for (int x = N - 1; x >= p + 2; --x) {
+        const double *Wx = which == 0 ? dW[x] : dWid;
+        gemm(kOhPlainBT, Dw(x + 1) * Db(x + 1), Dk(x) * 4, Dk(x + 1), Rc, ket(x), X);
+        gemm(kOhRX2, Dw(x) * 4, Db(x + 1) * Dk(x), Dw(x + 1) * 4, Wx, X, Y, Dw(x + 1));
+        gemm(kOhBraR, Db(x), Dw(x) * Dk(x), 4 * Db(x + 1), ci.site_ptr[x], Y, Rn, Dk(x));
+        std::swap(Rc, Rn);
+      }
+      TNQE_HIP(hipMemcpyAsync(Rq[which], Rc, sizeof(double) * Dw(p + 2) * Db(p + 2) * Dk(p + 2),
+                              hipMemcpyDeviceToDevice, st));
+    }
+    const double *LS = Lp + (int64_t)wIp * Db(p) * Dk(p);
+    // column k: <varphi_m|H|ket> and <varphi_m|ket>
+    const int b0 = Db(p), k0 = Dk(p), k2 = Dk(p + 2), b2 = Db(p + 2);
+    double *Th = c.dev<double>((size_t)4 * k0 * 4 * k2);
+    double *t1 = c.dev<double>((size_t)D[p] * b0 * 16 * k2);
+    double *t2 = c.dev<double>((size_t)D[p + 1] * 4 * b0 * 4 * k2);
+    double *t3 = c.dev<double>((size_t)D[p + 2] * 4 * 4 * b0 * k2);
+    double *VH = c.dev<double>((size_t)b0 * 16 * b2), *VS = c.dev<double>((size_t)b0 * 16 * b2);
+    double *s1 = c.dev<double>((size_t)b0 * 16 * k2);
+    gemm(kOhPlain, 4 * k0, 4 * k2, Dk(p + 1), ket(p), ket(p + 1), Th);
+    gemm(kOhPlain, D[p] * b0, 16 * k2, k0, Lp, Th, t1);
+    gemm(kOhWX, D[p + 1] * 4, b0 * 4 * k2, D[p] * 4, dW[p], t1, t2, D[p + 1], b0, 4 * k2);
+    gemm(kOhA3, D[p + 2] * 4, 4 * b0 * k2, D[p + 1] * 4, dW[p + 1], t2, t3, D[p + 2], b0, k2);
+    gemm(kOhA4, b0 * 16, b2, D[p + 2] * k2, t3, Rq[0], VH, b0, k2, b2);
+    gemm(kOhPlain, b0, 16 * k2, k0, LS, Th, s1);
+    gemm(kOhPlainBT, 16 * b0, b2, k2, s1, Rq[1], VS);
+    launch_oh_gather(VH, VS, pb.e_core, d_dense, n, dHc, M, k, st);
+    launch_oh_gather(VS, nullptr, 0.0, d_dense, n, dSc, M, k, st);
+    if (k == ei) {
+      // diagonal block: L (x) W_p W_{p+1} (x) R over every pair of one-hot entries
+      double *Z1 = c.dev<double>((size_t)D[p] * 16 * D[p + 2] * 16);
+      double *Z2 = c.dev<double>((size_t)b0 * b0 * 256 * D[p + 2]);
+      gemm(kOhD1, D[p] * 16, D[p + 2] * 16, D[p + 1], dW[p], dW[p + 1], Z1, D[p + 1]);
+      gemm(kOhPlainAT, b0 * b0, 256 * D[p + 2], D[p], Lp, Z1, Z2);
+      gemm(kOhD3, b0 * b0 * 256, b2 * b2, D[p + 2], Z2, Rq[0], dHd, b0, D[p + 2], b2, d_map);
+      launch_oh_sd(d_oh, n, LS, b0, Rq[1], b2, pb.e_core, dSd, dHd, st);
+    }
+    c.check_launch();
+    c.sync();
+    ctx->pool.rewind(mk);
+  }
+  TNQE_HIP(hipEventRecord(ctx->ev[3], st));
+  out.Hd.resize((size_t)n * n);
+  out.Sd.resize((size_t)n * n);
+  out.Hc.resize((size_t)n * M);
+  out.Sc.resize((size_t)n * M);
+  TNQE_HIP(hipMemcpyAsync(out.Hd.data(), dHd, out.Hd.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Sd.data(), dSd, out.Sd.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Hc.data(), dHc, out.Hc.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Sc.data(), dSc, out.Sc.size() * 8, hipMemcpyDeviceToHost, st));
+  c.sync();
+  float ms = 0.0f;
+  TNQE_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+  rep.t_env_ms = ms_since(te);
+  rep.env_kernel_ms = ms;
+  rep.env_flops = flops;
+  rep.svd_kernel_ms = ts.svd.ms;
+  rep.svd_flops = ts.svd.flops;
+  rep.alg_flops = flops + ts.svd.flops;
+  rep.max_discarded_weight_sum = 0.0;
+  for (double dd : ts.discarded) rep.max_discarded_weight_sum = std::max(rep.max_discarded_weight_sum, dd);
+  rep.min_rel_gap = ts.min_gap;
+  rep.n_pairs = M;
+  rep.mpo_max_bond = mpo.max_bond;
+  rep.t_total_ms = ms_since(t0);
+  for (double v : out.Hd) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite one-hot element");
+  for (double v : out.Hc) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite one-hot element");
+}
 
 // Upper bound of the device memory one solve takes from its pool (bytes):
 // the problem's site tensors, the MPO coefficients and structure, the two
@@ -2827,6 +3158,60 @@ tnqe_status tnqe_solve(tnqe_ctx *ctx, tnqe_problem *pb, const tnqe_options *opts
   });
   if (st != TNQE_OK) return st;
   copy_out(so, H, S, E, cvec, rep);
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_onehot_size(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                             const tnqe_options *opts, int32_t i, int32_t p, int32_t *n) {
+  if (!ham || !mps || !opts || !n) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  std::unique_ptr<tnqe_ctx> tmp;
+  if (!ctx) {
+    tmp = std::make_unique<tnqe_ctx>();
+    ctx = tmp.get();
+  }
+  int32_t out = 0;
+  tnqe_problem pb;
+  const tnqe_status st = guarded(ctx, [&] {
+    load_problem(ctx, ham, M, mps, &pb);
+    require(i >= 0 && i < M, TNQE_EINVAL, "expanded state out of range");
+    require(p >= 0 && p + 1 < pb.N, TNQE_EINVAL, "two-site position out of range");
+    out = (int32_t)onehot_list(pb, onehot_dims(pb, i, p), p).size();
+  });
+  if (st == TNQE_OK) *n = out;
+  return st;
+}
+
+tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                               const tnqe_options *opts, int32_t i, int32_t p, int32_t n, int32_t *index,
+                               double *Hd, double *Sd, double *Hc, double *Sc, tnqe_report *rep) {
+  if (!ctx || !ham || !mps || !opts || !index || !Hd || !Sd || !Hc || !Sc)
+    return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
+  OneHotOut oh;
+  tnqe_report r{};
+  tnqe_problem pb;
+  tnqe_status st = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    load_problem(ctx, ham, M, mps, &pb);
+    place_sites(ctx, &pb, mps);
+    onehot_one(ctx, pb, *opts, i, p, oh, r);
+    ctx->pool.release_all();
+    require((int)oh.index.size() == n, TNQE_ESHAPE,
+            "n differs from the number of one-hot entries (" + std::to_string(oh.index.size()) + ")");
+  });
+  free_sites(&pb);
+  if (st != TNQE_OK) return st;
+  for (int m = 0; m < n; ++m) {
+    index[4 * m] = oh.index[m].x;
+    index[4 * m + 1] = oh.index[m].y;
+    index[4 * m + 2] = oh.index[m].z;
+    index[4 * m + 3] = oh.index[m].w;
+  }
+  std::memcpy(Hd, oh.Hd.data(), oh.Hd.size() * sizeof(double));
+  std::memcpy(Sd, oh.Sd.data(), oh.Sd.size() * sizeof(double));
+  std::memcpy(Hc, oh.Hc.data(), oh.Hc.size() * sizeof(double));
+  std::memcpy(Sc, oh.Sc.data(), oh.Sc.size() * sizeof(double));
+  if (rep) *rep = r;
   return TNQE_OK;
 }
 

@@ -168,13 +168,14 @@ void launch_apply_lq(const KetTables &kt, int q, const Blk *blk, Units u, const 
                      double *const *old_left, hipStream_t st);
 // Exact centre moves by Householder QR of the gathered blocks idx[0..nblk)
 // of blk (one workgroup each, the block in LDS: qr_lds_bytes(b) <= kQrLdsBytes):
-// left = true factorises T^T (LQ of T, a move to the left), else T.  Writes
+// left = true factorises T^T (LQ of T, a move to the left), else T, with a
+// non-negative diagonal of the triangular factor.  Writes
 // U [n][R], B [n][C] and S [n] = 1 in the slots the SVD route fills for the
 // apply kernels (U takes L, B takes Q for a left move; U takes Q, B takes R
 // for a right move), so the move kernels apply L (or R) and write Q unscaled.
 constexpr int kQrLdsBytes = 150 * 1024;
 inline size_t qr_lds_bytes(const Blk &b) {
-  return ((size_t)b.R * b.C + (size_t)(b.R < b.C ? b.R : b.C)) * sizeof(double);
+  return ((size_t)b.R * b.C + 2 * (size_t)(b.R < b.C ? b.R : b.C)) * sizeof(double);
 }
 void launch_qr_blocks(const Blk *blk, const int *idx, int nblk, int lds_bytes, bool left, double *scratch,
                       hipStream_t st);
@@ -182,6 +183,9 @@ void launch_gather_qr(const KetTables &kt, int p, const Blk *blk, int nblk, doub
                       hipStream_t st);
 void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const double *scratch,
                      double *const *old_right, hipStream_t st);
+// zero the entries of site x outside its quantum-number blocks, every ket of
+// the set (max_elems: the largest site size of the set, for the grid)
+void launch_mask_site(const KetTables &kt, int x, int max_elems, hipStream_t st);
 void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n,
                  hipStream_t st);
 void launch_site_sign(double *const *site, const int *rows, int n, int cols, hipStream_t st);
@@ -288,6 +292,50 @@ void launch_env_final(const EnvGeom &g, int x, const double *const *bra, const T
 
 // FP32 copies of FP64 arrays
 void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st);
+
+// -------------------------------------------------------------- expanded one-hot pencil
+// One FP64 matrix-core GEMM C (M x N) = sum_k A(m, k) B(k, n) of the dense
+// contractions of the one-hot pencil: left and right environment steps with a
+// dense MPO site W[w_in][w_out][k'][k], the two-site blocks, and the dense
+// one-hot matrix.  kind selects how (m, k, n) map to the operands' layouts
+// (d0..d2 are the extra dimensions those maps need):
+//   Plain    A[m K + k]       B[k N + n]        C[m N + n]
+//   PlainBT  A[m K + k]       B[n K + k]        C[m N + n]
+//   PlainAT  A[k M + m]       B[k N + n]        C[m N + n]
+//   WX       m = (wo, ko), k = (wi, ki): A = W[((wi d0 + wo) 4 + ko) 4 + ki],
+//            n = (a, x < d2): B[((wi d1 + a) 4 + ki) d2 + x]            C[m N + n]
+//   BraL     A[k M + m], k = (a, k'), n = (w, b < d1): B[((w 4 + k') d0 + a) d1 + b],
+//            C[((w M) + m) d1 + b]
+//   RX2      A = W[((w d0 + w') 4 + k') 4 + k], m = (w, k'), k = (w', k):
+//            B[(w' N + n) 4 + k]                                        C[m N + n]
+//   BraR     A[m K + k], n = (w, a < d0): B[(w K + k) d0 + a]           C[((w M) + m) d0 + a]
+//   A3       A as WX; n = (kp, l < d1, b < d2), k = (w1, kq2):
+//            B[(w1 4 + kp) (4 d1 d2) + (l 4 + kq2) d2 + b]              C[m N + n]
+//   A4       m = (l, kp, kq), k = (w2, b < d1):
+//            A[(w2 4 + kq) (4 d0 d1) + (kp d0 + l) d1 + b], B[(w2 d2 + n) d1 + b], C[m N + n]
+//   D1       m = (w, kpkp2), k = w1: A[(w d0 + k) 16 + kpkp2]; B[k N + n]; C[m N + n]
+//   D3       m = ((l d0 + l2) 16 + kpkp2) 16 + kqkq2, k = w2:
+//            A[(l d0 + l2) (256 d1) + (kpkp2 d1 + k) 16 + kqkq2]; B[k N + n],
+//            n = (r, r2 < d2); stored to C[map(l, kp, kq, r) n_oh + map(l2, kp2, kq2, r2)]
+//            when both one-hot numbers exist (map: dense T index -> one-hot number or -1)
+enum OhKind { kOhPlain, kOhPlainBT, kOhPlainAT, kOhWX, kOhBraL, kOhRX2, kOhBraR, kOhA3, kOhA4, kOhD1, kOhD3 };
+struct OhGemm {
+  int kind, M, N, K;
+  const double *A, *B;
+  double *C;
+  int d0, d1, d2;
+  const int *map;
+  int n_oh;
+};
+void launch_oh_gemm(const OhGemm &g, hipStream_t st);
+// out[m ld + col] = V[idx[m]] (+ f S[idx[m]] when S is not null), m < n
+void launch_oh_gather(const double *V, const double *S, double f, const int *idx, int n, double *out, int ld, int col,
+                      hipStream_t st);
+// diagonal overlap block from the overlap environments and the one-hot
+// tuples oh[m] = (l, kp, kq, r): Sd[m][n] = [kp, kq equal] LS[l][l2] RS[r][r2]
+// (LS [Db][Db], RS [Db2][Db2]); Hd += e_core Sd
+void launch_oh_sd(const int4 *oh, int n, const double *LS, int Db, const double *RS, int Db2, double e_core,
+                  double *Sd, double *Hd, hipStream_t st);
 
 // -------------------------------------------------------------- eigensolve
 // For each subspace s: H, S at offs[s] ([M_s][M_s] row-major); writes

@@ -388,6 +388,121 @@ __global__ void k_cast(const double *const *src, float *const *dst, const int64_
     dst[i][e] = (float)src[i][e];
 }
 
+
+// ------------------------------------------------------------ one-hot pencil
+// Dense contractions of the expanded one-hot pencil (App. A1): the index maps
+// of each kind are listed with OhGemm.
+__device__ inline double oh_la(const OhGemm &g, int m, int k) {
+  switch (g.kind) {
+    case kOhPlainAT:
+    case kOhBraL:
+      return g.A[(int64_t)k * g.M + m];
+    case kOhWX:
+    case kOhA3: {
+      const int wo = m >> 2, ko = m & 3, wi = k >> 2, ki = k & 3;
+      return g.A[(((int64_t)wi * g.d0 + wo) * 4 + ko) * 4 + ki];
+    }
+    case kOhRX2: {
+      const int w = m >> 2, kp = m & 3, w2 = k >> 2, kk = k & 3;
+      return g.A[(((int64_t)w * g.d0 + w2) * 4 + kp) * 4 + kk];
+    }
+    case kOhA4: {
+      const int l = m >> 4, kp = (m >> 2) & 3, kq = m & 3, w2 = k / g.d1, b = k - w2 * g.d1;
+      return g.A[((int64_t)w2 * 4 + kq) * (4 * (int64_t)g.d0 * g.d1) + ((int64_t)kp * g.d0 + l) * g.d1 + b];
+    }
+    case kOhD1:
+      return g.A[((int64_t)(m >> 4) * g.d0 + k) * 16 + (m & 15)];
+    case kOhD3: {
+      const int ll2 = m >> 8, kpkp2 = (m >> 4) & 15, kqkq2 = m & 15;
+      return g.A[(int64_t)ll2 * (256 * (int64_t)g.d1) + ((int64_t)kpkp2 * g.d1 + k) * 16 + kqkq2];
+    }
+    default:   // Plain, PlainBT, BraR
+      return g.A[(int64_t)m * g.K + k];
+  }
+}
+
+__device__ inline double oh_lb(const OhGemm &g, int k, int n) {
+  switch (g.kind) {
+    case kOhPlainBT:
+      return g.B[(int64_t)n * g.K + k];
+    case kOhWX: {
+      const int wi = k >> 2, ki = k & 3, a = n / g.d2, x = n - a * g.d2;
+      return g.B[(((int64_t)wi * g.d1 + a) * 4 + ki) * g.d2 + x];
+    }
+    case kOhBraL: {
+      const int a = k >> 2, kp = k & 3, w = n / g.d1, b = n - w * g.d1;
+      return g.B[(((int64_t)w * 4 + kp) * g.d0 + a) * g.d1 + b];
+    }
+    case kOhRX2:
+      return g.B[((int64_t)(k >> 2) * g.N + n) * 4 + (k & 3)];
+    case kOhBraR: {
+      const int w = n / g.d0, a = n - w * g.d0;
+      return g.B[((int64_t)w * g.K + k) * g.d0 + a];
+    }
+    case kOhA3: {
+      const int w1 = k >> 2, kq2 = k & 3, kp = n / (g.d1 * g.d2), rest = n - kp * g.d1 * g.d2;
+      const int l = rest / g.d2, b = rest - l * g.d2;
+      return g.B[((int64_t)w1 * 4 + kp) * (4 * (int64_t)g.d1 * g.d2) + ((int64_t)l * 4 + kq2) * g.d2 + b];
+    }
+    case kOhA4: {
+      const int w2 = k / g.d1, b = k - w2 * g.d1;
+      return g.B[((int64_t)w2 * g.d2 + n) * g.d1 + b];
+    }
+    default:   // Plain, PlainAT, D1, D3
+      return g.B[(int64_t)k * g.N + n];
+  }
+}
+
+__device__ inline void oh_st(const OhGemm &g, int m, int n, double v) {
+  switch (g.kind) {
+    case kOhBraL: {
+      const int w = n / g.d1, b = n - w * g.d1;
+      g.C[((int64_t)w * g.M + m) * g.d1 + b] = v;
+      return;
+    }
+    case kOhBraR: {
+      const int w = n / g.d0, a = n - w * g.d0;
+      g.C[((int64_t)w * g.M + m) * g.d0 + a] = v;
+      return;
+    }
+    case kOhD3: {
+      const int ll2 = m >> 8, kp = (m >> 6) & 3, kp2 = (m >> 4) & 3, kq = (m >> 2) & 3, kq2 = m & 3;
+      const int l = ll2 / g.d0, l2 = ll2 - l * g.d0, r = n / g.d2, r2 = n - r * g.d2;
+      const int row = g.map[(((int64_t)l * 4 + kp) * 4 + kq) * g.d2 + r];
+      const int col = g.map[(((int64_t)l2 * 4 + kp2) * 4 + kq2) * g.d2 + r2];
+      if (row >= 0 && col >= 0) g.C[(int64_t)row * g.n_oh + col] = v;
+      return;
+    }
+    default:
+      g.C[(int64_t)m * g.N + n] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_oh_gemm(OhGemm g) {
+  const int tilesN = (g.N + 63) / 64;
+  const int m0 = (blockIdx.x / tilesN) * 64, n0 = (blockIdx.x % tilesN) * 64;
+  tile_gemm_mfma<double, 64, 64, 1>(
+      g.M, g.N, m0, n0, 1, [&](int) { return g.K; }, [&](int, int m, int k) { return oh_la(g, m, k); },
+      [&](int, int k, int n) { return oh_lb(g, k, n); }, [&](int m, int n, double v) { oh_st(g, m, n, v); });
+}
+
+__global__ void k_oh_gather(const double *V, const double *S, double f, const int *idx, int n, double *out, int ld,
+                            int col) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  out[(int64_t)m * ld + col] = V[idx[m]] + (S ? f * S[idx[m]] : 0.0);
+}
+
+__global__ void k_oh_sd(const int4 *oh, int n, const double *LS, int Db, const double *RS, int Db2, double e_core,
+                        double *Sd, double *Hd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int4 a = oh[e / n], b = oh[e % n];
+  const double v = (a.y == b.y && a.z == b.z) ? LS[(int64_t)a.x * Db + b.x] * RS[(int64_t)a.w * Db2 + b.w] : 0.0;
+  Sd[e] = v;
+  Hd[e] += e_core * v;
+}
+
 }  // namespace
 
 #define TNQE_TILE_SWITCH(KERNEL, T, tileM, tileN, grid, ...)                                   \
@@ -442,6 +557,27 @@ void launch_env_final(const EnvGeom &g, int x, const double *const *bra, const T
                       int nk, int nw, double *out, int npair, hipStream_t st) {
   if (npair == 0) return;
   hipLaunchKernelGGL(k_env_final<T>, dim3(npair), dim3(256), 0, st, g, x, bra, Y, fin, nk, nw, out);
+}
+
+void launch_oh_gemm(const OhGemm &g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return;
+  const int64_t tiles = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
+  if (tiles >= (int64_t)1 << 31) throw Error(TNQE_ESHAPE, "one-hot contraction too large");
+  hipLaunchKernelGGL(k_oh_gemm, dim3((unsigned)tiles), dim3(256), 0, st, g);
+}
+
+void launch_oh_gather(const double *V, const double *S, double f, const int *idx, int n, double *out, int ld, int col,
+                      hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_oh_gather, dim3((n + 255) / 256), dim3(256), 0, st, V, S, f, idx, n, out, ld, col);
+}
+
+void launch_oh_sd(const int4 *oh, int n, const double *LS, int Db, const double *RS, int Db2, double e_core,
+                  double *Sd, double *Hd, hipStream_t st) {
+  const int64_t tot = (int64_t)n * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_oh_sd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, oh, n, LS, Db, RS, Db2, e_core,
+                     Sd, Hd);
 }
 
 void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st) {

@@ -535,7 +535,8 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 // LDS column by column; reflector j (H = I - tau v v^T, v_j = 1, LAPACK sign
 // convention) is found by wave 0 and applied to the later columns by all
 // waves, one column per wave at a time with a wave-wide reduction; Q_X is
-// then formed in place from the reflectors (backward accumulation).  Outputs,
+// then formed in place from the reflectors (backward accumulation), with
+// signs that make diag(R_X) non-negative.  Outputs,
 // in the slots the move kernels read: U ([k][R]) and B ([k][C]) take R_X and
 // Q_X^T (left move) or Q_X^T and R_X (right move); the k "singular values"
 // are 1, so the apply kernels multiply by L (R_X) and write Q unscaled.
@@ -597,9 +598,14 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
   }
   double *Uo = scratch + b.offU, *Bo = scratch + b.offB, *So = scratch + b.offS;
   double *Rr = left ? Uo : Bo, *Qt = left ? Bo : Uo;
+  // signs that make the diagonal of R_X non-negative (for a block of full
+  // rank this fixes the factors, and with them the canonical form, uniquely)
+  double *sgn = tau + k;
+  for (int jj = threadIdx.x; jj < k; jj += kQrThreads) sgn[jj] = qx[(int64_t)jj * m + jj] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
   for (int e = threadIdx.x; e < k * c; e += kQrThreads) {
     const int jj = e / c, r = e - jj * c;
-    Rr[e] = r >= jj ? qx[(int64_t)r * m + jj] : 0.0;
+    Rr[e] = r >= jj ? sgn[jj] * qx[(int64_t)r * m + jj] : 0.0;
   }
   for (int e = threadIdx.x; e < k; e += kQrThreads) So[e] = 1.0;
   __syncthreads();
@@ -621,7 +627,31 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
     if (threadIdx.x == 0) x[j] = 1.0 - tj;
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < k * m; e += kQrThreads) Qt[e] = qx[e];
+  for (int e = threadIdx.x; e < k * m; e += kQrThreads) Qt[e] = sgn[e / m] * qx[e];
+}
+
+
+// Entries of site x outside its quantum-number blocks set to zero, for every
+// ket of the set (kernels that address a site by block never read them; a
+// dense contraction does).  grid: (chunks, kets).
+__global__ void k_mask_site(KetTables kt, int x) {
+  const int pair = blockIdx.y;
+  const int Dl = kt.dim(x, pair), Dr = kt.dim(x + 1, pair);
+  double *A = kt.site[pair * kt.N + x];
+  const int64_t tot = (int64_t)Dl * 4 * Dr;
+  const int2 *tl = kt.btab + ((int64_t)x * kt.npair + pair) * kt.nslot;
+  const int2 *tr = kt.btab + ((int64_t)(x + 1) * kt.npair + pair) * kt.nslot;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e / (4 * Dr)), k = (int)((e / Dr) & 3), r = (int)(e % Dr);
+    int sl = -1, sr = -1;
+    for (int q = 0; q < kt.nslot; ++q) {
+      if (l >= tl[q].x && l < tl[q].x + tl[q].y) sl = q;
+      if (r >= tr[q].x && r < tr[q].x + tr[q].y) sr = q;
+    }
+    const int nb1 = kt.nb + 1;
+    const bool ok = sl >= 0 && sr >= 0 && sr / nb1 == sl / nb1 + qk_a(k) && sr % nb1 == sl % nb1 + qk_b(k);
+    if (!ok) A[e] = 0.0;
+  }
 }
 
 }  // namespace
@@ -689,6 +719,12 @@ void launch_qr_blocks(const Blk *blk, const int *idx, int nblk, int lds_bytes, b
     attr_set = true;
   }
   hipLaunchKernelGGL(k_qr_blocks, dim3(nblk), dim3(kQrThreads), lds_bytes, st, blk, idx, scratch, left ? 1 : 0);
+}
+
+void launch_mask_site(const KetTables &kt, int x, int max_elems, hipStream_t st) {
+  if (kt.npair == 0 || max_elems <= 0) return;
+  const int chunks = std::min(1024, (max_elems + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_mask_site, dim3(chunks, kt.npair), dim3(kThreads), 0, st, kt, x);
 }
 
 void launch_copy(double *const *dst, double *const *src, const int64_t *count, int n, hipStream_t st) {

@@ -300,6 +300,13 @@ void mpo_build_structure(int N, MpoStructure &m) {
     }
     m.max_bond = std::max<int>(m.max_bond, (int)n);
   }
+  m.I_class.assign(N + 1, 0);
+  m.I_loc.assign(N + 1, 0);
+  for (int b = 0; b <= N; ++b) {
+    const int wI = chan[b].at(key_of(T_I, 0, 0));
+    m.I_class[b] = cls_of[b][wI];
+    m.I_loc[b] = loc_of[b][wI];
+  }
   {
     const int wI = chan[N].at(key_of(T_I, 0, 0)), wH = chan[N].at(key_of(T_H, 0, 0));
     if (cls_of[N][wI] != cls_of[N][wH] || m.classes[N].size() != 1 || m.classes[N][0].nw != 2)

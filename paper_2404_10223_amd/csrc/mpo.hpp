@@ -46,6 +46,7 @@ struct MpoStructure {
   std::vector<int> term_slot;                   // per term, in enumeration order
   std::vector<double> term_factor;              // sort sign x 1 or 1/2
   int final_class = 0, final_H = 0, final_I = 0;
+  std::vector<int> I_class, I_loc;              // per bond: class and index of the channel I
   int max_bond = 0;
   std::vector<int64_t> site_nnz, site_nnz_off;  // CSR sizes per site and offsets
 };

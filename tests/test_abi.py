@@ -123,3 +123,17 @@ def test_workspace_size_host_only(lib):
     assert e.value.status == -3
     with pytest.raises(T.TnqeError):
         T.workspace_size(p1, chi=0)
+
+
+def test_onehot_size_matches_oracle(lib):
+    """Number of one-hot states of the expanded pencil (host-only) against the
+    oracle's enumeration of the particle-number-conserving entries."""
+    from oracle.onehot import onehot_pencil
+    for k, i, p in [(1, 1, 1), (2, 2, 3), (2, 0, 0), (2, 3, 5)]:
+        prob = synth.make_config(k)
+        assert T.onehot_size(prob, i, p, chi=prob.chi) == len(onehot_pencil(prob, i, p)[0])
+    prob = synth.make_config(1)
+    with pytest.raises(T.TnqeError):
+        T.onehot_size(prob, 2, 0, chi=4)
+    with pytest.raises(T.TnqeError):
+        T.onehot_size(prob, 0, 3, chi=4)
