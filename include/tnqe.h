@@ -128,7 +128,9 @@ typedef struct {
   int32_t autotune;          /* 1: environment tile shapes from the context's tuned
                                 table (measured on first use, cached on disk); 0: the
                                 fixed shape rule                                       */
-  int32_t reserved[5];
+  int32_t workers;           /* batch calls (read from the first subspace's options):
+                                subspaces solved concurrently (0: default, 4)          */
+  int32_t reserved[4];
 } tnqe_options;
 
 typedef struct {
@@ -166,6 +168,7 @@ typedef struct {
   double move_kernel_ms;            /* device time of the centre-move factorisations    */
   double move_flops;                /*   and their flops (part of svd_kernel_ms/flops)  */
   double t_moves_ms;                /* host time issuing the gate phase's centre moves  */
+  double t_tune_ms;                 /* autotuning of tile shapes during the call        */
   int32_t move_launches;            /* centre-move factorisation launches timed         */
   int32_t reserved2;
 } tnqe_report;

@@ -35,7 +35,8 @@ class _Mps(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("chi_cap_override", C.c_int32), ("precision", C.c_int32),
                 ("eps_S", C.c_double), ("tau_w", C.c_double), ("max_sweeps", C.c_int32),
-                ("renormalize", C.c_int32), ("autotune", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("renormalize", C.c_int32), ("autotune", C.c_int32), ("workers", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class _Report(C.Structure):
@@ -54,7 +55,7 @@ class _Report(C.Structure):
                 ("n_fp32_pairs", C.c_int32),
                 ("reserved", C.c_int32 * 7), ("ws_peak_bytes", C.c_double),
                 ("move_kernel_ms", C.c_double), ("move_flops", C.c_double), ("t_moves_ms", C.c_double),
-                ("move_launches", C.c_int32), ("reserved2", C.c_int32)]
+                ("t_tune_ms", C.c_double), ("move_launches", C.c_int32), ("reserved2", C.c_int32)]
 
 
 EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "tnqe_upload",
@@ -146,7 +147,7 @@ def _check(st, ctx=None):
 
 
 def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-13, max_sweeps=40,
-            renormalize=False, autotune=False):
+            renormalize=False, autotune=False, workers=0):
     o = _Opts()
     lib().tnqe_default_options(C.byref(o))
     o.chi = chi
@@ -157,6 +158,7 @@ def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-
     o.max_sweeps = max_sweeps
     o.renormalize = int(bool(renormalize))
     o.autotune = int(bool(autotune))
+    o.workers = int(workers)
     return o
 
 

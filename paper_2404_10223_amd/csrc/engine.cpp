@@ -21,6 +21,8 @@
 #include <functional>
 #include <numeric>
 #include <thread>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <tuple>
 
 namespace tnqe {
@@ -605,7 +607,8 @@ bool debug_timing() {
 ThreadPool &host_pool(tnqe_ctx *ctx) {
   if (!ctx->pool_threads) {
     const int hw = (int)std::thread::hardware_concurrency();
-    ctx->pool_threads = std::make_unique<ThreadPool>(std::max(0, std::min(15, hw - 1)));
+    const int n = ctx->host_workers >= 0 ? ctx->host_workers : std::max(0, std::min(15, hw - 1));
+    ctx->pool_threads = std::make_unique<ThreadPool>(n);
   }
   return *ctx->pool_threads;
 }
@@ -1194,7 +1197,7 @@ enum { kEnvG1 = 0, kEnvMix = 1, kEnvDense = 2, kEnvG2 = 3, kEnvFinal = 4, kEnvKi
 
 struct EnvResult {
   std::vector<double> H, S;   // per env pair
-  double flops = 0.0, bytes = 0.0, kernel_ms = 0.0;
+  double flops = 0.0, bytes = 0.0, kernel_ms = 0.0, tune_ms = 0.0;
   double kind_ms[kEnvKinds] = {}, kind_flops[kEnvKinds] = {}, kind_bytes[kEnvKinds] = {};
   int kind_launches[kEnvKinds] = {};
   int max_pad = 0;
@@ -1432,10 +1435,48 @@ void plan_env_layout(const MpoStructure &mpo, const MpoDevice *mdev, int N, int 
 // rotated kets; pair q contracts bra item pairs[q].first with its ket item.
 // Block slots are sized by the largest dimensions over the items (one
 // descriptor list for all pairs); the kernels use each pair's own extents.
+// Tuned tile shapes: a text file of lines "kind bytes lgM lgN lgW tileM tileN"
+// (TNQE_TUNE_FILE, else $HOME/.cache/tnqe_env_tiles.txt).
+std::string tune_file() {
+  if (const char *f = std::getenv("TNQE_TUNE_FILE")) return f;
+  const char *h = std::getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/tnqe_env_tiles.txt";
+}
+
+void load_tiles(tnqe_ctx *ctx) {
+  if (ctx->tiles_loaded) return;
+  ctx->tiles_loaded = true;
+  FILE *f = std::fopen(tune_file().c_str(), "r");
+  if (!f) return;
+  int v[7];
+  while (std::fscanf(f, "%d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]) == 7)
+    ctx->tiles[{v[0], v[1], v[2], v[3], v[4]}] = {v[5], v[6]};
+  std::fclose(f);
+}
+
+void save_tiles(const tnqe_ctx *ctx) {
+  const std::string path = tune_file(), tmp = path + ".tmp" + std::to_string((long)getpid());
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;   // the cache is an optimisation: an unwritable path is not an error
+  for (const auto &kv : ctx->tiles)
+    std::fprintf(f, "%d %d %d %d %d %d %d\n", kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4],
+                 kv.second.first, kv.second.second);
+  std::fclose(f);
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+int ceil_log2(double v) {
+  int l = 0;
+  while ((double)(1ll << l) < v && l < 62) ++l;
+  return l;
+}
+
 template <typename T>
 void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
                const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
-               int64_t nnz_total, EnvResult &res) {
+               int64_t nnz_total, EnvResult &res, bool autotune = false) {
   hipStream_t st = c.ctx->stream;
   const auto tq0 = Clock::now();
   const int N = pb.N, M = pb.M, nslot = pb.nslot(), nbond = N + 1;
@@ -1687,6 +1728,99 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       }
       dbra[x] = c.upload(bp);
       dket[x] = c.upload(kp);
+    }
+    // autotuning (first batch, common layout): each environment GEMM list
+    // whose shape class has no tuned tile yet is timed with every tile shape
+    // on this batch's buffers (their contents are not used yet: the real
+    // sweep overwrites every output afterwards); the fastest is kept
+    if (autotune && p0 == 0 && !own_layouts) {
+      const auto tt0 = Clock::now();
+      load_tiles(c.ctx);
+      static const int cand[5][2] = {{256, 16}, {128, 32}, {64, 64}, {32, 128}, {16, 256}};
+      auto tiles = [](int64_t Mm, int64_t Nn, int tm, int tn) {
+        return (Mm <= 0 || Nn <= 0) ? (int64_t)0 : ((Mm + tm - 1) / tm) * ((Nn + tn - 1) / tn);
+      };
+      bool added = false;
+      for (int x = 0; x < N; ++x)
+        for (int kind = 0; kind < 2; ++kind) {
+          if (kind == 1 && x == N - 1) continue;
+          EnvSiteTabs &tb = lay.tabs[x];
+          const int nd = kind == 0 ? (int)tb.g1.size() : (int)tb.g2.size();
+          if (nd == 0) continue;
+          auto extent = [&](int di, int q, int64_t &Mm, int64_t &Nn) {
+            if (kind == 0) {
+              const EnvG1 &d = tb.g1[di];
+              Mm = (int64_t)idim(bra_item[q], x, d.sbra) * d.nw;
+              Nn = idim(ket_item[q], x + 1, d.sk);
+            } else {
+              const EnvG2 &d = tb.g2[di];
+              Mm = idim(bra_item[q], x + 1, d.sbn);
+              Nn = (int64_t)d.nw * idim(ket_item[q], x + 1, d.s);
+            }
+          };
+          int64_t maxM = 1, maxN = 1;
+          double work = 1.0;
+          for (int di = 0; di < nd; ++di)
+            for (int q = 0; q < nb_; ++q) {
+              int64_t Mm, Nn;
+              extent(di, q, Mm, Nn);
+              maxM = std::max(maxM, Mm);
+              maxN = std::max(maxN, Nn);
+              work += (double)Mm * Nn;
+            }
+          const std::array<int, 5> key = {kind, (int)sizeof(T), ceil_log2((double)maxM), ceil_log2((double)maxN),
+                                          ceil_log2(work)};
+          auto it = c.ctx->tiles.find(key);
+          if (it == c.ctx->tiles.end()) {
+            float best = 1e30f;
+            std::pair<int, int> pick = {64, 64};
+            for (const auto &cd : cand) {
+              std::vector<EnvWork> list;
+              int nwg = 0;
+              for (int di = 0; di < nd; ++di)
+                for (int q = 0; q < nb_; ++q) {
+                  int64_t Mm, Nn;
+                  extent(di, q, Mm, Nn);
+                  const int64_t cnt = tiles(Mm, Nn, cd[0], cd[1]);
+                  if (cnt <= 0) continue;
+                  require(nwg + cnt < (int64_t)1 << 31, TNQE_ESHAPE, "environment launch exceeds the grid limit");
+                  list.push_back(EnvWork{di, q, nwg});
+                  nwg += (int)cnt;
+                }
+              const EnvWork *dl = c.upload(list);
+              auto launch = [&] {
+                if (kind == 0)
+                  launch_env_g1<T>(ds[x].g1, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dL0, dket[x], dX, st);
+                else
+                  launch_env_g2<T>(ds[x].g2, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dbra[x], dY, dL1, st);
+              };
+              launch();
+              TNQE_HIP(hipEventRecord(e0, st));
+              for (int rep = 0; rep < 3; ++rep) launch();
+              TNQE_HIP(hipEventRecord(e1, st));
+              c.check_launch();
+              TNQE_HIP(hipEventSynchronize(e1));
+              float ms = 0.0f;
+              TNQE_HIP(hipEventElapsedTime(&ms, e0, e1));
+              if (ms < best) {
+                best = ms;
+                pick = {cd[0], cd[1]};
+              }
+            }
+            it = c.ctx->tiles.emplace(key, pick).first;
+            added = true;
+          }
+          if (kind == 0) {
+            tb.tm1 = it->second.first;
+            tb.tn1 = it->second.second;
+          } else {
+            tb.tm2 = it->second.first;
+            tb.tn2 = it->second.second;
+          }
+        }
+      c.sync();
+      if (added) save_tiles(c.ctx);
+      res.tune_ms += ms_since(tt0);
     }
     const auto tb0 = Clock::now();
     // work lists of the batch: only the tiles (chunks) inside every pair's
@@ -2160,7 +2294,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   const auto te = Clock::now();
   EnvResult er;
   if (op.precision == TNQE_ENV_FP32) {
-    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
+    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune != 0);
     rep.n_fp32_pairs = (int)pairs.size();
   } else if (op.precision == TNQE_ENV_MIXED) {
     // FP32 for pairs whose rotated ket kept at most kMixedNorm2 of its squared
@@ -2182,10 +2316,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     }
     EnvResult e64, e32;
     const size_t me = ctx->pool.mark();
-    if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64);
+    if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64, op.autotune != 0);
     c.sync();
     ctx->pool.rewind(me);
-    if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32);
+    if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32, op.autotune != 0);
     er.H.assign(pairs.size(), 0.0);
     er.S.assign(pairs.size(), 0.0);
     for (size_t q = 0; q < q64.size(); ++q) {
@@ -2197,6 +2331,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       er.S[q32[q]] = e32.S[q];
     }
     er.flops = e64.flops + e32.flops;
+    er.tune_ms = e64.tune_ms + e32.tune_ms;
     er.bytes = e64.bytes + e32.bytes;
     er.kernel_ms = e64.kernel_ms + e32.kernel_ms;
     er.max_pad = std::max(e64.max_pad, e32.max_pad);
@@ -2208,7 +2343,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     }
     rep.n_fp32_pairs = (int)p32.size();
   } else {
-    env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er);
+    env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune != 0);
   }
   rep.t_env_ms = ms_since(te);
   // ---- pencil and eigensolve
@@ -2260,6 +2395,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   rep.move_flops = ts.svd.cat_flops[kCatMove];
   rep.move_launches = ts.svd.cat_launches[kCatMove];
   rep.t_moves_ms = ts.move_wall_ms;
+  rep.t_tune_ms = er.tune_ms;
   for (int k = 0; k < kFactKinds; ++k) {
     rep.svd_kind_ms[k] = ts.svd.kind_ms[k];
     rep.svd_kind_flops[k] = ts.svd.kind_flops[k];
@@ -2971,6 +3107,67 @@ tnqe_status subspace_call(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M,
   return st;
 }
 
+// Independent subspaces run concurrently: up to kBatchWorkers worker
+// contexts on the same device, each with its own stream (default priority),
+// side streams, device pool and two host helper threads, take subspaces in
+// decreasing order of estimated cost; the GPU is shared by their launches.
+// tnqe_options.workers of the first subspace, else TNQE_BATCH_WORKERS, sets
+// the count (1: one after another).
+constexpr int kBatchWorkers = 4;
+
+int batch_workers(int n, const tnqe_options &o) {
+  static const int env = [] {
+    const char *e = std::getenv("TNQE_BATCH_WORKERS");
+    return e ? std::max(1, std::atoi(e)) : kBatchWorkers;
+  }();
+  return std::max(1, std::min(n, o.workers > 0 ? o.workers : env));
+}
+
+tnqe_ctx *worker(tnqe_ctx *ctx, int w) {
+  while ((int)ctx->sub.size() <= w) {
+    tnqe_ctx *sw = nullptr;
+    if (tnqe_create(&sw, ctx->device, nullptr) != TNQE_OK) throw Error(TNQE_EHIP, "cannot create a batch worker");
+    if (hipStreamCreateWithFlags(&sw->own_stream, hipStreamNonBlocking) != hipSuccess) {
+      tnqe_destroy(sw);
+      throw Error(TNQE_EHIP, "cannot create a batch worker stream");
+    }
+    sw->stream = sw->own_stream;
+    sw->host_workers = 2;
+    ctx->sub.push_back(sw);
+  }
+  return ctx->sub[w];
+}
+
+// Runs run(worker context, worker index, s) for s in order (cost-sorted by
+// the caller) on W workers; returns each subspace's status.  The workers'
+// streams first wait for work queued on the caller's stream.
+std::vector<tnqe_status> run_batch(tnqe_ctx *ctx, const std::vector<int> &order, int W,
+                                   const std::function<tnqe_status(tnqe_ctx *, int, int)> &run) {
+  const int n = (int)order.size();
+  std::vector<tnqe_status> st(n, TNQE_OK);
+  if (n == 0) return st;
+  std::vector<tnqe_ctx *> ws(W);
+  TNQE_HIP(hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int w = 0; w < W; ++w) {
+    ws[w] = worker(ctx, w);
+    TNQE_HIP(hipStreamWaitEvent(ws[w]->stream, ctx->fork_ev, 0));
+  }
+  std::atomic<int> next{0};
+  auto body = [&](int w) {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+      const int q = next.fetch_add(1);
+      if (q >= n) return;
+      st[order[q]] = run(ws[w], w, order[q]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < W; ++w) th.emplace_back(body, w);
+  body(0);
+  for (auto &t : th) t.join();
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3053,6 +3250,8 @@ tnqe_status tnqe_create(tnqe_ctx **out, int device, void *stream) {
 
 tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
   if (!ctx) return TNQE_EINVAL;
+  for (tnqe_ctx *w : ctx->sub) tnqe_destroy(w);
+  ctx->sub.clear();
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto &e : ctx->ev)
@@ -3069,6 +3268,10 @@ tnqe_status tnqe_destroy(tnqe_ctx *ctx) {
   if (ctx->sel_ev) (void)hipEventDestroy(ctx->sel_ev);
   if (ctx->sv_host) (void)hipHostFree(ctx->sv_host);
   for (auto &e : ctx->env_ev) (void)hipEventDestroy(e);
+  if (ctx->own_stream) {
+    (void)hipStreamSynchronize(ctx->own_stream);
+    (void)hipStreamDestroy(ctx->own_stream);
+  }
   delete ctx;
   return TNQE_OK;
 }
@@ -3219,9 +3422,37 @@ tnqe_status tnqe_solve_batch(tnqe_ctx *ctx, int32_t n, tnqe_problem *const *prob
                              double *const *H, double *const *S, double *E, tnqe_report *rep) {
   if (!ctx || !probs || !opts || !H || !S || !E || n < 0) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
   for (int s = 0; s < n; ++s) {
-    tnqe_status st = tnqe_solve(ctx, probs[s], opts + s, H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
-    if (st != TNQE_OK) return st;
+    if (!probs[s] || !H[s] || !S[s]) return fail(ctx, TNQE_EINVAL, "null argument");
+    if (check_options(ctx, opts + s) != TNQE_OK) return TNQE_EINVAL;
   }
+  std::vector<SolveOut> outs(n);
+  std::vector<std::string> errs(n);
+  std::vector<tnqe_status> st;
+  const tnqe_status st0 = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int s = 0; s < n; ++s) {
+      order[s] = s;
+      const tnqe_problem &pb = *probs[s];
+      const double chi = opts[s].chi_cap_override > 0 ? opts[s].chi_cap_override : opts[s].chi;
+      cost[s] = (double)pb.N * pb.N * pb.M * pb.M * chi * chi * chi;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    st = run_batch(ctx, order, batch_workers(n, opts[0]), [&](tnqe_ctx *w, int, int s) {
+      const tnqe_status r = guarded(w, [&] {
+        TNQE_HIP(hipSetDevice(w->device));
+        solve_one(w, *probs[s], opts[s], outs[s]);
+        w->pool.release_all();
+      });
+      if (r != TNQE_OK) errs[s] = w->last_error;
+      return r;
+    });
+  });
+  if (st0 != TNQE_OK) return st0;
+  for (int s = 0; s < n; ++s)
+    if (st[s] != TNQE_OK) return fail(ctx, st[s], "subspace " + std::to_string(s) + ": " + errs[s]);
+  for (int s = 0; s < n; ++s) copy_out(outs[s], H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
   return TNQE_OK;
 }
 
@@ -3262,13 +3493,40 @@ tnqe_status tnqe_subspace_batch(tnqe_ctx *ctx, int32_t n_sub, const tnqe_hamilto
     if (check_options(ctx, opts + s) != TNQE_OK) return TNQE_EINVAL;
   }
   std::vector<SolveOut> outs(n_sub);
-  for (int s = 0; s < n_sub; ++s) {
-    const tnqe_status st = subspace_call(ctx, ham + s, M[s], mps[s], opts + s, workspace, ws_bytes, false, outs[s]);
-    if (st != TNQE_OK) {
-      ctx->last_error = "subspace " + std::to_string(s) + ": " + ctx->last_error;
-      return st;
+  std::vector<std::string> errs(n_sub);
+  std::vector<tnqe_status> st;
+  const tnqe_status st0 = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    // costs (host-side bounds and estimates) and the worker count: with a
+    // workspace, each worker takes an equal part that holds the largest bound
+    std::vector<int> order(n_sub);
+    std::vector<double> cost(n_sub);
+    size_t need = 0;
+    for (int s = 0; s < n_sub; ++s) {
+      order[s] = s;
+      tnqe_problem pb;
+      load_problem(ctx, ham + s, M[s], mps[s], &pb);
+      const double chi = opts[s].chi_cap_override > 0 ? opts[s].chi_cap_override : opts[s].chi;
+      cost[s] = (double)pb.N * pb.N * pb.M * pb.M * chi * chi * chi;
+      if (workspace) need = std::max(need, workspace_bound(ctx, pb, opts[s]));
     }
-  }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int W = batch_workers(n_sub, opts[0]);
+    size_t part = 0;
+    if (workspace) {
+      W = (int)std::max<size_t>(1, std::min<size_t>(W, ws_bytes / std::max<size_t>(need, 1)));
+      part = (ws_bytes / W) & ~size_t(255);
+    }
+    st = run_batch(ctx, order, W, [&](tnqe_ctx *w, int wi, int s) {
+      void *ws = workspace ? static_cast<char *>(workspace) + (size_t)wi * part : nullptr;
+      const tnqe_status r = subspace_call(w, ham + s, M[s], mps[s], opts + s, ws, workspace ? part : 0, false, outs[s]);
+      if (r != TNQE_OK) errs[s] = w->last_error;
+      return r;
+    });
+  });
+  if (st0 != TNQE_OK) return st0;
+  for (int s = 0; s < n_sub; ++s)
+    if (st[s] != TNQE_OK) return fail(ctx, st[s], "subspace " + std::to_string(s) + ": " + errs[s]);
   for (int s = 0; s < n_sub; ++s) copy_out(outs[s], H[s], S[s], E + s, nullptr, rep ? rep + s : nullptr);
   return TNQE_OK;
 }

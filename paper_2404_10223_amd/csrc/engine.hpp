@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <condition_variable>
 #include <functional>
@@ -157,6 +158,16 @@ struct tnqe_ctx {
   hipEvent_t fork_ev = nullptr, join_ev[kAux] = {};
   std::vector<hipEvent_t> env_ev;   // per-launch timing of the environment kernels (grown on demand)
   std::unique_ptr<tnqe::ThreadPool> pool_threads;   // created on first use
+  int host_workers = -1;            // threads of pool_threads (-1: one per core, at most 15)
+  // tuned tile shapes of the environment GEMMs: (kernel, element bytes, log2
+  // of the largest M and N, log2 of the work) -> (tile M, tile N); read from
+  // and written to a file on first use of autotuning
+  std::map<std::array<int, 5>, std::pair<int, int>> tiles;
+  bool tiles_loaded = false;
+  // contexts of the batch workers (same device, each with a stream of its
+  // own), created on first use and destroyed with this context
+  std::vector<tnqe_ctx *> sub;
+  hipStream_t own_stream = nullptr; // a worker's stream (destroyed with it)
 };
 
 struct tnqe_problem {

@@ -407,3 +407,49 @@ def test_mixed_precision_full_size(ctx):
     relS = np.abs(Sm - S)[off] / np.abs(S)[off]
     print(f"mixed FP32 elements: max_rel_dH={relH.max():.2e} max_rel_dS={relS.max():.2e}", flush=True)
     assert relH.max() < 1e-3 and relS.max() < 1e-3
+
+
+def test_autotuned_tiles(ctx, tmp_path, monkeypatch):
+    """Tile shapes of the environment GEMMs picked by timing (autotune = 1),
+    cached on disk: the same pencil bit for bit (the K order of every output
+    does not depend on the tile), and a second call tunes nothing."""
+    monkeypatch.setenv("TNQE_TUNE_FILE", str(tmp_path / "tiles.txt"))
+    c = T.Context(0)
+    try:
+        prob = synth.make_config(3)
+        H0, S0, E0, _, _ = c.subspace(prob, chi=prob.chi)
+        H1, S1, E1, _, r1 = c.subspace(prob, chi=prob.chi, autotune=True)
+        lines = (tmp_path / "tiles.txt").read_text().split("\n")
+        assert r1["t_tune_ms"] > 0 and len([x for x in lines if x.strip()]) > 0
+        np.testing.assert_array_equal(H1, H0)
+        np.testing.assert_array_equal(S1, S0)
+        H2, S2, E2, _, r2 = c.subspace(prob, chi=prob.chi, autotune=True)
+        assert r2["t_tune_ms"] < 0.2 * r1["t_tune_ms"]
+        np.testing.assert_array_equal(H2, H0)
+        c2 = T.Context(0)          # a new context reads the cached table
+        try:
+            H3, _, _, _, r3 = c2.subspace(prob, chi=prob.chi, autotune=True)
+            assert r3["t_tune_ms"] < 0.2 * r1["t_tune_ms"]
+            np.testing.assert_array_equal(H3, H0)
+        finally:
+            c2.close()
+    finally:
+        c.close()
+
+
+def test_batch_concurrent_equals_sequential(ctx):
+    """Concurrent subspaces (worker contexts on their own streams) give the
+    same pencils as one after another."""
+    probs = synth.make_batch()[:12]
+    ups = [ctx.upload(p) for p in probs]
+    try:
+        Hs1, Ss1, Es1, _ = ctx.solve_batch(ups, [p.chi for p in probs], workers=1)
+        Hs4, Ss4, Es4, _ = ctx.solve_batch(ups, [p.chi for p in probs], workers=4)
+    finally:
+        for u in ups:
+            u.free()
+    for a, b in zip(Hs1, Hs4):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(Ss1, Ss4):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(Es1, Es4)
