@@ -82,10 +82,23 @@ typedef enum {
   TNQE_FP64 = 0,         /* everything in FP64                                      */
   TNQE_ENV_FP32 = 1,     /* environment sweep in FP32 (FP64 gates, SVD, final sum,
                             eigensolve); the element sum is compensated FP64        */
-  TNQE_ENV_MIXED = 2     /* per pair: FP32 environments where the rotated ket keeps
+  TNQE_ENV_MIXED = 2,    /* per pair: FP32 environments where the rotated ket keeps
                             at most 1e-6 of its squared norm (the element and its
                             FP32 rounding error are then bounded by the ket norm),
                             FP64 for every other pair (all diagonal pairs)          */
+  TNQE_ENV_FP32_SHIFT = 3, /* every pair in FP32 on the shifted operator H - c N,
+                            c N_e = the FP64 element H_00 (one FP64 pair): FP32
+                            rounding then acts on O(spread) values instead of
+                            O(|E|); the eigenproblem of (H - c N_e S, S) gives
+                            E - c N_e exactly in exact arithmetic; H is returned
+                            as H' + c N_e S (FP32-level absolute error)         */
+  TNQE_ENV_BF16 = 4,     /* as TNQE_ENV_FP32_SHIFT, the environment GEMMs on the
+                            BF16 matrix cores (operands rounded to BF16, FP32
+                            accumulation and storage)                            */
+  TNQE_ENV_BF16X3 = 5    /* as TNQE_ENV_FP32_SHIFT, each GEMM operand split into
+                            BF16 hi + lo and the product taken as three BF16
+                            matrix-core products (hi hi + hi lo + lo hi), FP32
+                            accumulation and storage                             */
 } tnqe_precision;
 
 /* Hamiltonian in the reference orbital basis.  All host pointers, row-major,

@@ -18,7 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libtnqe.so")
 TNQE_FP64 = 0
 TNQE_ENV_FP32 = 1
 TNQE_ENV_MIXED = 2
-PRECISIONS = {"fp64": TNQE_FP64, "fp32": TNQE_ENV_FP32, "mixed": TNQE_ENV_MIXED}
+TNQE_ENV_FP32_SHIFT = 3
+TNQE_ENV_BF16 = 4
+TNQE_ENV_BF16X3 = 5
+PRECISIONS = {"fp64": TNQE_FP64, "fp32": TNQE_ENV_FP32, "mixed": TNQE_ENV_MIXED, "fp32_shift": TNQE_ENV_FP32_SHIFT,
+              "bf16": TNQE_ENV_BF16, "bf16x3": TNQE_ENV_BF16X3}
 
 
 class _Ham(C.Structure):

@@ -1476,7 +1476,7 @@ int ceil_log2(double v) {
 template <typename T>
 void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
                const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
-               int64_t nnz_total, EnvResult &res, bool autotune = false) {
+               int64_t nnz_total, EnvResult &res, bool autotune = false, int cm = 0) {
   hipStream_t st = c.ctx->stream;
   const auto tq0 = Clock::now();
   const int N = pb.N, M = pb.M, nslot = pb.nslot(), nbond = N + 1;
@@ -1768,8 +1768,8 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               maxN = std::max(maxN, Nn);
               work += (double)Mm * Nn;
             }
-          const std::array<int, 5> key = {kind, (int)sizeof(T), ceil_log2((double)maxM), ceil_log2((double)maxN),
-                                          ceil_log2(work)};
+          const std::array<int, 5> key = {kind, (int)sizeof(T) + 100 * cm, ceil_log2((double)maxM),
+                                          ceil_log2((double)maxN), ceil_log2(work)};
           auto it = c.ctx->tiles.find(key);
           if (it == c.ctx->tiles.end()) {
             float best = 1e30f;
@@ -1790,9 +1790,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
               const EnvWork *dl = c.upload(list);
               auto launch = [&] {
                 if (kind == 0)
-                  launch_env_g1<T>(ds[x].g1, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dL0, dket[x], dX, st);
+                  launch_env_g1<T>(ds[x].g1, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dL0, dket[x], dX, st, cm);
                 else
-                  launch_env_g2<T>(ds[x].g2, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dbra[x], dY, dL1, st);
+                  launch_env_g2<T>(ds[x].g2, dl, (int)list.size(), nwg, cd[0], cd[1], geom, dbra[x], dY, dL1, st, cm);
               };
               launch();
               TNQE_HIP(hipEventRecord(e0, st));
@@ -1918,7 +1918,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       const EnvSiteTabs &tb = ctabs[x];
       const SiteWork &w = sw[x];
       tick(kEnvG1);
-      launch_env_g1<T>(cds[x].g1, dw[x].g1, (int)w.g1.size(), w.n1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, st);
+      launch_env_g1<T>(cds[x].g1, dw[x].g1, (int)w.g1.size(), w.n1, tb.tm1, tb.tn1, geom, Lc, dket[x], dX, st, cm);
       MixArgs ma{};
       ma.tasks = cds[x].tasks;
       ma.work = dw[x].mix;
@@ -1935,11 +1935,11 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
         tick(kEnvDense);
         launch_env_gd<T>(cds[x].dense[lv], dw[x].dense[lv], (int)w.dense[lv].size(), w.nd[lv], tb.tmd[lv],
-                         tb.tnd[lv], geom, dvptr, dX, dY, st);
+                         tb.tnd[lv], geom, dvptr, dX, dY, st, cm);
       }
       if (x < N - 1) {
         tick(kEnvG2);
-        launch_env_g2<T>(cds[x].g2, dw[x].g2, (int)w.g2.size(), w.n2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, st);
+        launch_env_g2<T>(cds[x].g2, dw[x].g2, (int)w.g2.size(), w.n2, tb.tm2, tb.tn2, geom, dbra[x], dY, Ln, st, cm);
         std::swap(Lc, Ln);
       } else {
         tick(kEnvFinal);
@@ -2293,8 +2293,40 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   // ---- environment sweep
   const auto te = Clock::now();
   EnvResult er;
+  double shift_total = 0.0;   // c N_e of the shifted FP32 mode
   if (op.precision == TNQE_ENV_FP32) {
     env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune != 0);
+    rep.n_fp32_pairs = (int)pairs.size();
+  } else if (op.precision == TNQE_ENV_FP32_SHIFT || op.precision == TNQE_ENV_BF16 ||
+             op.precision == TNQE_ENV_BF16X3) {
+    const int cm = op.precision == TNQE_ENV_BF16 ? 1 : op.precision == TNQE_ENV_BF16X3 ? 2 : 0;
+    // reference energy: the FP64 element of pair (0, 0)
+    {
+      EnvResult e0;
+      const size_t me = ctx->pool.mark();
+      const std::vector<std::pair<int, int>> p0 = {{0, 0}};
+      const std::vector<int> k0 = {-1};
+      env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p0, k0, mpo, dvals, nnz, e0, op.autotune != 0);
+      c.sync();
+      ctx->pool.rewind(me);
+      shift_total = e0.H[0];
+    }
+    // coefficients of H - c N in every basis: the one-electron diagonal moves
+    // by -c (the basis change is orthogonal, so the same c in every basis);
+    // the coefficient map is affine in (h, g), so the move is c times the
+    // values of (h = 1, g = 0) minus those of (0, 0)
+    const int ne = pb.na + pb.nb;
+    const double cpe = ne > 0 ? shift_total / ne : 0.0;
+    if (ne == 0) shift_total = 0.0;
+    std::vector<double> hI((size_t)N * N, 0.0), h0((size_t)N * N, 0.0), g0((size_t)N * N * N * N, 0.0), vI, v0, sv;
+    for (int p = 0; p < N; ++p) hI[(size_t)p * N + p] = 1.0;
+    mpo_values(mpo, hI.data(), g0.data(), vI, sv);
+    mpo_values(mpo, h0.data(), g0.data(), v0, sv);
+    for (size_t j = 0; j < vI.size(); ++j) vI[j] -= v0[j];
+    double *dvs = c.dev<double>((size_t)nnz * M);
+    launch_shift_vals(dvals, c.upload(vI), -cpe, nnz, M, dvs, ctx->stream);
+    c.check_launch();
+    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvs, nnz, er, op.autotune != 0, cm);
     rep.n_fp32_pairs = (int)pairs.size();
   } else if (op.precision == TNQE_ENV_MIXED) {
     // FP32 for pairs whose rotated ket kept at most kMixedNorm2 of its squared
@@ -2350,6 +2382,8 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   const auto tq = Clock::now();
   out.H.assign((size_t)M * M, 0.0);
   out.S.assign((size_t)M * M, 0.0);
+  // the eigenproblem runs on the pencil as computed (shifted by -c N_e S in
+  // the shifted FP32 mode: same eigenvectors, eigenvalue moved by -c N_e)
   for (size_t q = 0; q < pairs.size(); ++q) {
     const int i = pairs[q].first, j = pairs[q].second;
     const double h = er.H[q] + pb.e_core * er.S[q];
@@ -2370,12 +2404,19 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   c.sync();
   rep.t_gep_ms = ms_since(tq);
   require(go[5] == 0.0, TNQE_ESINGULAR, "S has no eigenvalue above the threshold");
-  out.E = go[0];
+  out.E = go[0] + shift_total;
   out.c.assign(go.begin() + 8, go.begin() + 8 + M);
   rep.cond_S = go[1];
   rep.lambda_min_S = go[2];
   rep.n_dropped = (int)go[3];
   rep.kappa1 = go[4];
+  if (shift_total != 0.0) {
+    // back to H: H' + c N_e S; kappa_1 of the unshifted eigenvalue (App. A2)
+    for (int x = 0; x < M * M; ++x) out.H[x] += shift_total * out.S[x];
+    double cc = 0.0;
+    for (double v : out.c) cc += v * v;
+    rep.kappa1 = cc / std::sqrt(out.E * out.E + 1.0);
+  }
   rep.max_discarded_weight_sum = 0.0;
   for (double d : ts.discarded) rep.max_discarded_weight_sum = std::max(rep.max_discarded_weight_sum, d);
   rep.min_rel_gap = ts.min_gap;
@@ -3057,7 +3098,7 @@ void free_sites(tnqe_problem *pb) {
 }
 
 tnqe_status check_options(tnqe_ctx *ctx, const tnqe_options *o) {
-  if (o->precision != TNQE_FP64 && o->precision != TNQE_ENV_FP32 && o->precision != TNQE_ENV_MIXED)
+  if (o->precision < TNQE_FP64 || o->precision > TNQE_ENV_BF16X3)
     return fail(ctx, TNQE_EINVAL, "unknown precision mode");
   if ((o->chi_cap_override > 0 ? o->chi_cap_override : o->chi) < 1) return fail(ctx, TNQE_EINVAL, "chi must be >= 1");
   return TNQE_OK;

@@ -237,16 +237,21 @@ struct EnvFinal {
   int64_t offY;
 };
 
-// tileM x tileN output tiles; work[0..nwork) covers nwg workgroups
+// tileM x tileN output tiles; work[0..nwork) covers nwg workgroups.  cm
+// (FP32 storage only) selects the matrix-core arithmetic: 0 FP32, 1 BF16
+// operands, 2 split BF16 (hi hi + hi lo + lo hi); FP32 accumulation.
 template <typename T>
 void launch_env_g1(const EnvG1 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st);
+                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st,
+                   int cm = 0);
 template <typename T>
 void launch_env_g2(const EnvG2 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st);
+                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st,
+                   int cm = 0);
 template <typename T>
 void launch_env_gd(const EnvGD *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st);
+                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st,
+                   int cm = 0);
 
 // channel mix: Y[c', s, k'] = sum over sources of coef * X[c, s_in, k].
 // One source of a task: a sparse MPO group (CSR over output x input channel,
@@ -290,6 +295,10 @@ template <typename T>
 void launch_env_final(const EnvGeom &g, int x, const double *const *bra, const T *const *Y, const EnvFinal *fin,
                       int nk, int nw, double *out, int npair, hipStream_t st);
 
+// MPO coefficients of every basis moved along a fixed direction:
+// y[b][j] = x[b][j] + a z[j], b < nbasis, j < nnz
+void launch_shift_vals(const double *x, const double *z, double a, int64_t nnz, int nbasis, double *y,
+                       hipStream_t st);
 // FP32 copies of FP64 arrays
 void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st);
 

@@ -46,6 +46,19 @@ template <> struct Mfma<float> {
   __device__ static int row(int r, int q) { return 4 * q + r; }
 };
 
+// BF16 compute on FP32 operands (CM = 1: the operands rounded to BF16; CM = 2:
+// each operand split as hi + lo, hi = bf16(x), lo = bf16(x - hi), and the
+// product taken as hi hi + hi lo + lo hi), FP32 accumulation, one
+// v_mfma_f32_16x16x16_bf16 per product and K chunk of 16: lane i + 16 q takes
+// A[i][4 q .. 4 q + 3] and B[4 q .. 4 q + 3][i]; accumulator rows as for the
+// FP32 instruction (D[4 q + r][j] in lane j + 16 q).
+typedef short v4s __attribute__((ext_vector_type(4)));
+__device__ inline unsigned short bf16_bits(float x) {   // round to nearest even
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
 // Matrix-core tile (FP64 or FP32, V): the TM x TN tile (m0, n0) of sum over
 // segments of A_q B_q, 256 threads = 4 waves, each wave a (TM / WM) x
 // (TN / WN) sub-tile of 16 x 16 blocks accumulated by the 16 x 16 x 4
@@ -53,8 +66,9 @@ template <> struct Mfma<float> {
 // lb(q, k, n) load the operands of segment q (K of segment q: kq(q));
 // sc(m, n, v) stores.  The loads of the next K chunk are issued before the
 // current chunk's products.
-template <typename V, int TM, int TN, int NSEG, class KQ, class LA, class LB, class SC>
+template <typename V, int TM, int TN, int NSEG, int CM = 0, class KQ, class LA, class LB, class SC>
 __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA la, LB lb, SC sc) {
+  static_assert(CM == 0 || std::is_same<V, float>::value, "BF16 compute takes FP32 operands");
   constexpr int KC = 16;
   typedef typename Mfma<V>::Acc Acc;
   constexpr int WM = TM == TN ? 2 : (TM > TN ? 4 : 1), WN = 4 / WM;
@@ -107,17 +121,50 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
       }
       __syncthreads();
       if (k0 + KC < K) fetch(q, K, k0 + KC);
+      if constexpr (CM == 0) {
 #pragma unroll
-      for (int ks = 0; ks < KC; ks += 4) {
-        V a[BI], b[BJ];
+        for (int ks = 0; ks < KC; ks += 4) {
+          V a[BI], b[BJ];
 #pragma unroll
-        for (int i = 0; i < BI; ++i) a[i] = sA[ks + lk][wm + 16 * i + li];
+          for (int i = 0; i < BI; ++i) a[i] = sA[ks + lk][wm + 16 * i + li];
 #pragma unroll
-        for (int j = 0; j < BJ; ++j) b[j] = sB[ks + lk][wn + 16 * j + li];
+          for (int j = 0; j < BJ; ++j) b[j] = sB[ks + lk][wn + 16 * j + li];
+#pragma unroll
+          for (int i = 0; i < BI; ++i)
+#pragma unroll
+            for (int j = 0; j < BJ; ++j) acc[i][j] = Mfma<V>::step(a[i], b[j], acc[i][j]);
+        }
+      } else {
+        v4s ah[BI], bh[BJ], al[BI], bl[BJ];
 #pragma unroll
         for (int i = 0; i < BI; ++i)
 #pragma unroll
-          for (int j = 0; j < BJ; ++j) acc[i][j] = Mfma<V>::step(a[i], b[j], acc[i][j]);
+          for (int e = 0; e < 4; ++e) {
+            const float x = sA[4 * lk + e][wm + 16 * i + li];
+            const unsigned short h = bf16_bits(x);
+            ah[i][e] = (short)h;
+            al[i][e] = (short)bf16_bits(x - bf16_value(h));
+          }
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float x = sB[4 * lk + e][wn + 16 * j + li];
+            const unsigned short h = bf16_bits(x);
+            bh[j][e] = (short)h;
+            bl[j][e] = (short)bf16_bits(x - bf16_value(h));
+          }
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j) {
+            v4f c = acc[i][j];
+            if constexpr (CM == 2) {
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], c, 0, 0, 0);
+            }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], c, 0, 0, 0);
+          }
       }
       __syncthreads();
     }
@@ -135,10 +182,10 @@ __device__ void tile_gemm_mfma(int M, int N, int m0, int n0, int nseg, KQ kq, LA
 
 // C tile (m0, n0) of sum_seg op(A) B on the matrix cores (tile_gemm_mfma, in
 // the precision of T).  C = alpha * sum (+ C if beta).
-template <typename T, int TM, int TN, int RM, int RN, int NSEG>
+template <typename T, int TM, int TN, int RM, int RN, int NSEG, int CM>
 __device__ void tile_gemm(int M, int N, int m0, int n0, const Seg<T> (&sg)[NSEG], int nseg, T *C, int ldc,
                           T alpha, int beta) {
-  tile_gemm_mfma<T, TM, TN, NSEG>(
+  tile_gemm_mfma<T, TM, TN, NSEG, CM>(
       M, N, m0, n0, nseg, [&](int q) { return sg[q].K; },
       [&](int q, int m, int k) {
         const Seg<T> &s = sg[q];
@@ -162,7 +209,7 @@ __device__ inline EnvWork find_work(const EnvWork *work, int nwork, int wg) {
 }
 
 // X[(c, s, k)] = L[(c, s)] A_ket[s, k, s + q(k)]
-template <typename T, int TM, int TN, int RM, int RN>
+template <typename T, int TM, int TN, int RM, int RN, int CM>
 __global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, const EnvWork *work, int nwork, EnvGeom g,
                                                 const T *const *L, const T *const *ket, T *const *X) {
   const EnvWork w = find_work(work, nwork, blockIdx.x);
@@ -183,11 +230,11 @@ __global__ void __launch_bounds__(256) k_env_g1(const EnvG1 *descs, const EnvWor
   sg[0].B = ket[pair] + ((int64_t)sk.x * 4 + d.k) * Dr + sn.x;
   sg[0].ldb = 4 * Dr;
   sg[0].K = sk.y;
-  tile_gemm<T, TM, TN, RM, RN, 1>(M, N, m0, n0, sg, 1, X[pair] + d.offX, N, T(1), 0);
+  tile_gemm<T, TM, TN, RM, RN, 1, CM>(M, N, m0, n0, sg, 1, X[pair] + d.offX, N, T(1), 0);
 }
 
 // L'[(c, s)] = sum_k' A_bra[s_a(k'), k', s + d]^T Y[(c, s, k')]
-template <typename T, int TM, int TN, int RM, int RN>
+template <typename T, int TM, int TN, int RM, int RN, int CM>
 __global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, const EnvWork *work, int nwork, EnvGeom g,
                                                 const T *const *bra, const T *const *Y, T *const *Ln) {
   const EnvWork w = find_work(work, nwork, blockIdx.x);
@@ -211,21 +258,21 @@ __global__ void __launch_bounds__(256) k_env_g2(const EnvG2 *descs, const EnvWor
     sg[q].ldb = N;
     sg[q].K = q < d.nseg ? sa.y : 0;
   }
-  tile_gemm<T, TM, TN, RM, RN, 4>(M, N, m0, n0, sg, d.nseg, Ln[pair] + d.offL, N, T(1), 0);
+  tile_gemm<T, TM, TN, RM, RN, 4, CM>(M, N, m0, n0, sg, d.nseg, Ln[pair] + d.offL, N, T(1), 0);
 }
 
 // C tile (m0, n0) of A B with element loaders (A: m x k, B: k x n) and an
 // accumulating store; same tiling as tile_gemm.
-template <typename T, int TM, int TN, int RM, int RN, class LA, class LB, class SC>
+template <typename T, int TM, int TN, int RM, int RN, int CM, class LA, class LB, class SC>
 __device__ void tile_gemm_f(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc) {
-  tile_gemm_mfma<T, TM, TN, 1>(
+  tile_gemm_mfma<T, TM, TN, 1, CM>(
       M, N, m0, n0, 1, [&](int) { return K; }, [&](int, int m, int k) { return la(m, k); },
       [&](int, int k, int n) { return lb(k, n); }, sc);
 }
 
 // dense channel coupling: Y[a][r0 + i][b] += f sum_j W[i][j] X[a][c0 + j][b],
 // one GEMM over all bra rows a of the block: M = nr, K = nc, N = (a, b)
-template <typename T, int TM, int TN, int RM, int RN>
+template <typename T, int TM, int TN, int RM, int RN, int CM>
 __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, const EnvWork *work, int nwork, EnvGeom g,
                                                 const T *const *vals, const T *const *X, T *const *Y) {
   const EnvWork w = find_work(work, nwork, blockIdx.x);
@@ -242,7 +289,7 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, const EnvWor
   T *Yb = Y[pair] + d.offY + (int64_t)d.r0 * db;
   const int nc = d.nc, xs = d.nw_in * db, ys = d.nw_out * db;
   const T f = (T)d.f;
-  tile_gemm_f<T, TM, TN, RM, RN>(
+  tile_gemm_f<T, TM, TN, RM, RN, CM>(
       d.nr, N, nc, m0, n0, [&](int m, int k) { return W[(int64_t)m * nc + k]; },
       [&](int k, int n) {
         const int a = n / db, b = n - a * db;
@@ -388,6 +435,12 @@ __global__ void k_cast(const double *const *src, float *const *dst, const int64_
     dst[i][e] = (float)src[i][e];
 }
 
+// y[b][j] = x[b][j] + a z[j] for every basis b (nnz entries each)
+__global__ void k_shift_vals(const double *x, const double *z, double a, int64_t nnz, double *y) {
+  const int64_t b = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x)
+    y[b * nnz + j] = x[b * nnz + j] + a * z[j];
+}
 
 // ------------------------------------------------------------ one-hot pencil
 // Dense contractions of the expanded one-hot pencil (App. A1): the index maps
@@ -505,39 +558,49 @@ __global__ void k_oh_sd(const int4 *oh, int n, const double *LS, int Db, const d
 
 }  // namespace
 
-#define TNQE_TILE_SWITCH(KERNEL, T, tileM, tileN, grid, ...)                                   \
+#define TNQE_TILE_SWITCH(KERNEL, T, CM, tileM, tileN, grid, ...)                               \
   do {                                                                                         \
     if (tileM == 256 && tileN == 16)                                                           \
-      hipLaunchKernelGGL((KERNEL<T, 256, 16, 16, 1>), grid, dim3(256), 0, __VA_ARGS__);        \
+      hipLaunchKernelGGL((KERNEL<T, 256, 16, 16, 1, CM>), grid, dim3(256), 0, __VA_ARGS__);    \
     else if (tileM == 16 && tileN == 256)                                                      \
-      hipLaunchKernelGGL((KERNEL<T, 16, 256, 1, 16>), grid, dim3(256), 0, __VA_ARGS__);        \
+      hipLaunchKernelGGL((KERNEL<T, 16, 256, 1, 16, CM>), grid, dim3(256), 0, __VA_ARGS__);    \
     else if (tileM == 128 && tileN == 32)                                                      \
-      hipLaunchKernelGGL((KERNEL<T, 128, 32, 8, 2>), grid, dim3(256), 0, __VA_ARGS__);         \
+      hipLaunchKernelGGL((KERNEL<T, 128, 32, 8, 2, CM>), grid, dim3(256), 0, __VA_ARGS__);     \
     else if (tileM == 32 && tileN == 128)                                                      \
-      hipLaunchKernelGGL((KERNEL<T, 32, 128, 2, 8>), grid, dim3(256), 0, __VA_ARGS__);         \
+      hipLaunchKernelGGL((KERNEL<T, 32, 128, 2, 8, CM>), grid, dim3(256), 0, __VA_ARGS__);     \
     else                                                                                       \
-      hipLaunchKernelGGL((KERNEL<T, 64, 64, 4, 4>), grid, dim3(256), 0, __VA_ARGS__);          \
+      hipLaunchKernelGGL((KERNEL<T, 64, 64, 4, 4, CM>), grid, dim3(256), 0, __VA_ARGS__);      \
+  } while (0)
+
+// compute mode cm (FP32 storage only): 0 native, 1 BF16, 2 split BF16
+#define TNQE_CM_SWITCH(KERNEL, T, cm, tileM, tileN, grid, ...)                                 \
+  do {                                                                                         \
+    if constexpr (std::is_same<T, float>::value) {                                             \
+      if (cm == 1) { TNQE_TILE_SWITCH(KERNEL, T, 1, tileM, tileN, grid, __VA_ARGS__); break; } \
+      if (cm == 2) { TNQE_TILE_SWITCH(KERNEL, T, 2, tileM, tileN, grid, __VA_ARGS__); break; } \
+    }                                                                                          \
+    TNQE_TILE_SWITCH(KERNEL, T, 0, tileM, tileN, grid, __VA_ARGS__);                           \
   } while (0)
 
 template <typename T>
 void launch_env_g1(const EnvG1 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st) {
+                   const EnvGeom &g, const T *const *L, const T *const *ket, T *const *X, hipStream_t st, int cm) {
   if (nwork == 0 || nwg == 0) return;
-  TNQE_TILE_SWITCH(k_env_g1, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, L, ket, X);
+  TNQE_CM_SWITCH(k_env_g1, T, cm, tileM, tileN, dim3(nwg), st, d, work, nwork, g, L, ket, X);
 }
 
 template <typename T>
 void launch_env_g2(const EnvG2 *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st) {
+                   const EnvGeom &g, const T *const *bra, const T *const *Y, T *const *Ln, hipStream_t st, int cm) {
   if (nwork == 0 || nwg == 0) return;
-  TNQE_TILE_SWITCH(k_env_g2, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, bra, Y, Ln);
+  TNQE_CM_SWITCH(k_env_g2, T, cm, tileM, tileN, dim3(nwg), st, d, work, nwork, g, bra, Y, Ln);
 }
 
 template <typename T>
 void launch_env_gd(const EnvGD *d, const EnvWork *work, int nwork, int nwg, int tileM, int tileN,
-                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st) {
+                   const EnvGeom &g, const T *const *vals, const T *const *X, T *const *Y, hipStream_t st, int cm) {
   if (nwork == 0 || nwg == 0) return;
-  TNQE_TILE_SWITCH(k_env_gd, T, tileM, tileN, dim3(nwg), st, d, work, nwork, g, vals, X, Y);
+  TNQE_CM_SWITCH(k_env_gd, T, cm, tileM, tileN, dim3(nwg), st, d, work, nwork, g, vals, X, Y);
 }
 
 template <typename T>
@@ -580,6 +643,12 @@ void launch_oh_sd(const int4 *oh, int n, const double *LS, int Db, const double 
                      Sd, Hd);
 }
 
+void launch_shift_vals(const double *x, const double *z, double a, int64_t nnz, int nbasis, double *y,
+                       hipStream_t st) {
+  if (nnz == 0 || nbasis == 0) return;
+  hipLaunchKernelGGL(k_shift_vals, dim3(64, nbasis), dim3(256), 0, st, x, z, a, nnz, y);
+}
+
 void launch_cast(const double *const *src, float *const *dst, const int64_t *count, int n, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_cast, dim3(64, n), dim3(256), 0, st, src, dst, count);
@@ -587,11 +656,11 @@ void launch_cast(const double *const *src, float *const *dst, const int64_t *cou
 
 #define TNQE_ENV_INST(T)                                                                                     \
   template void launch_env_g1<T>(const EnvG1 *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
-                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+                                 const T *const *, const T *const *, T *const *, hipStream_t, int);         \
   template void launch_env_g2<T>(const EnvG2 *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
-                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+                                 const T *const *, const T *const *, T *const *, hipStream_t, int);         \
   template void launch_env_gd<T>(const EnvGD *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
-                                 const T *const *, const T *const *, T *const *, hipStream_t);              \
+                                 const T *const *, const T *const *, T *const *, hipStream_t, int);         \
   template void launch_mix<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, hipStream_t); \
   template void launch_env_init<T>(T *const *, int, int64_t, hipStream_t);                                  \
   template void launch_env_final<T>(const EnvGeom &, int, const double *const *, const T *const *,          \
