@@ -311,6 +311,37 @@ def test_fp32_environments_meet_target(ctx):
     assert abs(E - float(g["E"])) <= 1e-6
 
 
+def test_reduced_precision_modes(ctx):
+    """Every pair in reduced precision at N = 12, chi = 64.  FP32 on the
+    shifted operator H - c N meets |dE| <= 1e-6 Ha; the BF16 modes are
+    measured against the FP64 oracle and bounded by their arithmetic (BF16
+    keeps 8 bits, split BF16 about 16)."""
+    prob = synth.make_config(3)
+    g = np.load(os.path.join(GOLD, "oracle_config3.npz"))
+    hmax = np.abs(g["H"]).max()
+    for prec, e_tol, h_tol in (("fp32_shift", 1e-6, 1e-6), ("bf16x3", 1e-3, 1e-4), ("bf16", 1e-1, 2e-2)):
+        H, S, E, c, rep = ctx.subspace(prob, chi=prob.chi, precision=prec)
+        dE = abs(E - float(g["E"]))
+        dH = np.abs(H - g["H"]).max() / hmax
+        dS = np.abs(S - g["S"]).max()
+        print(f"{prec}: dE={dE:.2e} dH_rel={dH:.2e} dS={dS:.2e}", flush=True)
+        assert rep["n_fp32_pairs"] == prob.M * (prob.M + 1) // 2
+        assert dE <= e_tol and dH <= h_tol
+        np.testing.assert_array_equal(H, H.T)
+
+
+@pytest.mark.xfail(strict=True, reason="FP32 on the shifted operator misses |dE| <= 1e-6 Ha at N = 24 (measured 1.4e-6)")
+def test_fp32_shift_full_size_target(ctx):
+    prob = synth.make_config(5)
+    up = ctx.upload(prob)
+    try:
+        H, S, E, c, rep = up.solve(chi=prob.chi)
+        Hm, Sm, Em, cm, repm = up.solve(chi=prob.chi, precision="fp32_shift")
+    finally:
+        up.free()
+    assert abs(Em - E) <= 1e-6
+
+
 def test_full_size_sampled_pairs(ctx):
     """N = 24, chi = 256, M = 16: the benchmark workload, checked on sampled pairs."""
     prob = synth.make_config(5)
