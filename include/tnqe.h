@@ -282,6 +282,76 @@ tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32
                                const tnqe_options *opts, int32_t i, int32_t p, int32_t n, int32_t *index,
                                double *Hd, double *Sd, double *Hc, double *Sc, tnqe_report *rep);
 
+/* One step of the generalized sweep (Alg. A.1) at sites (p, p+1) with state i
+ * as the expanded state (jset = {i}; App. A1), no single-site mitigation
+ * repetitions (App. A4):
+ *  1. the expanded pencil of tnqe_onehot_pencil, with the current pencil
+ *     (H, S) for the unexpanded states, in the order of eq. subs_exp: states
+ *     k < i, the n one-hot states of i, states k > i (D = n + M - 1 columns);
+ *  2. columns taken in that order are discarded when their squared distance
+ *     from the span of the kept earlier ones is below tol_ld times their
+ *     squared norm (Sec. V "Regulating the subspace condition number",
+ *     App. A2);
+ *  3. the lowest root E1 of the kept pencil by the projection method with the
+ *     eps_S threshold of opts (eq. exp_gen_eig);
+ *  4. parameter update (eq. param_upd): t'_m = C'[i m] / ||C'[i .]||, signed
+ *     so that sum_m t'_m t_m >= 0;
+ *  5. rotation of the bond (App. A3): none; the FSWAP f4, taken when it lowers
+ *     xi = 1 - sum_{l <= chi} sigma_l^2; or the Givens gate g4(theta) at
+ *     theta_opt = argmin xi(theta): the best of n_grid angles
+ *     (q - n_grid/2) pi / n_grid, then n_golden golden-section steps on one
+ *     spacing either side; a rotation is taken only when it lowers xi by
+ *     more than 1e-12 (below that the choice would be rounding);
+ *  6. truncation of the rotated two-site tensor with the rule of the gates
+ *     (chi, tau_w of opts): A_p = U, A_{p+1} = U^T T, centre at p + 1;
+ *  7. merge of the rotation into the orbital basis of state i:
+ *     U_i <- U_i R_p(theta)^T (FSWAP: columns p and p+1 exchanged), which
+ *     leaves the state unchanged up to the truncation;
+ *  8. accepted = E1 < E_old + e_tol (E_old: lowest root of (H, S)).
+ * Inputs: as tnqe_onehot_pencil, and H, S [M][M] host (the current pencil,
+ * e.g. from tnqe_subspace with the same options).  Outputs (host): res; the
+ * updated state i in the layout of tnqe_mps -- bond_dim [N+1], bond_qn
+ * [qn_cap][2] (sum of bond_dim entries used), sites [sites_cap] (site x is
+ * [bond_dim[x]][4][bond_dim[x+1]], in canonical form centred on p+1, bonds
+ * sorted by sector), U [N][N]; rep or NULL.  qn_cap >= sum of the input
+ * state's bond dimensions + chi and sites_cap >= the input state's site
+ * sizes + 4 chi (bond_dim[p] + bond_dim[p+2]) always suffice; smaller
+ * capacities that do not hold the result give TNQE_ESHAPE (outputs
+ * untouched).  D = n + M - 1 <= 1024 (TNQE_ESHAPE beyond); M <= 32.  Device
+ * memory from the context's pool. */
+typedef enum { TNQE_ROT_NONE = 0, TNQE_ROT_FSWAP = 1, TNQE_ROT_GIVENS = 2 } tnqe_rotation;
+typedef struct {
+  int32_t rotation;      /* tnqe_rotation */
+  int32_t n_grid;        /* Givens: grid angles, even (0: 36) */
+  int32_t n_golden;      /* Givens: golden-section steps (< 0: 40) */
+  int32_t reserved0;
+  double tol_ld;         /* discard threshold (0: 1e-3) */
+  double e_tol;          /* acceptance tolerance (Hartree) */
+  double reserved[2];
+} tnqe_sweep_options;
+typedef struct {
+  double E_old;          /* lowest root of the current pencil */
+  double E1;             /* lowest root of the expanded pencil */
+  double theta;          /* rotation applied: Givens angle, pi/2 for an accepted FSWAP, else 0 */
+  double xi_none, xi;    /* truncation error without / with the rotation */
+  double discarded;      /* discarded weight of the final truncation */
+  int32_t n_onehot;      /* n */
+  int32_t n_columns;     /* D */
+  int32_t n_kept;        /* columns kept by the discard */
+  int32_t n_dropped_S;   /* further directions dropped by the eps_S threshold */
+  int32_t accepted;      /* 1: E1 < E_old + e_tol */
+  int32_t new_bond;      /* bond dimension p + 1 after the truncation */
+  int32_t reserved[2];
+} tnqe_sweep_result;
+tnqe_status tnqe_sweep_step(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                            const tnqe_options *opts, const tnqe_sweep_options *sw, int32_t i, int32_t p,
+                            const double *H, const double *S, int32_t *bond_dim, int32_t *bond_qn, int64_t qn_cap,
+                            double *sites, int64_t sites_cap, double *U, tnqe_sweep_result *res,
+                            tnqe_report *rep);
+/* t'_m of the last tnqe_sweep_step on this context ([n_onehot] host), for
+ * checks; TNQE_EINVAL when n differs from that call's n_onehot. */
+tnqe_status tnqe_sweep_last_params(tnqe_ctx *ctx, int32_t n, double *t);
+
 /* For callers that cannot allocate memory (code under HIP stream capture,
  * tight serving loops, harnesses that forbid allocation): tnqe_subspace with
  * no workspace argument and no allocation of device or pinned host memory,

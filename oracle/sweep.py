@@ -23,7 +23,9 @@ chosen reference state) and no single-site mitigation repetitions (App. A4):
    it lowers the truncation error xi = 1 - sum_{l <= chi} sigma_l^2; or the
    Givens gate g4(theta) at theta_opt = argmin xi(theta), found on a grid of
    n_grid angles over [-pi/2, pi/2) (xi has period pi) refined by n_golden
-   golden-section steps around the best grid point.
+   golden-section steps around the best grid point.  "Lowers" means by more
+   than xi_tol (1e-12): xi is a difference of order-one sums, and below that
+   a rotation would be chosen by rounding alone.
 6. Truncation of the rotated two-site tensor with the rule of the gates
    (App. A1): A_p = U (left-orthonormal), A_{p+1} = Sigma V; centre at p+1.
 7. Merge of the rotation into the orbital basis of state i: applying g4(theta)
@@ -127,11 +129,11 @@ def theta_grid(n_grid):
     return [(q - n_grid // 2) * (np.pi / n_grid) for q in range(n_grid)]
 
 
-def optimise_theta(T4, qn_p, qn_p2, chi, n_grid=36, n_golden=40):
+def optimise_theta(T4, qn_p, qn_p2, chi, n_grid=36, n_golden=40, xi_tol=1e-12):
     """theta_opt = argmin xi(theta) (eq. theta_opt): the best of n_grid angles
     over [-pi/2, pi/2), then n_golden golden-section steps on the bracket of
     one grid spacing either side of it.  Returns (theta_opt, xi(theta_opt),
-    xi(0)); theta_opt is 0 unless it lowers xi below xi(0)."""
+    xi(0)); theta_opt is 0 unless it lowers xi below xi(0) - xi_tol."""
     f = lambda th: xi(apply_gate(T4, gates.g4(th)), qn_p, qn_p2, chi)
     grid = theta_grid(n_grid)
     vals = [f(th) for th in grid]
@@ -154,7 +156,7 @@ def optimise_theta(T4, qn_p, qn_p2, chi, n_grid=36, n_golden=40):
     th, fv = (x1, f1) if f1 <= f2 else (x2, f2)
     if vals[qb] < fv:
         th, fv = grid[qb], vals[qb]
-    if not fv < xi0:
+    if not fv < xi0 - xi_tol:
         th, fv = 0.0, xi0
     return float(th), float(fv), float(xi0)
 
@@ -210,7 +212,7 @@ def finish(T4, sites, qn, U, p, rotation, theta, chi_cap, tau_w):
 
 
 def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_tol=0.0, chi_cap=None,
-               tau_w=1e-13, n_grid=36, n_golden=40):
+               tau_w=1e-13, n_grid=36, n_golden=40, xi_tol=1e-12):
     """Steps 1-8 above.  H, S: the current pencil.  Returns a dict."""
     assert rotation in ROTATIONS
     chi_cap = prob.chi if chi_cap is None else chi_cap
@@ -239,10 +241,10 @@ def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_to
     theta, xi_rot = 0.0, xi_none
     if rotation == "fswap":
         xs = xi(apply_gate(T4, gates.f4()), qn[p], qn[p + 2], chi_cap)
-        if xs < xi_none:
+        if xs < xi_none - xi_tol:
             theta, xi_rot = np.pi / 2, xs
     elif rotation == "givens":
-        theta, xi_rot, _ = optimise_theta(T4, qn[p], qn[p + 2], chi_cap, n_grid, n_golden)
+        theta, xi_rot, _ = optimise_theta(T4, qn[p], qn[p + 2], chi_cap, n_grid, n_golden, xi_tol)
     new_sites, new_qn, U_new, T4r, st = finish(T4, sites, qn, bi.U, p, rotation, theta, chi_cap, tau_w)
     E_old = solve_projection(H, S, eps_S)["E"]
     return dict(E_old=E_old, E1=sol["E"], accepted=bool(sol["E"] < E_old + e_tol), keep=keep, pos=pos,

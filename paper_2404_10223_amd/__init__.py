@@ -43,6 +43,21 @@ class _Opts(C.Structure):
                 ("reserved", C.c_int32 * 4)]
 
 
+class _SweepOpts(C.Structure):
+    _fields_ = [("rotation", C.c_int32), ("n_grid", C.c_int32), ("n_golden", C.c_int32), ("reserved0", C.c_int32),
+                ("tol_ld", C.c_double), ("e_tol", C.c_double), ("reserved", C.c_double * 2)]
+
+
+class _SweepRes(C.Structure):
+    _fields_ = [("E_old", C.c_double), ("E1", C.c_double), ("theta", C.c_double), ("xi_none", C.c_double),
+                ("xi", C.c_double), ("discarded", C.c_double), ("n_onehot", C.c_int32),
+                ("n_columns", C.c_int32), ("n_kept", C.c_int32), ("n_dropped_S", C.c_int32),
+                ("accepted", C.c_int32), ("new_bond", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+ROTATIONS = {"none": 0, "fswap": 1, "givens": 2}
+
+
 class _Report(C.Structure):
     _fields_ = [("max_discarded_weight_sum", C.c_double), ("min_rel_gap", C.c_double),
                 ("cond_S", C.c_double), ("lambda_min_S", C.c_double), ("kappa1", C.c_double),
@@ -67,7 +82,7 @@ EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "
            "tnqe_subspace_batch", "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
            "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool", "tnqe_debug_select",
            "tnqe_debug_gep", "tnqe_subspace_noalloc", "tnqe_noalloc_capacity", "tnqe_onehot_size",
-           "tnqe_onehot_pencil"]
+           "tnqe_onehot_pencil", "tnqe_sweep_step", "tnqe_sweep_last_params"]
 
 _lib = None
 
@@ -110,6 +125,10 @@ def lib():
                                    C.POINTER(ip)]
     L.tnqe_onehot_pencil.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), ip, ip, ip,
                                      C.POINTER(ip), dp, dp, dp, dp, C.POINTER(_Report)]
+    L.tnqe_sweep_step.argtypes = [vp, C.POINTER(_Ham), ip, C.POINTER(_Mps), C.POINTER(_Opts), C.POINTER(_SweepOpts),
+                                  ip, ip, dp, dp, C.POINTER(ip), C.POINTER(ip), C.c_int64, dp, C.c_int64, dp,
+                                  C.POINTER(_SweepRes), C.POINTER(_Report)]
+    L.tnqe_sweep_last_params.argtypes = [vp, ip, dp]
     L.tnqe_noalloc_capacity.argtypes = []
     L.tnqe_noalloc_capacity.restype = C.c_size_t
     L.tnqe_status_string.argtypes = [C.c_int]
@@ -296,6 +315,48 @@ class Context:
                                          _iptr(index), _dptr(Hd), _dptr(Sd), _dptr(Hc), _dptr(Sc), C.byref(r)),
                self.h)
         return index, Hd, Sd, Hc, Sc, report_dict(r)
+
+    def sweep_step(self, prob, H, S, i, p, rotation="none", tol_ld=1e-3, e_tol=0.0, n_grid=36, n_golden=40, **kw):
+        """One generalized-sweep step at sites (p, p+1) for state i
+        (tnqe_sweep_step).  H, S: the current pencil.  Returns (result dict,
+        the updated state as an MPS-like (sites, bond_qn, U) triple, t' [n],
+        report)."""
+        pk = _Packed(prob)
+        o = options(**kw)
+        so = _SweepOpts(ROTATIONS[rotation], int(n_grid), int(n_golden), 0, float(tol_ld), float(e_tol))
+        m = prob.mps[i]
+        N = prob.N
+        chi = o.chi_cap_override if o.chi_cap_override > 0 else o.chi
+        dims_in = [q.shape[0] for q in m.bond_qn]
+        qn_cap = sum(dims_in) + chi
+        # (an out-of-range p is the library's to reject)
+        edge = dims_in[min(max(p, 0), N)] + dims_in[min(max(p + 2, 0), N)]
+        sites_cap = sum(a.size for a in m.sites) + 4 * chi * edge
+        bond_dim = np.zeros(N + 1, dtype=np.int32)
+        bond_qn = np.zeros((qn_cap, 2), dtype=np.int32)
+        sites = np.zeros(sites_cap)
+        U = np.zeros((N, N))
+        Hh = np.ascontiguousarray(H, dtype=np.float64)
+        Sh = np.ascontiguousarray(S, dtype=np.float64)
+        res = _SweepRes()
+        r = _Report()
+        _check(self.L.tnqe_sweep_step(self.h, C.byref(pk.ham), prob.M, pk.mps, C.byref(o), C.byref(so), int(i),
+                                      int(p), _dptr(Hh), _dptr(Sh), _iptr(bond_dim), _iptr(bond_qn),
+                                      int(qn_cap), _dptr(sites), int(sites_cap), _dptr(U), C.byref(res),
+                                      C.byref(r)), self.h)
+        out = {name: getattr(res, name) for name, _ in _SweepRes._fields_ if not name.startswith("reserved")}
+        t = np.zeros(res.n_onehot)
+        _check(self.L.tnqe_sweep_last_params(self.h, res.n_onehot, _dptr(t)), self.h)
+        # unpack the state (layout of tnqe_mps)
+        qns, st, o_q, o_s = [], [], 0, 0
+        for b in range(N + 1):
+            qns.append(bond_qn[o_q:o_q + bond_dim[b]].astype(np.int64).copy())
+            o_q += bond_dim[b]
+        for x in range(N):
+            n = bond_dim[x] * 4 * bond_dim[x + 1]
+            st.append(sites[o_s:o_s + n].reshape(bond_dim[x], 4, bond_dim[x + 1]).copy())
+            o_s += n
+        return out, (st, qns, U), t, report_dict(r)
 
     def subspace_noalloc(self, prob, **kw):
         """tnqe_subspace_noalloc: the library's fixed per-GPU scratch, no allocation."""

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtnqe.so")
 SOURCES = ["engine.cpp", "mpo.cpp", "kernels_gate.hip", "kernels_svd.hip", "kernels_env.hip", "kernels_gep.hip",
-           "noalloc.hip"]
+           "kernels_sweep.hip", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-pthread",
          # no packed FP32 instructions: the compiler would form them from float
          # code, and some of their forms have given silently wrong results on gfx950

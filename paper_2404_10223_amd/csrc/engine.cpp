@@ -12,6 +12,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -2509,6 +2510,17 @@ struct OneHotOut {
   std::vector<double> Hd, Sd, Hc, Sc;
 };
 
+// the pencil blocks on the device (valid while the Call lives), and state ei
+// in the canonical form centred on p
+struct OneHotDev {
+  std::vector<int4> index;
+  std::vector<int> dense_of;        // index m -> ((l * 4 + k_p) * 4 + k_{p+1}) * Dq + r
+  const int *d_dense = nullptr;
+  double *Hd = nullptr, *Sd = nullptr, *Hc = nullptr, *Sc = nullptr;   // [n][n], [n][n], [n][M], [n][M]
+  KetSet ci;
+  int Dp = 0, Dq = 0;               // total dimensions of bonds p and p + 2
+};
+
 // Expanded pencil of state ei at sites (p, p+1) (App. A1, single expanded
 // state): ei in canonical form centred on p; for every state k the ket is k
 // rotated into basis ei by its Givens network with truncation (k = ei: ei
@@ -2516,9 +2528,9 @@ struct OneHotOut {
 // sites > p + 1 with the dense MPO of H^(ei) (and with the identity for the
 // overlaps), then the two-site blocks.  Every contraction is a matrix-core
 // GEMM (launch_oh_gemm).
-void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei, int p, OneHotOut &out,
-                tnqe_report &rep) {
-  Call c{ctx};
+void onehot_core(Call &c, tnqe_problem &pb, const tnqe_options &op, int ei, int p, OneHotDev &out,
+                 tnqe_report &rep) {
+  tnqe_ctx *ctx = c.ctx;
   const auto t0 = Clock::now();
   const int N = pb.N, M = pb.M;
   require(ei >= 0 && ei < M, TNQE_EINVAL, "expanded state out of range");
@@ -2574,7 +2586,7 @@ void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei,
   TruncStats ts;
   gate_phase(c, pb, offd, chi_cap, op, max_sweeps, canon, kets, ts);
   const std::vector<int> cap = bond_caps(pb, chi_cap);
-  KetSet ci;
+  KetSet &ci = out.ci;
   ci.init(&c, 1, N, pb.na, pb.nb, cap);
   {
     std::vector<double *> dst(1), src(1);
@@ -2622,17 +2634,25 @@ void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei,
   const int n = (int)out.index.size();
   require(n > 0, TNQE_ESHAPE, "the two-site tensor has no entries in the particle-number sector");
   const int Dbp = ci.htot[p], Dbm = ci.htot[p + 1], Dbq = ci.htot[p + 2];
-  std::vector<int> dense_of(n), dmap((size_t)Dbp * 16 * Dbq, -1);
+  std::vector<int> &dense_of = out.dense_of, dmap((size_t)Dbp * 16 * Dbq, -1);
+  dense_of.resize(n);
+  out.Dp = Dbp;
+  out.Dq = Dbq;
   for (int m = 0; m < n; ++m) {
     const int4 &e = out.index[m];
     dense_of[m] = ((e.x * 4 + e.y) * 4 + e.z) * Dbq + e.w;
     dmap[dense_of[m]] = m;
   }
   const int *d_dense = c.upload(dense_of);
+  out.d_dense = d_dense;
   const int *d_map = c.upload(dmap);
   const int4 *d_oh = c.upload(out.index);
   double *dHc = c.dev<double>((size_t)n * M), *dSc = c.dev<double>((size_t)n * M);
   double *dHd = c.dev<double>((size_t)n * n), *dSd = c.dev<double>((size_t)n * n);
+  out.Hc = dHc;
+  out.Sc = dSc;
+  out.Hd = dHd;
+  out.Sd = dSd;
   (void)Dbm;
   // ---- environments and blocks, pair by pair
   const auto te = Clock::now();
@@ -2739,14 +2759,6 @@ void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei,
     ctx->pool.rewind(mk);
   }
   TNQE_HIP(hipEventRecord(ctx->ev[3], st));
-  out.Hd.resize((size_t)n * n);
-  out.Sd.resize((size_t)n * n);
-  out.Hc.resize((size_t)n * M);
-  out.Sc.resize((size_t)n * M);
-  TNQE_HIP(hipMemcpyAsync(out.Hd.data(), dHd, out.Hd.size() * 8, hipMemcpyDeviceToHost, st));
-  TNQE_HIP(hipMemcpyAsync(out.Sd.data(), dSd, out.Sd.size() * 8, hipMemcpyDeviceToHost, st));
-  TNQE_HIP(hipMemcpyAsync(out.Hc.data(), dHc, out.Hc.size() * 8, hipMemcpyDeviceToHost, st));
-  TNQE_HIP(hipMemcpyAsync(out.Sc.data(), dSc, out.Sc.size() * 8, hipMemcpyDeviceToHost, st));
   c.sync();
   float ms = 0.0f;
   TNQE_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
@@ -2762,8 +2774,474 @@ void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei,
   rep.n_pairs = M;
   rep.mpo_max_bond = mpo.max_bond;
   rep.t_total_ms = ms_since(t0);
+}
+
+void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei, int p, OneHotOut &out,
+                tnqe_report &rep) {
+  Call c{ctx};
+  OneHotDev dv;
+  onehot_core(c, pb, op, ei, p, dv, rep);
+  const size_t n = dv.index.size(), M = pb.M;
+  out.index = dv.index;
+  out.Hd.resize(n * n);
+  out.Sd.resize(n * n);
+  out.Hc.resize(n * M);
+  out.Sc.resize(n * M);
+  hipStream_t st = ctx->stream;
+  TNQE_HIP(hipMemcpyAsync(out.Hd.data(), dv.Hd, out.Hd.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Sd.data(), dv.Sd, out.Sd.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Hc.data(), dv.Hc, out.Hc.size() * 8, hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(out.Sc.data(), dv.Sc, out.Sc.size() * 8, hipMemcpyDeviceToHost, st));
+  c.sync();
   for (double v : out.Hd) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite one-hot element");
   for (double v : out.Hc) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite one-hot element");
+}
+
+// ------------------------------------------------------------ generalized-sweep step
+// One step of Alg. A.1 at sites (p, p+1) for the expanded state ei (App. A1:
+// one chosen reference state; no single-site mitigation repetitions): the
+// expanded pencil in the order of eq. subs_exp, the discard of dependent
+// columns (App. A2), the thresholded eigenproblem (eq. exp_gen_eig), the
+// parameter update (eq. param_upd), the rotation of the bond (App. A3), the
+// truncation to chi and the merge of the rotation into the orbital basis.
+struct SweepOut {
+  double E_old = 0.0, E1 = 0.0, theta = 0.0, xi_none = 0.0, xi = 0.0, discarded = 0.0;
+  int n = 0, D = 0, n_kept = 0, n_dropped_S = 0, accepted = 0, new_bond = 0;
+  std::vector<double> tnew;
+  std::vector<int32_t> bond_dim;
+  std::vector<int32_t> bond_qn;
+  std::vector<double> sites, U;
+};
+
+// FSWAP f4 on (k_p, k_{p+1}) (App. A3): (1 x f2 x 1)(f2 x f2)(1 x f2 x 1) in
+// the mode basis (p up, p down, p+1 up, p+1 down), entry x = row * 16 + col
+double fswap4_entry(int x) {
+  static const int kq[4] = {0, 2, 1, 3};   // local state k -> mode bits (n_up, n_dn)
+  static const double f2[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, -1};
+  const int I = kq[x >> 6] * 4 + kq[(x >> 4) & 3], J = kq[(x >> 2) & 3] * 4 + kq[x & 3];
+  // (1 x f2 x 1) maps mode bits 1, 2 of a row through f2 (a permutation with a sign)
+  static const int f2c[4] = {0, 2, 1, 3};
+  static const double f2s[4] = {1.0, 1.0, 1.0, -1.0};
+  const int ci = (I & 8) | (f2c[(I >> 1) & 3] << 1) | (I & 1), cj = (J & 8) | (f2c[(J >> 1) & 3] << 1) | (J & 1);
+  const double si = f2s[(I >> 1) & 3], sj = f2s[(J >> 1) & 3];
+  return si * f2[(ci >> 2) * 4 + (cj >> 2)] * f2[(ci & 3) * 4 + (cj & 3)] * sj + 0.0;
+}
+
+// a rotation is taken only when it lowers xi by more than this: xi is a
+// difference of order-one sums, and below it the choice would be rounding
+constexpr double kXiTol = 1e-12;
+
+using Gate16 = std::array<double, 256>;
+Gate16 givens_gate(double theta) {
+  Gate16 g;
+  const double c = std::cos(theta), s = std::sin(theta);
+  for (int x = 0; x < 256; ++x) g[x] = gate4_entry(c, s, x);
+  return g;
+}
+Gate16 fswap_gate() {
+  Gate16 g;
+  for (int x = 0; x < 256; ++x) g[x] = fswap4_entry(x);
+  return g;
+}
+
+// Quantum-number blocks of the two-site matrix (l, k_p) x (k_{p+1}, r) of
+// state ci at (p, p+1) for every gate of a list, with their SVDs done:
+// blocks of gate g are first[g] .. first[g+1] (pair = g), in sector order.
+struct RotatedBlocks {
+  std::vector<Blk> blks;
+  std::vector<int> first;
+  Blk *dblk = nullptr;
+  double *scratch = nullptr;
+  int max_values = 0;
+};
+void rotated_blocks(Call &c, KetSet &ci, int p, const double *dT, const std::vector<Gate16> &gates, int max_sweeps,
+                    RotatedBlocks &rb) {
+  const int nslot = ci.nslot, nb1 = ci.nb + 1;
+  std::vector<int> offp(nslot), offq(nslot);
+  for (int s = 0; s < nslot; ++s) {
+    offp[s] = ci.hbtab[((size_t)p * ci.n) * nslot + s].x;
+    offq[s] = ci.hbtab[((size_t)(p + 2) * ci.n) * nslot + s].x;
+  }
+  std::vector<Blk> one;
+  for (int s = 0; s < nslot; ++s) {
+    const int sa = s / nb1, sb = s % nb1;
+    Blk b{};
+    b.sa = sa;
+    b.sb = sb;
+    b.rs[0] = b.cs[0] = 0;
+    for (int k = 0; k < 4; ++k) {
+      b.rs[k + 1] = b.rs[k] + ci.dim_q(p, 0, sa - qk_a(k), sb - qk_b(k));
+      b.cs[k + 1] = b.cs[k] + ci.dim_q(p + 2, 0, sa + qk_a(k), sb + qk_b(k));
+    }
+    b.R = b.rs[4];
+    b.C = b.cs[4];
+    if (b.R == 0 || b.C == 0) continue;
+    plan_block(b);
+    one.push_back(b);
+  }
+  Scratch sc;
+  rb.blks.clear();
+  rb.first.assign(1, 0);
+  rb.max_values = 0;
+  for (size_t g = 0; g < gates.size(); ++g) {
+    int nv = 0;
+    for (Blk b : one) {
+      b.pair = (int)g;
+      take_block_storage(b, sc);
+      b.offS = sc.take(b.n);
+      b.kept = b.n;
+      nv += b.n;
+      rb.blks.push_back(b);
+    }
+    rb.first.push_back((int)rb.blks.size());
+    rb.max_values = std::max(rb.max_values, nv);
+  }
+  require(rb.max_values <= kXiMaxValues, TNQE_ESHAPE, "two-site matrix with too many singular values");
+  rb.scratch = c.dev<double>(sc.used);
+  std::vector<double> gflat(gates.size() * 256);
+  for (size_t g = 0; g < gates.size(); ++g) std::copy(gates[g].begin(), gates[g].end(), gflat.begin() + g * 256);
+  Call::Blob bl;
+  const size_t o_blk = bl.add(rb.blks), o_g = bl.add(gflat), o_p = bl.add(offp), o_q = bl.add(offq);
+  char *base = c.upload(bl);
+  rb.dblk = Call::at<Blk>(base, o_blk);
+  launch_sw_gate_blocks(rb.dblk, (int)rb.blks.size(), Call::at<const double>(base, o_g), dT, ci.htot[p + 2],
+                        Call::at<const int>(base, o_p), Call::at<const int>(base, o_q), ci.na, nb1, rb.scratch,
+                        c.ctx->stream);
+  run_svd(c, rb.dblk, rb.blks, max_sweeps, rb.scratch);
+  c.check_launch();
+}
+
+// xi (App. A3) of every gate of the list
+std::vector<double> truncation_errors(Call &c, KetSet &ci, int p, const double *dT, const std::vector<Gate16> &gates,
+                                      int chi, int max_sweeps) {
+  const size_t mk = c.ctx->pool.mark();
+  RotatedBlocks rb;
+  rotated_blocks(c, ci, p, dT, gates, max_sweeps, rb);
+  double *dxi = c.dev<double>(gates.size());
+  launch_sw_xi(rb.dblk, c.upload(rb.first), (int)gates.size(), rb.max_values, rb.scratch, chi, dxi, c.ctx->stream);
+  c.check_launch();
+  std::vector<double> xi(gates.size());
+  TNQE_HIP(hipMemcpyAsync(xi.data(), dxi, xi.size() * sizeof(double), hipMemcpyDeviceToHost, c.ctx->stream));
+  c.sync();
+  c.ctx->pool.rewind(mk);
+  return xi;
+}
+
+// eigen- (singular) decomposition of a symmetric positive semi-definite n x n
+// device matrix by the block Jacobi SVD: vectors by row ([n][n]) and values,
+// both in decreasing order of the values
+void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, double *&val) {
+  Blk b{};
+  b.R = b.C = n;
+  b.rs[0] = b.cs[0] = 0;
+  for (int k = 1; k <= 4; ++k) b.rs[k] = b.cs[k] = n;
+  plan_block(b);
+  Scratch sc;
+  take_block_storage(b, sc);
+  b.offS = sc.take(n);
+  b.kept = n;
+  double *scratch = c.dev<double>(sc.used);
+  TNQE_HIP(hipMemcpyAsync(scratch + b.offT, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c.ctx->stream));
+  std::vector<Blk> blks{b};
+  Blk *dblk = c.upload(blks);
+  run_svd(c, dblk, blks, max_sweeps, scratch);
+  c.check_launch();
+  vec = scratch + b.offU;
+  val = scratch + b.offS;
+}
+
+void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tnqe_sweep_options &so, int ei, int p,
+               const double *H, const double *S, SweepOut &out, tnqe_report &rep) {
+  Call c{ctx};
+  hipStream_t st = ctx->stream;
+  const int M = pb.M, N = pb.N, nslot = pb.nslot();
+  require(M <= kMaxM, TNQE_ESHAPE, "more than 32 states");
+  const int chi_cap = op.chi_cap_override > 0 ? op.chi_cap_override : op.chi;
+  const int max_sweeps = op.max_sweeps > 0 ? op.max_sweeps : 40;
+  const double eps_S = op.eps_S > 0 ? op.eps_S : 1e-12;
+  const double tol_ld = so.tol_ld > 0 ? so.tol_ld : 1e-3;
+  const int n_grid = so.n_grid > 0 ? so.n_grid : 36, n_golden = so.n_golden >= 0 ? so.n_golden : 40;
+  require(so.rotation >= TNQE_ROT_NONE && so.rotation <= TNQE_ROT_GIVENS, TNQE_EINVAL, "unknown rotation type");
+  require(n_grid % 2 == 0, TNQE_EINVAL, "n_grid must be even (the grid holds theta = 0)");
+  // current pencil and its lowest root
+  std::vector<double> hH(H, H + (size_t)M * M), hS(S, S + (size_t)M * M);
+  for (double v : hH) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite pencil element");
+  for (double v : hS) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite pencil element");
+  double *dH = c.upload(hH), *dS = c.upload(hS);
+  {
+    std::vector<int> Ms{M};
+    std::vector<int64_t> offs{0};
+    double *dout = c.dev<double>(8 + kMaxM);
+    launch_gep(dH, dS, c.upload(Ms), c.upload(offs), 1, eps_S, dout, st);
+    std::vector<double> g(8 + kMaxM);
+    TNQE_HIP(hipMemcpyAsync(g.data(), dout, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    c.sync();
+    require(g[5] == 0.0, TNQE_ESINGULAR, "the current pencil has no positive overlap eigenvalue");
+    out.E_old = g[0];
+  }
+  // 1. expanded pencil blocks; state ei centred on (p, p+1)
+  OneHotDev dv;
+  onehot_core(c, pb, op, ei, p, dv, rep);
+  KetSet &ci = dv.ci;
+  const int n = (int)dv.index.size(), D = n + M - 1;
+  out.n = n;
+  out.D = D;
+  require(D <= 1024, TNQE_ESHAPE, "expanded pencil wider than 1024 columns");
+  // 2. combined order of eq. subs_exp and assembly
+  std::vector<int> code(D);
+  for (int a = 0; a < D; ++a) code[a] = a < ei ? -(a + 1) : a < ei + n ? a - ei : -(a - n + 1 + 1);
+  double *Hx = c.dev<double>((size_t)D * D), *Sx = c.dev<double>((size_t)D * D);
+  launch_sw_assemble(c.upload(code), D, n, M, dH, dS, dv.Hd, dv.Sd, dv.Hc, dv.Sc, Hx, Sx, st);
+  // 3. discard of linearly dependent columns
+  double *A = c.dev<double>((size_t)D * D);
+  int *dkeep = c.dev<int>(D);
+  TNQE_HIP(hipMemcpyAsync(A, Sx, sizeof(double) * D * D, hipMemcpyDeviceToDevice, st));
+  launch_sw_discard(A, Sx, D, tol_ld, dkeep, st);
+  std::vector<int> keep(D);
+  TNQE_HIP(hipMemcpyAsync(keep.data(), dkeep, D * sizeof(int), hipMemcpyDeviceToHost, st));
+  c.sync();
+  std::vector<int> kidx, col_of(D, -1);
+  for (int a = 0; a < D; ++a)
+    if (keep[a]) {
+      col_of[a] = (int)kidx.size();
+      kidx.push_back(a);
+    }
+  const int Dk = (int)kidx.size();
+  out.n_kept = Dk;
+  require(Dk >= 1, TNQE_ESINGULAR, "every column of the expanded pencil was discarded");
+  double *Hk = c.dev<double>((size_t)Dk * Dk), *Sk = c.dev<double>((size_t)Dk * Dk);
+  launch_sw_gather(Hx, Sx, D, c.upload(kidx), Dk, Hk, Sk, st);
+  // 4. projection-thresholded eigenproblem of the kept columns
+  double *Uv = nullptr, *lam = nullptr;
+  psd_eigen(c, Sk, Dk, max_sweeps, Uv, lam);
+  std::vector<double> hl(Dk);
+  TNQE_HIP(hipMemcpyAsync(hl.data(), lam, Dk * sizeof(double), hipMemcpyDeviceToHost, st));
+  c.sync();
+  int r = 0;
+  while (r < Dk && hl[r] > eps_S * hl[0]) ++r;
+  out.n_dropped_S = Dk - r;
+  require(r >= 1, TNQE_ESINGULAR, "no overlap eigenvalue above the threshold");
+  double *X = c.dev<double>((size_t)Dk * r), *Y = c.dev<double>((size_t)Dk * r), *Cm = c.dev<double>((size_t)r * r);
+  double *Bm = c.dev<double>((size_t)r * r), *dshift = c.dev<double>(1), *ck = c.dev<double>(Dk);
+  launch_sw_whiten(Uv, lam, Dk, r, X, st);
+  auto gemm = [&](int kind, int Mm, int Nn, int Kk, const double *Am, const double *Bp, double *Cp) {
+    OhGemm g{};
+    g.kind = kind;
+    g.M = Mm;
+    g.N = Nn;
+    g.K = Kk;
+    g.A = Am;
+    g.B = Bp;
+    g.C = Cp;
+    launch_oh_gemm(g, st);
+  };
+  gemm(kOhPlain, Dk, r, Dk, Hk, X, Y);       // H_k X
+  gemm(kOhPlainAT, r, r, Dk, X, Y, Cm);      // X^T H_k X
+  launch_sw_shift(Cm, r, Bm, dshift, st);
+  double *Ub = nullptr, *sb = nullptr;
+  psd_eigen(c, Bm, r, max_sweeps, Ub, sb);
+  gemm(kOhPlain, Dk, 1, r, X, Ub, ck);       // c' = X y (y: the first vector)
+  double hs[2];
+  TNQE_HIP(hipMemcpyAsync(&hs[0], dshift, sizeof(double), hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(&hs[1], sb, sizeof(double), hipMemcpyDeviceToHost, st));
+  c.sync();
+  out.E1 = hs[0] - hs[1];
+  out.accepted = out.E1 < out.E_old + so.e_tol ? 1 : 0;
+  // 5. parameter update into the dense two-site tensor T[l][k_p][k_{p+1}][r]
+  std::vector<int> col(n);
+  for (int m = 0; m < n; ++m) col[m] = col_of[ei + m];
+  const int Dp = dv.Dp, Dq = dv.Dq;
+  const int64_t tsize = (int64_t)Dp * 16 * Dq;
+  double *dT = c.dev<double>(tsize), *dtn = c.dev<double>(n), *dstat = c.dev<double>(2);
+  launch_sw_update(ck, c.upload(col), dv.Sc + ei, M, n, dv.d_dense, dT, tsize, dtn, dstat, st);
+  out.tnew.resize(n);
+  TNQE_HIP(hipMemcpyAsync(out.tnew.data(), dtn, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  c.sync();
+  // 6. rotation of the bond
+  const Gate16 ident = givens_gate(0.0);
+  Gate16 chosen = ident;
+  if (so.rotation == TNQE_ROT_NONE) {
+    out.xi_none = truncation_errors(c, ci, p, dT, {ident}, chi_cap, max_sweeps)[0];
+    out.xi = out.xi_none;
+  } else if (so.rotation == TNQE_ROT_FSWAP) {
+    const Gate16 f = fswap_gate();
+    const std::vector<double> x = truncation_errors(c, ci, p, dT, {ident, f}, chi_cap, max_sweeps);
+    out.xi_none = out.xi = x[0];
+    if (x[1] < x[0] - kXiTol) {
+      out.theta = M_PI / 2;
+      out.xi = x[1];
+      chosen = f;
+    }
+  } else {
+    // theta_opt: the grid, then golden-section steps on one spacing either
+    // side of its best point
+    std::vector<Gate16> gg;
+    std::vector<double> grid(n_grid);
+    for (int q = 0; q < n_grid; ++q) {
+      grid[q] = (double)(q - n_grid / 2) * (M_PI / n_grid);
+      gg.push_back(givens_gate(grid[q]));
+    }
+    const std::vector<double> vals = truncation_errors(c, ci, p, dT, gg, chi_cap, max_sweeps);
+    int qb = 0;
+    for (int q = 1; q < n_grid; ++q)
+      if (vals[q] < vals[qb]) qb = q;
+    const double xi0 = vals[n_grid / 2];
+    out.xi_none = xi0;
+    auto f = [&](double th) { return truncation_errors(c, ci, p, dT, {givens_gate(th)}, chi_cap, max_sweeps)[0]; };
+    const double h = M_PI / n_grid, gr = (std::sqrt(5.0) - 1.0) / 2.0;
+    double a = grid[qb] - h, b = grid[qb] + h;
+    double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+    double f1 = f(x1), f2 = f(x2);
+    for (int it = 0; it < n_golden; ++it) {
+      if (f1 <= f2) {
+        b = x2;
+        x2 = x1;
+        f2 = f1;
+        x1 = b - gr * (b - a);
+        f1 = f(x1);
+      } else {
+        a = x1;
+        x1 = x2;
+        f1 = f2;
+        x2 = a + gr * (b - a);
+        f2 = f(x2);
+      }
+    }
+    double th = f1 <= f2 ? x1 : x2, fv = f1 <= f2 ? f1 : f2;
+    if (vals[qb] < fv) {
+      th = grid[qb];
+      fv = vals[qb];
+    }
+    if (!(fv < xi0 - kXiTol)) {
+      th = 0.0;
+      fv = xi0;
+    }
+    out.theta = th;
+    out.xi = fv;
+    chosen = givens_gate(th);
+  }
+  // 7. truncation of the rotated tensor (rule of the gates) and the new sites
+  RotatedBlocks rb;
+  rotated_blocks(c, ci, p, dT, {chosen}, max_sweeps, rb);
+  std::vector<std::vector<double>> sv(rb.blks.size());
+  for (size_t q = 0; q < rb.blks.size(); ++q) {
+    sv[q].resize(rb.blks[q].n);
+    TNQE_HIP(hipMemcpyAsync(sv[q].data(), rb.scratch + rb.blks[q].offS, sv[q].size() * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+  }
+  c.sync();
+  std::vector<double> all;
+  std::vector<int> owner;
+  for (size_t q = 0; q < sv.size(); ++q)
+    for (double v : sv[q]) {
+      all.push_back(v);
+      owner.push_back((int)q);
+    }
+  double total = 0.0;
+  for (double v : all) total += v * v;
+  int nnz = 0;
+  for (double v : all) nnz += v * v > op.tau_w * total ? 1 : 0;
+  const int keep_n = std::min(chi_cap, nnz);
+  std::vector<int> order(all.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x] > all[y]; });
+  std::vector<int> kept(rb.blks.size(), 0);
+  double kept_w = 0.0;
+  for (int q = 0; q < keep_n; ++q) {
+    kept[owner[order[q]]]++;
+    kept_w += all[order[q]] * all[order[q]];
+  }
+  out.discarded = 0.0;
+  for (int q = keep_n; q < (int)order.size(); ++q) out.discarded += all[order[q]] * all[order[q]];
+  (void)kept_w;
+  for (size_t q = 0; q < rb.blks.size(); ++q) rb.blks[q].kept = kept[q];
+  {
+    Blk *dblk = c.upload(rb.blks);
+    const std::vector<int> uf = unit_prefix(rb.blks, [](const Blk &b) { return factor_units(b); });
+    const int *duf = c.upload(uf);
+    launch_svd_factor(dblk, Units{duf, (int)rb.blks.size(), uf.back()}, rb.scratch, st);
+    c.check_launch();
+  }
+  std::vector<std::vector<double>> Uh(rb.blks.size()), Bh(rb.blks.size());
+  for (size_t q = 0; q < rb.blks.size(); ++q) {
+    const Blk &b = rb.blks[q];
+    Uh[q].resize((size_t)b.kept * b.R);
+    Bh[q].resize((size_t)b.kept * b.C);
+    if (b.kept == 0) continue;
+    TNQE_HIP(hipMemcpyAsync(Uh[q].data(), rb.scratch + b.offU, Uh[q].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    TNQE_HIP(hipMemcpyAsync(Bh[q].data(), rb.scratch + b.offB, Bh[q].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  // the canonical sites of state ei
+  std::vector<std::vector<double>> site(N);
+  for (int x = 0; x < N; ++x) {
+    site[x].resize((size_t)ci.htot[x] * 4 * ci.htot[x + 1]);
+    TNQE_HIP(hipMemcpyAsync(site[x].data(), ci.site_ptr[x], site[x].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  c.sync();
+  const int Dn = keep_n;
+  out.new_bond = Dn;
+  std::vector<double> Ap((size_t)Dp * 4 * Dn, 0.0), Aq((size_t)Dn * 4 * Dq, 0.0);
+  std::vector<int32_t> newq;
+  {
+    auto offp = [&](int a, int b2) { return ci.off_q(p, 0, a, b2); };
+    auto offq = [&](int a, int b2) { return ci.off_q(p + 2, 0, a, b2); };
+    int j0 = 0;
+    for (size_t q = 0; q < rb.blks.size(); ++q) {
+      const Blk &b = rb.blks[q];
+      for (int j = 0; j < b.kept; ++j) {
+        newq.push_back(b.sa);
+        newq.push_back(b.sb);
+        for (int row = 0; row < b.R; ++row) {
+          int kp = 0;
+          while (row >= b.rs[kp + 1]) ++kp;
+          const int l = offp(b.sa - qk_a(kp), b.sb - qk_b(kp)) + row - b.rs[kp];
+          Ap[((size_t)l * 4 + kp) * Dn + j0 + j] = Uh[q][(size_t)j * b.R + row];
+        }
+        for (int cl = 0; cl < b.C; ++cl) {
+          int kq = 0;
+          while (cl >= b.cs[kq + 1]) ++kq;
+          const int rr = offq(b.sa + qk_a(kq), b.sb + qk_b(kq)) + cl - b.cs[kq];
+          Aq[((size_t)(j0 + j) * 4 + kq) * Dq + rr] = Bh[q][(size_t)j * b.C + cl];
+        }
+      }
+      j0 += b.kept;
+    }
+  }
+  site[p] = std::move(Ap);
+  site[p + 1] = std::move(Aq);
+  out.bond_dim.assign(N + 1, 0);
+  out.bond_qn.clear();
+  for (int bd = 0; bd <= N; ++bd) {
+    if (bd == p + 1) {
+      out.bond_dim[bd] = Dn;
+      out.bond_qn.insert(out.bond_qn.end(), newq.begin(), newq.end());
+      continue;
+    }
+    out.bond_dim[bd] = ci.htot[bd];
+    for (int s2 = 0; s2 < nslot; ++s2)
+      for (int d = 0; d < ci.dim(bd, 0, s2); ++d) {
+        out.bond_qn.push_back(s2 / (pb.nb + 1));
+        out.bond_qn.push_back(s2 % (pb.nb + 1));
+      }
+  }
+  out.sites.clear();
+  for (int x = 0; x < N; ++x) out.sites.insert(out.sites.end(), site[x].begin(), site[x].end());
+  // 8. merge: g4(theta) on the sites is G(R_p(theta)), compensated by
+  // U <- U R_p(theta)^T; the FSWAP is G(P) with P exchanging p and p+1
+  out.U = pb.mps[ei].U;
+  if (out.theta != 0.0) {
+    std::vector<double> &U = out.U;
+    if (so.rotation == TNQE_ROT_FSWAP) {
+      for (int r2 = 0; r2 < N; ++r2) std::swap(U[(size_t)r2 * N + p], U[(size_t)r2 * N + p + 1]);
+    } else {
+      const double cth = std::cos(out.theta), sth = std::sin(out.theta);
+      for (int r2 = 0; r2 < N; ++r2) {
+        const double u0 = U[(size_t)r2 * N + p], u1 = U[(size_t)r2 * N + p + 1];
+        U[(size_t)r2 * N + p] = cth * u0 + sth * u1;
+        U[(size_t)r2 * N + p + 1] = -sth * u0 + cth * u1;
+      }
+    }
+  }
 }
 
 // Upper bound of the device memory one solve takes from its pool (bytes):
@@ -3456,6 +3934,62 @@ tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32
   std::memcpy(Hc, oh.Hc.data(), oh.Hc.size() * sizeof(double));
   std::memcpy(Sc, oh.Sc.data(), oh.Sc.size() * sizeof(double));
   if (rep) *rep = r;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_sweep_step(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
+                            const tnqe_options *opts, const tnqe_sweep_options *sw, int32_t i, int32_t p,
+                            const double *H, const double *S, int32_t *bond_dim, int32_t *bond_qn, int64_t qn_cap,
+                            double *sites, int64_t sites_cap, double *U, tnqe_sweep_result *res,
+                            tnqe_report *rep) {
+  if (!ctx || !ham || !mps || !opts || !sw || !H || !S || !bond_dim || !bond_qn || !sites || !U || !res)
+    return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (check_options(ctx, opts) != TNQE_OK) return TNQE_EINVAL;
+  SweepOut out;
+  tnqe_report r{};
+  tnqe_problem pb;
+  tnqe_status st = guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    load_problem(ctx, ham, M, mps, &pb);
+    require(i >= 0 && i < M, TNQE_EINVAL, "expanded state out of range");
+    require(p >= 0 && p + 1 < pb.N, TNQE_EINVAL, "two-site position out of range");
+    place_sites(ctx, &pb, mps);
+    sweep_one(ctx, pb, *opts, *sw, i, p, H, S, out, r);
+    ctx->pool.release_all();
+    require((int64_t)out.bond_qn.size() / 2 <= qn_cap, TNQE_ESHAPE,
+            "qn_cap too small: " + std::to_string(out.bond_qn.size() / 2) + " labels");
+    require((int64_t)out.sites.size() <= sites_cap, TNQE_ESHAPE,
+            "sites_cap too small: " + std::to_string(out.sites.size()) + " doubles");
+  });
+  free_sites(&pb);
+  if (st != TNQE_OK) return st;
+  std::memcpy(bond_dim, out.bond_dim.data(), out.bond_dim.size() * sizeof(int32_t));
+  std::memcpy(bond_qn, out.bond_qn.data(), out.bond_qn.size() * sizeof(int32_t));
+  std::memcpy(sites, out.sites.data(), out.sites.size() * sizeof(double));
+  std::memcpy(U, out.U.data(), out.U.size() * sizeof(double));
+  tnqe_sweep_result q{};
+  q.E_old = out.E_old;
+  q.E1 = out.E1;
+  q.theta = out.theta;
+  q.xi_none = out.xi_none;
+  q.xi = out.xi;
+  q.discarded = out.discarded;
+  q.n_onehot = out.n;
+  q.n_columns = out.D;
+  q.n_kept = out.n_kept;
+  q.n_dropped_S = out.n_dropped_S;
+  q.accepted = out.accepted;
+  q.new_bond = out.new_bond;
+  *res = q;
+  ctx->sweep_t = std::move(out.tnew);
+  if (rep) *rep = r;
+  return TNQE_OK;
+}
+
+tnqe_status tnqe_sweep_last_params(tnqe_ctx *ctx, int32_t n, double *t) {
+  if (!ctx || !t) return ctx ? fail(ctx, TNQE_EINVAL, "null argument") : TNQE_EINVAL;
+  if (n != (int32_t)ctx->sweep_t.size()) return fail(ctx, TNQE_EINVAL, "n differs from the last sweep step's");
+  std::memcpy(t, ctx->sweep_t.data(), ctx->sweep_t.size() * sizeof(double));
   return TNQE_OK;
 }
 

@@ -164,6 +164,7 @@ struct tnqe_ctx {
   // and written to a file on first use of autotuning
   std::map<std::array<int, 5>, std::pair<int, int>> tiles;
   bool tiles_loaded = false;
+  std::vector<double> sweep_t;        // parameters t'_m of the last sweep step
   // contexts of the batch workers (same device, each with a stream of its
   // own), created on first use and destroyed with this context
   std::vector<tnqe_ctx *> sub;

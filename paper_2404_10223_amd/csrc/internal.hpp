@@ -346,6 +346,24 @@ void launch_oh_gather(const double *V, const double *S, double f, const int *idx
 void launch_oh_sd(const int4 *oh, int n, const double *LS, int Db, const double *RS, int Db2, double e_core,
                   double *Sd, double *Hd, hipStream_t st);
 
+// ------------------------------------------------- generalized-sweep step
+// expanded pencil (H', S') [D][D] in the combined order (code: see kernel)
+void launch_sw_assemble(const int *code, int D, int n, int M, const double *H, const double *S, const double *Hd,
+                        const double *Sd, const double *Hc, const double *Sc, double *Hx, double *Sx, hipStream_t st);
+// keep[j] for the columns of S taken in order (A: a copy of S, overwritten)
+void launch_sw_discard(double *A, const double *S, int D, double tol, int *keep, hipStream_t st);
+void launch_sw_gather(const double *Hx, const double *Sx, int D, const int *kidx, int Dk, double *Hk, double *Sk,
+                      hipStream_t st);
+void launch_sw_whiten(const double *U, const double *lam, int Dk, int r, double *X, hipStream_t st);
+void launch_sw_shift(const double *C, int r, double *B, double *out, hipStream_t st);
+void launch_sw_update(const double *ck, const int *col, const double *told, int told_ld, int n, const int *dense_of,
+                      double *T, int64_t tsize, double *tnew, double *stats, hipStream_t st);
+void launch_sw_gate_blocks(const Blk *blk, int nblk, const double *gates, const double *T, int Dq, const int *offp,
+                           const int *offq, int na, int nb1, double *scratch, hipStream_t st);
+constexpr int kXiMaxValues = 8192;   // singular values per gate in k_sw_xi (LDS)
+void launch_sw_xi(const Blk *blk, const int *first, int ngate, int max_values, const double *scratch, int chi,
+                  double *xi, hipStream_t st);
+
 // -------------------------------------------------------------- eigensolve
 // For each subspace s: H, S at offs[s] ([M_s][M_s] row-major); writes
 // out[s * (8 + kMaxM) + ...] = E, cond_S, lambda_min, n_dropped, kappa1, status, -, -, c[0..M_s).

@@ -1,0 +1,126 @@
+"""One generalized-sweep step (Alg. A.1, App. A1-A3) on the GPU through the C
+ABI against the oracle (oracle.sweep), on the same inputs: the current pencil
+(H, S) is the oracle's stored one for the workload.
+
+Compared: the sizes and the discard decisions (exact), E_old and E1 (1e-10
+relative), the updated parameters t' (1e-8, eigenvector accuracy of a
+pencil of condition ~1e3 after the discard), the rotation decision (FSWAP:
+exact; Givens: theta within 1e-6 -- xi is flat at its minimum -- and xi at
+the two angles within 1e-12), the truncation (kept count exact, discarded
+weight 1e-12), the truncated two-site product A_p A_{p+1} against the
+oracle's truncation of its own update at the GPU's angle (1e-8), the other
+sites of the canonical form (1e-10; the gauge is fixed by the non-negative
+triangular diagonal), the bond labels (exact) and the merged basis U (1e-10).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2404_10223_amd as T
+import tnqe_synth as synth
+from oracle import sweep
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _pair(k):
+    prob = synth.make_config(k)
+    g = np.load(os.path.join(GOLD, f"oracle_config{k}.npz"))
+    return prob, g["H"], g["S"]
+
+
+def _duplicate():
+    """Config 1 with a third state equal to state 1: expanding state 1, the
+    copy lies in the span of its one-hot states and is discarded."""
+    from oracle.subspace import subspace as oracle_subspace
+    prob = synth.make_config(1)
+    p2 = synth.Problem(prob.N, prob.n_alpha, prob.n_beta, prob.h, prob.L, prob.e_core, prob.chi,
+                       list(prob.mps) + [prob.mps[1]], name="config1_dup")
+    H, S, _, _, _ = oracle_subspace(p2)
+    return p2, H, S
+
+
+# (workload, state, site, rotation): no cut / cut at the bond, FSWAP taken and
+# not taken, Givens with and without a gain, a discarded column
+CASES = [(1, 0, 1, "none"), (1, 1, 0, "fswap"), (1, 1, 2, "givens"), (2, 2, 3, "none"), (2, 2, 3, "fswap"),
+         (2, 1, 3, "fswap"), (2, 3, 2, "givens"), (2, 0, 5, "givens"), ("dup", 1, 1, "none")]
+
+
+@pytest.mark.parametrize("k,i,p,rotation", CASES)
+def test_sweep_step_matches_oracle(ctx, k, i, p, rotation):
+    prob, H, S = _duplicate() if k == "dup" else _pair(k)
+    print(f"config {k} state {i} sites ({p}, {p + 1}) rotation {rotation}", flush=True)
+    res, (sites, qn, U), t, rep = ctx.sweep_step(prob, H, S, i, p, rotation=rotation, chi=prob.chi)
+    o = sweep.sweep_step(prob, H, S, i, p, rotation=rotation)
+    print(f"E_old {res['E_old']:.12f} E1 {res['E1']:.12f} ({o['E1']:.12f}) kept {res['n_kept']}/{res['n_columns']} "
+          f"theta {res['theta']:.9f} ({o['theta']:.9f}) xi {res['xi']:.3e} bond {res['new_bond']}", flush=True)
+    assert res["n_onehot"] == o["n_onehot"] and res["n_columns"] == len(o["keep"])
+    assert res["n_kept"] == int(o["keep"].sum())
+    assert res["n_dropped_S"] == o["n_dropped_S"]
+    assert abs(res["E_old"] - o["E_old"]) <= 1e-12 * abs(o["E_old"])
+    assert abs(res["E1"] - o["E1"]) <= 1e-10 * abs(o["E1"])
+    assert res["accepted"] == int(o["accepted"])
+    np.testing.assert_allclose(t, o["t_new"], atol=1e-8)
+    assert abs(res["xi_none"] - o["xi_none"]) <= 1e-12
+    if rotation == "givens":
+        assert abs(res["theta"] - o["theta"]) <= 1e-6
+        assert abs(res["xi"] - o["xi"]) <= 1e-12
+    else:
+        assert res["theta"] == o["theta"]
+        assert abs(res["xi"] - o["xi"]) <= 1e-12
+    # the oracle's truncation of its update at the GPU's angle
+    s_o, q_o, U_o, _, st = sweep.finish(o["T4"], o["canon_sites"], o["canon_qn"], prob.mps[i].U, p, rotation,
+                                        res["theta"], prob.chi, 1e-13)
+    assert res["new_bond"] == st["kept"]
+    assert abs(res["discarded"] - st["discarded"]) <= 1e-12
+    for b in range(prob.N + 1):
+        np.testing.assert_array_equal(qn[b], q_o[b])
+    two = lambda s: np.einsum("akm,mlb->aklb", s[p], s[p + 1])
+    np.testing.assert_allclose(two(sites), two(s_o), atol=1e-8)
+    for x in range(prob.N):
+        if x not in (p, p + 1):
+            np.testing.assert_allclose(sites[x], s_o[x], atol=1e-10)
+    A = sites[p].reshape(-1, sites[p].shape[2])
+    np.testing.assert_allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
+    np.testing.assert_allclose(U, U_o, atol=1e-10)
+
+
+def test_sweep_step_result_feeds_the_subspace(ctx):
+    """The updated state goes back through tnqe_subspace.  Expanding state 0
+    without a rotation, every element of the new pencil that involves it uses
+    the same rotated kets as the expanded pencil, and the truncated state lies
+    in the span of its one-hot states: the new lowest root is not below E1,
+    and the new norm is 1 minus the discarded weight."""
+    prob, H, S = _pair(2)
+    res, (sites, qn, U), t, _ = ctx.sweep_step(prob, H, S, 0, 2, chi=prob.chi)
+    p2 = synth.Problem(prob.N, prob.n_alpha, prob.n_beta, prob.h, prob.L, prob.e_core, prob.chi,
+                       list(prob.mps), name="updated")
+    p2.mps[0] = synth.MPS(sites, qn, U)
+    H2, S2, E2, c2, _ = ctx.subspace(p2, chi=prob.chi)
+    print(f"E_old {res['E_old']:.10f} E1 {res['E1']:.10f} after truncation {E2:.10f} "
+          f"(discarded {res['discarded']:.2e})", flush=True)
+    assert res["discarded"] > 0.0
+    assert E2 >= res["E1"] - 1e-10 * abs(E2)
+    assert abs(S2[0, 0] - (1.0 - res["discarded"])) < 1e-10
+
+
+def test_sweep_step_errors(ctx):
+    prob, H, S = _pair(1)
+    with pytest.raises(T.TnqeError) as e:
+        ctx.sweep_step(prob, H, S, 0, prob.N - 1, chi=prob.chi)
+    assert e.value.status == -1
+    with pytest.raises(T.TnqeError) as e:
+        ctx.sweep_step(prob, H, S, 0, 1, rotation="givens", n_grid=35, chi=prob.chi)
+    assert e.value.status == -1
+    # the context still works
+    res, _, _, _ = ctx.sweep_step(prob, H, S, 0, 1, chi=prob.chi)
+    assert np.isfinite(res["E1"])

@@ -158,6 +158,6 @@ def test_fswap_decision_and_acceptance():
     rf = sweep.sweep_step(prob, H, S, 1, 3, rotation="fswap")
     T4, qn, p = rf["T4"], rf["canon_qn"], 3
     xs = sweep.xi(sweep.apply_gate(T4, gates.f4()), qn[p], qn[p + 2], prob.chi)
-    assert (rf["theta"] != 0.0) == (xs < rf["xi_none"])
+    assert (rf["theta"] != 0.0) == (xs < rf["xi_none"] - 1e-12)
     assert rf["xi"] == (xs if rf["theta"] != 0.0 else rf["xi_none"])
     assert rf["accepted"] == (rf["E1"] < rf["E_old"])
