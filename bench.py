@@ -255,6 +255,41 @@ def batch_line(ctx, steps):
     return out
 
 
+def sweep_line(ctx, steps, with_cpu):
+    """One generalized-sweep step (Alg. A.1: expanded pencil of one state at
+    one bond, discard, expanded root, parameter update, Givens angle search,
+    truncation) at N = 7 (chi = 16, state 3, sites 2-3) and N = 12 (chi = 64,
+    state 0, sites 1-2), the current pencil from the library; the oracle's
+    time for the N = 7 step when the CPU leg runs."""
+    import torch
+    import tnqe_synth as synth
+    out = {}
+    for k, i, p in ((2, 3, 2), (3, 0, 1)):
+        prob = synth.make_config(k)
+        H, S, E, c, _ = ctx.subspace(prob, chi=prob.chi)
+        ctx.sweep_step(prob, H, S, i, p, rotation="givens", chi=prob.chi)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, steps)):
+            res, _, _, rep = ctx.sweep_step(prob, H, S, i, p, rotation="givens", chi=prob.chi)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / max(1, steps) * 1e3
+        d = {"workload": f"N={prob.N}, chi={prob.chi}, M={prob.M}, state {i}, sites {p}-{p + 1}, Givens rotation",
+             "ms_per_step": ms, "one_hot_states": res["n_onehot"], "columns": res["n_columns"],
+             "kept_columns": res["n_kept"], "E_old": res["E_old"], "E1": res["E1"], "theta": res["theta"],
+             "xi_none": res["xi_none"], "xi": res["xi"], "pencil_networks_ms": rep["t_gates_ms"],
+             "pencil_contractions_ms": rep["t_env_ms"]}
+        if with_cpu and k == 2:
+            from oracle import sweep as osweep
+            t1 = time.perf_counter()
+            osweep.sweep_step(prob, H, S, i, p, rotation="givens")
+            d["cpu_oracle_ms"] = (time.perf_counter() - t1) * 1e3
+        out[f"N{prob.N}"] = d
+        log(f"  sweep step N={prob.N}: {ms:.1f} ms (E_old {res['E_old']:.6f} -> E1 {res['E1']:.6f}, "
+            f"theta {res['theta']:.4f})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +298,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--rotations", choices=["expm", "perm", "identity"], default="expm",
                     help="orbital rotations of the MPS: random (TNQE, the headline workload), "
                          "permutations (fermionic-swap networks, TNQE-F) or none (LC-MPS)")
@@ -333,6 +369,7 @@ def main():
                            "max_rel_dS": float(np.max(np.abs(Sm - S) / np.maximum(np.abs(S), 1e-300)))}
             log(f"  {name}: dE {dE:.2e} Ha, {tm * 1e3:.1f} ms per solve")
     batch = None if args.no_batch else batch_line(ctx, args.steps)
+    sweep = None if args.no_sweep else sweep_line(ctx, args.steps, not args.no_cpu)
     roof = roofline(rep)
     cpu = None
     if not args.no_cpu:
@@ -353,7 +390,7 @@ def main():
                                                    "svd_kernel_ms", "svd_flops", "move_kernel_ms", "move_flops",
                                                    "move_launches", "t_moves_ms", "env_kernel_ms", "env_flops",
                                                    "alg_bytes")},
-            "mixed": mixed, "autotune_ms": tune_ms, "batch": batch, "roofline": roof,
+            "mixed": mixed, "autotune_ms": tune_ms, "batch": batch, "sweep_step": sweep, "roofline": roof,
             "kernels": kernel_breakdown(rep), "cpu_baseline": cpu,
             "pcie_inclusive": {"upload_ms": upload_s * 1e3, "value": n_pairs / (t64 + upload_s),
                                "note": "one host-to-HBM upload of the integrals and the 16 MPS (first upload of "

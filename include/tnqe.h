@@ -318,7 +318,9 @@ tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32
  * sizes + 4 chi (bond_dim[p] + bond_dim[p+2]) always suffice; smaller
  * capacities that do not hold the result give TNQE_ESHAPE (outputs
  * untouched).  D = n + M - 1 <= 1024 (TNQE_ESHAPE beyond); M <= 32.  Device
- * memory from the context's pool. */
+ * memory from the context's pool.  rep: t_gates_ms and t_env_ms as for
+ * tnqe_onehot_pencil, t_gep_ms (steps 2-4), t_total_ms (the whole step; the
+ * rest is steps 5-7). */
 typedef enum { TNQE_ROT_NONE = 0, TNQE_ROT_FSWAP = 1, TNQE_ROT_GIVENS = 2 } tnqe_rotation;
 typedef struct {
   int32_t rotation;      /* tnqe_rotation */

@@ -2953,6 +2953,7 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
 void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tnqe_sweep_options &so, int ei, int p,
                const double *H, const double *S, SweepOut &out, tnqe_report &rep) {
   Call c{ctx};
+  const auto t0 = Clock::now();
   hipStream_t st = ctx->stream;
   const int M = pb.M, N = pb.N, nslot = pb.nslot();
   require(M <= kMaxM, TNQE_ESHAPE, "more than 32 states");
@@ -2987,6 +2988,7 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
   out.n = n;
   out.D = D;
   require(D <= 1024, TNQE_ESHAPE, "expanded pencil wider than 1024 columns");
+  const auto tg = Clock::now();
   // 2. combined order of eq. subs_exp and assembly
   std::vector<int> code(D);
   for (int a = 0; a < D; ++a) code[a] = a < ei ? -(a + 1) : a < ei + n ? a - ei : -(a - n + 1 + 1);
@@ -3057,19 +3059,19 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
   out.tnew.resize(n);
   TNQE_HIP(hipMemcpyAsync(out.tnew.data(), dtn, n * sizeof(double), hipMemcpyDeviceToHost, st));
   c.sync();
-  // 6. rotation of the bond
+  rep.t_gep_ms = ms_since(tg);
+  // 6. rotation of the bond (nothing to gain when xi(0) is below the
+  // tolerance: xi is not negative, so no rotation lowers it by more)
   const Gate16 ident = givens_gate(0.0);
   Gate16 chosen = ident;
-  if (so.rotation == TNQE_ROT_NONE) {
-    out.xi_none = truncation_errors(c, ci, p, dT, {ident}, chi_cap, max_sweeps)[0];
-    out.xi = out.xi_none;
+  out.xi_none = out.xi = truncation_errors(c, ci, p, dT, {ident}, chi_cap, max_sweeps)[0];
+  if (so.rotation == TNQE_ROT_NONE || out.xi_none < kXiTol) {
   } else if (so.rotation == TNQE_ROT_FSWAP) {
     const Gate16 f = fswap_gate();
-    const std::vector<double> x = truncation_errors(c, ci, p, dT, {ident, f}, chi_cap, max_sweeps);
-    out.xi_none = out.xi = x[0];
-    if (x[1] < x[0] - kXiTol) {
+    const double xs = truncation_errors(c, ci, p, dT, {f}, chi_cap, max_sweeps)[0];
+    if (xs < out.xi_none - kXiTol) {
       out.theta = M_PI / 2;
-      out.xi = x[1];
+      out.xi = xs;
       chosen = f;
     }
   } else {
@@ -3086,7 +3088,6 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
     for (int q = 1; q < n_grid; ++q)
       if (vals[q] < vals[qb]) qb = q;
     const double xi0 = vals[n_grid / 2];
-    out.xi_none = xi0;
     auto f = [&](double th) { return truncation_errors(c, ci, p, dT, {givens_gate(th)}, chi_cap, max_sweeps)[0]; };
     const double h = M_PI / n_grid, gr = (std::sqrt(5.0) - 1.0) / 2.0;
     double a = grid[qb] - h, b = grid[qb] + h;
@@ -3242,6 +3243,7 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
       }
     }
   }
+  rep.t_total_ms = ms_since(t0);
 }
 
 // Upper bound of the device memory one solve takes from its pool (bytes):
