@@ -278,7 +278,8 @@ def sweep_line(ctx, steps, with_cpu):
              "ms_per_step": ms, "one_hot_states": res["n_onehot"], "columns": res["n_columns"],
              "kept_columns": res["n_kept"], "E_old": res["E_old"], "E1": res["E1"], "theta": res["theta"],
              "xi_none": res["xi_none"], "xi": res["xi"], "pencil_networks_ms": rep["t_gates_ms"],
-             "pencil_contractions_ms": rep["t_env_ms"]}
+             "pencil_contractions_ms": rep["t_env_ms"], "discard_and_eigensolve_ms": rep["t_gep_ms"],
+             "step_ms_in_library": rep["t_total_ms"]}
         if with_cpu and k == 2:
             from oracle import sweep as osweep
             t1 = time.perf_counter()
