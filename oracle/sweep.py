@@ -211,16 +211,10 @@ def finish(T4, sites, qn, U, p, rotation, theta, chi_cap, tau_w):
     return s2, q2, U, T4, st
 
 
-def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_tol=0.0, chi_cap=None,
-               tau_w=1e-13, n_grid=36, n_golden=40, xi_tol=1e-12):
-    """Steps 1-8 above.  H, S: the current pencil.  Returns a dict."""
-    assert rotation in ROTATIONS
-    chi_cap = prob.chi if chi_cap is None else chi_cap
-    M = prob.M
-    bi = prob.mps[i]
-    sites, qn = canonical_at(bi.sites, bi.bond_qn, p)
-    index, Hd, Sd, Hc, Sc, t = onehot_pencil(prob, i, p, chi_cap, tau_w)
-    n = len(index)
+def solve_expanded(H, S, Hd, Sd, Hc, Sc, i, t_cur, tol_ld, eps_S):
+    """Steps 2-4 on an expanded pencil whose state-i block is spanned by an
+    orthonormal set (Hd, Sd, Hc, Sc as in oracle.onehot): the discard, the
+    lowest root and the normalised, signed coefficients of that set."""
     Hx, Sx, pos = expanded_pencil(H, S, Hd, Sd, Hc, Sc, i)
     keep = discard_dependent(Sx, tol_ld)
     kidx = np.nonzero(keep)[0]
@@ -230,9 +224,143 @@ def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_to
     tn = c[pos]
     nrm = np.linalg.norm(tn)
     tn = tn / nrm if nrm > 0.0 else tn
-    ov = float(tn @ t)
+    ov = float(tn @ t_cur)
     if ov < 0.0 or (ov == 0.0 and tn[np.argmax(np.abs(tn))] < 0.0):
         tn = -tn
+    return sol, keep, pos, tn
+
+
+def onehot_gate_matrix(index, G16):
+    """[G]_{m'm}: the new one-hot state m (after the gate G16 on the sites was
+    merged into the orbital basis) in the old one-hot basis, i.e. the
+    coefficient G16[(k_p, k_{p+1})_m, (k_p, k_{p+1})_m'] for equal (l, r)
+    (App. A4: the rotation represented in the one-hot basis)."""
+    n = len(index)
+    at = {e: m for m, e in enumerate(index)}
+    G = np.zeros((n, n))
+    for m, (l, kp, kq, r) in enumerate(index):
+        for x in range(16):
+            m2 = at.get((l, x >> 2, x & 3, r))
+            if m2 is not None:
+                G[m2, m] = G16[kp * 4 + kq, x]
+    return G
+
+
+def single_site_index(qn_l, qn_r):
+    """One-hot entries (a, k, b) of a single-site tensor [dl, 4, dr] that
+    conserve the particle numbers, row-major."""
+    out = []
+    for a in range(qn_l.shape[0]):
+        for k in range(4):
+            want = qn_l[a] + QK[k]
+            for b in range(qn_r.shape[0]):
+                if qn_r[b][0] == want[0] and qn_r[b][1] == want[1]:
+                    out.append((a, k, b))
+    return out
+
+
+def _positive_split(A, qn_l, qn_r, left):
+    """Exact QR (left=True: A[(a,k), b] = Q R with Q over rows (a, k)) or LQ
+    (A[a, (k,b)] = L Q) of a single-site tensor per sector, non-negative
+    triangular diagonal, bond kept as is.  Returns (orthonormal factor as a
+    site tensor, triangle)."""
+    dl, _, dr = A.shape
+    if left:
+        rowq = (qn_l[:, None, :] + QK[None, :, :]).reshape(-1, 2)
+        M = A.reshape(dl * 4, dr)
+        Q = np.zeros_like(M)
+        R = np.zeros((dr, dr))
+        for s in mpsops._sectors(qn_r):
+            cols = mpsops._where(qn_r, s)
+            rows = mpsops._where(rowq, s)
+            q, r = mpsops._positive_qr(M[np.ix_(rows, cols)])
+            Q[np.ix_(rows, cols)] = q
+            R[np.ix_(cols, cols)] = r
+        return Q.reshape(dl, 4, dr), R
+    colq = (qn_r[None, :, :] - QK[:, None, :]).reshape(-1, 2)
+    M = A.reshape(dl, 4 * dr)
+    Q = np.zeros_like(M)
+    L = np.zeros((dl, dl))
+    for s in mpsops._sectors(qn_l):
+        rows = mpsops._where(qn_l, s)
+        cols = mpsops._where(colq, s)
+        q, r = mpsops._positive_qr(M[np.ix_(rows, cols)].T)
+        Q[np.ix_(rows, cols)] = q.T
+        L[np.ix_(rows, rows)] = r.T
+    return Q.reshape(dl, 4, dr), L
+
+
+def mitigate(prob, H, S, i, p, index, Hd, Sd, Hc, Sc, G16, Ap, Aq, qn, newq, nreps, tol_ld, eps_S):
+    """App. A4: the two-site pencil moved to the rotated basis
+    (H^[ii] -> G^T H^[ii] G, H^[ik] -> G^T H^[ik]), then nreps rounds of
+    single-site expansions at p and p+1.  For site p the two-site state is
+    (U Sigma) V with V right-orthonormal; the single-site one-hot states times
+    V map to the two-site one-hot states by the isometry T[m1, n] =
+    V[b, k_{p+1}, r] where (l, k_p) agree, and the pencil becomes T H T^T
+    (and T H^[ik] for the columns); the root updates U Sigma.  For site p+1
+    the left site is made orthonormal by an exact QR and the isometry is
+    T[m2, n] = Q[l, k_p, b] where (k_{p+1}, r) agree.  Returns the final
+    (A_p, A_{p+1}) (centre at p+1), the last root and the discard counts."""
+    Gm = onehot_gate_matrix(index, G16)
+    Hd2, Sd2 = Gm.T @ Hd @ Gm, Gm.T @ Sd @ Gm
+    Hc2, Sc2 = Gm.T @ Hc, Gm.T @ Sc
+    at = {e: m for m, e in enumerate(index)}
+    n = len(index)
+    qp, qq = qn[p], qn[p + 2]
+    last = None
+    for _ in range(nreps):
+        for site in (p, p + 1):
+            if site == p:
+                # site p+1 right-orthonormal: A_{p+1} = L Q
+                V, Lm = _positive_split(Aq, newq, qq, left=False)
+                T1 = np.einsum("akb,bc->akc", Ap, Lm)
+                sidx = single_site_index(qp, newq)
+                Tiso = np.zeros((len(sidx), n))
+                for m1, (l, kp, b) in enumerate(sidx):
+                    for kq in range(4):
+                        for r in range(qq.shape[0]):
+                            m2 = at.get((l, kp, kq, r))
+                            if m2 is not None:
+                                Tiso[m1, m2] = V[b, kq, r]
+            else:
+                # site p left-orthonormal: A_p = Q R
+                Q, Rm = _positive_split(Ap, qp, newq, left=True)
+                T1 = np.einsum("ab,bkc->akc", Rm, Aq)
+                sidx = single_site_index(newq, qq)
+                Tiso = np.zeros((len(sidx), n))
+                for m1, (b, kq, r) in enumerate(sidx):
+                    for l in range(qp.shape[0]):
+                        for kp in range(4):
+                            m2 = at.get((l, kp, kq, r))
+                            if m2 is not None:
+                                Tiso[m1, m2] = Q[l, kp, b]
+            t_cur = np.array([T1[e] for e in sidx])
+            sol, keep, pos, tn = solve_expanded(H, S, Tiso @ Hd2 @ Tiso.T, Tiso @ Sd2 @ Tiso.T, Tiso @ Hc2,
+                                                 Tiso @ Sc2, i, t_cur, tol_ld, eps_S)
+            T1n = np.zeros_like(T1)
+            for m1, e in enumerate(sidx):
+                T1n[e] = tn[m1]
+            if site == p:
+                Ap, Aq = T1n, V
+            else:
+                Ap, Aq = Q, T1n
+            last = (sol, keep)
+    return Ap, Aq, last
+
+
+def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_tol=0.0, chi_cap=None,
+               tau_w=1e-13, n_grid=36, n_golden=40, xi_tol=1e-12, nreps=0):
+    """Steps 1-8 above (with nreps > 0, the single-site mitigation of App. A4
+    after step 7; E_new is then its last root).  H, S: the current pencil.
+    Returns a dict."""
+    assert rotation in ROTATIONS
+    chi_cap = prob.chi if chi_cap is None else chi_cap
+    M = prob.M
+    bi = prob.mps[i]
+    sites, qn = canonical_at(bi.sites, bi.bond_qn, p)
+    index, Hd, Sd, Hc, Sc, t = onehot_pencil(prob, i, p, chi_cap, tau_w)
+    n = len(index)
+    sol, keep, pos, tn = solve_expanded(H, S, Hd, Sd, Hc, Sc, i, t, tol_ld, eps_S)
     dl, dr = sites[p].shape[0], sites[p + 1].shape[2]
     T4 = np.zeros((dl, 4, 4, dr))
     for m, (l, kp, kq, r) in enumerate(index):
@@ -247,7 +375,18 @@ def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_to
         theta, xi_rot, _ = optimise_theta(T4, qn[p], qn[p + 2], chi_cap, n_grid, n_golden, xi_tol)
     new_sites, new_qn, U_new, T4r, st = finish(T4, sites, qn, bi.U, p, rotation, theta, chi_cap, tau_w)
     E_old = solve_projection(H, S, eps_S)["E"]
-    return dict(E_old=E_old, E1=sol["E"], accepted=bool(sol["E"] < E_old + e_tol), keep=keep, pos=pos,
+    E_new, mit = sol["E"], None
+    if nreps > 0:
+        G16 = np.eye(16)
+        if theta != 0.0:
+            G16 = gates.g4(theta) if rotation == "givens" else gates.f4()
+        Ap, Aq, (msol, mkeep) = mitigate(prob, H, S, i, p, index, Hd, Sd, Hc, Sc, G16, new_sites[p],
+                                         new_sites[p + 1], qn, new_qn[p + 1], nreps, tol_ld, eps_S)
+        new_sites[p], new_sites[p + 1] = Ap, Aq
+        E_new = msol["E"]
+        mit = dict(E=msol["E"], n_kept=int(mkeep.sum()), n_columns=len(mkeep), n_dropped_S=msol["n_dropped"])
+    return dict(E_old=E_old, E1=sol["E"], E_new=E_new, mitigation=mit,
+                accepted=bool(E_new < E_old + e_tol), keep=keep, pos=pos,
                 n_onehot=n, index=index, t_old=t, t_new=tn, T4=T4, T4_rotated=T4r, theta=theta,
                 xi_none=xi_none, xi=xi_rot, canon_sites=sites, canon_qn=qn, sites=new_sites, qn=new_qn,
-                U=U_new, trunc=st, n_dropped_S=sol["n_dropped"], Hx=Hx, Sx=Sx)
+                U=U_new, trunc=st, n_dropped_S=sol["n_dropped"], onehot=(Hd, Sd, Hc, Sc))

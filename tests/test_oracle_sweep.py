@@ -161,3 +161,74 @@ def test_fswap_decision_and_acceptance():
     assert (rf["theta"] != 0.0) == (xs < rf["xi_none"] - 1e-12)
     assert rf["xi"] == (xs if rf["theta"] != 0.0 else rf["xi_none"])
     assert rf["accepted"] == (rf["E1"] < rf["E_old"])
+
+
+# ------------------------------------------------ single-site mitigation (App. A4)
+def test_onehot_gate_matrix_gives_the_rotated_basis():
+    """The rotation in the one-hot basis (App. A4) maps the expanded pencil to
+    the one computed directly in the merged orbital basis: G^T H^[ii] G equals
+    the diagonal block of the state with U_i R_p(theta)^T, and G is
+    orthogonal."""
+    from oracle.onehot import onehot_pencil
+    prob = synth.make_config(2)
+    H, S, E, c, _ = oracle_subspace(prob)
+    i, p = 3, 2
+    r = sweep.sweep_step(prob, H, S, i, p, rotation="givens")
+    assert r["theta"] != 0.0
+    Hd, Sd, Hc, Sc = r["onehot"]
+    G = sweep.onehot_gate_matrix(r["index"], gates.g4(r["theta"]))
+    np.testing.assert_allclose(G.T @ G, np.eye(len(G)), atol=1e-13)
+    # the same environments (canonical form of the same state), integrals in
+    # the merged basis
+    p2 = _with_state(prob, i, prob.mps[i].sites, prob.mps[i].bond_qn, r["U"])
+    idx2, Hd2, Sd2, _, _, _ = onehot_pencil(p2, i, p)
+    assert idx2 == r["index"]
+    np.testing.assert_allclose(G.T @ Hd @ G, Hd2, atol=1e-11)
+    np.testing.assert_allclose(Sd2, np.eye(len(G)), atol=1e-13)
+
+
+@pytest.mark.parametrize("nreps", [1, 2])
+def test_mitigated_state_reproduces_last_root(nreps):
+    """Lossless rotations: the state after the single-site expansions, put
+    back into an independent subspace evaluation, has the last root as its
+    lowest root (its optimum lies in the span of the other states and the
+    updated one)."""
+    prob = synth.make_config(1)
+    big = 4 ** prob.N
+    H, S, E, c, _ = oracle_subspace(prob, chi_cap=big)
+    r = sweep.sweep_step(prob, H, S, 1, 1, rotation="givens", chi_cap=big, tau_w=0.0, nreps=nreps)
+    assert r["mitigation"] is not None
+    p2 = _with_state(prob, 1, r["sites"], r["qn"], r["U"])
+    H2, S2, E2, _, _ = oracle_subspace(p2, chi_cap=big)
+    assert abs(E2 - r["E_new"]) < 1e-9 * (1 + abs(E2)), (E2, r["E_new"])
+    assert r["E_new"] >= r["E1"] - 1e-10
+    A = r["sites"][1].reshape(-1, r["sites"][1].shape[2])
+    np.testing.assert_allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
+
+
+def test_mitigation_improves_on_the_truncated_state():
+    """With a cut at the bond, the first single-site expansion contains the
+    truncated state itself, so the mitigated root is not above the truncated
+    state's energy in the same expanded pencil, nor below the two-site root."""
+    prob = synth.make_config(2)
+    H, S, E, c, _ = oracle_subspace(prob)
+    i, p = 3, 2
+    r = sweep.sweep_step(prob, H, S, i, p, rotation="givens", nreps=1)
+    Hd, Sd, Hc, Sc = r["onehot"]
+    G = sweep.onehot_gate_matrix(r["index"], gates.g4(r["theta"]))
+    s_t, _, _, _, st = sweep.finish(r["T4"], r["canon_sites"], r["canon_qn"], prob.mps[i].U, p, "givens",
+                                    r["theta"], prob.chi, 1e-13)
+    assert st["discarded"] > 1e-8
+    T2 = np.einsum("akm,mlb->aklb", s_t[p], s_t[p + 1])
+    x = np.array([T2[e] for e in r["index"]])
+    Hr, Sr = H.copy(), S.copy()
+    Hr[i, i], Sr[i, i] = x @ (G.T @ Hd @ G) @ x, x @ (G.T @ Sd @ G) @ x
+    for k in range(prob.M):
+        if k != i:
+            Hr[i, k] = Hr[k, i] = x @ (G.T @ Hc[:, k])
+            Sr[i, k] = Sr[k, i] = x @ (G.T @ Sc[:, k])
+    from oracle.gep import solve_projection
+    E_trunc = solve_projection(Hr, Sr)["E"]
+    print(r["E1"], r["E_new"], E_trunc)
+    assert r["E_new"] <= E_trunc + 1e-12
+    assert r["E_new"] >= r["E1"] - 1e-12
