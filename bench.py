@@ -258,7 +258,7 @@ def batch_line(ctx, steps):
 def sweep_line(ctx, steps, with_cpu):
     """One generalized-sweep step (Alg. A.1: expanded pencil of one state at
     one bond, discard, expanded root, parameter update, Givens angle search,
-    truncation) at N = 7 (chi = 16, state 3, sites 2-3) and N = 12 (chi = 64,
+    truncation, one single-site mitigation round of App. A4) at N = 7 (chi = 16, state 3, sites 2-3) and N = 12 (chi = 64,
     state 0, sites 1-2), the current pencil from the library; the oracle's
     time for the N = 7 step when the CPU leg runs."""
     import torch
@@ -267,23 +267,25 @@ def sweep_line(ctx, steps, with_cpu):
     for k, i, p in ((2, 3, 2), (3, 0, 1)):
         prob = synth.make_config(k)
         H, S, E, c, _ = ctx.subspace(prob, chi=prob.chi)
-        ctx.sweep_step(prob, H, S, i, p, rotation="givens", chi=prob.chi)      # warm-up
+        ctx.sweep_step(prob, H, S, i, p, rotation="givens", nreps=1, chi=prob.chi)      # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(max(1, steps)):
-            res, _, _, rep = ctx.sweep_step(prob, H, S, i, p, rotation="givens", chi=prob.chi)
+            res, _, _, rep = ctx.sweep_step(prob, H, S, i, p, rotation="givens", nreps=1, chi=prob.chi)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / max(1, steps) * 1e3
-        d = {"workload": f"N={prob.N}, chi={prob.chi}, M={prob.M}, state {i}, sites {p}-{p + 1}, Givens rotation",
+        d = {"workload": f"N={prob.N}, chi={prob.chi}, M={prob.M}, state {i}, sites {p}-{p + 1}, Givens rotation, "
+                         "one single-site mitigation round",
              "ms_per_step": ms, "one_hot_states": res["n_onehot"], "columns": res["n_columns"],
-             "kept_columns": res["n_kept"], "E_old": res["E_old"], "E1": res["E1"], "theta": res["theta"],
+             "kept_columns": res["n_kept"], "E_old": res["E_old"], "E1": res["E1"], "E_new": res["E_new"],
+             "theta": res["theta"],
              "xi_none": res["xi_none"], "xi": res["xi"], "pencil_networks_ms": rep["t_gates_ms"],
              "pencil_contractions_ms": rep["t_env_ms"], "discard_and_eigensolve_ms": rep["t_gep_ms"],
              "step_ms_in_library": rep["t_total_ms"]}
         if with_cpu and k == 2:
             from oracle import sweep as osweep
             t1 = time.perf_counter()
-            osweep.sweep_step(prob, H, S, i, p, rotation="givens")
+            osweep.sweep_step(prob, H, S, i, p, rotation="givens", nreps=1)
             d["cpu_oracle_ms"] = (time.perf_counter() - t1) * 1e3
         out[f"N{prob.N}"] = d
         log(f"  sweep step N={prob.N}: {ms:.1f} ms (E_old {res['E_old']:.6f} -> E1 {res['E1']:.6f}, "

@@ -307,7 +307,16 @@ tnqe_status tnqe_onehot_pencil(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32
  *  7. merge of the rotation into the orbital basis of state i:
  *     U_i <- U_i R_p(theta)^T (FSWAP: columns p and p+1 exchanged), which
  *     leaves the state unchanged up to the truncation;
- *  8. accepted = E1 < E_old + e_tol (E_old: lowest root of (H, S)).
+ *  8. with nreps > 0, the single-site mitigation of App. A4: the expanded
+ *     pencil moved to the rotated basis (the gate in the one-hot basis,
+ *     H^[ii] -> G^T H^[ii] G, H^[ik] -> G^T H^[ik]), then nreps rounds of
+ *     expansions over the single-site one-hot states at p and then p+1, the
+ *     other site held as an orthonormal basis of its space in the current
+ *     two-site tensor with the truncated bond (its singular vectors), each
+ *     with steps 2-4 on the pencil projected by the isometry T (T H T^T,
+ *     T H^[ik]); A_p is then that orthonormal basis, A_{p+1} the updated site;
+ *  9. accepted = E_new < E_old + e_tol (E_old: lowest root of (H, S); E_new:
+ *     E1, or the last root of step 8).
  * Inputs: as tnqe_onehot_pencil, and H, S [M][M] host (the current pencil,
  * e.g. from tnqe_subspace with the same options).  Outputs (host): res; the
  * updated state i in the layout of tnqe_mps -- bond_dim [N+1], bond_qn
@@ -326,7 +335,7 @@ typedef struct {
   int32_t rotation;      /* tnqe_rotation */
   int32_t n_grid;        /* Givens: grid angles, even (0: 36) */
   int32_t n_golden;      /* Givens: golden-section steps (< 0: 40) */
-  int32_t reserved0;
+  int32_t nreps;         /* single-site mitigation rounds (App. A4), 0 .. 64 */
   double tol_ld;         /* discard threshold (0: 1e-3) */
   double e_tol;          /* acceptance tolerance (Hartree) */
   double reserved[2];
@@ -343,7 +352,9 @@ typedef struct {
   int32_t n_dropped_S;   /* further directions dropped by the eps_S threshold */
   int32_t accepted;      /* 1: E1 < E_old + e_tol */
   int32_t new_bond;      /* bond dimension p + 1 after the truncation */
-  int32_t reserved[2];
+  int32_t mit_columns;   /* columns of the last single-site expanded pencil (0: no mitigation) */
+  int32_t mit_kept;      /* of them kept by the discard */
+  double E_new;          /* the last root: E1, or after the mitigation rounds their last one */
 } tnqe_sweep_result;
 tnqe_status tnqe_sweep_step(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t M, const tnqe_mps *mps,
                             const tnqe_options *opts, const tnqe_sweep_options *sw, int32_t i, int32_t p,

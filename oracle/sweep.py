@@ -349,10 +349,11 @@ def mitigate(prob, H, S, i, p, index, Hd, Sd, Hc, Sc, G16, Ap, Aq, qn, newq, nre
 
 
 def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_tol=0.0, chi_cap=None,
-               tau_w=1e-13, n_grid=36, n_golden=40, xi_tol=1e-12, nreps=0):
+               tau_w=1e-13, n_grid=36, n_golden=40, xi_tol=1e-12, nreps=0, theta_given=None):
     """Steps 1-8 above (with nreps > 0, the single-site mitigation of App. A4
     after step 7; E_new is then its last root).  H, S: the current pencil.
-    Returns a dict."""
+    theta_given: a Givens angle to use instead of the search (checks of what
+    follows the search, at another implementation's angle).  Returns a dict."""
     assert rotation in ROTATIONS
     chi_cap = prob.chi if chi_cap is None else chi_cap
     M = prob.M
@@ -371,6 +372,9 @@ def sweep_step(prob, H, S, i, p, rotation="none", tol_ld=1e-3, eps_S=1e-12, e_to
         xs = xi(apply_gate(T4, gates.f4()), qn[p], qn[p + 2], chi_cap)
         if xs < xi_none - xi_tol:
             theta, xi_rot = np.pi / 2, xs
+    elif rotation == "givens" and theta_given is not None:
+        theta = float(theta_given)
+        xi_rot = xi(apply_gate(T4, gates.g4(theta)), qn[p], qn[p + 2], chi_cap) if theta != 0.0 else xi_none
     elif rotation == "givens":
         theta, xi_rot, _ = optimise_theta(T4, qn[p], qn[p + 2], chi_cap, n_grid, n_golden, xi_tol)
     new_sites, new_qn, U_new, T4r, st = finish(T4, sites, qn, bi.U, p, rotation, theta, chi_cap, tau_w)

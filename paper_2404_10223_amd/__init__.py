@@ -44,7 +44,7 @@ class _Opts(C.Structure):
 
 
 class _SweepOpts(C.Structure):
-    _fields_ = [("rotation", C.c_int32), ("n_grid", C.c_int32), ("n_golden", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("rotation", C.c_int32), ("n_grid", C.c_int32), ("n_golden", C.c_int32), ("nreps", C.c_int32),
                 ("tol_ld", C.c_double), ("e_tol", C.c_double), ("reserved", C.c_double * 2)]
 
 
@@ -52,7 +52,8 @@ class _SweepRes(C.Structure):
     _fields_ = [("E_old", C.c_double), ("E1", C.c_double), ("theta", C.c_double), ("xi_none", C.c_double),
                 ("xi", C.c_double), ("discarded", C.c_double), ("n_onehot", C.c_int32),
                 ("n_columns", C.c_int32), ("n_kept", C.c_int32), ("n_dropped_S", C.c_int32),
-                ("accepted", C.c_int32), ("new_bond", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("accepted", C.c_int32), ("new_bond", C.c_int32), ("mit_columns", C.c_int32),
+                ("mit_kept", C.c_int32), ("E_new", C.c_double)]
 
 
 ROTATIONS = {"none": 0, "fswap": 1, "givens": 2}
@@ -316,14 +317,15 @@ class Context:
                self.h)
         return index, Hd, Sd, Hc, Sc, report_dict(r)
 
-    def sweep_step(self, prob, H, S, i, p, rotation="none", tol_ld=1e-3, e_tol=0.0, n_grid=36, n_golden=40, **kw):
+    def sweep_step(self, prob, H, S, i, p, rotation="none", tol_ld=1e-3, e_tol=0.0, n_grid=36, n_golden=40, nreps=0,
+                   **kw):
         """One generalized-sweep step at sites (p, p+1) for state i
         (tnqe_sweep_step).  H, S: the current pencil.  Returns (result dict,
         the updated state as an MPS-like (sites, bond_qn, U) triple, t' [n],
         report)."""
         pk = _Packed(prob)
         o = options(**kw)
-        so = _SweepOpts(ROTATIONS[rotation], int(n_grid), int(n_golden), 0, float(tol_ld), float(e_tol))
+        so = _SweepOpts(ROTATIONS[rotation], int(n_grid), int(n_golden), int(nreps), float(tol_ld), float(e_tol))
         m = prob.mps[i]
         N = prob.N
         chi = o.chi_cap_override if o.chi_cap_override > 0 else o.chi

@@ -2516,6 +2516,9 @@ struct OneHotDev {
   std::vector<int4> index;
   std::vector<int> dense_of;        // index m -> ((l * 4 + k_p) * 4 + k_{p+1}) * Dq + r
   const int *d_dense = nullptr;
+  std::vector<int> dmap;            // dense index -> m (-1: not a one-hot entry)
+  const int4 *d_oh = nullptr;       // the index on the device
+  const int *d_map = nullptr;       // dmap on the device
   double *Hd = nullptr, *Sd = nullptr, *Hc = nullptr, *Sc = nullptr;   // [n][n], [n][n], [n][M], [n][M]
   KetSet ci;
   int Dp = 0, Dq = 0;               // total dimensions of bonds p and p + 2
@@ -2634,7 +2637,8 @@ void onehot_core(Call &c, tnqe_problem &pb, const tnqe_options &op, int ei, int 
   const int n = (int)out.index.size();
   require(n > 0, TNQE_ESHAPE, "the two-site tensor has no entries in the particle-number sector");
   const int Dbp = ci.htot[p], Dbm = ci.htot[p + 1], Dbq = ci.htot[p + 2];
-  std::vector<int> &dense_of = out.dense_of, dmap((size_t)Dbp * 16 * Dbq, -1);
+  std::vector<int> &dense_of = out.dense_of, &dmap = out.dmap;
+  dmap.assign((size_t)Dbp * 16 * Dbq, -1);
   dense_of.resize(n);
   out.Dp = Dbp;
   out.Dq = Dbq;
@@ -2647,6 +2651,8 @@ void onehot_core(Call &c, tnqe_problem &pb, const tnqe_options &op, int ei, int 
   out.d_dense = d_dense;
   const int *d_map = c.upload(dmap);
   const int4 *d_oh = c.upload(out.index);
+  out.d_map = d_map;
+  out.d_oh = d_oh;
   double *dHc = c.dev<double>((size_t)n * M), *dSc = c.dev<double>((size_t)n * M);
   double *dHd = c.dev<double>((size_t)n * n), *dSd = c.dev<double>((size_t)n * n);
   out.Hc = dHc;
@@ -2805,8 +2811,8 @@ void onehot_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, int ei,
 // parameter update (eq. param_upd), the rotation of the bond (App. A3), the
 // truncation to chi and the merge of the rotation into the orbital basis.
 struct SweepOut {
-  double E_old = 0.0, E1 = 0.0, theta = 0.0, xi_none = 0.0, xi = 0.0, discarded = 0.0;
-  int n = 0, D = 0, n_kept = 0, n_dropped_S = 0, accepted = 0, new_bond = 0;
+  double E_old = 0.0, E1 = 0.0, E_new = 0.0, theta = 0.0, xi_none = 0.0, xi = 0.0, discarded = 0.0;
+  int n = 0, D = 0, n_kept = 0, n_dropped_S = 0, accepted = 0, new_bond = 0, mit_columns = 0, mit_kept = 0;
   std::vector<double> tnew;
   std::vector<int32_t> bond_dim;
   std::vector<int32_t> bond_qn;
@@ -2950,6 +2956,295 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
   val = scratch + b.offS;
 }
 
+void sw_gemm(Call &c, int kind, int Mm, int Nn, int Kk, const double *A, const double *B, double *C) {
+  OhGemm g{};
+  g.kind = kind;
+  g.M = Mm;
+  g.N = Nn;
+  g.K = Kk;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  launch_oh_gemm(g, c.ctx->stream);
+}
+
+// Steps 2-4 on an expanded pencil whose state-ei block is spanned by n
+// orthonormal states (device Hd, Sd [n][n], Hc, Sc [n][M]): the combined
+// order of eq. subs_exp, the discard of dependent columns, the
+// projection-thresholded lowest root, and the normalised coefficients of the
+// n states (tnew, device [n]) signed against told (device, stride told_ld);
+// with dense_of and T non-null they are scattered into the dense tensor T.
+struct ExpandedRoot {
+  double E = 0.0;
+  int D = 0, n_kept = 0, n_dropped_S = 0;
+};
+ExpandedRoot expanded_root(Call &c, const double *dH, const double *dS, int M, int ei, int n, const double *Hd,
+                           const double *Sd, const double *Hc, const double *Sc, const double *told, int told_ld,
+                           double tol_ld, double eps_S, int max_sweeps, double *tnew, const int *dense_of, double *T,
+                           int64_t tsize) {
+  hipStream_t st = c.ctx->stream;
+  ExpandedRoot er;
+  const int D = n + M - 1;
+  er.D = D;
+  require(D <= 1024, TNQE_ESHAPE, "expanded pencil wider than 1024 columns");
+  // combined order of eq. subs_exp and assembly
+  std::vector<int> code(D);
+  for (int a = 0; a < D; ++a) code[a] = a < ei ? -(a + 1) : a < ei + n ? a - ei : -(a - n + 1 + 1);
+  double *Hx = c.dev<double>((size_t)D * D), *Sx = c.dev<double>((size_t)D * D);
+  launch_sw_assemble(c.upload(code), D, n, M, dH, dS, Hd, Sd, Hc, Sc, Hx, Sx, st);
+  // discard of linearly dependent columns
+  double *A = c.dev<double>((size_t)D * D);
+  int *dkeep = c.dev<int>(D);
+  TNQE_HIP(hipMemcpyAsync(A, Sx, sizeof(double) * D * D, hipMemcpyDeviceToDevice, st));
+  launch_sw_discard(A, Sx, D, tol_ld, dkeep, st);
+  std::vector<int> keep(D);
+  TNQE_HIP(hipMemcpyAsync(keep.data(), dkeep, D * sizeof(int), hipMemcpyDeviceToHost, st));
+  c.sync();
+  std::vector<int> kidx, col_of(D, -1);
+  for (int a = 0; a < D; ++a)
+    if (keep[a]) {
+      col_of[a] = (int)kidx.size();
+      kidx.push_back(a);
+    }
+  const int Dk = (int)kidx.size();
+  er.n_kept = Dk;
+  require(Dk >= 1, TNQE_ESINGULAR, "every column of the expanded pencil was discarded");
+  double *Hk = c.dev<double>((size_t)Dk * Dk), *Sk = c.dev<double>((size_t)Dk * Dk);
+  launch_sw_gather(Hx, Sx, D, c.upload(kidx), Dk, Hk, Sk, st);
+  // projection-thresholded eigenproblem of the kept columns
+  double *Uv = nullptr, *lam = nullptr;
+  psd_eigen(c, Sk, Dk, max_sweeps, Uv, lam);
+  std::vector<double> hl(Dk);
+  TNQE_HIP(hipMemcpyAsync(hl.data(), lam, Dk * sizeof(double), hipMemcpyDeviceToHost, st));
+  c.sync();
+  int r = 0;
+  while (r < Dk && hl[r] > eps_S * hl[0]) ++r;
+  er.n_dropped_S = Dk - r;
+  require(r >= 1, TNQE_ESINGULAR, "no overlap eigenvalue above the threshold");
+  double *X = c.dev<double>((size_t)Dk * r), *Y = c.dev<double>((size_t)Dk * r), *Cm = c.dev<double>((size_t)r * r);
+  double *Bm = c.dev<double>((size_t)r * r), *dshift = c.dev<double>(1), *ck = c.dev<double>(Dk);
+  launch_sw_whiten(Uv, lam, Dk, r, X, st);
+  sw_gemm(c, kOhPlain, Dk, r, Dk, Hk, X, Y);       // H_k X
+  sw_gemm(c, kOhPlainAT, r, r, Dk, X, Y, Cm);      // X^T H_k X
+  launch_sw_shift(Cm, r, Bm, dshift, st);
+  double *Ub = nullptr, *sb = nullptr;
+  psd_eigen(c, Bm, r, max_sweeps, Ub, sb);
+  sw_gemm(c, kOhPlain, Dk, 1, r, X, Ub, ck);       // c' = X y (y: the first vector)
+  double hs[2];
+  TNQE_HIP(hipMemcpyAsync(&hs[0], dshift, sizeof(double), hipMemcpyDeviceToHost, st));
+  TNQE_HIP(hipMemcpyAsync(&hs[1], sb, sizeof(double), hipMemcpyDeviceToHost, st));
+  c.sync();
+  er.E = hs[0] - hs[1];
+  // parameter update (eq. param_upd)
+  std::vector<int> col(n);
+  for (int m = 0; m < n; ++m) col[m] = col_of[ei + m];
+  double *dstat = c.dev<double>(2);
+  launch_sw_update(ck, c.upload(col), told, told_ld, n, dense_of, T, tsize, tnew, dstat, st);
+  c.check_launch();
+  return er;
+}
+
+// Single-site mitigation (App. A4) after the truncation of a sweep step.  The
+// expanded pencil is moved to the rotated basis (the gate in the one-hot
+// basis, G: H^[ii] -> G^T H^[ii] G, H^[ik] -> G^T H^[ik]); then, nreps
+// times, the state's two-site tensor X is expanded over single-site one-hot
+// states at p and at p+1 with the other site held fixed: at p the fixed site
+// is the orthonormal row basis V of X (its right singular vectors per
+// sector), at p+1 the orthonormal column basis Q (its left singular vectors),
+// with as many vectors per sector as the truncated bond holds.  A one-hot
+// state of the expanded site times the fixed one is a combination of
+// two-site one-hot states: rows of an isometry T, and the pencil block
+// becomes T H T^T (and T H^[ik]).  Any orthonormal basis of the fixed site's
+// space gives the same roots and updated X; the singular vectors are used
+// here.  Returns the last root; A_p (= Q) and A_{p+1} (the updated site) on
+// the host, centre at p+1.
+struct MitOut {
+  double E = 0.0;
+  int columns = 0, kept = 0;
+};
+MitOut mitigate(Call &c, KetSet &ci, int p, const OneHotDev &dv, const Gate16 &G16, const double *dH,
+                const double *dS, int M, int ei, const std::vector<int> &kept, int nreps, double tol_ld, double eps_S,
+                int max_sweeps, std::vector<double> &Ap, std::vector<double> &Aq, int Dn) {
+  hipStream_t st = c.ctx->stream;
+  const int n = (int)dv.index.size(), Dp = dv.Dp, Dq = dv.Dq, nb1 = ci.nb + 1;
+  const int64_t tsize = (int64_t)Dp * 16 * Dq;
+  // the pencil in the rotated basis
+  std::vector<double> g(G16.begin(), G16.end());
+  double *Gm = c.dev<double>((size_t)n * n), *tmp = c.dev<double>((size_t)n * std::max(n, M));
+  double *Hd2 = c.dev<double>((size_t)n * n), *Sd2 = c.dev<double>((size_t)n * n);
+  double *Hc2 = c.dev<double>((size_t)n * M), *Sc2 = c.dev<double>((size_t)n * M);
+  launch_sw_onehot_gate(dv.d_oh, dv.d_map, n, Dq, c.upload(g), Gm, st);
+  sw_gemm(c, kOhPlain, n, n, n, dv.Hd, Gm, tmp);
+  sw_gemm(c, kOhPlainAT, n, n, n, Gm, tmp, Hd2);
+  sw_gemm(c, kOhPlain, n, n, n, dv.Sd, Gm, tmp);
+  sw_gemm(c, kOhPlainAT, n, n, n, Gm, tmp, Sd2);
+  sw_gemm(c, kOhPlainAT, n, M, n, Gm, dv.Hc, Hc2);
+  sw_gemm(c, kOhPlainAT, n, M, n, Gm, dv.Sc, Sc2);
+  // the truncated state's coefficients in the one-hot basis
+  double *x = c.dev<double>(n), *dX = c.dev<double>(tsize);
+  launch_sw_product(c.upload(Ap), c.upload(Aq), Dn, Dq, dv.d_oh, n, x, st);
+  c.check_launch();
+  auto offp = [&](int a, int b) { return ci.off_q(p, 0, a, b); };
+  auto offq = [&](int a, int b) { return ci.off_q(p + 2, 0, a, b); };
+  // sector of every index of bonds p, p+1 (new), p+2
+  std::vector<int> secp(Dp), secq(Dq);
+  for (int s = 0; s < ci.nslot; ++s) {
+    for (int d = 0; d < ci.dim(p, 0, s); ++d) secp[ci.off_q(p, 0, s / nb1, s % nb1) + d] = s;
+    for (int d = 0; d < ci.dim(p + 2, 0, s); ++d) secq[ci.off_q(p + 2, 0, s / nb1, s % nb1) + d] = s;
+  }
+  MitOut mo;
+  const Gate16 ident = givens_gate(0.0);
+  for (int rep = 0; rep < nreps; ++rep) {
+    for (int site = p; site <= p + 1; ++site) {
+      const size_t mk = c.ctx->pool.mark();
+      launch_sw_scatter(x, n, dv.d_dense, dX, tsize, st);
+      RotatedBlocks rb;
+      rotated_blocks(c, ci, p, dX, {ident}, max_sweeps, rb);
+      require(rb.blks.size() == kept.size(), TNQE_ESHAPE, "two-site blocks changed during the mitigation");
+      std::vector<int> j0(kept.size() + 1, 0), blk_of_slot(ci.nslot, -1);
+      for (size_t q = 0; q < kept.size(); ++q) {
+        rb.blks[q].kept = kept[q];
+        j0[q + 1] = j0[q] + kept[q];
+        blk_of_slot[rb.blks[q].sa * nb1 + rb.blks[q].sb] = (int)q;
+      }
+      {
+        Blk *dblk = c.upload(rb.blks);
+        const std::vector<int> uf = unit_prefix(rb.blks, [](const Blk &b) { return factor_units(b); });
+        launch_svd_factor(dblk, Units{c.upload(uf), (int)rb.blks.size(), uf.back()}, rb.scratch, st);
+        c.check_launch();
+      }
+      std::vector<std::vector<double>> U(kept.size()), B(kept.size()), sv(kept.size());
+      for (size_t q = 0; q < kept.size(); ++q) {
+        const Blk &b = rb.blks[q];
+        U[q].resize((size_t)b.kept * b.R);
+        B[q].resize((size_t)b.kept * b.C);
+        sv[q].resize(b.kept);
+        if (b.kept == 0) continue;
+        TNQE_HIP(hipMemcpyAsync(U[q].data(), rb.scratch + b.offU, U[q].size() * 8, hipMemcpyDeviceToHost, st));
+        TNQE_HIP(hipMemcpyAsync(B[q].data(), rb.scratch + b.offB, B[q].size() * 8, hipMemcpyDeviceToHost, st));
+        TNQE_HIP(hipMemcpyAsync(sv[q].data(), rb.scratch + b.offS, sv[q].size() * 8, hipMemcpyDeviceToHost, st));
+      }
+      c.sync();
+      // the single-site one-hot states (row-major over the expanded site's
+      // indices) and the isometry to the two-site one-hot states
+      std::vector<double> Tiso;
+      int n1 = 0;
+      auto add_row = [&]() {
+        Tiso.resize(Tiso.size() + n, 0.0);
+        return n1++;
+      };
+      if (site == p) {
+        for (int l = 0; l < Dp; ++l)
+          for (int kp = 0; kp < 4; ++kp) {
+            const int sa = secp[l] / nb1 + qk_a(kp), sb = secp[l] % nb1 + qk_b(kp);
+            if (sa > ci.na || sb > ci.nb) continue;
+            const int q = blk_of_slot[sa * nb1 + sb];
+            if (q < 0) continue;
+            const Blk &b = rb.blks[q];
+            for (int jj = 0; jj < kept[q]; ++jj) {
+              require(sv[q][jj] > 0.0, TNQE_ESINGULAR, "the truncated bond has a vanishing singular value");
+              const int m1 = add_row();
+              for (int kq = 0; kq < 4; ++kq) {
+                const int ra = sa + qk_a(kq), rbb = sb + qk_b(kq);
+                if (ra > ci.na || rbb > ci.nb) continue;
+                const int r0 = offq(ra, rbb), nr = ci.dim_q(p + 2, 0, ra, rbb);
+                for (int r = r0; r < r0 + nr; ++r) {
+                  const int m2 = dv.dmap[(((size_t)l * 4 + kp) * 4 + kq) * Dq + r];
+                  if (m2 < 0) continue;
+                  Tiso[(size_t)m1 * n + m2] = B[q][(size_t)jj * b.C + b.cs[kq] + r - r0] / sv[q][jj];
+                }
+              }
+            }
+          }
+      } else {
+        for (size_t q = 0; q < kept.size(); ++q) {
+          const Blk &b = rb.blks[q];
+          for (int jj = 0; jj < kept[q]; ++jj)
+            for (int kq = 0; kq < 4; ++kq) {
+              const int ra = b.sa + qk_a(kq), rbb = b.sb + qk_b(kq);
+              if (ra > ci.na || rbb > ci.nb) continue;
+              const int r0 = offq(ra, rbb), nr = ci.dim_q(p + 2, 0, ra, rbb);
+              for (int r = r0; r < r0 + nr; ++r) {
+                const int m1 = add_row();
+                for (int kp = 0; kp < 4; ++kp) {
+                  const int la = b.sa - qk_a(kp), lb = b.sb - qk_b(kp);
+                  if (la < 0 || lb < 0) continue;
+                  const int l0 = offp(la, lb), nl = ci.dim_q(p, 0, la, lb);
+                  for (int l = l0; l < l0 + nl; ++l) {
+                    const int m2 = dv.dmap[(((size_t)l * 4 + kp) * 4 + kq) * Dq + r];
+                    if (m2 < 0) continue;
+                    Tiso[(size_t)m1 * n + m2] = U[q][(size_t)jj * b.R + b.rs[kp] + l - l0];
+                  }
+                }
+              }
+            }
+        }
+      }
+      require(n1 >= 1, TNQE_ESHAPE, "no single-site one-hot states");
+      double *dTi = c.upload(Tiso);
+      double *P = c.dev<double>((size_t)n1 * n), *Hd1 = c.dev<double>((size_t)n1 * n1);
+      double *Sd1 = c.dev<double>((size_t)n1 * n1), *Hc1 = c.dev<double>((size_t)n1 * M);
+      double *Sc1 = c.dev<double>((size_t)n1 * M), *tcur = c.dev<double>(n1), *t1 = c.dev<double>(n1);
+      sw_gemm(c, kOhPlain, n1, n, n, dTi, Hd2, P);
+      sw_gemm(c, kOhPlainBT, n1, n1, n, P, dTi, Hd1);
+      sw_gemm(c, kOhPlain, n1, n, n, dTi, Sd2, P);
+      sw_gemm(c, kOhPlainBT, n1, n1, n, P, dTi, Sd1);
+      sw_gemm(c, kOhPlain, n1, M, n, dTi, Hc2, Hc1);
+      sw_gemm(c, kOhPlain, n1, M, n, dTi, Sc2, Sc1);
+      sw_gemm(c, kOhPlain, n1, 1, n, dTi, x, tcur);
+      const ExpandedRoot er = expanded_root(c, dH, dS, M, ei, n1, Hd1, Sd1, Hc1, Sc1, tcur, 1, tol_ld, eps_S,
+                                            max_sweeps, t1, nullptr, nullptr, 0);
+      sw_gemm(c, kOhPlainAT, n, 1, n1, dTi, t1, x);    // the updated two-site coefficients
+      // TNQE_DEBUG_MITIGATE=1: each round's root and sizes (diagnostics)
+      static const bool dbg = std::getenv("TNQE_DEBUG_MITIGATE") != nullptr;
+      if (dbg) {
+        std::vector<double> hx(n), hc(n1);
+        TNQE_HIP(hipMemcpyAsync(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        TNQE_HIP(hipMemcpyAsync(hc.data(), tcur, n1 * sizeof(double), hipMemcpyDeviceToHost, st));
+        c.sync();
+        double nx = 0.0, nc = 0.0;
+        for (double v : hx) nx += v * v;
+        for (double v : hc) nc += v * v;
+        std::fprintf(stderr, "mitigation rep %d site %d: n1 %d columns %d kept %d E %.15f |x'|^2 %.15f |t_cur|^2 %.15f\n",
+                     rep, site, n1, er.D, er.n_kept, er.E, nx, nc);
+      }
+      mo.E = er.E;
+      mo.columns = er.D;
+      mo.kept = er.n_kept;
+      if (rep == nreps - 1 && site == p + 1) {
+        // A_p = Q (the fixed left site), A_{p+1} = the updated site
+        std::vector<double> h1(n1);
+        TNQE_HIP(hipMemcpyAsync(h1.data(), t1, n1 * sizeof(double), hipMemcpyDeviceToHost, st));
+        c.sync();
+        std::fill(Ap.begin(), Ap.end(), 0.0);
+        std::fill(Aq.begin(), Aq.end(), 0.0);
+        int m1 = 0;
+        for (size_t q = 0; q < kept.size(); ++q) {
+          const Blk &b = rb.blks[q];
+          for (int jj = 0; jj < kept[q]; ++jj) {
+            const int j = j0[q] + jj;
+            for (int kp = 0; kp < 4; ++kp) {
+              const int la = b.sa - qk_a(kp), lb = b.sb - qk_b(kp);
+              if (la < 0 || lb < 0) continue;
+              const int l0 = offp(la, lb), nl = ci.dim_q(p, 0, la, lb);
+              for (int l = l0; l < l0 + nl; ++l)
+                Ap[((size_t)l * 4 + kp) * Dn + j] = U[q][(size_t)jj * b.R + b.rs[kp] + l - l0];
+            }
+            for (int kq = 0; kq < 4; ++kq) {
+              const int ra = b.sa + qk_a(kq), rbb = b.sb + qk_b(kq);
+              if (ra > ci.na || rbb > ci.nb) continue;
+              const int r0 = offq(ra, rbb), nr = ci.dim_q(p + 2, 0, ra, rbb);
+              for (int r = r0; r < r0 + nr; ++r) Aq[((size_t)j * 4 + kq) * Dq + r] = h1[m1++];
+            }
+          }
+        }
+      }
+      c.ctx->pool.rewind(mk);
+    }
+  }
+  return mo;
+}
+
 void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tnqe_sweep_options &so, int ei, int p,
                const double *H, const double *S, SweepOut &out, tnqe_report &rep) {
   Call c{ctx};
@@ -2964,6 +3259,7 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
   const int n_grid = so.n_grid > 0 ? so.n_grid : 36, n_golden = so.n_golden >= 0 ? so.n_golden : 40;
   require(so.rotation >= TNQE_ROT_NONE && so.rotation <= TNQE_ROT_GIVENS, TNQE_EINVAL, "unknown rotation type");
   require(n_grid % 2 == 0, TNQE_EINVAL, "n_grid must be even (the grid holds theta = 0)");
+  require(so.nreps >= 0 && so.nreps <= 64, TNQE_EINVAL, "nreps out of range");
   // current pencil and its lowest root
   std::vector<double> hH(H, H + (size_t)M * M), hS(S, S + (size_t)M * M);
   for (double v : hH) require(std::isfinite(v), TNQE_ENONFINITE, "non-finite pencil element");
@@ -2989,73 +3285,19 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
   out.D = D;
   require(D <= 1024, TNQE_ESHAPE, "expanded pencil wider than 1024 columns");
   const auto tg = Clock::now();
-  // 2. combined order of eq. subs_exp and assembly
-  std::vector<int> code(D);
-  for (int a = 0; a < D; ++a) code[a] = a < ei ? -(a + 1) : a < ei + n ? a - ei : -(a - n + 1 + 1);
-  double *Hx = c.dev<double>((size_t)D * D), *Sx = c.dev<double>((size_t)D * D);
-  launch_sw_assemble(c.upload(code), D, n, M, dH, dS, dv.Hd, dv.Sd, dv.Hc, dv.Sc, Hx, Sx, st);
-  // 3. discard of linearly dependent columns
-  double *A = c.dev<double>((size_t)D * D);
-  int *dkeep = c.dev<int>(D);
-  TNQE_HIP(hipMemcpyAsync(A, Sx, sizeof(double) * D * D, hipMemcpyDeviceToDevice, st));
-  launch_sw_discard(A, Sx, D, tol_ld, dkeep, st);
-  std::vector<int> keep(D);
-  TNQE_HIP(hipMemcpyAsync(keep.data(), dkeep, D * sizeof(int), hipMemcpyDeviceToHost, st));
-  c.sync();
-  std::vector<int> kidx, col_of(D, -1);
-  for (int a = 0; a < D; ++a)
-    if (keep[a]) {
-      col_of[a] = (int)kidx.size();
-      kidx.push_back(a);
-    }
-  const int Dk = (int)kidx.size();
-  out.n_kept = Dk;
-  require(Dk >= 1, TNQE_ESINGULAR, "every column of the expanded pencil was discarded");
-  double *Hk = c.dev<double>((size_t)Dk * Dk), *Sk = c.dev<double>((size_t)Dk * Dk);
-  launch_sw_gather(Hx, Sx, D, c.upload(kidx), Dk, Hk, Sk, st);
-  // 4. projection-thresholded eigenproblem of the kept columns
-  double *Uv = nullptr, *lam = nullptr;
-  psd_eigen(c, Sk, Dk, max_sweeps, Uv, lam);
-  std::vector<double> hl(Dk);
-  TNQE_HIP(hipMemcpyAsync(hl.data(), lam, Dk * sizeof(double), hipMemcpyDeviceToHost, st));
-  c.sync();
-  int r = 0;
-  while (r < Dk && hl[r] > eps_S * hl[0]) ++r;
-  out.n_dropped_S = Dk - r;
-  require(r >= 1, TNQE_ESINGULAR, "no overlap eigenvalue above the threshold");
-  double *X = c.dev<double>((size_t)Dk * r), *Y = c.dev<double>((size_t)Dk * r), *Cm = c.dev<double>((size_t)r * r);
-  double *Bm = c.dev<double>((size_t)r * r), *dshift = c.dev<double>(1), *ck = c.dev<double>(Dk);
-  launch_sw_whiten(Uv, lam, Dk, r, X, st);
-  auto gemm = [&](int kind, int Mm, int Nn, int Kk, const double *Am, const double *Bp, double *Cp) {
-    OhGemm g{};
-    g.kind = kind;
-    g.M = Mm;
-    g.N = Nn;
-    g.K = Kk;
-    g.A = Am;
-    g.B = Bp;
-    g.C = Cp;
-    launch_oh_gemm(g, st);
-  };
-  gemm(kOhPlain, Dk, r, Dk, Hk, X, Y);       // H_k X
-  gemm(kOhPlainAT, r, r, Dk, X, Y, Cm);      // X^T H_k X
-  launch_sw_shift(Cm, r, Bm, dshift, st);
-  double *Ub = nullptr, *sb = nullptr;
-  psd_eigen(c, Bm, r, max_sweeps, Ub, sb);
-  gemm(kOhPlain, Dk, 1, r, X, Ub, ck);       // c' = X y (y: the first vector)
-  double hs[2];
-  TNQE_HIP(hipMemcpyAsync(&hs[0], dshift, sizeof(double), hipMemcpyDeviceToHost, st));
-  TNQE_HIP(hipMemcpyAsync(&hs[1], sb, sizeof(double), hipMemcpyDeviceToHost, st));
-  c.sync();
-  out.E1 = hs[0] - hs[1];
-  out.accepted = out.E1 < out.E_old + so.e_tol ? 1 : 0;
-  // 5. parameter update into the dense two-site tensor T[l][k_p][k_{p+1}][r]
-  std::vector<int> col(n);
-  for (int m = 0; m < n; ++m) col[m] = col_of[ei + m];
+  // 2-5. discard, expanded root, parameter update into the dense two-site
+  // tensor T[l][k_p][k_{p+1}][r]
   const int Dp = dv.Dp, Dq = dv.Dq;
   const int64_t tsize = (int64_t)Dp * 16 * Dq;
-  double *dT = c.dev<double>(tsize), *dtn = c.dev<double>(n), *dstat = c.dev<double>(2);
-  launch_sw_update(ck, c.upload(col), dv.Sc + ei, M, n, dv.d_dense, dT, tsize, dtn, dstat, st);
+  double *dT = c.dev<double>(tsize), *dtn = c.dev<double>(n);
+  {
+    const ExpandedRoot er = expanded_root(c, dH, dS, M, ei, n, dv.Hd, dv.Sd, dv.Hc, dv.Sc, dv.Sc + ei, M, tol_ld,
+                                          eps_S, max_sweeps, dtn, dv.d_dense, dT, tsize);
+    out.E1 = er.E;
+    out.n_kept = er.n_kept;
+    out.n_dropped_S = er.n_dropped_S;
+  }
+  out.E_new = out.E1;
   out.tnew.resize(n);
   TNQE_HIP(hipMemcpyAsync(out.tnew.data(), dtn, n * sizeof(double), hipMemcpyDeviceToHost, st));
   c.sync();
@@ -3208,6 +3450,17 @@ void sweep_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, const tn
       j0 += b.kept;
     }
   }
+  // single-site mitigation (App. A4)
+  if (so.nreps > 0) {
+    std::vector<int> kept_blk(rb.blks.size());
+    for (size_t q = 0; q < rb.blks.size(); ++q) kept_blk[q] = rb.blks[q].kept;
+    const MitOut mo = mitigate(c, ci, p, dv, chosen, dH, dS, M, ei, kept_blk, so.nreps, tol_ld, eps_S, max_sweeps,
+                               Ap, Aq, Dn);
+    out.E_new = mo.E;
+    out.mit_columns = mo.columns;
+    out.mit_kept = mo.kept;
+  }
+  out.accepted = out.E_new < out.E_old + so.e_tol ? 1 : 0;
   site[p] = std::move(Ap);
   site[p + 1] = std::move(Aq);
   out.bond_dim.assign(N + 1, 0);
@@ -3982,6 +4235,9 @@ tnqe_status tnqe_sweep_step(tnqe_ctx *ctx, const tnqe_hamiltonian *ham, int32_t 
   q.n_dropped_S = out.n_dropped_S;
   q.accepted = out.accepted;
   q.new_bond = out.new_bond;
+  q.E_new = out.E_new;
+  q.mit_columns = out.mit_columns;
+  q.mit_kept = out.mit_kept;
   *res = q;
   ctx->sweep_t = std::move(out.tnew);
   if (rep) *rep = r;

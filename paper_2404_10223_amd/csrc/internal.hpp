@@ -360,6 +360,13 @@ void launch_sw_update(const double *ck, const int *col, const double *told, int 
                       double *T, int64_t tsize, double *tnew, double *stats, hipStream_t st);
 void launch_sw_gate_blocks(const Blk *blk, int nblk, const double *gates, const double *T, int Dq, const int *offp,
                            const int *offq, int na, int nb1, double *scratch, hipStream_t st);
+// single-site mitigation: the gate in the one-hot basis [n][n]; the two-site
+// coefficients of A_p A_{p+1} at the one-hot entries; their dense scatter
+void launch_sw_onehot_gate(const int4 *oh, const int *map, int n, int Dq, const double *G16, double *Gm,
+                           hipStream_t st);
+void launch_sw_product(const double *Ap, const double *Aq, int Dn, int Dq, const int4 *oh, int n, double *x,
+                       hipStream_t st);
+void launch_sw_scatter(const double *x, int n, const int *dense_of, double *T, int64_t tsize, hipStream_t st);
 constexpr int kXiMaxValues = 8192;   // singular values per gate in k_sw_xi (LDS)
 void launch_sw_xi(const Blk *blk, const int *first, int ngate, int max_values, const double *scratch, int chi,
                   double *xi, hipStream_t st);

@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_sw_update(const double *ck, con
   s_o[threadIdx.x] = ov;
   s_m[threadIdx.x] = am;
   s_i[threadIdx.x] = ai;
-  for (int64_t e = threadIdx.x; e < tsize; e += kUpdThreads) T[e] = 0.0;
+  if (T)
+    for (int64_t e = threadIdx.x; e < tsize; e += kUpdThreads) T[e] = 0.0;
   __syncthreads();
   for (int o = kUpdThreads / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_sw_update(const double *ck, con
   for (int m = threadIdx.x; m < n; m += kUpdThreads) {
     const double v = (col[m] >= 0 ? ck[col[m]] : 0.0) * f;
     tnew[m] = v;
-    T[dense_of[m]] = v;
+    if (T) T[dense_of[m]] = v;
   }
   if (threadIdx.x == 0) {
     stats[0] = nrm;
@@ -227,7 +228,55 @@ __global__ void __launch_bounds__(kXiThreads) k_sw_xi(const Blk *blk, const int 
   if (threadIdx.x == 0) xi[g] = 1.0 - part[0];
 }
 
+// The gate G16 in the one-hot basis: column m (one-hot m = (l, k_p, k_{p+1},
+// r)) holds G16[(k_p, k_{p+1}), x] at the one-hot state (l, x, r); one thread
+// per column (it also clears the column).  map: dense index -> one-hot index.
+__global__ void k_sw_onehot_gate(const int4 *oh, const int *map, int n, int Dq, const double *G16, double *Gm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  for (int m2 = 0; m2 < n; ++m2) Gm[(int64_t)m2 * n + m] = 0.0;
+  const int4 e = oh[m];
+  for (int x = 0; x < 16; ++x) {
+    const int m2 = map[(((int64_t)e.x * 4 + (x >> 2)) * 4 + (x & 3)) * Dq + e.w];
+    if (m2 >= 0) Gm[(int64_t)m2 * n + m] = G16[(e.y * 4 + e.z) * 16 + x];
+  }
+}
+
+// x[m] = sum_j Ap[l][k_p][j] Aq[j][k_{p+1}][r] at the one-hot entries
+__global__ void k_sw_product(const double *Ap, const double *Aq, int Dn, int Dq, const int4 *oh, int n, double *x) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const int4 e = oh[m];
+  double v = 0.0;
+  for (int j = 0; j < Dn; ++j)
+    v += Ap[((int64_t)e.x * 4 + e.y) * Dn + j] * Aq[((int64_t)j * 4 + e.z) * Dq + e.w];
+  x[m] = v;
+}
+
+// dense tensor T (cleared) with x[m] at dense_of[m]
+constexpr int kScatterThreads = 256;
+__global__ void __launch_bounds__(kScatterThreads) k_sw_scatter(const double *x, int n, const int *dense_of, double *T,
+                                                                 int64_t tsize) {
+  for (int64_t e = threadIdx.x; e < tsize; e += kScatterThreads) T[e] = 0.0;
+  __syncthreads();
+  for (int m = threadIdx.x; m < n; m += kScatterThreads) T[dense_of[m]] = x[m];
+}
+
 }  // namespace
+
+void launch_sw_onehot_gate(const int4 *oh, const int *map, int n, int Dq, const double *G16, double *Gm,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_sw_onehot_gate, dim3((n + 127) / 128), dim3(128), 0, st, oh, map, n, Dq, G16, Gm);
+}
+
+void launch_sw_product(const double *Ap, const double *Aq, int Dn, int Dq, const int4 *oh, int n, double *x,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_sw_product, dim3((n + 127) / 128), dim3(128), 0, st, Ap, Aq, Dn, Dq, oh, n, x);
+}
+
+void launch_sw_scatter(const double *x, int n, const int *dense_of, double *T, int64_t tsize, hipStream_t st) {
+  hipLaunchKernelGGL(k_sw_scatter, dim3(1), dim3(kScatterThreads), 0, st, x, n, dense_of, T, tsize);
+}
 
 void launch_sw_assemble(const int *code, int D, int n, int M, const double *H, const double *S, const double *Hd,
                         const double *Sd, const double *Hc, const double *Sc, double *Hx, double *Sx,

@@ -124,3 +124,41 @@ def test_sweep_step_errors(ctx):
     # the context still works
     res, _, _, _ = ctx.sweep_step(prob, H, S, 0, 1, chi=prob.chi)
     assert np.isfinite(res["E1"])
+
+
+# (cases whose cut has a clear gap: with tied singular values at the cut the
+# kept set, and everything after it, is one of several valid choices)
+@pytest.mark.parametrize("k,i,p,rotation,nreps", [(1, 0, 1, "givens", 1), (2, 3, 2, "givens", 1),
+                                                   (2, 0, 2, "fswap", 2), (2, 2, 3, "none", 1),
+                                                   (2, 1, 2, "givens", 3)])
+def test_sweep_step_with_mitigation_matches_oracle(ctx, k, i, p, rotation, nreps):
+    """The single-site mitigation rounds (App. A4) after the truncation: the
+    last root, the last pencil's size and discard count, and the final
+    two-site product (the fixed site's basis inside a sector is a gauge
+    choice, so the factors themselves are not compared)."""
+    prob, H, S = _pair(k)
+    print(f"config {k} state {i} sites ({p}, {p + 1}) rotation {rotation} nreps {nreps}", flush=True)
+    res, (sites, qn, U), t, rep = ctx.sweep_step(prob, H, S, i, p, rotation=rotation, nreps=nreps, chi=prob.chi)
+    # the angle search itself is compared in test_sweep_step_matches_oracle;
+    # here the oracle continues from the GPU's angle (the roots after the
+    # rotation move with it at first order)
+    o = sweep.sweep_step(prob, H, S, i, p, rotation=rotation, nreps=nreps,
+                         theta_given=res["theta"] if rotation == "givens" else None)
+    print(f"E1 {res['E1']:.12f} E_new {res['E_new']:.12f} ({o['E_new']:.12f}) columns {res['mit_columns']} "
+          f"kept {res['mit_kept']}", flush=True)
+    assert abs(res["E1"] - o["E1"]) <= 1e-10 * abs(o["E1"])
+    assert o["trunc"]["gap"] is None or o["trunc"]["gap"] > 1e-3
+    assert res["mit_columns"] == o["mitigation"]["n_columns"]
+    assert res["mit_kept"] == o["mitigation"]["n_kept"]
+    assert abs(res["E_new"] - o["E_new"]) <= 1e-10 * abs(o["E_new"])
+    assert res["accepted"] == int(o["accepted"])
+    two = lambda s: np.einsum("akm,mlb->aklb", s[p], s[p + 1])
+    np.testing.assert_allclose(two(sites), two(o["sites"]), atol=1e-8)
+    for x in range(prob.N):
+        if x not in (p, p + 1):
+            np.testing.assert_allclose(sites[x], o["sites"][x], atol=1e-10)
+    for b in range(prob.N + 1):
+        np.testing.assert_array_equal(qn[b], o["qn"][b])
+    A = sites[p].reshape(-1, sites[p].shape[2])
+    np.testing.assert_allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
+    np.testing.assert_allclose(U, o["U"], atol=1e-10)
