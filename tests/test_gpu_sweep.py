@@ -162,3 +162,39 @@ def test_sweep_step_with_mitigation_matches_oracle(ctx, k, i, p, rotation, nreps
     A = sites[p].reshape(-1, sites[p].shape[2])
     np.testing.assert_allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
     np.testing.assert_allclose(U, o["U"], atol=1e-10)
+
+
+def _single_state():
+    prob = synth.make_config(1)
+    one = synth.Problem(prob.N, prob.n_alpha, prob.n_beta, prob.h, prob.L, prob.e_core, prob.chi, [prob.mps[1]],
+                        name="config1_single")
+    from oracle.subspace import subspace as oracle_subspace
+    H, S, _, _, _ = oracle_subspace(one)
+    return one, H, S
+
+
+# edge cases: one state (no other columns), the boundary bonds, chi = 1 and 2
+EDGE = [("single", 0, 0, "none", 0, None), ("single", 0, 2, "givens", 1, None), (1, 1, 2, "givens", 2, None),
+        (1, 1, 1, "givens", 1, 1), (1, 0, 1, "fswap", 1, 2), (1, 1, 0, "givens", 1, 3)]
+
+
+@pytest.mark.parametrize("k,i,p,rotation,nreps,chi", EDGE)
+def test_sweep_step_edge_cases(ctx, k, i, p, rotation, nreps, chi):
+    prob, H, S = _single_state() if k == "single" else _pair(k)
+    chi = prob.chi if chi is None else chi
+    print(f"{k} state {i} sites ({p}, {p + 1}) {rotation} nreps {nreps} chi {chi}", flush=True)
+    res, (sites, qn, U), t, rep = ctx.sweep_step(prob, H, S, i, p, rotation=rotation, nreps=nreps, chi=chi)
+    o = sweep.sweep_step(prob, H, S, i, p, rotation=rotation, nreps=nreps, chi_cap=chi,
+                         theta_given=res["theta"] if rotation == "givens" else None)
+    print(f"E1 {res['E1']:.12f} ({o['E1']:.12f}) E_new {res['E_new']:.12f} ({o['E_new']:.12f}) "
+          f"bond {res['new_bond']} gap {o['trunc']['gap']}", flush=True)
+    assert o["trunc"]["gap"] is None or o["trunc"]["gap"] > 1e-3
+    assert res["n_columns"] == len(o["keep"]) and res["n_kept"] == int(o["keep"].sum())
+    assert abs(res["E1"] - o["E1"]) <= 1e-10 * abs(o["E1"])
+    assert abs(res["E_new"] - o["E_new"]) <= 1e-10 * abs(o["E_new"])
+    assert res["new_bond"] == o["trunc"]["kept"]
+    two = lambda s: np.einsum("akm,mlb->aklb", s[p], s[p + 1])
+    np.testing.assert_allclose(two(sites), two(o["sites"]), atol=1e-8)
+    for b in range(prob.N + 1):
+        np.testing.assert_array_equal(qn[b], o["qn"][b])
+    np.testing.assert_allclose(U, o["U"], atol=1e-10)
