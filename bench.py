@@ -307,9 +307,17 @@ def main():
                          "permutations (fermionic-swap networks, TNQE-F) or none (LC-MPS)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the generalized-sweep-step line (for profiling it); prints that line")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep_only:
+        import paper_2404_10223_amd as T
+        ctx = T.Context(0)
+        print(json.dumps({"sweep_step": sweep_line(ctx, args.steps, not args.no_cpu)}))
+        ctx.close()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (the pairs would be "

@@ -433,6 +433,20 @@ tnqe_status tnqe_debug_select(tnqe_ctx *ctx, int32_t nket, const int32_t *nblk, 
 tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const double *S, double eps_S,
                            double *out);
 
+/* tnqe_debug_psd_eigen: the device eigensolver of the dense eigenproblems of
+ * the generalized sweep (the overlap matrix of the kept expanded columns and
+ * the shifted whitened Hamiltonian, eq. exp_gen_eig) on a given symmetric
+ * positive semi-definite A ([n][n] host, row-major, 1 <= n <= 1024): the
+ * one-sided Jacobi SVD, which for such A is its eigendecomposition.  path 0
+ * is the choice of the sweep step (register kernels when they hold the
+ * matrix, else the global-memory Jacobi spread over the chip), 1 the
+ * global-memory Jacobi in one workgroup, 2 the one spread over the chip
+ * (paths 1 and 2 give the same bits).  Outputs (host): val[n] in decreasing
+ * order, vec[n][n] with row k the unit vector of val[k].  TNQE_EINVAL on bad
+ * arguments. */
+tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,
+                                 double *vec, double *val);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,7 +83,7 @@ EXPORTS = ["tnqe_default_options", "tnqe_create", "tnqe_destroy", "tnqe_trim", "
            "tnqe_subspace_batch", "tnqe_status_string", "tnqe_last_error", "tnqe_version", "tnqe_debug_givens",
            "tnqe_debug_gate", "tnqe_debug_mpo_dense", "tnqe_debug_host_pool", "tnqe_debug_select",
            "tnqe_debug_gep", "tnqe_subspace_noalloc", "tnqe_noalloc_capacity", "tnqe_onehot_size",
-           "tnqe_onehot_pencil", "tnqe_sweep_step", "tnqe_sweep_last_params"]
+           "tnqe_onehot_pencil", "tnqe_sweep_step", "tnqe_sweep_last_params", "tnqe_debug_psd_eigen"]
 
 _lib = None
 
@@ -130,6 +130,7 @@ def lib():
                                   ip, ip, dp, dp, C.POINTER(ip), C.POINTER(ip), C.c_int64, dp, C.c_int64, dp,
                                   C.POINTER(_SweepRes), C.POINTER(_Report)]
     L.tnqe_sweep_last_params.argtypes = [vp, ip, dp]
+    L.tnqe_debug_psd_eigen.argtypes = [vp, ip, dp, ip, ip, dp, dp]
     L.tnqe_noalloc_capacity.argtypes = []
     L.tnqe_noalloc_capacity.restype = C.c_size_t
     L.tnqe_status_string.argtypes = [C.c_int]
@@ -404,6 +405,18 @@ class Context:
         _check(self.L.tnqe_debug_gep(self.h, M, _dptr(H), _dptr(S), float(eps_S), _dptr(out)), self.h)
         return dict(E=out[0], cond_S=out[1], lambda_min=out[2], n_dropped=int(out[3]), kappa1=out[4],
                     status=int(out[5]), c=out[8:8 + M].copy())
+
+    def debug_psd_eigen(self, A, path=0, max_sweeps=40):
+        """Device eigensolver of the sweep step's dense eigenproblems on a
+        symmetric positive semi-definite A: (values in decreasing order,
+        vectors by row).  path 0: the sweep step's choice, 1: one-workgroup
+        global-memory Jacobi, 2: the same sweeps spread over the chip."""
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        n = A.shape[0]
+        vec, val = np.zeros((n, n)), np.zeros(n)
+        _check(self.L.tnqe_debug_psd_eigen(self.h, n, _dptr(A), int(path), int(max_sweeps), _dptr(vec),
+                                           _dptr(val)), self.h)
+        return val, vec
 
     def debug_select(self, blocks, chi, tau):
         """Device truncation rule on given singular values: blocks[t] is the

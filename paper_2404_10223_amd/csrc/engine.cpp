@@ -2934,23 +2934,45 @@ std::vector<double> truncation_errors(Call &c, KetSet &ci, int p, const double *
 }
 
 // eigen- (singular) decomposition of a symmetric positive semi-definite n x n
-// device matrix by the block Jacobi SVD: vectors by row ([n][n]) and values,
-// both in decreasing order of the values
-void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, double *&val) {
+// device matrix by the Jacobi SVD: vectors by row ([n][n]) and values, both
+// in decreasing order of the values.  Matrices too wide for the register
+// kernels take the global-memory Jacobi with its sweeps spread over the chip
+// (path 0); path 1 forces the one-workgroup global-memory kernel and path 2
+// the chip-wide one, at any n (both give the same bits).
+void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, double *&val, int path = 0) {
   Blk b{};
   b.R = b.C = n;
   b.rs[0] = b.cs[0] = 0;
   for (int k = 1; k <= 4; ++k) b.rs[k] = b.cs[k] = n;
   plan_block(b);
+  if (path != 0) b.offW = 0;   // global-memory storage
+  const bool wide = b.offW >= 0 && path != 1;
   Scratch sc;
   take_block_storage(b, sc);
   b.offS = sc.take(n);
   b.kept = n;
   double *scratch = c.dev<double>(sc.used);
-  TNQE_HIP(hipMemcpyAsync(scratch + b.offT, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c.ctx->stream));
+  hipStream_t st = c.ctx->stream;
+  TNQE_HIP(hipMemcpyAsync(scratch + b.offT, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
   std::vector<Blk> blks{b};
   Blk *dblk = c.upload(blks);
-  run_svd(c, dblk, blks, max_sweeps, scratch);
+  if (!wide) {
+    run_svd(c, dblk, blks, max_sweeps, scratch);
+  } else {
+    // the sweep loop on the host: one sync per sweep to read its rotation flag
+    const int *didx = c.upload(std::vector<int>{0});
+    unsigned long long *ctl = c.dev<unsigned long long>(4);
+    launch_jacobi_wide_load(dblk, didx, scratch, ctl, st);
+    int sweep = 0;
+    for (; sweep < max_sweeps && n > 1; ++sweep) {
+      launch_jacobi_wide_sweep(scratch + b.offW, n, n, ctl, sweep & 1, st);
+      unsigned long long rot = 0;
+      TNQE_HIP(hipMemcpyAsync(&rot, ctl + 2 + (sweep & 1), sizeof(rot), hipMemcpyDeviceToHost, st));
+      c.sync();
+      if (rot == 0) break;
+    }
+    launch_jacobi_wide_finish(dblk, didx, scratch, sweep, nullptr, st);
+  }
   c.check_launch();
   vec = scratch + b.offU;
   val = scratch + b.offS;
@@ -4492,6 +4514,25 @@ tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const doub
     TNQE_HIP(hipMemcpyAsync(go.data(), dout, go.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     c.sync();
     std::copy(go.begin(), go.begin() + 8 + M, out);
+    ctx->pool.rewind(mk);
+  });
+}
+
+tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,
+                                 double *vec, double *val) {
+  if (!ctx) return TNQE_EINVAL;
+  if (n < 1 || n > 1024 || !A || !vec || !val || path < 0 || path > 2 || max_sweeps < 1)
+    return fail(ctx, TNQE_EINVAL, "bad argument to tnqe_debug_psd_eigen");
+  return guarded(ctx, [&] {
+    TNQE_HIP(hipSetDevice(ctx->device));
+    Call c{ctx};
+    const size_t mk = ctx->pool.mark();
+    const std::vector<double> a(A, A + (size_t)n * n);
+    double *dv = nullptr, *dl = nullptr;
+    psd_eigen(c, c.upload(a), n, max_sweeps, dv, dl, path);
+    TNQE_HIP(hipMemcpyAsync(vec, dv, sizeof(double) * n * n, hipMemcpyDeviceToHost, ctx->stream));
+    TNQE_HIP(hipMemcpyAsync(val, dl, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    c.sync();
     ctx->pool.rewind(mk);
   });
 }

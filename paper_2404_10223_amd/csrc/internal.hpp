@@ -139,6 +139,18 @@ constexpr int jacobi_max_threads(int E) { return E > 20 ? 768 : 1024; }
 constexpr int kJacobiLdsBytes = 160 * 1024 - 1024;   // dynamic LDS cap per workgroup
 void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,
                    double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st);
+// The global-memory Jacobi of ONE block (blk[idx[0]], kJacobiGlobal storage)
+// with its sweeps spread over the chip: load fills the work area and clears
+// the four control words ctl; each sweep (slot = sweep & 1) is one norm
+// launch and one launch per round, after which ctl[2 + slot] is non-zero iff
+// a pair rotated; finish writes the sorted values and vectors exactly as
+// launch_jacobi does (same bits), sweeps_out[idx[0]] = sweeps_done if given.
+constexpr int kJwFull = 0, kJwLoad = 1, kJwFinish = 2;
+void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, unsigned long long *ctl,
+                             hipStream_t st);
+void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st);
+void launch_jacobi_wide_finish(const Blk *blk, const int *idx, double *scratch, int sweeps_done, int *sweeps_out,
+                               hipStream_t st);
 // the other factor of the first `kept` sorted vectors of every block (units:
 // factor_units)
 void launch_svd_factor(const Blk *blk, Units u, double *scratch, hipStream_t st);

@@ -337,8 +337,13 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
 
 // Blocks too large for k_jacobi: the vectors live in a global work area and
 // are rotated in cyclic round-robin order by groups of G lanes (same output).
+// mode kJwFull runs everything in this workgroup; kJwLoad only fills the work
+// area (and clears the control words ctl of the chip-wide variant), kJwFinish
+// only takes the final norms, ranks and writes the vectors after `sweeps_done`
+// sweeps made by k_jw_norms / k_jw_round.
 __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const int *idx, double *scratch,
-                                                        int max_sweeps, int *sweeps_out) {
+                                                        int max_sweeps, int *sweeps_out, int mode,
+                                                        int sweeps_done, unsigned long long *ctl) {
   constexpr int NT = 1024, NW = NT / 64;
   const Blk b = blks[idx[blockIdx.x]];
   const int R = b.R, C = b.C;
@@ -354,17 +359,23 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
     s_rot[0] = 0;
     s_rot[1] = 0;
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
-    const int i = e / m, l = e - (int64_t)i * m;
-    X[e] = cols ? T[(int64_t)l * C + i] : T[(int64_t)i * C + l];
+  if (mode != kJwFinish) {
+    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
+      const int i = e / m, l = e - (int64_t)i * m;
+      X[e] = cols ? T[(int64_t)l * C + i] : T[(int64_t)i * C + l];
+    }
+    if (mode == kJwLoad) {
+      if (threadIdx.x < 4) ctl[threadIdx.x] = 0ull;
+      return;
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = 64, ngroup = NT / G, grp = threadIdx.x / G, gl = threadIdx.x % G;
   const int np = n + (n & 1);
   const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
-  int sweep = 0;
-  for (; sweep < max_sweeps && n > 1; ++sweep) {
+  int sweep = mode == kJwFinish ? sweeps_done : 0;
+  for (; mode == kJwFull && sweep < max_sweeps && n > 1; ++sweep) {
     const int fl = sweep & 1;
     int rotated = 0;
     if (threadIdx.x == 0) s_amax = 0ull;
@@ -534,6 +545,73 @@ __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, d
   }
 }
 
+// The sweeps of k_jacobi_global spread over the chip for one wide block (the
+// dense eigenproblems of the generalized sweep are 400 and more columns wide,
+// and one workgroup then waits on its own loads most of the time).  A sweep is
+// one k_jw_norms launch and one k_jw_round launch per round of the
+// round-robin ordering, one wave per pair; the kernel boundaries order the
+// rounds.  Lane partition, sums, angles and norm updates are those of
+// k_jacobi_global, so both give the same bits.  Control words: ctl[slot] the
+// sweep's largest squared norm (as bits), ctl[2 + slot] set when a pair of
+// the sweep rotated; sweep s uses slot s & 1 and clears the other slot.
+constexpr int kJwWaves = 2;
+
+__global__ void __launch_bounds__(64 * kJwWaves) k_jw_norms(double *X, int n, int m, unsigned long long *ctl,
+                                                           int slot) {
+  const int lane = threadIdx.x & 63, i = blockIdx.x * kJwWaves + (threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[slot ^ 1] = 0ull;
+    ctl[2 + (slot ^ 1)] = 0ull;
+  }
+  if (i >= n) return;
+  const double *x = X + (int64_t)i * m;
+  double s2 = 0.0;
+  for (int l = lane; l < m; l += 64) s2 += x[l] * x[l];
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    X[(int64_t)n * m + i] = s2;
+    atomicMax(&ctl[slot], (unsigned long long)__double_as_longlong(s2));
+  }
+}
+
+__global__ void __launch_bounds__(64 * kJwWaves) k_jw_round(double *X, int n, int m, int rd,
+                                                           unsigned long long *ctl, int slot) {
+  const int lane = threadIdx.x & 63, k = blockIdx.x * kJwWaves + (threadIdx.x >> 6);
+  const int np = n + (n & 1);
+  if (k >= np / 2) return;
+  int i, j;
+  if (k == 0) {
+    i = np - 1;
+    j = rd;
+  } else {
+    i = (rd + k) % (np - 1);
+    j = (rd - k + np - 1) % (np - 1);
+  }
+  if (i >= n || j >= n) return;
+  double *sig = X + (int64_t)n * m;
+  const double tiny = __longlong_as_double((long long)ctl[slot]) * 1e-28;
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  const double al = sig[i], be = sig[j];
+  if (al <= tiny || be <= tiny) return;
+  double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
+  double ga = 0.0;
+  for (int l = lane; l < m; l += 64) ga += xi[l] * xj[l];
+  ga = wave_sum(ga);
+  if (fabs(ga) <= tol * sqrt(al * be)) return;
+  double c, s;
+  const double tn = jacobi_angle(al, be, ga, c, s);
+  for (int l = lane; l < m; l += 64) {
+    const double u = xi[l], v = xj[l];
+    xi[l] = c * u - s * v;
+    xj[l] = s * u + c * v;
+  }
+  if (lane == 0) {
+    sig[i] = fmax(al - tn * ga, 0.0);
+    sig[j] = be + tn * ga;
+    atomicOr(&ctl[2 + slot], 1ull);
+  }
+}
+
 template <int E>
 void set_lds_cap() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jacobi<E>),
@@ -571,9 +649,29 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
     case 5: launch_e<24>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
     default:
       hipLaunchKernelGGL(k_jacobi_global, dim3(nblk), dim3(1024), 0, st, blk, idx, scratch, max_sweeps,
-                         sweeps_out);
+                         sweeps_out, kJwFull, 0, nullptr);
       break;
   }
+}
+
+void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, unsigned long long *ctl,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_global, dim3(1), dim3(1024), 0, st, blk, idx, scratch, 0, nullptr, kJwLoad, 0, ctl);
+}
+
+void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_jw_norms, dim3((n + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m, ctl,
+                     slot);
+  const int np = n + (n & 1), pairs = np / 2;
+  for (int rd = 0; rd < np - 1; ++rd)
+    hipLaunchKernelGGL(k_jw_round, dim3((pairs + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m,
+                       rd, ctl, slot);
+}
+
+void launch_jacobi_wide_finish(const Blk *blk, const int *idx, double *scratch, int sweeps_done, int *sweeps_out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_global, dim3(1), dim3(1024), 0, st, blk, idx, scratch, 0, sweeps_out, kJwFinish,
+                     sweeps_done, nullptr);
 }
 
 void launch_svd_factor(const Blk *blk, Units u, double *scratch, hipStream_t st) {

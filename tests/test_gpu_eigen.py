@@ -1,0 +1,87 @@
+"""The device eigensolver of the generalized sweep's dense eigenproblems
+(eq. exp_gen_eig: the overlap of the kept expanded columns and the shifted
+whitened Hamiltonian) against matrices with a known spectrum.
+
+A = Q diag(lam) Q^T with lam chosen here and Q a seeded random orthogonal
+matrix, so the eigenvalues are known without any eigensolver; the vectors are
+checked by their residuals and orthonormality.  The one-workgroup and the
+chip-wide Jacobi run the same sweeps in the same arithmetic and must agree
+bit for bit."""
+import numpy as np
+import pytest
+
+import paper_2404_10223_amd as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _psd(n, kind, seed):
+    rng = np.random.default_rng(seed)
+    Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+    Q = Q * np.sign(np.diag(R))
+    if kind == "spread":          # 1 down to 1e-6, geometric
+        lam = np.geomspace(1.0, 1e-6, n)
+    elif kind == "repeated":      # clusters of equal values
+        lam = np.repeat(np.linspace(2.0, 0.5, (n + 3) // 4), 4)[:n]
+    elif kind == "deficient":     # a quarter of the values exactly zero
+        lam = np.concatenate([np.linspace(3.0, 0.1, n - n // 4), np.zeros(n // 4)])
+    else:
+        raise ValueError(kind)
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), np.sort(lam)[::-1]
+
+
+def _check(A, lam, val, vec):
+    n = A.shape[0]
+    scale = lam[0]
+    assert np.all(np.diff(val) <= 0.0), "values not in decreasing order"
+    np.testing.assert_allclose(val, lam, rtol=0, atol=1e-11 * scale)
+    big = val > 1e-8 * scale
+    V = vec[big]
+    res = A @ V.T - V.T * val[big]
+    assert np.abs(res).max() <= 1e-10 * scale
+    np.testing.assert_allclose(V @ V.T, np.eye(int(big.sum())), rtol=0, atol=1e-10)
+    assert V.shape[0] == n or lam[V.shape[0]] <= 1e-8 * scale
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 150, 230, 407])
+@pytest.mark.parametrize("kind", ["spread", "repeated", "deficient"])
+def test_psd_eigen_default_path(ctx, n, kind):
+    print(f"psd_eigen path 0 n={n} kind={kind}", flush=True)
+    A, lam = _psd(n, kind, 100 + n)
+    val, vec = ctx.debug_psd_eigen(A)
+    _check(A, lam, val, vec)
+
+
+@pytest.mark.parametrize("n", [2, 5, 64, 301, 407])
+def test_chip_wide_jacobi_same_bits(ctx, n):
+    print(f"psd_eigen paths 1, 2 n={n}", flush=True)
+    A, lam = _psd(n, "spread", 200 + n)
+    v1, u1 = ctx.debug_psd_eigen(A, path=1)
+    v2, u2 = ctx.debug_psd_eigen(A, path=2)
+    assert np.array_equal(v1, v2) and np.array_equal(u1, u2)
+    _check(A, lam, v2, u2)
+
+
+@pytest.mark.parametrize("n", [700, 1024])
+def test_chip_wide_jacobi_largest(ctx, n):
+    print(f"psd_eigen path 2 n={n}", flush=True)
+    A, lam = _psd(n, "spread", 300 + n)
+    val, vec = ctx.debug_psd_eigen(A, path=2)
+    _check(A, lam, val, vec)
+
+
+def test_psd_eigen_errors(ctx):
+    A = np.eye(4)
+    for kw in (dict(path=3), dict(path=-1), dict(max_sweeps=0)):
+        with pytest.raises(T.TnqeError):
+            ctx.debug_psd_eigen(A, **kw)
+    with pytest.raises(T.TnqeError):
+        ctx.debug_psd_eigen(np.eye(1025))
