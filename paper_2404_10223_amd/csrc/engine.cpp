@@ -2969,7 +2969,7 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
       unsigned long long rot = 0;
       TNQE_HIP(hipMemcpyAsync(&rot, ctl + 2 + (sweep & 1), sizeof(rot), hipMemcpyDeviceToHost, st));
       c.sync();
-      if (rot == 0) break;
+      if ((rot & 2) == 0) break;   // no rotation of a pair not yet orthogonal to 1e-10
     }
     launch_jacobi_wide_finish(dblk, didx, scratch, sweep, nullptr, st);
   }

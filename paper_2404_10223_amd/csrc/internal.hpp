@@ -142,8 +142,10 @@ void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threa
 // The global-memory Jacobi of ONE block (blk[idx[0]], kJacobiGlobal storage)
 // with its sweeps spread over the chip: load fills the work area and clears
 // the four control words ctl; each sweep (slot = sweep & 1) is one norm
-// launch and one launch per round, after which ctl[2 + slot] is non-zero iff
-// a pair rotated; finish writes the sorted values and vectors exactly as
+// launch and one launch per round, after which bit 0 of ctl[2 + slot] tells
+// whether a pair rotated and bit 1 whether one was not yet orthogonal to
+// 1e-10 (the sweeps stop at the first sweep without such a rotation); finish
+// writes the sorted values and vectors exactly as
 // launch_jacobi does (same bits), sweeps_out[idx[0]] = sweeps_done if given.
 constexpr int kJwFull = 0, kJwLoad = 1, kJwFinish = 2;
 void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, unsigned long long *ctl,

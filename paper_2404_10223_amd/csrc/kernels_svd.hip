@@ -352,12 +352,12 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
   if (n == 0) return;
   double *X = scratch + b.offW;                 // X[i*m + l]: vector i
   double *sig = X + (int64_t)n * m;
-  __shared__ int s_rot[2];
+  __shared__ int s_rot[2], s_big[2];
   __shared__ unsigned long long s_amax;
   const double *T = scratch + b.offT;
   if (threadIdx.x == 0) {
-    s_rot[0] = 0;
-    s_rot[1] = 0;
+    s_rot[0] = s_rot[1] = 0;
+    s_big[0] = s_big[1] = 0;
   }
   if (mode != kJwFinish) {
     for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += NT) {
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
   int sweep = mode == kJwFinish ? sweeps_done : 0;
   for (; mode == kJwFull && sweep < max_sweeps && n > 1; ++sweep) {
     const int fl = sweep & 1;
-    int rotated = 0;
+    int rotated = 0, big = 0;
     if (threadIdx.x == 0) s_amax = 0ull;
     __syncthreads();
     for (int i = grp; i < n; i += ngroup) {
@@ -409,6 +409,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
         for (int l = gl; l < m; l += G) ga += xi[l] * xj[l];
         ga = wave_sum(ga);
         if (fabs(ga) <= tol * sqrt(al * be)) continue;
+        big |= ga * ga > kBig2 * (al * be) ? 1 : 0;
         double c, s;
         const double tn = jacobi_angle(al, be, ga, c, s);
         for (int l = gl; l < m; l += G) {
@@ -425,10 +426,13 @@ __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const i
       __syncthreads();
     }
     if (rotated) atomicOr(&s_rot[fl], 1);
+    if (big) atomicOr(&s_big[fl], 1);
     __syncthreads();
-    const int any = s_rot[fl];
-    if (threadIdx.x == 0) s_rot[fl ^ 1] = 0;
-    if (any == 0) break;
+    const int any = s_rot[fl], any_big = s_big[fl];
+    if (threadIdx.x == 0) s_rot[fl ^ 1] = s_big[fl ^ 1] = 0;
+    // converged as in k_jacobi: no rotation, or only rotations of pairs
+    // already orthogonal to 1e-10
+    if (any == 0 || any_big == 0) break;
   }
   if (sweeps_out && threadIdx.x == 0) sweeps_out[idx[blockIdx.x]] = sweep;
   for (int i = wave; i < n; i += NW) {
@@ -552,9 +556,11 @@ __global__ void __launch_bounds__(256) k_svd_factor(const Blk *blks, Units un, d
 // round-robin ordering, one wave per pair; the kernel boundaries order the
 // rounds.  Lane partition, sums, angles and norm updates are those of
 // k_jacobi_global, so both give the same bits.  Control words: ctl[slot] the
-// sweep's largest squared norm (as bits), ctl[2 + slot] set when a pair of
-// the sweep rotated; sweep s uses slot s & 1 and clears the other slot.
-constexpr int kJwWaves = 2;
+// sweep's largest squared norm (as bits), ctl[2 + slot] bit 0 set when a pair
+// of the sweep rotated, bit 1 when one was not yet orthogonal to 1e-10 (the
+// sweeps end at the first sweep without such a rotation, as in
+// k_jacobi_global); sweep s uses slot s & 1 and clears the other slot.
+constexpr int kJwWaves = 2, kJwMaxE = 16;
 
 __global__ void __launch_bounds__(64 * kJwWaves) k_jw_norms(double *X, int n, int m, unsigned long long *ctl,
                                                            int slot) {
@@ -588,27 +594,42 @@ __global__ void __launch_bounds__(64 * kJwWaves) k_jw_round(double *X, int n, in
     j = (rd - k + np - 1) % (np - 1);
   }
   if (i >= n || j >= n) return;
+  // every load of the pair issued at once (vectors of at most 64 kJwMaxE)
   double *sig = X + (int64_t)n * m;
-  const double tiny = __longlong_as_double((long long)ctl[slot]) * 1e-28;
-  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
-  const double al = sig[i], be = sig[j];
-  if (al <= tiny || be <= tiny) return;
   double *xi = X + (int64_t)i * m, *xj = X + (int64_t)j * m;
+  double u[kJwMaxE], v[kJwMaxE];
+#pragma unroll
+  for (int e = 0; e < kJwMaxE; ++e) {
+    const int l = lane + 64 * e;
+    u[e] = l < m ? xi[l] : 0.0;
+    v[e] = l < m ? xj[l] : 0.0;
+  }
+  const double amax = __longlong_as_double((long long)ctl[slot]);
+  const double al = sig[i], be = sig[j];
+  const double tiny = amax * 1e-28;
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  if (al <= tiny || be <= tiny) return;
   double ga = 0.0;
-  for (int l = lane; l < m; l += 64) ga += xi[l] * xj[l];
+#pragma unroll
+  for (int e = 0; e < kJwMaxE; ++e)
+    if (lane + 64 * e < m) ga += u[e] * v[e];
   ga = wave_sum(ga);
   if (fabs(ga) <= tol * sqrt(al * be)) return;
+  const bool big = ga * ga > kBig2 * (al * be);
   double c, s;
   const double tn = jacobi_angle(al, be, ga, c, s);
-  for (int l = lane; l < m; l += 64) {
-    const double u = xi[l], v = xj[l];
-    xi[l] = c * u - s * v;
-    xj[l] = s * u + c * v;
+#pragma unroll
+  for (int e = 0; e < kJwMaxE; ++e) {
+    const int l = lane + 64 * e;
+    if (l < m) {
+      xi[l] = c * u[e] - s * v[e];
+      xj[l] = s * u[e] + c * v[e];
+    }
   }
   if (lane == 0) {
     sig[i] = fmax(al - tn * ga, 0.0);
     sig[j] = be + tn * ga;
-    atomicOr(&ctl[2 + slot], 1ull);
+    atomicOr(&ctl[2 + slot], big ? 3ull : 1ull);
   }
 }
 
@@ -660,6 +681,7 @@ void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, un
 }
 
 void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
+  if (m > 64 * kJwMaxE) throw Error(TNQE_ESHAPE, "chip-wide Jacobi: vectors longer than 1024");
   hipLaunchKernelGGL(k_jw_norms, dim3((n + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m, ctl,
                      slot);
   const int np = n + (n & 1), pairs = np / 2;
