@@ -199,6 +199,44 @@ __global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks,
       }
       if (gl == 0) atomicMax(&s_amax, (unsigned long long)__double_as_longlong(mx));   // >= 0 orders as an integer
     }
+    // vectors placed by decreasing norm: the larger half resident (processor
+    // p holds the p-th largest), the smaller half in the traveller slots, so
+    // that each sweep first rotates every large vector against every small
+    // one (about a fifth fewer sweeps on the gate blocks).  The vectors pass,
+    // in sorted order, through rows of G E doubles (each lane's chunk whole,
+    // no bounds checks) laid over the U and B areas, unused until the end;
+    // blocks whose areas cannot hold the padded rows keep their placement.
+    const bool sorted = b.offB >= b.offU && (int64_t)n * G * E <= (b.offB - b.offU) + (int64_t)n * C;
+    if (sorted) {
+      if (act && gl == 0) sig[p] = rn;
+      __syncthreads();   // every traveller norm written
+      for (int i = threadIdx.x; i < NTr; i += blockDim.x) sig[P + i] = tnrm[i];
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += blockDim.x) rnk[i] = rank_of(sig, n, i);
+      __syncthreads();
+      double *stage = scratch + b.offU + l0, *snrm = scratch + b.offS;
+      const int64_t rs = (int64_t)G * E;
+      if (act) {
+        const int rr = rnk[p];
+        st_chunk<E>(stage + rr * rs, res);
+        if (gl == 0) snrm[rr] = rn;
+        if (p < NTr) {
+          const int rt = rnk[P + p];
+          st_chunk<E>(stage + rt * rs, trv);
+          if (gl == 0) snrm[rt] = tnrm[p];
+        }
+      }
+      __syncthreads();
+      if (act) {
+        ld_chunk<E>(stage + p * rs, res);
+        rn = snrm[p];
+        if (p < NTr) {
+          ld_chunk<E>(stage + (P + p) * rs, trv);
+          st_chunk<E>(Xl + p * mp, trv);
+          if (gl == 0) tnrm[p] = snrm[P + p];
+        }
+      }
+    }
     __syncthreads();
     // vectors below 1e-14 of the largest are rounding noise of a rank-deficient
     // block: they are not rotated (they never survive a truncation)
