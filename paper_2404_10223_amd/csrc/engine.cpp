@@ -703,11 +703,11 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     lds[key] = std::max(lds[key], jp.lds);
     work[i] = (int64_t)b.n * b.n * m;
   }
-  // launches in decreasing estimated duration, each on the side stream with
-  // the least estimated work so far (longest processing time first): the
-  // launch of the few largest blocks runs beside launches of many small ones.
-  // Duration estimate: the largest block's n m (rounds x vector length) or
-  // the launch's total n^2 m spread over the chip, whichever is larger.
+  // launches in decreasing estimated duration (longest processing time
+  // first): the launch of the few largest blocks runs beside launches of many
+  // small ones.  Duration estimate: the largest block's n m (rounds x vector
+  // length) or the launch's total n^2 m spread over the chip, whichever is
+  // larger.
   std::vector<std::pair<double, std::pair<int, int>>> order;
   for (auto &kv : groups) {
     std::vector<int> &idx = kv.second;
@@ -734,14 +734,14 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   }
   TNQE_HIP(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int i = 0; i < nstream; ++i) TNQE_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
-  double load[tnqe_ctx::kAux] = {};
-  for (size_t g = 0; g < order.size(); ++g) {
+  // list scheduling: the first launches go to the side streams at once; each
+  // further one (in the same order) is issued to whichever side stream has
+  // finished its launch first, found by polling the event recorded after it.
+  // Durations vary with the sweeps each block needs, so a launch assigned in
+  // advance would often wait behind a long one while another stream is idle.
+  auto issue = [&](size_t g, int si) {
     const auto key = order[g].second;
     const std::vector<int> &idx = groups[key];
-    int si = 0;
-    for (int i = 1; i < nstream; ++i)
-      if (load[i] < load[si]) si = i;
-    load[si] += -order[g].first;
     hipStream_t s = ctx->aux[si];
     int slot = -1;
     if (timer) {
@@ -752,11 +752,21 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     launch_jacobi(dblk, didx[g], (int)idx.size(), key.first, key.second, (int)lds[key], scratch, max_sweeps,
                   dsweeps, s);
     if (timer) timer->end(ctx, s, slot);
+    TNQE_HIP(hipEventRecord(ctx->join_ev[si], s));
+  };
+  size_t g = 0;
+  for (int i = 0; i < nstream; ++i) issue(g++, i);
+  while (g < order.size()) {
+    for (int i = 0; i < nstream && g < order.size(); ++i) {
+      const hipError_t q = hipEventQuery(ctx->join_ev[i]);
+      if (q == hipSuccess) {
+        issue(g++, i);
+      } else if (q != hipErrorNotReady) {
+        TNQE_HIP(q);
+      }
+    }
   }
-  for (int i = 0; i < nstream; ++i) {
-    TNQE_HIP(hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
-    TNQE_HIP(hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
-  }
+  for (int i = 0; i < nstream; ++i) TNQE_HIP(hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
   c.check_launch();
   // times of the earlier launches, while these run (the host would wait for
   // them anyway)
