@@ -42,9 +42,13 @@ __global__ void k_sw_assemble(const int *code, int D, int n, int M, const double
 // span of the kept earlier columns -- the diagonal of the Schur complement
 // left by a Cholesky factorisation over the kept columns -- is at least
 // tol S_jj.  A (D x D, a copy of S) is overwritten by that factorisation.
-constexpr int kDiscardThreads = 1024;
+// The pivot column goes to LDS once scaled; the trailing update then takes a
+// row per wave and consecutive columns per lane (contiguous in A).
+constexpr int kDiscardThreads = 1024, kDiscardMaxD = 1024;
 __global__ void __launch_bounds__(kDiscardThreads) k_sw_discard(double *A, const double *S, int D, double tol,
                                                                  int *keep) {
+  __shared__ double l[kDiscardMaxD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kDiscardThreads / 64;
   for (int j = 0; j < D; ++j) {
     __syncthreads();
     const double d = A[(int64_t)j * D + j];
@@ -52,13 +56,17 @@ __global__ void __launch_bounds__(kDiscardThreads) k_sw_discard(double *A, const
     if (threadIdx.x == 0) keep[j] = kj ? 1 : 0;
     if (!kj) continue;
     const double inv = 1.0 / sqrt(d);
-    for (int r = j + 1 + threadIdx.x; r < D; r += kDiscardThreads) A[(int64_t)r * D + j] *= inv;
+    for (int r = j + 1 + threadIdx.x; r < D; r += kDiscardThreads) {
+      const double v = A[(int64_t)r * D + j] * inv;
+      A[(int64_t)r * D + j] = v;
+      l[r] = v;
+    }
     __syncthreads();
     // trailing lower triangle: A[r][c] -= L[r][j] L[c][j], j < c <= r
-    const int w = D - j - 1;
-    for (int64_t e = threadIdx.x; e < (int64_t)w * w; e += kDiscardThreads) {
-      const int r = j + 1 + (int)(e / w), c = j + 1 + (int)(e - (e / w) * w);
-      if (c <= r) A[(int64_t)r * D + c] -= A[(int64_t)r * D + j] * A[(int64_t)c * D + j];
+    for (int r = j + 1 + wave; r < D; r += nwave) {
+      const double lr = l[r];
+      double *row = A + (int64_t)r * D;
+      for (int c = j + 1 + lane; c <= r; c += 64) row[c] -= lr * l[c];
     }
   }
 }
@@ -287,6 +295,7 @@ void launch_sw_assemble(const int *code, int D, int n, int M, const double *H, c
 }
 
 void launch_sw_discard(double *A, const double *S, int D, double tol, int *keep, hipStream_t st) {
+  if (D > kDiscardMaxD) throw Error(TNQE_ESHAPE, "expanded pencil wider than 1024 columns");
   hipLaunchKernelGGL(k_sw_discard, dim3(1), dim3(kDiscardThreads), 0, st, A, S, D, tol, keep);
 }
 
