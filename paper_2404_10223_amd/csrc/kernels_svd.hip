@@ -131,9 +131,18 @@ __device__ inline int rank_of(const double *sig, int n, int i) {
 // squared relative inner product above which a rotation keeps the sweeps going
 constexpr double kBig2 = 1e-20;
 
-// at most 1024 threads (E <= 20) or 768 (E = 24, for the register budget)
+// at most 1024 threads (E <= 20) or 768 (E = 24, for the register budget).
+// Waves per SIMD the register allocation must allow: 6 for E = 8 and 5 for
+// E = 12 (80 and 96 registers; the few values that then leave the registers
+// are reloaded once per sweep, outside the rotation rounds), so that two
+// workgroups of 768 threads, or three of 512, share a compute unit.
 template <int E>
-__global__ void __launch_bounds__(E > 20 ? 768 : 1024) k_jacobi(const Blk *blks, const int *idx, double *scratch,
+constexpr int jacobi_waves_per_simd() {
+  return E == 8 ? 6 : E == 12 ? 5 : 1;
+}
+template <int E>
+__global__ void __launch_bounds__(E > 20 ? 768 : 1024) __attribute__((amdgpu_waves_per_eu(jacobi_waves_per_simd<E>())))
+k_jacobi(const Blk *blks, const int *idx, double *scratch,
                                                                 int max_sweeps, int *sweeps_out) {
   extern __shared__ __align__(16) double lds[];
   const Blk b = blks[idx[blockIdx.x]];

@@ -1,12 +1,13 @@
-"""Writes the stored oracle values of one generalized-sweep step at the
-N = 12, chi = 64, M = 8 workload (state 0, sites 1-2, Givens search, one
-single-site mitigation round; the expanded pencil has 400 one-hot states and
-407 columns).  The oracle takes tens of minutes here (every one-hot state is
-a sector-FCI vector), too long for a test, so its results are stored.
+"""Writes the stored oracle values of generalized-sweep steps at the
+N = 12, chi = 64, M = 8 workload: state 0 at sites 1-2 with the Givens
+search, and state 5 at sites 9-10 with the FSWAP test, each with one
+single-site mitigation round (400 one-hot states, 407 columns).  The oracle
+takes tens of minutes per step here (every one-hot state is a sector-FCI
+vector), too long for a test, so its results are stored.
 
 Calls only the seeded generator (tnqe_synth) and the FP64 oracle (oracle/),
 with the pencil (H, S) of oracle_config3.npz; nothing here touches the GPU
-library.  Usage:  python tests/golden/make_golden_sweep.py
+library.  Usage:  python tests/golden/make_golden_sweep.py [case names...]
 """
 import os
 import sys
@@ -20,11 +21,13 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import tnqe_synth as synth                     # noqa: E402
 from oracle import sweep                       # noqa: E402
 
-I_STATE, P_SITE, ROTATION, NREPS = 0, 1, "givens", 1
+# name: (state, left site, rotation, mitigation rounds)
+CASES = {"oracle_sweep_config3": (0, 1, "givens", 1), "oracle_sweep_config3_b": (5, 9, "fswap", 1)}
 N_SAMPLE = 4000   # sampled off-diagonal entries of the one-hot block H^[ii]
 
 
-def main():
+def case(name):
+    I_STATE, P_SITE, ROTATION, NREPS = CASES[name]
     prob = synth.make_config(3)
     g = np.load(os.path.join(HERE, "oracle_config3.npz"))
     t0 = time.time()
@@ -39,8 +42,8 @@ def main():
     st = o["trunc"]
     mit = o["mitigation"]
     np.savez_compressed(
-        os.path.join(HERE, "oracle_sweep_config3.npz"),
-        i=I_STATE, p=P_SITE, nreps=NREPS,
+        os.path.join(HERE, name + ".npz"),
+        i=I_STATE, p=P_SITE, nreps=NREPS, rotation=ROTATION,
         E_old=o["E_old"], E1=o["E1"], E_new=o["E_new"], accepted=int(o["accepted"]),
         n_onehot=o["n_onehot"], n_columns=len(o["keep"]), n_kept=int(o["keep"].sum()),
         n_dropped_S=o["n_dropped_S"], t_new=o["t_new"], theta=o["theta"], xi_none=o["xi_none"], xi=o["xi"],
@@ -50,8 +53,9 @@ def main():
         qn_len=np.array([q.shape[0] for q in o["qn"]]),
         index=np.array(o["index"], dtype=np.int32), Hd_diag=np.diag(Hd).copy(),
         Hd_rows=ra, Hd_cols=rb, Hd_vals=Hd[ra, rb], Sd_dev=np.abs(Sd - np.eye(n)).max(), Hc=Hc, Sc=Sc)
-    print("written", flush=True)
+    print("written", name, flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    for name in sys.argv[1:] or list(CASES):
+        case(name)

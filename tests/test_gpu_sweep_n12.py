@@ -1,11 +1,12 @@
 """The expanded one-hot pencil (Sec. II.E eq. subs_exp, App. A1) and one
 generalized-sweep step (Alg. A.1 with one single-site mitigation round,
 App. A4) at the N = 12, chi = 64, M = 8 workload, against stored oracle
-values (tests/golden/make_golden_sweep.py: state 0, sites 1-2, Givens search;
-400 one-hot states, 407 columns, so the dense eigensolves take the chip-wide
-Jacobi).  The oracle needs about 20 minutes here, so its results are stored:
-all blocks' diagonals and state columns, 4000 sampled entries of the one-hot
-block, and the step's outcome."""
+values (tests/golden/make_golden_sweep.py: state 0 at sites 1-2 with the
+Givens search, state 5 at sites 9-10 with the FSWAP test; 400 one-hot states
+and 407 columns each, so the dense eigensolves take the chip-wide Jacobi).
+The oracle needs about 20 minutes per step here, so its results are stored:
+the one-hot block's diagonal and 4000 sampled entries, the state columns, and
+the step's outcome."""
 import os
 
 import numpy as np
@@ -26,13 +27,17 @@ def ctx():
     c.close()
 
 
-@pytest.fixture(scope="module")
-def gold():
-    g = np.load(os.path.join(GOLD, "oracle_sweep_config3.npz"))
+CASES = ["oracle_sweep_config3", "oracle_sweep_config3_b"]
+
+
+def _gold(name):
+    g = np.load(os.path.join(GOLD, name + ".npz"))
     return {k: g[k] for k in g.files}
 
 
-def test_onehot_pencil_n12(ctx, gold):
+@pytest.mark.parametrize("name", CASES)
+def test_onehot_pencil_n12(ctx, name):
+    gold = _gold(name)
     prob = synth.make_config(3)
     i, p = int(gold["i"]), int(gold["p"])
     print(f"N = 12 one-hot pencil, state {i}, sites ({p}, {p + 1})", flush=True)
@@ -47,12 +52,14 @@ def test_onehot_pencil_n12(ctx, gold):
     np.testing.assert_allclose(Hd, Hd.T, atol=1e-12 * h)
 
 
-def test_sweep_step_n12(ctx, gold):
+@pytest.mark.parametrize("name", CASES)
+def test_sweep_step_n12(ctx, name):
+    gold = _gold(name)
     prob = synth.make_config(3)
     H0 = np.load(os.path.join(GOLD, "oracle_config3.npz"))
-    i, p, nreps = int(gold["i"]), int(gold["p"]), int(gold["nreps"])
-    print(f"N = 12 sweep step, state {i}, sites ({p}, {p + 1}), givens, nreps {nreps}", flush=True)
-    res, (sites, qn, U), t, rep = ctx.sweep_step(prob, H0["H"], H0["S"], i, p, rotation="givens", nreps=nreps,
+    i, p, nreps, rotation = int(gold["i"]), int(gold["p"]), int(gold["nreps"]), str(gold["rotation"])
+    print(f"N = 12 sweep step, state {i}, sites ({p}, {p + 1}), {rotation}, nreps {nreps}", flush=True)
+    res, (sites, qn, U), t, rep = ctx.sweep_step(prob, H0["H"], H0["S"], i, p, rotation=rotation, nreps=nreps,
                                                  chi=prob.chi)
     print(f"E1 {res['E1']:.12f} ({float(gold['E1']):.12f}) E_new {res['E_new']:.12f} "
           f"columns {res['n_columns']} kept {res['n_kept']}", flush=True)
