@@ -439,9 +439,10 @@ tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const doub
  * positive semi-definite A ([n][n] host, row-major, 1 <= n <= 1024): the
  * one-sided Jacobi SVD, which for such A is its eigendecomposition.  path 0
  * is the choice of the sweep step (register kernels when they hold the
- * matrix, else the global-memory Jacobi spread over the chip), 1 the
- * global-memory Jacobi in one workgroup, 2 the one spread over the chip
- * (paths 1 and 2 give the same bits).  Outputs (host): val[n] in decreasing
+ * matrix, else the global-memory Jacobi spread over the chip by blocks of
+ * columns), 1 the global-memory Jacobi in one workgroup, 2 the one spread
+ * over the chip by column pairs (paths 1 and 2 give the same bits), 3 the one
+ * spread over the chip by blocks of columns.  Outputs (host): val[n] in decreasing
  * order, vec[n][n] with row k the unit vector of val[k].  TNQE_EINVAL on bad
  * arguments. */
 tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,

@@ -410,7 +410,8 @@ class Context:
         """Device eigensolver of the sweep step's dense eigenproblems on a
         symmetric positive semi-definite A: (values in decreasing order,
         vectors by row).  path 0: the sweep step's choice, 1: one-workgroup
-        global-memory Jacobi, 2: the same sweeps spread over the chip."""
+        global-memory Jacobi, 2: the same sweeps spread over the chip by
+        column pairs, 3: spread over the chip by blocks of columns."""
         A = np.ascontiguousarray(A, dtype=np.float64)
         n = A.shape[0]
         vec, val = np.zeros((n, n)), np.zeros(n)

@@ -2947,8 +2947,9 @@ std::vector<double> truncation_errors(Call &c, KetSet &ci, int p, const double *
 // device matrix by the Jacobi SVD: vectors by row ([n][n]) and values, both
 // in decreasing order of the values.  Matrices too wide for the register
 // kernels take the global-memory Jacobi with its sweeps spread over the chip
-// (path 0); path 1 forces the one-workgroup global-memory kernel and path 2
-// the chip-wide one, at any n (both give the same bits).
+// by blocks of columns (path 0).  At any n, path 1 forces the one-workgroup
+// global-memory kernel, path 2 the chip-wide one by column pairs (the same
+// bits as path 1) and path 3 the chip-wide one by column blocks.
 void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, double *&val, int path = 0) {
   Blk b{};
   b.R = b.C = n;
@@ -2957,6 +2958,7 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
   plan_block(b);
   if (path != 0) b.offW = 0;   // global-memory storage
   const bool wide = b.offW >= 0 && path != 1;
+  const bool blocked = path == 0 || path == 3;
   Scratch sc;
   take_block_storage(b, sc);
   b.offS = sc.take(n);
@@ -2975,7 +2977,10 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
     launch_jacobi_wide_load(dblk, didx, scratch, ctl, st);
     int sweep = 0;
     for (; sweep < max_sweeps && n > 1; ++sweep) {
-      launch_jacobi_wide_sweep(scratch + b.offW, n, n, ctl, sweep & 1, st);
+      if (blocked)
+        launch_jacobi_wide_sweep_blocked(scratch + b.offW, n, n, ctl, sweep & 1, st);
+      else
+        launch_jacobi_wide_sweep(scratch + b.offW, n, n, ctl, sweep & 1, st);
       unsigned long long rot = 0;
       TNQE_HIP(hipMemcpyAsync(&rot, ctl + 2 + (sweep & 1), sizeof(rot), hipMemcpyDeviceToHost, st));
       c.sync();
@@ -4531,7 +4536,7 @@ tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const doub
 tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,
                                  double *vec, double *val) {
   if (!ctx) return TNQE_EINVAL;
-  if (n < 1 || n > 1024 || !A || !vec || !val || path < 0 || path > 2 || max_sweeps < 1)
+  if (n < 1 || n > 1024 || !A || !vec || !val || path < 0 || path > 3 || max_sweeps < 1)
     return fail(ctx, TNQE_EINVAL, "bad argument to tnqe_debug_psd_eigen");
   return guarded(ctx, [&] {
     TNQE_HIP(hipSetDevice(ctx->device));

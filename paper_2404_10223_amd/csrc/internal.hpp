@@ -151,6 +151,9 @@ constexpr int kJwFull = 0, kJwLoad = 1, kJwFinish = 2;
 void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, unsigned long long *ctl,
                              hipStream_t st);
 void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st);
+// the same sweep by blocks of 8 columns (one launch per round of block pairs;
+// not the same bits as the column-pair rounds)
+void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st);
 void launch_jacobi_wide_finish(const Blk *blk, const int *idx, double *scratch, int sweeps_done, int *sweeps_out,
                                hipStream_t st);
 // the other factor of the first `kept` sorted vectors of every block (units:

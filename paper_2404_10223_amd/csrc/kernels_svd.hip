@@ -680,6 +680,100 @@ __global__ void __launch_bounds__(64 * kJwWaves) k_jw_round(double *X, int n, in
   }
 }
 
+// The same sweeps by blocks of columns: the n vectors form nb blocks of
+// kJbCols (the last one padded with zero vectors, which never rotate), and a
+// round of the round-robin ordering over the blocks pairs them up, one
+// workgroup per block pair.  The workgroup holds its 2 kJbCols vectors in LDS
+// and rotates every pair among them once (a round-robin over the 16 vectors
+// in 15 inner rounds of 8 disjoint pairs, one wave per pair).  Every pair of
+// vectors meets at least once per sweep (the pairs inside a block at each of
+// its meetings), so the sweep is a block cyclic Jacobi sweep, in nb - 1
+// launches instead of n - 1.  Angles, norm updates and the control words are
+// those of k_jw_round.
+constexpr int kJbCols = 8, kJbThreads = 512;
+
+__global__ void __launch_bounds__(kJbThreads) k_jwb_round(double *X, int n, int m, int nb, int rd,
+                                                          unsigned long long *ctl, int slot) {
+  extern __shared__ __align__(16) double v[];   // [2 kJbCols][m]
+  __shared__ double s_n[2 * kJbCols];
+  const int nbp = nb + (nb & 1), k = blockIdx.x;
+  int I, J;
+  if (k == 0) {
+    I = nbp - 1;
+    J = rd;
+  } else {
+    I = (rd + k) % (nbp - 1);
+    J = (rd - k + nbp - 1) % (nbp - 1);
+  }
+  // with an odd block count one block meets the empty block nb (its vectors
+  // read as zero and are never written): its own pairs are still rotated
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kJbThreads / 64, NV = 2 * kJbCols;
+  double *sig = X + (int64_t)n * m;
+  for (int q = wave; q < NV; q += NW) {
+    const int c = (q < kJbCols ? I : J) * kJbCols + (q % kJbCols);
+    for (int l = lane; l < m; l += 64) v[q * m + l] = c < n ? X[(int64_t)c * m + l] : 0.0;
+    if (lane == 0) s_n[q] = c < n ? sig[c] : 0.0;
+  }
+  __syncthreads();
+  const double tiny = __longlong_as_double((long long)ctl[slot]) * 1e-28;
+  const double tol = fmax(1e-15, 2.3e-16 * sqrt((double)m));
+  int rotated = 0, big = 0;
+  for (int r = 0; r < NV - 1; ++r) {
+    int a, b;
+    if (wave == 0) {
+      a = NV - 1;
+      b = r;
+    } else {
+      a = (r + wave) % (NV - 1);
+      b = (r - wave + NV - 1) % (NV - 1);
+    }
+    const double al = s_n[a], be = s_n[b];
+    if (al > tiny && be > tiny) {
+      // the pair's components in registers (at most kJwMaxE per lane), the
+      // sum over the wave by DPP within rows of 16 lanes
+      double *xa = v + a * m, *xb = v + b * m;
+      double u[kJwMaxE], w[kJwMaxE];
+#pragma unroll
+      for (int e = 0; e < kJwMaxE; ++e) {
+        const int l = lane + 64 * e;
+        u[e] = l < m ? xa[l] : 0.0;
+        w[e] = l < m ? xb[l] : 0.0;
+      }
+      double ga = 0.0;
+#pragma unroll
+      for (int e = 0; e < kJwMaxE; ++e) ga = fma(u[e], w[e], ga);
+      ga = group_sum(ga, 64);
+      if (fabs(ga) > tol * sqrt(al * be)) {
+        big |= ga * ga > kBig2 * (al * be) ? 1 : 0;
+        double c, s;
+        const double tn = jacobi_angle(al, be, ga, c, s);
+#pragma unroll
+        for (int e = 0; e < kJwMaxE; ++e) {
+          const int l = lane + 64 * e;
+          if (l < m) {
+            xa[l] = c * u[e] - s * w[e];
+            xb[l] = s * u[e] + c * w[e];
+          }
+        }
+        if (lane == 0) {
+          s_n[a] = fmax(al - tn * ga, 0.0);
+          s_n[b] = be + tn * ga;
+        }
+        rotated = 1;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = wave; q < NV; q += NW) {
+    const int c = (q < kJbCols ? I : J) * kJbCols + (q % kJbCols);
+    if (c >= n) continue;
+    for (int l = lane; l < m; l += 64) X[(int64_t)c * m + l] = v[q * m + l];
+    if (lane == 0) sig[c] = s_n[q];
+  }
+  if (lane == 0 && rotated) atomicOr(&ctl[2 + slot], big ? 3ull : 1ull);
+}
+
 template <int E>
 void set_lds_cap() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jacobi<E>),
@@ -735,6 +829,22 @@ void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, 
   for (int rd = 0; rd < np - 1; ++rd)
     hipLaunchKernelGGL(k_jw_round, dim3((pairs + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m,
                        rd, ctl, slot);
+}
+
+void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
+  if (m > 1024) throw Error(TNQE_ESHAPE, "chip-wide Jacobi: vectors longer than 1024");
+  static bool attr_set = false;
+  if (!attr_set) {
+    TNQE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jwb_round),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kJbCols * 1024 * 8));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_jw_norms, dim3((n + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m, ctl,
+                     slot);
+  const int nb = (n + kJbCols - 1) / kJbCols, nbp = nb + (nb & 1);
+  const size_t lds = (size_t)2 * kJbCols * m * sizeof(double);
+  for (int rd = 0; rd < nbp - 1; ++rd)
+    hipLaunchKernelGGL(k_jwb_round, dim3(nbp / 2), dim3(kJbThreads), lds, st, X, n, m, nb, rd, ctl, slot);
 }
 
 void launch_jacobi_wide_finish(const Blk *blk, const int *idx, double *scratch, int sweeps_done, int *sweeps_out,

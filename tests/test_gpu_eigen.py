@@ -78,9 +78,20 @@ def test_chip_wide_jacobi_largest(ctx, n):
     _check(A, lam, val, vec)
 
 
+@pytest.mark.parametrize("n", [2, 7, 8, 9, 17, 64, 301, 407, 1024])
+@pytest.mark.parametrize("kind", ["spread", "repeated", "deficient"])
+def test_chip_wide_blocked_jacobi(ctx, n, kind):
+    """The sweeps by blocks of 8 columns (the sweep step's choice for wide
+    matrices): block counts odd and even, a last block only partly filled."""
+    print(f"psd_eigen path 3 n={n} kind={kind}", flush=True)
+    A, lam = _psd(n, kind, 400 + n)
+    val, vec = ctx.debug_psd_eigen(A, path=3)
+    _check(A, lam, val, vec)
+
+
 def test_psd_eigen_errors(ctx):
     A = np.eye(4)
-    for kw in (dict(path=3), dict(path=-1), dict(max_sweeps=0)):
+    for kw in (dict(path=4), dict(path=-1), dict(max_sweeps=0)):
         with pytest.raises(T.TnqeError):
             ctx.debug_psd_eigen(A, **kw)
     with pytest.raises(T.TnqeError):
