@@ -541,6 +541,25 @@ JacobiPlan jacobi_plan(int n, int m) {
       break;
     }
   }
+  // workgroups wider than `wide` threads take half the lanes per vector (twice
+  // the components per lane, at most 16) when that fits: two such workgroups
+  // then share a compute unit (tuning: TNQE_JACOBI_WIDE; at N = 24, chi = 256
+  // 768 gave 1.36-1.38 s per solve, 512 1.39-1.40 s, no halving 1.43-1.44 s)
+  static const int wide = [] {
+    const char *e = std::getenv("TNQE_JACOBI_WIDE");
+    return e ? std::atoi(e) : 768;
+  }();
+  if (best >= 2 && jp.threads > wide) {
+    const int G = best / 2, E = ((m + G - 1) / G + 3) / 4 * 4;
+    const int64_t lds = ((int64_t)NTr * G * (E + 2) + NTr + n) * 8 + (int64_t)n * 4;
+    if (E <= 16 && P * G <= jacobi_max_threads(E) && lds <= kJacobiLdsBytes) {
+      jp.kind = E / 4 - 1;
+      jp.grp = G;
+      jp.threads = (P * G + 63) / 64 * 64;
+      jp.mpad = G * (E + 2);
+      jp.lds = lds;
+    }
+  }
   return jp;
 }
 
