@@ -142,8 +142,7 @@ constexpr int jacobi_waves_per_simd() {
 }
 template <int E>
 __global__ void __launch_bounds__(E > 20 ? 768 : 1024) __attribute__((amdgpu_waves_per_eu(jacobi_waves_per_simd<E>())))
-k_jacobi(const Blk *blks, const int *idx, double *scratch,
-                                                                int max_sweeps, int *sweeps_out) {
+k_jacobi(const Blk *blks, const int *idx, double *scratch, int max_sweeps, int *sweeps_out) {
   extern __shared__ __align__(16) double lds[];
   const Blk b = blks[idx[blockIdx.x]];
   const int R = b.R, C = b.C;
@@ -387,7 +386,7 @@ k_jacobi(const Blk *blks, const int *idx, double *scratch,
 // mode kJwFull runs everything in this workgroup; kJwLoad only fills the work
 // area (and clears the control words ctl of the chip-wide variant), kJwFinish
 // only takes the final norms, ranks and writes the vectors after `sweeps_done`
-// sweeps made by k_jw_norms / k_jw_round.
+// sweeps made by k_jw_norms with k_jw_round or k_jwb_round.
 __global__ void __launch_bounds__(1024) k_jacobi_global(const Blk *blks, const int *idx, double *scratch,
                                                         int max_sweeps, int *sweeps_out, int mode,
                                                         int sweeps_done, unsigned long long *ctl) {
