@@ -698,12 +698,13 @@ void launch_apply_qr(const KetTables &kt, int p, const Blk *blk, int nblk, const
 void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double *scratch, int chi, double tau,
                    const KetTables &kt, int bond, int *kept_out, double *stats, double *scale, hipStream_t st) {
   if (nket == 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
+  // once per process (thread-safe initialisation of a function-local static)
+  static const bool attr_set = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kSelectLdsBytes);
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   const size_t lds = select_lds_bytes(maxv, kt.nslot);
   hipLaunchKernelGGL(k_select, dim3(nket), dim3(kSelThreads), lds, st, blk, kfirst, maxv, scratch, chi, tau, kt,
                      bond, kept_out, stats, scale);
@@ -712,12 +713,12 @@ void launch_select(Blk *blk, const int *kfirst, int nket, int maxv, const double
 void launch_qr_blocks(const Blk *blk, const int *idx, int nblk, int lds_bytes, bool left, double *scratch,
                       hipStream_t st) {
   if (nblk == 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static const bool attr_set = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_qr_blocks),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kQrLdsBytes);
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   hipLaunchKernelGGL(k_qr_blocks, dim3(nblk), dim3(kQrThreads), lds_bytes, st, blk, idx, scratch, left ? 1 : 0);
 }
 

@@ -791,16 +791,17 @@ void launch_e(const Blk *blk, const int *idx, int nblk, int threads, int lds_byt
 void launch_jacobi(const Blk *blk, const int *idx, int nblk, int kind, int threads, int lds_bytes,
                    double *scratch, int max_sweeps, int *sweeps_out, hipStream_t st) {
   if (nblk == 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
+  // once per process (thread-safe initialisation of a function-local static)
+  static const bool attr_set = [] {
     set_lds_cap<4>();
     set_lds_cap<8>();
     set_lds_cap<12>();
     set_lds_cap<16>();
     set_lds_cap<20>();
     set_lds_cap<24>();
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   switch (kind) {
     case 0: launch_e<4>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
     case 1: launch_e<8>(blk, idx, nblk, threads, lds_bytes, scratch, max_sweeps, sweeps_out, st); break;
@@ -832,12 +833,12 @@ void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, 
 
 void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
   if (m > 1024) throw Error(TNQE_ESHAPE, "chip-wide Jacobi: vectors longer than 1024");
-  static bool attr_set = false;
-  if (!attr_set) {
+  static const bool attr_set = [] {
     TNQE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jwb_round),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kJbCols * 1024 * 8));
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   hipLaunchKernelGGL(k_jw_norms, dim3((n + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m, ctl,
                      slot);
   const int nb = (n + kJbCols - 1) / kJbCols, nbp = nb + (nb & 1);
