@@ -31,7 +31,7 @@ def log(*a):
 
 SVD_KERNELS = ["k_jacobi<%d>" % (4 * (k + 1)) for k in range(6)] + ["k_jacobi_global", "k_qr_blocks"] + [None] * 8
 JACOBI_FAMILY = "k_jacobi<E>"
-KERNEL_SOURCE = {"k_jacobi": "kernels_svd.hip", "k_env": "kernels_env.hip", "k_mix": "kernels_env.hip"}
+KERNEL_SOURCE = {"k_jacobi": "kernels_svd.hip", "k_env": "kernels_env.hip", "k_mix": "kernels_env.hip", "k_qr": "kernels_gate.hip"}
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.md")
 ENV_KERNELS = ["k_env_g1", "k_mix", "k_env_gd", "k_env_g2", "k_env_final", None, None, None]
 MACHINE_BALANCE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte
