@@ -542,10 +542,55 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 // are 1, so the apply kernels multiply by L (R_X) and write Q unscaled.
 constexpr int kQrThreads = 256, kQrWaves = kQrThreads / 64;
 
+// one 64-bit value moved by a DPP lane permutation (two 32-bit moves)
+template <int CTRL>
+__device__ inline double qr_dpp64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave, the same bits in every lane (each step
+// adds two lanes' partial sums, and the two lanes of a step add the same
+// operands): DPP within rows of 16 lanes, then two cross-row exchanges.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += qr_dpp64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  v += qr_dpp64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  v += qr_dpp64<0x141>(v);   // row_half_mirror: the other quad of 8
+  v += qr_dpp64<0x140>(v);   // row_mirror: the other half of 16
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
+}
+
+// (I - tj v v^T) applied to columns r0, r0 + kQrWaves, ... < rend of the
+// m-row matrix X in LDS (v: x[j + 1 ..] with an implicit 1 at row j), two
+// columns at a time so that their reductions overlap; one wave's part
+__device__ inline void apply_reflector(double *qx, int m, int j, int r0, int rend, const double *x, double tj,
+                                       int lane) {
+  for (int r = r0; r < rend; r += 2 * kQrWaves) {
+    const int r2 = r + kQrWaves;
+    const bool two = r2 < rend;
+    double *y = qx + (int64_t)r * m, *y2 = qx + (int64_t)(two ? r2 : r) * m;
+    double w = lane == 0 ? y[j] : 0.0, w2 = (two && lane == 0) ? y2[j] : 0.0;
+    for (int i = j + 1 + lane; i < m; i += 64) {
+      const double xi = x[i];
+      w += xi * y[i];
+      if (two) w2 += xi * y2[i];
+    }
+    w = wave_sum(w) * tj;
+    w2 = wave_sum(w2) * tj;
+    if (lane == 0) {
+      y[j] -= w;
+      if (two) y2[j] -= w2;
+    }
+    for (int i = j + 1 + lane; i < m; i += 64) {
+      const double xi = x[i];
+      y[i] -= w * xi;
+      if (two) y2[i] -= w2 * xi;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const int *idx, double *scratch,
@@ -584,16 +629,7 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
     }
     __syncthreads();
     const double tj = tau[j];
-    if (tj != 0.0) {
-      for (int r = j + 1 + wave; r < c; r += kQrWaves) {
-        double *y = qx + (int64_t)r * m;
-        double w = lane == 0 ? y[j] : 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
-        w = wave_sum(w) * tj;
-        if (lane == 0) y[j] -= w;
-        for (int i = j + 1 + lane; i < m; i += 64) y[i] -= w * x[i];
-      }
-    }
+    if (tj != 0.0) apply_reflector(qx, m, j, j + 1 + wave, c, x, tj, lane);
     __syncthreads();
   }
   double *Uo = scratch + b.offU, *Bo = scratch + b.offB, *So = scratch + b.offS;
@@ -613,14 +649,7 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
   for (int j = k - 1; j >= 0; --j) {
     double *x = qx + (int64_t)j * m;
     const double tj = tau[j];
-    for (int r = j + 1 + wave; r < k; r += kQrWaves) {
-      double *y = qx + (int64_t)r * m;
-      double w = lane == 0 ? y[j] : 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
-      w = wave_sum(w) * tj;
-      if (lane == 0) y[j] -= w;
-      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= w * x[i];
-    }
+    apply_reflector(qx, m, j, j + 1 + wave, k, x, tj, lane);
     __syncthreads();
     for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) x[i] *= -tj;
     for (int i = threadIdx.x; i < j; i += kQrThreads) x[i] = 0.0;
