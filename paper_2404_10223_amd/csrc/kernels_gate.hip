@@ -593,6 +593,28 @@ __device__ inline void apply_reflector(double *qx, int m, int j, int r0, int ren
   }
 }
 
+// Householder reflector of column j of X (rows j..m-1) by one wave: tau[j],
+// R_jj in x[j] and v (implicit 1 at row j) in x[j+1 ..]
+__device__ inline void make_reflector(double *qx, int m, int j, int lane, double *tau) {
+  double *x = qx + (int64_t)j * m;
+  double sg = 0.0;
+  for (int i = j + 1 + lane; i < m; i += 64) sg += x[i] * x[i];
+  sg = wave_sum(sg);
+  const double alpha = x[j];
+  double t = 0.0, beta = alpha, scale = 0.0;
+  if (sg > 0.0) {
+    const double nrm = sqrt(alpha * alpha + sg);
+    beta = alpha >= 0.0 ? -nrm : nrm;
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int i = j + 1 + lane; i < m; i += 64) x[i] *= scale;
+  if (lane == 0) {
+    tau[j] = t;
+    x[j] = beta;
+  }
+}
+
 __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const int *idx, double *scratch,
                                                           int left) {
   extern __shared__ __align__(16) double qx[];
@@ -607,29 +629,20 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // one barrier per reflector: wave 0, which owns column j + 1, updates it
+  // first and forms reflector j + 1 while the other waves still apply j
+  if (k > 0 && wave == 0) make_reflector(qx, m, 0, lane, tau);
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
-    double *x = qx + (int64_t)j * m;
-    if (wave == 0) {
-      double sg = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) sg += x[i] * x[i];
-      sg = wave_sum(sg);
-      const double alpha = x[j];
-      double t = 0.0, beta = alpha, scale = 0.0;
-      if (sg > 0.0) {
-        const double nrm = sqrt(alpha * alpha + sg);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        t = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      for (int i = j + 1 + lane; i < m; i += 64) x[i] *= scale;
-      if (lane == 0) {
-        tau[j] = t;
-        x[j] = beta;
-      }
-    }
-    __syncthreads();
+    const double *x = qx + (int64_t)j * m;
     const double tj = tau[j];
-    if (tj != 0.0) apply_reflector(qx, m, j, j + 1 + wave, c, x, tj, lane);
+    if (wave == 0 && j + 1 < k) {
+      if (tj != 0.0) apply_reflector(qx, m, j, j + 1, j + 2, x, tj, lane);
+      make_reflector(qx, m, j + 1, lane, tau);
+      if (tj != 0.0) apply_reflector(qx, m, j, j + 1 + kQrWaves, c, x, tj, lane);
+    } else if (tj != 0.0) {
+      apply_reflector(qx, m, j, j + 1 + wave, c, x, tj, lane);
+    }
     __syncthreads();
   }
   double *Uo = scratch + b.offU, *Bo = scratch + b.offB, *So = scratch + b.offS;
