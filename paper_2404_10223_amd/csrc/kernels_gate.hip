@@ -593,6 +593,15 @@ __device__ inline void apply_reflector(double *qx, int m, int j, int r0, int ren
   }
 }
 
+// column j of Q from the stored reflector j (v in x[j+1 ..], tau tj) once the
+// later reflectors have been applied to it, by one wave
+__device__ inline void form_q_column(double *qx, int m, int j, double tj, int lane) {
+  double *x = qx + (int64_t)j * m;
+  for (int i = j + 1 + lane; i < m; i += 64) x[i] *= -tj;
+  for (int i = lane; i < j; i += 64) x[i] = 0.0;
+  if (lane == 0) x[j] = 1.0 - tj;
+}
+
 // Householder reflector of column j of X (rows j..m-1) by one wave: tau[j],
 // R_jj in x[j] and v (implicit 1 at row j) in x[j+1 ..]
 __device__ inline void make_reflector(double *qx, int m, int j, int lane, double *tau) {
@@ -658,17 +667,17 @@ __global__ void __launch_bounds__(kQrThreads) k_qr_blocks(const Blk *blks, const
   }
   for (int e = threadIdx.x; e < k; e += kQrThreads) So[e] = 1.0;
   __syncthreads();
-  // Q_X (m x k) in place of the first k columns
+  // Q_X (m x k) in place of the first k columns, backwards; column j + 1
+  // becomes a column of Q (it is no longer read as reflector j + 1) in step j,
+  // by wave 0, which then applies reflector j to it: one barrier per step
   for (int j = k - 1; j >= 0; --j) {
-    double *x = qx + (int64_t)j * m;
-    const double tj = tau[j];
-    apply_reflector(qx, m, j, j + 1 + wave, k, x, tj, lane);
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) x[i] *= -tj;
-    for (int i = threadIdx.x; i < j; i += kQrThreads) x[i] = 0.0;
-    if (threadIdx.x == 0) x[j] = 1.0 - tj;
+    const double *x = qx + (int64_t)j * m;
+    if (wave == 0 && j + 1 < k) form_q_column(qx, m, j + 1, tau[j + 1], lane);
+    apply_reflector(qx, m, j, j + 1 + wave, k, x, tau[j], lane);
     __syncthreads();
   }
+  if (k > 0 && wave == 0) form_q_column(qx, m, 0, tau[0], lane);
+  __syncthreads();
   for (int e = threadIdx.x; e < k * m; e += kQrThreads) Qt[e] = sgn[e / m] * qx[e];
 }
 
