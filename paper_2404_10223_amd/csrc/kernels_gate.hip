@@ -540,7 +540,7 @@ __global__ void k_site_sign(double *const *site, const int *rows, int cols) {
 // in the slots the move kernels read: U ([k][R]) and B ([k][C]) take R_X and
 // Q_X^T (left move) or Q_X^T and R_X (right move); the k "singular values"
 // are 1, so the apply kernels multiply by L (R_X) and write Q unscaled.
-constexpr int kQrThreads = 256, kQrWaves = kQrThreads / 64;
+constexpr int kQrThreads = 1024, kQrWaves = kQrThreads / 64;
 
 // one 64-bit value moved by a DPP lane permutation (two 32-bit moves)
 template <int CTRL>
