@@ -1874,37 +1874,39 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       auto tiles = [](int64_t M, int64_t Nn, int tm, int tn) {
         return (M <= 0 || Nn <= 0) ? (int64_t)0 : ((M + tm - 1) / tm) * ((Nn + tn - 1) / tn);
       };
-      for (size_t di = 0; di < tb.g1.size(); ++di) {
-        const EnvG1 &d = tb.g1[di];
-        for (int q = 0; q < nb_; ++q)
+      // pair-major order: the problems of one pair, which share their
+      // operand blocks, run close together in time and reuse them from L2
+      for (int q = 0; q < nb_; ++q)
+        for (size_t di = 0; di < tb.g1.size(); ++di) {
+          const EnvG1 &d = tb.g1[di];
           add(w.g1, w.n1, (int)di, q,
               tiles((int64_t)idim(bra_item[q], x, d.sbra) * d.nw, idim(ket_item[q], x + 1, d.sk), tb.tm1, tb.tn1));
-      }
-      for (size_t ti = 0; ti < tb.tasks.size(); ++ti) {
-        const MixTask &tk = tb.tasks[ti];
-        for (int q = 0; q < nb_; ++q) {
-          const int64_t items = (int64_t)((idim(bra_item[q], x, tk.sa) + kMixRows - 1) / kMixRows) * tk.nw_out *
-                                ((idim(ket_item[q], x + 1, tk.s) + 3) / 4);
+        }
+      for (int q = 0; q < nb_; ++q)
+        for (size_t ti = 0; ti < tb.tasks.size(); ++ti) {
+          const MixTask &tk = tb.tasks[ti];
+          const int da = idim(bra_item[q], x, tk.sa), db = idim(ket_item[q], x + 1, tk.s);
+          const int64_t items =
+              (int64_t)((da + kMixRows - 1) / kMixRows) * tk.nw_out * ((db + kMixCols - 1) / kMixCols);
           add(w.mix, w.nmix, (int)ti, q, (items + 255) / 256);
         }
-      }
       w.dense.resize(tb.dense.size());
       w.nd.assign(tb.dense.size(), 0);
       for (size_t lv = 0; lv < tb.dense.size(); ++lv)
-        for (size_t di = 0; di < tb.dense[lv].size(); ++di) {
-          const EnvGD &d = tb.dense[lv][di];
-          for (int q = 0; q < nb_; ++q)
+        for (int q = 0; q < nb_; ++q)
+          for (size_t di = 0; di < tb.dense[lv].size(); ++di) {
+            const EnvGD &d = tb.dense[lv][di];
             add(w.dense[lv], w.nd[lv], (int)di, q,
                 tiles(d.nr, (int64_t)idim(bra_item[q], x, d.sa) * idim(ket_item[q], x + 1, d.s), tb.tmd[lv],
                       tb.tnd[lv]));
-        }
-      for (size_t di = 0; di < tb.g2.size(); ++di) {
-        const EnvG2 &d = tb.g2[di];
-        for (int q = 0; q < nb_; ++q)
+          }
+      for (int q = 0; q < nb_; ++q)
+        for (size_t di = 0; di < tb.g2.size(); ++di) {
+          const EnvG2 &d = tb.g2[di];
           add(w.g2, w.n2, (int)di, q,
               tiles(idim(bra_item[q], x + 1, d.sbn), (int64_t)d.nw * idim(ket_item[q], x + 1, d.s), tb.tm2,
                     tb.tn2));
-      }
+        }
     });
     struct DevWork {
       const EnvWork *g1, *mix, *g2;

@@ -288,9 +288,11 @@ struct MixTask {
   int x, sa, s, nw_out;
   int src0, nsrc;      // range in the site's source array
 };
-// A channel-mix thread computes 4 consecutive ket columns of kMixRows bra
-// rows (same output channel): the coupling structure is loaded once for them.
-constexpr int kMixRows = 2;
+// A channel-mix thread computes kMixCols ket columns of kMixRows bra rows
+// (same output channel): the coupling structure is loaded once for them.
+constexpr int kMixRows = 8;
+constexpr int kMixCols = 1;
+constexpr int kMixUnroll = 2;
 struct MixArgs {
   const MixTask *tasks;
   const EnvWork *work;      // (task, pair, first chunk of 256 items)

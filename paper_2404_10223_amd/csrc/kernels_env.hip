@@ -305,26 +305,30 @@ __global__ void __launch_bounds__(256) k_env_gd(const EnvGD *descs, const EnvWor
 // ------------------------------------------------------------------ channel mix
 // Y[a][w'][b] = sum over the task's sources and the nonzeros z of row w' of
 // each source's MPO group of factor * v_z * X[a][col_z][b].  A thread takes
-// four consecutive b of kMixRows consecutive bra rows a with the same w', so
-// each coupling it loads serves all of them; a row's couplings are shared by
-// all threads of the row.
+// RA = kMixRows consecutive bra rows a of one output channel w' and CJ =
+// kMixCols ket columns b = t + j qpr (j < CJ, qpr = ceil(db / CJ)); the qpr
+// threads of a (rows, w') group are consecutive, so each load and store
+// instruction covers contiguous columns across the group's lanes, and each
+// coupling a thread loads serves all its rows and columns.  The loads of
+// kMixUnroll couplings are issued together.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
-  constexpr int RA = kMixRows;
+  constexpr int RA = kMixRows, CJ = kMixCols, U = kMixUnroll;
   const EnvWork wk = find_work(a.work, a.nwork, blockIdx.x);
   const int pair = wk.pair;
   const MixTask tk = a.tasks[wk.desc];
   const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
-  const int qpr = (db + 3) >> 2, nag = (da + RA - 1) / RA;
+  const int qpr = (db + CJ - 1) / CJ, nag = (da + RA - 1) / RA;
   const int item = (blockIdx.x - wk.first) * 256 + threadIdx.x;
   if (item >= nag * tk.nw_out * qpr) return;
-  const int row = item / qpr, b0 = (item - row * qpr) * 4;
+  const int row = item / qpr, b0 = item - row * qpr;
   const int ag = row / tk.nw_out, w = row - ag * tk.nw_out;
   const int ap0 = ag * RA, na = min(RA, da - ap0);
   const double *vals = a.vals + a.basis[pair] * a.basis_stride;
   const T *Xp = X[pair];
-  const int nb = min(4, db - b0);
-  double acc[RA][4] = {};
+  // columns b0 + j qpr, j < nb, lie inside the block
+  const int nb = (db - b0 + qpr - 1) / qpr;
+  double acc[RA][CJ] = {};
   for (int si = tk.src0; si < tk.src0 + tk.nsrc; ++si) {
     const MixSrc sr = a.srcs[si];
     const int z0 = a.rowptr[sr.rp + w], z1 = a.rowptr[sr.rp + w + 1];
@@ -332,35 +336,35 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
     const double *v = vals + sr.vbase;
     const int64_t rs = (int64_t)sr.nw_in * db;   // X row stride between bra rows
     const T *xb = Xp + sr.offX + (int64_t)ap0 * rs + b0;
-    // two couplings at a time: their loads (both bra rows) are issued
-    // together; the terms are added in coupling order
+    // U couplings at a time: their loads (all rows) are issued together;
+    // the terms are added in coupling order
     int z = z0;
-    for (; z + 2 <= z1; z += 2) {
-      double cf[2], xv[2][RA][4];
+    for (; z + U <= z1; z += U) {
+      double cf[U], xv[U][RA][CJ];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < U; ++u) {
         cf[u] = sr.factor * v[z + u];
         const T *xr = xb + (int64_t)col[z + u] * db;
 #pragma unroll
         for (int r = 0; r < RA; ++r)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) xv[u][r][j] = (r < na && j < nb) ? (double)xr[r * rs + j] : 0.0;
+          for (int j = 0; j < CJ; ++j) xv[u][r][j] = (r < na && j < nb) ? (double)xr[r * rs + j * qpr] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int r = 0; r < RA; ++r)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[r][j] += cf[u] * xv[u][r][j];
+          for (int j = 0; j < CJ; ++j) acc[r][j] += cf[u] * xv[u][r][j];
     }
-    if (z < z1) {
+    for (; z < z1; ++z) {
       const double cf = sr.factor * v[z];
       const T *xr = xb + (int64_t)col[z] * db;
 #pragma unroll
       for (int r = 0; r < RA; ++r)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (r < na && j < nb) acc[r][j] += cf * (double)xr[r * rs + j];
+        for (int j = 0; j < CJ; ++j)
+          if (r < na && j < nb) acc[r][j] += cf * (double)xr[r * rs + j * qpr];
     }
   }
 #pragma unroll
@@ -368,8 +372,8 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
     if (r >= na) break;
     T *yr = Y[pair] + tk.offY + ((int64_t)(ap0 + r) * tk.nw_out + w) * db + b0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j < nb) yr[j] = (T)acc[r][j];
+    for (int j = 0; j < CJ; ++j)
+      if (j < nb) yr[j * qpr] = (T)acc[r][j];
   }
 }
 
