@@ -442,7 +442,9 @@ tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const doub
  * matrix, else the global-memory Jacobi spread over the chip by blocks of
  * columns), 1 the global-memory Jacobi in one workgroup, 2 the one spread
  * over the chip by column pairs (paths 1 and 2 give the same bits), 3 the one
- * spread over the chip by blocks of columns.  Outputs (host): val[n] in decreasing
+ * spread over the chip by blocks of columns, each sweep's launches replayed
+ * from a captured HIP graph (as path 0 does), 4 the same with the launches
+ * issued one by one (paths 3 and 4 give the same bits).  Outputs (host): val[n] in decreasing
  * order, vec[n][n] with row k the unit vector of val[k].  TNQE_EINVAL on bad
  * arguments. */
 tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,

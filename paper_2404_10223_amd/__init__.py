@@ -411,7 +411,9 @@ class Context:
         symmetric positive semi-definite A: (values in decreasing order,
         vectors by row).  path 0: the sweep step's choice, 1: one-workgroup
         global-memory Jacobi, 2: the same sweeps spread over the chip by
-        column pairs, 3: spread over the chip by blocks of columns."""
+        column pairs, 3: spread over the chip by blocks of columns with each
+        sweep replayed from a captured HIP graph, 4: as 3 with the launches
+        issued one by one."""
         A = np.ascontiguousarray(A, dtype=np.float64)
         n = A.shape[0]
         vec, val = np.zeros((n, n)), np.zeros(n)

@@ -2971,6 +2971,19 @@ std::vector<double> truncation_errors(Call &c, KetSet &ci, int p, const double *
 // by blocks of columns (path 0).  At any n, path 1 forces the one-workgroup
 // global-memory kernel, path 2 the chip-wide one by column pairs (the same
 // bits as path 1) and path 3 the chip-wide one by column blocks.
+// the two instantiated sweep graphs of a chip-wide eigensolve (one per
+// control slot), released when the solve returns or throws
+struct SweepGraphs {
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  SweepGraphs() = default;
+  SweepGraphs(const SweepGraphs &) = delete;
+  SweepGraphs &operator=(const SweepGraphs &) = delete;
+  ~SweepGraphs() {
+    for (hipGraphExec_t e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
+};
+
 void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, double *&val, int path = 0) {
   Blk b{};
   b.R = b.C = n;
@@ -2979,7 +2992,8 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
   plan_block(b);
   if (path != 0) b.offW = 0;   // global-memory storage
   const bool wide = b.offW >= 0 && path != 1;
-  const bool blocked = path == 0 || path == 3;
+  const bool blocked = path == 0 || path == 3 || path == 4;
+  const bool graphs = path == 0 || path == 3;
   Scratch sc;
   take_block_storage(b, sc);
   b.offS = sc.take(n);
@@ -2996,14 +3010,41 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
     const int *didx = c.upload(std::vector<int>{0});
     unsigned long long *ctl = c.dev<unsigned long long>(4);
     launch_jacobi_wide_load(dblk, didx, scratch, ctl, st);
+    // a blocked sweep is 1 + (blocks - 1) launches with the same arguments in
+    // every sweep of the same control slot: each slot's sequence is captured
+    // once into a graph and replayed on the call's stream (kernel nodes only;
+    // captured on a side stream of the library, since the caller's stream
+    // may be the null stream, which cannot be captured)
+    SweepGraphs sg;
+    hipStream_t cst = c.ctx->aux[0];
+    if (graphs) prepare_jacobi_wide_sweep_blocked();
     int sweep = 0;
     for (; sweep < max_sweeps && n > 1; ++sweep) {
-      if (blocked)
-        launch_jacobi_wide_sweep_blocked(scratch + b.offW, n, n, ctl, sweep & 1, st);
-      else
-        launch_jacobi_wide_sweep(scratch + b.offW, n, n, ctl, sweep & 1, st);
+      const int slot = sweep & 1;
+      if (graphs) {
+        if (!sg.exec[slot]) {
+          TNQE_HIP(hipStreamBeginCapture(cst, hipStreamCaptureModeRelaxed));
+          hipGraph_t g = nullptr;
+          try {
+            launch_jacobi_wide_sweep_blocked(scratch + b.offW, n, n, ctl, slot, cst);
+          } catch (...) {
+            (void)hipStreamEndCapture(cst, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          TNQE_HIP(hipStreamEndCapture(cst, &g));
+          const hipError_t e = hipGraphInstantiate(&sg.exec[slot], g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          TNQE_HIP(e);
+        }
+        TNQE_HIP(hipGraphLaunch(sg.exec[slot], st));
+      } else if (blocked) {
+        launch_jacobi_wide_sweep_blocked(scratch + b.offW, n, n, ctl, slot, st);
+      } else {
+        launch_jacobi_wide_sweep(scratch + b.offW, n, n, ctl, slot, st);
+      }
       unsigned long long rot = 0;
-      TNQE_HIP(hipMemcpyAsync(&rot, ctl + 2 + (sweep & 1), sizeof(rot), hipMemcpyDeviceToHost, st));
+      TNQE_HIP(hipMemcpyAsync(&rot, ctl + 2 + slot, sizeof(rot), hipMemcpyDeviceToHost, st));
       c.sync();
       if ((rot & 2) == 0) break;   // no rotation of a pair not yet orthogonal to 1e-10
     }
@@ -4557,7 +4598,7 @@ tnqe_status tnqe_debug_gep(tnqe_ctx *ctx, int32_t M, const double *H, const doub
 tnqe_status tnqe_debug_psd_eigen(tnqe_ctx *ctx, int32_t n, const double *A, int32_t path, int32_t max_sweeps,
                                  double *vec, double *val) {
   if (!ctx) return TNQE_EINVAL;
-  if (n < 1 || n > 1024 || !A || !vec || !val || path < 0 || path > 3 || max_sweeps < 1)
+  if (n < 1 || n > 1024 || !A || !vec || !val || path < 0 || path > 4 || max_sweeps < 1)
     return fail(ctx, TNQE_EINVAL, "bad argument to tnqe_debug_psd_eigen");
   return guarded(ctx, [&] {
     TNQE_HIP(hipSetDevice(ctx->device));

@@ -152,7 +152,9 @@ void launch_jacobi_wide_load(const Blk *blk, const int *idx, double *scratch, un
                              hipStream_t st);
 void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st);
 // the same sweep by blocks of 8 columns (one launch per round of block pairs;
-// not the same bits as the column-pair rounds)
+// not the same bits as the column-pair rounds); prepare_... sets the kernel's
+// LDS limit once, so that a stream capture of the launches holds launches only
+void prepare_jacobi_wide_sweep_blocked();
 void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st);
 void launch_jacobi_wide_finish(const Blk *blk, const int *idx, double *scratch, int sweeps_done, int *sweeps_out,
                                hipStream_t st);

@@ -831,14 +831,19 @@ void launch_jacobi_wide_sweep(double *X, int n, int m, unsigned long long *ctl, 
                        rd, ctl, slot);
 }
 
-void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
-  if (m > 1024) throw Error(TNQE_ESHAPE, "chip-wide Jacobi: vectors longer than 1024");
+void prepare_jacobi_wide_sweep_blocked() {
+  // once per process (thread-safe initialisation of a function-local static)
   static const bool attr_set = [] {
     TNQE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jwb_round),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kJbCols * 1024 * 8));
     return true;
   }();
   (void)attr_set;
+}
+
+void launch_jacobi_wide_sweep_blocked(double *X, int n, int m, unsigned long long *ctl, int slot, hipStream_t st) {
+  if (m > 1024) throw Error(TNQE_ESHAPE, "chip-wide Jacobi: vectors longer than 1024");
+  prepare_jacobi_wide_sweep_blocked();
   hipLaunchKernelGGL(k_jw_norms, dim3((n + kJwWaves - 1) / kJwWaves), dim3(64 * kJwWaves), 0, st, X, n, m, ctl,
                      slot);
   const int nb = (n + kJbCols - 1) / kJbCols, nbp = nb + (nb & 1);

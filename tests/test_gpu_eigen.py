@@ -89,9 +89,25 @@ def test_chip_wide_blocked_jacobi(ctx, n, kind):
     _check(A, lam, val, vec)
 
 
+@pytest.mark.parametrize("n", [9, 64, 407, 1024])
+def test_sweep_graphs_same_bits(ctx, n):
+    """The blocked sweeps replayed from captured graphs (two graphs, one per
+    control slot, each replayed every other sweep) against the same launches
+    issued one by one: the same bits, on two calls in a row with other work
+    of the library between them."""
+    for rep in range(2):
+        print(f"psd_eigen paths 3, 4 n={n} call {rep}", flush=True)
+        A, lam = _psd(n, "spread" if rep == 0 else "repeated", 500 + n + rep)
+        v3, u3 = ctx.debug_psd_eigen(A, path=3)
+        ctx.debug_psd_eigen(np.eye(17) * 2.0, path=0)
+        v4, u4 = ctx.debug_psd_eigen(A, path=4)
+        assert np.array_equal(v3, v4) and np.array_equal(u3, u4)
+        _check(A, lam, v3, u3)
+
+
 def test_psd_eigen_errors(ctx):
     A = np.eye(4)
-    for kw in (dict(path=4), dict(path=-1), dict(max_sweeps=0)):
+    for kw in (dict(path=5), dict(path=-1), dict(max_sweeps=0)):
         with pytest.raises(T.TnqeError):
             ctx.debug_psd_eigen(A, **kw)
     with pytest.raises(T.TnqeError):
