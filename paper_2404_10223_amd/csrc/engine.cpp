@@ -1311,7 +1311,7 @@ void plan_env_layout(const MpoStructure &mpo, const MpoDevice *mdev, int N, int 
           d.offX = xo;
           offX[(ci * nslot + s) * 4 + k] = xo;
           const int Mp = dpad[x][sbra] * d.nw, Np = dpad[x + 1][sk];
-          xo += (int64_t)Mp * Np;
+          xo += ((int64_t)Mp * Np + 1) & ~(int64_t)1;   // even offsets: pairs of columns load as one vector
           maxM1 = std::max(maxM1, Mp);
           maxN1 = std::max(maxN1, Np);
           tb.g1.push_back(d);
@@ -1379,7 +1379,7 @@ void plan_env_layout(const MpoStructure &mpo, const MpoDevice *mdev, int N, int 
           tk.offY = yo;
           offY[(co * nslot + s) * 4 + kp] = yo;
           const int64_t tot = (int64_t)dpad[x][s_a] * tk.nw_out * dpad[x + 1][s];
-          yo += tot;
+          yo += (tot + 1) & ~(int64_t)1;
           // dense sources accumulate after the sparse pass, one source of a
           // block per launch so no two problems of a launch share an output
           for (size_t q = 0; q < dsrc.size(); ++q) {
@@ -1656,6 +1656,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   };
   auto sizes_of = [&](const EnvLayout &ly) {
     LaySizes z;
+    z.Xmax = z.Ymax = 2;   // even: every pair's X and Y start 16-byte aligned
     for (int b = 0; b <= N; ++b) z.Lmax = std::max(z.Lmax, ly.Lsize[b]);
     for (int x = 0; x < N; ++x) {
       z.Xmax = std::max(z.Xmax, ly.tabs[x].Xsize);
@@ -1677,7 +1678,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     }
     return d;
   };
-  const double fixed = 256.0 * (4 * N + 24);
+  const double fixed = 256.0 * (5 * N + 24);
   // per pair: the four environment buffers, its entries of the work lists
   // (at most one per descriptor) and its pointer-table entries
   auto per_pair_of = [&](const LaySizes &z) {
@@ -1856,9 +1857,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     // work lists of the batch: only the tiles (chunks) inside every pair's
     // own extents; sites in parallel on the host workers
     struct SiteWork {
-      std::vector<EnvWork> g1, mix, g2;
+      std::vector<EnvWork> g1, mix, mix2, g2;
       std::vector<std::vector<EnvWork>> dense;
-      int n1 = 0, nmix = 0, n2 = 0;
+      int n1 = 0, nmix = 0, nmix2 = 0, n2 = 0;
       std::vector<int> nd;
     };
     std::vector<SiteWork> sw(N);
@@ -1882,10 +1883,17 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           add(w.g1, w.n1, (int)di, q,
               tiles((int64_t)idim(bra_item[q], x, d.sbra) * d.nw, idim(ket_item[q], x + 1, d.sk), tb.tm1, tb.tn1));
         }
+      // channel mix: blocks of an even number of ket columns take the kernel
+      // that loads column pairs as one vector (all X and Y offsets are even)
       for (int q = 0; q < nb_; ++q)
         for (size_t ti = 0; ti < tb.tasks.size(); ++ti) {
           const MixTask &tk = tb.tasks[ti];
           const int da = idim(bra_item[q], x, tk.sa), db = idim(ket_item[q], x + 1, tk.s);
+          if (db % 2 == 0) {
+            const int64_t items = (int64_t)((da + kMix2Rows - 1) / kMix2Rows) * tk.nw_out * (db / 2);
+            add(w.mix2, w.nmix2, (int)ti, q, (items + 255) / 256);
+            continue;
+          }
           const int64_t items =
               (int64_t)((da + kMixRows - 1) / kMixRows) * tk.nw_out * ((db + kMixCols - 1) / kMixCols);
           add(w.mix, w.nmix, (int)ti, q, (items + 255) / 256);
@@ -1909,13 +1917,14 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
         }
     });
     struct DevWork {
-      const EnvWork *g1, *mix, *g2;
+      const EnvWork *g1, *mix, *mix2, *g2;
       std::vector<const EnvWork *> dense;
     };
     std::vector<DevWork> dw(N);
     for (int x = 0; x < N; ++x) {
       dw[x].g1 = c.upload(sw[x].g1);
       dw[x].mix = c.upload(sw[x].mix);
+      dw[x].mix2 = c.upload(sw[x].mix2);
       dw[x].g2 = c.upload(sw[x].g2);
       for (auto &lv : sw[x].dense) dw[x].dense.push_back(c.upload(lv));
     }
@@ -1964,6 +1973,11 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       ma.basis = dbasis;
       tick(kEnvMix);
       launch_mix<T>(ma, geom, dX, dY, st);
+      MixArgs m2 = ma;
+      m2.work = dw[x].mix2;
+      m2.nwork = (int)w.mix2.size();
+      m2.nchunk = w.nmix2;
+      launch_mix2<T>(m2, geom, dX, dY, st);
       for (size_t lv = 0; lv < tb.dense.size(); ++lv) {
         tick(kEnvDense);
         launch_env_gd<T>(cds[x].dense[lv], dw[x].dense[lv], (int)w.dense[lv].size(), w.nd[lv], tb.tmd[lv],
@@ -3728,7 +3742,7 @@ size_t workspace_bound(tnqe_ctx *ctx, const tnqe_problem &pb, const tnqe_options
   }
   // one pair, with the allowance the batching keeps free for its tables
   env += 2 * a256(eb * Lmax) + a256(eb * Xmax) + a256(eb * Ymax) + (double)ndesc * sizeof(EnvWork) +
-         (2.0 * N + 12) * sizeof(void *) + 256.0 * (4 * N + 24) + 64.0 * (ndesc + 64) + 256.0 * (6 * N + 24);
+         (2.0 * N + 12) * sizeof(void *) + 256.0 * (5 * N + 24) + 64.0 * (ndesc + 64) + 256.0 * (6 * N + 24);
   // mixed precision runs the FP64 pairs first, then the FP32 ones
   (void)npair;
   const size_t gep = 4 * a256(8.0 * M * M) + a256(8.0 * (8 + kMaxM)) + 2 * a256(8.0);

@@ -295,6 +295,9 @@ struct MixTask {
 constexpr int kMixRows = 8;
 constexpr int kMixCols = 1;
 constexpr int kMixUnroll = 2;
+// The vector channel mix (blocks with an even number db of ket columns): a
+// thread computes the column pair (2t, 2t + 1) of kMix2Rows bra rows.
+constexpr int kMix2Rows = 4;
 struct MixArgs {
   const MixTask *tasks;
   const EnvWork *work;      // (task, pair, first chunk of 256 items)
@@ -307,6 +310,10 @@ struct MixArgs {
 };
 template <typename T>
 void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, hipStream_t st);
+// the same for the task-pairs of even db, column pairs loaded as one vector
+// (X and Y offsets even, every pair's buffers 16-byte aligned)
+template <typename T>
+void launch_mix2(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, hipStream_t st);
 
 template <typename T>
 void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st);

@@ -378,6 +378,86 @@ __global__ void __launch_bounds__(256) k_mix(MixArgs a, EnvGeom g, const T *cons
 }
 
 template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  typedef double2 type;
+};
+template <>
+struct Pair2<float> {
+  typedef float2 type;
+};
+
+// The channel mix of the task-pairs with an even number db of ket columns: a
+// thread takes kMix2Rows consecutive bra rows of one output channel and the
+// column pair (2t, 2t + 1), loaded and stored as one vector (the offsets of
+// every X and Y block, and with db even every row, are even).  Terms in the
+// order of k_mix.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mix2(MixArgs a, EnvGeom g, const T *const *X, T *const *Y) {
+  constexpr int RA = kMix2Rows, U = kMixUnroll;
+  typedef typename Pair2<T>::type T2;
+  const EnvWork wk = find_work(a.work, a.nwork, blockIdx.x);
+  const int pair = wk.pair;
+  const MixTask tk = a.tasks[wk.desc];
+  const int da = g.sec(g.bra[pair], tk.x, tk.sa).y, db = g.sec(g.ket[pair], tk.x + 1, tk.s).y;
+  const int qpr = db >> 1, nag = (da + RA - 1) / RA;
+  const int item = (blockIdx.x - wk.first) * 256 + threadIdx.x;
+  if (item >= nag * tk.nw_out * qpr) return;
+  const int row = item / qpr, b = 2 * (item - row * qpr);
+  const int ag = row / tk.nw_out, w = row - ag * tk.nw_out;
+  const int ap0 = ag * RA, na = min(RA, da - ap0);
+  const double *vals = a.vals + a.basis[pair] * a.basis_stride;
+  const T *Xp = X[pair];
+  double acc[RA][2] = {};
+  for (int si = tk.src0; si < tk.src0 + tk.nsrc; ++si) {
+    const MixSrc sr = a.srcs[si];
+    const int z0 = a.rowptr[sr.rp + w], z1 = a.rowptr[sr.rp + w + 1];
+    const int *col = a.col + sr.cp;
+    const double *v = vals + sr.vbase;
+    const int64_t rs = (int64_t)sr.nw_in * db;   // X row stride between bra rows
+    const T *xb = Xp + sr.offX + (int64_t)ap0 * rs + b;
+    int z = z0;
+    for (; z + U <= z1; z += U) {
+      double cf[U];
+      T2 xv[U][RA];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cf[u] = sr.factor * v[z + u];
+        const T *xr = xb + (int64_t)col[z + u] * db;
+#pragma unroll
+        for (int r = 0; r < RA; ++r)
+          xv[u][r] = r < na ? *reinterpret_cast<const T2 *>(xr + r * rs) : T2{T(0), T(0)};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+          acc[r][0] += cf[u] * (double)xv[u][r].x;
+          acc[r][1] += cf[u] * (double)xv[u][r].y;
+        }
+    }
+    for (; z < z1; ++z) {
+      const double cf = sr.factor * v[z];
+      const T *xr = xb + (int64_t)col[z] * db;
+#pragma unroll
+      for (int r = 0; r < RA; ++r)
+        if (r < na) {
+          const T2 xv = *reinterpret_cast<const T2 *>(xr + r * rs);
+          acc[r][0] += cf * (double)xv.x;
+          acc[r][1] += cf * (double)xv.y;
+        }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    if (r >= na) break;
+    T *yr = Y[pair] + tk.offY + ((int64_t)(ap0 + r) * tk.nw_out + w) * db + b;
+    *reinterpret_cast<T2 *>(yr) = T2{(T)acc[r][0], (T)acc[r][1]};
+  }
+}
+
+template <typename T>
 __global__ void k_env_init(T *const *L, int64_t size) {
   T *p = L[blockIdx.y];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < size; e += (int64_t)gridDim.x * blockDim.x)
@@ -614,6 +694,12 @@ void launch_mix(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const 
 }
 
 template <typename T>
+void launch_mix2(const MixArgs &a, const EnvGeom &g, const T *const *X, T *const *Y, hipStream_t st) {
+  if (a.nwork == 0 || a.nchunk == 0) return;
+  hipLaunchKernelGGL(k_mix2<T>, dim3(a.nchunk), dim3(256), 0, st, a, g, X, Y);
+}
+
+template <typename T>
 void launch_env_init(T *const *L, int npair, int64_t size, hipStream_t st) {
   if (npair == 0) return;
   hipLaunchKernelGGL(k_env_init<T>, dim3(1, npair), dim3(64), 0, st, L, size);
@@ -666,6 +752,7 @@ void launch_cast(const double *const *src, float *const *dst, const int64_t *cou
   template void launch_env_gd<T>(const EnvGD *, const EnvWork *, int, int, int, int, const EnvGeom &,       \
                                  const T *const *, const T *const *, T *const *, hipStream_t, int);         \
   template void launch_mix<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, hipStream_t); \
+  template void launch_mix2<T>(const MixArgs &, const EnvGeom &, const T *const *, T *const *, hipStream_t); \
   template void launch_env_init<T>(T *const *, int, int64_t, hipStream_t);                                  \
   template void launch_env_final<T>(const EnvGeom &, int, const double *const *, const T *const *,          \
                                     const EnvFinal *, int, int, double *, int, hipStream_t);
