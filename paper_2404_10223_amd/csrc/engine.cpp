@@ -2986,13 +2986,16 @@ std::vector<double> truncation_errors(Call &c, KetSet &ci, int p, const double *
 // global-memory kernel, path 2 the chip-wide one by column pairs (the same
 // bits as path 1) and path 3 the chip-wide one by column blocks.
 // the two instantiated sweep graphs of a chip-wide eigensolve (one per
-// control slot), released when the solve returns or throws
+// control slot), released when the solve returns or throws (after the stream
+// they were launched on has drained)
 struct SweepGraphs {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
-  SweepGraphs() = default;
+  hipStream_t stream = nullptr;
+  explicit SweepGraphs(hipStream_t st) : stream(st) {}
   SweepGraphs(const SweepGraphs &) = delete;
   SweepGraphs &operator=(const SweepGraphs &) = delete;
   ~SweepGraphs() {
+    if (exec[0] || exec[1]) (void)hipStreamSynchronize(stream);
     for (hipGraphExec_t e : exec)
       if (e) (void)hipGraphExecDestroy(e);
   }
@@ -3029,7 +3032,7 @@ void psd_eigen(Call &c, const double *A, int n, int max_sweeps, double *&vec, do
     // once into a graph and replayed on the call's stream (kernel nodes only;
     // captured on a side stream of the library, since the caller's stream
     // may be the null stream, which cannot be captured)
-    SweepGraphs sg;
+    SweepGraphs sg(st);
     hipStream_t cst = c.ctx->aux[0];
     if (graphs) prepare_jacobi_wide_sweep_blocked();
     int sweep = 0;
