@@ -627,7 +627,13 @@ bool debug_timing() {
 ThreadPool &host_pool(tnqe_ctx *ctx) {
   if (!ctx->pool_threads) {
     const int hw = (int)std::thread::hardware_concurrency();
-    const int n = ctx->host_workers >= 0 ? ctx->host_workers : std::max(0, std::min(15, hw - 1));
+    // tuning: TNQE_HOST_WORKERS sets the count of a context that has none
+    static const int env = [] {
+      const char *e = std::getenv("TNQE_HOST_WORKERS");
+      return e ? std::max(0, std::min(63, std::atoi(e))) : -1;
+    }();
+    const int dflt = env >= 0 ? env : std::max(0, std::min(15, hw - 1));
+    const int n = ctx->host_workers >= 0 ? ctx->host_workers : dflt;
     ctx->pool_threads = std::make_unique<ThreadPool>(n);
   }
   return *ctx->pool_threads;
