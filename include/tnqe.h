@@ -140,7 +140,9 @@ typedef struct {
                                 0 (default): plain projection, no rescaling           */
   int32_t autotune;          /* 1: environment tile shapes from the context's tuned
                                 table (measured on first use, cached on disk); 0: the
-                                fixed shape rule                                       */
+                                fixed shape rule; 2 + k (k < 5, for tests): tile k of
+                                256x16, 128x32, 64x64, 32x128, 16x256 on every
+                                environment GEMM; other values TNQE_EINVAL             */
   int32_t workers;           /* batch calls (read from the first subspace's options):
                                 subspaces solved concurrently (0: default, 4)          */
   int32_t reserved[4];

@@ -182,7 +182,7 @@ def options(chi=16, precision="fp64", chi_cap_override=0, eps_S=1e-12, tau_w=1e-
     o.tau_w = tau_w
     o.max_sweeps = max_sweeps
     o.renormalize = int(bool(renormalize))
-    o.autotune = int(bool(autotune))
+    o.autotune = int(autotune)   # False/0 rule, True/1 tuned, 2 + k tile candidate k
     o.workers = int(workers)
     return o
 

@@ -1217,6 +1217,11 @@ const MpoDevice &mpo_dev_for(Call &c, const MpoStructure &mpo) {
 
 // ------------------------------------------------------------ environment sweep
 // Tile shape for a list of problems with largest extents maxM x maxN.
+// tile shapes of the environment GEMMs the autotuner times (tile modes 2 + k
+// force candidate k on every GEMM list, for tests)
+constexpr int kTileCands = 5;
+constexpr int kTileCand[kTileCands][2] = {{256, 16}, {128, 32}, {64, 64}, {32, 128}, {16, 256}};
+
 void pick_tile(int maxM, int maxN, bool long_m, int &tm, int &tn) {
   if (long_m) {
     if (maxN <= 16) { tm = 256; tn = 16; }
@@ -1512,7 +1517,7 @@ int ceil_log2(double v) {
 template <typename T>
 void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<std::pair<int, int>> &pairs,
                const std::vector<int> &ket_of_pair, const MpoStructure &mpo, const double *dvals,
-               int64_t nnz_total, EnvResult &res, bool autotune = false, int cm = 0) {
+               int64_t nnz_total, EnvResult &res, int tile_mode = 0, int cm = 0) {
   hipStream_t st = c.ctx->stream;
   const auto tq0 = Clock::now();
   const int N = pb.N, M = pb.M, nslot = pb.nslot(), nbond = N + 1;
@@ -1579,6 +1584,20 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
   const auto tq1 = Clock::now();
   EnvLayout lay;
   plan_env_layout(mpo, &mdev, N, pb.na, pb.nb, dpad, host_pool(c.ctx), lay);
+  // tile mode 2 + k: candidate k on every GEMM list (tests of each shape)
+  auto force_tiles = [&](EnvLayout &ly) {
+    if (tile_mode < 2) return;
+    const int *t = kTileCand[tile_mode - 2];
+    for (EnvSiteTabs &tb : ly.tabs) {
+      tb.tm1 = tb.tm2 = t[0];
+      tb.tn1 = tb.tn2 = t[1];
+      for (size_t lv = 0; lv < tb.tmd.size(); ++lv) {
+        tb.tmd[lv] = t[0];
+        tb.tnd[lv] = t[1];
+      }
+    }
+  };
+  force_tiles(lay);
   const std::vector<int64_t> &Lsize = lay.Lsize;
   std::vector<EnvSiteTabs> &tabs = lay.tabs;
   const auto tq2 = Clock::now();
@@ -1725,6 +1744,7 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
       for (int b = 0; b <= N; ++b)
         for (int s2 = 0; s2 < nslot; ++s2) dq[b][s2] = std::max(idim(bi, b, s2), idim(ki, b, s2));
       plan_env_layout(mpo, &mdev, N, pb.na, pb.nb, dq, host_pool(c.ctx), own);
+      force_tiles(own);
       cur = &own;
       z = sizes_of(own);
       require(per_pair_of(z) <= (double)c.ctx->pool.available() - fixed - 64.0 * (z.ndesc + 64), TNQE_EWORKSPACE,
@@ -1770,10 +1790,9 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
     // whose shape class has no tuned tile yet is timed with every tile shape
     // on this batch's buffers (their contents are not used yet: the real
     // sweep overwrites every output afterwards); the fastest is kept
-    if (autotune && p0 == 0 && !own_layouts) {
+    if (tile_mode == 1 && p0 == 0 && !own_layouts) {
       const auto tt0 = Clock::now();
       load_tiles(c.ctx);
-      static const int cand[5][2] = {{256, 16}, {128, 32}, {64, 64}, {32, 128}, {16, 256}};
       auto tiles = [](int64_t Mm, int64_t Nn, int tm, int tn) {
         return (Mm <= 0 || Nn <= 0) ? (int64_t)0 : ((Mm + tm - 1) / tm) * ((Nn + tn - 1) / tn);
       };
@@ -1811,11 +1830,12 @@ void env_phase(Call &c, const tnqe_problem &pb, KetSet *kets, const std::vector<
           if (it == c.ctx->tiles.end()) {
             float best = 1e30f;
             std::pair<int, int> pick = {64, 64};
-            for (const auto &cd : cand) {
+            for (const auto &cd : kTileCand) {
+              // pair-major, as the sweep's own lists
               std::vector<EnvWork> list;
               int nwg = 0;
-              for (int di = 0; di < nd; ++di)
-                for (int q = 0; q < nb_; ++q) {
+              for (int q = 0; q < nb_; ++q)
+                for (int di = 0; di < nd; ++di) {
                   int64_t Mm, Nn;
                   extent(di, q, Mm, Nn);
                   const int64_t cnt = tiles(Mm, Nn, cd[0], cd[1]);
@@ -2347,7 +2367,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
   EnvResult er;
   double shift_total = 0.0;   // c N_e of the shifted FP32 mode
   if (op.precision == TNQE_ENV_FP32) {
-    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune != 0);
+    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune);
     rep.n_fp32_pairs = (int)pairs.size();
   } else if (op.precision == TNQE_ENV_FP32_SHIFT || op.precision == TNQE_ENV_BF16 ||
              op.precision == TNQE_ENV_BF16X3) {
@@ -2358,7 +2378,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
       const size_t me = ctx->pool.mark();
       const std::vector<std::pair<int, int>> p0 = {{0, 0}};
       const std::vector<int> k0 = {-1};
-      env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p0, k0, mpo, dvals, nnz, e0, op.autotune != 0);
+      env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p0, k0, mpo, dvals, nnz, e0, op.autotune);
       c.sync();
       ctx->pool.rewind(me);
       shift_total = e0.H[0];
@@ -2378,7 +2398,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     double *dvs = c.dev<double>((size_t)nnz * M);
     launch_shift_vals(dvals, c.upload(vI), -cpe, nnz, M, dvs, ctx->stream);
     c.check_launch();
-    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvs, nnz, er, op.autotune != 0, cm);
+    env_phase<float>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvs, nnz, er, op.autotune, cm);
     rep.n_fp32_pairs = (int)pairs.size();
   } else if (op.precision == TNQE_ENV_MIXED) {
     // FP32 for pairs whose rotated ket kept at most kMixedNorm2 of its squared
@@ -2400,10 +2420,10 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     }
     EnvResult e64, e32;
     const size_t me = ctx->pool.mark();
-    if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64, op.autotune != 0);
+    if (!p64.empty()) env_phase<double>(c, pb, P > 0 ? &kets : nullptr, p64, k64, mpo, dvals, nnz, e64, op.autotune);
     c.sync();
     ctx->pool.rewind(me);
-    if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32, op.autotune != 0);
+    if (!p32.empty()) env_phase<float>(c, pb, P > 0 ? &kets : nullptr, p32, k32, mpo, dvals, nnz, e32, op.autotune);
     er.H.assign(pairs.size(), 0.0);
     er.S.assign(pairs.size(), 0.0);
     for (size_t q = 0; q < q64.size(); ++q) {
@@ -2427,7 +2447,7 @@ void solve_one(tnqe_ctx *ctx, tnqe_problem &pb, const tnqe_options &op, SolveOut
     }
     rep.n_fp32_pairs = (int)p32.size();
   } else {
-    env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune != 0);
+    env_phase<double>(c, pb, P > 0 ? &kets : nullptr, pairs, ket_of_pair, mpo, dvals, nnz, er, op.autotune);
   }
   rep.t_env_ms = ms_since(te);
   // ---- pencil and eigensolve
@@ -3956,6 +3976,7 @@ tnqe_status check_options(tnqe_ctx *ctx, const tnqe_options *o) {
   if (o->precision < TNQE_FP64 || o->precision > TNQE_ENV_BF16X3)
     return fail(ctx, TNQE_EINVAL, "unknown precision mode");
   if ((o->chi_cap_override > 0 ? o->chi_cap_override : o->chi) < 1) return fail(ctx, TNQE_EINVAL, "chi must be >= 1");
+  if (o->autotune < 0 || o->autotune >= 2 + kTileCands) return fail(ctx, TNQE_EINVAL, "unknown tile mode");
   return TNQE_OK;
 }
 

@@ -468,6 +468,22 @@ def test_autotuned_tiles(ctx, tmp_path, monkeypatch):
         c.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_every_tile_shape(ctx, precision):
+    """Every tile shape of the environment GEMMs forced on all of them
+    (tile mode 2 + k): the pencil bit for bit the same as with the shape
+    rule, in FP64 and in the FP32 and split-BF16 matrix-core variants."""
+    prob = synth.make_config(3)
+    H0, S0, _, _, _ = ctx.subspace(prob, chi=prob.chi, precision=precision)
+    for k in range(5):
+        print(f"tile candidate {k}, {precision}", flush=True)
+        H, S, _, _, _ = ctx.subspace(prob, chi=prob.chi, precision=precision, autotune=2 + k)
+        np.testing.assert_array_equal(H, H0)
+        np.testing.assert_array_equal(S, S0)
+    with pytest.raises(T.TnqeError):
+        ctx.subspace(prob, chi=prob.chi, autotune=7)
+
+
 def test_batch_concurrent_equals_sequential(ctx):
     """Concurrent subspaces (worker contexts on their own streams) give the
     same pencils as one after another."""
