@@ -1113,8 +1113,9 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   // without a round trip through the host
   tnqe_ctx *ctx = c.ctx;
   const int nblk = (int)blks.size();
-  int *dkept = c.dev<int>(nblk);
-  double *dstats = c.dev<double>((size_t)3 * ks.n);
+  // per-ket statistics and kept counts in one device buffer (one copy back)
+  double *dstats = c.dev<double>((size_t)3 * ks.n + ((size_t)nblk + 1) / 2);
+  int *dkept = reinterpret_cast<int *>(dstats + (size_t)3 * ks.n);
   const KetTables kt_new = ks.tables();
   double *dscale = renormalize ? c.dev<double>(ks.n) : nullptr;
   launch_select(dblk, Call::at<const int>(base, o_kf), ks.n, maxv, scratch, chi_cap, tau_w, kt_new, a + 1, dkept,
@@ -1145,8 +1146,8 @@ void gate_step(KetSet &ks, int a, const std::vector<double> &gates, int chi_cap,
   double *hstats = hbuf;
   int *hkept = reinterpret_cast<int *>(hbuf + (size_t)3 * ks.n);
   TNQE_HIP(hipStreamWaitEvent(ctx->aux[0], ctx->sel_ev, 0));
-  TNQE_HIP(hipMemcpyAsync(hstats, dstats, (size_t)3 * ks.n * sizeof(double), hipMemcpyDeviceToHost, ctx->aux[0]));
-  TNQE_HIP(hipMemcpyAsync(hkept, dkept, (size_t)nblk * sizeof(int), hipMemcpyDeviceToHost, ctx->aux[0]));
+  TNQE_HIP(hipMemcpyAsync(hstats, dstats, ((size_t)3 * ks.n + ((size_t)nblk + 1) / 2) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->aux[0]));
   TNQE_HIP(hipEventRecord(ctx->sv_ev, ctx->aux[0]));
   const auto ts0 = Clock::now();
   for (;;) {
