@@ -700,7 +700,7 @@ struct SvdTimer {
 };
 
 // Launch the SVDs of all blocks, grouped by kernel and workgroup size; within
-// a launch the largest blocks go first.
+// a launch the longest blocks go first.
 void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_sweeps, double *scratch,
              SvdTimer *timer = nullptr, int cat = kCatTrunc, const std::vector<int> *subset = nullptr) {
   static const int kThreadSteps[6] = {64, 128, 256, 512, 768, 1024};
@@ -709,7 +709,7 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
   // TNQE_DEBUG_SVD=1: print the Jacobi sweep counts of every launch (diagnostics)
   static const bool dbg = std::getenv("TNQE_DEBUG_SVD") != nullptr;
   int *dsweeps = dbg ? c.dev<int>(blks.size()) : nullptr;
-  std::vector<int64_t> work(blks.size());
+  std::vector<int64_t> work(blks.size()), sweep_cost(blks.size());
   const size_t nsel = subset ? subset->size() : blks.size();
   if (nsel == 0) return;
   for (size_t si = 0; si < nsel; ++si) {
@@ -727,16 +727,20 @@ void run_svd(Call &c, const Blk *dblk, const std::vector<Blk> &blks, int max_swe
     groups[key].push_back((int)i);
     lds[key] = std::max(lds[key], jp.lds);
     work[i] = (int64_t)b.n * b.n * m;
+    sweep_cost[i] = (int64_t)b.n * m;
   }
   // launches in decreasing estimated duration (longest processing time
   // first): the launch of the few largest blocks runs beside launches of many
   // small ones.  Duration estimate: the largest block's n m (rounds x vector
   // length) or the launch's total n^2 m spread over the chip, whichever is
   // larger.
+  // Within a launch blocks go in decreasing n m (rounds per sweep times vector
+  // length: the duration of a sweep at the launch's common lanes per vector;
+  // measured 1.5-2 % faster per solve than decreasing n^2 m, n, or n m^2).
   std::vector<std::pair<double, std::pair<int, int>>> order;
   for (auto &kv : groups) {
     std::vector<int> &idx = kv.second;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return work[x] > work[y]; });
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return sweep_cost[x] > sweep_cost[y]; });
     double w = 0.0, lat = 0.0;
     for (int i : idx) {
       w += (double)work[i];
